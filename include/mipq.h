@@ -1,0 +1,134 @@
+/*
+ * mipq -- product quantisation and inverted-index hot path for MI355X (gfx950).
+ *
+ * C ABI.  Every entry point returns an int status (MIPQ_OK or a negative
+ * MIPQ_E* code), never throws and never aborts; the text of the last error on
+ * the calling thread is returned by mipq_last_error().
+ *
+ * Memory.  Unless stated otherwise every array argument is a DEVICE pointer
+ * owned by the caller; the library allocates no device memory.  Calls that
+ * need scratch space take a caller-owned device workspace `ws` of `ws_bytes`
+ * bytes (at least what the matching *_workspace_size() query returns, aligned
+ * to 256 bytes) and fail with MIPQ_ENOMEM when it is smaller.  The workspace
+ * contents on entry are ignored.
+ *
+ * Streams.  `stream` is a hipStream_t (NULL = the default stream).  Calls only
+ * enqueue work on it and return before it runs; outputs are valid once the
+ * stream has reached the end of the call.  Calls that share a workspace must
+ * be ordered on one stream.
+ *
+ * Layouts.
+ *   rows       float32 [n][d], row-major, rows contiguous
+ *   codebook   float32 [m][ks][ds], ds = d / m: centroid k of subspace j is the
+ *              ds floats at codebook + (j*ks + k)*ds; subspace j covers the
+ *              contiguous columns [j*ds, (j+1)*ds)
+ *   codes      uint8 [n][m] (ks <= 256)
+ *
+ * Precision (the arithmetic used to rank candidate centroids):
+ *   MIPQ_FP32  every candidate distance in float32 from the difference form
+ *   MIPQ_BF16  distances ranked on matrix cores from bfloat16 operands split
+ *              into high and low parts, with float32 accumulation; every
+ *              (row, subspace) whose two best candidates are not separated
+ *              by a proven error bound is re-decided in MIPQ_FP32 arithmetic.
+ * Both give the same codes: the code of a (row, subspace) is the lowest index
+ * k minimising the float32 difference-form distance
+ *     sum over t ascending of (x_t - c_kt)^2,
+ * with every subtraction, square and sum rounded to float32 (no fused
+ * multiply-add).  Centroid sums, objectives and reconstruction errors are
+ * accumulated in float64.
+ */
+#ifndef MIPQ_H
+#define MIPQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MIPQ_ABI_VERSION 1
+
+enum mipq_status {
+  MIPQ_OK = 0,
+  MIPQ_EINVAL = -1,       /* bad shape, null required pointer, bad enum */
+  MIPQ_ENOMEM = -2,       /* workspace smaller than the *_workspace_size() query */
+  MIPQ_EHIP = -3,         /* a HIP runtime call failed (text in mipq_last_error) */
+  MIPQ_EUNSUPPORTED = -4  /* valid request this build does not implement */
+};
+
+enum mipq_precision { MIPQ_FP32 = 0, MIPQ_BF16 = 1 };
+
+/* Version of this header's ABI (MIPQ_ABI_VERSION). */
+int mipq_abi_version(void);
+
+/* Text of the last failure on the calling thread ("" if none). */
+const char* mipq_last_error(void);
+
+/* -------------------------------------------------------------------------
+ * k-means codebook fit (paper Section 2.1: split the d dimensions into m
+ * subspaces and fit ks centroids in each with k-means).
+ *
+ * Lloyd iteration, `iters` rounds, no tolerance test.  Each round assigns
+ * every training row to its nearest centroid in each subspace (the code rule
+ * above) and replaces every centroid that received rows by the float64 mean
+ * of those rows; a centroid that received none keeps its value.
+ *
+ *   x            training rows [n][d] (or the rows indexed by train_rows)
+ *   train_rows   optional int64 [n_train]: when non-NULL the training set is
+ *                x[train_rows[i]] (gathered into the workspace), and the
+ *                n argument is the number of rows of x
+ *   n_train      number of training rows (used only with train_rows)
+ *   init_rows    int64 [m][ks]: centroid k of subspace j starts as the
+ *                subspace-j block of training row init_rows[j*ks + k];
+ *                ignored when init_codebook is non-NULL
+ *   init_codebook optional float32 [m][ks][ds] starting codebook (resume)
+ *   codebook     OUT float32 [m][ks][ds]: float64 centroids rounded to nearest
+ *   codebook64   OUT optional float64 [m][ks][ds]
+ *   labels       OUT optional uint8 [n_train][m]: codes of the LAST
+ *                assignment (against the codebook before the last update)
+ *   objective    OUT optional float64 [iters]: objective[t] = sum over rows
+ *                and subspaces of the float32 distance of the chosen centroid
+ *                in round t, summed in float64
+ * Requirements: d % m == 0, d/m <= 16 (BF16) or <= 32 (FP32), 1 <= ks <= 256,
+ * n_train >= 1, iters >= 0, init rows in range.
+ * ------------------------------------------------------------------------- */
+size_t mipq_pq_fit_workspace_size(int64_t n_train, int d, int m, int ks, int iters, int precision);
+int mipq_pq_fit(const float* x, int64_t n, const int64_t* train_rows, int64_t n_train,
+                int d, int m, int ks, int iters,
+                const int64_t* init_rows, const float* init_codebook, int precision,
+                float* codebook, double* codebook64, uint8_t* labels, double* objective,
+                void* ws, size_t ws_bytes, void* stream);
+
+/* -------------------------------------------------------------------------
+ * Encode (paper Section 2.1: each row of each subspace is represented by
+ * its nearest subspace centroid, so a row becomes m codes).
+ *
+ *   codes     OUT uint8 [n][m]
+ *   rescored  OUT optional int64 [1]: number of (row, subspace) pairs the
+ *             BF16 path re-decided in FP32 arithmetic (0 for MIPQ_FP32)
+ * ------------------------------------------------------------------------- */
+size_t mipq_pq_encode_workspace_size(int64_t n, int d, int m, int ks, int precision);
+int mipq_pq_encode(const float* x, int64_t n, int d, int m, int ks, const float* codebook,
+                   int precision, uint8_t* codes, int64_t* rescored,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* -------------------------------------------------------------------------
+ * Decode and reconstruction error (paper Section 3: rows are encoded and
+ * decoded to measure the reconstruction RMSE).
+ *
+ *   x_hat     OUT optional float32 [n][d]: concatenated coded centroids
+ *   x         optional rows [n][d]; required for the error
+ *   sse_rmse  OUT optional float64 [2]: SSE = sum of (x - x_hat)^2 in float64,
+ *             RMSE = sqrt(SSE / (n*d)); requires x
+ * ------------------------------------------------------------------------- */
+size_t mipq_pq_decode_rmse_workspace_size(int64_t n, int d, int m, int ks);
+int mipq_pq_decode_rmse(const uint8_t* codes, int64_t n, int d, int m, int ks,
+                        const float* codebook, const float* x, float* x_hat, double* sse_rmse,
+                        void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MIPQ_H */

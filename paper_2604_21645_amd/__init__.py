@@ -1,0 +1,120 @@
+"""MI355X-native product quantisation and inverted-index hot path.
+
+Thin Python layer over libmipq.so (include/mipq.h): every function checks
+dtypes and devices, allocates outputs and workspaces with torch, passes raw
+pointers and torch's current HIP stream to the C ABI, and returns tensors.
+All arithmetic runs in the library's HIP kernels; there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import torch
+
+from ._lib import MipqError, check, lib  # noqa: F401
+
+FP32, BF16 = 0, 1
+_PREC = {"fp32": FP32, "bf16": BF16, FP32: FP32, BF16: BF16}
+
+
+def _prec(p) -> int:
+    try:
+        return _PREC[p]
+    except KeyError:
+        raise ValueError("precision must be 'fp32' or 'bf16'") from None
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.device.type != "cuda":
+        raise ValueError("%s must be on the GPU" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s (got %s)" % (name, dtype, t.dtype))
+    return t.contiguous()
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def pq_fit(x: torch.Tensor, m: int, ks: int, iters: int, init_rows: torch.Tensor | None = None,
+           init_codebook: torch.Tensor | None = None, train_rows: torch.Tensor | None = None,
+           precision="bf16", labels: bool = True, codebook64: bool = False, objective: bool = True):
+    """Fit per-subspace k-means codebooks (Lloyd, ``iters`` rounds).
+
+    Returns a dict with ``codebook`` float32 [m, ks, d/m] and, on request,
+    ``labels`` uint8 [n_train, m] (last assignment), ``codebook64`` and
+    ``objective`` float64 [iters].
+    """
+    L = lib()
+    x = _dev(x, torch.float32, "x")
+    dev = x.device
+    n, d = x.shape
+    ds = d // m if m else 0
+    tr = _dev(train_rows, torch.int64, "train_rows") if train_rows is not None else None
+    n_train = tr.numel() if tr is not None else n
+    ir = _dev(init_rows, torch.int64, "init_rows") if init_rows is not None else None
+    ic = _dev(init_codebook, torch.float32, "init_codebook") if init_codebook is not None else None
+    p = _prec(precision)
+    out = {"codebook": torch.empty((m, ks, ds), dtype=torch.float32, device=dev)}
+    if labels:
+        out["labels"] = torch.empty((n_train, m), dtype=torch.uint8, device=dev)
+    if codebook64:
+        out["codebook64"] = torch.empty((m, ks, ds), dtype=torch.float64, device=dev)
+    if objective:
+        out["objective"] = torch.empty(max(iters, 0), dtype=torch.float64, device=dev)
+    nbytes = L.mipq_pq_fit_workspace_size(n_train, d, m, ks, iters, p)
+    ws = _ws(nbytes, dev)
+    check(L.mipq_pq_fit(_ptr(x), n, _ptr(tr), n_train, d, m, ks, iters, _ptr(ir), _ptr(ic), p,
+                        _ptr(out["codebook"]), _ptr(out.get("codebook64")), _ptr(out.get("labels")),
+                        _ptr(out.get("objective")), _ptr(ws), ws.numel(), _stream(dev)))
+    return out
+
+
+def pq_encode(x: torch.Tensor, codebook: torch.Tensor, precision="bf16", rescored: bool = False):
+    """Codes uint8 [n, m]; with ``rescored=True`` also the int64 count of
+    (row, subspace) pairs the BF16 path re-decided in float32."""
+    L = lib()
+    x = _dev(x, torch.float32, "x")
+    cb = _dev(codebook, torch.float32, "codebook")
+    dev = x.device
+    n, d = x.shape
+    m, ks, ds = cb.shape
+    if m * ds != d:
+        raise ValueError("codebook shape %s does not match d=%d" % (tuple(cb.shape), d))
+    p = _prec(precision)
+    codes = torch.empty((n, m), dtype=torch.uint8, device=dev)
+    resc = torch.zeros(1, dtype=torch.int64, device=dev) if rescored else None
+    ws = _ws(L.mipq_pq_encode_workspace_size(n, d, m, ks, p), dev)
+    check(L.mipq_pq_encode(_ptr(x), n, d, m, ks, _ptr(cb), p, _ptr(codes), _ptr(resc), _ptr(ws),
+                           ws.numel(), _stream(dev)))
+    return (codes, resc) if rescored else codes
+
+
+def pq_decode_rmse(codes: torch.Tensor, codebook: torch.Tensor, x: torch.Tensor | None = None,
+                   x_hat: bool = False):
+    """Decode codes; returns (x_hat or None, sse_rmse float64 [2] or None)."""
+    L = lib()
+    codes = _dev(codes, torch.uint8, "codes")
+    cb = _dev(codebook, torch.float32, "codebook")
+    dev = codes.device
+    n, m = codes.shape
+    m2, ks, ds = cb.shape
+    if m2 != m:
+        raise ValueError("codes have %d subspaces, codebook %d" % (m, m2))
+    d = m * ds
+    xx = _dev(x, torch.float32, "x") if x is not None else None
+    xh = torch.empty((n, d), dtype=torch.float32, device=dev) if x_hat else None
+    sr = torch.empty(2, dtype=torch.float64, device=dev) if xx is not None else None
+    ws = _ws(L.mipq_pq_decode_rmse_workspace_size(n, d, m, ks), dev)
+    check(L.mipq_pq_decode_rmse(_ptr(codes), n, d, m, ks, _ptr(cb), _ptr(xx), _ptr(xh), _ptr(sr),
+                                _ptr(ws), ws.numel(), _stream(dev)))
+    return xh, sr

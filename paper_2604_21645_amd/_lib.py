@@ -1,0 +1,79 @@
+"""ctypes loader for libmipq.so (argument marshalling only).
+
+torch is imported before the library is opened so that the library binds to
+the HIP runtime torch already mapped (one runtime per process: torch's
+streams and device pointers are then valid inside the library).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch  # noqa: F401  (must precede loading the library)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmipq.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "mipq.h")
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_L = ctypes.c_int64
+_S = ctypes.c_size_t
+
+SIGNATURES = {
+    "mipq_abi_version": (_I, []),
+    "mipq_last_error": (ctypes.c_char_p, []),
+    "mipq_pq_fit_workspace_size": (_S, [_L, _I, _I, _I, _I, _I]),
+    "mipq_pq_fit": (_I, [_P, _L, _P, _L, _I, _I, _I, _I, _P, _P, _I, _P, _P, _P, _P, _P, _S, _P]),
+    "mipq_pq_encode_workspace_size": (_S, [_L, _I, _I, _I, _I]),
+    "mipq_pq_encode": (_I, [_P, _L, _I, _I, _I, _P, _I, _P, _P, _P, _S, _P]),
+    "mipq_pq_decode_rmse_workspace_size": (_S, [_L, _I, _I, _I]),
+    "mipq_pq_decode_rmse": (_I, [_P, _L, _I, _I, _I, _P, _P, _P, _P, _P, _S, _P]),
+}
+
+_lib = None
+
+
+class MipqError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("mipq error %d: %s" % (code, msg))
+        self.code = code
+
+
+def header_functions(path: str = HEADER):
+    """Names of the functions declared in include/mipq.h."""
+    with open(path) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(mipq_\w+)\s*\(", text)))
+
+
+def hip_runtimes_mapped():
+    """Paths of every libamdhip64 mapped into this process."""
+    with open("/proc/self/maps") as f:
+        return sorted(set(re.findall(r"\S*libamdhip64\S*", f.read())))
+
+
+def lib():
+    """The loaded library; raises if it is not built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libmipq.so is not built; run `python -m paper_2604_21645_amd.build`")
+    handle = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(handle, name)
+        fn.restype = res
+        fn.argtypes = args
+    runtimes = hip_runtimes_mapped()
+    if len(runtimes) > 1:
+        raise RuntimeError("more than one HIP runtime mapped: %s" % runtimes)
+    _lib = handle
+    return _lib
+
+
+def check(rc: int) -> None:
+    if rc != 0:
+        raise MipqError(rc, lib().mipq_last_error().decode())

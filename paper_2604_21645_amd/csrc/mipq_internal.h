@@ -1,0 +1,87 @@
+// Internal declarations shared by the HIP sources of libmipq.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "mipq.h"
+
+namespace mipq {
+
+// ---- error reporting -------------------------------------------------------
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+
+#define MIPQ_HIP(call)                                   \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return ::mipq::hip_fail(e_, #call); \
+  } while (0)
+
+#define MIPQ_LAUNCHED(what)                              \
+  do {                                                   \
+    hipError_t e_ = hipGetLastError();                   \
+    if (e_ != hipSuccess) return ::mipq::hip_fail(e_, what); \
+  } while (0)
+
+// ---- workspace carving -----------------------------------------------------
+// Sub-buffers are 256-byte aligned; the same carving code sizes and fills.
+struct Carver {
+  char* base;
+  size_t used = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    used = (used + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
+    used += count * sizeof(T);
+    return p;
+  }
+  size_t bytes() const { return (used + 255) & ~size_t(255); }
+};
+
+// ---- constants ---------------------------------------------------------------
+constexpr int kMaxKs = 256;        // codes are uint8
+constexpr int kMaxDsBf16 = 16;     // two 8-dimension blocks per subspace
+constexpr int kMaxDsFp32 = 64;
+constexpr int kMaxDsFit = 32;      // float64 centroid sums held in LDS
+
+// number of 32x32x16 MFMAs per 32-centroid tile for NB 8-dim blocks
+__host__ __device__ constexpr int bf16_nmfma(int nb) { return nb + (nb + 1) / 2 + ((nb % 2 == 0) ? 1 : 0); }
+inline int ceil_div(int64_t a, int64_t b) { return int((a + b - 1) / b); }
+inline int tiles_for(int ks) { return ks <= 32 ? 1 : ks <= 64 ? 2 : ks <= 128 ? 4 : 8; }
+
+// ---- launchers (each returns MIPQ_OK or an error code) ---------------------
+int launch_zero_u32(uint32_t* p, size_t count, hipStream_t s);
+int launch_gather_rows(const float* x, int64_t n, int d, const int64_t* rows, int64_t n_rows,
+                       float* out, uint32_t* bad, hipStream_t s);
+int launch_init_codebook(const float* train, int64_t n_train, int d, int m, int ks,
+                         const int64_t* init_rows, const float* init_cb, double* c64, float* c32,
+                         uint32_t* bad, hipStream_t s);
+int launch_check_flag(const uint32_t* bad, int* host_flag, hipStream_t s);
+int launch_assign_fp32(const float* x, int64_t n, int d, int m, int ks, const float* c32,
+                       uint8_t* codes, hipStream_t s);
+int accumulate_chunks(int64_t n, int m);
+int launch_accumulate(const float* x, int64_t n, int d, int m, int ks, const uint8_t* codes,
+                      const float* c32, int nch, double* part_s, uint32_t* part_cnt,
+                      double* part_j, hipStream_t s);
+int launch_finalize(int m, int ks, int ds, int nch, const double* part_s, const uint32_t* part_cnt,
+                    const double* part_j, double* c64, float* c32, double* j_sub, hipStream_t s);
+int launch_objective(const double* j_sub, int iters, int m, double* objective, hipStream_t s);
+int launch_copy_f64(const double* src, double* dst, size_t count, hipStream_t s);
+int launch_decode_sse(const uint8_t* codes, int64_t n, int d, int m, int ks, const float* c32,
+                      const float* x, float* x_hat, double* partials, int nblk, hipStream_t s);
+int decode_blocks(int64_t n, int m);
+int launch_sse_final(const double* partials, int nblk, int64_t n, int d, double* out, hipStream_t s);
+
+// BF16 matrix-core path
+size_t bf16_operand_count(int m, int ks, int ds);   // number of 16-byte operand slots
+int launch_pack_bf16(const float* c32, int m, int ks, int ds, void* aop, float* cmax, hipStream_t s);
+int launch_assign_bf16(const float* x, int64_t n, int d, int m, int ks, const void* aop,
+                       const float* cmax, uint8_t* codes, uint32_t* queue, uint32_t* qcount,
+                       hipStream_t s);
+int launch_fixup(const float* x, int d, int m, int ks, const float* c32, const uint32_t* queue,
+                 const uint32_t* qcount, uint8_t* codes, int64_t* rescored_total, hipStream_t s);
+
+}  // namespace mipq

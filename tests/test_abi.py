@@ -1,0 +1,77 @@
+"""The C ABI loads without a GPU, exports every declared symbol and rejects bad
+arguments with the documented status codes before touching the device."""
+
+import ctypes
+
+import pytest
+
+from paper_2604_21645_amd import _lib
+
+EINVAL, ENOMEM, EUNSUPPORTED = -1, -2, -4
+
+
+@pytest.fixture(scope="module")
+def L():
+    return _lib.lib()
+
+
+def test_every_header_function_is_exported(L):
+    names = _lib.header_functions()
+    assert "mipq_pq_fit" in names and "mipq_pq_encode" in names
+    for name in names:
+        assert hasattr(L, name), name
+        assert name in _lib.SIGNATURES, name
+
+
+def test_single_hip_runtime_and_version(L):
+    assert len(_lib.hip_runtimes_mapped()) == 1
+    assert L.mipq_abi_version() == 1
+
+
+def test_workspace_queries(L):
+    small = L.mipq_pq_encode_workspace_size(1000, 128, 16, 256, 1)
+    big = L.mipq_pq_encode_workspace_size(100000, 128, 16, 256, 1)
+    assert 0 < small < big
+    assert L.mipq_pq_encode_workspace_size(1000, 128, 16, 256, 0) == 0   # FP32 needs none
+    assert L.mipq_pq_encode_workspace_size(1000, 130, 16, 256, 1) == 0   # invalid shape
+    assert L.mipq_pq_fit_workspace_size(1000, 128, 16, 256, 25, 1) > 0
+    assert L.mipq_pq_decode_rmse_workspace_size(1000, 128, 16, 256) > 0
+
+
+def _encode(L, n=10, d=128, m=16, ks=256, prec=1, ws=None, ws_bytes=0, x=1, cb=1, codes=1):
+    return L.mipq_pq_encode(x, n, d, m, ks, cb, prec, codes, None, ws, ws_bytes, None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(d=130), EINVAL),
+    (dict(m=0), EINVAL),
+    (dict(ks=0), EINVAL),
+    (dict(ks=257), EINVAL),
+    (dict(n=-1), EINVAL),
+    (dict(prec=7), EINVAL),
+    (dict(d=512, m=16), EUNSUPPORTED),
+    (dict(x=None), EINVAL),
+    (dict(ws=None), EINVAL),
+    (dict(ws=256, ws_bytes=16), ENOMEM),
+])
+def test_encode_rejects_bad_arguments(L, kw, code):
+    assert _encode(L, **kw) == code
+    assert len(L.mipq_last_error()) > 0
+
+
+def test_fit_rejects_bad_arguments(L):
+    fit = L.mipq_pq_fit
+    # no initial codebook or rows
+    assert fit(1, 100, None, 0, 128, 16, 256, 5, None, None, 1, 1, None, None, None, 256, 1 << 30, None) == EINVAL
+    # negative iterations
+    assert fit(1, 100, None, 0, 128, 16, 256, -1, 1, None, 1, 1, None, None, None, 256, 1 << 30, None) == EINVAL
+    # workspace too small
+    assert fit(1, 100, None, 0, 128, 16, 256, 5, 1, None, 1, 1, None, None, None, 256, 64, None) == ENOMEM
+    assert b"workspace" in L.mipq_last_error()
+    # misaligned workspace
+    assert fit(1, 100, None, 0, 128, 16, 256, 5, 1, None, 1, 1, None, None, None, 257, 1 << 30, None) == EINVAL
+
+
+def test_decode_needs_x_for_the_error(L):
+    rc = L.mipq_pq_decode_rmse(1, 10, 128, 16, 256, 1, None, None, 1, 256, 1 << 20, None)
+    assert rc == EINVAL

@@ -1,0 +1,154 @@
+"""GPU parity of the PQ hot path (fit, encode, decode + RMSE) against the CPU oracle.
+
+Every call goes through the C ABI (paper_2604_21645_amd -> libmipq.so).  Codes
+must equal the oracle's float32-decision codes bit for bit in every precision,
+and the float64 oracle's codes outside its near-ties; centroids, objective and
+RMSE are compared with tolerances derived from float64 summation order.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2604_21645_amd as mipq
+from oracle import pq
+from synth import workloads as wl
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _data(kind, n, d, seed):
+    if kind == "integer":
+        return wl.gaussian_mixture(seed, n, d, 50, mean_hi=255.0, sigma=20.0, integer_clip=(0, 255))
+    return wl.gaussian_mixture(seed, n, d, 40, sigma=0.05)
+
+
+def _codebook(x, m, ks, seed):
+    """float32 codebook from seeded rows, jittered so equal rows do not tie."""
+    n = x.shape[0]
+    rng = np.random.default_rng(seed)
+    rows = np.stack([rng.choice(n, size=ks, replace=ks > n) for _ in range(m)])
+    cb = pq.init_codebook(x, rows, m)
+    cb = cb + rng.standard_normal(cb.shape) * (np.abs(cb).mean() * 1e-3)
+    return cb.astype(np.float32)
+
+
+ENCODE_CASES = [
+    dict(n=3001, d=128, m=16, ks=256, kind="integer"),   # ds=8, ragged tail
+    dict(n=2077, d=128, m=8, ks=256, kind="float"),      # ds=16
+    dict(n=1000, d=64, m=16, ks=100, kind="float"),      # ds=4, partial tile
+    dict(n=513, d=36, m=12, ks=16, kind="float"),        # ds=3, one tile
+    dict(n=700, d=96, m=8, ks=200, kind="float"),        # ds=12, two 8-dim blocks
+    dict(n=77, d=40, m=8, ks=1, kind="float"),           # ks=1, ds=5
+    dict(n=1, d=96, m=12, ks=256, kind="float"),         # single row
+    dict(n=33, d=128, m=16, ks=64, kind="integer"),      # one row past a tile
+]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("case", ENCODE_CASES, ids=lambda c: "n%(n)d_d%(d)d_m%(m)d_ks%(ks)d" % c)
+def test_encode_matches_oracle(prec, case):
+    print("encode", prec, case, flush=True)
+    x = _data(case["kind"], case["n"], case["d"], seed=case["n"])
+    cb = _codebook(x, case["m"], case["ks"], seed=case["d"])
+    codes = mipq.pq_encode(_t(x), _t(cb), prec).cpu().numpy().astype(np.int64)
+    ref32, _, _ = pq.assign(x, cb.astype(np.float64), "fp32")
+    np.testing.assert_array_equal(codes, ref32)
+    ref64, _, tie = pq.assign(x, cb.astype(np.float64), "fp64")
+    assert np.all(codes[~tie] == ref64[~tie])
+
+
+def test_encode_empty_input():
+    x = torch.empty((0, 128), dtype=torch.float32, device=DEV)
+    cb = torch.zeros((16, 256, 8), dtype=torch.float32, device=DEV)
+    for prec in ("fp32", "bf16"):
+        assert mipq.pq_encode(x, cb, prec).shape == (0, 16)
+
+
+def test_bf16_and_fp32_agree_on_duplicate_rows_and_ties():
+    # duplicated centroids and rows equidistant from several centroids: every
+    # such pair is ambiguous for the matrix cores and decided by the exact rule
+    rng = np.random.default_rng(3)
+    cb = rng.integers(0, 4, size=(16, 64, 8)).astype(np.float32)
+    cb[:, 32:] = cb[:, :32]
+    x = rng.integers(0, 4, size=(2000, 128)).astype(np.float32)
+    a = mipq.pq_encode(_t(x), _t(cb), "fp32").cpu().numpy()
+    b, resc = mipq.pq_encode(_t(x), _t(cb), "bf16", rescored=True)
+    np.testing.assert_array_equal(a, b.cpu().numpy())
+    ref32, _, _ = pq.assign(x, cb.astype(np.float64), "fp32")
+    np.testing.assert_array_equal(a.astype(np.int64), ref32)
+    assert int(resc.item()) > 0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_fit_end_to_end_and_lockstep(prec):
+    w = wl.plain_pq(seed=1, n=4000, m=8, ks=64, iters=6)
+    print("fit", prec, flush=True)
+    out = mipq.pq_fit(_t(w.x), w.m, w.ks, w.iters, init_rows=_t(w.init_rows), precision=prec,
+                      codebook64=True)
+    ref = pq.lloyd(w.x, w.init_rows, w.m, w.iters, decide="fp32")
+    np.testing.assert_array_equal(out["labels"].cpu().numpy().astype(np.int64), ref["codes"])
+    np.testing.assert_allclose(out["codebook64"].cpu().numpy(), ref["codebook"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_array_equal(out["codebook"].cpu().numpy(), ref["codebook"].astype(np.float32))
+    np.testing.assert_allclose(out["objective"].cpu().numpy(), ref["objective"], rtol=1e-6)
+    # lockstep: one round at a time from the GPU's own centroids
+    cb = pq.init_codebook(w.x, w.init_rows, w.m).astype(np.float32)
+    for _ in range(3):
+        step = mipq.pq_fit(_t(w.x), w.m, w.ks, 1, init_codebook=_t(cb), precision=prec, codebook64=True)
+        codes, _, _ = pq.assign(w.x, cb.astype(np.float64), "fp32")
+        np.testing.assert_array_equal(step["labels"].cpu().numpy().astype(np.int64), codes)
+        upd, _, _ = pq.update(w.x, codes, cb.astype(np.float64))
+        np.testing.assert_allclose(step["codebook64"].cpu().numpy(), upd, rtol=1e-12, atol=1e-12)
+        cb = step["codebook"].cpu().numpy()
+
+
+def test_fit_on_a_row_sample_with_empty_clusters():
+    w = wl.integer_pq(seed=2, n=20000, n_comp=30, m=16, ks=256, iters=4, n_train=5000)
+    # duplicate init rows force empty clusters (the later duplicate never wins)
+    init = w.init_rows.copy()
+    init[:, 200:] = init[:, :56]
+    out = mipq.pq_fit(_t(w.x), w.m, w.ks, w.iters, init_rows=_t(init), train_rows=_t(w.train_rows),
+                      precision="bf16", codebook64=True)
+    ref = pq.lloyd(w.train, init, w.m, w.iters, decide="fp32")
+    np.testing.assert_array_equal(out["labels"].cpu().numpy().astype(np.int64), ref["codes"])
+    # integer rows: float64 sums are exact in any order, centroids are identical
+    np.testing.assert_array_equal(out["codebook64"].cpu().numpy(), ref["codebook"])
+
+
+@pytest.mark.parametrize("m,ks", [(16, 256), (8, 37)])
+def test_decode_rmse_matches_oracle(m, ks):
+    x = _data("float", 5003, 128, seed=9)
+    cb = _codebook(x, m, ks, seed=10)
+    codes = mipq.pq_encode(_t(x), _t(cb), "bf16")
+    xh, sr = mipq.pq_decode_rmse(codes, _t(cb), _t(x), x_hat=True)
+    c = codes.cpu().numpy().astype(np.int64)
+    np.testing.assert_array_equal(xh.cpu().numpy(), pq.decode(c, cb.astype(np.float64)).astype(np.float32))
+    sse, rmse = pq.sse_rmse(x, c, cb.astype(np.float64))
+    got = sr.cpu().numpy()
+    assert got[0] == pytest.approx(sse, rel=1e-12)
+    assert got[1] == pytest.approx(rmse, rel=1e-12)
+
+
+def test_full_size_integer_workload_sampled_parity():
+    """1M x 128 integer rows, 100k-row sample, M=16, Ks=256, 25 rounds: the
+    bench workload.  BF16 and FP32 produce identical codes on all 1M rows;
+    sampled rows equal the oracle's."""
+    w = wl.integer_pq()
+    xt = _t(w.x)
+    fit = mipq.pq_fit(xt, w.m, w.ks, w.iters, init_rows=_t(w.init_rows), train_rows=_t(w.train_rows),
+                      precision="bf16")
+    cb = fit["codebook"]
+    obj = fit["objective"].cpu().numpy()
+    assert np.all(np.diff(obj) <= 1e-9 * obj[:-1])
+    cb16, resc = mipq.pq_encode(xt, cb, "bf16", rescored=True)
+    c32 = mipq.pq_encode(xt, cb, "fp32")
+    assert torch.equal(cb16, c32)
+    print("rescored pairs", int(resc.item()), "of", w.x.shape[0] * w.m, flush=True)
+    rows = np.random.default_rng(0).choice(w.x.shape[0], 4000, replace=False)
+    ref32, _, _ = pq.assign(w.x[rows], cb.cpu().numpy().astype(np.float64), "fp32")
+    np.testing.assert_array_equal(cb16.cpu().numpy()[rows].astype(np.int64), ref32)
