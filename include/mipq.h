@@ -87,9 +87,9 @@ const char* mipq_last_error(void);
  *   codebook64   OUT optional float64 [m][ks][ds]
  *   labels       OUT optional uint8 [n_train][m]: codes of the LAST
  *                assignment (against the codebook before the last update)
- *   objective    OUT optional float64 [iters]: objective[t] = sum over rows
- *                and subspaces of the float32 distance of the chosen centroid
- *                in round t, summed in float64
+ *   objective    OUT optional float64 [iters]: objective[t] = sum over rows,
+ *                subspaces and dimensions of (x - c)^2 in float64, c the
+ *                float32 centroid chosen in round t
  * Requirements: d % m == 0, d/m <= 16 (BF16) or <= 32 (FP32), 1 <= ks <= 256,
  * n_train >= 1, iters >= 0, init rows in range.
  * ------------------------------------------------------------------------- */
@@ -126,6 +126,26 @@ size_t mipq_pq_decode_rmse_workspace_size(int64_t n, int d, int m, int ks);
 int mipq_pq_decode_rmse(const uint8_t* codes, int64_t n, int d, int m, int ks,
                         const float* codebook, const float* x, float* x_hat, double* sse_rmse,
                         void* ws, size_t ws_bytes, void* stream);
+
+/* -------------------------------------------------------------------------
+ * Per-kernel timing (tracing aid, off by default).
+ *
+ * mipq_profile_enable(1) makes every subsequent launch of the kernels below
+ * record a pair of HIP events on its own stream; mipq_profile_collect()
+ * waits for the recorded events of one kernel, returns the number of
+ * launches and their summed duration in milliseconds, and forgets them.
+ * ------------------------------------------------------------------------- */
+enum mipq_kernel {
+  MIPQ_K_ASSIGN_FP32 = 0,   /* plain float32 assignment */
+  MIPQ_K_ASSIGN_BF16 = 1,   /* matrix-core assignment (with exact re-decision) */
+  MIPQ_K_UPDATE = 2,        /* float64 centroid sums per row chunk */
+  MIPQ_K_FINALIZE = 3,      /* centroid means, objective (+ operand packing) */
+  MIPQ_K_PACK_BF16 = 4,     /* stand-alone centroid operand packing */
+  MIPQ_K_DECODE = 5,        /* decode + squared error */
+  MIPQ_KERNEL_COUNT = 6
+};
+int mipq_profile_enable(int on);
+int mipq_profile_collect(int kernel, int64_t* launches, double* total_ms);
 
 #ifdef __cplusplus
 }

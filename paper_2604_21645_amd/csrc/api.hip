@@ -48,19 +48,17 @@ int check_shape(int64_t n, int d, int m, int ks, int precision, bool fit) {
 struct EncodeWs {
   void* aop = nullptr;
   float* cmax = nullptr;
-  uint32_t* queue = nullptr;
-  uint32_t* qcount = nullptr;
+  float* mu = nullptr;
   size_t bytes = 0;
 };
 
-EncodeWs carve_encode(void* ws, int64_t n, int d, int m, int ks, int precision) {
+EncodeWs carve_encode(void* ws, int m, int ks, int ds, int precision) {
   Carver c(ws);
   EncodeWs e;
   if (precision == MIPQ_BF16) {
-    e.aop = c.take<uint4>(bf16_operand_count(m, ks, d / m));
+    e.aop = c.take<uint4>(bf16_operand_count(m, ks, ds));
     e.cmax = c.take<float>(m);
-    e.qcount = c.take<uint32_t>(4);
-    e.queue = c.take<uint32_t>((size_t)n * m);
+    e.mu = c.take<float>((size_t)m * kMaxDsBf16);
   }
   e.bytes = c.bytes();
   return e;
@@ -85,7 +83,7 @@ FitWs carve_fit(void* ws, int64_t n_train, bool gather, int d, int m, int ks, in
   Carver c(ws);
   FitWs f;
   const int ds = d / m;
-  f.nch = accumulate_chunks(n_train, m);
+  f.nch = update_chunks(n_train, m);
   if (gather) f.xs = c.take<float>((size_t)n_train * d);
   if (need_codes) f.codes = c.take<uint8_t>((size_t)n_train * m);
   if (need_c64) f.c64 = c.take<double>((size_t)m * ks * ds);
@@ -94,9 +92,8 @@ FitWs carve_fit(void* ws, int64_t n_train, bool gather, int d, int m, int ks, in
   f.part_j = c.take<double>((size_t)f.nch * m);
   f.j_sub = c.take<double>((size_t)(iters > 0 ? iters : 1) * m);
   f.bad = c.take<uint32_t>(4);
-  // the encode part lives at the end of the carve
   const size_t off = c.bytes();
-  EncodeWs e = carve_encode(ws ? static_cast<char*>(ws) + off : nullptr, n_train, d, m, ks, precision);
+  EncodeWs e = carve_encode(ws ? static_cast<char*>(ws) + off : nullptr, m, ks, ds, precision);
   f.enc = e;
   f.bytes = off + e.bytes;
   return f;
@@ -110,15 +107,11 @@ int check_ws(void* ws, size_t have, size_t need) {
   return MIPQ_OK;
 }
 
-// codes of `x` against `c32`, exact rule; the BF16 path re-decides ambiguous pairs
+// codes of `x` against `c32` by the exact rule (operands already packed for BF16)
 int assign_any(const float* x, int64_t n, int d, int m, int ks, const float* c32, int precision,
-               uint8_t* codes, const EncodeWs& e, int64_t* rescored, hipStream_t s, bool repack) {
-  int rc;
+               uint8_t* codes, const EncodeWs& e, int64_t* rescored, hipStream_t s) {
   if (precision == MIPQ_FP32) return launch_assign_fp32(x, n, d, m, ks, c32, codes, s);
-  if (repack && (rc = launch_pack_bf16(c32, m, ks, d / m, e.aop, e.cmax, s))) return rc;
-  if ((rc = launch_zero_u32(e.qcount, 1, s))) return rc;
-  if ((rc = launch_assign_bf16(x, n, d, m, ks, e.aop, e.cmax, codes, e.queue, e.qcount, s))) return rc;
-  return launch_fixup(x, d, m, ks, c32, e.queue, e.qcount, codes, rescored, s);
+  return launch_assign_bf16(x, n, d, m, ks, e.aop, e.cmax, e.mu, c32, codes, rescored, s);
 }
 
 }  // namespace
@@ -164,14 +157,15 @@ int mipq_pq_fit(const float* x, int64_t n, const int64_t* train_rows, int64_t n_
   double* c64 = codebook64 ? codebook64 : f.c64;
   float* c32 = codebook;   // working float32 codebook, final value on return
   if ((rc = launch_init_codebook(train, nt, d, m, ks, init_codebook ? nullptr : init_rows, init_codebook,
-                                 c64, c32, f.bad, s)))
+                                 c64, c32, f.bad, nullptr, s)))
     return rc;
+  const bool bf = precision == MIPQ_BF16;
+  if (bf && iters > 0 && (rc = launch_pack_bf16(c32, m, ks, ds, f.enc.aop, f.enc.cmax, f.enc.mu, s))) return rc;
   for (int it = 0; it < iters; ++it) {
-    if ((rc = assign_any(train, nt, d, m, ks, c32, precision, codes, f.enc, nullptr, s, true))) return rc;
-    if ((rc = launch_accumulate(train, nt, d, m, ks, codes, c32, f.nch, f.part_s, f.part_cnt, f.part_j, s)))
-      return rc;
-    if ((rc = launch_finalize(m, ks, ds, f.nch, f.part_s, f.part_cnt, f.part_j, c64, c32,
-                              f.j_sub + (size_t)it * m, s)))
+    if ((rc = assign_any(train, nt, d, m, ks, c32, precision, codes, f.enc, nullptr, s))) return rc;
+    // the update also packs the next round's operands (BF16)
+    if ((rc = launch_update(train, nt, d, m, ks, codes, c32, c64, f.nch, f.part_s, f.part_cnt, f.part_j,
+                            f.j_sub + (size_t)it * m, bf ? f.enc.aop : nullptr, f.enc.cmax, f.enc.mu, s)))
       return rc;
   }
   if (objective && (rc = launch_objective(f.j_sub, iters, m, objective, s))) return rc;
@@ -180,7 +174,7 @@ int mipq_pq_fit(const float* x, int64_t n, const int64_t* train_rows, int64_t n_
 
 size_t mipq_pq_encode_workspace_size(int64_t n, int d, int m, int ks, int precision) {
   if (check_shape(n, d, m, ks, precision, false) != MIPQ_OK) return 0;
-  return carve_encode(nullptr, n, d, m, ks, precision).bytes;
+  return carve_encode(nullptr, m, ks, d / m, precision).bytes;
 }
 
 int mipq_pq_encode(const float* x, int64_t n, int d, int m, int ks, const float* codebook,
@@ -190,11 +184,13 @@ int mipq_pq_encode(const float* x, int64_t n, int d, int m, int ks, const float*
   if ((rc = check_shape(n, d, m, ks, precision, false))) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (n > 0 && (!x || !codebook || !codes)) return fail(MIPQ_EINVAL, "x, codebook and codes are required");
-  EncodeWs e = carve_encode(ws, n, d, m, ks, precision);
+  EncodeWs e = carve_encode(ws, m, ks, d / m, precision);
   if (n > 0 && (rc = check_ws(ws, ws_bytes, e.bytes))) return rc;
   if (rescored && (rc = launch_zero_u32(reinterpret_cast<uint32_t*>(rescored), 2, s))) return rc;
   if (n == 0) return MIPQ_OK;
-  return assign_any(x, n, d, m, ks, codebook, precision, codes, e, rescored, s, true);
+  if (precision == MIPQ_BF16 && (rc = launch_pack_bf16(codebook, m, ks, d / m, e.aop, e.cmax, e.mu, s)))
+    return rc;
+  return assign_any(x, n, d, m, ks, codebook, precision, codes, e, rescored, s);
 }
 
 size_t mipq_pq_decode_rmse_workspace_size(int64_t n, int d, int m, int ks) {

@@ -25,6 +25,20 @@ int hip_fail(hipError_t e, const char* what);
     if (e_ != hipSuccess) return ::mipq::hip_fail(e_, what); \
   } while (0)
 
+// ---- per-kernel event timing (see mipq_profile_enable) -----------------------
+class ProfScope {
+ public:
+  ProfScope(int kernel, hipStream_t s);
+  ~ProfScope();
+  ProfScope(const ProfScope&) = delete;
+  ProfScope& operator=(const ProfScope&) = delete;
+
+ private:
+  int kernel_;
+  hipStream_t s_;
+  hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+
 // ---- workspace carving -----------------------------------------------------
 // Sub-buffers are 256-byte aligned; the same carving code sizes and fills.
 struct Carver {
@@ -58,16 +72,14 @@ int launch_gather_rows(const float* x, int64_t n, int d, const int64_t* rows, in
                        float* out, uint32_t* bad, hipStream_t s);
 int launch_init_codebook(const float* train, int64_t n_train, int d, int m, int ks,
                          const int64_t* init_rows, const float* init_cb, double* c64, float* c32,
-                         uint32_t* bad, hipStream_t s);
-int launch_check_flag(const uint32_t* bad, int* host_flag, hipStream_t s);
+                         uint32_t* bad, uint32_t* done, hipStream_t s);
 int launch_assign_fp32(const float* x, int64_t n, int d, int m, int ks, const float* c32,
                        uint8_t* codes, hipStream_t s);
-int accumulate_chunks(int64_t n, int m);
-int launch_accumulate(const float* x, int64_t n, int d, int m, int ks, const uint8_t* codes,
-                      const float* c32, int nch, double* part_s, uint32_t* part_cnt,
-                      double* part_j, hipStream_t s);
-int launch_finalize(int m, int ks, int ds, int nch, const double* part_s, const uint32_t* part_cnt,
-                    const double* part_j, double* c64, float* c32, double* j_sub, hipStream_t s);
+// Lloyd update of one round; aop == NULL: plain path (no operand packing)
+int update_chunks(int64_t n, int m);
+int launch_update(const float* x, int64_t n, int d, int m, int ks, const uint8_t* codes, float* c32,
+                  double* c64, int nch, double* part_s, uint32_t* part_cnt, double* part_j,
+                  double* j_sub, void* aop, float* cmax, float* mu, hipStream_t s);
 int launch_objective(const double* j_sub, int iters, int m, double* objective, hipStream_t s);
 int launch_copy_f64(const double* src, double* dst, size_t count, hipStream_t s);
 int launch_decode_sse(const uint8_t* codes, int64_t n, int d, int m, int ks, const float* c32,
@@ -76,12 +88,20 @@ int decode_blocks(int64_t n, int m);
 int launch_sse_final(const double* partials, int nblk, int64_t n, int d, double* out, hipStream_t s);
 
 // BF16 matrix-core path
+struct Bf16Geom {
+  int groups = 1;    // blocks of 4 subspaces
+  int rpb = 32;      // rows per block (multiple of 32)
+  int rowblks = 0;   // row blocks covering n
+  int blocks = 0;    // launched blocks (XCD-padded)
+};
+Bf16Geom bf16_geometry(int64_t n, int m);
 size_t bf16_operand_count(int m, int ks, int ds);   // number of 16-byte operand slots
-int launch_pack_bf16(const float* c32, int m, int ks, int ds, void* aop, float* cmax, hipStream_t s);
+// operands of the centred codebook; mu: m * kMaxDsBf16 floats (subspace centres)
+int launch_pack_bf16(const float* c32, int m, int ks, int ds, void* aop, float* cmax, float* mu,
+                     hipStream_t s);
+// rescored: optional int64 counter, incremented by the pairs re-decided exactly
 int launch_assign_bf16(const float* x, int64_t n, int d, int m, int ks, const void* aop,
-                       const float* cmax, uint8_t* codes, uint32_t* queue, uint32_t* qcount,
-                       hipStream_t s);
-int launch_fixup(const float* x, int d, int m, int ks, const float* c32, const uint32_t* queue,
-                 const uint32_t* qcount, uint8_t* codes, int64_t* rescored_total, hipStream_t s);
+                       const float* cmax, const float* mu, const float* c32, uint8_t* codes,
+                       int64_t* rescored, hipStream_t s);
 
 }  // namespace mipq

@@ -55,9 +55,11 @@ __global__ void k_gather_rows(const float* __restrict__ x, int64_t n, int d,
 __global__ void k_init_codebook(const float* __restrict__ train, int64_t n_train, int d, int m,
                                 int ks, const int64_t* __restrict__ init_rows,
                                 const float* __restrict__ init_cb, double* __restrict__ c64,
-                                float* __restrict__ c32, uint32_t* bad) {
+                                float* __restrict__ c32, uint32_t* bad, uint32_t* done) {
   const int ds = d / m;
   const int64_t total = (int64_t)m * ks * ds;
+  if (done && blockIdx.x == 0)
+    for (int j = threadIdx.x; j < m; j += blockDim.x) done[j] = 0u;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
     float v;
@@ -126,89 +128,6 @@ __device__ __forceinline__ double block_sum_f64(double v, double* red) {
   return s;   // valid on thread 0
 }
 
-// Float64 centroid sums and counts of one subspace over one row chunk, in LDS;
-// the chunk partials are summed in a fixed order by k_finalize.  Also the
-// objective: the float32 distance of each row to its assigned centroid.
-template <int DS>
-__global__ __launch_bounds__(kThreads) void k_accumulate(const float* __restrict__ x, int64_t n,
-                                                         int d, int m, int ks, int ds_rt,
-                                                         const uint8_t* __restrict__ codes,
-                                                         const float* __restrict__ c32, int64_t rpc,
-                                                         double* __restrict__ part_s,
-                                                         uint32_t* __restrict__ part_cnt,
-                                                         double* __restrict__ part_j) {
-  extern __shared__ double smem[];
-  const int ds = DS ? DS : ds_rt;
-  constexpr int CAP = DS ? DS : kMaxDsFit;
-  double* S = smem;
-  uint32_t* cnt = reinterpret_cast<uint32_t*>(S + (size_t)ks * ds);
-  double* red = S + (size_t)ks * ds + (ks + 1) / 2;
-  const int c = blockIdx.x, sub = blockIdx.y;
-  for (int i = threadIdx.x; i < ks * ds; i += blockDim.x) S[i] = 0.0;
-  for (int i = threadIdx.x; i < ks; i += blockDim.x) cnt[i] = 0u;
-  __syncthreads();
-  const int64_t r0 = (int64_t)c * rpc;
-  const int64_t r1 = min(n, r0 + rpc);
-  const float* cb = c32 + (int64_t)sub * ks * ds;
-  double jl = 0.0;
-  for (int64_t row = r0 + threadIdx.x; row < r1; row += blockDim.x) {
-    const int code = codes[row * m + sub];
-    const float* xr = x + row * d + (int64_t)sub * ds;
-    float xv[CAP];
-#pragma unroll
-    for (int t = 0; t < CAP; ++t) xv[t] = (t < ds) ? xr[t] : 0.0f;
-    if (code >= ks) {       // corrupt code: poison the objective, touch nothing
-      jl += NAN;
-      continue;
-    }
-    const float dd = DS ? sqdist_fixed<DS>(xv, cb + code * DS) : sqdist_rt(xv, cb + code * ds, ds);
-    jl += (double)dd;
-#pragma unroll
-    for (int t = 0; t < CAP; ++t)
-      if (t < ds) atomicAdd(&S[code * ds + t], (double)xv[t]);
-    atomicAdd(&cnt[code], 1u);
-  }
-  const double js = block_sum_f64(jl, red);
-  __syncthreads();
-  const size_t base = ((size_t)c * m + sub);
-  for (int i = threadIdx.x; i < ks * ds; i += blockDim.x) part_s[base * ks * ds + i] = S[i];
-  for (int i = threadIdx.x; i < ks; i += blockDim.x) part_cnt[base * ks + i] = cnt[i];
-  if (threadIdx.x == 0) part_j[base] = js;
-}
-
-// Lloyd update of one subspace: centroid = float64 sum / count over all chunks
-// (fixed chunk order), an empty centroid keeps its value; float32 copy by
-// round-to-nearest.  Also the subspace's objective for this round.
-__global__ __launch_bounds__(kThreads) void k_finalize(int m, int ks, int ds, int nch,
-                                                       const double* __restrict__ part_s,
-                                                       const uint32_t* __restrict__ part_cnt,
-                                                       const double* __restrict__ part_j,
-                                                       double* __restrict__ c64,
-                                                       float* __restrict__ c32,
-                                                       double* __restrict__ j_sub) {
-  const int sub = blockIdx.x;
-  const size_t per = (size_t)ks * ds;
-  for (int i = threadIdx.x; i < ks * ds; i += blockDim.x) {
-    const int k = i / ds;
-    double s = 0.0;
-    uint64_t cn = 0;
-    for (int c = 0; c < nch; ++c) {
-      const size_t base = (size_t)c * m + sub;
-      s += part_s[base * per + i];
-      cn += part_cnt[base * ks + k];
-    }
-    const size_t o = (size_t)sub * per + i;
-    const double v = cn ? s / (double)cn : c64[o];
-    c64[o] = v;
-    c32[o] = (float)v;
-  }
-  if (threadIdx.x == 0) {
-    double j = 0.0;
-    for (int c = 0; c < nch; ++c) j += part_j[(size_t)c * m + sub];
-    j_sub[sub] = j;
-  }
-}
-
 __global__ void k_objective(const double* __restrict__ j_sub, int iters, int m, double* objective) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= iters) return;
@@ -223,8 +142,11 @@ __global__ void k_copy_f64(const double* __restrict__ src, double* __restrict__ 
     dst[i] = src[i];
 }
 
-// Decode (concatenate coded centroids) and the float64 squared error, one
-// thread per (row, subspace); per-block partial sums, reduced in block order.
+// Decode (concatenate coded centroids) and the float64 squared error.  VEC:
+// one thread per 4 consecutive elements of a row (ds % 4 == 0, so the four lie
+// in one subspace): 16-byte loads and stores.  Otherwise one thread per
+// element.  Per-block partial sums, reduced in a fixed order.
+template <int VEC>
 __global__ __launch_bounds__(kThreads) void k_decode_sse(const uint8_t* __restrict__ codes,
                                                          int64_t n, int d, int m, int ks, int ds,
                                                          const float* __restrict__ c32,
@@ -233,25 +155,43 @@ __global__ __launch_bounds__(kThreads) void k_decode_sse(const uint8_t* __restri
                                                          double* __restrict__ partials) {
   __shared__ double red[kThreads / 64];
   double acc = 0.0;
-  const int64_t pairs = n * m;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < pairs;
+  const int per_row = d / VEC;
+  const int64_t items = n * per_row;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < items;
        p += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = p / m;
-    const int sub = int(p - row * m);
-    const int code = codes[p];
-    const int64_t off = row * d + (int64_t)sub * ds;
-    if (code >= ks) {
-      if (x_hat)
-        for (int t = 0; t < ds; ++t) x_hat[off + t] = NAN;
-      acc += NAN;
-      continue;
+    const int64_t row = p / per_row;
+    const int col = int(p - row * per_row) * VEC;
+    const int sub = col / ds;
+    const int t = col - sub * ds;
+    const int code = codes[row * m + sub];
+    const int64_t off = row * d + col;
+    float cv[VEC];
+    const bool ok = code < ks;
+    const float* c = c32 + ((int64_t)sub * ks + (ok ? code : 0)) * ds + t;
+    if (VEC == 4) {
+      const float4 q = *reinterpret_cast<const float4*>(c);
+      cv[0] = q.x; cv[VEC > 1 ? 1 : 0] = q.y; cv[VEC > 2 ? 2 : 0] = q.z; cv[VEC > 3 ? 3 : 0] = q.w;
+    } else {
+      cv[0] = c[0];
     }
-    const float* c = c32 + ((int64_t)sub * ks + code) * ds;
-    for (int t = 0; t < ds; ++t) {
-      const float cv = c[t];
-      if (x_hat) x_hat[off + t] = cv;
-      if (x) {
-        const double df = (double)x[off + t] - (double)cv;
+    if (!ok)
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) cv[i] = NAN;
+    if (x_hat) {
+      if (VEC == 4) *reinterpret_cast<float4*>(x_hat + off) = make_float4(cv[0], cv[VEC > 1 ? 1 : 0], cv[VEC > 2 ? 2 : 0], cv[VEC > 3 ? 3 : 0]);
+      else x_hat[off] = cv[0];
+    }
+    if (x) {
+      float xv[VEC];
+      if (VEC == 4) {
+        const float4 q = *reinterpret_cast<const float4*>(x + off);
+        xv[0] = q.x; xv[VEC > 1 ? 1 : 0] = q.y; xv[VEC > 2 ? 2 : 0] = q.z; xv[VEC > 3 ? 3 : 0] = q.w;
+      } else {
+        xv[0] = x[off];
+      }
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) {
+        const double df = (double)xv[i] - (double)cv[i];
         acc += df * df;
       }
     }
@@ -260,14 +200,25 @@ __global__ __launch_bounds__(kThreads) void k_decode_sse(const uint8_t* __restri
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-__global__ void k_sse_final(const double* __restrict__ partials, int nblk, int64_t n, int d,
-                            double* out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Sum of the block partials: thread i adds partials i, i+256, ... in order,
+// then a fixed pairwise tree over the threads.
+__global__ __launch_bounds__(kThreads) void k_sse_final(const double* __restrict__ partials, int nblk,
+                                                        int64_t n, int d, double* out) {
+  __shared__ double red[kThreads];
   double s = 0.0;
-  for (int i = 0; i < nblk; ++i) s += partials[i];
-  out[0] = s;
-  const double cnt = (double)n * (double)d;
-  out[1] = cnt > 0 ? sqrt(s / cnt) : 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += partials[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double tot = red[0];
+    out[0] = tot;
+    const double cnt = (double)n * (double)d;
+    out[1] = cnt > 0 ? sqrt(tot / cnt) : 0.0;
+  }
 }
 
 int grid_for(int64_t work, int per_block, int cap) {
@@ -295,10 +246,10 @@ int launch_gather_rows(const float* x, int64_t n, int d, const int64_t* rows, in
 
 int launch_init_codebook(const float* train, int64_t n_train, int d, int m, int ks,
                          const int64_t* init_rows, const float* init_cb, double* c64, float* c32,
-                         uint32_t* bad, hipStream_t s) {
+                         uint32_t* bad, uint32_t* done, hipStream_t s) {
   const int64_t total = (int64_t)d * ks;   // m * ks * ds
   k_init_codebook<<<grid_for(total, kThreads, 4096), kThreads, 0, s>>>(train, n_train, d, m, ks, init_rows,
-                                                                       init_cb, c64, c32, bad);
+                                                                       init_cb, c64, c32, bad, done);
   MIPQ_LAUNCHED("k_init_codebook");
   return MIPQ_OK;
 }
@@ -323,42 +274,12 @@ int launch_assign_fp32(const float* x, int64_t n, int d, int m, int ks, const fl
   const int groups = ceil_div(m, 4);
   const int rowblks = ceil_div(n, 64);
   const int blocks = ceil_div(rowblks, 8) * 8 * groups;
+  ProfScope ps(MIPQ_K_ASSIGN_FP32, s);
 #define CALL(DSV) \
   k_assign_fp32<DSV><<<blocks, kThreads, 0, s>>>(x, n, d, m, ks, ds, c32, codes, groups)
   MIPQ_DS_SWITCH(ds, CALL)
 #undef CALL
   MIPQ_LAUNCHED("k_assign_fp32");
-  return MIPQ_OK;
-}
-
-int accumulate_chunks(int64_t n, int m) {
-  int nch = ceil_div(n, 2048);
-  if (nch < 1) nch = 1;
-  const int cap = m >= 16 ? 64 : 128;
-  return nch > cap ? cap : nch;
-}
-
-int launch_accumulate(const float* x, int64_t n, int d, int m, int ks, const uint8_t* codes,
-                      const float* c32, int nch, double* part_s, uint32_t* part_cnt,
-                      double* part_j, hipStream_t s) {
-  const int ds = d / m;
-  const int64_t rpc = (n + nch - 1) / nch;
-  const size_t shm = (size_t)ks * ds * sizeof(double) + ((ks + 1) / 2) * sizeof(double) +
-                     (kThreads / 64) * sizeof(double);
-  dim3 grid(nch, m);
-#define CALL(DSV)                                                                              \
-  k_accumulate<DSV><<<grid, kThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, part_s, \
-                                                part_cnt, part_j)
-  MIPQ_DS_SWITCH(ds, CALL)
-#undef CALL
-  MIPQ_LAUNCHED("k_accumulate");
-  return MIPQ_OK;
-}
-
-int launch_finalize(int m, int ks, int ds, int nch, const double* part_s, const uint32_t* part_cnt,
-                    const double* part_j, double* c64, float* c32, double* j_sub, hipStream_t s) {
-  k_finalize<<<m, kThreads, 0, s>>>(m, ks, ds, nch, part_s, part_cnt, part_j, c64, c32, j_sub);
-  MIPQ_LAUNCHED("k_finalize");
   return MIPQ_OK;
 }
 
@@ -380,13 +301,20 @@ int decode_blocks(int64_t n, int m) { return grid_for(n * m, kThreads, 2048); }
 
 int launch_decode_sse(const uint8_t* codes, int64_t n, int d, int m, int ks, const float* c32,
                       const float* x, float* x_hat, double* partials, int nblk, hipStream_t s) {
-  k_decode_sse<<<nblk, kThreads, 0, s>>>(codes, n, d, m, ks, d / m, c32, x, x_hat, partials);
+  ProfScope ps(MIPQ_K_DECODE, s);
+  const int ds = d / m;
+  const bool vec = (ds % 4 == 0) && ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(x_hat) |
+                                      reinterpret_cast<uintptr_t>(c32)) & 15) == 0;
+  if (vec)
+    k_decode_sse<4><<<nblk, kThreads, 0, s>>>(codes, n, d, m, ks, ds, c32, x, x_hat, partials);
+  else
+    k_decode_sse<1><<<nblk, kThreads, 0, s>>>(codes, n, d, m, ks, ds, c32, x, x_hat, partials);
   MIPQ_LAUNCHED("k_decode_sse");
   return MIPQ_OK;
 }
 
 int launch_sse_final(const double* partials, int nblk, int64_t n, int d, double* out, hipStream_t s) {
-  k_sse_final<<<1, 64, 0, s>>>(partials, nblk, n, d, out);
+  k_sse_final<<<1, kThreads, 0, s>>>(partials, nblk, n, d, out);
   MIPQ_LAUNCHED("k_sse_final");
   return MIPQ_OK;
 }

@@ -9,8 +9,9 @@
 // 32x32x16 bfloat16 MFMAs with float32 accumulation:
 //   * x and -2c are split into high and low bfloat16 parts (v = hi + lo + e,
 //     |e| <= 2^-16 |v|); the MFMA sums hi*hi + hi*lo + lo*hi over the
-//     dimensions, and ||c||^2 enters the same contraction as three bfloat16
-//     pieces multiplied by ones, so the accumulator starts at zero;
+//     dimensions, and ||c||^2 and ||x||^2 enter the same contraction as three
+//     bfloat16 pieces each multiplied by ones, so the accumulator starts at
+//     zero and ends at an estimate of the distance itself (>= -error);
 //   * layout: A = centroid operands (32 centroids x K), B = row operands
 //     (K x 32 rows); lane l receives row l%32 and, for each of the 8 tiles
 //     of 32 centroids, 16 scores (centroids 8*(r/4) + 4*(l/32) + r%4);
@@ -20,12 +21,12 @@
 //     one lane differ in tile or in register);
 //   * the lane pair (l, l^32) merges; if the gap between best and runner-up
 //     does not exceed a proven bound on the error of the scores plus the
-//     rounding of the exact rule, the (row, subspace) goes to a queue and
-//     k_fixup re-decides it with the exact float32 rule.  Otherwise the
-//     matrix-core winner IS the exact rule's unique winner.
+//     rounding of the exact rule, the whole wave re-decides that (row,
+//     subspace) with the exact float32 rule.  Otherwise the matrix-core winner
+//     IS the exact rule's unique winner.
 #include <math.h>
 
-#include "dist32.h"
+#include "bf16_pack.h"
 #include "mipq_internal.h"
 
 namespace mipq {
@@ -38,109 +39,6 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kThreads = 256;   // 4 waves, one subspace each
-
-// ---- operand encoding (shared by the packer and the row side) --------------
-// MFMA f of a tile, for NB 8-dimension blocks (see bf16_nmfma):
-//   f <  NB           : A = [hi_f | lo_f]         B = [xh_f | xh_f]
-//   f <  NB+(NB+1)/2  : pair p = f-NB, block b = 2p + half
-//                       b < NB: A = hi_b, B = xl_b ; else A = norm, B = ones
-//   otherwise         : A = [norm | 0]            B = [ones | 0]
-// "half" is lane/32: lanes 0-31 supply K columns 0-7, lanes 32-63 columns 8-15.
-
-__device__ __forceinline__ uint16_t bf16_bits_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
-
-struct Pack8 {
-  uint16_t v[8];
-};
-
-__device__ __forceinline__ void store_pack(uint4* dst, const Pack8& p) {
-  uint4 q;
-  q.x = (uint32_t)p.v[0] | ((uint32_t)p.v[1] << 16);
-  q.y = (uint32_t)p.v[2] | ((uint32_t)p.v[3] << 16);
-  q.z = (uint32_t)p.v[4] | ((uint32_t)p.v[5] << 16);
-  q.w = (uint32_t)p.v[6] | ((uint32_t)p.v[7] << 16);
-  *dst = q;
-}
-
-// One block per subspace: writes its NT*NMF*64 operand slots and the largest
-// centroid norm (rounded up), used by the error bound.
-template <int NB>
-__global__ __launch_bounds__(kThreads) void k_pack_bf16(const float* __restrict__ c32, int m, int ks,
-                                                        int ds, int nt, uint4* __restrict__ aop,
-                                                        float* __restrict__ cmax) {
-  constexpr int NMF = bf16_nmfma(NB);
-  __shared__ float red[kThreads];
-  const int sub = blockIdx.x;
-  const int slots = nt * NMF * 64;
-  for (int s = threadIdx.x; s < slots; s += blockDim.x) {
-    const int l = s & 63;
-    const int f = (s >> 6) % NMF;
-    const int t = s / (NMF * 64);
-    const int i = l & 31, half = l >> 5;
-    const int k = t * 32 + i;
-    const bool real = k < ks;
-    float hi[NB * 8], lo[NB * 8];
-    double cn = 0.0;
-#pragma unroll
-    for (int e = 0; e < NB * 8; ++e) {
-      const float c = (real && e < ds) ? c32[((size_t)sub * ks + k) * ds + e] : 0.0f;
-      cn += (double)c * (double)c;
-      const float v = -2.0f * c;
-      const uint16_t h = bf16_bits_rne(v);
-      hi[e] = bf16_bits_to_f32(h);
-      lo[e] = bf16_bits_to_f32(bf16_bits_rne(v - hi[e]));
-    }
-    Pack8 norm = {};
-    if (real) {
-      const uint16_t h = bf16_bits_rne((float)cn);
-      const double r1 = cn - (double)bf16_bits_to_f32(h);
-      const uint16_t md = bf16_bits_rne((float)r1);
-      const double r2 = r1 - (double)bf16_bits_to_f32(md);
-      norm.v[0] = h;
-      norm.v[1] = md;
-      norm.v[2] = bf16_bits_rne((float)r2);
-    } else {
-      norm.v[0] = 0x7F80u;   // +inf: padded centroids never win
-    }
-    Pack8 out = {};
-    auto block_of = [&](const float* src, int b) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) out.v[e] = bf16_bits_rne(src[b * 8 + e]);
-    };
-    if (f < NB) {
-      block_of(half ? lo : hi, f);
-    } else if (f < NB + (NB + 1) / 2) {
-      const int b = 2 * (f - NB) + half;
-      if (b < NB) block_of(hi, b);
-      else out = norm;
-    } else {
-      if (!half) out = norm;
-    }
-    store_pack(aop + ((size_t)(sub * nt + t) * NMF + f) * 64 + l, out);
-  }
-  // largest centroid norm of the subspace
-  float mx = 0.0f;
-  for (int k = threadIdx.x; k < ks; k += blockDim.x) {
-    double cn = 0.0;
-    for (int e = 0; e < ds; ++e) {
-      const double c = c32[((size_t)sub * ks + k) * ds + e];
-      cn += c * c;
-    }
-    mx = fmaxf(mx, (float)(sqrt(cn) * (1.0 + 1e-6)));
-  }
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) cmax[sub] = red[0];
-}
 
 // ---- row side --------------------------------------------------------------
 __device__ __forceinline__ bf16x8 to_bf16x8(const float* v) {
@@ -163,15 +61,23 @@ __device__ __forceinline__ float min16(const f32x16& a) {
   const float m2 = min3f(a[6], a[7], a[8]);
   const float m3 = min3f(a[9], a[10], a[11]);
   const float m4 = min3f(a[12], a[13], a[14]);
-  return min3f(min3f(m0, m1, m2), min3f(m3, m4, a[15]), INFINITY);
+  return fminf(min3f(m0, m1, m2), min3f(m3, m4, a[15]));
 }
 
+// signed-integer key: the float's bits with its low bits replaced by an index;
+// for non-negative floats integer order is float order (up to the replaced bits)
 __device__ __forceinline__ int key_of(float v, int mask, int idx) {
   return (__float_as_int(v) & mask) | idx;
 }
 
 // median of three signed ints (v_med3_i32)
 __device__ __forceinline__ int med3i(int a, int b, int c) { return max(min(a, b), min(max(a, b), c)); }
+
+// values of lane l%32 (.x) and lane 32 + l%32 (.y), for every lane
+__device__ __forceinline__ int2 halves(int v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return make_int2((int)r[0], (int)r[1]);
+}
 
 struct XcdMap {
   int rowblk, group;
@@ -185,12 +91,58 @@ __device__ __forceinline__ XcdMap xcd_map(int lin, int groups) {
   return r;
 }
 
+// One wave = one subspace over the rows of one row block, 32 rows at a time.
+// Ambiguous (row, subspace) pairs are re-decided by the wave with the exact
+// rule; their number is added to *rescored when that is non-NULL.
+// Exact float32 rule for one (row, subspace) by the whole wave: lane i scans
+// centroids i, i+64, ... in ascending order, then a lexicographic (distance,
+// index) minimum over the lanes.  Dimensions t >= ds contribute exact zeros, so
+// the sums equal the ds-term sums of the plain path bit for bit.
+template <int DW>
+__device__ __forceinline__ int exact_code_wave(const float* __restrict__ xr, const float* __restrict__ cb,
+                                               int ds, int ks, int lane) {
+  float xo[DW];
+#pragma unroll
+  for (int t = 0; t < DW; ++t) {
+    const float v = xr[t < ds ? t : ds - 1];
+    xo[t] = t < ds ? v : 0.0f;
+  }
+  float best = INFINITY;
+  int bk = 0x7FFFFFFF;
+  for (int k = lane; k < ks; k += 64) {
+    const float* c = cb + (int64_t)k * ds;
+    float acc = 0.0f;
+#pragma unroll
+    for (int t = 0; t < DW; ++t) {
+      const float cv = c[t < ds ? t : ds - 1];
+      const float df = xo[t] - (t < ds ? cv : 0.0f);
+      const float sq = df * df;
+      acc = acc + sq;
+    }
+    if (acc < best) {
+      best = acc;
+      bk = k;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const float ob = __shfl_xor(best, off, 64);
+    const int ok = __shfl_xor(bk, off, 64);
+    if (ob < best || (ob == best && ok < bk)) {
+      best = ob;
+      bk = ok;
+    }
+  }
+  return bk < ks ? bk : 0;
+}
+
 template <int NB, int NT, bool FULL>
 __global__ __launch_bounds__(kThreads) void k_assign_bf16(
     const float* __restrict__ x, int64_t n, int d, int m, int ks, int ds,
-    const bf16x8* __restrict__ aop, const float* __restrict__ cmax, uint8_t* __restrict__ codes,
-    uint32_t* __restrict__ queue, uint32_t* __restrict__ qcount, int groups, int tiles_per_block,
-    float e_cross, float e_norm, float g_exact) {
+    const bf16x8* __restrict__ aop, const float* __restrict__ cmax, const float* __restrict__ mu,
+    const float* __restrict__ c32, uint8_t* __restrict__ codes,
+    unsigned long long* __restrict__ rescored, int groups, int rpb, float e_cross, float e_norm,
+    float g_exact) {
   constexpr int NMF = bf16_nmfma(NB);
   constexpr int DW = NB * 8;
   const XcdMap bm = xcd_map(blockIdx.x, groups);
@@ -198,10 +150,10 @@ __global__ __launch_bounds__(kThreads) void k_assign_bf16(
   const int half = lane >> 5;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int sub = bm.group * 4 + w;
-  const int64_t rows_per_block = (int64_t)tiles_per_block * 32;
-  const int64_t rbeg = (int64_t)bm.rowblk * rows_per_block;
+  const int64_t rbeg = (int64_t)bm.rowblk * rpb;
   if (sub >= m || rbeg >= n) return;
-  const int64_t rend = min(n, rbeg + rows_per_block);
+  const int64_t rend = min(n, rbeg + rpb);
+  const float* cbsub = c32 + (int64_t)sub * ks * ds;
 
   // centroid operands of this subspace stay in registers for the whole block
   bf16x8 A[NT][NMF];
@@ -210,18 +162,15 @@ __global__ __launch_bounds__(kThreads) void k_assign_bf16(
 #pragma unroll
     for (int f = 0; f < NMF; ++f) A[t][f] = aop[((size_t)(sub * NT + t) * NMF + f) * 64 + lane];
   const float cm = cmax[sub];
-
-  bf16x8 ones = {};
-  ones[0] = (__bf16)1.0f;
-  ones[1] = (__bf16)1.0f;
-  ones[2] = (__bf16)1.0f;
+  float muv[DW];   // subspace centre, held in scalar registers (wave-uniform)
+#pragma unroll
+  for (int e = 0; e < DW; ++e)
+    muv[e] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(mu[sub * kMaxDsBf16 + e])));
   const bf16x8 zero8 = {};
 
-  for (int64_t r0 = rbeg; r0 < rend; r0 += 32) {
+  auto load_rows = [&](float* xv, int64_t r0) {
     const int64_t row = r0 + (lane & 31);
-    const bool valid = row < rend;
-    const float* xr = x + (valid ? row : r0) * d + (int64_t)sub * ds;
-    float xv[DW];
+    const float* xr = x + (row < rend ? row : r0) * d + (int64_t)sub * ds;
     if (FULL) {   // ds == DW and 16-byte aligned rows: vector loads
 #pragma unroll
       for (int e = 0; e < DW; e += 4) {
@@ -231,10 +180,30 @@ __global__ __launch_bounds__(kThreads) void k_assign_bf16(
         xv[e + 2] = v.z;
         xv[e + 3] = v.w;
       }
-    } else {
+    } else {   // clamped loads, then zero the padding dimensions
 #pragma unroll
-      for (int e = 0; e < DW; ++e) xv[e] = (e < ds) ? xr[e] : 0.0f;
+      for (int e = 0; e < DW; ++e) {
+        const float v = xr[e < ds ? e : ds - 1];
+        xv[e] = (e < ds) ? v : 0.0f;
+      }
     }
+  };
+
+  uint32_t nres = 0;   // pairs this wave re-decided with the exact rule
+  // rows of this wave awaiting the exact rule, decided after the main loop so
+  // that it stays lean (LDS: rpb entries per wave, so the list cannot overflow)
+  extern __shared__ uint32_t pend_all[];
+  uint32_t* pend = pend_all + w * rpb;
+  int np = 0;
+  float xnext[DW];
+  load_rows(xnext, rbeg);
+  for (int64_t r0 = rbeg; r0 < rend; r0 += 32) {
+    const int64_t row = r0 + (lane & 31);
+    const bool valid = row < rend;
+    float xv[DW];   // centred row slice
+#pragma unroll
+    for (int e = 0; e < DW; ++e) xv[e] = xnext[e] - muv[e];
+    if (r0 + 32 < rend) load_rows(xnext, r0 + 32);   // next tile's rows in flight
 
     // row operands
     float xn = 0.0f;
@@ -249,6 +218,16 @@ __global__ __launch_bounds__(kThreads) void k_assign_bf16(
       for (int e = 0; e < 8; ++e) rem[e] = xv[b * 8 + e] - (float)XH[b][e];
       XL[b] = to_bf16x8(rem);
     }
+    bf16x8 normB = {};
+    {
+      const __bf16 h = (__bf16)xn;
+      const float r1 = xn - (float)h;
+      const __bf16 md = (__bf16)r1;
+      normB[0] = normB[1] = normB[2] = (__bf16)1.0f;
+      normB[3] = h;
+      normB[4] = md;
+      normB[5] = (__bf16)(r1 - (float)md);
+    }
     bf16x8 B[NMF];
 #pragma unroll
     for (int f = 0; f < NMF; ++f) {
@@ -257,134 +236,95 @@ __global__ __launch_bounds__(kThreads) void k_assign_bf16(
       } else if (f < NB + (NB + 1) / 2) {
         const int b0 = 2 * (f - NB);
         if (b0 + 1 < NB) B[f] = half ? XL[b0 + 1] : XL[b0];
-        else B[f] = half ? ones : XL[b0];
+        else B[f] = half ? normB : XL[b0];
       } else {
-        B[f] = half ? zero8 : ones;
+        B[f] = half ? zero8 : normB;
       }
     }
+    auto tile = [&](int t) {
+      f32x16 acc = {};
+#pragma unroll
+      for (int f = 0; f < NMF; ++f) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[t][f], B[f], acc, 0, 0, 0);
+      return acc;
+    };
 
-    // scores, reduced by tile (amin) and by accumulator register (bmin)
+    // distance estimates, reduced by tile (amin) and by accumulator register (bmin)
     float amin[NT];
     float bmin[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) bmin[r] = INFINITY;
 #pragma unroll
     for (int t = 0; t < NT; t += 2) {
-      f32x16 acc0 = {};
-#pragma unroll
-      for (int f = 0; f < NMF; ++f) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[t][f], B[f], acc0, 0, 0, 0);
-      amin[t] = min16(acc0);
+      const f32x16 c0 = tile(t);
+      amin[t] = min16(c0);
       if (t + 1 < NT) {
-        f32x16 acc1 = {};
+        const f32x16 c1 = tile(t + 1 < NT ? t + 1 : 0);
+        amin[t + 1] = min16(c1);
 #pragma unroll
-        for (int f = 0; f < NMF; ++f)
-          acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[t + 1][f], B[f], acc1, 0, 0, 0);
-        amin[t + 1] = min16(acc1);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) bmin[r] = min3f(bmin[r], acc0[r], acc1[r]);
+        for (int r = 0; r < 16; ++r) bmin[r] = min3f(bmin[r], c0[r], c1[r]);
       } else {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) bmin[r] = fminf(bmin[r], acc0[r]);
+        for (int r = 0; r < 16; ++r) bmin[r] = fminf(bmin[r], c0[r]);
       }
     }
 
-    // shift to distances (>= -error) and order as signed integers; the low
-    // bits carry the tile (3 bits) or the register (4 bits)
+    // smallest two keys of each grouping; the low bits carry the tile
+    // (3 bits) or the register (4 bits)
     int a1 = INT_MAX, a2 = INT_MAX, b1 = INT_MAX, b2 = INT_MAX;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const int k = key_of(amin[t] + xn, ~7, t);
+      const int k = key_of(amin[t], ~7, t);
       a2 = min(a2, max(a1, k));
       a1 = min(a1, k);
     }
 #pragma unroll
     for (int r = 0; r < 16; r += 2) {
-      const int ka = key_of(bmin[r] + xn, ~15, r);
-      const int kb = key_of(bmin[r + 1] + xn, ~15, r + 1);
+      const int ka = key_of(bmin[r], ~15, r);
+      const int kb = key_of(bmin[r + 1], ~15, r + 1);
       b2 = min(b2, med3i(ka, kb, b1));   // runner-up of {b1, b2, ka, kb}, b1 <= b2
       b1 = min(b1, min(ka, kb));
     }
     const int rl = b1 & 15;
     const int s2 = min(a2, b2);
 
-    // merge with the lane holding the other 128 candidates of this row
-    const int pa1 = __shfl_xor(a1, 32, 64);
-    const int ps2 = __shfl_xor(s2, 32, 64);
-    const int prl = __shfl_xor(rl, 32, 64);
-    const bool mine = (a1 < pa1) || (a1 == pa1 && half == 0);
-    const int w1 = min(a1, pa1);
-    const int sec = min(max(a1, pa1), min(s2, ps2));
-    const int tw = (mine ? a1 : pa1) & 7;
-    const int rw = mine ? rl : prl;
-    const int hw = mine ? half : (half ^ 1);
-    const int code = tw * 32 + (rw >> 2) * 8 + hw * 4 + (rw & 3);
+    // merge the two lanes holding the 256 candidates of a row
+    const int2 A1 = halves(a1);
+    const int2 S2 = halves(s2);
+    const int2 RL = halves(rl);
+    const bool hiw = A1.y < A1.x;
+    const int w1 = min(A1.x, A1.y);
+    const int sec = min(max(A1.x, A1.y), min(S2.x, S2.y));
+    const int tw = (hiw ? A1.y : A1.x) & 7;
+    const int rw = hiw ? RL.y : RL.x;
+    const int code = tw * 32 + (rw >> 2) * 8 + (hiw ? 4 : 0) + (rw & 3);
 
     const float f1 = __int_as_float(w1);
     const float f2 = __int_as_float(sec);
     const float xnorm = sqrtf(xn) * 1.0001f;
-    const float beta = e_cross * xnorm * cm + e_norm * cm * cm;
+    const float beta = e_cross * xnorm * cm + e_norm * (cm * cm + xn);
     const float q = 3.815e-6f + g_exact;                       // 2^-18 + gamma
     const float thr = 2.0f * beta + q * (fabsf(f1) + fabsf(f2)) +
                       2.0f * g_exact * (beta + g_exact * xn);
     const float gap = f2 - f1;
     const bool amb = !(gap > thr) || code >= ks;
 
+    // rows whose two best candidates are not separated are re-decided by the
+    // whole wave with the exact rule (rare); their codes are overwritten then
     if (half == 0 && valid) codes[row * m + sub] = (uint8_t)code;
     const bool push = (half == 0) && valid && amb;
     const uint64_t mask = __ballot(push);
     if (mask) {
-      uint32_t base = 0;
-      if (lane == 0) base = atomicAdd(qcount, (uint32_t)__popcll(mask));
-      base = __shfl(base, 0, 64);
-      if (push) {
-        const uint32_t below = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-        queue[base + below] = (uint32_t)(row * m + sub);
-      }
+      if (push) pend[np + __popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)(row - rbeg);
+      np += __popcll(mask);
     }
   }
-}
-
-// Exact re-decision of queued (row, subspace) pairs: one wave per pair, the
-// float32 rule over all centroids, lowest index on ties.
-template <int DS>
-__global__ __launch_bounds__(kThreads) void k_fixup(const float* __restrict__ x, int d, int m, int ks,
-                                                    const float* __restrict__ c32,
-                                                    const uint32_t* __restrict__ queue,
-                                                    const uint32_t* __restrict__ qcount,
-                                                    uint8_t* __restrict__ codes,
-                                                    unsigned long long* __restrict__ total) {
-  const uint32_t cnt = *qcount;
-  if (total && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(total, (unsigned long long)cnt);
-  const int lane = threadIdx.x & 63;
-  const uint32_t wid = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const uint32_t nw = gridDim.x * (blockDim.x >> 6);
-  for (uint32_t e = wid; e < cnt; e += nw) {
-    const uint32_t pr = queue[e];
-    const uint32_t row = pr / (uint32_t)m;
-    const int sub = int(pr - row * (uint32_t)m);
-    const float* xr = x + (int64_t)row * d + (int64_t)sub * DS;
-    float xv[DS];
-#pragma unroll
-    for (int t = 0; t < DS; ++t) xv[t] = xr[t];
-    float best = INFINITY;
-    int bk = 0x7FFFFFFF;
-    for (int k = lane; k < ks; k += 64) {
-      const float dk = sqdist_fixed<DS>(xv, c32 + ((int64_t)sub * ks + k) * DS);
-      if (dk < best) {
-        best = dk;
-        bk = k;
-      }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      const float ob = __shfl_xor(best, off, 64);
-      const int ok = __shfl_xor(bk, off, 64);
-      if (ob < best || (ob == best && ok < bk)) {
-        best = ob;
-        bk = ok;
-      }
-    }
-    if (lane == 0) codes[pr] = (uint8_t)(bk < ks ? bk : 0);
+  for (int i = 0; i < np; ++i) {
+    const int64_t prow = rbeg + pend[i];
+    const int ec = exact_code_wave<DW>(x + prow * d + (int64_t)sub * ds, cbsub, ds, ks, lane);
+    if (lane == 0) codes[prow * m + sub] = (uint8_t)ec;
   }
+  nres = (uint32_t)np;
+  if (rescored && lane == 0 && nres) atomicAdd(rescored, (unsigned long long)nres);
 }
 
 }  // namespace
@@ -394,48 +334,50 @@ size_t bf16_operand_count(int m, int ks, int ds) {
   return (size_t)m * tiles_for(ks) * bf16_nmfma(nb) * 64;
 }
 
-int launch_pack_bf16(const float* c32, int m, int ks, int ds, void* aop, float* cmax, hipStream_t s) {
-  const int nt = tiles_for(ks);
-  if (ds <= 8)
-    k_pack_bf16<1><<<m, kThreads, 0, s>>>(c32, m, ks, ds, nt, (uint4*)aop, cmax);
-  else
-    k_pack_bf16<2><<<m, kThreads, 0, s>>>(c32, m, ks, ds, nt, (uint4*)aop, cmax);
-  MIPQ_LAUNCHED("k_pack_bf16");
-  return MIPQ_OK;
+Bf16Geom bf16_geometry(int64_t n, int m) {
+  Bf16Geom g;
+  g.groups = ceil_div(m, 4);
+  // aim for ~8 resident blocks per CU over the whole launch
+  const int64_t row_tiles = (n + 31) / 32;
+  int64_t tpb = (row_tiles * g.groups + 2047) / 2048;
+  if (tpb < 1) tpb = 1;
+  if (tpb > 64) tpb = 64;
+  g.rpb = int(tpb * 32);
+  g.rowblks = n > 0 ? ceil_div(n, g.rpb) : 0;
+  g.blocks = ceil_div(g.rowblks, 8) * 8 * g.groups;
+  return g;
 }
 
 int launch_assign_bf16(const float* x, int64_t n, int d, int m, int ks, const void* aop,
-                       const float* cmax, uint8_t* codes, uint32_t* queue, uint32_t* qcount,
-                       hipStream_t s) {
+                       const float* cmax, const float* mu, const float* c32, uint8_t* codes,
+                       int64_t* rescored, hipStream_t s) {
   const int ds = d / m;
   const int nb = (ds + 7) / 8;
   const int nt = tiles_for(ks);
-  const int groups = ceil_div(m, 4);
-  // aim for ~8 resident blocks per CU over the whole launch
-  const int64_t row_tiles = (n + 31) / 32;
-  int64_t tpb = (row_tiles * groups + 2047) / 2048;
-  if (tpb < 1) tpb = 1;
-  if (tpb > 64) tpb = 64;
-  const int rowblks = ceil_div(row_tiles, tpb);
-  const int blocks = ceil_div(rowblks, 8) * 8 * groups;
-  // error-bound constants (see the header of this file and DESIGN notes in the
-  // package): split products 3.1 u^2 per term (u = 2^-8) doubled for the -2
-  // factor, plus float32 accumulation over K = 16*NMF terms at 2^-23 each
+  const Bf16Geom g = bf16_geometry(n, m);
+  if (g.blocks == 0) return MIPQ_OK;
+  // error-bound constants: split products 3.1 u^2 per term (u = 2^-8), twice
+  // for the -2 factor, plus float32 accumulation over K = 16*NMF terms at
+  // 2^-23 each, plus the rounding of the centring (2^-22 of the squared
+  // norms); g_exact bounds the relative error of the exact float32 rule
   const int nmf = bf16_nmfma(nb);
   const float e_cross = 1.25e-4f * (nb == 1 ? 1.0f : 1.05f);
-  const float e_norm = 2.4e-6f * nmf;
+  const float e_norm = 2.4e-6f * nmf + 2.4e-7f;
   const float g_exact = (float)((ds + 2) * 1.01 / 16777216.0);
+  ProfScope ps(MIPQ_K_ASSIGN_BF16, s);
   const bool full = (ds == nb * 8) && (d % 4 == 0) && ((reinterpret_cast<uintptr_t>(x) & 15) == 0);
+  unsigned long long* resc = reinterpret_cast<unsigned long long*>(rescored);
+  const size_t pend_bytes = (size_t)(kThreads / 64) * g.rpb * sizeof(uint32_t);
 #define LAUNCH(NB, NT)                                                                              \
   do {                                                                                              \
     if (full)                                                                                       \
-      k_assign_bf16<NB, NT, true><<<blocks, kThreads, 0, s>>>(x, n, d, m, ks, ds, (const bf16x8*)aop, \
-                                                              cmax, codes, queue, qcount, groups,   \
-                                                              (int)tpb, e_cross, e_norm, g_exact);  \
+      k_assign_bf16<NB, NT, true><<<g.blocks, kThreads, pend_bytes, s>>>(                           \
+          x, n, d, m, ks, ds, (const bf16x8*)aop, cmax, mu, c32, codes, resc, g.groups, g.rpb,      \
+          e_cross, e_norm, g_exact);                                                                \
     else                                                                                            \
-      k_assign_bf16<NB, NT, false><<<blocks, kThreads, 0, s>>>(x, n, d, m, ks, ds, (const bf16x8*)aop, \
-                                                               cmax, codes, queue, qcount, groups,   \
-                                                               (int)tpb, e_cross, e_norm, g_exact); \
+      k_assign_bf16<NB, NT, false><<<g.blocks, kThreads, pend_bytes, s>>>(                          \
+          x, n, d, m, ks, ds, (const bf16x8*)aop, cmax, mu, c32, codes, resc, g.groups, g.rpb,      \
+          e_cross, e_norm, g_exact);                                                                \
   } while (0)
   if (nb == 1) {
     switch (nt) {
@@ -454,36 +396,6 @@ int launch_assign_bf16(const float* x, int64_t n, int d, int m, int ks, const vo
   }
 #undef LAUNCH
   MIPQ_LAUNCHED("k_assign_bf16");
-  return MIPQ_OK;
-}
-
-int launch_fixup(const float* x, int d, int m, int ks, const float* c32, const uint32_t* queue,
-                 const uint32_t* qcount, uint8_t* codes, int64_t* rescored_total, hipStream_t s) {
-  const int ds = d / m;
-  const int blocks = 1024;
-  unsigned long long* tot = reinterpret_cast<unsigned long long*>(rescored_total);
-#define FIX(DSV) k_fixup<DSV><<<blocks, kThreads, 0, s>>>(x, d, m, ks, c32, queue, qcount, codes, tot)
-  switch (ds) {
-    case 1: FIX(1); break;
-    case 2: FIX(2); break;
-    case 3: FIX(3); break;
-    case 4: FIX(4); break;
-    case 5: FIX(5); break;
-    case 6: FIX(6); break;
-    case 7: FIX(7); break;
-    case 8: FIX(8); break;
-    case 9: FIX(9); break;
-    case 10: FIX(10); break;
-    case 11: FIX(11); break;
-    case 12: FIX(12); break;
-    case 13: FIX(13); break;
-    case 14: FIX(14); break;
-    case 15: FIX(15); break;
-    case 16: FIX(16); break;
-    default: return fail(MIPQ_EUNSUPPORTED, "BF16 path supports d/m <= 16 (got %d)", ds);
-  }
-#undef FIX
-  MIPQ_LAUNCHED("k_fixup");
   return MIPQ_OK;
 }
 

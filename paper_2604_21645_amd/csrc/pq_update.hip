@@ -1,0 +1,214 @@
+// Lloyd update (paper Section 2.1: k-means in every subspace): float64
+// centroid sums per row chunk, then per subspace the centroid means, the
+// round's objective and, for the matrix-core path, the packed centroid
+// operands of the next round.  Also the stand-alone operand packing used
+// before the first round and by encoding.
+#include <math.h>
+
+#include "bf16_pack.h"
+#include "mipq_internal.h"
+
+namespace mipq {
+
+namespace {
+
+constexpr int kUpdThreads = 1024;
+constexpr int kPackThreads = 256;
+constexpr int kPackRed = 544;   // floats of LDS scratch for pack_subspace
+
+// Block (c, j) adds the rows of chunk c to subspace j's float64 sums and counts
+// in LDS (lane l takes dimension l % ds of row l / ds; sums centroid-major with
+// a padded stride ds + 1 so that one centroid's dimensions sit in different
+// banks) and the float64 squared distance of each row to its centroid, then
+// stores them as the chunk's partials.
+__global__ __launch_bounds__(kUpdThreads) void k_accumulate(
+    const float* __restrict__ x, int64_t n, int d, int m, int ks, int ds,
+    const uint8_t* __restrict__ codes, const float* __restrict__ c32, int64_t rpc,
+    double* __restrict__ part_s, uint32_t* __restrict__ part_cnt, double* __restrict__ part_j) {
+  extern __shared__ double smem[];
+  __shared__ double redj[kUpdThreads / 64];
+  const int stride = ds + 1;
+  double* S = smem;
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(S + (size_t)ks * stride);
+  float* cbs = reinterpret_cast<float*>(S + (size_t)ks * stride + (ks + 1) / 2);
+  const int c = blockIdx.x, sub = blockIdx.y;
+  const int per = ks * ds;
+  for (int i = threadIdx.x; i < ks * stride; i += blockDim.x) S[i] = 0.0;
+  for (int i = threadIdx.x; i < ks; i += blockDim.x) cnt[i] = 0u;
+  for (int i = threadIdx.x; i < per; i += blockDim.x) cbs[i] = c32[(int64_t)sub * per + i];
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int rpw = 64 / ds;                 // rows per wave step
+  const int g = lane / ds, t = lane - g * ds;
+  const int64_t r0 = (int64_t)c * rpc;
+  const int64_t r1 = min(n, r0 + rpc);
+  const int64_t step = (int64_t)(blockDim.x >> 6) * rpw;
+  double jl = 0.0;
+  constexpr int U = 8;   // rows in flight per lane
+  if (g < rpw && r0 < r1) {
+    for (int64_t row0 = r0 + (int64_t)wave * rpw + g; row0 < r1; row0 += step * U) {
+      int code[U];
+      float xv[U];
+      // clamped, unconditional loads: all U rows are in flight together
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t row = row0 + u * step;
+        const int64_t rc = row < r1 ? row : row0;
+        const int cd = (int)codes[rc * m + sub];
+        code[u] = row < r1 ? cd : -1;
+        xv[u] = x[rc * d + (int64_t)sub * ds + t];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (code[u] < 0) continue;
+        if (code[u] >= ks) {   // corrupt code: poison the objective, touch nothing
+          jl += NAN;
+          continue;
+        }
+        const double df = (double)xv[u] - (double)cbs[code[u] * ds + t];
+        jl += df * df;
+        atomicAdd(&S[code[u] * stride + t], (double)xv[u]);
+        if (t == 0) atomicAdd(&cnt[code[u]], 1u);
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) jl += __shfl_xor(jl, off, 64);
+  if (lane == 0) redj[wave] = jl;
+  __syncthreads();
+  const size_t base = (size_t)c * m + sub;
+  for (int i = threadIdx.x; i < per; i += blockDim.x) {
+    const int k = i / ds;
+    part_s[base * per + i] = S[k * stride + (i - k * ds)];
+  }
+  for (int i = threadIdx.x; i < ks; i += blockDim.x) part_cnt[base * ks + i] = cnt[i];
+  if (threadIdx.x == 0) {
+    double js = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) js += redj[i];
+    part_j[base] = js;
+  }
+}
+
+// One block per subspace: sums the chunk partials in chunk order, centroid =
+// sum / count (an empty centroid keeps its value), float32 copy by
+// round-to-nearest, the subspace objective, and with PACK the next round's
+// operands.
+template <int NB, bool PACK>
+__global__ __launch_bounds__(kUpdThreads) void k_finalize(int m, int ks, int ds, int nch,
+                                                          const double* __restrict__ part_s,
+                                                          const uint32_t* __restrict__ part_cnt,
+                                                          const double* __restrict__ part_j,
+                                                          float* __restrict__ c32, double* __restrict__ c64,
+                                                          double* __restrict__ j_sub, uint4* __restrict__ aop,
+                                                          float* __restrict__ cmax, float* __restrict__ mu,
+                                                          int nt) {
+  extern __shared__ float newc[];   // new float32 centroids of this subspace
+  __shared__ float packred[kPackRed];
+  const int sub = blockIdx.x;
+  const int per = ks * ds;
+  for (int e = threadIdx.x; e < per; e += blockDim.x) {
+    const int k = e / ds;
+    double sacc = 0.0;
+    uint64_t cacc = 0;
+    constexpr int V = 8;   // partials in flight, added in chunk order
+    for (int c0 = 0; c0 < nch; c0 += V) {
+      double sv[V];
+      uint32_t cv[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const int cc = c0 + v < nch ? c0 + v : nch - 1;
+        const size_t b2 = (size_t)cc * m + sub;
+        sv[v] = part_s[b2 * per + e];
+        cv[v] = part_cnt[b2 * ks + k];
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        if (c0 + v < nch) {
+          sacc += sv[v];
+          cacc += cv[v];
+        }
+    }
+    const size_t o = (size_t)sub * per + e;
+    const double v = cacc ? sacc / (double)cacc : c64[o];
+    c64[o] = v;
+    const float f = (float)v;
+    c32[o] = f;
+    newc[e] = f;
+  }
+  if (threadIdx.x < 64) {   // objective: lane-strided chunk sums, then a fixed xor tree
+    double js = 0.0;
+    for (int cc = threadIdx.x; cc < nch; cc += 64) js += part_j[(size_t)cc * m + sub];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) js += __shfl_xor(js, off, 64);
+    if (threadIdx.x == 0) j_sub[sub] = js;
+  }
+  __syncthreads();
+  if (PACK) pack_subspace<NB>(newc, ks, ds, nt, sub, 0, nt, aop, cmax + sub, mu + sub * kMaxDsBf16, true, packred);
+}
+
+// Stand-alone packing: block (t, j) packs tile t of subspace j; block (0, j)
+// also stores the subspace centre and norm bound.
+template <int NB>
+__global__ __launch_bounds__(kPackThreads) void k_pack_bf16(const float* __restrict__ c32, int ks, int ds,
+                                                            int nt, uint4* __restrict__ aop,
+                                                            float* __restrict__ cmax, float* __restrict__ mu) {
+  __shared__ float red[kPackRed];
+  const int t = blockIdx.x, sub = blockIdx.y;
+  pack_subspace<NB>(c32 + (int64_t)sub * ks * ds, ks, ds, nt, sub, t, t + 1, aop, cmax + sub,
+                    mu + sub * kMaxDsBf16, t == 0, red);
+}
+
+}  // namespace
+
+// about one 1024-thread block per CU over all (chunk, subspace) pairs
+int update_chunks(int64_t n, int m) {
+  int nch = ceil_div(n, 1024);
+  int cap = 256 / m;
+  if (cap < 1) cap = 1;
+  if (nch > cap) nch = cap;
+  return nch < 1 ? 1 : nch;
+}
+
+int launch_update(const float* x, int64_t n, int d, int m, int ks, const uint8_t* codes, float* c32,
+                  double* c64, int nch, double* part_s, uint32_t* part_cnt, double* part_j,
+                  double* j_sub, void* aop, float* cmax, float* mu, hipStream_t s) {
+  const int ds = d / m;
+  const int64_t rpc = (n + nch - 1) / nch;
+  {
+    const size_t shm = (size_t)ks * (ds + 1) * sizeof(double) + ((ks + 1) / 2) * sizeof(double) +
+                       (size_t)ks * ds * sizeof(float);
+    dim3 grid(nch, m);
+    ProfScope ps(MIPQ_K_UPDATE, s);
+    k_accumulate<<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, part_s, part_cnt, part_j);
+    MIPQ_LAUNCHED("k_accumulate");
+  }
+  const int nt = tiles_for(ks);
+  const size_t shm = (size_t)ks * ds * sizeof(float);
+  ProfScope ps(MIPQ_K_FINALIZE, s);
+#define FIN(NB, PK)                                                                                  \
+  k_finalize<NB, PK><<<m, kUpdThreads, shm, s>>>(m, ks, ds, nch, part_s, part_cnt, part_j, c32, c64, \
+                                                 j_sub, (uint4*)aop, cmax, mu, nt)
+  if (!aop) FIN(1, false);
+  else if (ds <= 8) FIN(1, true);
+  else FIN(2, true);
+#undef FIN
+  MIPQ_LAUNCHED("k_finalize");
+  return MIPQ_OK;
+}
+
+int launch_pack_bf16(const float* c32, int m, int ks, int ds, void* aop, float* cmax, float* mu,
+                     hipStream_t s) {
+  const int nt = tiles_for(ks);
+  ProfScope ps(MIPQ_K_PACK_BF16, s);
+  dim3 grid(nt, m);
+  if (ds <= 8)
+    k_pack_bf16<1><<<grid, kPackThreads, 0, s>>>(c32, ks, ds, nt, (uint4*)aop, cmax, mu);
+  else
+    k_pack_bf16<2><<<grid, kPackThreads, 0, s>>>(c32, ks, ds, nt, (uint4*)aop, cmax, mu);
+  MIPQ_LAUNCHED("k_pack_bf16");
+  return MIPQ_OK;
+}
+
+}  // namespace mipq

@@ -31,7 +31,8 @@ def test_single_hip_runtime_and_version(L):
 def test_workspace_queries(L):
     small = L.mipq_pq_encode_workspace_size(1000, 128, 16, 256, 1)
     big = L.mipq_pq_encode_workspace_size(100000, 128, 16, 256, 1)
-    assert 0 < small < big
+    assert 0 < small <= big
+    assert L.mipq_pq_fit_workspace_size(1000, 128, 16, 256, 25, 1) < L.mipq_pq_fit_workspace_size(100000, 128, 16, 256, 25, 1)
     assert L.mipq_pq_encode_workspace_size(1000, 128, 16, 256, 0) == 0   # FP32 needs none
     assert L.mipq_pq_encode_workspace_size(1000, 130, 16, 256, 1) == 0   # invalid shape
     assert L.mipq_pq_fit_workspace_size(1000, 128, 16, 256, 25, 1) > 0
