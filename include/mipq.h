@@ -128,6 +128,27 @@ int mipq_pq_decode_rmse(const uint8_t* codes, int64_t n, int d, int m, int ks,
                         void* ws, size_t ws_bytes, void* stream);
 
 /* -------------------------------------------------------------------------
+ * Reconstruction-loss backward with the codes held fixed.
+ *
+ * For x_hat_n = concatenation over subspaces j of C_j[codes[n][j]] (the
+ * decode of Section 3) and L = sum over n of ||x_n - x_hat_n||^2:
+ *   dL/dx_n    = 2 g (x_n - x_hat_n)
+ *   dL/dC_j[k] = 2 g (cnt_jk C_j[k] - S_jk),  S_jk / cnt_jk the float64 sum /
+ *                number of the subspace-j blocks of the rows coded k
+ * (setting dL/dC = 0 gives the k-means mean of Section 2.1's fit).
+ *
+ *   grad_out      optional float64 [1]: upstream g (NULL: g = 1)
+ *   grad_x        OUT optional float32 [n][d]
+ *   grad_codebook OUT optional float32 [m][ks][ds]
+ *   loss          OUT optional float64 [1]: L, summed in float64
+ * Codes >= ks make the loss and the affected grad_x entries NaN.
+ * ------------------------------------------------------------------------- */
+size_t mipq_recon_backward_workspace_size(int64_t n, int d, int m, int ks);
+int mipq_recon_backward(const float* x, const uint8_t* codes, const float* codebook, int64_t n, int d,
+                        int m, int ks, const double* grad_out, float* grad_x, float* grad_codebook,
+                        double* loss, void* ws, size_t ws_bytes, void* stream);
+
+/* -------------------------------------------------------------------------
  * Per-kernel timing (tracing aid, off by default).
  *
  * mipq_profile_enable(1) makes every subsequent launch of the kernels below
@@ -142,7 +163,8 @@ enum mipq_kernel {
   MIPQ_K_FINALIZE = 3,      /* centroid means, objective (+ operand packing) */
   MIPQ_K_PACK_BF16 = 4,     /* stand-alone centroid operand packing */
   MIPQ_K_DECODE = 5,        /* decode + squared error */
-  MIPQ_KERNEL_COUNT = 6
+  MIPQ_K_BACKWARD = 6,      /* reconstruction-loss gradient pass */
+  MIPQ_KERNEL_COUNT = 7
 };
 int mipq_profile_enable(int on);
 int mipq_profile_collect(int kernel, int64_t* launches, double* total_ms);

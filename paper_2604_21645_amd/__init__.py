@@ -118,3 +118,55 @@ def pq_decode_rmse(codes: torch.Tensor, codebook: torch.Tensor, x: torch.Tensor 
     check(L.mipq_pq_decode_rmse(_ptr(codes), n, d, m, ks, _ptr(cb), _ptr(xx), _ptr(xh), _ptr(sr),
                                 _ptr(ws), ws.numel(), _stream(dev)))
     return xh, sr
+
+
+def recon_backward(x: torch.Tensor, codebook: torch.Tensor, codes: torch.Tensor,
+                   grad_out: torch.Tensor | None = None, grad_x: bool = True, grad_codebook: bool = True):
+    """Reconstruction loss L = sum ||x - x_hat||^2 (codes fixed) and its gradients.
+
+    Returns (loss float64 [1], dL/dx float32 [n, d] or None, dL/dC float32
+    [m, ks, ds] or None), each gradient scaled by ``grad_out`` (float64 [1],
+    default 1)."""
+    L = lib()
+    x = _dev(x, torch.float32, "x")
+    cb = _dev(codebook, torch.float32, "codebook")
+    codes = _dev(codes, torch.uint8, "codes")
+    dev = x.device
+    n, d = x.shape
+    m, ks, ds = cb.shape
+    if m * ds != d or codes.shape != (n, m):
+        raise ValueError("shapes of x %s, codebook %s and codes %s disagree"
+                         % (tuple(x.shape), tuple(cb.shape), tuple(codes.shape)))
+    g = None
+    if grad_out is not None:
+        g = grad_out.detach().to(device=dev, dtype=torch.float64).reshape(1).contiguous()
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    gx = torch.empty((n, d), dtype=torch.float32, device=dev) if grad_x else None
+    gc = torch.empty((m, ks, ds), dtype=torch.float32, device=dev) if grad_codebook else None
+    ws = _ws(L.mipq_recon_backward_workspace_size(n, d, m, ks), dev)
+    check(L.mipq_recon_backward(_ptr(x), _ptr(codes), _ptr(cb), n, d, m, ks, _ptr(g), _ptr(gx), _ptr(gc),
+                                _ptr(loss), _ptr(ws), ws.numel(), _stream(dev)))
+    return loss, gx, gc
+
+
+class PQReconLoss(torch.autograd.Function):
+    """L = sum over rows of ||x - decode(codes, codebook)||^2 with the codes held
+    fixed; differentiable in x and codebook (float64 loss, float32 gradients).
+
+        loss = PQReconLoss.apply(x, codebook, codes)
+    """
+
+    @staticmethod
+    def forward(ctx, x, codebook, codes):
+        _, sr = pq_decode_rmse(codes, codebook, x)
+        ctx.save_for_backward(x, codebook, codes)
+        return sr[0].reshape(())
+
+    @staticmethod
+    def backward(ctx, g):
+        x, codebook, codes = ctx.saved_tensors
+        need_x, need_c = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        if not (need_x or need_c):
+            return None, None, None
+        _, gx, gc = recon_backward(x, codebook, codes, grad_out=g, grad_x=need_x, grad_codebook=need_c)
+        return gx, gc, None

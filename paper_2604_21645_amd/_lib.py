@@ -31,12 +31,15 @@ SIGNATURES = {
     "mipq_pq_encode": (_I, [_P, _L, _I, _I, _I, _P, _I, _P, _P, _P, _S, _P]),
     "mipq_pq_decode_rmse_workspace_size": (_S, [_L, _I, _I, _I]),
     "mipq_pq_decode_rmse": (_I, [_P, _L, _I, _I, _I, _P, _P, _P, _P, _P, _S, _P]),
+    "mipq_recon_backward_workspace_size": (_S, [_L, _I, _I, _I]),
+    "mipq_recon_backward": (_I, [_P, _P, _P, _L, _I, _I, _I, _P, _P, _P, _P, _P, _S, _P]),
     "mipq_profile_enable": (_I, [_I]),
     "mipq_profile_collect": (_I, [_I, ctypes.POINTER(_L), ctypes.POINTER(ctypes.c_double)]),
 }
 
 # kernel ids of mipq_profile_collect (enum mipq_kernel)
-KERNELS = {"assign_fp32": 0, "assign_bf16": 1, "update": 2, "finalize": 3, "pack_bf16": 4, "decode": 5}
+KERNELS = {"assign_fp32": 0, "assign_bf16": 1, "update": 2, "finalize": 3, "pack_bf16": 4, "decode": 5,
+           "backward": 6}
 
 _lib = None
 

@@ -220,4 +220,36 @@ int mipq_pq_decode_rmse(const uint8_t* codes, int64_t n, int d, int m, int ks, c
   return MIPQ_OK;
 }
 
+size_t mipq_recon_backward_workspace_size(int64_t n, int d, int m, int ks) {
+  if (check_shape(n, d, m, ks, MIPQ_FP32, true) != MIPQ_OK) return 0;
+  const int nch = backward_chunks(n, m);
+  Carver c(nullptr);
+  c.take<double>((size_t)nch * d * ks);
+  c.take<uint32_t>((size_t)nch * m * ks);
+  c.take<double>((size_t)nch * m);
+  c.take<double>(m);
+  return c.bytes();
+}
+
+int mipq_recon_backward(const float* x, const uint8_t* codes, const float* codebook, int64_t n, int d,
+                        int m, int ks, const double* grad_out, float* grad_x, float* grad_codebook,
+                        double* loss, void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_shape(n, d, m, ks, MIPQ_FP32, true))) return rc;
+  if (!codebook || (n > 0 && (!x || !codes))) return fail(MIPQ_EINVAL, "x, codes and codebook are required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nch = backward_chunks(n, m);
+  Carver c(ws);
+  double* part_s = c.take<double>((size_t)nch * d * ks);
+  uint32_t* part_cnt = c.take<uint32_t>((size_t)nch * m * ks);
+  double* part_j = c.take<double>((size_t)nch * m);
+  double* loss_sub = c.take<double>(m);
+  if ((rc = check_ws(ws, ws_bytes, c.bytes()))) return rc;
+  if ((rc = launch_backward(x, n, d, m, ks, codes, codebook, grad_out, grad_x, grad_codebook, nch, part_s,
+                            part_cnt, part_j, loss_sub, s)))
+    return rc;
+  if (loss && (rc = launch_objective(loss_sub, 1, m, loss, s))) return rc;
+  return MIPQ_OK;
+}
+
 }  // extern "C"

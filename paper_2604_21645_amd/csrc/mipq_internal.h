@@ -96,6 +96,12 @@ struct Bf16Geom {
 };
 Bf16Geom bf16_geometry(int64_t n, int m);
 size_t bf16_operand_count(int m, int ks, int ds);   // number of 16-byte operand slots
+// reconstruction-loss backward with fixed codes: grad_x (optional), grad_c
+// (optional), per-subspace loss; g = *gscale (NULL: 1)
+int backward_chunks(int64_t n, int m);
+int launch_backward(const float* x, int64_t n, int d, int m, int ks, const uint8_t* codes,
+                    const float* c32, const double* gscale, float* grad_x, float* grad_c, int nch,
+                    double* part_s, uint32_t* part_cnt, double* part_j, double* loss_sub, hipStream_t s);
 // operands of the centred codebook; mu: m * kMaxDsBf16 floats (subspace centres)
 int launch_pack_bf16(const float* c32, int m, int ks, int ds, void* aop, float* cmax, float* mu,
                      hipStream_t s);

@@ -21,10 +21,14 @@ constexpr int kPackRed = 544;   // floats of LDS scratch for pack_subspace
 // a padded stride ds + 1 so that one centroid's dimensions sit in different
 // banks) and the float64 squared distance of each row to its centroid, then
 // stores them as the chunk's partials.
+// With GX the block also writes dL/dx = 2 g (x - c) (float64 product rounded to
+// float32, g = *gscale) for the reconstruction loss L = sum (x - x_hat)^2.
+template <bool GX>
 __global__ __launch_bounds__(kUpdThreads) void k_accumulate(
     const float* __restrict__ x, int64_t n, int d, int m, int ks, int ds,
     const uint8_t* __restrict__ codes, const float* __restrict__ c32, int64_t rpc,
-    double* __restrict__ part_s, uint32_t* __restrict__ part_cnt, double* __restrict__ part_j) {
+    double* __restrict__ part_s, uint32_t* __restrict__ part_cnt, double* __restrict__ part_j,
+    const double* __restrict__ gscale, float* __restrict__ grad_x) {
   extern __shared__ double smem[];
   __shared__ double redj[kUpdThreads / 64];
   const int stride = ds + 1;
@@ -46,6 +50,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_accumulate(
   const int64_t r1 = min(n, r0 + rpc);
   const int64_t step = (int64_t)(blockDim.x >> 6) * rpw;
   double jl = 0.0;
+  const double g2 = GX ? 2.0 * (gscale ? *gscale : 1.0) : 0.0;
   constexpr int U = 8;   // rows in flight per lane
   if (g < rpw && r0 < r1) {
     for (int64_t row0 = r0 + (int64_t)wave * rpw + g; row0 < r1; row0 += step * U) {
@@ -63,12 +68,15 @@ __global__ __launch_bounds__(kUpdThreads) void k_accumulate(
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (code[u] < 0) continue;
-        if (code[u] >= ks) {   // corrupt code: poison the objective, touch nothing
+        const int64_t gi = (row0 + u * step) * d + (int64_t)sub * ds + t;
+        if (code[u] >= ks) {   // corrupt code: poison the objective, touch no sum
           jl += NAN;
+          if (GX) grad_x[gi] = NAN;
           continue;
         }
         const double df = (double)xv[u] - (double)cbs[code[u] * ds + t];
         jl += df * df;
+        if (GX) grad_x[gi] = (float)(g2 * df);
         atomicAdd(&S[code[u] * stride + t], (double)xv[u]);
         if (t == 0) atomicAdd(&cnt[code[u]], 1u);
       }
@@ -148,6 +156,54 @@ __global__ __launch_bounds__(kUpdThreads) void k_finalize(int m, int ks, int ds,
   if (PACK) pack_subspace<NB>(newc, ks, ds, nt, sub, 0, nt, aop, cmax + sub, mu + sub * kMaxDsBf16, true, packred);
 }
 
+// dL/dC_j[k] = 2 g (cnt_jk C_j[k] - S_jk) with the chunk partials summed in
+// chunk order (float64), rounded to float32; also subspace j's loss.
+__global__ __launch_bounds__(kUpdThreads) void k_grad_codebook(int m, int ks, int ds, int nch,
+                                                               const double* __restrict__ part_s,
+                                                               const uint32_t* __restrict__ part_cnt,
+                                                               const double* __restrict__ part_j,
+                                                               const float* __restrict__ c32,
+                                                               const double* __restrict__ gscale,
+                                                               float* __restrict__ grad_c,
+                                                               double* __restrict__ loss_sub) {
+  const int sub = blockIdx.x;
+  const int per = ks * ds;
+  const double g2 = 2.0 * (gscale ? *gscale : 1.0);
+  if (grad_c)
+    for (int e = threadIdx.x; e < per; e += blockDim.x) {
+      const int k = e / ds;
+      double sacc = 0.0;
+      uint64_t cacc = 0;
+      constexpr int V = 8;
+      for (int c0 = 0; c0 < nch; c0 += V) {
+        double sv[V];
+        uint32_t cv[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const int cc = c0 + v < nch ? c0 + v : nch - 1;
+          const size_t b2 = (size_t)cc * m + sub;
+          sv[v] = part_s[b2 * per + e];
+          cv[v] = part_cnt[b2 * ks + k];
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+          if (c0 + v < nch) {
+            sacc += sv[v];
+            cacc += cv[v];
+          }
+      }
+      const size_t o = (size_t)sub * per + e;
+      grad_c[o] = (float)(g2 * ((double)cacc * (double)c32[o] - sacc));
+    }
+  if (threadIdx.x < 64) {
+    double js = 0.0;
+    for (int cc = threadIdx.x; cc < nch; cc += 64) js += part_j[(size_t)cc * m + sub];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) js += __shfl_xor(js, off, 64);
+    if (threadIdx.x == 0) loss_sub[sub] = js;
+  }
+}
+
 // Stand-alone packing: block (t, j) packs tile t of subspace j; block (0, j)
 // also stores the subspace centre and norm bound.
 template <int NB>
@@ -181,7 +237,8 @@ int launch_update(const float* x, int64_t n, int d, int m, int ks, const uint8_t
                        (size_t)ks * ds * sizeof(float);
     dim3 grid(nch, m);
     ProfScope ps(MIPQ_K_UPDATE, s);
-    k_accumulate<<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, part_s, part_cnt, part_j);
+    k_accumulate<false><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, part_s, part_cnt,
+                                                       part_j, nullptr, nullptr);
     MIPQ_LAUNCHED("k_accumulate");
   }
   const int nt = tiles_for(ks);
@@ -195,6 +252,38 @@ int launch_update(const float* x, int64_t n, int d, int m, int ks, const uint8_t
   else FIN(2, true);
 #undef FIN
   MIPQ_LAUNCHED("k_finalize");
+  return MIPQ_OK;
+}
+
+int backward_chunks(int64_t n, int m) {
+  int nch = ceil_div(n, 2048);
+  int cap = 2048 / m;
+  if (cap < 1) cap = 1;
+  if (nch > cap) nch = cap;
+  return nch < 1 ? 1 : nch;
+}
+
+int launch_backward(const float* x, int64_t n, int d, int m, int ks, const uint8_t* codes,
+                    const float* c32, const double* gscale, float* grad_x, float* grad_c, int nch,
+                    double* part_s, uint32_t* part_cnt, double* part_j, double* loss_sub, hipStream_t s) {
+  const int ds = d / m;
+  const int64_t rpc = (n + nch - 1) / nch;
+  {
+    const size_t shm = (size_t)ks * (ds + 1) * sizeof(double) + ((ks + 1) / 2) * sizeof(double) +
+                       (size_t)ks * ds * sizeof(float);
+    dim3 grid(nch, m);
+    ProfScope ps(MIPQ_K_BACKWARD, s);
+    if (grad_x)
+      k_accumulate<true><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, part_s, part_cnt,
+                                                        part_j, gscale, grad_x);
+    else
+      k_accumulate<false><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, part_s, part_cnt,
+                                                         part_j, nullptr, nullptr);
+    MIPQ_LAUNCHED("k_accumulate");
+  }
+  k_grad_codebook<<<m, kUpdThreads, 0, s>>>(m, ks, ds, nch, part_s, part_cnt, part_j, c32, gscale, grad_c,
+                                            loss_sub);
+  MIPQ_LAUNCHED("k_grad_codebook");
   return MIPQ_OK;
 }
 
