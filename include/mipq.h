@@ -128,6 +128,76 @@ int mipq_pq_decode_rmse(const uint8_t* codes, int64_t n, int d, int m, int ks,
                         void* ws, size_t ws_bytes, void* stream);
 
 /* -------------------------------------------------------------------------
+ * Inverted file (paper Section 2.2: the ids of rows are stored per bucket and
+ * a query returns its first to k-th nearest neighbours).  Buckets are coarse
+ * k-means lists; each row stores the PQ codes of its residual x - c_list.
+ *
+ * Coarse rule: label = lowest l minimising the sum over dimensions t
+ * ascending of (x_t - c_lt)^2 with the difference rounded to float32 and the
+ * squares and sums in float64.  MIPQ_BF16 ranks on matrix cores and
+ * re-decides unseparated rows with that rule; MIPQ_FP32 applies it directly.
+ *
+ * mipq_coarse_assign: labels int32 [n] of rows x [n][d] against coarse
+ *   float32 [kc][d]; rescored: optional int64 [1] counter (rows re-decided).
+ *
+ * mipq_ii_build:
+ *   x             rows [n][d]
+ *   train_rows    int64 [n_train]: the training sample (rows of x) for the
+ *                 coarse quantiser and the residual PQ
+ *   coarse_init   int64 [kc]: coarse centroid l starts as training row
+ *                 coarse_init[l] (an index into the sample)
+ *   pq_init       int64 [m][ks]: residual PQ initial rows (indices into the
+ *                 sample), as mipq_pq_fit's init_rows
+ *   coarse        OUT float32 [kc][d]   pq_codebook OUT float32 [m][ks][d/m]
+ *   offsets       OUT int64 [kc+1]: list l holds sorted positions
+ *                 offsets[l] .. offsets[l+1]-1
+ *   ids           OUT int32 [n]: row ids by list, ascending inside a list
+ *   codes_sorted  OUT uint8 [n][m]: residual codes of ids[i] at row i
+ *   labels        OUT optional int32 [n]: coarse label of every row
+ *   coarse_objective OUT optional float64 [coarse_iters]
+ * Steps: coarse Lloyd (coarse_iters rounds, centroid = float64 mean of its
+ * rows in id order, empty keeps its value) on the sample; final labels of the
+ * sample; residual PQ fit (pq_iters rounds) on the sample's residuals; labels
+ * and residual codes of all rows; stable bucketing by label.
+ * Requirements: kc <= 65536, n < 2^31, d % m == 0, d % 16 == 0 and d <= 256
+ * for MIPQ_BF16 coarse ranking.
+ * ------------------------------------------------------------------------- */
+size_t mipq_coarse_assign_workspace_size(int d, int kc, int precision);
+int mipq_coarse_assign(const float* x, int64_t n, int d, const float* coarse, int kc, int precision,
+                       int32_t* labels, int64_t* rescored, void* ws, size_t ws_bytes, void* stream);
+size_t mipq_ii_build_workspace_size(int64_t n, int d, int kc, int64_t n_train, int m, int ks, int pq_iters,
+                                    int coarse_iters, int precision);
+int mipq_ii_build(const float* x, int64_t n, int d, int kc, int coarse_iters, const int64_t* train_rows,
+                  int64_t n_train, const int64_t* coarse_init, int m, int ks, int pq_iters,
+                  const int64_t* pq_init, int precision, float* coarse, float* pq_codebook,
+                  int64_t* offsets, int32_t* ids, uint8_t* codes_sorted, int32_t* labels,
+                  double* coarse_objective, void* ws, size_t ws_bytes, void* stream);
+
+/* -------------------------------------------------------------------------
+ * ADC search over an index built by mipq_ii_build (paper Section 2.2: the
+ * first to k-th nearest neighbours of a query).
+ *
+ * For query q: the nprobe lists with the smallest coarse distance (coarse
+ * rule above, ties to the lower list); for each probed list l a table
+ * LUT[j][k] = float32 subspace-j distance (the code rule) of (q - c_l) to the
+ * residual centroid C_j[k]; every row of the list scores
+ * s = sum over j ascending of LUT[j][code_j] in float32; the topk smallest
+ * (s, id) pairs, ascending, are returned (ids -1 and +inf when fewer rows).
+ *
+ *   q         float32 [nq][d]      out_ids  OUT int32 [nq][topk]
+ *   out_dist  OUT float32 [nq][topk]
+ *   wide      OUT optional int64 [1]: queries whose probe selection needed the
+ *             exact rule on every list
+ * Requirements: 1 <= nprobe <= min(kc, 256), 1 <= topk <= 1024, d/m in
+ * {1, 2, 4, 8, 16}, d <= 16 or d in {32, 64, 96, 128, 192, 256}.
+ * ------------------------------------------------------------------------- */
+size_t mipq_adc_search_workspace_size(int nq, int d, int kc, int nprobe);
+int mipq_adc_search(const float* q, int nq, int d, const float* coarse, int kc, const float* pq_codebook,
+                    int m, int ks, const int64_t* offsets, const int32_t* ids, const uint8_t* codes_sorted,
+                    int nprobe, int topk, int32_t* out_ids, float* out_dist, int64_t* wide, void* ws,
+                    size_t ws_bytes, void* stream);
+
+/* -------------------------------------------------------------------------
  * Reconstruction-loss backward with the codes held fixed.
  *
  * For x_hat_n = concatenation over subspaces j of C_j[codes[n][j]] (the
@@ -164,7 +234,12 @@ enum mipq_kernel {
   MIPQ_K_PACK_BF16 = 4,     /* stand-alone centroid operand packing */
   MIPQ_K_DECODE = 5,        /* decode + squared error */
   MIPQ_K_BACKWARD = 6,      /* reconstruction-loss gradient pass */
-  MIPQ_KERNEL_COUNT = 7
+  MIPQ_K_COARSE_PACK = 7,   /* coarse centre + operand packing */
+  MIPQ_K_COARSE_ASSIGN = 8, /* coarse assignment */
+  MIPQ_K_SORT = 9,          /* stable bucketing by label */
+  MIPQ_K_COARSE_UPDATE = 10,/* coarse centroid update */
+  MIPQ_K_ADC = 11,          /* ADC search */
+  MIPQ_KERNEL_COUNT = 12
 };
 int mipq_profile_enable(int on);
 int mipq_profile_collect(int kernel, int64_t* launches, double* total_ms);

@@ -170,3 +170,78 @@ class PQReconLoss(torch.autograd.Function):
             return None, None, None
         _, gx, gc = recon_backward(x, codebook, codes, grad_out=g, grad_x=need_x, grad_codebook=need_c)
         return gx, gc, None
+
+
+def coarse_assign(x: torch.Tensor, coarse: torch.Tensor, precision="bf16", rescored: bool = False):
+    """Coarse list label (int32 [n]) of every row; optionally the int64 number
+    of rows re-decided with the exact rule."""
+    L = lib()
+    x = _dev(x, torch.float32, "x")
+    cc = _dev(coarse, torch.float32, "coarse")
+    dev = x.device
+    n, d = x.shape
+    kc = cc.shape[0]
+    p = _prec(precision)
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    resc = torch.zeros(1, dtype=torch.int64, device=dev) if rescored else None
+    ws = _ws(L.mipq_coarse_assign_workspace_size(d, kc, p), dev)
+    check(L.mipq_coarse_assign(_ptr(x), n, d, _ptr(cc), kc, p, _ptr(labels), _ptr(resc), _ptr(ws), ws.numel(),
+                               _stream(dev)))
+    return (labels, resc) if rescored else labels
+
+
+def ii_build(x: torch.Tensor, kc: int, coarse_iters: int, train_rows: torch.Tensor, coarse_init: torch.Tensor,
+             m: int, ks: int, pq_iters: int, pq_init: torch.Tensor, precision="bf16", labels: bool = True,
+             coarse_objective: bool = False):
+    """Inverted file with residual PQ; returns a dict with coarse, pq_codebook,
+    offsets, ids, codes_sorted (and labels, coarse_objective on request)."""
+    L = lib()
+    x = _dev(x, torch.float32, "x")
+    tr = _dev(train_rows, torch.int64, "train_rows")
+    ci = _dev(coarse_init, torch.int64, "coarse_init")
+    pi = _dev(pq_init, torch.int64, "pq_init")
+    dev = x.device
+    n, d = x.shape
+    n_train = tr.numel()
+    p = _prec(precision)
+    out = {
+        "coarse": torch.empty((kc, d), dtype=torch.float32, device=dev),
+        "pq_codebook": torch.empty((m, ks, d // m), dtype=torch.float32, device=dev),
+        "offsets": torch.empty(kc + 1, dtype=torch.int64, device=dev),
+        "ids": torch.empty(n, dtype=torch.int32, device=dev),
+        "codes_sorted": torch.empty((n, m), dtype=torch.uint8, device=dev),
+    }
+    if labels:
+        out["labels"] = torch.empty(n, dtype=torch.int32, device=dev)
+    if coarse_objective:
+        out["coarse_objective"] = torch.empty(max(coarse_iters, 1), dtype=torch.float64, device=dev)
+    ws = _ws(L.mipq_ii_build_workspace_size(n, d, kc, n_train, m, ks, pq_iters, coarse_iters, p), dev)
+    check(L.mipq_ii_build(_ptr(x), n, d, kc, coarse_iters, _ptr(tr), n_train, _ptr(ci), m, ks, pq_iters, _ptr(pi), p,
+                          _ptr(out["coarse"]), _ptr(out["pq_codebook"]), _ptr(out["offsets"]), _ptr(out["ids"]),
+                          _ptr(out["codes_sorted"]), _ptr(out.get("labels")), _ptr(out.get("coarse_objective")),
+                          _ptr(ws), ws.numel(), _stream(dev)))
+    return out
+
+
+def adc_search(q: torch.Tensor, index: dict, nprobe: int, topk: int, wide: bool = False):
+    """Top-k (ids int32 [nq, topk], distances float32 [nq, topk]) per query
+    over an index from ``ii_build``; optionally the int64 number of queries
+    whose probe selection ranked every list exactly."""
+    L = lib()
+    q = _dev(q, torch.float32, "q")
+    dev = q.device
+    nq, d = q.shape
+    cc = _dev(index["coarse"], torch.float32, "coarse")
+    pqc = _dev(index["pq_codebook"], torch.float32, "pq_codebook")
+    off = _dev(index["offsets"], torch.int64, "offsets")
+    ids = _dev(index["ids"], torch.int32, "ids")
+    codes = _dev(index["codes_sorted"], torch.uint8, "codes_sorted")
+    kc = cc.shape[0]
+    m, ks, _ = pqc.shape
+    out_ids = torch.empty((nq, topk), dtype=torch.int32, device=dev)
+    out_d = torch.empty((nq, topk), dtype=torch.float32, device=dev)
+    w = torch.zeros(1, dtype=torch.int64, device=dev) if wide else None
+    ws = _ws(L.mipq_adc_search_workspace_size(nq, d, kc, nprobe), dev)
+    check(L.mipq_adc_search(_ptr(q), nq, d, _ptr(cc), kc, _ptr(pqc), m, ks, _ptr(off), _ptr(ids), _ptr(codes),
+                            nprobe, topk, _ptr(out_ids), _ptr(out_d), _ptr(w), _ptr(ws), ws.numel(), _stream(dev)))
+    return (out_ids, out_d, w) if wide else (out_ids, out_d)

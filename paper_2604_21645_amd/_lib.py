@@ -33,13 +33,20 @@ SIGNATURES = {
     "mipq_pq_decode_rmse": (_I, [_P, _L, _I, _I, _I, _P, _P, _P, _P, _P, _S, _P]),
     "mipq_recon_backward_workspace_size": (_S, [_L, _I, _I, _I]),
     "mipq_recon_backward": (_I, [_P, _P, _P, _L, _I, _I, _I, _P, _P, _P, _P, _P, _S, _P]),
+    "mipq_coarse_assign_workspace_size": (_S, [_I, _I, _I]),
+    "mipq_coarse_assign": (_I, [_P, _L, _I, _P, _I, _I, _P, _P, _P, _S, _P]),
+    "mipq_ii_build_workspace_size": (_S, [_L, _I, _I, _L, _I, _I, _I, _I, _I]),
+    "mipq_ii_build": (_I, [_P, _L, _I, _I, _I, _P, _L, _P, _I, _I, _I, _P, _I, _P, _P, _P, _P, _P, _P, _P,
+                           _P, _S, _P]),
+    "mipq_adc_search_workspace_size": (_S, [_I, _I, _I, _I]),
+    "mipq_adc_search": (_I, [_P, _I, _I, _P, _I, _P, _I, _I, _P, _P, _P, _I, _I, _P, _P, _P, _P, _S, _P]),
     "mipq_profile_enable": (_I, [_I]),
     "mipq_profile_collect": (_I, [_I, ctypes.POINTER(_L), ctypes.POINTER(ctypes.c_double)]),
 }
 
 # kernel ids of mipq_profile_collect (enum mipq_kernel)
 KERNELS = {"assign_fp32": 0, "assign_bf16": 1, "update": 2, "finalize": 3, "pack_bf16": 4, "decode": 5,
-           "backward": 6}
+           "backward": 6, "coarse_pack": 7, "coarse_assign": 8, "sort": 9, "coarse_update": 10, "adc": 11}
 
 _lib = None
 

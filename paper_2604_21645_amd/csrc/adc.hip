@@ -1,0 +1,409 @@
+// Asymmetric-distance (ADC) search over the inverted file (paper Section 2.2:
+// a query returns its first to k-th nearest neighbours).
+//
+// 1. k_adc_dist: distance estimates of every (query, coarse centroid) pair on
+//    matrix cores (queries as the A operand, the packed coarse operands as B).
+// 2. k_adc_probe: per query, the nprobe lists with the smallest exact coarse
+//    distance (float32 differences, float64 squares and sums), ties to the
+//    lower list.  The estimate's error is at most beta, so every exact
+//    top-nprobe list has an estimate <= T + 2 beta, T the nprobe-th smallest
+//    estimate; exactly those candidates are re-scored with the exact rule and
+//    sorted.
+// 3. k_adc_scan: per query and probed list l, the table
+//    LUT[j][k] = subspace-j distance of (q - c_l) to C_j[k] (float32 rule),
+//    then s = sum over j ascending of LUT[j][code_j] (float32) for every row
+//    of the list; the topk smallest (s, id) pairs, kept with a threshold and
+//    an LDS candidate buffer, sorted at the end.
+#include <math.h>
+
+#include "bf16_pack.h"
+#include "dist32.h"
+#include "mipq_internal.h"
+
+namespace mipq {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kT = 256;
+constexpr int kTilesPerWave = 16;
+
+__device__ __forceinline__ bf16x8 to_bf16x8(const float* v) {
+  bf16x8 r;
+#pragma unroll
+  for (int e = 0; e < 8; e += 2) {
+    f32x2 p = {v[e], v[e + 1]};
+    bf16x2 q = __builtin_convertvector(p, bf16x2);
+    r[e] = q[0];
+    r[e + 1] = q[1];
+  }
+  return r;
+}
+
+// Wave (query group g of 32, tile range): A = centred queries (lane l: query
+// l%32, dimensions 16s + 8h .. +7), B = packed coarse operands.  Output row
+// q of est holds the kc estimates of query q.
+template <int S>
+__global__ __launch_bounds__(kT) void k_adc_dist(const float* __restrict__ q, int nq, int d, int kc,
+                                                 const bf16x8* __restrict__ aop, const float* __restrict__ mu,
+                                                 float* __restrict__ est) {
+  constexpr int NK = S + 1;
+  const int lane = threadIdx.x & 63;
+  const int h = lane >> 5;
+  const int nt = (kc + 31) / 32;
+  const int tgroups = (nt + kTilesPerWave - 1) / kTilesPerWave;
+  const int wid = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int g = wid / tgroups;
+  const int tg = wid - g * tgroups;
+  const int q0 = g * 32;
+  if (q0 >= nq) return;
+  const int qi = q0 + (lane & 31);
+  const float* qr = q + (int64_t)(qi < nq ? qi : q0) * d;
+  bf16x8 A[NK];
+  float xn_part = 0.0f;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int dim = 16 * s + 8 * h + e;
+      const float xv = qr[dim < d ? dim : d - 1];
+      v[e] = dim < d ? xv - mu[dim] : 0.0f;
+      xn_part = xn_part + v[e] * v[e];
+    }
+    A[s] = to_bf16x8(v);
+  }
+  const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_int(xn_part), __float_as_int(xn_part), false, false);
+  const float xn = __int_as_float((int)sw[0]) + __int_as_float((int)sw[1]);
+  {
+    bf16x8 nb = {};
+    if (h == 0) {
+      const __bf16 hb = (__bf16)xn;
+      const float r1 = xn - (float)hb;
+      const __bf16 mb = (__bf16)r1;
+      nb[0] = nb[1] = nb[2] = (__bf16)1.0f;
+      nb[3] = hb;
+      nb[4] = mb;
+      nb[5] = (__bf16)(r1 - (float)mb);
+    }
+    A[S] = nb;
+  }
+  const int t0 = tg * kTilesPerWave;
+  const int t1 = min(nt, t0 + kTilesPerWave);
+  for (int t = t0; t < t1; ++t) {
+    f32x16 acc = {};
+#pragma unroll
+    for (int s = 0; s < NK; ++s)
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s], aop[((size_t)t * NK + s) * 64 + lane], acc, 0, 0, 0);
+    const int k = t * 32 + (lane & 31);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int qq = q0 + (r >> 2) * 8 + h * 4 + (r & 3);
+      if (qq < nq && k < kc) est[(int64_t)qq * kc + k] = acc[r];
+    }
+  }
+}
+
+__device__ __forceinline__ double coarse_exact(const float* __restrict__ qr, const float* __restrict__ c, int d) {
+  double acc = 0.0;
+  for (int t = 0; t < d; ++t) {
+    const double df = (double)(qr[t] - c[t]);
+    acc = acc + df * df;
+  }
+  return acc;
+}
+
+// order-preserving uint of a float (negatives below positives)
+__device__ __forceinline__ uint32_t fkey(float f) {
+  const uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+struct DK {   // (distance, list) ordered lexicographically
+  double d;
+  int l;
+};
+__device__ __forceinline__ bool dk_less(const DK& a, const DK& b) { return a.d < b.d || (a.d == b.d && a.l < b.l); }
+
+constexpr int kBandMax = 512;
+
+// One block per query: select the nprobe lists (exact rule, ties to the lower
+// list) from the estimates; see the file comment for the band argument.
+__global__ __launch_bounds__(kT) void k_adc_probe(const float* __restrict__ q, int d, const float* __restrict__ cc,
+                                                  int kc, const float* __restrict__ est, const float* __restrict__ mu,
+                                                  const unsigned int* __restrict__ cmax_bits, int nprobe,
+                                                  float e_cross, float e_norm, float g_exact,
+                                                  int32_t* __restrict__ probes, unsigned long long* __restrict__ wide) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t sel_prefix, sel_need;
+  __shared__ DK band[kBandMax];
+  __shared__ int nband;
+  __shared__ float red[kT / 64];
+  const int qi = blockIdx.x;
+  const float* qr = q + (int64_t)qi * d;
+  const float* er = est + (int64_t)qi * kc;
+  // ||q - mu|| for the error bound
+  float xn = 0.0f;
+  for (int t = threadIdx.x; t < d; t += blockDim.x) {
+    const float v = qr[t] - mu[t];
+    xn += v * v;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) xn += __shfl_xor(xn, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = xn;
+  // radix select of the nprobe-th smallest estimate (order-preserving keys)
+  if (threadIdx.x == 0) {
+    sel_prefix = 0u;
+    sel_need = (uint32_t)nprobe;
+    nband = 0;
+  }
+  __syncthreads();
+  float xs = 0.0f;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) xs += red[i];
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    hist[threadIdx.x] = 0u;
+    __syncthreads();
+    const uint32_t pmask = shift == 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
+    for (int l = threadIdx.x; l < kc; l += blockDim.x) {
+      const uint32_t k = fkey(er[l]);
+      if ((k & pmask) == sel_prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t need = sel_need, b = 0;
+      while (b < 255 && hist[b] < need) {
+        need -= hist[b];
+        ++b;
+      }
+      sel_prefix |= b << shift;
+      sel_need = need;
+    }
+    __syncthreads();
+  }
+  const uint32_t tk = sel_prefix;
+  const float T = __uint_as_float((tk & 0x80000000u) ? (tk & 0x7FFFFFFFu) : ~tk);
+  const float cm = __uint_as_float(*cmax_bits);
+  const float beta = e_cross * sqrtf(xs) * 1.0001f * cm + e_norm * (cm * cm + xs);
+  const float lim = T + 2.0f * beta + g_exact * (2.0f * fabsf(T) + 4.0f * beta + 2.0f * xs * g_exact);
+  // band members, re-scored with the exact rule
+  bool overflow = false;
+  for (int l = threadIdx.x; l < kc; l += blockDim.x) {
+    if (!(er[l] <= lim)) continue;
+    const int p = atomicAdd(&nband, 1);
+    if (p < kBandMax) band[p] = DK{coarse_exact(qr, cc + (int64_t)l * d, d), l};
+  }
+  __syncthreads();
+  int nb = nband;
+  if (nb > kBandMax) {
+    overflow = true;
+    nb = kBandMax;
+  }
+  if (overflow) {   // too many near the boundary: rank every list exactly, keep the nprobe best
+    if (threadIdx.x == 0 && wide) atomicAdd(wide, 1ull);
+    __syncthreads();
+    if (threadIdx.x == 0) nband = 0;
+    __syncthreads();
+    // exact distances in chunks, merged with the best nprobe kept in front
+    for (int next = 0; next < kc;) {
+      const int keep = next == 0 ? 0 : nprobe;
+      for (int i = threadIdx.x; i < kBandMax - keep; i += blockDim.x) {
+        const int l = next + i;
+        band[keep + i] = l < kc ? DK{coarse_exact(qr, cc + (int64_t)l * d, d), l} : DK{INFINITY, 0x7FFFFFFF};
+      }
+      next += kBandMax - keep;
+      __syncthreads();
+      for (int kk = 2; kk <= kBandMax; kk <<= 1)
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+          for (int i = threadIdx.x; i < kBandMax; i += blockDim.x) {
+            const int ij = i ^ j;
+            if (ij > i) {
+              const bool up = (i & kk) == 0;
+              const DK a = band[i], b = band[ij];
+              if (up ? dk_less(b, a) : dk_less(a, b)) {
+                band[i] = b;
+                band[ij] = a;
+              }
+            }
+          }
+          __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < nprobe; i += blockDim.x) probes[(int64_t)qi * nprobe + i] = band[i].l;
+    return;
+  }
+  // sort the band (padded to a power of two) and keep the first nprobe
+  int p2 = 1;
+  while (p2 < nb) p2 <<= 1;
+  for (int i = nb + threadIdx.x; i < p2; i += blockDim.x) band[i] = DK{INFINITY, 0x7FFFFFFF};
+  __syncthreads();
+  for (int kk = 2; kk <= p2; kk <<= 1)
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < p2; i += blockDim.x) {
+        const int ij = i ^ j;
+        if (ij > i) {
+          const bool up = (i & kk) == 0;
+          const DK a = band[i], b = band[ij];
+          if (up ? dk_less(b, a) : dk_less(a, b)) {
+            band[i] = b;
+            band[ij] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = threadIdx.x; i < nprobe; i += blockDim.x) probes[(int64_t)qi * nprobe + i] = i < nb ? band[i].l : -1;
+}
+
+constexpr int kCap = 2048;   // LDS candidate buffer (uint64 keys)
+
+__device__ void sort_keys(uint64_t* buf, int n2) {
+  for (int kk = 2; kk <= n2; kk <<= 1)
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+        const int ij = i ^ j;
+        if (ij > i) {
+          const bool up = (i & kk) == 0;
+          const uint64_t a = buf[i], b = buf[ij];
+          if (up ? (b < a) : (a < b)) {
+            buf[i] = b;
+            buf[ij] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+}
+
+// One block per query.  LDS: the table (m*ks floats), the query residual
+// (d floats), and the candidate buffer of (score bits << 32 | id) keys.
+template <int DS>
+__global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, int d, const float* __restrict__ cc,
+                                                 const float* __restrict__ pq, int m, int ks,
+                                                 const int64_t* __restrict__ offsets, const int32_t* __restrict__ ids,
+                                                 const uint8_t* __restrict__ codes, const int32_t* __restrict__ probes,
+                                                 int nprobe, int topk, int32_t* __restrict__ out_ids,
+                                                 float* __restrict__ out_dist) {
+  extern __shared__ float sm[];
+  float* lut = sm;                                   // m*ks
+  float* rq = lut + m * ks;                          // d
+  uint64_t* buf = reinterpret_cast<uint64_t*>(rq + ((d + 1) & ~1));   // kCap
+  __shared__ int cnt;
+  __shared__ uint64_t thresh;
+  const int qi = blockIdx.x;
+  const float* qr = q + (int64_t)qi * d;
+  if (threadIdx.x == 0) {
+    cnt = 0;
+    thresh = ~0ull;
+  }
+  for (int pi = 0; pi < nprobe; ++pi) {
+    const int l = probes[(int64_t)qi * nprobe + pi];
+    if (l < 0) continue;   // block-uniform
+    __syncthreads();
+    for (int t = threadIdx.x; t < d; t += blockDim.x) rq[t] = qr[t] - cc[(int64_t)l * d + t];
+    __syncthreads();
+    for (int e = threadIdx.x; e < m * ks; e += blockDim.x) {
+      const int j = e / ks, k = e - j * ks;
+      lut[e] = sqdist_fixed<DS>(rq + j * DS, pq + ((int64_t)j * ks + k) * DS);
+    }
+    __syncthreads();
+    const int64_t a = offsets[l], b = offsets[l + 1];
+    for (int64_t p0 = a; p0 < b; p0 += blockDim.x) {
+      const int64_t p = p0 + threadIdx.x;
+      if (p < b) {
+        const uint8_t* cr = codes + p * m;
+        float s = lut[cr[0]];
+        for (int j = 1; j < m; ++j) s = s + lut[j * ks + cr[j]];
+        const uint64_t key = ((uint64_t)__float_as_uint(s) << 32) | (uint32_t)ids[p];
+        if (key < thresh) {
+          const int slot = atomicAdd(&cnt, 1);
+          if (slot < kCap) buf[slot] = key;
+        }
+      }
+      __syncthreads();
+      if (cnt > kCap - (int)blockDim.x) {   // compact: keep the best topk, tighten the threshold
+        const int c = cnt < kCap ? cnt : kCap;
+        for (int i = c + threadIdx.x; i < kCap; i += blockDim.x) buf[i] = ~0ull;
+        __syncthreads();
+        sort_keys(buf, kCap);
+        if (threadIdx.x == 0) {
+          const int keep = c < topk ? c : topk;
+          cnt = keep;
+          if (keep == topk) thresh = buf[topk - 1];
+        }
+        __syncthreads();
+      }
+    }
+  }
+  __syncthreads();
+  const int c = cnt < kCap ? cnt : kCap;
+  int p2 = 1;
+  while (p2 < c) p2 <<= 1;
+  for (int i = c + threadIdx.x; i < p2; i += blockDim.x) buf[i] = ~0ull;
+  __syncthreads();
+  sort_keys(buf, p2);
+  for (int i = threadIdx.x; i < topk; i += blockDim.x) {
+    const bool real = i < c;
+    out_ids[(int64_t)qi * topk + i] = real ? (int32_t)(uint32_t)(buf[i] & 0xFFFFFFFFull) : -1;
+    out_dist[(int64_t)qi * topk + i] = real ? __uint_as_float((uint32_t)(buf[i] >> 32)) : INFINITY;
+  }
+}
+
+}  // namespace
+
+int adc_scan_smem(int d, int m, int ks) {
+  return (int)((size_t)m * ks * sizeof(float) + (size_t)((d + 1) & ~1) * sizeof(float) + kCap * sizeof(uint64_t));
+}
+
+int launch_adc(const float* q, int nq, int d, const float* cc, int kc, const void* aop, const float* mu,
+               const unsigned int* cmax_bits, const float* pq, int m, int ks, const int64_t* offsets,
+               const int32_t* ids, const uint8_t* codes, int nprobe, int topk, float* est, int32_t* probes,
+               int64_t* wide, int32_t* out_ids, float* out_dist, hipStream_t s) {
+  if (nq == 0) return MIPQ_OK;
+  ProfScope ps(MIPQ_K_ADC, s);
+  const int S = coarse_ksteps(d);
+  const int nt = (kc + 31) / 32;
+  const int tgroups = (nt + kTilesPerWave - 1) / kTilesPerWave;
+  const int waves = ceil_div(nq, 32) * tgroups;
+  const int blocks = ceil_div(waves, kT / 64);
+#define AD(SV) k_adc_dist<SV><<<blocks, kT, 0, s>>>(q, nq, d, kc, (const bf16x8*)aop, mu, est)
+  switch (S) {
+    case 1: AD(1); break;
+    case 2: AD(2); break;
+    case 4: AD(4); break;
+    case 6: AD(6); break;
+    case 8: AD(8); break;
+    case 12: AD(12); break;
+    case 16: AD(16); break;
+    default: return fail(MIPQ_EUNSUPPORTED, "ADC needs d <= 16 or d in {32, 64, 96, 128, 192, 256}");
+  }
+#undef AD
+  MIPQ_LAUNCHED("k_adc_dist");
+  const float e_cross = 0.0165f;
+  const float e_norm = 16.0f * (S + 1) * 1.2e-7f + 2.4e-7f;
+  const float g_exact = 1.3e-7f;
+  k_adc_probe<<<nq, kT, 0, s>>>(q, d, cc, kc, est, mu, cmax_bits, nprobe, e_cross, e_norm, g_exact, probes,
+                                reinterpret_cast<unsigned long long*>(wide));
+  MIPQ_LAUNCHED("k_adc_probe");
+  const int ds = d / m;
+  const size_t shm = adc_scan_smem(d, m, ks);
+#define SC(DSV)                                                                                      \
+  k_adc_scan<DSV><<<nq, kT, shm, s>>>(q, d, cc, pq, m, ks, offsets, ids, codes, probes, nprobe, topk, \
+                                      out_ids, out_dist)
+  switch (ds) {
+    case 1: SC(1); break;
+    case 2: SC(2); break;
+    case 4: SC(4); break;
+    case 8: SC(8); break;
+    case 16: SC(16); break;
+    default: return fail(MIPQ_EUNSUPPORTED, "ADC supports d/m in {1, 2, 4, 8, 16} (got %d)", ds);
+  }
+#undef SC
+  MIPQ_LAUNCHED("k_adc_scan");
+  return MIPQ_OK;
+}
+
+}  // namespace mipq

@@ -252,4 +252,226 @@ int mipq_recon_backward(const float* x, const uint8_t* codes, const float* codeb
   return MIPQ_OK;
 }
 
+// ---------------------------------------------------------------- inverted file
+namespace {
+
+struct CoarseWs {
+  void* aop = nullptr;
+  float* mu = nullptr;
+  unsigned int* cmax = nullptr;
+};
+
+CoarseWs carve_coarse(Carver& c, int d, int kc, int precision) {
+  CoarseWs w;
+  if (precision == MIPQ_BF16) {
+    w.aop = c.take<uint4>(coarse_operand_count(kc, d));
+    w.mu = c.take<float>(d);
+    w.cmax = c.take<unsigned int>(4);
+  }
+  return w;
+}
+
+int check_coarse(int64_t n, int d, int kc, int precision) {
+  if (n < 0 || n >= (int64_t(1) << 31)) return fail(MIPQ_EINVAL, "n out of range (%lld)", (long long)n);
+  if (d <= 0) return fail(MIPQ_EINVAL, "d must be positive");
+  if (kc < 1 || kc > 65536) return fail(MIPQ_EINVAL, "kc must be in [1, 65536] (got %d)", kc);
+  if (precision == MIPQ_BF16) {
+    const int S = coarse_ksteps(d);
+    if (d > 256 || !(S == 1 || S == 2 || S == 4 || S == 6 || S == 8 || S == 12 || S == 16))
+      return fail(MIPQ_EUNSUPPORTED, "coarse matrix-core path needs d <= 16 or d in {32, 64, 96, 128, 192, 256}");
+  } else if (precision != MIPQ_FP32) {
+    return fail(MIPQ_EINVAL, "unknown precision %d", precision);
+  }
+  return MIPQ_OK;
+}
+
+int coarse_assign_any(const float* x, int64_t n, int d, const float* cc, int kc, int precision,
+                      const CoarseWs& w, int32_t* labels, int64_t* rescored, hipStream_t s) {
+  int rc;
+  if (precision == MIPQ_BF16 && (rc = launch_coarse_prepare(cc, kc, d, w.mu, w.cmax, w.aop, s))) return rc;
+  return launch_coarse_assign(x, n, d, cc, kc, w.aop, w.mu, w.cmax, labels, rescored,
+                              precision != MIPQ_BF16, s);
+}
+
+struct BuildWs {
+  float* xs;
+  double* cc64;
+  int32_t* tlabels;
+  uint32_t *keys_a, *keys_b, *keys_sorted, *hist;
+  int32_t *vals_a, *vals_b, *tids;
+  int64_t* toffsets;
+  double* obj_list;
+  CoarseWs cw;
+  float* rtrain;
+  int32_t* lab;
+  uint8_t* codes;
+  float* rbuf;
+  int64_t chunk;
+  void* sub;
+  size_t sub_bytes;
+  size_t bytes;
+};
+
+BuildWs carve_build(void* ws, int64_t n, int d, int kc, int64_t n_train, int m, int ks, int pq_iters,
+                    int precision, bool need_labels) {
+  Carver c(ws);
+  BuildWs b;
+  const int64_t nmax = n > n_train ? n : n_train;
+  b.xs = c.take<float>((size_t)n_train * d);
+  b.cc64 = c.take<double>((size_t)kc * d);
+  b.tlabels = c.take<int32_t>(n_train);
+  b.keys_a = c.take<uint32_t>(nmax);
+  b.keys_b = c.take<uint32_t>(nmax);
+  b.keys_sorted = c.take<uint32_t>(nmax);
+  b.hist = c.take<uint32_t>((size_t)64 * sort_blocks(nmax));
+  b.vals_a = c.take<int32_t>(nmax);
+  b.vals_b = c.take<int32_t>(nmax);
+  b.tids = c.take<int32_t>(n_train);
+  b.toffsets = c.take<int64_t>(kc + 1);
+  b.obj_list = c.take<double>(kc);
+  b.cw = carve_coarse(c, d, kc, precision);
+  b.rtrain = c.take<float>((size_t)n_train * d);
+  b.lab = need_labels ? c.take<int32_t>(n) : nullptr;
+  b.codes = c.take<uint8_t>((size_t)n * m);
+  b.chunk = n < (int64_t(1) << 20) ? n : (int64_t(1) << 20);
+  b.rbuf = c.take<float>((size_t)b.chunk * d);
+  const size_t fitb = mipq_pq_fit_workspace_size(n_train, d, m, ks, pq_iters, precision);
+  const size_t encb = mipq_pq_encode_workspace_size(b.chunk, d, m, ks, precision);
+  b.sub_bytes = fitb > encb ? fitb : encb;
+  b.sub = c.take<char>(b.sub_bytes);
+  b.bytes = c.bytes();
+  return b;
+}
+
+}  // namespace
+
+size_t mipq_coarse_assign_workspace_size(int d, int kc, int precision) {
+  if (check_coarse(0, d, kc, precision) != MIPQ_OK) return 0;
+  Carver c(nullptr);
+  carve_coarse(c, d, kc, precision);
+  return c.bytes();
+}
+
+int mipq_coarse_assign(const float* x, int64_t n, int d, const float* coarse, int kc, int precision,
+                       int32_t* labels, int64_t* rescored, void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_coarse(n, d, kc, precision))) return rc;
+  if (!coarse || (n > 0 && (!x || !labels))) return fail(MIPQ_EINVAL, "x, coarse and labels are required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Carver c(ws);
+  CoarseWs w = carve_coarse(c, d, kc, precision);
+  if ((rc = check_ws(ws, ws_bytes, c.bytes()))) return rc;
+  if (rescored && (rc = launch_zero_u32(reinterpret_cast<uint32_t*>(rescored), 2, s))) return rc;
+  if (n == 0) return MIPQ_OK;
+  return coarse_assign_any(x, n, d, coarse, kc, precision, w, labels, rescored, s);
+}
+
+size_t mipq_ii_build_workspace_size(int64_t n, int d, int kc, int64_t n_train, int m, int ks, int pq_iters,
+                                    int coarse_iters, int precision) {
+  if (check_coarse(n, d, kc, precision) != MIPQ_OK || check_shape(n_train, d, m, ks, precision, true) != MIPQ_OK)
+    return 0;
+  (void)coarse_iters;
+  return carve_build(nullptr, n, d, kc, n_train, m, ks, pq_iters, precision, true).bytes;
+}
+
+int mipq_ii_build(const float* x, int64_t n, int d, int kc, int coarse_iters, const int64_t* train_rows,
+                  int64_t n_train, const int64_t* coarse_init, int m, int ks, int pq_iters,
+                  const int64_t* pq_init, int precision, float* coarse, float* pq_codebook,
+                  int64_t* offsets, int32_t* ids, uint8_t* codes_sorted, int32_t* labels,
+                  double* coarse_objective, void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_coarse(n, d, kc, precision))) return rc;
+  if ((rc = check_shape(n_train, d, m, ks, precision, true))) return rc;
+  if (n < 1 || n_train < 1) return fail(MIPQ_EINVAL, "n and n_train must be positive");
+  if (coarse_iters < 0 || pq_iters < 0) return fail(MIPQ_EINVAL, "iteration counts must be >= 0");
+  if (!x || !train_rows || !coarse_init || !pq_init || !coarse || !pq_codebook || !offsets || !ids || !codes_sorted)
+    return fail(MIPQ_EINVAL, "a required pointer is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  BuildWs b = carve_build(ws, n, d, kc, n_train, m, ks, pq_iters, precision, labels == nullptr);
+  if ((rc = check_ws(ws, ws_bytes, b.bytes))) return rc;
+  int32_t* lab = labels ? labels : b.lab;
+  uint32_t* bad = reinterpret_cast<uint32_t*>(b.hist);   // scratch flag before the first sort
+  // 1. training sample and coarse init
+  if ((rc = launch_gather_rows(x, n, d, train_rows, n_train, b.xs, bad, s))) return rc;
+  if ((rc = launch_gather_coarse(b.xs, n_train, d, coarse_init, kc, coarse, b.cc64, s))) return rc;
+  // 2. coarse Lloyd rounds on the sample
+  for (int it = 0; it < coarse_iters; ++it) {
+    if ((rc = coarse_assign_any(b.xs, n_train, d, coarse, kc, precision, b.cw, b.tlabels, nullptr, s))) return rc;
+    if ((rc = launch_sort_by_label(b.tlabels, n_train, kc, b.keys_a, b.keys_b, b.vals_a, b.vals_b, b.hist, b.tids,
+                                   b.keys_sorted, b.toffsets, s)))
+      return rc;
+    if ((rc = launch_coarse_update(b.xs, d, b.tids, b.toffsets, kc, coarse, b.cc64, b.obj_list,
+                                   coarse_objective ? coarse_objective + it : nullptr, s)))
+      return rc;
+  }
+  // 3. final sample labels, residuals, residual PQ fit
+  if ((rc = coarse_assign_any(b.xs, n_train, d, coarse, kc, precision, b.cw, b.tlabels, nullptr, s))) return rc;
+  if ((rc = launch_residuals(b.xs, n_train, d, b.tlabels, coarse, kc, b.rtrain, s))) return rc;
+  if ((rc = mipq_pq_fit(b.rtrain, n_train, nullptr, 0, d, m, ks, pq_iters, pq_init, nullptr, precision,
+                        pq_codebook, nullptr, nullptr, nullptr, b.sub, b.sub_bytes, stream)))
+    return rc;
+  // 4. labels and residual codes of all rows (residuals formed chunk by chunk)
+  if ((rc = coarse_assign_any(x, n, d, coarse, kc, precision, b.cw, lab, nullptr, s))) return rc;
+  for (int64_t a = 0; a < n; a += b.chunk) {
+    const int64_t cnt = (n - a) < b.chunk ? (n - a) : b.chunk;
+    if ((rc = launch_residuals(x + a * d, cnt, d, lab + a, coarse, kc, b.rbuf, s))) return rc;
+    if ((rc = mipq_pq_encode(b.rbuf, cnt, d, m, ks, pq_codebook, precision, b.codes + a * m, nullptr, b.sub,
+                             b.sub_bytes, stream)))
+      return rc;
+  }
+  // 5. stable bucketing by label, codes in list order
+  if ((rc = launch_sort_by_label(lab, n, kc, b.keys_a, b.keys_b, b.vals_a, b.vals_b, b.hist, ids, b.keys_sorted,
+                                 offsets, s)))
+    return rc;
+  return launch_gather_codes(b.codes, n, m, ids, codes_sorted, s);
+}
+
+namespace {
+struct AdcWs {
+  CoarseWs cw;
+  float* est;
+  int32_t* probes;
+  size_t bytes;
+};
+AdcWs carve_adc(void* ws, int nq, int d, int kc, int nprobe) {
+  Carver c(ws);
+  AdcWs a;
+  a.cw = carve_coarse(c, d, kc, MIPQ_BF16);
+  a.est = c.take<float>((size_t)nq * kc);
+  a.probes = c.take<int32_t>((size_t)nq * nprobe);
+  a.bytes = c.bytes();
+  return a;
+}
+}  // namespace
+
+size_t mipq_adc_search_workspace_size(int nq, int d, int kc, int nprobe) {
+  if (nq < 0 || check_coarse(0, d, kc, MIPQ_BF16) != MIPQ_OK || nprobe < 1) return 0;
+  return carve_adc(nullptr, nq, d, kc, nprobe).bytes;
+}
+
+int mipq_adc_search(const float* q, int nq, int d, const float* coarse, int kc, const float* pq_codebook,
+                    int m, int ks, const int64_t* offsets, const int32_t* ids, const uint8_t* codes_sorted,
+                    int nprobe, int topk, int32_t* out_ids, float* out_dist, int64_t* wide, void* ws,
+                    size_t ws_bytes, void* stream) {
+  int rc;
+  if (nq < 0) return fail(MIPQ_EINVAL, "nq must be >= 0");
+  if ((rc = check_coarse(0, d, kc, MIPQ_BF16))) return rc;
+  if ((rc = check_shape(0, d, m, ks, MIPQ_FP32, false))) return rc;
+  const int ds = d / m;
+  if (!(ds == 1 || ds == 2 || ds == 4 || ds == 8 || ds == 16))
+    return fail(MIPQ_EUNSUPPORTED, "ADC supports d/m in {1, 2, 4, 8, 16} (got %d)", ds);
+  if (nprobe < 1 || nprobe > kc || nprobe > 256) return fail(MIPQ_EINVAL, "nprobe must be in [1, min(kc, 256)]");
+  if (topk < 1 || topk > 1024) return fail(MIPQ_EINVAL, "topk must be in [1, 1024]");
+  if (nq > 0 && (!q || !coarse || !pq_codebook || !offsets || !ids || !codes_sorted || !out_ids || !out_dist))
+    return fail(MIPQ_EINVAL, "a required pointer is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  AdcWs a = carve_adc(ws, nq, d, kc, nprobe);
+  if ((rc = check_ws(ws, ws_bytes, a.bytes))) return rc;
+  if (wide && (rc = launch_zero_u32(reinterpret_cast<uint32_t*>(wide), 2, s))) return rc;
+  if (nq == 0) return MIPQ_OK;
+  if ((rc = launch_coarse_prepare(coarse, kc, d, a.cw.mu, a.cw.cmax, a.cw.aop, s))) return rc;
+  return launch_adc(q, nq, d, coarse, kc, a.cw.aop, a.cw.mu, a.cw.cmax, pq_codebook, m, ks, offsets, ids,
+                    codes_sorted, nprobe, topk, a.est, a.probes, wide, out_ids, out_dist, s);
+}
+
 }  // extern "C"

@@ -102,6 +102,32 @@ int backward_chunks(int64_t n, int m);
 int launch_backward(const float* x, int64_t n, int d, int m, int ks, const uint8_t* codes,
                     const float* c32, const double* gscale, float* grad_x, float* grad_c, int nch,
                     double* part_s, uint32_t* part_cnt, double* part_j, double* loss_sub, hipStream_t s);
+// inverted file (ivf.hip)
+int coarse_ksteps(int d);
+size_t coarse_operand_count(int kc, int d);
+int launch_coarse_prepare(const float* cc, int kc, int d, float* mu, unsigned int* cmax_bits, void* aop,
+                          hipStream_t s);
+int launch_coarse_assign(const float* x, int64_t n, int d, const float* cc, int kc, const void* aop,
+                         const float* mu, const unsigned int* cmax_bits, int32_t* labels, int64_t* rescored,
+                         bool exact_only, hipStream_t s);
+int sort_blocks(int64_t n);
+int launch_sort_by_label(const int32_t* labels, int64_t n, int kc, uint32_t* keys_a, uint32_t* keys_b,
+                         int32_t* vals_a, int32_t* vals_b, uint32_t* hist, int32_t* ids_out,
+                         uint32_t* keys_out_sorted, int64_t* offsets, hipStream_t s);
+int launch_coarse_update(const float* x, int d, const int32_t* ids, const int64_t* offsets, int kc, float* cc,
+                         double* cc64, double* obj_list, double* obj_out, hipStream_t s);
+int launch_gather_coarse(const float* x, int64_t n, int d, const int64_t* rows, int kc, float* cc, double* cc64,
+                         hipStream_t s);
+int launch_residuals(const float* x, int64_t n, int d, const int32_t* labels, const float* cc, int kc, float* r,
+                     hipStream_t s);
+int launch_gather_codes(const uint8_t* codes, int64_t n, int m, const int32_t* ids, uint8_t* out, hipStream_t s);
+
+// ADC search (adc.hip)
+int launch_adc(const float* q, int nq, int d, const float* cc, int kc, const void* aop, const float* mu,
+               const unsigned int* cmax_bits, const float* pq, int m, int ks, const int64_t* offsets,
+               const int32_t* ids, const uint8_t* codes, int nprobe, int topk, float* est, int32_t* probes,
+               int64_t* wide, int32_t* out_ids, float* out_dist, hipStream_t s);
+
 // operands of the centred codebook; mu: m * kMaxDsBf16 floats (subspace centres)
 int launch_pack_bf16(const float* c32, int m, int ks, int ds, void* aop, float* cmax, float* mu,
                      hipStream_t s);

@@ -1,0 +1,127 @@
+"""GPU parity of the inverted file: coarse assignment, stable bucketing, the
+full index build and ADC top-k search, against the oracle in its
+kernel-decision mode (bit for bit) and the float64 oracle outside near-ties."""
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2604_21645_amd as mipq
+from oracle import ivf, pq
+from synth import workloads as wl
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("n,d,kc", [(3001, 128, 100), (777, 64, 33), (1000, 32, 300), (64, 16, 7)])
+def test_coarse_assign_matches_oracle(prec, n, d, kc):
+    print("coarse", prec, n, d, kc, flush=True)
+    x = wl.gaussian_mixture(n + d, n, d, 50, sigma=0.05)
+    cc = wl.gaussian_mixture(kc, kc, d, 50, sigma=0.05)
+    lab, resc = mipq.coarse_assign(_t(x), _t(cc), prec, rescored=True)
+    ref, tie = ivf.coarse_assign(x, cc, "kernel")
+    np.testing.assert_array_equal(lab.cpu().numpy().astype(np.int64), ref)
+    r64, _ = ivf.coarse_assign(x, cc, "fp64")
+    got = lab.cpu().numpy()
+    assert np.all(got[~tie] == r64[~tie])
+
+
+def test_coarse_assign_duplicate_centroids_are_decided_exactly():
+    rng = np.random.default_rng(4)
+    cc = rng.integers(0, 3, size=(40, 32)).astype(np.float32)
+    cc[20:] = cc[:20]
+    x = rng.integers(0, 3, size=(500, 32)).astype(np.float32)
+    lab, resc = mipq.coarse_assign(_t(x), _t(cc), "bf16", rescored=True)
+    ref, _ = ivf.coarse_assign(x, cc, "kernel")
+    np.testing.assert_array_equal(lab.cpu().numpy().astype(np.int64), ref)
+    assert int(resc.item()) > 0
+
+
+def _small():
+    return wl.ivf_adc(seed=21, n=20000, d=32, n_comp=64, kc=64, n_query=40, m=4, ks=16, coarse_iters=5,
+                      pq_iters=5, n_train=4000, nprobe=6, topk=25)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_index_build_matches_oracle(prec):
+    w = _small()
+    idx = mipq.ii_build(_t(w.x), w.kc, w.coarse_iters, _t(w.coarse_train), _t(w.coarse_init), w.m, w.ks,
+                        w.pq_iters, _t(w.pq_init), precision=prec, coarse_objective=True)
+    ref = ivf.build(w.x, w.coarse_train, w.coarse_init, w.coarse_iters, w.m, w.pq_init, w.pq_iters)
+    # coarse centroids: same decisions, same float64 sums in id order
+    np.testing.assert_array_equal(idx["coarse"].cpu().numpy(), ref["coarse"].astype(np.float32))
+    np.testing.assert_array_equal(idx["labels"].cpu().numpy().astype(np.int64), ref["labels"])
+    np.testing.assert_array_equal(idx["offsets"].cpu().numpy(), ref["offsets"])
+    np.testing.assert_array_equal(idx["ids"].cpu().numpy().astype(np.int64), ref["ids"])
+    pqc = idx["pq_codebook"].cpu().numpy()
+    np.testing.assert_allclose(pqc, ref["pq"], rtol=1e-6, atol=1e-7)
+    # residual codes in list order, against the oracle's encode with the GPU codebook
+    r = ivf.residuals(w.x, ref["labels"], ref["coarse"].astype(np.float32))
+    codes_ref, _ = pq.encode(r, pqc.astype(np.float64), decide="fp32")
+    np.testing.assert_array_equal(idx["codes_sorted"].cpu().numpy().astype(np.int64), codes_ref[ref["ids"]])
+    obj = idx["coarse_objective"].cpu().numpy()
+    assert np.all(np.diff(obj) <= 1e-9 * obj[:-1])
+
+
+def _gpu_index_np(idx):
+    return (idx["coarse"].cpu().numpy(), idx["pq_codebook"].cpu().numpy(), idx["offsets"].cpu().numpy(),
+            idx["ids"].cpu().numpy().astype(np.int64))
+
+
+@pytest.mark.parametrize("nprobe,topk", [(6, 25), (1, 300), (64, 10)])
+def test_adc_search_matches_oracle(nprobe, topk):
+    w = _small()
+    idx = mipq.ii_build(_t(w.x), w.kc, w.coarse_iters, _t(w.coarse_train), _t(w.coarse_init), w.m, w.ks,
+                        w.pq_iters, _t(w.pq_init))
+    cc, pqc, off, ids = _gpu_index_np(idx)
+    codes_sorted = idx["codes_sorted"].cpu().numpy().astype(np.int64)
+    codes_by_id = np.empty_like(codes_sorted)
+    codes_by_id[ids] = codes_sorted
+    gi, gd = mipq.adc_search(_t(w.queries), idx, nprobe, topk)
+    ri, rd = ivf.adc_search(w.queries, cc, pqc, off, ids, codes_by_id, nprobe, topk, decide="kernel")
+    np.testing.assert_array_equal(gi.cpu().numpy().astype(np.int64), ri)
+    np.testing.assert_array_equal(gd.cpu().numpy(), rd.astype(np.float32))
+
+
+def test_full_size_index_and_search_sampled():
+    """10M x 128 rows, Kc = 4096, residual PQ M=16 Ks=256, 10k queries,
+    nprobe 32, top-100: bucket invariants on every row, sampled labels and
+    codes, and 100 sampled queries against the oracle."""
+    w = wl.ivf_adc()
+    xt = _t(w.x)
+    print("build", flush=True)
+    idx = mipq.ii_build(xt, w.kc, w.coarse_iters, _t(w.coarse_train), _t(w.coarse_init), w.m, w.ks, w.pq_iters,
+                        _t(w.pq_init))
+    n = w.x.shape[0]
+    cc, pqc, off, ids = _gpu_index_np(idx)
+    lab = idx["labels"].cpu().numpy()
+    assert off[0] == 0 and off[-1] == n and np.all(np.diff(off) >= 0)
+    np.testing.assert_array_equal(np.diff(off), np.bincount(lab, minlength=w.kc))
+    assert np.array_equal(np.sort(ids), np.arange(n))
+    for l in np.random.default_rng(1).choice(w.kc, 64, replace=False):
+        seg = ids[off[l]:off[l + 1]]
+        assert np.all(np.diff(seg) > 0) and np.all(lab[seg] == l)
+    rows = np.random.default_rng(2).choice(n, 3000, replace=False)
+    ref_lab, _ = ivf.coarse_assign(w.x[rows], cc, "kernel")
+    np.testing.assert_array_equal(lab[rows].astype(np.int64), ref_lab)
+    codes_sorted = idx["codes_sorted"].cpu().numpy()
+    pos = np.empty(n, dtype=np.int64)
+    pos[ids] = np.arange(n)
+    r = ivf.residuals(w.x[rows], ref_lab, cc)
+    cref, _ = pq.encode(r, pqc.astype(np.float64), decide="fp32")
+    np.testing.assert_array_equal(codes_sorted[pos[rows]].astype(np.int64), cref)
+    print("search", flush=True)
+    gi, gd, wide = mipq.adc_search(_t(w.queries), idx, w.nprobe, w.topk, wide=True)
+    print("wide probe selections", int(wide.item()), flush=True)
+    codes_by_id = np.empty_like(codes_sorted)
+    codes_by_id[ids] = codes_sorted
+    qs = np.random.default_rng(3).choice(w.queries.shape[0], 100, replace=False)
+    ri, rd = ivf.adc_search(w.queries[qs], cc, pqc, off, ids, codes_by_id, w.nprobe, w.topk, decide="kernel")
+    np.testing.assert_array_equal(gi.cpu().numpy()[qs].astype(np.int64), ri)
+    np.testing.assert_array_equal(gd.cpu().numpy()[qs], rd.astype(np.float32))
