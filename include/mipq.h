@@ -128,6 +128,68 @@ int mipq_pq_decode_rmse(const uint8_t* codes, int64_t n, int d, int m, int ks,
                         void* ws, size_t ws_bytes, void* stream);
 
 /* -------------------------------------------------------------------------
+ * Batched fit + encode of many independent problems (paper Section 3: the
+ * rows are split into chunks that are quantised in parallel, each chunk with
+ * its own codebook).
+ *
+ * Problem p fits its own codebook on all of its own rows (the Lloyd rounds
+ * of mipq_pq_fit with train_rows NULL, `iters` rounds, from its init_rows),
+ * encodes all of its rows with the final codebook and, when sse_rmse is
+ * non-NULL, reports the reconstruction error of those codes.  All problems
+ * share d, m, ks and precision (MIPQ_BF16 only).  Per problem the outputs are
+ * those of mipq_pq_fit + mipq_pq_encode + mipq_pq_decode_rmse on that
+ * problem: same code rule, same row chunks for the float64 centroid sums,
+ * same reduction order for the objective and the error.  (Within a chunk the
+ * float64 sums are formed by atomic additions, so their last bits, and hence
+ * rarely a float32 centroid, can differ between any two runs; integer-valued
+ * rows make every sum exact.)
+ *
+ * Each phase is one launch over all problems: a persistent matrix-core
+ * assignment over the flat list of (problem, 4-subspace group, 32-row tile)
+ * units, one accumulation launch over all (problem, row chunk, subspace)
+ * items and one finalisation launch over all (problem, subspace) pairs.
+ */
+typedef struct mipq_problem {
+  const float* x;            /* rows [n][d] */
+  int64_t n;                 /* number of rows, >= 1, n*m < 2^32 */
+  const int64_t* init_rows;  /* int64 [m][ks]: centroid k of subspace j starts as
+                                row init_rows[j*ks + k] of x */
+  float* codebook;           /* OUT float32 [m][ks][ds] */
+  uint8_t* codes;            /* OUT uint8 [n][m]: codes against the final codebook */
+  double* sse_rmse;          /* OUT optional float64 [2]: SSE and RMSE of the codes */
+  double* objective;         /* OUT optional float64 [iters] (as mipq_pq_fit) */
+} mipq_problem;
+
+/* Launch plan for one problem table: the grid of the persistent assignment
+ * (MIPQ_PLAN_AUTOTUNE: the fastest of a few sizes, timed on the problems'
+ * own round-0 assignment, which writes their codes and codebooks) and, with
+ * MIPQ_PLAN_GRAPH, the launch sequence recorded as HIP graphs (set-up, one
+ * Lloyd round replayed `iters` times, encode + error).  A plan is bound to the
+ * problem table (pointers and sizes), the shapes and the workspace it was
+ * made with; the plan object is host memory owned by the library.
+ * mipq_plan_create waits for `stream`.  Graphs are replayed on whatever
+ * stream mipq_pq_fit_batched is given. */
+typedef struct mipq_plan mipq_plan;
+enum mipq_plan_flags { MIPQ_PLAN_AUTOTUNE = 1, MIPQ_PLAN_GRAPH = 2 };
+
+/* n: host int64 [nprob], the rows of every problem. */
+size_t mipq_pq_fit_batched_workspace_size(const int64_t* n, int nprob, int d, int m, int ks, int iters,
+                                          int precision);
+/* probs: host array [nprob].  plan: optional (NULL: default grid, no graphs;
+ * the problem table is then copied into the workspace and the call waits
+ * for that copy).  rescored: optional int64 [1], pairs the final encode
+ * re-decided with the exact rule, summed over problems. */
+int mipq_pq_fit_batched(const mipq_problem* probs, int nprob, int d, int m, int ks, int iters, int precision,
+                        const mipq_plan* plan, int64_t* rescored, void* ws, size_t ws_bytes, void* stream);
+int mipq_plan_create(mipq_plan** plan, const mipq_problem* probs, int nprob, int d, int m, int ks, int iters,
+                     int precision, int flags, void* ws, size_t ws_bytes, void* stream);
+/* info (host int64 [count], count >= 4): [0] assignment grid, [1] resident
+ * blocks of the assignment kernel, [2] graphs recorded (0/1), [3] candidates
+ * timed, then (grid, nanoseconds per launch) for each candidate. */
+int mipq_plan_info(const mipq_plan* plan, int64_t* info, int count);
+int mipq_plan_destroy(mipq_plan* plan);
+
+/* -------------------------------------------------------------------------
  * Inverted file (paper Section 2.2: the ids of rows are stored per bucket and
  * a query returns its first to k-th nearest neighbours).  Buckets are coarse
  * k-means lists; each row stores the PQ codes of its residual x - c_list.
@@ -239,7 +301,8 @@ enum mipq_kernel {
   MIPQ_K_SORT = 9,          /* stable bucketing by label */
   MIPQ_K_COARSE_UPDATE = 10,/* coarse centroid update */
   MIPQ_K_ADC = 11,          /* ADC search */
-  MIPQ_KERNEL_COUNT = 12
+  MIPQ_K_ASSIGN_BF16_BATCHED = 12, /* persistent matrix-core assignment, many problems */
+  MIPQ_KERNEL_COUNT = 13
 };
 int mipq_profile_enable(int on);
 int mipq_profile_collect(int kernel, int64_t* launches, double* total_ms);

@@ -10,7 +10,9 @@ from __future__ import annotations
 
 import torch
 
-from ._lib import MipqError, check, lib  # noqa: F401
+import ctypes
+
+from ._lib import PLAN_AUTOTUNE, PLAN_GRAPH, MipqError, MipqProblem, check, lib  # noqa: F401
 
 FP32, BF16 = 0, 1
 _PREC = {"fp32": FP32, "bf16": BF16, FP32: FP32, BF16: BF16}
@@ -245,3 +247,95 @@ def adc_search(q: torch.Tensor, index: dict, nprobe: int, topk: int, wide: bool 
     check(L.mipq_adc_search(_ptr(q), nq, d, _ptr(cc), kc, _ptr(pqc), m, ks, _ptr(off), _ptr(ids), _ptr(codes),
                             nprobe, topk, _ptr(out_ids), _ptr(out_d), _ptr(w), _ptr(ws), ws.numel(), _stream(dev)))
     return (out_ids, out_d, w) if wide else (out_ids, out_d)
+
+
+class BatchedFit:
+    """Fit + encode of many independent problems sharing d, m and ks, every
+    phase one launch over all problems (``mipq_pq_fit_batched``).
+
+    ``xs``: list of float32 [n_i, d] device tensors; ``init_rows``: list of
+    int64 [m, ks] device tensors (rows of the matching x).  With ``plan`` the
+    grid is fixed once (``autotune``: timed on the problems) and, with
+    ``graph``, the launches are replayed from HIP graphs.  ``run()`` fills
+    ``results[i]`` = dict(codebook, codes, sse_rmse, objective).
+    """
+
+    def __init__(self, xs, init_rows, m: int, ks: int, iters: int, precision="bf16", plan: bool = True,
+                 autotune: bool = True, graph: bool = True, objective: bool = True, sse: bool = True):
+        L = lib()
+        if len(xs) != len(init_rows) or not xs:
+            raise ValueError("need one init_rows tensor per problem (and at least one problem)")
+        self.xs = [_dev(x, torch.float32, "xs[%d]" % i) for i, x in enumerate(xs)]
+        self.init_rows = [_dev(r, torch.int64, "init_rows[%d]" % i) for i, r in enumerate(init_rows)]
+        dev = self.xs[0].device
+        d = self.xs[0].shape[1]
+        if any(x.dim() != 2 or x.shape[1] != d for x in self.xs):
+            raise ValueError("every problem needs rows of the same width")
+        if any(r.shape != (m, ks) for r in self.init_rows):
+            raise ValueError("init_rows must be [m, ks] per problem")
+        self.device, self.d, self.m, self.ks, self.iters = dev, d, m, ks, iters
+        self.precision = _prec(precision)
+        ds = d // m if m else 0
+        self.results = []
+        table = (MipqProblem * len(self.xs))()
+        for i, (x, r) in enumerate(zip(self.xs, self.init_rows)):
+            res = {"codebook": torch.empty((m, ks, ds), dtype=torch.float32, device=dev),
+                   "codes": torch.empty((x.shape[0], m), dtype=torch.uint8, device=dev)}
+            if sse:
+                res["sse_rmse"] = torch.empty(2, dtype=torch.float64, device=dev)
+            if objective:
+                res["objective"] = torch.empty(max(iters, 1), dtype=torch.float64, device=dev)
+            self.results.append(res)
+            table[i] = MipqProblem(x.data_ptr(), x.shape[0], r.data_ptr(), res["codebook"].data_ptr(),
+                                   res["codes"].data_ptr(), _ptr(res.get("sse_rmse")), _ptr(res.get("objective")))
+        self._table = table
+        sizes = (ctypes.c_int64 * len(self.xs))(*[x.shape[0] for x in self.xs])
+        nbytes = L.mipq_pq_fit_batched_workspace_size(sizes, len(self.xs), d, m, ks, iters, self.precision)
+        if nbytes == 0:
+            check(L.mipq_pq_fit_batched(table, len(self.xs), d, m, ks, iters, self.precision, None, None, None, 0,
+                                        _stream(dev)))
+        self.ws = _ws(nbytes, dev)
+        self._plan = ctypes.c_void_p()
+        if plan:
+            flags = (PLAN_AUTOTUNE if autotune else 0) | (PLAN_GRAPH if graph else 0)
+            check(L.mipq_plan_create(ctypes.byref(self._plan), table, len(self.xs), d, m, ks, iters, self.precision,
+                                     flags, _ptr(self.ws), self.ws.numel(), _stream(dev)))
+
+    def run(self, rescored: bool = False):
+        """Enqueue the whole batched fit + encode on torch's current stream."""
+        resc = torch.zeros(1, dtype=torch.int64, device=self.device) if rescored else None
+        check(lib().mipq_pq_fit_batched(self._table, len(self.xs), self.d, self.m, self.ks, self.iters,
+                                        self.precision, self._plan if self._plan.value else None, _ptr(resc),
+                                        _ptr(self.ws), self.ws.numel(), _stream(self.device)))
+        return resc
+
+    def info(self) -> dict:
+        """Plan choices: assignment grid, resident blocks, graphs, timed candidates."""
+        if not self._plan.value:
+            return {}
+        buf = (ctypes.c_int64 * 32)()
+        check(lib().mipq_plan_info(self._plan, buf, 32))
+        k = int(buf[3])
+        return {"grid": int(buf[0]), "resident": int(buf[1]), "graph": bool(buf[2]),
+                "candidates": [(int(buf[4 + 2 * i]), int(buf[5 + 2 * i])) for i in range(min(k, 14))]}
+
+    def close(self):
+        if getattr(self, "_plan", None) is not None and self._plan.value:
+            lib().mipq_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pq_fit_batched(xs, init_rows, m: int, ks: int, iters: int, precision="bf16", plan: bool = False,
+                   autotune: bool = False, graph: bool = False):
+    """One-shot batched fit + encode; returns the list of per-problem result dicts."""
+    b = BatchedFit(xs, init_rows, m, ks, iters, precision, plan=plan, autotune=autotune, graph=graph)
+    b.run()
+    torch.cuda.current_stream(b.device).synchronize()
+    b.close()
+    return b.results

@@ -40,13 +40,28 @@ SIGNATURES = {
                            _P, _S, _P]),
     "mipq_adc_search_workspace_size": (_S, [_I, _I, _I, _I]),
     "mipq_adc_search": (_I, [_P, _I, _I, _P, _I, _P, _I, _I, _P, _P, _P, _I, _I, _P, _P, _P, _P, _S, _P]),
+    "mipq_pq_fit_batched_workspace_size": (_S, [_P, _I, _I, _I, _I, _I, _I]),
+    "mipq_pq_fit_batched": (_I, [_P, _I, _I, _I, _I, _I, _I, _P, _P, _P, _S, _P]),
+    "mipq_plan_create": (_I, [_P, _P, _I, _I, _I, _I, _I, _I, _I, _P, _S, _P]),
+    "mipq_plan_info": (_I, [_P, _P, _I]),
+    "mipq_plan_destroy": (_I, [_P]),
     "mipq_profile_enable": (_I, [_I]),
     "mipq_profile_collect": (_I, [_I, ctypes.POINTER(_L), ctypes.POINTER(ctypes.c_double)]),
 }
 
 # kernel ids of mipq_profile_collect (enum mipq_kernel)
 KERNELS = {"assign_fp32": 0, "assign_bf16": 1, "update": 2, "finalize": 3, "pack_bf16": 4, "decode": 5,
-           "backward": 6, "coarse_pack": 7, "coarse_assign": 8, "sort": 9, "coarse_update": 10, "adc": 11}
+           "backward": 6, "coarse_pack": 7, "coarse_assign": 8, "sort": 9, "coarse_update": 10, "adc": 11,
+           "assign_bf16_batched": 12}
+
+
+class MipqProblem(ctypes.Structure):
+    """struct mipq_problem of include/mipq.h"""
+    _fields_ = [("x", _P), ("n", _L), ("init_rows", _P), ("codebook", _P), ("codes", _P),
+                ("sse_rmse", _P), ("objective", _P)]
+
+
+PLAN_AUTOTUNE, PLAN_GRAPH = 1, 2
 
 _lib = None
 

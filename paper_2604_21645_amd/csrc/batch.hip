@@ -1,0 +1,402 @@
+// Batched fit + encode of many independent PQ problems (paper Section 3: the
+// rows are split into chunks that are quantised in parallel).
+//
+// All problems advance together: each phase is ONE launch over every
+// problem -- the persistent matrix-core assignment walks a flat list of
+// (problem, subspace group, 32-row tile) units, the accumulation and the
+// finalisation cover every (problem, chunk, subspace) item and every
+// (problem, subspace) pair.  A plan fixes the assignment grid (optionally by
+// timing candidates on the problems themselves) and can record the launch
+// sequence as three HIP graphs: set-up, one Lloyd round (replayed `iters`
+// times; the round index lives in device memory) and encode + error.
+#include <string.h>
+
+#include <vector>
+
+#include "mipq_internal.h"
+
+struct mipq_plan {
+  std::vector<mipq_problem> probs;
+  int d = 0, m = 0, ks = 0, iters = 0, precision = 0, flags = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  int grid = 0;       // blocks of the persistent assignment
+  int resident = 0;   // its resident blocks on this device
+  std::vector<int64_t> tried;   // (grid, nanoseconds) per timed candidate
+  hipGraphExec_t g_setup = nullptr, g_round = nullptr, g_final = nullptr;
+};
+
+namespace mipq {
+
+namespace {
+
+__global__ void k_copy_i64(const int64_t* __restrict__ src, int64_t* __restrict__ dst) {
+  if (threadIdx.x == 0) dst[0] = src[0];
+}
+
+struct BatchLayout {
+  BatchProb* probs = nullptr;   // device problem table
+  uint32_t* round = nullptr;    // [0] round counter, [1] bad-init flag
+  int64_t* resc = nullptr;      // pairs re-decided by the final encode
+  double* c64 = nullptr;
+  uint4* aop = nullptr;
+  size_t aop_stride = 0;        // operand slots per problem
+  float* cmax = nullptr;
+  float* mu = nullptr;
+  double* part_s = nullptr;
+  uint32_t* part_cnt = nullptr;
+  double* part_j = nullptr;
+  double* j_all = nullptr;
+  double* dpart = nullptr;
+  int64_t units = 0, items = 0, dblocks = 0;
+  size_t bytes = 0;
+};
+
+// Work-list offsets of every problem (table may be NULL) and the workspace
+// carving; the same code sizes and fills.
+BatchLayout carve_batch(void* ws, const int64_t* n, int nprob, int d, int m, int ks, int iters,
+                        std::vector<BatchProb>* table, const mipq_problem* probs) {
+  BatchLayout L;
+  const int ds = d / m;
+  const int groups = ceil_div(m, 4);
+  if (table) table->resize(nprob);
+  for (int p = 0; p < nprob; ++p) {
+    const int64_t np = n[p];
+    const int nch = update_chunks(np, m);
+    const int nblk = decode_blocks(np, m);
+    if (table) {
+      BatchProb& b = (*table)[p];
+      b.x = probs[p].x;
+      b.n = np;
+      b.init_rows = probs[p].init_rows;
+      b.c32 = probs[p].codebook;
+      b.codes = probs[p].codes;
+      b.sse_rmse = probs[p].sse_rmse;
+      b.objective = probs[p].objective;
+      b.unit0 = L.units;
+      b.item0 = L.items;
+      b.rpc = (np + nch - 1) / nch;
+      b.dblk0 = L.dblocks;
+      b.nch = nch;
+      b.nblk = nblk;
+    }
+    L.units += (int64_t)groups * ((np + 31) / 32);
+    L.items += (int64_t)nch * m;
+    L.dblocks += nblk;
+  }
+  Carver c(ws);
+  const size_t per = (size_t)ks * ds;
+  L.probs = c.take<BatchProb>(nprob);
+  L.round = c.take<uint32_t>(4);
+  L.resc = c.take<int64_t>(1);
+  L.c64 = c.take<double>((size_t)nprob * m * per);
+  L.aop_stride = bf16_operand_count(m, ks, ds);
+  L.aop = c.take<uint4>((size_t)nprob * L.aop_stride);
+  L.cmax = c.take<float>((size_t)nprob * m);
+  L.mu = c.take<float>((size_t)nprob * m * kMaxDsBf16);
+  L.part_s = c.take<double>((size_t)L.items * per);
+  L.part_cnt = c.take<uint32_t>((size_t)L.items * ks);
+  L.part_j = c.take<double>((size_t)L.items);
+  L.j_all = c.take<double>((size_t)(iters > 0 ? iters : 1) * nprob * m);
+  L.dpart = c.take<double>((size_t)L.dblocks);
+  L.bytes = c.bytes();
+  return L;
+}
+
+int check_batch_shape(int nprob, int d, int m, int ks, int iters, int precision) {
+  if (nprob < 1) return fail(MIPQ_EINVAL, "nprob must be >= 1 (got %d)", nprob);
+  if (d <= 0 || m <= 0 || d % m) return fail(MIPQ_EINVAL, "d=%d must be a positive multiple of m=%d", d, m);
+  if (ks < 1 || ks > kMaxKs) return fail(MIPQ_EINVAL, "ks must be in [1, %d] (got %d)", kMaxKs, ks);
+  if (iters < 0 || iters > (1 << 16)) return fail(MIPQ_EINVAL, "iters out of range (%d)", iters);
+  if (precision != MIPQ_BF16)
+    return fail(MIPQ_EUNSUPPORTED, "batched fit runs the MIPQ_BF16 path only (got precision %d)", precision);
+  if (d / m > kMaxDsBf16) return fail(MIPQ_EUNSUPPORTED, "batched fit supports d/m <= %d (got %d)", kMaxDsBf16, d / m);
+  return MIPQ_OK;
+}
+
+int check_problems(const mipq_problem* probs, int nprob, int m) {
+  if (!probs) return fail(MIPQ_EINVAL, "problem table is NULL");
+  int64_t units = 0, blocks = 0;
+  for (int p = 0; p < nprob; ++p) {
+    const mipq_problem& q = probs[p];
+    if (q.n < 1) return fail(MIPQ_EINVAL, "problem %d: n must be >= 1 (got %lld)", p, (long long)q.n);
+    if ((uint64_t)q.n * (uint64_t)m >= (1ull << 32)) return fail(MIPQ_EUNSUPPORTED, "problem %d: n*m >= 2^32", p);
+    if (!q.x || !q.init_rows || !q.codebook || !q.codes)
+      return fail(MIPQ_EINVAL, "problem %d: x, init_rows, codebook and codes are required", p);
+    units += (q.n + 31) / 32;
+    blocks += update_chunks(q.n, m) * (int64_t)m;
+  }
+  if (units * ceil_div(m, 4) >= (1ll << 40) || blocks >= (1ll << 31))
+    return fail(MIPQ_EUNSUPPORTED, "batched work list too long");
+  return MIPQ_OK;
+}
+
+std::vector<int64_t> sizes_of(const mipq_problem* probs, int nprob) {
+  std::vector<int64_t> n(nprob);
+  for (int p = 0; p < nprob; ++p) n[p] = probs[p].n;
+  return n;
+}
+
+struct BatchRun {
+  BatchLayout L;
+  int nprob, d, m, ks, iters;
+  bool full, vec;
+  int grid;
+};
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+BatchRun make_run(const BatchLayout& L, const mipq_problem* probs, int nprob, int d, int m, int ks, int iters,
+                  int grid) {
+  BatchRun r{L, nprob, d, m, ks, iters, true, true, grid};
+  const int ds = d / m;
+  const int nb = (ds + 7) / 8;
+  r.full = (ds == nb * 8) && (d % 4 == 0);
+  r.vec = ds % 4 == 0;
+  for (int p = 0; p < nprob; ++p) {
+    r.full = r.full && aligned16(probs[p].x);
+    r.vec = r.vec && aligned16(probs[p].x) && aligned16(probs[p].codebook);
+  }
+  return r;
+}
+
+// starting codebooks, round counter, operands of round 0
+int run_setup(const BatchRun& r, hipStream_t s) {
+  int rc;
+  const BatchLayout& L = r.L;
+  if ((rc = launch_zero_u32(L.round, 4, s))) return rc;
+  if ((rc = launch_init_batched(L.probs, r.nprob, r.d, r.m, r.ks, L.c64, L.round + 1, s))) return rc;
+  return launch_pack_bf16_batched(L.probs, r.nprob, r.m, r.ks, r.d / r.m, L.aop, L.aop_stride, L.cmax, L.mu, s);
+}
+
+// one Lloyd round of every problem: assign, accumulate, finalise (+ pack)
+int run_round(const BatchRun& r, hipStream_t s) {
+  int rc;
+  const BatchLayout& L = r.L;
+  if ((rc = launch_assign_bf16_batched(L.probs, r.nprob, L.units, r.d, r.m, r.ks, L.aop, L.aop_stride, L.cmax, L.mu,
+                                       r.full, r.grid, nullptr, s)))
+    return rc;
+  return launch_update_batched(L.probs, r.nprob, L.items, r.d, r.m, r.ks, L.c64, L.part_s, L.part_cnt, L.part_j,
+                               L.j_all, L.round, r.iters, L.aop, L.aop_stride, L.cmax, L.mu, s);
+}
+
+// encode with the final codebooks, reconstruction errors, objectives
+int run_final(const BatchRun& r, hipStream_t s) {
+  int rc;
+  const BatchLayout& L = r.L;
+  if ((rc = launch_zero_u32(reinterpret_cast<uint32_t*>(L.resc), 2, s))) return rc;
+  if ((rc = launch_assign_bf16_batched(L.probs, r.nprob, L.units, r.d, r.m, r.ks, L.aop, L.aop_stride, L.cmax, L.mu,
+                                       r.full, r.grid, L.resc, s)))
+    return rc;
+  if ((rc = launch_decode_sse_batched(L.probs, r.nprob, L.dblocks, r.d, r.m, r.ks, r.vec, L.dpart, s))) return rc;
+  return launch_objective_batched(L.probs, r.nprob, r.iters, r.m, L.j_all, s);
+}
+
+int upload_table(const BatchLayout& L, const std::vector<BatchProb>& table, hipStream_t s) {
+  MIPQ_HIP(hipMemcpyAsync(L.probs, table.data(), table.size() * sizeof(BatchProb), hipMemcpyHostToDevice, s));
+  MIPQ_HIP(hipStreamSynchronize(s));   // the host table is a local
+  return MIPQ_OK;
+}
+
+int capture(hipStream_t cs, hipGraphExec_t* out, int (*fn)(const BatchRun&, hipStream_t), const BatchRun& r) {
+  MIPQ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  const int rc = fn(r, cs);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(cs, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  const hipError_t ei = hipGraphInstantiateWithFlags(out, g, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) return hip_fail(ei, "hipGraphInstantiateWithFlags");
+  return MIPQ_OK;
+}
+
+void destroy_graphs(mipq_plan* p) {
+  for (hipGraphExec_t* g : {&p->g_setup, &p->g_round, &p->g_final})
+    if (*g) {
+      (void)hipGraphExecDestroy(*g);
+      *g = nullptr;
+    }
+}
+
+bool same_problems(const mipq_problem* a, const std::vector<mipq_problem>& b, int nprob) {
+  if ((int)b.size() != nprob) return false;
+  return memcmp(a, b.data(), sizeof(mipq_problem) * nprob) == 0;
+}
+
+}  // namespace
+}  // namespace mipq
+
+using namespace mipq;
+
+extern "C" {
+
+size_t mipq_pq_fit_batched_workspace_size(const int64_t* n, int nprob, int d, int m, int ks, int iters,
+                                          int precision) {
+  if (!n || check_batch_shape(nprob, d, m, ks, iters, precision) != MIPQ_OK) return 0;
+  for (int p = 0; p < nprob; ++p)
+    if (n[p] < 1) return 0;
+  return carve_batch(nullptr, n, nprob, d, m, ks, iters, nullptr, nullptr).bytes;
+}
+
+int mipq_plan_create(mipq_plan** out, const mipq_problem* probs, int nprob, int d, int m, int ks, int iters,
+                     int precision, int flags, void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if (!out) return fail(MIPQ_EINVAL, "plan output pointer is NULL");
+  *out = nullptr;
+  if ((rc = check_batch_shape(nprob, d, m, ks, iters, precision))) return rc;
+  if ((rc = check_problems(probs, nprob, m))) return rc;
+  if (flags & ~(MIPQ_PLAN_AUTOTUNE | MIPQ_PLAN_GRAPH)) return fail(MIPQ_EINVAL, "unknown plan flags 0x%x", flags);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const std::vector<int64_t> n = sizes_of(probs, nprob);
+  std::vector<BatchProb> table;
+  const BatchLayout L = carve_batch(ws, n.data(), nprob, d, m, ks, iters, &table, probs);
+  if (!ws) return fail(MIPQ_EINVAL, "workspace pointer is NULL (%zu bytes needed)", L.bytes);
+  if (ws_bytes < L.bytes) return fail(MIPQ_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, L.bytes);
+  if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(MIPQ_EINVAL, "workspace must be 256-byte aligned");
+
+  mipq_plan* plan = new mipq_plan;
+  plan->probs.assign(probs, probs + nprob);
+  plan->d = d;
+  plan->m = m;
+  plan->ks = ks;
+  plan->iters = iters;
+  plan->precision = precision;
+  plan->flags = flags;
+  plan->ws = ws;
+  plan->ws_bytes = ws_bytes;
+  BatchRun r = make_run(L, probs, nprob, d, m, ks, iters, 8);
+  auto bail = [&](int code) {
+    destroy_graphs(plan);
+    delete plan;
+    return code;
+  };
+  if ((rc = assign_bf16_batched_resident(d / m, ks, r.full, &plan->resident))) return bail(rc);
+  const int res8 = ((plan->resident > 8 ? plan->resident : 8) + 7) / 8 * 8;
+  plan->grid = 2 * res8;
+  if ((rc = upload_table(L, table, s))) return bail(rc);
+
+  if (flags & MIPQ_PLAN_AUTOTUNE) {
+    // time the assignment of round 0 (initial codebooks) at a few grid sizes;
+    // the codes it writes are overwritten by the fit
+    if ((rc = run_setup(r, s))) return bail(rc);
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      if (a) (void)hipEventDestroy(a);
+      return bail(fail(MIPQ_EHIP, "hipEventCreate failed"));
+    }
+    float best = 0.0f;
+    for (int mult : {1, 2, 4, 8}) {
+      r.grid = res8 * mult;
+      float ms = 0.0f;
+      hipError_t e = hipSuccess;
+      rc = launch_assign_bf16_batched(L.probs, nprob, L.units, d, m, ks, L.aop, L.aop_stride, L.cmax, L.mu, r.full,
+                                      r.grid, nullptr, s);   // warm-up
+      if (!rc && (e = hipEventRecord(a, s)) == hipSuccess) {
+        for (int rep = 0; rep < 2 && !rc; ++rep)
+          rc = launch_assign_bf16_batched(L.probs, nprob, L.units, d, m, ks, L.aop, L.aop_stride, L.cmax, L.mu,
+                                          r.full, r.grid, nullptr, s);
+        if (!rc && (e = hipEventRecord(b, s)) == hipSuccess && (e = hipEventSynchronize(b)) == hipSuccess)
+          e = hipEventElapsedTime(&ms, a, b);
+      }
+      if (rc || e != hipSuccess) {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        return bail(rc ? rc : hip_fail(e, "autotune timing"));
+      }
+      plan->tried.push_back(r.grid);
+      plan->tried.push_back((int64_t)(ms * 0.5e6));
+      if (best == 0.0f || ms < best) {
+        best = ms;
+        plan->grid = r.grid;
+      }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+  r.grid = plan->grid;
+
+  if (flags & MIPQ_PLAN_GRAPH) {
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+      return bail(fail(MIPQ_EHIP, "hipStreamCreateWithFlags failed"));
+    rc = capture(cs, &plan->g_setup, run_setup, r);
+    if (!rc) rc = capture(cs, &plan->g_round, run_round, r);
+    if (!rc) rc = capture(cs, &plan->g_final, run_final, r);
+    (void)hipStreamDestroy(cs);
+    if (rc) return bail(rc);
+  }
+  const hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return bail(hip_fail(e, "hipStreamSynchronize"));
+  *out = plan;
+  return MIPQ_OK;
+}
+
+int mipq_plan_info(const mipq_plan* plan, int64_t* info, int count) {
+  if (!plan || !info || count < 4) return fail(MIPQ_EINVAL, "plan and info[>= 4] are required");
+  info[0] = plan->grid;
+  info[1] = plan->resident;
+  info[2] = plan->g_round != nullptr;
+  info[3] = (int64_t)plan->tried.size() / 2;
+  for (int i = 4; i < count; ++i) info[i] = (size_t)(i - 4) < plan->tried.size() ? plan->tried[i - 4] : 0;
+  return MIPQ_OK;
+}
+
+int mipq_plan_destroy(mipq_plan* plan) {
+  if (!plan) return MIPQ_OK;
+  destroy_graphs(plan);
+  delete plan;
+  return MIPQ_OK;
+}
+
+int mipq_pq_fit_batched(const mipq_problem* probs, int nprob, int d, int m, int ks, int iters, int precision,
+                        const mipq_plan* plan, int64_t* rescored, void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_batch_shape(nprob, d, m, ks, iters, precision))) return rc;
+  if ((rc = check_problems(probs, nprob, m))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const std::vector<int64_t> n = sizes_of(probs, nprob);
+  if (plan) {
+    if (plan->d != d || plan->m != m || plan->ks != ks || plan->iters != iters || plan->precision != precision ||
+        !same_problems(probs, plan->probs, nprob))
+      return fail(MIPQ_EINVAL, "the plan was made for other problems or shapes");
+    if (plan->ws != ws || plan->ws_bytes > ws_bytes) return fail(MIPQ_EINVAL, "the plan was made for another workspace");
+  }
+  std::vector<BatchProb> table;
+  const BatchLayout L = carve_batch(ws, n.data(), nprob, d, m, ks, iters, plan ? nullptr : &table, probs);
+  if (!ws) return fail(MIPQ_EINVAL, "workspace pointer is NULL (%zu bytes needed)", L.bytes);
+  if (ws_bytes < L.bytes) return fail(MIPQ_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, L.bytes);
+  if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(MIPQ_EINVAL, "workspace must be 256-byte aligned");
+  if (plan && plan->g_round) {
+    MIPQ_HIP(hipGraphLaunch(plan->g_setup, s));
+    for (int it = 0; it < iters; ++it) MIPQ_HIP(hipGraphLaunch(plan->g_round, s));
+    MIPQ_HIP(hipGraphLaunch(plan->g_final, s));
+  } else {
+    int grid = 0;
+    if (plan) {
+      grid = plan->grid;
+    } else {
+      if ((rc = upload_table(L, table, s))) return rc;
+      const int ds = d / m;
+      int resident = 0;
+      if ((rc = assign_bf16_batched_resident(ds, ks, make_run(L, probs, nprob, d, m, ks, iters, 8).full, &resident)))
+        return rc;
+      grid = 2 * (((resident > 8 ? resident : 8) + 7) / 8 * 8);
+    }
+    const BatchRun r = make_run(L, probs, nprob, d, m, ks, iters, grid);
+    if ((rc = run_setup(r, s))) return rc;
+    for (int it = 0; it < iters; ++it)
+      if ((rc = run_round(r, s))) return rc;
+    if ((rc = run_final(r, s))) return rc;
+  }
+  if (rescored) {
+    k_copy_i64<<<1, 64, 0, s>>>(L.resc, rescored);
+    MIPQ_LAUNCHED("k_copy_i64");
+  }
+  return MIPQ_OK;
+}
+
+}  // extern "C"

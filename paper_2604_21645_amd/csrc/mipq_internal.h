@@ -61,6 +61,27 @@ constexpr int kMaxDsBf16 = 16;     // two 8-dimension blocks per subspace
 constexpr int kMaxDsFp32 = 64;
 constexpr int kMaxDsFit = 32;      // float64 centroid sums held in LDS
 
+// One problem of a batched fit (device copy, built by the host from the
+// caller's problem table).  Work-list offsets: unit0 = first (32-row tile x
+// subspace group) assignment unit, item0 = first (chunk x subspace)
+// accumulation item, dblk0 = first decode block of this problem.
+struct BatchProb {
+  const float* x;
+  int64_t n;
+  const int64_t* init_rows;
+  float* c32;
+  uint8_t* codes;
+  double* sse_rmse;
+  double* objective;
+  int64_t unit0;
+  int64_t item0;
+  int64_t rpc;      // rows per accumulation chunk
+  int64_t dblk0;
+  int nch;          // accumulation chunks
+  int nblk;         // decode blocks
+};
+constexpr int kBatchPend = 512;   // pending exact re-decisions per wave (LDS)
+
 // number of 32x32x16 MFMAs per 32-centroid tile for NB 8-dim blocks
 __host__ __device__ constexpr int bf16_nmfma(int nb) { return nb + (nb + 1) / 2 + ((nb % 2 == 0) ? 1 : 0); }
 inline int ceil_div(int64_t a, int64_t b) { return int((a + b - 1) / b); }
@@ -131,6 +152,25 @@ int launch_adc(const float* q, int nq, int d, const float* cc, int kc, const voi
 // operands of the centred codebook; mu: m * kMaxDsBf16 floats (subspace centres)
 int launch_pack_bf16(const float* c32, int m, int ks, int ds, void* aop, float* cmax, float* mu,
                      hipStream_t s);
+// batched problems (device table probs[nprob], see BatchProb)
+int launch_init_batched(const BatchProb* probs, int nprob, int d, int m, int ks, double* c64_all, uint32_t* bad,
+                        hipStream_t s);
+int launch_pack_bf16_batched(const BatchProb* probs, int nprob, int m, int ks, int ds, void* aop,
+                             size_t aop_stride, float* cmax, float* mu, hipStream_t s);
+int assign_bf16_batched_resident(int ds, int ks, bool full, int* resident);
+int launch_assign_bf16_batched(const BatchProb* probs, int nprob, int64_t units, int d, int m, int ks,
+                               const void* aop, size_t aop_stride, const float* cmax, const float* mu, bool full,
+                               int grid, int64_t* rescored, hipStream_t s);
+// one Lloyd update of every problem, then advances *round
+int launch_update_batched(const BatchProb* probs, int nprob, int64_t items, int d, int m, int ks, double* c64,
+                          double* part_s, uint32_t* part_cnt, double* part_j, double* j_all,
+                          const uint32_t* round, int iters, void* aop, size_t aop_stride, float* cmax, float* mu,
+                          hipStream_t s);
+int launch_decode_sse_batched(const BatchProb* probs, int nprob, int64_t blocks, int d, int m, int ks, bool vec,
+                              double* partials, hipStream_t s);
+int launch_objective_batched(const BatchProb* probs, int nprob, int iters, int m, const double* j_all,
+                             hipStream_t s);
+
 // rescored: optional int64 counter, incremented by the pairs re-decided exactly
 int launch_assign_bf16(const float* x, int64_t n, int d, int m, int ks, const void* aop,
                        const float* cmax, const float* mu, const float* c32, uint8_t* codes,

@@ -145,20 +145,17 @@ __global__ void k_copy_f64(const double* __restrict__ src, double* __restrict__ 
 // Decode (concatenate coded centroids) and the float64 squared error.  VEC:
 // one thread per 4 consecutive elements of a row (ds % 4 == 0, so the four lie
 // in one subspace): 16-byte loads and stores.  Otherwise one thread per
-// element.  Per-block partial sums, reduced in a fixed order.
+// element.  Block blk of nblk takes items blk*256 + tid, stepping by
+// nblk*256; per-block partial sums are reduced in a fixed order.
 template <int VEC>
-__global__ __launch_bounds__(kThreads) void k_decode_sse(const uint8_t* __restrict__ codes,
-                                                         int64_t n, int d, int m, int ks, int ds,
-                                                         const float* __restrict__ c32,
-                                                         const float* __restrict__ x,
-                                                         float* __restrict__ x_hat,
-                                                         double* __restrict__ partials) {
-  __shared__ double red[kThreads / 64];
+__device__ __forceinline__ double decode_sse_part(const uint8_t* __restrict__ codes, int64_t n, int d, int m,
+                                                  int ks, int ds, const float* __restrict__ c32,
+                                                  const float* __restrict__ x, float* __restrict__ x_hat,
+                                                  int64_t blk, int64_t nblk) {
   double acc = 0.0;
   const int per_row = d / VEC;
   const int64_t items = n * per_row;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < items;
-       p += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t p = blk * blockDim.x + threadIdx.x; p < items; p += nblk * blockDim.x) {
     const int64_t row = p / per_row;
     const int col = int(p - row * per_row) * VEC;
     const int sub = col / ds;
@@ -196,15 +193,53 @@ __global__ __launch_bounds__(kThreads) void k_decode_sse(const uint8_t* __restri
       }
     }
   }
+  return acc;
+}
+
+template <int VEC>
+__global__ __launch_bounds__(kThreads) void k_decode_sse(const uint8_t* __restrict__ codes,
+                                                         int64_t n, int d, int m, int ks, int ds,
+                                                         const float* __restrict__ c32,
+                                                         const float* __restrict__ x,
+                                                         float* __restrict__ x_hat,
+                                                         double* __restrict__ partials) {
+  __shared__ double red[kThreads / 64];
+  const double acc = decode_sse_part<VEC>(codes, n, d, m, ks, ds, c32, x, x_hat, blockIdx.x, gridDim.x);
   const double s = block_sum_f64(acc, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// the last problem p with key(p) <= i (problems in ascending key order)
+template <class Key>
+__device__ __forceinline__ int find_problem(const BatchProb* __restrict__ probs, int nprob, int64_t i, Key key) {
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (key(probs[mid]) <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Many problems: block i is decode block i - dblk0 of problem p, with the
+// single-problem partition of that problem's rows (same partial sums).
+template <int VEC>
+__global__ __launch_bounds__(kThreads) void k_decode_sse_batched(const BatchProb* __restrict__ probs, int nprob,
+                                                                 int d, int m, int ks, int ds,
+                                                                 double* __restrict__ partials) {
+  __shared__ double red[kThreads / 64];
+  const int64_t i = blockIdx.x;
+  const int p = find_problem(probs, nprob, i, [](const BatchProb& b) { return b.dblk0; });
+  const double acc = decode_sse_part<VEC>(probs[p].codes, probs[p].n, d, m, ks, ds, probs[p].c32, probs[p].x,
+                                          nullptr, i - probs[p].dblk0, probs[p].nblk);
+  const double s = block_sum_f64(acc, red);
+  if (threadIdx.x == 0) partials[i] = s;
+}
+
 // Sum of the block partials: thread i adds partials i, i+256, ... in order,
-// then a fixed pairwise tree over the threads.
-__global__ __launch_bounds__(kThreads) void k_sse_final(const double* __restrict__ partials, int nblk,
-                                                        int64_t n, int d, double* out) {
-  __shared__ double red[kThreads];
+// then a fixed pairwise tree over the threads; out = {SSE, RMSE}.
+__device__ __forceinline__ void sse_final_body(const double* __restrict__ partials, int nblk, int64_t n, int d,
+                                               double* out, double* red) {
   double s = 0.0;
   for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += partials[i];
   red[threadIdx.x] = s;
@@ -213,12 +248,67 @@ __global__ __launch_bounds__(kThreads) void k_sse_final(const double* __restrict
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && out) {
     const double tot = red[0];
     out[0] = tot;
     const double cnt = (double)n * (double)d;
     out[1] = cnt > 0 ? sqrt(tot / cnt) : 0.0;
   }
+}
+
+__global__ __launch_bounds__(kThreads) void k_sse_final(const double* __restrict__ partials, int nblk,
+                                                        int64_t n, int d, double* out) {
+  __shared__ double red[kThreads];
+  sse_final_body(partials, nblk, n, d, out, red);
+}
+
+// block p: problem p's SSE and RMSE
+__global__ __launch_bounds__(kThreads) void k_sse_final_batched(const BatchProb* __restrict__ probs, int d,
+                                                                const double* __restrict__ partials) {
+  __shared__ double red[kThreads];
+  const BatchProb& P = probs[blockIdx.x];
+  sse_final_body(partials + P.dblk0, P.nblk, P.n, d, P.sse_rmse, red);
+}
+
+// Many problems: the starting codebook of problem p from its own rows
+// (c64 of problem p at c64_all + p * m*ks*ds).
+__global__ void k_init_batched(const BatchProb* __restrict__ probs, int nprob, int d, int m, int ks,
+                               double* __restrict__ c64_all, uint32_t* bad) {
+  const int ds = d / m;
+  const int64_t per = (int64_t)m * ks * ds;
+  const int64_t total = per * nprob;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int p = (int)(i / per);
+    const int64_t e = i - p * per;
+    const int64_t jk = e / ds;   // j * ks + k
+    const int t = int(e - jk * ds);
+    const int j = int(jk / ks);
+    const int64_t r = probs[p].init_rows[jk];
+    float v;
+    if (r < 0 || r >= probs[p].n) {
+      v = NAN;
+      if (t == 0) atomicOr(bad, 1u);
+    } else {
+      v = probs[p].x[r * d + (int64_t)j * ds + t];
+    }
+    c64_all[i] = (double)v;
+    probs[p].c32[e] = v;
+  }
+}
+
+// Many problems: objective[r] of problem p = sum over subspaces j ascending of
+// j_all[(r * nprob + p) * m + j].
+__global__ void k_objective_batched(const BatchProb* __restrict__ probs, int nprob, int iters, int m,
+                                    const double* __restrict__ j_all) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nprob * iters) return;
+  const int p = t / iters, r = t - (t / iters) * iters;
+  double* out = probs[p].objective;
+  if (!out) return;
+  double s = 0.0;
+  for (int j = 0; j < m; ++j) s += j_all[((size_t)r * nprob + p) * m + j];
+  out[r] = s;
 }
 
 int grid_for(int64_t work, int per_block, int cap) {
@@ -316,6 +406,38 @@ int launch_decode_sse(const uint8_t* codes, int64_t n, int d, int m, int ks, con
 int launch_sse_final(const double* partials, int nblk, int64_t n, int d, double* out, hipStream_t s) {
   k_sse_final<<<1, kThreads, 0, s>>>(partials, nblk, n, d, out);
   MIPQ_LAUNCHED("k_sse_final");
+  return MIPQ_OK;
+}
+
+int launch_init_batched(const BatchProb* probs, int nprob, int d, int m, int ks, double* c64_all, uint32_t* bad,
+                        hipStream_t s) {
+  const int64_t total = (int64_t)nprob * d * ks;
+  k_init_batched<<<grid_for(total, kThreads, 8192), kThreads, 0, s>>>(probs, nprob, d, m, ks, c64_all, bad);
+  MIPQ_LAUNCHED("k_init_batched");
+  return MIPQ_OK;
+}
+
+int launch_decode_sse_batched(const BatchProb* probs, int nprob, int64_t blocks, int d, int m, int ks, bool vec,
+                              double* partials, hipStream_t s) {
+  const int ds = d / m;
+  {
+    ProfScope ps(MIPQ_K_DECODE, s);
+    if (vec)
+      k_decode_sse_batched<4><<<(unsigned)blocks, kThreads, 0, s>>>(probs, nprob, d, m, ks, ds, partials);
+    else
+      k_decode_sse_batched<1><<<(unsigned)blocks, kThreads, 0, s>>>(probs, nprob, d, m, ks, ds, partials);
+    MIPQ_LAUNCHED("k_decode_sse_batched");
+  }
+  k_sse_final_batched<<<nprob, kThreads, 0, s>>>(probs, d, partials);
+  MIPQ_LAUNCHED("k_sse_final_batched");
+  return MIPQ_OK;
+}
+
+int launch_objective_batched(const BatchProb* probs, int nprob, int iters, int m, const double* j_all,
+                             hipStream_t s) {
+  if (iters <= 0) return MIPQ_OK;
+  k_objective_batched<<<ceil_div((int64_t)nprob * iters, 64), 64, 0, s>>>(probs, nprob, iters, m, j_all);
+  MIPQ_LAUNCHED("k_objective_batched");
   return MIPQ_OK;
 }
 

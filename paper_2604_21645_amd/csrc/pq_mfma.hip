@@ -79,6 +79,13 @@ __device__ __forceinline__ int2 halves(int v) {
   return make_int2((int)r[0], (int)r[1]);
 }
 
+// a wave-uniform 64-bit value moved to scalar registers
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 struct XcdMap {
   int rowblk, group;
 };
@@ -91,9 +98,6 @@ __device__ __forceinline__ XcdMap xcd_map(int lin, int groups) {
   return r;
 }
 
-// One wave = one subspace over the rows of one row block, 32 rows at a time.
-// Ambiguous (row, subspace) pairs are re-decided by the wave with the exact
-// rule; their number is added to *rescored when that is non-NULL.
 // Exact float32 rule for one (row, subspace) by the whole wave: lane i scans
 // centroids i, i+64, ... in ascending order, then a lexicographic (distance,
 // index) minimum over the lanes.  Dimensions t >= ds contribute exact zeros, so
@@ -136,6 +140,237 @@ __device__ __forceinline__ int exact_code_wave(const float* __restrict__ xr, con
   return bk < ks ? bk : 0;
 }
 
+// Centroid-side state of one subspace, held in registers while a wave walks a
+// range of rows: the packed operands, the centre mu (scalar registers) and the
+// bound on the centred centroid norms.
+template <int NB, int NT>
+struct SubOps {
+  static constexpr int NMF = bf16_nmfma(NB);
+  static constexpr int DW = NB * 8;
+  bf16x8 A[NT][NMF];
+  float muv[DW];
+  float cm;
+};
+
+template <int NB, int NT>
+__device__ __forceinline__ void load_sub_ops(SubOps<NB, NT>& o, const bf16x8* __restrict__ aop,
+                                             const float* __restrict__ cmax, const float* __restrict__ mu,
+                                             int sub, int lane) {
+  constexpr int NMF = SubOps<NB, NT>::NMF;
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int f = 0; f < NMF; ++f) o.A[t][f] = aop[((size_t)(sub * NT + t) * NMF + f) * 64 + lane];
+  o.cm = cmax[sub];
+#pragma unroll
+  for (int e = 0; e < NB * 8; ++e)
+    o.muv[e] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(mu[sub * kMaxDsBf16 + e])));
+}
+
+// error-bound constants of the separation test (see launch_assign_bf16)
+struct Band {
+  float e_cross, e_norm, g_exact;
+};
+
+// Raw slice of row r0 + lane%32 (clamped to r0 past the end) of subspace sub.
+template <int DW, bool FULL>
+__device__ __forceinline__ void load_rows(float (&xv)[DW], const float* __restrict__ x, int64_t r0, int64_t rend,
+                                          int d, int sub, int ds, int lane) {
+  const int64_t row = r0 + (lane & 31);
+  const float* xr = x + (row < rend ? row : r0) * d + (int64_t)sub * ds;
+  if (FULL) {   // ds == DW and 16-byte aligned rows: vector loads
+#pragma unroll
+    for (int e = 0; e < DW; e += 4) {
+      const float4 v = *reinterpret_cast<const float4*>(xr + e);
+      xv[e] = v.x;
+      xv[e + 1] = v.y;
+      xv[e + 2] = v.z;
+      xv[e + 3] = v.w;
+    }
+  } else {   // clamped loads, then zero the padding dimensions
+#pragma unroll
+    for (int e = 0; e < DW; ++e) {
+      const float v = xr[e < ds ? e : ds - 1];
+      xv[e] = (e < ds) ? v : 0.0f;
+    }
+  }
+}
+
+// Matrix-core decision for the row held by lanes l and l^32 (raw slice xraw):
+// returns the winning candidate and sets amb when the two best are not
+// separated by the error bound (then the exact rule must decide).
+template <int NB, int NT>
+__device__ __forceinline__ int decide_tile(const float (&xraw)[NB * 8], const SubOps<NB, NT>& o, int half, int ks,
+                                           const Band& bd, bool& amb) {
+  constexpr int NMF = SubOps<NB, NT>::NMF;
+  constexpr int DW = NB * 8;
+  float xv[DW];   // centred row slice
+#pragma unroll
+  for (int e = 0; e < DW; ++e) xv[e] = xraw[e] - o.muv[e];
+
+  // row operands
+  float xn = 0.0f;
+#pragma unroll
+  for (int e = 0; e < DW; ++e) xn = xn + xv[e] * xv[e];
+  bf16x8 XH[NB], XL[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    XH[b] = to_bf16x8(xv + b * 8);
+    float rem[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) rem[e] = xv[b * 8 + e] - (float)XH[b][e];
+    XL[b] = to_bf16x8(rem);
+  }
+  const bf16x8 zero8 = {};
+  bf16x8 normB = {};
+  {
+    const __bf16 h = (__bf16)xn;
+    const float r1 = xn - (float)h;
+    const __bf16 md = (__bf16)r1;
+    normB[0] = normB[1] = normB[2] = (__bf16)1.0f;
+    normB[3] = h;
+    normB[4] = md;
+    normB[5] = (__bf16)(r1 - (float)md);
+  }
+  bf16x8 B[NMF];
+#pragma unroll
+  for (int f = 0; f < NMF; ++f) {
+    if (f < NB) {
+      B[f] = XH[f];
+    } else if (f < NB + (NB + 1) / 2) {
+      const int b0 = 2 * (f - NB);
+      if (b0 + 1 < NB) B[f] = half ? XL[b0 + 1] : XL[b0];
+      else B[f] = half ? normB : XL[b0];
+    } else {
+      B[f] = half ? zero8 : normB;
+    }
+  }
+  auto tile = [&](int t) {
+    f32x16 acc = {};
+#pragma unroll
+    for (int f = 0; f < NMF; ++f) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.A[t][f], B[f], acc, 0, 0, 0);
+    return acc;
+  };
+
+  // distance estimates, reduced by tile (amin) and by accumulator register (bmin)
+  float amin[NT];
+  float bmin[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) bmin[r] = INFINITY;
+#pragma unroll
+  for (int t = 0; t < NT; t += 2) {
+    const f32x16 c0 = tile(t);
+    amin[t] = min16(c0);
+    if (t + 1 < NT) {
+      const f32x16 c1 = tile(t + 1 < NT ? t + 1 : 0);
+      amin[t + 1] = min16(c1);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) bmin[r] = min3f(bmin[r], c0[r], c1[r]);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) bmin[r] = fminf(bmin[r], c0[r]);
+    }
+  }
+
+  // smallest two keys of each grouping; the low bits carry the tile
+  // (3 bits) or the register (4 bits)
+  int a1 = INT_MAX, a2 = INT_MAX, b1 = INT_MAX, b2 = INT_MAX;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int k = key_of(amin[t], ~7, t);
+    a2 = min(a2, max(a1, k));
+    a1 = min(a1, k);
+  }
+#pragma unroll
+  for (int r = 0; r < 16; r += 2) {
+    const int ka = key_of(bmin[r], ~15, r);
+    const int kb = key_of(bmin[r + 1], ~15, r + 1);
+    b2 = min(b2, med3i(ka, kb, b1));   // runner-up of {b1, b2, ka, kb}, b1 <= b2
+    b1 = min(b1, min(ka, kb));
+  }
+  const int rl = b1 & 15;
+  const int s2 = min(a2, b2);
+
+  // merge the two lanes holding the 256 candidates of a row
+  const int2 A1 = halves(a1);
+  const int2 S2 = halves(s2);
+  const int2 RL = halves(rl);
+  const bool hiw = A1.y < A1.x;
+  const int w1 = min(A1.x, A1.y);
+  const int sec = min(max(A1.x, A1.y), min(S2.x, S2.y));
+  const int tw = (hiw ? A1.y : A1.x) & 7;
+  const int rw = hiw ? RL.y : RL.x;
+  const int code = tw * 32 + (rw >> 2) * 8 + (hiw ? 4 : 0) + (rw & 3);
+
+  const float f1 = __int_as_float(w1);
+  const float f2 = __int_as_float(sec);
+  const float xnorm = sqrtf(xn) * 1.0001f;
+  const float beta = bd.e_cross * xnorm * o.cm + bd.e_norm * (o.cm * o.cm + xn);
+  const float q = 3.815e-6f + bd.g_exact;                       // 2^-18 + gamma
+  const float thr = 2.0f * beta + q * (fabsf(f1) + fabsf(f2)) + 2.0f * bd.g_exact * (beta + bd.g_exact * xn);
+  const float gap = f2 - f1;
+  amb = !(gap > thr) || code >= ks;
+  return code;
+}
+
+// The exact rule for the np pending rows (absolute row indices) of subspace
+// sub, one row at a time by the whole wave; overwrites their codes.
+template <int DW>
+__device__ __forceinline__ void redecide(const uint32_t* pend, int np, const float* __restrict__ x, int d, int m,
+                                         int ks, int ds, int sub, const float* __restrict__ cbsub,
+                                         uint8_t* __restrict__ codes, int lane) {
+  for (int i = 0; i < np; ++i) {
+    const int64_t prow = pend[i];
+    const int ec = exact_code_wave<DW>(x + prow * d + (int64_t)sub * ds, cbsub, ds, ks, lane);
+    if (lane == 0) codes[prow * m + sub] = (uint8_t)ec;
+  }
+}
+
+// One wave assigns rows [rb, re) of subspace sub, 32 rows at a time (lane l
+// and l^32 share row l%32), the next tile's rows in flight.  Ambiguous rows
+// are queued in the wave's LDS list and re-decided with the exact rule after
+// the loop (and, with MIDFLUSH, whenever more than flush_at are queued).
+// Returns the number of re-decided rows.
+template <int NB, int NT, bool FULL, bool MIDFLUSH>
+__device__ __forceinline__ uint32_t assign_rows(const float* __restrict__ x, int d, int ds, int m, int ks, int sub,
+                                                int64_t rb, int64_t re, const SubOps<NB, NT>& o,
+                                                const float* __restrict__ cbsub, uint8_t* __restrict__ codes,
+                                                uint32_t* pend, int flush_at, const Band& bd, int lane) {
+  constexpr int DW = NB * 8;
+  const int half = lane >> 5;
+  uint32_t nres = 0;
+  int np = 0;
+  float xnext[DW];
+  load_rows<DW, FULL>(xnext, x, rb, re, d, sub, ds, lane);
+  for (int64_t r0 = rb; r0 < re; r0 += 32) {
+    if (MIDFLUSH && np > flush_at) {
+      redecide<DW>(pend, np, x, d, m, ks, ds, sub, cbsub, codes, lane);
+      nres += (uint32_t)np;
+      np = 0;
+    }
+    const int64_t row = r0 + (lane & 31);
+    const bool valid = row < re;
+    float xv[DW];
+#pragma unroll
+    for (int e = 0; e < DW; ++e) xv[e] = xnext[e];
+    if (r0 + 32 < re) load_rows<DW, FULL>(xnext, x, r0 + 32, re, d, sub, ds, lane);   // next tile in flight
+    bool amb;
+    const int code = decide_tile<NB, NT>(xv, o, half, ks, bd, amb);
+    // rows whose two best candidates are not separated are re-decided by the
+    // whole wave with the exact rule (rare); their codes are overwritten then
+    if (half == 0 && valid) codes[row * m + sub] = (uint8_t)code;
+    const bool push = (half == 0) && valid && amb;
+    const uint64_t mask = __ballot(push);
+    if (mask) {
+      if (push) pend[np + __popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)row;
+      np += __popcll(mask);
+    }
+  }
+  redecide<DW>(pend, np, x, d, m, ks, ds, sub, cbsub, codes, lane);
+  return nres + (uint32_t)np;
+}
+
+// One problem: block = (row block, group of 4 subspaces), one subspace per wave.
 template <int NB, int NT, bool FULL>
 __global__ __launch_bounds__(kThreads) void k_assign_bf16(
     const float* __restrict__ x, int64_t n, int d, int m, int ks, int ds,
@@ -143,187 +378,81 @@ __global__ __launch_bounds__(kThreads) void k_assign_bf16(
     const float* __restrict__ c32, uint8_t* __restrict__ codes,
     unsigned long long* __restrict__ rescored, int groups, int rpb, float e_cross, float e_norm,
     float g_exact) {
-  constexpr int NMF = bf16_nmfma(NB);
-  constexpr int DW = NB * 8;
   const XcdMap bm = xcd_map(blockIdx.x, groups);
   const int lane = threadIdx.x & 63;
-  const int half = lane >> 5;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int sub = bm.group * 4 + w;
   const int64_t rbeg = (int64_t)bm.rowblk * rpb;
   if (sub >= m || rbeg >= n) return;
   const int64_t rend = min(n, rbeg + rpb);
-  const float* cbsub = c32 + (int64_t)sub * ks * ds;
-
-  // centroid operands of this subspace stay in registers for the whole block
-  bf16x8 A[NT][NMF];
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int f = 0; f < NMF; ++f) A[t][f] = aop[((size_t)(sub * NT + t) * NMF + f) * 64 + lane];
-  const float cm = cmax[sub];
-  float muv[DW];   // subspace centre, held in scalar registers (wave-uniform)
-#pragma unroll
-  for (int e = 0; e < DW; ++e)
-    muv[e] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(mu[sub * kMaxDsBf16 + e])));
-  const bf16x8 zero8 = {};
-
-  auto load_rows = [&](float* xv, int64_t r0) {
-    const int64_t row = r0 + (lane & 31);
-    const float* xr = x + (row < rend ? row : r0) * d + (int64_t)sub * ds;
-    if (FULL) {   // ds == DW and 16-byte aligned rows: vector loads
-#pragma unroll
-      for (int e = 0; e < DW; e += 4) {
-        const float4 v = *reinterpret_cast<const float4*>(xr + e);
-        xv[e] = v.x;
-        xv[e + 1] = v.y;
-        xv[e + 2] = v.z;
-        xv[e + 3] = v.w;
-      }
-    } else {   // clamped loads, then zero the padding dimensions
-#pragma unroll
-      for (int e = 0; e < DW; ++e) {
-        const float v = xr[e < ds ? e : ds - 1];
-        xv[e] = (e < ds) ? v : 0.0f;
-      }
-    }
-  };
-
-  uint32_t nres = 0;   // pairs this wave re-decided with the exact rule
-  // rows of this wave awaiting the exact rule, decided after the main loop so
-  // that it stays lean (LDS: rpb entries per wave, so the list cannot overflow)
+  SubOps<NB, NT> o;
+  load_sub_ops<NB, NT>(o, aop, cmax, mu, sub, lane);
+  // LDS: rpb list entries per wave, so the list cannot overflow
   extern __shared__ uint32_t pend_all[];
-  uint32_t* pend = pend_all + w * rpb;
-  int np = 0;
-  float xnext[DW];
-  load_rows(xnext, rbeg);
-  for (int64_t r0 = rbeg; r0 < rend; r0 += 32) {
-    const int64_t row = r0 + (lane & 31);
-    const bool valid = row < rend;
-    float xv[DW];   // centred row slice
-#pragma unroll
-    for (int e = 0; e < DW; ++e) xv[e] = xnext[e] - muv[e];
-    if (r0 + 32 < rend) load_rows(xnext, r0 + 32);   // next tile's rows in flight
+  const Band bd{e_cross, e_norm, g_exact};
+  const uint32_t nres = assign_rows<NB, NT, FULL, false>(x, d, ds, m, ks, sub, rbeg, rend, o,
+                                                         c32 + (int64_t)sub * ks * ds, codes, pend_all + w * rpb,
+                                                         0, bd, lane);
+  if (rescored && lane == 0 && nres) atomicAdd(rescored, (unsigned long long)nres);
+}
 
-    // row operands
-    float xn = 0.0f;
-#pragma unroll
-    for (int e = 0; e < DW; ++e) xn = xn + xv[e] * xv[e];
-    bf16x8 XH[NB], XL[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      XH[b] = to_bf16x8(xv + b * 8);
-      float rem[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) rem[e] = xv[b * 8 + e] - (float)XH[b][e];
-      XL[b] = to_bf16x8(rem);
-    }
-    bf16x8 normB = {};
-    {
-      const __bf16 h = (__bf16)xn;
-      const float r1 = xn - (float)h;
-      const __bf16 md = (__bf16)r1;
-      normB[0] = normB[1] = normB[2] = (__bf16)1.0f;
-      normB[3] = h;
-      normB[4] = md;
-      normB[5] = (__bf16)(r1 - (float)md);
-    }
-    bf16x8 B[NMF];
-#pragma unroll
-    for (int f = 0; f < NMF; ++f) {
-      if (f < NB) {
-        B[f] = XH[f];
-      } else if (f < NB + (NB + 1) / 2) {
-        const int b0 = 2 * (f - NB);
-        if (b0 + 1 < NB) B[f] = half ? XL[b0 + 1] : XL[b0];
-        else B[f] = half ? normB : XL[b0];
-      } else {
-        B[f] = half ? zero8 : normB;
-      }
-    }
-    auto tile = [&](int t) {
-      f32x16 acc = {};
-#pragma unroll
-      for (int f = 0; f < NMF; ++f) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[t][f], B[f], acc, 0, 0, 0);
-      return acc;
-    };
-
-    // distance estimates, reduced by tile (amin) and by accumulator register (bmin)
-    float amin[NT];
-    float bmin[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) bmin[r] = INFINITY;
-#pragma unroll
-    for (int t = 0; t < NT; t += 2) {
-      const f32x16 c0 = tile(t);
-      amin[t] = min16(c0);
-      if (t + 1 < NT) {
-        const f32x16 c1 = tile(t + 1 < NT ? t + 1 : 0);
-        amin[t + 1] = min16(c1);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) bmin[r] = min3f(bmin[r], c0[r], c1[r]);
-      } else {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) bmin[r] = fminf(bmin[r], c0[r]);
-      }
-    }
-
-    // smallest two keys of each grouping; the low bits carry the tile
-    // (3 bits) or the register (4 bits)
-    int a1 = INT_MAX, a2 = INT_MAX, b1 = INT_MAX, b2 = INT_MAX;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int k = key_of(amin[t], ~7, t);
-      a2 = min(a2, max(a1, k));
-      a1 = min(a1, k);
-    }
-#pragma unroll
-    for (int r = 0; r < 16; r += 2) {
-      const int ka = key_of(bmin[r], ~15, r);
-      const int kb = key_of(bmin[r + 1], ~15, r + 1);
-      b2 = min(b2, med3i(ka, kb, b1));   // runner-up of {b1, b2, ka, kb}, b1 <= b2
-      b1 = min(b1, min(ka, kb));
-    }
-    const int rl = b1 & 15;
-    const int s2 = min(a2, b2);
-
-    // merge the two lanes holding the 256 candidates of a row
-    const int2 A1 = halves(a1);
-    const int2 S2 = halves(s2);
-    const int2 RL = halves(rl);
-    const bool hiw = A1.y < A1.x;
-    const int w1 = min(A1.x, A1.y);
-    const int sec = min(max(A1.x, A1.y), min(S2.x, S2.y));
-    const int tw = (hiw ? A1.y : A1.x) & 7;
-    const int rw = hiw ? RL.y : RL.x;
-    const int code = tw * 32 + (rw >> 2) * 8 + (hiw ? 4 : 0) + (rw & 3);
-
-    const float f1 = __int_as_float(w1);
-    const float f2 = __int_as_float(sec);
-    const float xnorm = sqrtf(xn) * 1.0001f;
-    const float beta = e_cross * xnorm * cm + e_norm * (cm * cm + xn);
-    const float q = 3.815e-6f + g_exact;                       // 2^-18 + gamma
-    const float thr = 2.0f * beta + q * (fabsf(f1) + fabsf(f2)) +
-                      2.0f * g_exact * (beta + g_exact * xn);
-    const float gap = f2 - f1;
-    const bool amb = !(gap > thr) || code >= ks;
-
-    // rows whose two best candidates are not separated are re-decided by the
-    // whole wave with the exact rule (rare); their codes are overwritten then
-    if (half == 0 && valid) codes[row * m + sub] = (uint8_t)code;
-    const bool push = (half == 0) && valid && amb;
-    const uint64_t mask = __ballot(push);
-    if (mask) {
-      if (push) pend[np + __popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)(row - rbeg);
-      np += __popcll(mask);
-    }
+// Many problems in one persistent launch.  The work is the list of units
+// (problem, group of 4 subspaces, 32-row tile): problem-major, then group,
+// then tile.  Logical block b takes the contiguous range [U b / G, U (b+1) / G)
+// of the U units, so it crosses few (problem, group) segments and keeps one
+// segment's operands in registers while it lasts.  Logical blocks are
+// numbered so that each XCD (hardware block id mod 8) holds a contiguous
+// eighth of the list: neighbouring segments share that XCD's L2.
+template <int NB, int NT, bool FULL>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NB == 1 ? 3 : 1, 8))) void k_assign_bf16_batched(
+    const BatchProb* __restrict__ probs, int nprob, int64_t units, int d, int m, int ks, int ds,
+    const bf16x8* __restrict__ aop, size_t aop_stride, const float* __restrict__ cmax,
+    const float* __restrict__ mu, unsigned long long* __restrict__ rescored, float e_cross, float e_norm,
+    float g_exact) {
+  constexpr int PC = kBatchPend;
+  __shared__ uint32_t pend_all[(kThreads / 64) * PC];
+  const int G = gridDim.x;   // a multiple of 8
+  const int lb = (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3);
+  // block-uniform work indices, kept in scalar registers (the divisions
+  // themselves run on the vector unit)
+  int64_t u = uniform64(units * lb / G);
+  const int64_t uend = uniform64(units * (lb + 1) / G);
+  if (u >= uend) return;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int groups = (m + 3) >> 2;
+  const Band bd{e_cross, e_norm, g_exact};
+  // the problem holding unit u: the last p with unit0 <= u
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (probs[mid].unit0 <= u) lo = mid;
+    else hi = mid - 1;
   }
-  for (int i = 0; i < np; ++i) {
-    const int64_t prow = rbeg + pend[i];
-    const int ec = exact_code_wave<DW>(x + prow * d + (int64_t)sub * ds, cbsub, ds, ks, lane);
-    if (lane == 0) codes[prow * m + sub] = (uint8_t)ec;
+  int p = lo;
+  uint32_t nres = 0;
+  while (u < uend) {
+    while (p + 1 < nprob && probs[p + 1].unit0 <= u) ++p;
+    const float* px = probs[p].x;
+    const int64_t n = probs[p].n;
+    const int64_t tiles = (n + 31) >> 5;
+    const int64_t local = u - probs[p].unit0;   // < groups * tiles < 2^32
+    const int group = __builtin_amdgcn_readfirstlane((int)((uint32_t)local / (uint32_t)tiles));
+    const int64_t t0 = local - (int64_t)group * tiles;
+    const int64_t t1 = min(tiles, t0 + (uend - u));
+    u += t1 - t0;
+    const int sub = group * 4 + w;
+    if (group >= groups || sub >= m) continue;
+    SubOps<NB, NT> o;
+    load_sub_ops<NB, NT>(o, aop + (size_t)p * aop_stride, cmax + (size_t)p * m, mu + (size_t)p * m * kMaxDsBf16,
+                         sub, lane);
+    // rows in pieces of PC, so that a piece's pending list fits the wave's LDS
+    const int64_t rb = t0 * 32, re = min(n, t1 * 32);
+    for (int64_t pb = rb; pb < re; pb += PC)
+      nres += assign_rows<NB, NT, FULL, false>(px, d, ds, m, ks, sub, pb, min(re, pb + PC), o,
+                                               probs[p].c32 + (int64_t)sub * ks * ds, probs[p].codes,
+                                               pend_all + w * PC, 0, bd, lane);
   }
-  nres = (uint32_t)np;
   if (rescored && lane == 0 && nres) atomicAdd(rescored, (unsigned long long)nres);
 }
 
@@ -348,6 +477,22 @@ Bf16Geom bf16_geometry(int64_t n, int m) {
   return g;
 }
 
+namespace {
+// error-bound constants: split products 3.1 u^2 per term (u = 2^-8), twice
+// for the -2 factor, plus float32 accumulation over K = 16*NMF terms at
+// 2^-23 each, plus the rounding of the centring (2^-22 of the squared
+// norms); g_exact bounds the relative error of the exact float32 rule
+Band band_for(int ds) {
+  const int nb = (ds + 7) / 8;
+  const int nmf = bf16_nmfma(nb);
+  Band b;
+  b.e_cross = 1.25e-4f * (nb == 1 ? 1.0f : 1.05f);
+  b.e_norm = 2.4e-6f * nmf + 2.4e-7f;
+  b.g_exact = (float)((ds + 2) * 1.01 / 16777216.0);
+  return b;
+}
+}  // namespace
+
 int launch_assign_bf16(const float* x, int64_t n, int d, int m, int ks, const void* aop,
                        const float* cmax, const float* mu, const float* c32, uint8_t* codes,
                        int64_t* rescored, hipStream_t s) {
@@ -356,14 +501,7 @@ int launch_assign_bf16(const float* x, int64_t n, int d, int m, int ks, const vo
   const int nt = tiles_for(ks);
   const Bf16Geom g = bf16_geometry(n, m);
   if (g.blocks == 0) return MIPQ_OK;
-  // error-bound constants: split products 3.1 u^2 per term (u = 2^-8), twice
-  // for the -2 factor, plus float32 accumulation over K = 16*NMF terms at
-  // 2^-23 each, plus the rounding of the centring (2^-22 of the squared
-  // norms); g_exact bounds the relative error of the exact float32 rule
-  const int nmf = bf16_nmfma(nb);
-  const float e_cross = 1.25e-4f * (nb == 1 ? 1.0f : 1.05f);
-  const float e_norm = 2.4e-6f * nmf + 2.4e-7f;
-  const float g_exact = (float)((ds + 2) * 1.01 / 16777216.0);
+  const Band bd = band_for(ds);
   ProfScope ps(MIPQ_K_ASSIGN_BF16, s);
   const bool full = (ds == nb * 8) && (d % 4 == 0) && ((reinterpret_cast<uintptr_t>(x) & 15) == 0);
   unsigned long long* resc = reinterpret_cast<unsigned long long*>(rescored);
@@ -373,11 +511,11 @@ int launch_assign_bf16(const float* x, int64_t n, int d, int m, int ks, const vo
     if (full)                                                                                       \
       k_assign_bf16<NB, NT, true><<<g.blocks, kThreads, pend_bytes, s>>>(                           \
           x, n, d, m, ks, ds, (const bf16x8*)aop, cmax, mu, c32, codes, resc, g.groups, g.rpb,      \
-          e_cross, e_norm, g_exact);                                                                \
+          bd.e_cross, bd.e_norm, bd.g_exact);                                                       \
     else                                                                                            \
       k_assign_bf16<NB, NT, false><<<g.blocks, kThreads, pend_bytes, s>>>(                          \
           x, n, d, m, ks, ds, (const bf16x8*)aop, cmax, mu, c32, codes, resc, g.groups, g.rpb,      \
-          e_cross, e_norm, g_exact);                                                                \
+          bd.e_cross, bd.e_norm, bd.g_exact);                                                       \
   } while (0)
   if (nb == 1) {
     switch (nt) {
@@ -396,6 +534,52 @@ int launch_assign_bf16(const float* x, int64_t n, int d, int m, int ks, const vo
   }
 #undef LAUNCH
   MIPQ_LAUNCHED("k_assign_bf16");
+  return MIPQ_OK;
+}
+
+namespace {
+template <int NB, int NT, bool FULL>
+const void* batched_fn() {
+  return reinterpret_cast<const void*>(&k_assign_bf16_batched<NB, NT, FULL>);
+}
+const void* pick_batched(int ds, int ks, bool full) {
+  const int nb = (ds + 7) / 8;
+  const int nt = tiles_for(ks);
+#define PICK(NB)                                                                  \
+  switch (nt) {                                                                   \
+    case 1: return full ? batched_fn<NB, 1, true>() : batched_fn<NB, 1, false>(); \
+    case 2: return full ? batched_fn<NB, 2, true>() : batched_fn<NB, 2, false>(); \
+    case 4: return full ? batched_fn<NB, 4, true>() : batched_fn<NB, 4, false>(); \
+    default: return full ? batched_fn<NB, 8, true>() : batched_fn<NB, 8, false>(); \
+  }
+  if (nb == 1) PICK(1)
+  PICK(2)
+#undef PICK
+}
+}  // namespace
+
+int assign_bf16_batched_resident(int ds, int ks, bool full, int* resident) {
+  int per_cu = 0, dev = 0, cus = 0;
+  MIPQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pick_batched(ds, ks, full), kThreads, 0));
+  MIPQ_HIP(hipGetDevice(&dev));
+  MIPQ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  *resident = per_cu * cus;
+  return MIPQ_OK;
+}
+
+int launch_assign_bf16_batched(const BatchProb* probs, int nprob, int64_t units, int d, int m, int ks,
+                               const void* aop, size_t aop_stride, const float* cmax, const float* mu, bool full,
+                               int grid, int64_t* rescored, hipStream_t s) {
+  if (units == 0) return MIPQ_OK;
+  if (grid < 8 || grid % 8) return fail(MIPQ_EINVAL, "batched assignment grid must be a positive multiple of 8");
+  const int ds = d / m;
+  Band bd = band_for(ds);
+  unsigned long long* resc = reinterpret_cast<unsigned long long*>(rescored);
+  ProfScope ps(MIPQ_K_ASSIGN_BF16_BATCHED, s);
+  void* args[] = {(void*)&probs, (void*)&nprob, (void*)&units, (void*)&d, (void*)&m, (void*)&ks, (void*)&ds,
+                  (void*)&aop, (void*)&aop_stride, (void*)&cmax, (void*)&mu, (void*)&resc,
+                  (void*)&bd.e_cross, (void*)&bd.e_norm, (void*)&bd.g_exact};
+  MIPQ_HIP(hipLaunchKernel(pick_batched(ds, ks, full), dim3(grid), dim3(kThreads), args, 0, s));
   return MIPQ_OK;
 }
 

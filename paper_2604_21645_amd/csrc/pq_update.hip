@@ -24,18 +24,15 @@ constexpr int kPackRed = 544;   // floats of LDS scratch for pack_subspace
 // With GX the block also writes dL/dx = 2 g (x - c) (float64 product rounded to
 // float32, g = *gscale) for the reconstruction loss L = sum (x - x_hat)^2.
 template <bool GX>
-__global__ __launch_bounds__(kUpdThreads) void k_accumulate(
+__device__ __forceinline__ void accumulate_chunk(
     const float* __restrict__ x, int64_t n, int d, int m, int ks, int ds,
-    const uint8_t* __restrict__ codes, const float* __restrict__ c32, int64_t rpc,
+    const uint8_t* __restrict__ codes, const float* __restrict__ c32, int64_t rpc, int c, int sub,
     double* __restrict__ part_s, uint32_t* __restrict__ part_cnt, double* __restrict__ part_j,
-    const double* __restrict__ gscale, float* __restrict__ grad_x) {
-  extern __shared__ double smem[];
-  __shared__ double redj[kUpdThreads / 64];
+    const double* __restrict__ gscale, float* __restrict__ grad_x, double* smem, double* redj) {
   const int stride = ds + 1;
   double* S = smem;
   uint32_t* cnt = reinterpret_cast<uint32_t*>(S + (size_t)ks * stride);
   float* cbs = reinterpret_cast<float*>(S + (size_t)ks * stride + (ks + 1) / 2);
-  const int c = blockIdx.x, sub = blockIdx.y;
   const int per = ks * ds;
   for (int i = threadIdx.x; i < ks * stride; i += blockDim.x) S[i] = 0.0;
   for (int i = threadIdx.x; i < ks; i += blockDim.x) cnt[i] = 0u;
@@ -99,22 +96,63 @@ __global__ __launch_bounds__(kUpdThreads) void k_accumulate(
   }
 }
 
-// One block per subspace: sums the chunk partials in chunk order, centroid =
-// sum / count (an empty centroid keeps its value), float32 copy by
-// round-to-nearest, the subspace objective, and with PACK the next round's
-// operands.
+// One problem: block (c, j) = chunk c, subspace j.
+template <bool GX>
+__global__ __launch_bounds__(kUpdThreads) void k_accumulate(
+    const float* __restrict__ x, int64_t n, int d, int m, int ks, int ds,
+    const uint8_t* __restrict__ codes, const float* __restrict__ c32, int64_t rpc,
+    double* __restrict__ part_s, uint32_t* __restrict__ part_cnt, double* __restrict__ part_j,
+    const double* __restrict__ gscale, float* __restrict__ grad_x) {
+  extern __shared__ double smem[];
+  __shared__ double redj[kUpdThreads / 64];
+  accumulate_chunk<GX>(x, n, d, m, ks, ds, codes, c32, rpc, blockIdx.x, blockIdx.y, part_s, part_cnt, part_j,
+                       gscale, grad_x, smem, redj);
+}
+
+// the last problem p with key(p) <= i (problems in ascending key order)
+template <class Key>
+__device__ __forceinline__ int find_problem(const BatchProb* __restrict__ probs, int nprob, int64_t i, Key key) {
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (key(probs[mid]) <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Many problems: block i is accumulation item i = (problem p, chunk c,
+// subspace j) with items problem-major, then chunk, then subspace; problem p's
+// partials use the single-problem layout at offset item0.
+__global__ __launch_bounds__(kUpdThreads) void k_accumulate_batched(const BatchProb* __restrict__ probs, int nprob,
+                                                                    int d, int m, int ks, int ds,
+                                                                    double* __restrict__ part_s,
+                                                                    uint32_t* __restrict__ part_cnt,
+                                                                    double* __restrict__ part_j) {
+  extern __shared__ double smem[];
+  __shared__ double redj[kUpdThreads / 64];
+  const int64_t i = blockIdx.x;
+  const int p = find_problem(probs, nprob, i, [](const BatchProb& b) { return b.item0; });
+  const int64_t item0 = probs[p].item0;
+  const int local = (int)(i - item0);
+  const int c = local / m, sub = local - (local / m) * m;
+  const size_t per = (size_t)ks * ds;
+  accumulate_chunk<false>(probs[p].x, probs[p].n, d, m, ks, ds, probs[p].codes, probs[p].c32, probs[p].rpc, c, sub,
+                          part_s + item0 * per, part_cnt + item0 * ks, part_j + item0, nullptr, nullptr, smem, redj);
+}
+
+// Subspace sub: sums the chunk partials in chunk order, centroid = sum /
+// count (an empty centroid keeps its value), float32 copy by
+// round-to-nearest, the subspace objective (*j_out), and with PACK the next
+// round's operands.  newc: ks*ds floats of LDS.
 template <int NB, bool PACK>
-__global__ __launch_bounds__(kUpdThreads) void k_finalize(int m, int ks, int ds, int nch,
-                                                          const double* __restrict__ part_s,
-                                                          const uint32_t* __restrict__ part_cnt,
-                                                          const double* __restrict__ part_j,
-                                                          float* __restrict__ c32, double* __restrict__ c64,
-                                                          double* __restrict__ j_sub, uint4* __restrict__ aop,
-                                                          float* __restrict__ cmax, float* __restrict__ mu,
-                                                          int nt) {
-  extern __shared__ float newc[];   // new float32 centroids of this subspace
-  __shared__ float packred[kPackRed];
-  const int sub = blockIdx.x;
+__device__ __forceinline__ void finalize_sub(int sub, int m, int ks, int ds, int nch,
+                                             const double* __restrict__ part_s,
+                                             const uint32_t* __restrict__ part_cnt,
+                                             const double* __restrict__ part_j, float* __restrict__ c32,
+                                             double* __restrict__ c64, double* __restrict__ j_out,
+                                             uint4* __restrict__ aop, float* __restrict__ cmax,
+                                             float* __restrict__ mu, int nt, float* newc, float* packred) {
   const int per = ks * ds;
   for (int e = threadIdx.x; e < per; e += blockDim.x) {
     const int k = e / ds;
@@ -150,10 +188,60 @@ __global__ __launch_bounds__(kUpdThreads) void k_finalize(int m, int ks, int ds,
     for (int cc = threadIdx.x; cc < nch; cc += 64) js += part_j[(size_t)cc * m + sub];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) js += __shfl_xor(js, off, 64);
-    if (threadIdx.x == 0) j_sub[sub] = js;
+    if (threadIdx.x == 0 && j_out) *j_out = js;
   }
   __syncthreads();
   if (PACK) pack_subspace<NB>(newc, ks, ds, nt, sub, 0, nt, aop, cmax + sub, mu + sub * kMaxDsBf16, true, packred);
+}
+
+// One block per subspace.
+template <int NB, bool PACK>
+__global__ __launch_bounds__(kUpdThreads) void k_finalize(int m, int ks, int ds, int nch,
+                                                          const double* __restrict__ part_s,
+                                                          const uint32_t* __restrict__ part_cnt,
+                                                          const double* __restrict__ part_j,
+                                                          float* __restrict__ c32, double* __restrict__ c64,
+                                                          double* __restrict__ j_sub, uint4* __restrict__ aop,
+                                                          float* __restrict__ cmax, float* __restrict__ mu,
+                                                          int nt) {
+  extern __shared__ float newc[];   // new float32 centroids of this subspace
+  __shared__ float packred[kPackRed];
+  finalize_sub<NB, PACK>(blockIdx.x, m, ks, ds, nch, part_s, part_cnt, part_j, c32, c64, j_sub + blockIdx.x, aop,
+                         cmax, mu, nt, newc, packred);
+}
+
+// Many problems: block b = (problem b / m, subspace b % m).  The round index
+// is read from *round (advanced by k_next_round at the end of each round), so
+// that one recorded sequence of launches serves every round: the objective of
+// round r goes to j_all[(r * nprob + p) * m + j].
+template <int NB>
+__global__ __launch_bounds__(kUpdThreads) void k_finalize_batched(const BatchProb* __restrict__ probs, int nprob,
+                                                                  int m, int ks, int ds,
+                                                                  const double* __restrict__ part_s,
+                                                                  const uint32_t* __restrict__ part_cnt,
+                                                                  const double* __restrict__ part_j,
+                                                                  double* __restrict__ c64_all,
+                                                                  double* __restrict__ j_all,
+                                                                  const uint32_t* __restrict__ round, int iters,
+                                                                  uint4* __restrict__ aop_all, size_t aop_stride,
+                                                                  float* __restrict__ cmax_all,
+                                                                  float* __restrict__ mu_all, int nt) {
+  extern __shared__ float newc[];
+  __shared__ float packred[kPackRed];
+  const int p = blockIdx.x / m;
+  const int sub = blockIdx.x - p * m;
+  const int64_t item0 = probs[p].item0;
+  const size_t per = (size_t)ks * ds;
+  const uint32_t r = *round;
+  double* j_out = r < (uint32_t)iters ? j_all + ((size_t)r * nprob + p) * m + sub : nullptr;
+  finalize_sub<NB, true>(sub, m, ks, ds, probs[p].nch, part_s + item0 * per, part_cnt + item0 * ks,
+                         part_j + item0, probs[p].c32, c64_all + (size_t)p * m * per, j_out,
+                         aop_all + (size_t)p * aop_stride, cmax_all + (size_t)p * m,
+                         mu_all + (size_t)p * m * kMaxDsBf16, nt, newc, packred);
+}
+
+__global__ void k_next_round(uint32_t* round) {
+  if (threadIdx.x == 0) round[0] = round[0] + 1u;
 }
 
 // dL/dC_j[k] = 2 g (cnt_jk C_j[k] - S_jk) with the chunk partials summed in
@@ -214,6 +302,19 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_bf16(const float* __restr
   const int t = blockIdx.x, sub = blockIdx.y;
   pack_subspace<NB>(c32 + (int64_t)sub * ks * ds, ks, ds, nt, sub, t, t + 1, aop, cmax + sub,
                     mu + sub * kMaxDsBf16, t == 0, red);
+}
+
+// Many problems: block (t, j, p) packs tile t of subspace j of problem p.
+template <int NB>
+__global__ __launch_bounds__(kPackThreads) void k_pack_bf16_batched(const BatchProb* __restrict__ probs, int ks,
+                                                                    int ds, int m, int nt, uint4* __restrict__ aop_all,
+                                                                    size_t aop_stride, float* __restrict__ cmax_all,
+                                                                    float* __restrict__ mu_all) {
+  __shared__ float red[kPackRed];
+  const int t = blockIdx.x, sub = blockIdx.y, p = blockIdx.z;
+  pack_subspace<NB>(probs[p].c32 + (int64_t)sub * ks * ds, ks, ds, nt, sub, t, t + 1,
+                    aop_all + (size_t)p * aop_stride, cmax_all + (size_t)p * m + sub,
+                    mu_all + ((size_t)p * m + sub) * kMaxDsBf16, t == 0, red);
 }
 
 }  // namespace
@@ -297,6 +398,49 @@ int launch_pack_bf16(const float* c32, int m, int ks, int ds, void* aop, float* 
   else
     k_pack_bf16<2><<<grid, kPackThreads, 0, s>>>(c32, ks, ds, nt, (uint4*)aop, cmax, mu);
   MIPQ_LAUNCHED("k_pack_bf16");
+  return MIPQ_OK;
+}
+
+int launch_pack_bf16_batched(const BatchProb* probs, int nprob, int m, int ks, int ds, void* aop,
+                             size_t aop_stride, float* cmax, float* mu, hipStream_t s) {
+  const int nt = tiles_for(ks);
+  ProfScope ps(MIPQ_K_PACK_BF16, s);
+  dim3 grid(nt, m, nprob);
+  if (ds <= 8)
+    k_pack_bf16_batched<1><<<grid, kPackThreads, 0, s>>>(probs, ks, ds, m, nt, (uint4*)aop, aop_stride, cmax, mu);
+  else
+    k_pack_bf16_batched<2><<<grid, kPackThreads, 0, s>>>(probs, ks, ds, m, nt, (uint4*)aop, aop_stride, cmax, mu);
+  MIPQ_LAUNCHED("k_pack_bf16_batched");
+  return MIPQ_OK;
+}
+
+int launch_update_batched(const BatchProb* probs, int nprob, int64_t items, int d, int m, int ks, double* c64,
+                          double* part_s, uint32_t* part_cnt, double* part_j, double* j_all,
+                          const uint32_t* round, int iters, void* aop, size_t aop_stride, float* cmax, float* mu,
+                          hipStream_t s) {
+  const int ds = d / m;
+  {
+    const size_t shm = (size_t)ks * (ds + 1) * sizeof(double) + ((ks + 1) / 2) * sizeof(double) +
+                       (size_t)ks * ds * sizeof(float);
+    ProfScope ps(MIPQ_K_UPDATE, s);
+    k_accumulate_batched<<<(unsigned)items, kUpdThreads, shm, s>>>(probs, nprob, d, m, ks, ds, part_s, part_cnt,
+                                                                   part_j);
+    MIPQ_LAUNCHED("k_accumulate_batched");
+  }
+  const int nt = tiles_for(ks);
+  const size_t shm = (size_t)ks * ds * sizeof(float);
+  ProfScope ps(MIPQ_K_FINALIZE, s);
+  if (ds <= 8)
+    k_finalize_batched<1><<<nprob * m, kUpdThreads, shm, s>>>(probs, nprob, m, ks, ds, part_s, part_cnt, part_j, c64,
+                                                              j_all, round, iters, (uint4*)aop, aop_stride, cmax,
+                                                              mu, nt);
+  else
+    k_finalize_batched<2><<<nprob * m, kUpdThreads, shm, s>>>(probs, nprob, m, ks, ds, part_s, part_cnt, part_j, c64,
+                                                              j_all, round, iters, (uint4*)aop, aop_stride, cmax,
+                                                              mu, nt);
+  MIPQ_LAUNCHED("k_finalize_batched");
+  k_next_round<<<1, 64, 0, s>>>(const_cast<uint32_t*>(round));
+  MIPQ_LAUNCHED("k_next_round");
   return MIPQ_OK;
 }
 

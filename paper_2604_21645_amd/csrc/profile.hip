@@ -3,7 +3,8 @@
 // When enabled, every launcher brackets its kernel with a pair of events on
 // the stream it launches on; mipq_profile_collect() waits for them and reports
 // the number of launches and their summed duration per kernel.  Disabled (the
-// default), the brackets cost one relaxed atomic load.
+// default), the brackets cost one relaxed atomic load.  Launches recorded into
+// a graph (stream capture) are not bracketed.
 #include <atomic>
 #include <mutex>
 #include <vector>
@@ -33,6 +34,8 @@ hipEvent_t take_event() {
 
 ProfScope::ProfScope(int kernel, hipStream_t s) : kernel_(kernel), s_(s) {
   if (!g_on.load(std::memory_order_relaxed)) return;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;   // graph capture
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_pool.empty()) {
     Pair p = g_pool.back();

@@ -76,3 +76,55 @@ def test_fit_rejects_bad_arguments(L):
 def test_decode_needs_x_for_the_error(L):
     rc = L.mipq_pq_decode_rmse(1, 10, 128, 16, 256, 1, None, None, 1, 256, 1 << 20, None)
     assert rc == EINVAL
+
+
+def _table(ns, m=12, ks=256, ok_ptrs=True):
+    t = (_lib.MipqProblem * len(ns))()
+    for i, n in enumerate(ns):
+        p = 4096 * (i + 1) if ok_ptrs else None
+        t[i] = _lib.MipqProblem(p, n, p, p, p, None, None)
+    return t
+
+
+def test_batched_workspace_grows_with_problems(L):
+    one = (ctypes.c_int64 * 1)(20000)
+    two = (ctypes.c_int64 * 2)(20000, 500000)
+    a = L.mipq_pq_fit_batched_workspace_size(one, 1, 96, 12, 256, 20, 1)
+    b = L.mipq_pq_fit_batched_workspace_size(two, 2, 96, 12, 256, 20, 1)
+    assert 0 < a < b
+    assert L.mipq_pq_fit_batched_workspace_size(two, 2, 96, 12, 256, 20, 0) == 0   # FP32: not offered
+    bad = (ctypes.c_int64 * 2)(20000, 0)
+    assert L.mipq_pq_fit_batched_workspace_size(bad, 2, 96, 12, 256, 20, 1) == 0
+
+
+@pytest.mark.parametrize("case,code", [
+    (dict(nprob=0), EINVAL),
+    (dict(prec=0), EUNSUPPORTED),
+    (dict(d=97), EINVAL),
+    (dict(d=384, m=12), EUNSUPPORTED),    # d/m = 32 > 16
+    (dict(ns=[100, 0]), EINVAL),
+    (dict(ok_ptrs=False), EINVAL),
+    (dict(ws=None), EINVAL),
+    (dict(ws_bytes=64), ENOMEM),
+    (dict(ws=4096 + 8), EINVAL),           # misaligned
+])
+def test_batched_rejects_bad_arguments(L, case, code):
+    ns = case.get("ns", [100, 3000])
+    t = _table(ns, ok_ptrs=case.get("ok_ptrs", True))
+    nprob = case.get("nprob", len(ns))
+    rc = L.mipq_pq_fit_batched(t, nprob, case.get("d", 96), case.get("m", 12), 256, 5, case.get("prec", 1), None,
+                               None, case.get("ws", 4096), case.get("ws_bytes", 1 << 30), None)
+    assert rc == code
+    assert len(L.mipq_last_error()) > 0
+
+
+def test_plan_rejects_bad_arguments(L):
+    plan = ctypes.c_void_p()
+    t = _table([100, 3000])
+    assert L.mipq_plan_create(None, t, 2, 96, 12, 256, 5, 1, 3, 4096, 1 << 30, None) == EINVAL
+    assert L.mipq_plan_create(ctypes.byref(plan), t, 2, 96, 12, 256, 5, 1, 64, 4096, 1 << 30, None) == EINVAL
+    assert L.mipq_plan_create(ctypes.byref(plan), t, 2, 96, 12, 256, 5, 1, 3, 4096, 64, None) == ENOMEM
+    assert plan.value is None
+    assert L.mipq_plan_destroy(None) == 0
+    info = (ctypes.c_int64 * 4)()
+    assert L.mipq_plan_info(None, info, 4) == EINVAL

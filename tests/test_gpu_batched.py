@@ -1,0 +1,176 @@
+"""GPU parity of the batched fit + encode (many independent problems, one
+launch per phase, optional plan with autotuned grid and HIP graphs).
+
+Each problem's results must equal the single-problem calls on that problem
+(pq_fit + pq_encode + pq_decode_rmse): the same code rule, the same row
+chunks and reduction orders.  Integer-valued rows make every float64 sum
+exact, so there the comparison is bit for bit end to end; on real-valued
+rows the codes and errors are compared in lockstep (same codebook).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2604_21645_amd as mipq
+from oracle import pq
+from synth import workloads as wl
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _problems(sizes, d, m, ks, kind, seed):
+    total = int(sum(sizes))
+    if kind == "integer":
+        allx = wl.gaussian_mixture(seed, total, d, 40, mean_hi=255.0, sigma=20.0, integer_clip=(0, 255))
+    else:
+        allx = wl.gaussian_mixture(seed, total, d, 60, sphere_kappa=50.0)
+    xs, inits, off = [], [], 0
+    for i, n in enumerate(sizes):
+        xs.append(allx[off:off + n])
+        off += n
+        inits.append(wl.init_rows_per_subspace(seed, n, m, ks, key=i))
+    return xs, inits
+
+
+def _single(x, init, m, ks, iters):
+    xt = _t(x)
+    fit = mipq.pq_fit(xt, m, ks, iters, init_rows=_t(init), precision="bf16", labels=False)
+    codes = mipq.pq_encode(xt, fit["codebook"], "bf16")
+    _, sr = mipq.pq_decode_rmse(codes, fit["codebook"], xt)
+    return fit["codebook"], codes, sr, fit["objective"]
+
+
+def _run(xs, inits, m, ks, iters, mode):
+    xt = [_t(x) for x in xs]
+    it = [_t(i) for i in inits]
+    if mode == "eager":
+        b = mipq.BatchedFit(xt, it, m, ks, iters, plan=False)
+    elif mode == "plan":
+        b = mipq.BatchedFit(xt, it, m, ks, iters, plan=True, autotune=False, graph=False)
+    else:
+        b = mipq.BatchedFit(xt, it, m, ks, iters, plan=True, autotune=True, graph=True)
+    resc = b.run(rescored=True)
+    torch.cuda.synchronize()
+    return b, resc
+
+
+SIZES = [64, 65, 97, 1000, 4097, 20011, 333]
+
+
+@pytest.mark.parametrize("mode", ["eager", "plan", "graph"])
+def test_integer_rows_equal_single_calls_bit_for_bit(mode):
+    m, ks, iters, d = 12, 64, 5, 96
+    xs, inits = _problems(SIZES, d, m, ks, "integer", seed=31)
+    print("batched", mode, flush=True)
+    b, resc = _run(xs, inits, m, ks, iters, mode)
+    for i, (x, init) in enumerate(zip(xs, inits)):
+        cb, codes, sr, obj = _single(x, init, m, ks, iters)
+        r = b.results[i]
+        assert torch.equal(r["codebook"], cb), i
+        assert torch.equal(r["codes"], codes), i
+        assert torch.equal(r["sse_rmse"], sr), i
+        assert torch.equal(r["objective"], obj), i
+    assert int(resc.item()) >= 0
+    if mode == "graph":
+        info = b.info()
+        print("plan", info, flush=True)
+        assert info["graph"] and info["grid"] % 8 == 0 and len(info["candidates"]) >= 2
+    b.close()
+
+
+def test_integer_rows_match_the_oracle():
+    m, ks, iters, d = 12, 64, 4, 96
+    xs, inits = _problems([64, 700, 2001], d, m, ks, "integer", seed=32)
+    b, _ = _run(xs, inits, m, ks, iters, "graph")
+    for i, (x, init) in enumerate(zip(xs, inits)):
+        ref = pq.lloyd(x, init, m, iters, decide="fp32")
+        r = b.results[i]
+        # integer rows: float64 sums exact in any order
+        np.testing.assert_array_equal(r["codebook"].cpu().numpy(), ref["codebook"].astype(np.float32))
+        np.testing.assert_allclose(r["objective"].cpu().numpy(), ref["objective"], rtol=1e-12)
+        codes_ref, _ = pq.encode(x, ref["codebook"].astype(np.float32).astype(np.float64), decide="fp32")
+        np.testing.assert_array_equal(r["codes"].cpu().numpy().astype(np.int64), codes_ref)
+        sse, rmse = pq.sse_rmse(x, codes_ref, ref["codebook"].astype(np.float32).astype(np.float64))
+        got = r["sse_rmse"].cpu().numpy()
+        assert got[0] == pytest.approx(sse, rel=1e-12) and got[1] == pytest.approx(rmse, rel=1e-12)
+    b.close()
+
+
+@pytest.mark.parametrize("d,m,ks", [(96, 12, 256), (64, 4, 100), (48, 16, 16)])
+def test_unit_sphere_rows_lockstep(d, m, ks):
+    """Real-valued rows (ds = 8, 16, 3; ks = 256, 100, 16): codes and errors
+    in lockstep with the single calls on the batched codebooks; codebooks
+    equal to the single fits up to float64 summation order."""
+    iters = 6
+    sizes = [ks, 3001, 777, 12345]
+    xs, inits = _problems(sizes, d, m, ks, "sphere", seed=33)
+    b, _ = _run(xs, inits, m, ks, iters, "graph")
+    for i, (x, init) in enumerate(zip(xs, inits)):
+        r = b.results[i]
+        xt = _t(x)
+        codes = mipq.pq_encode(xt, r["codebook"], "bf16")
+        assert torch.equal(codes, r["codes"]), i
+        _, sr = mipq.pq_decode_rmse(codes, r["codebook"], xt)
+        assert torch.equal(sr, r["sse_rmse"]), i
+        cb, _, _, obj = _single(x, init, m, ks, iters)
+        np.testing.assert_allclose(r["codebook"].cpu().numpy(), cb.cpu().numpy(), rtol=1e-5, atol=1e-6)
+        np.testing.assert_allclose(r["objective"].cpu().numpy(), obj.cpu().numpy(), rtol=1e-6)
+        rows = np.random.default_rng(i).choice(x.shape[0], min(500, x.shape[0]), replace=False)
+        ref, _ = pq.encode(x[rows], r["codebook"].cpu().numpy().astype(np.float64), decide="fp32")
+        np.testing.assert_array_equal(r["codes"].cpu().numpy()[rows].astype(np.int64), ref)
+    b.close()
+
+
+def test_plan_replays_and_zero_rounds():
+    m, ks, d = 12, 64, 96
+    xs, inits = _problems([100, 2000], d, m, ks, "integer", seed=34)
+    b, _ = _run(xs, inits, m, ks, 3, "graph")
+    first = [{k: v.clone() for k, v in r.items()} for r in b.results]
+    for r in b.results:
+        for v in r.values():
+            v.zero_()
+    b.run()
+    torch.cuda.synchronize()
+    for r0, r1 in zip(first, b.results):
+        for k in r0:
+            assert torch.equal(r0[k], r1[k]), k
+    b.close()
+    # zero rounds: the initial rows are the codebook
+    b0, _ = _run(xs, inits, m, ks, 0, "graph")
+    for x, init, r in zip(xs, inits, b0.results):
+        np.testing.assert_array_equal(r["codebook"].cpu().numpy(), pq.init_codebook(x, init, m).astype(np.float32))
+    b0.close()
+
+
+def test_full_size_uneven_batch_sampled():
+    """64 problems, N_i log-uniform in [20k, 500k] (about 9.5M rows), D=96,
+    M=12, Ks=256, 20 rounds on all rows of each problem, autotuned plan with
+    graphs: sampled codes against the oracle on the final codebooks, objective
+    non-increasing, errors against the oracle on four problems."""
+    w = wl.batched_uneven()
+    xs = [p.x for p in w.problems]
+    inits = [p.init_rows for p in w.problems]
+    print("problems", len(xs), "rows", sum(x.shape[0] for x in xs), flush=True)
+    b, resc = _run(xs, inits, w.m, w.ks, w.iters, "graph")
+    print("plan", b.info(), "rescored", int(resc.item()), flush=True)
+    rng = np.random.default_rng(7)
+    for i, x in enumerate(xs):
+        r = b.results[i]
+        obj = r["objective"].cpu().numpy()
+        assert np.all(np.diff(obj) <= 1e-9 * obj[:-1]), i
+        cb = r["codebook"].cpu().numpy().astype(np.float64)
+        rows = rng.choice(x.shape[0], 300, replace=False)
+        ref, _ = pq.encode(x[rows], cb, decide="fp32")
+        np.testing.assert_array_equal(r["codes"].cpu().numpy()[rows].astype(np.int64), ref)
+    for i in np.argsort([x.shape[0] for x in xs])[:4]:
+        r = b.results[i]
+        sse, _ = pq.sse_rmse(xs[i], r["codes"].cpu().numpy().astype(np.int64),
+                             r["codebook"].cpu().numpy().astype(np.float64))
+        assert r["sse_rmse"][0].item() == pytest.approx(sse, rel=1e-12)
+    b.close()
