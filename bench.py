@@ -9,9 +9,14 @@ the reconstruction RMSE computed.  One step = fit + encode + decode/RMSE,
 inputs resident in HBM.  The headline precision is BF16 on matrix cores; the
 plain FP32 path runs the same step for comparison (identical codes).
 
+Other workloads (one JSON line each, same contract, selected with
+--workload): batched_uneven (64 uneven problems fitted and encoded together),
+ivf_adc (10M-row inverted file with residual PQ, ADC top-100 search) and
+diff_codebooks (2M x 256 encode + reconstruction loss + backward).
+
 Prints one JSON line on stdout; progress goes to stderr.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 
 from __future__ import annotations
@@ -38,6 +43,46 @@ def log(*a):
 def kernel_source_hash() -> str:
     with open(MFMA_SOURCE, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def kernel_totals(L, names):
+    """(launches, summed ms) of each named kernel since the last collection."""
+    import ctypes
+
+    from paper_2604_21645_amd import _lib
+    out = {}
+    for name in names:
+        a, b = ctypes.c_int64(0), ctypes.c_double(0)
+        L.mipq_profile_collect(_lib.KERNELS[name], ctypes.byref(a), ctypes.byref(b))
+        out[name] = (a.value, b.value)
+    return out
+
+
+def drop_profile(L):
+    from paper_2604_21645_amd import _lib
+    for k in _lib.KERNELS.values():
+        L.mipq_profile_collect(k, None, None)
+
+
+def timed_steps(fn, steps, warmup):
+    """Run fn warmup times, then time exactly `steps` calls between two
+    device synchronisations; returns ms per step and the last result."""
+    import torch
+    out = None
+    for _ in range(warmup):
+        out = fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / max(steps, 1) * 1e3, out
+
+
+def base_record(metric, value, unit, steps, warmup, ms, dtype, config):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": dtype, "data": "synthetic", "config": config}
 
 
 def measured_traffic(per_launch_alg_bytes: float):
@@ -107,23 +152,9 @@ def oracle_parity(w, codes, cb, rmse, sample: int):
     }
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--fp32-steps", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-frac", type=float, default=0.02)
-    ap.add_argument("--oracle-sample", type=int, default=20000)
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a 1 GiB device copy (reference for HBM counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the PQ hot path runs on a single "
-              "MI355X); --gpus %d is not supported" % args.gpus, file=sys.stderr)
-        return 2
-
+def bench_integer_pq(args) -> dict:
+    """Headline workload: fit + encode + decode/RMSE of integer_pq (BF16),
+    with the FP32 plain step beside it."""
     import numpy as np
     import torch
 
@@ -264,9 +295,300 @@ def main() -> int:
         "kernels_ms_per_step": {k: v[1] / args.steps for k, v in kernel_stats.items()},
         "cpu_baseline": base,
     }
-    print(json.dumps(res), flush=True)
+    return res
+
+
+def bench_batched(args) -> dict:
+    """64 uneven problems (N_i log-uniform in [20k, 500k], D=96 unit rows,
+    M=12, Ks=256, 20 rounds on all rows of each, then encode + error), fitted
+    together: one launch per phase, autotuned plan, HIP graphs."""
+    import numpy as np
+    import torch
+
+    import paper_2604_21645_amd as mipq
+    from paper_2604_21645_amd import _lib
+    from synth import workloads as wl
+
+    dev = torch.device("cuda:0")
+    log("generating batched_uneven")
+    w = wl.batched_uneven()
+    sizes = [p.x.shape[0] for p in w.problems]
+    total = int(sum(sizes))
+    d = w.problems[0].x.shape[1]
+    allx = torch.from_numpy(np.concatenate([p.x for p in w.problems])).to(dev)
+    xs = list(torch.split(allx, sizes))
+    inits = [torch.from_numpy(p.init_rows).to(dev) for p in w.problems]
+    torch.cuda.synchronize()
+    log("plan: autotune + graph capture")
+    t0 = time.perf_counter()
+    b = mipq.BatchedFit(xs, inits, w.m, w.ks, w.iters, plan=True, autotune=True, graph=True)
+    plan_s = time.perf_counter() - t0
+    info = b.info()
+    log("plan", info, "%.2fs" % plan_s)
+    log("%d warmup + %d timed steps" % (args.warmup, args.steps))
+    ms, _ = timed_steps(lambda: b.run(), args.steps, args.warmup)
+    resc = b.run(rescored=True)
+    torch.cuda.synchronize()
+    rmse = np.array([r["sse_rmse"][1].item() for r in b.results])
+
+    log("profiled eager run (same kernels, no graphs)")
+    L = _lib.lib()
+    pe = mipq.BatchedFit(xs, inits, w.m, w.ks, w.iters, plan=True, autotune=True, graph=False)
+    pe.run()
+    torch.cuda.synchronize()
+    drop_profile(L)
+    L.mipq_profile_enable(1)
+    pe.run()
+    torch.cuda.synchronize()
+    L.mipq_profile_enable(0)
+    kt = kernel_totals(L, ["assign_bf16_batched", "update", "finalize", "pack_bf16", "decode"])
+    nl, tot = kt["assign_bf16_batched"]
+    alg = total * (4 * d + w.m)
+    avg = tot / max(nl, 1)
+    achieved = alg / (avg * 1e-3) / 1e9
+    same = all(torch.equal(r0["codes"], r1["codes"]) for r0, r1 in zip(b.results, pe.results))
+    pe.close()
+
+    base = None
+    if not args.no_cpu_baseline:
+        from oracle import pq
+        n_s = min(args.batched_cpu_rows, sizes[0])
+        xs0 = w.problems[0].x[:n_s]
+        init = wl.init_rows_per_subspace(w.meta["seed"], n_s, w.m, w.ks, key=99)
+        log("oracle leg: fit + encode of %d rows of problem 0" % n_s)
+        t1 = time.perf_counter()
+        fit = pq.lloyd(xs0, init, w.m, w.iters, decide="fp32")
+        pq.encode(xs0, fit["codebook"], decide="fp32")
+        t2 = time.perf_counter()
+        base = {"value": n_s / (t2 - t1), "unit": "vectors/s", "cores": 1, "host_cpus": os.cpu_count(),
+                "kind": "oracle",
+                "sample": "%d rows of problem 0 fitted %d rounds and encoded (float32 decisions, numpy single "
+                          "thread, %.1fs)" % (n_s, w.iters, t2 - t1)}
+    b.close()
+    rec = base_record("PQ fit+encode vectors/s, 64 uneven problems batched (BF16-MFMA)", total / (ms * 1e-3),
+                      "vectors/s", args.steps, args.warmup, ms, "bf16",
+                      {"workload": "batched_uneven: 64 problems, N_i log-uniform in [20k, 500k] (%d rows in total), "
+                                   "D=96 unit-norm rows, M=12, Ks=256, 20 Lloyd rounds on all rows of each problem, "
+                                   "encode + RMSE per problem" % total,
+                       "problems": len(sizes), "rows": total, "d": d, "m": w.m, "ks": w.ks, "iters": w.iters,
+                       "precision": "bf16", "parallelism": "single GPU"})
+    rec.update({
+        "plan": dict(info, seconds=plan_s),
+        "rescored_pairs_final_encode": int(resc.item()),
+        "graph_and_eager_codes_identical": bool(same),
+        "rmse_mean": float(rmse.mean()),
+        "roofline": {"bound": "hbm", "kernel": "k_assign_bf16_batched", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "alg_bytes_per_launch": alg, "avg_launch_ms": avg, "launches": nl},
+        "kernels_ms_per_step": {k: v[1] for k, v in kt.items()},
+        "cpu_baseline": base,
+    })
+    return rec
+
+
+def bench_ivf(args) -> dict:
+    """10M x 128 rows, coarse Kc=4096 (20 rounds on a 262,144-row sample),
+    residual PQ M=16 Ks=256, stable bucketing; 10k queries, nprobe 32, top-100."""
+    import numpy as np
+    import torch
+
+    import paper_2604_21645_amd as mipq
+    from paper_2604_21645_amd import _lib
+    from synth import workloads as wl
+
+    dev = torch.device("cuda:0")
+    log("generating ivf_adc")
+    w = wl.ivf_adc()
+    n, d = w.x.shape
+    nq = w.queries.shape[0]
+    x = torch.from_numpy(w.x).to(dev)
+    q = torch.from_numpy(w.queries).to(dev)
+    tr = torch.from_numpy(w.coarse_train).to(dev)
+    ci = torch.from_numpy(w.coarse_init).to(dev)
+    pi = torch.from_numpy(w.pq_init).to(dev)
+    torch.cuda.synchronize()
+
+    def build():
+        return mipq.ii_build(x, w.kc, w.coarse_iters, tr, ci, w.m, w.ks, w.pq_iters, pi, labels=False)
+
+    log("index build: 1 warmup + %d timed" % args.build_steps)
+    build_ms, idx = timed_steps(build, args.build_steps, 1)
+    log("build %.1f ms; search: %d warmup + %d timed" % (build_ms, args.warmup, args.steps))
+    ms, (ids, dist) = timed_steps(lambda: mipq.adc_search(q, idx, w.nprobe, w.topk), args.steps, args.warmup)
+
+    log("profiled legs: coarse assignment of all rows, one build, one search")
+    L = _lib.lib()
+    drop_profile(L)
+    L.mipq_profile_enable(1)
+    for _ in range(3):
+        mipq.coarse_assign(x, idx["coarse"], "bf16")
+    torch.cuda.synchronize()
+    ca = kernel_totals(L, ["coarse_assign"])["coarse_assign"]
+    build()
+    torch.cuda.synchronize()
+    kb = kernel_totals(L, ["coarse_pack", "coarse_assign", "sort", "coarse_update", "assign_bf16", "update",
+                           "finalize", "pack_bf16"])
+    mipq.adc_search(q, idx, w.nprobe, w.topk)
+    torch.cuda.synchronize()
+    ka = kernel_totals(L, ["adc"])
+    L.mipq_profile_enable(0)
+    flops = 2.0 * n * d * w.kc
+    avg = ca[1] / max(ca[0], 1)
+    achieved = flops / (avg * 1e-3) / 1e12
+
+    base, parity = None, None
+    if not args.no_cpu_baseline:
+        from oracle import ivf
+        k = min(args.ivf_cpu_queries, nq)
+        log("oracle leg: ADC search of %d queries on the GPU-built index" % k)
+        cc = idx["coarse"].cpu().numpy()
+        pqc = idx["pq_codebook"].cpu().numpy()
+        off = idx["offsets"].cpu().numpy()
+        idn = idx["ids"].cpu().numpy().astype(np.int64)
+        cs = idx["codes_sorted"].cpu().numpy()
+        cbi = np.empty_like(cs)
+        cbi[idn] = cs
+        t1 = time.perf_counter()
+        ri, rd = ivf.adc_search(w.queries[:k], cc, pqc, off, idn, cbi, w.nprobe, w.topk, decide="kernel")
+        t2 = time.perf_counter()
+        base = {"value": k / (t2 - t1), "unit": "queries/s", "cores": 1, "host_cpus": os.cpu_count(),
+                "kind": "oracle",
+                "sample": "ADC top-%d of the first %d queries (nprobe %d) on the GPU-built index, float32 table "
+                          "arithmetic, numpy single thread, %.1fs" % (w.topk, k, w.nprobe, t2 - t1)}
+        gi = ids.cpu().numpy()[:k].astype(np.int64)
+        parity = {"queries": k, "top100_identical_pct": 100.0 * float(np.all(gi == ri, axis=1).mean()),
+                  "distances_identical": bool(np.array_equal(dist.cpu().numpy()[:k], rd.astype(np.float32)))}
+    rec = base_record("ADC top-100 queries/s on a 10M-row IVF-PQ index (nprobe 32)", nq / (ms * 1e-3), "queries/s",
+                      args.steps, args.warmup, ms, "f32",
+                      {"workload": "ivf_adc: 10M x 128 rows (4,096-component mixture), coarse Kc=4096 fitted 20 "
+                                   "rounds on 262,144 sampled rows, residual PQ M=16 Ks=256 (20 rounds), stable "
+                                   "bucketing; 10,000 queries, nprobe 32, top-100",
+                       "n": n, "d": d, "kc": w.kc, "m": w.m, "ks": w.ks, "nq": nq, "nprobe": w.nprobe,
+                       "topk": w.topk, "precision": "bf16 ranking, exact float32/float64 decisions",
+                       "parallelism": "single GPU"})
+    rec.update({
+        "build_ms": build_ms,
+        "build_vectors_per_s": n / (build_ms * 1e-3),
+        "oracle_parity": parity,
+        "roofline": {"bound": "mfma", "kernel": "k_coarse_assign_mfma", "achieved": achieved, "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": achieved / 2500.0, "traffic": None,
+                     "alg_flops_per_launch": flops, "avg_launch_ms": avg, "launches": ca[0],
+                     "note": "coarse assignment of all 10M rows against Kc=4096 (2*N*D*Kc flops per launch)"},
+        "build_kernels_ms": {k2: v[1] for k2, v in kb.items() if v[0]},
+        "search_kernels_ms": {k2: v[1] for k2, v in ka.items()},
+        "cpu_baseline": base,
+    })
+    return rec
+
+
+def bench_diff(args) -> dict:
+    """2M x 256 rows, M=32, Ks=256 codebooks (fitted once, 20 rounds on a
+    200k sample, BF16): one step = BF16 encode of all rows + reconstruction
+    loss + backward to the codebooks and the inputs."""
+    import numpy as np
+    import torch
+
+    import paper_2604_21645_amd as mipq
+    from paper_2604_21645_amd import _lib
+    from synth import workloads as wl
+
+    dev = torch.device("cuda:0")
+    log("generating diff_codebooks")
+    w = wl.diff_codebooks()
+    n, d = w.x.shape
+    x0 = torch.from_numpy(w.x).to(dev)
+    fit = mipq.pq_fit(x0, w.m, w.ks, w.iters, init_rows=torch.from_numpy(w.init_rows).to(dev),
+                      train_rows=torch.from_numpy(w.train_rows).to(dev), precision="bf16", labels=False)
+    xr = x0.clone().requires_grad_(True)
+    cb = fit["codebook"].clone().requires_grad_(True)
+    torch.cuda.synchronize()
+
+    def step():
+        xr.grad = None
+        cb.grad = None
+        codes = mipq.pq_encode(xr.detach(), cb.detach(), "bf16")
+        loss = mipq.PQReconLoss.apply(xr, cb, codes)
+        loss.backward()
+        return loss
+
+    log("%d warmup + %d timed steps" % (args.warmup, args.steps))
+    ms, loss = timed_steps(step, args.steps, args.warmup)
+    L = _lib.lib()
+    drop_profile(L)
+    L.mipq_profile_enable(1)
+    step()
+    torch.cuda.synchronize()
+    L.mipq_profile_enable(0)
+    kt = kernel_totals(L, ["assign_bf16", "pack_bf16", "decode", "backward"])
+    nl, tot = kt["backward"]
+    alg = n * (8 * d + w.m)
+    avg = tot / max(nl, 1)
+    achieved = alg / (avg * 1e-3) / 1e9
+
+    base = None
+    if not args.no_cpu_baseline:
+        from oracle import grad, pq
+        k = min(args.diff_cpu_rows, n)
+        log("oracle leg: encode + loss + gradients of %d rows" % k)
+        cbn = cb.detach().cpu().numpy().astype(np.float64)
+        t1 = time.perf_counter()
+        codes_o, _ = pq.encode(w.x[:k], cbn, decide="fp32")
+        grad.grads(w.x[:k], codes_o, cbn)
+        t2 = time.perf_counter()
+        base = {"value": k / (t2 - t1), "unit": "vectors/s", "cores": 1, "host_cpus": os.cpu_count(),
+                "kind": "oracle",
+                "sample": "encode (float32 decisions) + float64 loss and gradients of the first %d rows, numpy "
+                          "single thread, %.1fs" % (k, t2 - t1)}
+    rec = base_record("Reconstruction-loss forward+backward vectors/s (BF16 encode, fixed codes)", n / (ms * 1e-3),
+                      "vectors/s", args.steps, args.warmup, ms, "bf16",
+                      {"workload": "diff_codebooks: 2M x 256 rows (8,192-component mixture), M=32, Ks=256 codebooks "
+                                   "fitted once (20 rounds on 200k rows); step = BF16 encode of all rows + float64 "
+                                   "loss + dL/dx and dL/dC",
+                       "n": n, "d": d, "m": w.m, "ks": w.ks, "precision": "bf16 encode, float64 loss/sums",
+                       "parallelism": "single GPU"})
+    rec.update({
+        "loss": float(loss.item()),
+        "roofline": {"bound": "hbm", "kernel": "k_accumulate<grad_x> (backward)", "achieved": achieved,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "alg_bytes_per_launch": alg, "avg_launch_ms": avg, "launches": nl},
+        "kernels_ms_per_step": {k2: v[1] for k2, v in kt.items()},
+        "cpu_baseline": base,
+    })
+    return rec
+
+
+WORKLOADS = {"integer_pq": bench_integer_pq, "batched_uneven": bench_batched, "ivf_adc": bench_ivf,
+             "diff_codebooks": bench_diff}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="integer_pq", choices=sorted(WORKLOADS))
+    ap.add_argument("--fp32-steps", type=int, default=3)
+    ap.add_argument("--build-steps", type=int, default=2, help="ivf_adc: timed index builds")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-frac", type=float, default=0.02)
+    ap.add_argument("--batched-cpu-rows", type=int, default=8000)
+    ap.add_argument("--ivf-cpu-queries", type=int, default=100)
+    ap.add_argument("--diff-cpu-rows", type=int, default=20000)
+    ap.add_argument("--oracle-sample", type=int, default=20000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (reference for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the PQ hot path runs on a single "
+              "MI355X); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        return 2
+    import torch
+    torch.cuda.set_device(0)
+    rec = WORKLOADS[args.workload](args)
+    print(json.dumps(rec), flush=True)
     return 0
 
 
 if __name__ == "__main__":
     sys.exit(main())
+
