@@ -421,7 +421,7 @@ def bench_ivf(args) -> dict:
     drop_profile(L)
     L.mipq_profile_enable(1)
     for _ in range(3):
-        mipq.coarse_assign(x, idx["coarse"], "bf16")
+        _, ca_resc = mipq.coarse_assign(x, idx["coarse"], "bf16", rescored=True)
     torch.cuda.synchronize()
     ca = kernel_totals(L, ["coarse_assign"])["coarse_assign"]
     build()
@@ -474,6 +474,7 @@ def bench_ivf(args) -> dict:
                      "unit": "TFLOP/s", "frac": achieved / 2500.0, "traffic": None,
                      "alg_flops_per_launch": flops, "avg_launch_ms": avg, "launches": ca[0],
                      "note": "coarse assignment of all 10M rows against Kc=4096 (2*N*D*Kc flops per launch)"},
+        "coarse_rows_rescored": int(ca_resc.item()),
         "build_kernels_ms": {k2: v[1] for k2, v in kb.items() if v[0]},
         "search_kernels_ms": {k2: v[1] for k2, v in ka.items()},
         "cpu_baseline": base,

@@ -36,6 +36,9 @@ EXTRA = {
     # min/max of matrix-core scores need no NaN quieting: inputs are finite
     # and matrix-core results go straight to VGPRs (no accumulator reads)
     "pq_mfma.hip": ["-fno-honor-nans", "-mno-amdgpu-ieee", "-mllvm", "-amdgpu-mfma-vgpr-form"],
+    # matrix-core results straight to VGPRs
+    "ivf.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "adc.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
 }
 
 

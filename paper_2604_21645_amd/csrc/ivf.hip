@@ -183,98 +183,219 @@ __global__ __launch_bounds__(kT) void k_coarse_assign_exact(const float* __restr
 }
 
 // ---------------------------------------------------------------- MFMA assign
-// One wave = 32 rows; lane l holds row l%32 and the dimensions 16s + 8h .. +7
-// (h = l/32) of every K-step s.  For each 32-centroid tile the wave runs S+1
-// MFMAs; lane l receives 16 distance estimates of its row (centroids
-// 8(r/4) + 4h + r%4 of the tile) and keeps its best two and the best index.
-template <int S>
+// One wave = RG groups of 32 rows; lane l holds row l%32 of each group and the
+// dimensions 16s + 8h .. +7 (h = l/32) of every K-step s.  For each
+// 32-centroid tile the wave loads the tile's S+1 operands once and runs S+1
+// MFMAs per row group; lane l receives 16 distance estimates of its row
+// (centroids 8(r/4) + 4h + r%4 of the tile) and keeps its best two and the
+// best index.
+//
+// A row whose best two estimates are not separated by the proven bound is
+// ambiguous.  The wave then recomputes the estimates of its row groups that
+// hold ambiguous rows, collects every (row, centroid) whose estimate is within
+// the bound of the row's best (the exact winner is always among them) in an
+// LDS list, and decides each such row by the exact rule over its candidates
+// only.  Rows whose candidates do not fit the list are decided by the exact
+// rule over all centroids.
+constexpr int kCandCap = 256;   // candidate pairs per wave
+
+template <int S, int RG>
 __global__ __launch_bounds__(kT) void k_coarse_assign_mfma(
     const float* __restrict__ x, int64_t n, int d, int kc, const bf16x8* __restrict__ aop,
     const float* __restrict__ mu, const unsigned int* __restrict__ cmax_bits, const float* __restrict__ cc,
     int32_t* __restrict__ labels, unsigned long long* __restrict__ rescored, float e_cross, float e_norm,
     float g_exact) {
   constexpr int NK = S + 1;
+  __shared__ uint32_t cand_rk_all[kT / 64][kCandCap];   // (row in wave) << 16 | centroid
+  __shared__ double cand_d_all[kT / 64][kCandCap];
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
-  const int64_t r0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 32;
+  const int w = threadIdx.x >> 6;
+  const int64_t r0 = ((int64_t)blockIdx.x * (kT / 64) + w) * (32 * RG);
   if (r0 >= n) return;
-  const int64_t row = r0 + (lane & 31);
-  const bool valid = row < n;
-  const float* xr = x + (valid ? row : r0) * d;
+  uint32_t* cand_rk = cand_rk_all[w];
+  double* cand_d = cand_d_all[w];
   const float cm = __uint_as_float(*cmax_bits);
 
-  // row operands (centred), and this lane's part of ||x - mu||^2
-  bf16x8 B[NK];
-  float xn_part = 0.0f;
+  // row operands (centred), ||x - mu||^2
+  bf16x8 B[RG][NK];
+  float xn[RG];
 #pragma unroll
-  for (int s = 0; s < S; ++s) {
-    float v[8];
+  for (int g = 0; g < RG; ++g) {
+    const int64_t row = r0 + 32 * g + (lane & 31);
+    const float* xr = x + (row < n ? row : r0) * d;
+    float xn_part = 0.0f;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int dim = 16 * s + 8 * h + e;
-      const float xv = xr[dim < d ? dim : d - 1];
-      v[e] = dim < d ? xv - mu[dim] : 0.0f;
-      xn_part = xn_part + v[e] * v[e];
+    for (int s = 0; s < S; ++s) {
+      float v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int dim = 16 * s + 8 * h + e;
+        const float xv = xr[dim < d ? dim : d - 1];
+        v[e] = dim < d ? xv - mu[dim] : 0.0f;
+        xn_part = xn_part + v[e] * v[e];
+      }
+      B[g][s] = to_bf16x8(v);
     }
-    B[s] = to_bf16x8(v);
-  }
-  const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_int(xn_part), __float_as_int(xn_part), false, false);
-  const float xn = __int_as_float((int)sw[0]) + __int_as_float((int)sw[1]);
-  {
+    const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_int(xn_part), __float_as_int(xn_part), false, false);
+    xn[g] = __int_as_float((int)sw[0]) + __int_as_float((int)sw[1]);
     bf16x8 nb = {};
     if (h == 0) {
-      const __bf16 hb = (__bf16)xn;
-      const float r1 = xn - (float)hb;
+      const __bf16 hb = (__bf16)xn[g];
+      const float r1 = xn[g] - (float)hb;
       const __bf16 mb = (__bf16)r1;
       nb[0] = nb[1] = nb[2] = (__bf16)1.0f;
       nb[3] = hb;
       nb[4] = mb;
       nb[5] = (__bf16)(r1 - (float)mb);
     }
-    B[S] = nb;
+    B[g][S] = nb;
   }
 
-  float v1 = INFINITY, v2 = INFINITY;
-  int i1 = 0;
+  float v1[RG], v2[RG];
+  int i1[RG];
+#pragma unroll
+  for (int g = 0; g < RG; ++g) {
+    v1[g] = INFINITY;
+    v2[g] = INFINITY;
+    i1[g] = 0;
+  }
   const int nt = (kc + 31) / 32;
   for (int t = 0; t < nt; ++t) {
-    f32x16 acc = {};
+    bf16x8 A[NK];
 #pragma unroll
-    for (int s = 0; s < NK; ++s)
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aop[((size_t)t * NK + s) * 64 + lane], B[s], acc, 0, 0, 0);
+    for (int s = 0; s < NK; ++s) A[s] = aop[((size_t)t * NK + s) * 64 + lane];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const float v = acc[r];
-      const int k = t * 32 + (r >> 2) * 8 + h * 4 + (r & 3);
-      v2 = fminf(v2, fmaxf(v1, v));   // runner-up of {v1, v2, v}, v1 <= v2
-      const bool lt = v < v1;
-      i1 = lt ? k : i1;
-      v1 = lt ? v : v1;
+    for (int g = 0; g < RG; ++g) {
+      f32x16 acc = {};
+#pragma unroll
+      for (int s = 0; s < NK; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s], B[g][s], acc, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float v = acc[r];
+        const int k = t * 32 + (r >> 2) * 8 + h * 4 + (r & 3);
+        v2[g] = fminf(v2[g], fmaxf(v1[g], v));   // runner-up of {v1, v2, v}, v1 <= v2
+        const bool lt = v < v1[g];
+        i1[g] = lt ? k : i1[g];
+        v1[g] = lt ? v : v1[g];
+      }
     }
   }
-  // merge the two lanes of each row
-  const auto a = __builtin_amdgcn_permlane32_swap(__float_as_int(v1), __float_as_int(v1), false, false);
-  const auto b = __builtin_amdgcn_permlane32_swap(__float_as_int(v2), __float_as_int(v2), false, false);
-  const auto c = __builtin_amdgcn_permlane32_swap(i1, i1, false, false);
-  const float v1l = __int_as_float((int)a[0]), v1h = __int_as_float((int)a[1]);
-  const float v2l = __int_as_float((int)b[0]), v2h = __int_as_float((int)b[1]);
-  const int i1l = (int)c[0], i1h = (int)c[1];
-  const bool hiw = (v1h < v1l) || (v1h == v1l && i1h < i1l);
-  const float f1 = fminf(v1l, v1h);
-  const float f2 = fminf(fmaxf(v1l, v1h), fminf(v2l, v2h));
-  const int code = hiw ? i1h : i1l;
-  const float beta = e_cross * sqrtf(xn) * 1.0001f * cm + e_norm * (cm * cm + xn);
-  const float gap = f2 - f1;
-  const float thr = 2.0f * beta + g_exact * (fabsf(f1) + fabsf(f2) + 2.0f * beta + 2.0f * xn * g_exact);
-  const bool amb = !(gap > thr) || code >= kc;
-  if (h == 0 && valid) labels[row] = code;
-  uint64_t mask = __ballot((h == 0) && valid && amb);
-  if (rescored && lane == 0 && mask) atomicAdd(rescored, (unsigned long long)__popcll(mask));
-  while (mask) {   // wave-uniform
-    const int l = __ffsll((unsigned long long)mask) - 1;
-    mask &= mask - 1;
-    const int ec = coarse_exact_wave(x + (r0 + l) * d, cc, kc, d, lane);
-    if (lane == 0) labels[r0 + l] = ec;
+
+  // merge the two lanes of each row; separation test
+  float f1[RG], beta[RG];
+  bool amb[RG];
+  uint64_t any_amb = 0;
+#pragma unroll
+  for (int g = 0; g < RG; ++g) {
+    const auto a = __builtin_amdgcn_permlane32_swap(__float_as_int(v1[g]), __float_as_int(v1[g]), false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(__float_as_int(v2[g]), __float_as_int(v2[g]), false, false);
+    const auto c = __builtin_amdgcn_permlane32_swap(i1[g], i1[g], false, false);
+    const float v1l = __int_as_float((int)a[0]), v1h = __int_as_float((int)a[1]);
+    const float v2l = __int_as_float((int)b[0]), v2h = __int_as_float((int)b[1]);
+    const int i1l = (int)c[0], i1h = (int)c[1];
+    const bool hiw = (v1h < v1l) || (v1h == v1l && i1h < i1l);
+    f1[g] = fminf(v1l, v1h);
+    const float f2 = fminf(fmaxf(v1l, v1h), fminf(v2l, v2h));
+    const int code = hiw ? i1h : i1l;
+    beta[g] = e_cross * sqrtf(xn[g]) * 1.0001f * cm + e_norm * (cm * cm + xn[g]);
+    const float gap = f2 - f1[g];
+    const float thr = 2.0f * beta[g] + g_exact * (fabsf(f1[g]) + fabsf(f2) + 2.0f * beta[g] + 2.0f * xn[g] * g_exact);
+    const int64_t row = r0 + 32 * g + (lane & 31);
+    const bool valid = row < n;
+    amb[g] = valid && (!(gap > thr) || code >= kc);
+    if (h == 0 && valid) labels[row] = code;
+    any_amb |= __ballot(h == 0 && amb[g]);
+    if (rescored && lane == 0) {
+      const int c2 = __popcll(__ballot(h == 0 && amb[g]));
+      if (c2) atomicAdd(rescored, (unsigned long long)c2);
+    }
+  }
+  if (!any_amb) return;
+
+  // candidates of the ambiguous rows: est_k - f1 within the bound
+  int nc = 0;
+  bool ovf[RG];
+#pragma unroll
+  for (int g = 0; g < RG; ++g) ovf[g] = false;
+  uint64_t gmask = 0;
+#pragma unroll
+  for (int g = 0; g < RG; ++g)
+    if (__ballot(amb[g])) gmask |= 1ull << g;
+  for (int t = 0; t < nt; ++t) {
+    bf16x8 A[NK];
+#pragma unroll
+    for (int s = 0; s < NK; ++s) A[s] = aop[((size_t)t * NK + s) * 64 + lane];
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+      if (!((gmask >> g) & 1)) continue;   // wave-uniform
+      f32x16 acc = {};
+#pragma unroll
+      for (int s = 0; s < NK; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s], B[g][s], acc, 0, 0, 0);
+      uint32_t mine = 0;   // bit r: candidate in accumulator register r
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float v = acc[r];
+        const int k = t * 32 + (r >> 2) * 8 + h * 4 + (r & 3);
+        const float lim = 2.0f * beta[g] + g_exact * (fabsf(f1[g]) + fabsf(v) + 2.0f * beta[g] +
+                                                      2.0f * xn[g] * g_exact);
+        const bool cand = amb[g] && k < kc && !(v - f1[g] > lim);
+        mine |= cand ? (1u << r) : 0u;
+      }
+      if (!__ballot(mine != 0)) continue;
+      const uint32_t rl = (uint32_t)(32 * g + (lane & 31)) << 16;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const bool cand = (mine >> r) & 1u;
+        const uint64_t m = __ballot(cand);
+        if (!m) continue;
+        if (cand) {
+          const int pos = nc + __popcll(m & ((1ull << lane) - 1ull));
+          const int k = t * 32 + (r >> 2) * 8 + h * 4 + (r & 3);
+          if (pos < kCandCap) cand_rk[pos] = rl | (uint32_t)k;
+          else ovf[g] = true;
+        }
+        nc += __popcll(m);
+      }
+    }
+  }
+  const int ncl = nc < kCandCap ? nc : kCandCap;
+  __builtin_amdgcn_wave_barrier();
+  for (int i = lane; i < ncl; i += 64) {
+    const uint32_t rk = cand_rk[i];
+    const int64_t row = r0 + (rk >> 16);
+    cand_d[i] = coarse_exact_dist(x + row * d, cc + (int64_t)(rk & 0xFFFFu) * d, d);
+  }
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int g = 0; g < RG; ++g) {
+    // a row overflowed when either of its two lanes dropped a candidate
+    const uint64_t ob = __ballot(ovf[g]);
+    const uint32_t rows_full = (uint32_t)(ob | (ob >> 32));
+    const int64_t row = r0 + 32 * g + (lane & 31);
+    if (h == 0 && amb[g] && !((rows_full >> (lane & 31)) & 1u)) {
+      const uint32_t rl = (uint32_t)(32 * g + (lane & 31));
+      double best = INFINITY;
+      int bk = 0x7FFFFFFF;
+      for (int i = 0; i < ncl; ++i) {
+        const uint32_t rk = cand_rk[i];
+        if ((rk >> 16) != rl) continue;
+        const double dv = cand_d[i];
+        const int k = (int)(rk & 0xFFFFu);
+        if (dv < best || (dv == best && k < bk)) {
+          best = dv;
+          bk = k;
+        }
+      }
+      labels[row] = bk;
+    }
+    uint32_t fm = rows_full & (uint32_t)__ballot(h == 0 && amb[g]);
+    while (fm) {   // wave-uniform
+      const int l = __ffs(fm) - 1;
+      fm &= fm - 1;
+      const int ec = coarse_exact_wave(x + (r0 + 32 * g + l) * d, cc, kc, d, lane);
+      if (lane == 0) labels[r0 + 32 * g + l] = ec;
+    }
   }
 }
 
@@ -512,11 +633,16 @@ int launch_coarse_assign(const float* x, int64_t n, int d, const float* cc, int 
   const float e_cross = 0.0165f;
   const float e_norm = 16.0f * (S + 1) * 1.2e-7f + 2.4e-7f;
   const float g_exact = 1.3e-7f;
-  const int blocks = ceil_div((n + 31) / 32, kT / 64);
   unsigned long long* resc = reinterpret_cast<unsigned long long*>(rescored);
-#define CA(SV)                                                                                               \
-  k_coarse_assign_mfma<SV><<<blocks, kT, 0, s>>>(x, n, d, kc, (const bf16x8*)aop, mu, cmax_bits, cc, labels, \
-                                                 resc, e_cross, e_norm, g_exact)
+  // two row groups per wave (operands loaded once per tile for 64 rows) while
+  // the row operands fit the registers
+#define CA(SV)                                                                                                  \
+  do {                                                                                                          \
+    constexpr int RGV = SV <= 8 ? 2 : 1;                                                                        \
+    const int blocks = ceil_div((n + 32 * RGV - 1) / (32 * RGV), kT / 64);                                      \
+    k_coarse_assign_mfma<SV, RGV><<<blocks, kT, 0, s>>>(x, n, d, kc, (const bf16x8*)aop, mu, cmax_bits, cc,     \
+                                                        labels, resc, e_cross, e_norm, g_exact);                \
+  } while (0)
   switch (S) {
     case 1: CA(1); break;
     case 2: CA(2); break;

@@ -43,6 +43,21 @@ def test_coarse_assign_duplicate_centroids_are_decided_exactly():
     assert int(resc.item()) > 0
 
 
+def test_coarse_assign_split_clusters_use_the_candidate_path():
+    # every mixture component carries two centroids a hair apart (as k-means
+    # leaves split clusters): most rows have two nearly equal best distances
+    rng = np.random.default_rng(11)
+    means = rng.uniform(0, 1, size=(60, 128))
+    cc = np.concatenate([means + 1e-3 * rng.standard_normal(means.shape),
+                         means + 1e-3 * rng.standard_normal(means.shape)]).astype(np.float32)
+    x = wl.gaussian_mixture(12, 5000, 128, 60, sigma=0.05, means=means)
+    lab, resc = mipq.coarse_assign(_t(x), _t(cc), "bf16", rescored=True)
+    ref, tie = ivf.coarse_assign(x, cc, "kernel")
+    np.testing.assert_array_equal(lab.cpu().numpy().astype(np.int64), ref)
+    print("rescored rows", int(resc.item()), "of", x.shape[0], flush=True)
+    assert int(resc.item()) > 50
+
+
 def _small():
     return wl.ivf_adc(seed=21, n=20000, d=32, n_comp=64, kc=64, n_query=40, m=4, ks=16, coarse_iters=5,
                       pq_iters=5, n_train=4000, nprobe=6, topk=25)
