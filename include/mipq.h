@@ -253,7 +253,7 @@ int mipq_ii_build(const float* x, int64_t n, int d, int kc, int coarse_iters, co
  * Requirements: 1 <= nprobe <= min(kc, 256), 1 <= topk <= 1024, d/m in
  * {1, 2, 4, 8, 16}, d <= 16 or d in {32, 64, 96, 128, 192, 256}.
  * ------------------------------------------------------------------------- */
-size_t mipq_adc_search_workspace_size(int nq, int d, int kc, int nprobe);
+size_t mipq_adc_search_workspace_size(int nq, int d, int kc, int nprobe, int topk);
 int mipq_adc_search(const float* q, int nq, int d, const float* coarse, int kc, const float* pq_codebook,
                     int m, int ks, const int64_t* offsets, const int32_t* ids, const uint8_t* codes_sorted,
                     int nprobe, int topk, int32_t* out_ids, float* out_dist, int64_t* wide, void* ws,

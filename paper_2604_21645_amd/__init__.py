@@ -243,7 +243,7 @@ def adc_search(q: torch.Tensor, index: dict, nprobe: int, topk: int, wide: bool 
     out_ids = torch.empty((nq, topk), dtype=torch.int32, device=dev)
     out_d = torch.empty((nq, topk), dtype=torch.float32, device=dev)
     w = torch.zeros(1, dtype=torch.int64, device=dev) if wide else None
-    ws = _ws(L.mipq_adc_search_workspace_size(nq, d, kc, nprobe), dev)
+    ws = _ws(L.mipq_adc_search_workspace_size(nq, d, kc, nprobe, topk), dev)
     check(L.mipq_adc_search(_ptr(q), nq, d, _ptr(cc), kc, _ptr(pqc), m, ks, _ptr(off), _ptr(ids), _ptr(codes),
                             nprobe, topk, _ptr(out_ids), _ptr(out_d), _ptr(w), _ptr(ws), ws.numel(), _stream(dev)))
     return (out_ids, out_d, w) if wide else (out_ids, out_d)

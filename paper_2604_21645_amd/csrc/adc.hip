@@ -9,11 +9,13 @@
 //    top-nprobe list has an estimate <= T + 2 beta, T the nprobe-th smallest
 //    estimate; exactly those candidates are re-scored with the exact rule and
 //    sorted.
-// 3. k_adc_scan: per query and probed list l, the table
+// 3. k_adc_scan: one block per (query, probed list l): the table
 //    LUT[j][k] = subspace-j distance of (q - c_l) to C_j[k] (float32 rule),
 //    then s = sum over j ascending of LUT[j][code_j] (float32) for every row
-//    of the list; the topk smallest (s, id) pairs, kept with a threshold and
-//    an LDS candidate buffer, sorted at the end.
+//    of the list; the list's topk smallest (s, id) pairs, kept with a
+//    threshold and an LDS buffer.  The per-query threshold is shared through
+//    global memory, so lists scanned later prune against earlier ones.
+// 4. k_adc_merge: per query, the topk smallest of its lists' candidates.
 #include <math.h>
 
 #include "bf16_pack.h"
@@ -258,7 +260,7 @@ __global__ __launch_bounds__(kT) void k_adc_probe(const float* __restrict__ q, i
   for (int i = threadIdx.x; i < nprobe; i += blockDim.x) probes[(int64_t)qi * nprobe + i] = i < nb ? band[i].l : -1;
 }
 
-constexpr int kCap = 2048;   // LDS candidate buffer (uint64 keys)
+constexpr int kBatch = kT;   // keys inserted per block step (one per thread)
 
 __device__ void sort_keys(uint64_t* buf, int n2) {
   for (int kk = 2; kk <= n2; kk <<= 1)
@@ -278,90 +280,187 @@ __device__ void sort_keys(uint64_t* buf, int n2) {
     }
 }
 
-// One block per query.  LDS: the table (m*ks floats), the query residual
-// (d floats), and the candidate buffer of (score bits << 32 | id) keys.
-template <int DS>
-__global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, int d, const float* __restrict__ cc,
-                                                 const float* __restrict__ pq, int m, int ks,
-                                                 const int64_t* __restrict__ offsets, const int32_t* __restrict__ ids,
-                                                 const uint8_t* __restrict__ codes, const int32_t* __restrict__ probes,
-                                                 int nprobe, int topk, int32_t* __restrict__ out_ids,
-                                                 float* __restrict__ out_dist) {
-  extern __shared__ float sm[];
-  float* lut = sm;                                   // m*ks
-  float* rq = lut + m * ks;                          // d
-  uint64_t* buf = reinterpret_cast<uint64_t*>(rq + ((d + 1) & ~1));   // kCap
-  __shared__ int cnt;
-  __shared__ uint64_t thresh;
-  const int qi = blockIdx.x;
-  const float* qr = q + (int64_t)qi * d;
+__device__ __forceinline__ uint64_t load_relaxed(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Block-wide top-k collection of unique uint64 keys: a key is kept while it is
+// <= *thr; once the LDS buffer (cap, a power of two) could not take another
+// batch, it is sorted, cut to the best topk and *thr lowered to the topk-th
+// key (and to *ext, a bound shared with other blocks, when given).  Call
+// after a barrier that follows the batch's insertions.
+__device__ __forceinline__ void topk_compact(uint64_t* buf, int cap, int topk, int* cnt, uint64_t* thr,
+                                             const unsigned long long* ext) {
+  if (*cnt <= cap - kBatch) return;   // block-uniform
+  const int c = *cnt < cap ? *cnt : cap;
+  for (int i = c + threadIdx.x; i < cap; i += blockDim.x) buf[i] = ~0ull;
+  __syncthreads();
+  sort_keys(buf, cap);
   if (threadIdx.x == 0) {
-    cnt = 0;
-    thresh = ~0ull;
-  }
-  for (int pi = 0; pi < nprobe; ++pi) {
-    const int l = probes[(int64_t)qi * nprobe + pi];
-    if (l < 0) continue;   // block-uniform
-    __syncthreads();
-    for (int t = threadIdx.x; t < d; t += blockDim.x) rq[t] = qr[t] - cc[(int64_t)l * d + t];
-    __syncthreads();
-    for (int e = threadIdx.x; e < m * ks; e += blockDim.x) {
-      const int j = e / ks, k = e - j * ks;
-      lut[e] = sqdist_fixed<DS>(rq + j * DS, pq + ((int64_t)j * ks + k) * DS);
+    const int keep = c < topk ? c : topk;
+    *cnt = keep;
+    uint64_t t = *thr;
+    if (keep == topk && buf[topk - 1] < t) t = buf[topk - 1];
+    if (ext) {
+      const uint64_t e = load_relaxed(ext);
+      if (e < t) t = e;
     }
-    __syncthreads();
-    const int64_t a = offsets[l], b = offsets[l + 1];
-    for (int64_t p0 = a; p0 < b; p0 += blockDim.x) {
-      const int64_t p = p0 + threadIdx.x;
-      if (p < b) {
-        const uint8_t* cr = codes + p * m;
-        float s = lut[cr[0]];
-        for (int j = 1; j < m; ++j) s = s + lut[j * ks + cr[j]];
-        const uint64_t key = ((uint64_t)__float_as_uint(s) << 32) | (uint32_t)ids[p];
-        if (key < thresh) {
-          const int slot = atomicAdd(&cnt, 1);
-          if (slot < kCap) buf[slot] = key;
-        }
-      }
-      __syncthreads();
-      if (cnt > kCap - (int)blockDim.x) {   // compact: keep the best topk, tighten the threshold
-        const int c = cnt < kCap ? cnt : kCap;
-        for (int i = c + threadIdx.x; i < kCap; i += blockDim.x) buf[i] = ~0ull;
-        __syncthreads();
-        sort_keys(buf, kCap);
-        if (threadIdx.x == 0) {
-          const int keep = c < topk ? c : topk;
-          cnt = keep;
-          if (keep == topk) thresh = buf[topk - 1];
-        }
-        __syncthreads();
-      }
-    }
+    *thr = t;
   }
   __syncthreads();
-  const int c = cnt < kCap ? cnt : kCap;
+}
+
+// final sort of the first c keys of buf (padded to a power of two)
+__device__ __forceinline__ void topk_finish(uint64_t* buf, int c) {
   int p2 = 1;
   while (p2 < c) p2 <<= 1;
   for (int i = c + threadIdx.x; i < p2; i += blockDim.x) buf[i] = ~0ull;
   __syncthreads();
   sort_keys(buf, p2);
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Block = (probe slot pi, query qi), probe-major so that every query's nearest
+// lists are scanned first.  LDS: the table (m*ks floats), the query residual
+// (d floats) and the key buffer.  Keys: (score bits << 32 | id); scores are
+// non-negative floats, so integer order is (score, id) order.  The block
+// writes its list's best topk keys (~0 padded) and lowers the query's shared
+// bound qthr to its topk-th key: a row above the topk-th key of any single
+// list cannot be in the query's top topk.
+template <int DS, bool V16>
+__global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, int d, const float* __restrict__ cc,
+                                                 const float* __restrict__ pq, int m, int ks,
+                                                 const int64_t* __restrict__ offsets, const int32_t* __restrict__ ids,
+                                                 const uint8_t* __restrict__ codes, const int32_t* __restrict__ probes,
+                                                 int nq, int nprobe, int topk, int cap,
+                                                 unsigned long long* __restrict__ qthr,
+                                                 uint64_t* __restrict__ pair_out) {
+  extern __shared__ float sm[];
+  float* lut = sm;                                   // m*ks
+  float* rq = lut + m * ks;                          // d
+  uint64_t* buf = reinterpret_cast<uint64_t*>(rq + ((d + 1) & ~1));   // cap
+  __shared__ int cnt;
+  __shared__ uint64_t thr;
+  const int pi = blockIdx.x / nq;
+  const int qi = blockIdx.x - pi * nq;
+  uint64_t* outp = pair_out + ((size_t)qi * nprobe + pi) * topk;
+  const int l = probes[(int64_t)qi * nprobe + pi];
+  if (l < 0) {   // block-uniform
+    for (int i = threadIdx.x; i < topk; i += blockDim.x) outp[i] = ~0ull;
+    return;
+  }
+  const float* qr = q + (int64_t)qi * d;
+  if (threadIdx.x == 0) {
+    cnt = 0;
+    thr = load_relaxed(qthr + qi);
+  }
+  for (int t = threadIdx.x; t < d; t += blockDim.x) rq[t] = qr[t] - cc[(int64_t)l * d + t];
+  __syncthreads();
+  for (int e = threadIdx.x; e < m * ks; e += blockDim.x) {
+    const int j = e / ks, k = e - j * ks;
+    lut[e] = sqdist_fixed<DS>(rq + j * DS, pq + ((int64_t)j * ks + k) * DS);
+  }
+  __syncthreads();
+  const int64_t a = offsets[l], b = offsets[l + 1];
+  for (int64_t p0 = a; p0 < b; p0 += kBatch) {
+    const int64_t p = p0 + threadIdx.x;
+    const uint64_t tl = thr;
+    if (p < b) {
+      float s;
+      if (V16) {   // m % 16 == 0 and aligned rows: 16 codes per load
+        const uint4* cr = reinterpret_cast<const uint4*>(codes + p * m);
+        s = 0.0f;
+        for (int j0 = 0; j0 < m; j0 += 16) {
+          const uint4 v = cr[j0 >> 4];
+          const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int j = j0 + u;
+            const float e = lut[j * ks + ((w4[u >> 2] >> (8 * (u & 3))) & 0xFFu)];
+            s = (j == 0) ? e : s + e;
+          }
+        }
+      } else {
+        const uint8_t* cr = codes + p * m;
+        s = lut[cr[0]];
+        for (int j = 1; j < m; ++j) s = s + lut[j * ks + cr[j]];
+      }
+      const uint64_t key = ((uint64_t)__float_as_uint(s) << 32) | (uint32_t)ids[p];
+      if (key <= tl) {
+        const int slot = atomicAdd(&cnt, 1);
+        buf[slot] = key;   // slot < cap: room for a whole batch is kept free
+      }
+    }
+    __syncthreads();
+    topk_compact(buf, cap, topk, &cnt, &thr, qthr + qi);
+  }
+  const int c = cnt;
+  topk_finish(buf, c);
+  const int keep = c < topk ? c : topk;
+  for (int i = threadIdx.x; i < topk; i += blockDim.x) outp[i] = i < keep ? buf[i] : ~0ull;
+  if (threadIdx.x == 0 && keep == topk) atomicMin(qthr + qi, (unsigned long long)buf[topk - 1]);
+}
+
+// One block per query: the best topk of its lists' candidates (keys <= the
+// query's final bound), ascending; ids -1 and distance +inf past the end.
+__global__ __launch_bounds__(kT) void k_adc_merge(const uint64_t* __restrict__ pair_out, int nprobe, int topk,
+                                                  int cap, const unsigned long long* __restrict__ qthr,
+                                                  int32_t* __restrict__ out_ids, float* __restrict__ out_dist) {
+  extern __shared__ uint64_t mbuf[];
+  __shared__ int cnt;
+  __shared__ uint64_t thr;
+  const int qi = blockIdx.x;
+  if (threadIdx.x == 0) {
+    cnt = 0;
+    thr = qthr[qi];
+  }
+  __syncthreads();
+  const int total = nprobe * topk;
+  const uint64_t* src = pair_out + (size_t)qi * total;
+  for (int i0 = 0; i0 < total; i0 += kBatch) {
+    const int i = i0 + threadIdx.x;
+    const uint64_t tl = thr;
+    const uint64_t key = i < total ? src[i] : ~0ull;
+    if (key != ~0ull && key <= tl) {
+      const int slot = atomicAdd(&cnt, 1);
+      mbuf[slot] = key;
+    }
+    __syncthreads();
+    topk_compact(mbuf, cap, topk, &cnt, &thr, nullptr);
+  }
+  const int c = cnt;
+  topk_finish(mbuf, c);
   for (int i = threadIdx.x; i < topk; i += blockDim.x) {
     const bool real = i < c;
-    out_ids[(int64_t)qi * topk + i] = real ? (int32_t)(uint32_t)(buf[i] & 0xFFFFFFFFull) : -1;
-    out_dist[(int64_t)qi * topk + i] = real ? __uint_as_float((uint32_t)(buf[i] >> 32)) : INFINITY;
+    out_ids[(int64_t)qi * topk + i] = real ? (int32_t)(uint32_t)(mbuf[i] & 0xFFFFFFFFull) : -1;
+    out_dist[(int64_t)qi * topk + i] = real ? __uint_as_float((uint32_t)(mbuf[i] >> 32)) : INFINITY;
   }
 }
 
 }  // namespace
 
-int adc_scan_smem(int d, int m, int ks) {
-  return (int)((size_t)m * ks * sizeof(float) + (size_t)((d + 1) & ~1) * sizeof(float) + kCap * sizeof(uint64_t));
+// key buffer of a scan block / the merge block: a power of two with room for
+// topk kept keys plus one full batch
+int adc_key_cap(int topk) {
+  int c = 512;
+  while (c < topk + kBatch) c <<= 1;
+  return c;
+}
+
+int adc_scan_smem(int d, int m, int ks, int topk) {
+  return (int)((size_t)m * ks * sizeof(float) + (size_t)((d + 1) & ~1) * sizeof(float) +
+               (size_t)adc_key_cap(topk) * sizeof(uint64_t));
 }
 
 int launch_adc(const float* q, int nq, int d, const float* cc, int kc, const void* aop, const float* mu,
                const unsigned int* cmax_bits, const float* pq, int m, int ks, const int64_t* offsets,
                const int32_t* ids, const uint8_t* codes, int nprobe, int topk, float* est, int32_t* probes,
-               int64_t* wide, int32_t* out_ids, float* out_dist, hipStream_t s) {
+               unsigned long long* qthr, uint64_t* pair_out, int64_t* wide, int32_t* out_ids, float* out_dist,
+               hipStream_t s) {
   if (nq == 0) return MIPQ_OK;
   ProfScope ps(MIPQ_K_ADC, s);
   const int S = coarse_ksteps(d);
@@ -388,11 +487,22 @@ int launch_adc(const float* q, int nq, int d, const float* cc, int kc, const voi
   k_adc_probe<<<nq, kT, 0, s>>>(q, d, cc, kc, est, mu, cmax_bits, nprobe, e_cross, e_norm, g_exact, probes,
                                 reinterpret_cast<unsigned long long*>(wide));
   MIPQ_LAUNCHED("k_adc_probe");
+  k_fill_u64<<<ceil_div(nq, kT), kT, 0, s>>>(qthr, nq, ~0ull);
+  MIPQ_LAUNCHED("k_fill_u64");
   const int ds = d / m;
-  const size_t shm = adc_scan_smem(d, m, ks);
-#define SC(DSV)                                                                                      \
-  k_adc_scan<DSV><<<nq, kT, shm, s>>>(q, d, cc, pq, m, ks, offsets, ids, codes, probes, nprobe, topk, \
-                                      out_ids, out_dist)
+  const int cap = adc_key_cap(topk);
+  const size_t shm = adc_scan_smem(d, m, ks, topk);
+  const bool v16 = (m % 16 == 0) && ((reinterpret_cast<uintptr_t>(codes) & 15) == 0);
+  const unsigned sblocks = (unsigned)((int64_t)nq * nprobe);
+#define SC(DSV)                                                                                              \
+  do {                                                                                                       \
+    if (v16)                                                                                                 \
+      k_adc_scan<DSV, true><<<sblocks, kT, shm, s>>>(q, d, cc, pq, m, ks, offsets, ids, codes, probes, nq,   \
+                                                     nprobe, topk, cap, qthr, pair_out);                     \
+    else                                                                                                     \
+      k_adc_scan<DSV, false><<<sblocks, kT, shm, s>>>(q, d, cc, pq, m, ks, offsets, ids, codes, probes, nq,  \
+                                                      nprobe, topk, cap, qthr, pair_out);                    \
+  } while (0)
   switch (ds) {
     case 1: SC(1); break;
     case 2: SC(2); break;
@@ -403,6 +513,8 @@ int launch_adc(const float* q, int nq, int d, const float* cc, int kc, const voi
   }
 #undef SC
   MIPQ_LAUNCHED("k_adc_scan");
+  k_adc_merge<<<nq, kT, (size_t)cap * sizeof(uint64_t), s>>>(pair_out, nprobe, topk, cap, qthr, out_ids, out_dist);
+  MIPQ_LAUNCHED("k_adc_merge");
   return MIPQ_OK;
 }
 

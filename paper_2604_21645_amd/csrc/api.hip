@@ -431,22 +431,26 @@ struct AdcWs {
   CoarseWs cw;
   float* est;
   int32_t* probes;
+  unsigned long long* qthr;
+  uint64_t* pair_out;
   size_t bytes;
 };
-AdcWs carve_adc(void* ws, int nq, int d, int kc, int nprobe) {
+AdcWs carve_adc(void* ws, int nq, int d, int kc, int nprobe, int topk) {
   Carver c(ws);
   AdcWs a;
   a.cw = carve_coarse(c, d, kc, MIPQ_BF16);
   a.est = c.take<float>((size_t)nq * kc);
   a.probes = c.take<int32_t>((size_t)nq * nprobe);
+  a.qthr = c.take<unsigned long long>((size_t)nq);
+  a.pair_out = c.take<uint64_t>((size_t)nq * nprobe * topk);
   a.bytes = c.bytes();
   return a;
 }
 }  // namespace
 
-size_t mipq_adc_search_workspace_size(int nq, int d, int kc, int nprobe) {
-  if (nq < 0 || check_coarse(0, d, kc, MIPQ_BF16) != MIPQ_OK || nprobe < 1) return 0;
-  return carve_adc(nullptr, nq, d, kc, nprobe).bytes;
+size_t mipq_adc_search_workspace_size(int nq, int d, int kc, int nprobe, int topk) {
+  if (nq < 0 || check_coarse(0, d, kc, MIPQ_BF16) != MIPQ_OK || nprobe < 1 || topk < 1 || topk > 1024) return 0;
+  return carve_adc(nullptr, nq, d, kc, nprobe, topk).bytes;
 }
 
 int mipq_adc_search(const float* q, int nq, int d, const float* coarse, int kc, const float* pq_codebook,
@@ -464,14 +468,15 @@ int mipq_adc_search(const float* q, int nq, int d, const float* coarse, int kc, 
   if (topk < 1 || topk > 1024) return fail(MIPQ_EINVAL, "topk must be in [1, 1024]");
   if (nq > 0 && (!q || !coarse || !pq_codebook || !offsets || !ids || !codes_sorted || !out_ids || !out_dist))
     return fail(MIPQ_EINVAL, "a required pointer is NULL");
+  if ((int64_t)nq * nprobe >= (1ll << 31)) return fail(MIPQ_EUNSUPPORTED, "nq * nprobe must be < 2^31");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  AdcWs a = carve_adc(ws, nq, d, kc, nprobe);
+  AdcWs a = carve_adc(ws, nq, d, kc, nprobe, topk);
   if ((rc = check_ws(ws, ws_bytes, a.bytes))) return rc;
   if (wide && (rc = launch_zero_u32(reinterpret_cast<uint32_t*>(wide), 2, s))) return rc;
   if (nq == 0) return MIPQ_OK;
   if ((rc = launch_coarse_prepare(coarse, kc, d, a.cw.mu, a.cw.cmax, a.cw.aop, s))) return rc;
   return launch_adc(q, nq, d, coarse, kc, a.cw.aop, a.cw.mu, a.cw.cmax, pq_codebook, m, ks, offsets, ids,
-                    codes_sorted, nprobe, topk, a.est, a.probes, wide, out_ids, out_dist, s);
+                    codes_sorted, nprobe, topk, a.est, a.probes, a.qthr, a.pair_out, wide, out_ids, out_dist, s);
 }
 
 }  // extern "C"

@@ -147,7 +147,8 @@ int launch_gather_codes(const uint8_t* codes, int64_t n, int m, const int32_t* i
 int launch_adc(const float* q, int nq, int d, const float* cc, int kc, const void* aop, const float* mu,
                const unsigned int* cmax_bits, const float* pq, int m, int ks, const int64_t* offsets,
                const int32_t* ids, const uint8_t* codes, int nprobe, int topk, float* est, int32_t* probes,
-               int64_t* wide, int32_t* out_ids, float* out_dist, hipStream_t s);
+               unsigned long long* qthr, uint64_t* pair_out, int64_t* wide, int32_t* out_ids, float* out_dist,
+               hipStream_t s);
 
 // operands of the centred codebook; mu: m * kMaxDsBf16 floats (subspace centres)
 int launch_pack_bf16(const float* c32, int m, int ks, int ds, void* aop, float* cmax, float* mu,
