@@ -250,6 +250,21 @@ def bench_integer_pq(args) -> dict:
             "rmse": float(sr32[1].item()),
         }
 
+    fp8 = None
+    if args.fp8_steps > 0:
+        log("fp8: 1 warmup + %d timed steps" % args.fp8_steps)
+        ms8, ph8, (cb8, codes8, sr8) = timed("fp8", args.fp8_steps, 1, profile=False)
+        _, resc8 = mipq.pq_encode(x, cb8, "fp8", rescored=True)
+        fp8 = {
+            "vectors_per_s": n / (ms8 * 1e-3),
+            "fit_encode_vectors_per_s": n / ((ph8[0] + ph8[1]) * 1e-3),
+            "ms_per_step": ms8,
+            "codes_identical_to_bf16": bool(torch.equal(codes8, codes)),
+            "codebook_identical_to_bf16": bool(torch.equal(cb8, cb)),
+            "encode_pairs_rescored_pct": 100.0 * float(resc8.item()) / (n * w.m),
+            "rmse": float(sr8[1].item()),
+        }
+
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
@@ -284,6 +299,7 @@ def bench_integer_pq(args) -> dict:
         "phases_ms": {"fit": ph[0], "encode": ph[1], "decode_rmse": ph[2]},
         "fit_encode_vectors_per_s": n / ((ph[0] + ph[1]) * 1e-3),
         "fp32_plain": fp32,
+        "fp8": fp8,
         "rmse": rmse,
         "oracle_parity": parity or None,
         "roofline": {
@@ -575,6 +591,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="integer_pq", choices=sorted(WORKLOADS))
     ap.add_argument("--fp32-steps", type=int, default=3)
+    ap.add_argument("--fp8-steps", type=int, default=3)
     ap.add_argument("--build-steps", type=int, default=2, help="ivf_adc: timed index builds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frac", type=float, default=0.02)

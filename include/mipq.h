@@ -30,7 +30,11 @@
  *              into high and low parts, with float32 accumulation; every
  *              (row, subspace) whose two best candidates are not separated
  *              by a proven error bound is re-decided in MIPQ_FP32 arithmetic.
- * Both give the same codes: the code of a (row, subspace) is the lowest index
+ *   MIPQ_FP8   as MIPQ_BF16 with OCP E4M3 operands (high and low parts) under
+ *              a power-of-two scale per subspace; its wider error bound sends
+ *              more pairs to the exact re-decision.  Not offered for the
+ *              coarse quantiser, the batched fit or the index build.
+ * All give the same codes: the code of a (row, subspace) is the lowest index
  * k minimising the float32 difference-form distance
  *     sum over t ascending of (x_t - c_kt)^2,
  * with every subtraction, square and sum rounded to float32 (no fused
@@ -57,7 +61,7 @@ enum mipq_status {
   MIPQ_EUNSUPPORTED = -4  /* valid request this build does not implement */
 };
 
-enum mipq_precision { MIPQ_FP32 = 0, MIPQ_BF16 = 1 };
+enum mipq_precision { MIPQ_FP32 = 0, MIPQ_BF16 = 1, MIPQ_FP8 = 2 };
 
 /* Version of this header's ABI (MIPQ_ABI_VERSION). */
 int mipq_abi_version(void);
@@ -302,7 +306,9 @@ enum mipq_kernel {
   MIPQ_K_COARSE_UPDATE = 10,/* coarse centroid update */
   MIPQ_K_ADC = 11,          /* ADC search */
   MIPQ_K_ASSIGN_BF16_BATCHED = 12, /* persistent matrix-core assignment, many problems */
-  MIPQ_KERNEL_COUNT = 13
+  MIPQ_K_ASSIGN_FP8 = 13,   /* FP8 matrix-core assignment (with exact re-decision) */
+  MIPQ_K_PACK_FP8 = 14,     /* FP8 centroid operand packing */
+  MIPQ_KERNEL_COUNT = 15
 };
 int mipq_profile_enable(int on);
 int mipq_profile_collect(int kernel, int64_t* launches, double* total_ms);

@@ -14,15 +14,15 @@ import ctypes
 
 from ._lib import PLAN_AUTOTUNE, PLAN_GRAPH, MipqError, MipqProblem, check, lib  # noqa: F401
 
-FP32, BF16 = 0, 1
-_PREC = {"fp32": FP32, "bf16": BF16, FP32: FP32, BF16: BF16}
+FP32, BF16, FP8 = 0, 1, 2
+_PREC = {"fp32": FP32, "bf16": BF16, "fp8": FP8, FP32: FP32, BF16: BF16, FP8: FP8}
 
 
 def _prec(p) -> int:
     try:
         return _PREC[p]
     except KeyError:
-        raise ValueError("precision must be 'fp32' or 'bf16'") from None
+        raise ValueError("precision must be 'fp32', 'bf16' or 'fp8'") from None
 
 
 def _dev(t: torch.Tensor, dtype, name: str) -> torch.Tensor:

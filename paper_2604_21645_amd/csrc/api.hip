@@ -35,10 +35,11 @@ int check_shape(int64_t n, int d, int m, int ks, int precision, bool fit) {
     if (ds > (fit ? kMaxDsFit : kMaxDsFp32))
       return fail(MIPQ_EUNSUPPORTED, "FP32 path supports d/m <= %d here (got %d)",
                   fit ? kMaxDsFit : kMaxDsFp32, ds);
-  } else if (precision == MIPQ_BF16) {
-    if (ds > kMaxDsBf16) return fail(MIPQ_EUNSUPPORTED, "BF16 path supports d/m <= %d (got %d)", kMaxDsBf16, ds);
+  } else if (precision == MIPQ_BF16 || precision == MIPQ_FP8) {
+    if (ds > kMaxDsBf16)
+      return fail(MIPQ_EUNSUPPORTED, "matrix-core paths support d/m <= %d (got %d)", kMaxDsBf16, ds);
     if ((uint64_t)n * (uint64_t)m >= (1ull << 32))
-      return fail(MIPQ_EUNSUPPORTED, "BF16 path needs n*m < 2^32");
+      return fail(MIPQ_EUNSUPPORTED, "matrix-core paths need n*m < 2^32");
   } else {
     return fail(MIPQ_EINVAL, "unknown precision %d", precision);
   }
@@ -59,6 +60,9 @@ EncodeWs carve_encode(void* ws, int m, int ks, int ds, int precision) {
     e.aop = c.take<uint4>(bf16_operand_count(m, ks, ds));
     e.cmax = c.take<float>(m);
     e.mu = c.take<float>((size_t)m * kMaxDsBf16);
+  } else if (precision == MIPQ_FP8) {
+    e.aop = c.take<uint4>(2 * fp8_operand_count(m, ks));   // 32-byte slots
+    e.mu = c.take<float>(fp8_stats_count(m));               // per-subspace statistics
   }
   e.bytes = c.bytes();
   return e;
@@ -111,7 +115,15 @@ int check_ws(void* ws, size_t have, size_t need) {
 int assign_any(const float* x, int64_t n, int d, int m, int ks, const float* c32, int precision,
                uint8_t* codes, const EncodeWs& e, int64_t* rescored, hipStream_t s) {
   if (precision == MIPQ_FP32) return launch_assign_fp32(x, n, d, m, ks, c32, codes, s);
+  if (precision == MIPQ_FP8) return launch_assign_fp8(x, n, d, m, ks, e.aop, e.mu, c32, codes, rescored, s);
   return launch_assign_bf16(x, n, d, m, ks, e.aop, e.cmax, e.mu, c32, codes, rescored, s);
+}
+
+// operands of the matrix-core paths for the codebook c32
+int pack_any(const float* c32, int m, int ks, int ds, int precision, const EncodeWs& e, hipStream_t s) {
+  if (precision == MIPQ_BF16) return launch_pack_bf16(c32, m, ks, ds, e.aop, e.cmax, e.mu, s);
+  if (precision == MIPQ_FP8) return launch_pack_fp8(c32, m, ks, ds, e.aop, e.mu, s);
+  return MIPQ_OK;
 }
 
 }  // namespace
@@ -160,12 +172,14 @@ int mipq_pq_fit(const float* x, int64_t n, const int64_t* train_rows, int64_t n_
                                  c64, c32, f.bad, nullptr, s)))
     return rc;
   const bool bf = precision == MIPQ_BF16;
-  if (bf && iters > 0 && (rc = launch_pack_bf16(c32, m, ks, ds, f.enc.aop, f.enc.cmax, f.enc.mu, s))) return rc;
+  if (iters > 0 && (rc = pack_any(c32, m, ks, ds, precision, f.enc, s))) return rc;
   for (int it = 0; it < iters; ++it) {
     if ((rc = assign_any(train, nt, d, m, ks, c32, precision, codes, f.enc, nullptr, s))) return rc;
     // the update also packs the next round's operands (BF16)
     if ((rc = launch_update(train, nt, d, m, ks, codes, c32, c64, f.nch, f.part_s, f.part_cnt, f.part_j,
                             f.j_sub + (size_t)it * m, bf ? f.enc.aop : nullptr, f.enc.cmax, f.enc.mu, s)))
+      return rc;
+    if (precision == MIPQ_FP8 && it + 1 < iters && (rc = launch_pack_fp8(c32, m, ks, ds, f.enc.aop, f.enc.mu, s)))
       return rc;
   }
   if (objective && (rc = launch_objective(f.j_sub, iters, m, objective, s))) return rc;
@@ -188,8 +202,7 @@ int mipq_pq_encode(const float* x, int64_t n, int d, int m, int ks, const float*
   if (n > 0 && (rc = check_ws(ws, ws_bytes, e.bytes))) return rc;
   if (rescored && (rc = launch_zero_u32(reinterpret_cast<uint32_t*>(rescored), 2, s))) return rc;
   if (n == 0) return MIPQ_OK;
-  if (precision == MIPQ_BF16 && (rc = launch_pack_bf16(codebook, m, ks, d / m, e.aop, e.cmax, e.mu, s)))
-    return rc;
+  if ((rc = pack_any(codebook, m, ks, d / m, precision, e, s))) return rc;
   return assign_any(x, n, d, m, ks, codebook, precision, codes, e, rescored, s);
 }
 
@@ -279,6 +292,8 @@ int check_coarse(int64_t n, int d, int kc, int precision) {
     const int S = coarse_ksteps(d);
     if (d > 256 || !(S == 1 || S == 2 || S == 4 || S == 6 || S == 8 || S == 12 || S == 16))
       return fail(MIPQ_EUNSUPPORTED, "coarse matrix-core path needs d <= 16 or d in {32, 64, 96, 128, 192, 256}");
+  } else if (precision == MIPQ_FP8) {
+    return fail(MIPQ_EUNSUPPORTED, "the coarse quantiser runs in MIPQ_FP32 or MIPQ_BF16");
   } else if (precision != MIPQ_FP32) {
     return fail(MIPQ_EINVAL, "unknown precision %d", precision);
   }

@@ -172,6 +172,13 @@ int launch_decode_sse_batched(const BatchProb* probs, int nprob, int64_t blocks,
 int launch_objective_batched(const BatchProb* probs, int nprob, int iters, int m, const double* j_all,
                              hipStream_t s);
 
+// FP8 matrix-core path: operands (32-byte slots) and per-subspace statistics
+size_t fp8_operand_count(int m, int ks);
+size_t fp8_stats_count(int m);
+int launch_pack_fp8(const float* c32, int m, int ks, int ds, void* aop, float* stats, hipStream_t s);
+int launch_assign_fp8(const float* x, int64_t n, int d, int m, int ks, const void* aop, const float* stats,
+                      const float* c32, uint8_t* codes, int64_t* rescored, hipStream_t s);
+
 // rescored: optional int64 counter, incremented by the pairs re-decided exactly
 int launch_assign_bf16(const float* x, int64_t n, int d, int m, int ks, const void* aop,
                        const float* cmax, const float* mu, const float* c32, uint8_t* codes,

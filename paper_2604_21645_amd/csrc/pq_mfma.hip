@@ -196,8 +196,77 @@ __device__ __forceinline__ void load_rows(float (&xv)[DW], const float* __restri
   }
 }
 
-// Matrix-core decision for the row held by lanes l and l^32 (raw slice xraw):
-// returns the winning candidate and sets amb when the two best are not
+// Reduction of the NT tiles of 32-centroid estimates of one row (lanes l and
+// l^32): the best estimate f1, the runner-up f2 and the index of the best.
+// Each lane reduces its 16*NT values with two groupings -- by tile (amin) and
+// by accumulator register (bmin) -- whose minima give the best value, its tile
+// and register (hence its index), and the runner-up (two candidates of one
+// lane differ in tile or in register); then the lane pair merges.
+template <int NT, class TileFn>
+__device__ __forceinline__ int reduce_scores(TileFn tile, float& f1, float& f2) {
+  float amin[NT];
+  float bmin[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) bmin[r] = INFINITY;
+#pragma unroll
+  for (int t = 0; t < NT; t += 2) {
+    const f32x16 c0 = tile(t);
+    amin[t] = min16(c0);
+    if (t + 1 < NT) {
+      const f32x16 c1 = tile(t + 1 < NT ? t + 1 : 0);
+      amin[t + 1] = min16(c1);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) bmin[r] = min3f(bmin[r], c0[r], c1[r]);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) bmin[r] = fminf(bmin[r], c0[r]);
+    }
+  }
+
+  // smallest two keys of each grouping; the low bits carry the tile
+  // (3 bits) or the register (4 bits)
+  int a1 = INT_MAX, a2 = INT_MAX, b1 = INT_MAX, b2 = INT_MAX;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int k = key_of(amin[t], ~7, t);
+    a2 = min(a2, max(a1, k));
+    a1 = min(a1, k);
+  }
+#pragma unroll
+  for (int r = 0; r < 16; r += 2) {
+    const int ka = key_of(bmin[r], ~15, r);
+    const int kb = key_of(bmin[r + 1], ~15, r + 1);
+    b2 = min(b2, med3i(ka, kb, b1));   // runner-up of {b1, b2, ka, kb}, b1 <= b2
+    b1 = min(b1, min(ka, kb));
+  }
+  const int rl = b1 & 15;
+  const int s2 = min(a2, b2);
+
+  // merge the two lanes holding the candidates of a row
+  const int2 A1 = halves(a1);
+  const int2 S2 = halves(s2);
+  const int2 RL = halves(rl);
+  const bool hiw = A1.y < A1.x;
+  const int w1 = min(A1.x, A1.y);
+  const int sec = min(max(A1.x, A1.y), min(S2.x, S2.y));
+  const int tw = (hiw ? A1.y : A1.x) & 7;
+  const int rw = hiw ? RL.y : RL.x;
+  f1 = __int_as_float(w1);
+  f2 = __int_as_float(sec);
+  return tw * 32 + (rw >> 2) * 8 + (hiw ? 4 : 0) + (rw & 3);
+}
+
+// Separation test: true when the two best estimates f1 <= f2 (error at most
+// beta each) may not order the exact rule's distances; q covers the key
+// truncation and the exact rule's rounding (g relative), xn the row norm.
+__device__ __forceinline__ bool not_separated(float f1, float f2, float beta, float g, float xn) {
+  const float q = 3.815e-6f + g;   // 2^-18 + g
+  const float thr = 2.0f * beta + q * (fabsf(f1) + fabsf(f2)) + 2.0f * g * (beta + g * xn);
+  return !(f2 - f1 > thr);
+}
+
+// BF16 matrix-core decision for the row held by lanes l and l^32 (raw slice
+// xraw): returns the winning candidate and sets amb when the two best are not
 // separated by the error bound (then the exact rule must decide).
 template <int NB, int NT>
 __device__ __forceinline__ int decide_tile(const float (&xraw)[NB * 8], const SubOps<NB, NT>& o, int half, int ks,
@@ -251,65 +320,11 @@ __device__ __forceinline__ int decide_tile(const float (&xraw)[NB * 8], const Su
     for (int f = 0; f < NMF; ++f) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.A[t][f], B[f], acc, 0, 0, 0);
     return acc;
   };
-
-  // distance estimates, reduced by tile (amin) and by accumulator register (bmin)
-  float amin[NT];
-  float bmin[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) bmin[r] = INFINITY;
-#pragma unroll
-  for (int t = 0; t < NT; t += 2) {
-    const f32x16 c0 = tile(t);
-    amin[t] = min16(c0);
-    if (t + 1 < NT) {
-      const f32x16 c1 = tile(t + 1 < NT ? t + 1 : 0);
-      amin[t + 1] = min16(c1);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) bmin[r] = min3f(bmin[r], c0[r], c1[r]);
-    } else {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) bmin[r] = fminf(bmin[r], c0[r]);
-    }
-  }
-
-  // smallest two keys of each grouping; the low bits carry the tile
-  // (3 bits) or the register (4 bits)
-  int a1 = INT_MAX, a2 = INT_MAX, b1 = INT_MAX, b2 = INT_MAX;
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int k = key_of(amin[t], ~7, t);
-    a2 = min(a2, max(a1, k));
-    a1 = min(a1, k);
-  }
-#pragma unroll
-  for (int r = 0; r < 16; r += 2) {
-    const int ka = key_of(bmin[r], ~15, r);
-    const int kb = key_of(bmin[r + 1], ~15, r + 1);
-    b2 = min(b2, med3i(ka, kb, b1));   // runner-up of {b1, b2, ka, kb}, b1 <= b2
-    b1 = min(b1, min(ka, kb));
-  }
-  const int rl = b1 & 15;
-  const int s2 = min(a2, b2);
-
-  // merge the two lanes holding the 256 candidates of a row
-  const int2 A1 = halves(a1);
-  const int2 S2 = halves(s2);
-  const int2 RL = halves(rl);
-  const bool hiw = A1.y < A1.x;
-  const int w1 = min(A1.x, A1.y);
-  const int sec = min(max(A1.x, A1.y), min(S2.x, S2.y));
-  const int tw = (hiw ? A1.y : A1.x) & 7;
-  const int rw = hiw ? RL.y : RL.x;
-  const int code = tw * 32 + (rw >> 2) * 8 + (hiw ? 4 : 0) + (rw & 3);
-
-  const float f1 = __int_as_float(w1);
-  const float f2 = __int_as_float(sec);
+  float f1, f2;
+  const int code = reduce_scores<NT>(tile, f1, f2);
   const float xnorm = sqrtf(xn) * 1.0001f;
   const float beta = bd.e_cross * xnorm * o.cm + bd.e_norm * (o.cm * o.cm + xn);
-  const float q = 3.815e-6f + bd.g_exact;                       // 2^-18 + gamma
-  const float thr = 2.0f * beta + q * (fabsf(f1) + fabsf(f2)) + 2.0f * bd.g_exact * (beta + bd.g_exact * xn);
-  const float gap = f2 - f1;
-  amb = !(gap > thr) || code >= ks;
+  amb = not_separated(f1, f2, beta, bd.g_exact, xn) || code >= ks;
   return code;
 }
 
@@ -331,12 +346,11 @@ __device__ __forceinline__ void redecide(const uint32_t* pend, int np, const flo
 // are queued in the wave's LDS list and re-decided with the exact rule after
 // the loop (and, with MIDFLUSH, whenever more than flush_at are queued).
 // Returns the number of re-decided rows.
-template <int NB, int NT, bool FULL, bool MIDFLUSH>
+template <int DW, bool FULL, bool MIDFLUSH, class Decide>
 __device__ __forceinline__ uint32_t assign_rows(const float* __restrict__ x, int d, int ds, int m, int ks, int sub,
-                                                int64_t rb, int64_t re, const SubOps<NB, NT>& o,
+                                                int64_t rb, int64_t re, Decide decide,
                                                 const float* __restrict__ cbsub, uint8_t* __restrict__ codes,
-                                                uint32_t* pend, int flush_at, const Band& bd, int lane) {
-  constexpr int DW = NB * 8;
+                                                uint32_t* pend, int flush_at, int lane) {
   const int half = lane >> 5;
   uint32_t nres = 0;
   int np = 0;
@@ -355,7 +369,7 @@ __device__ __forceinline__ uint32_t assign_rows(const float* __restrict__ x, int
     for (int e = 0; e < DW; ++e) xv[e] = xnext[e];
     if (r0 + 32 < re) load_rows<DW, FULL>(xnext, x, r0 + 32, re, d, sub, ds, lane);   // next tile in flight
     bool amb;
-    const int code = decide_tile<NB, NT>(xv, o, half, ks, bd, amb);
+    const int code = decide(xv, half, amb);
     // rows whose two best candidates are not separated are re-decided by the
     // whole wave with the exact rule (rare); their codes are overwritten then
     if (half == 0 && valid) codes[row * m + sub] = (uint8_t)code;
@@ -390,9 +404,12 @@ __global__ __launch_bounds__(kThreads) void k_assign_bf16(
   // LDS: rpb list entries per wave, so the list cannot overflow
   extern __shared__ uint32_t pend_all[];
   const Band bd{e_cross, e_norm, g_exact};
-  const uint32_t nres = assign_rows<NB, NT, FULL, false>(x, d, ds, m, ks, sub, rbeg, rend, o,
+  auto decide = [&](const float (&xv)[NB * 8], int half, bool& amb) {
+    return decide_tile<NB, NT>(xv, o, half, ks, bd, amb);
+  };
+  const uint32_t nres = assign_rows<NB * 8, FULL, false>(x, d, ds, m, ks, sub, rbeg, rend, decide,
                                                          c32 + (int64_t)sub * ks * ds, codes, pend_all + w * rpb,
-                                                         0, bd, lane);
+                                                         0, lane);
   if (rescored && lane == 0 && nres) atomicAdd(rescored, (unsigned long long)nres);
 }
 
@@ -448,11 +465,303 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NB == 
                          sub, lane);
     // rows in pieces of PC, so that a piece's pending list fits the wave's LDS
     const int64_t rb = t0 * 32, re = min(n, t1 * 32);
+    auto decide = [&](const float (&xv)[NB * 8], int half, bool& amb) {
+      return decide_tile<NB, NT>(xv, o, half, ks, bd, amb);
+    };
     for (int64_t pb = rb; pb < re; pb += PC)
-      nres += assign_rows<NB, NT, FULL, false>(px, d, ds, m, ks, sub, pb, min(re, pb + PC), o,
+      nres += assign_rows<NB * 8, FULL, false>(px, d, ds, m, ks, sub, pb, min(re, pb + PC), decide,
                                                probs[p].c32 + (int64_t)sub * ks * ds, probs[p].codes,
-                                               pend_all + w * PC, 0, bd, lane);
+                                               pend_all + w * PC, 0, lane);
   }
+  if (rescored && lane == 0 && nres) atomicAdd(rescored, (unsigned long long)nres);
+}
+
+// ---- FP8 (OCP E4M3) matrix-core path ----------------------------------------
+// One v_mfma_f32_32x32x64_f8f6f4 per 32-centroid tile.  Per subspace a power of
+// two sigma maps the centred centroids into [-16, 16] (x~ = (x - mu)/sigma,
+// c^ = -2 (c - mu)/sigma); each value v is split into fp8 parts vh = fp8(v),
+// vl = fp8(v - vh), with residual ev = v - vh - vl.  K slots (same for A, B):
+//   hh: ch.xh   lh: cl.xh   hl: ch.xl   (DW slots each)
+//   4 slots: pieces of ||c~||^2 times 16, 1, 1/16, 1/256 (row side holds the
+//   multipliers), 4 slots: 256, 16, 1, 1/16 times pieces of ||x~||^2.
+// DW = 8: all 32 slots in lane half 0 (half 1 zero); DW = 16: hh, lh in half
+// 0, hl and the norm slots in half 1.  The estimate is ||x~ - c~||^2 up to the
+// dropped terms xl.cl + (xh + xl).ec + ex.c^, the norm residuals and the
+// float32 accumulation; the bound uses the measured norms of the parts, so it
+// holds for any rounding of the conversions.  Values are clamped to the fp8
+// range first; a clamped row gets a large residual and goes to the exact rule.
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+constexpr int kFp8Stats = 24;   // per subspace: mu[16], 1/sigma, sigma^2, Lc, Ec, Cc, Rc, ncmax, pad
+constexpr float kFp8Max = 448.0f;
+
+__device__ __forceinline__ float clamp8(float v) { return fminf(fmaxf(v, -kFp8Max), kFp8Max); }
+// two floats to two fp8 bytes (low 16 bits), then back to float
+__device__ __forceinline__ uint32_t pk8(float a, float b) {
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(clamp8(a), clamp8(b), 0, false) & 0xFFFFu;
+}
+__device__ __forceinline__ f32x2 unpk8(uint32_t w) { return __builtin_amdgcn_cvt_pk_f32_fp8((int)w, false); }
+
+struct Split8 {   // fp8 high/low parts of a DW-vector, packed 4 per dword
+  uint32_t h[4], l[4];   // DW <= 16
+  float nl, ne;          // ||vl||, ||v - vh - vl||
+};
+template <int DW>
+__device__ __forceinline__ Split8 split8(const float (&v)[DW]) {
+  Split8 s;
+  float sl = 0.0f, se = 0.0f;
+#pragma unroll
+  for (int i = 0; i < DW; i += 4) {
+    const uint32_t h01 = pk8(v[i], v[i + 1]), h23 = pk8(v[i + 2], v[i + 3]);
+    const f32x2 fh01 = unpk8(h01), fh23 = unpk8(h23);
+    const float r0 = v[i] - fh01[0], r1 = v[i + 1] - fh01[1], r2 = v[i + 2] - fh23[0], r3 = v[i + 3] - fh23[1];
+    const uint32_t l01 = pk8(r0, r1), l23 = pk8(r2, r3);
+    const f32x2 fl01 = unpk8(l01), fl23 = unpk8(l23);
+    const float e0 = r0 - fl01[0], e1 = r1 - fl01[1], e2 = r2 - fl23[0], e3 = r3 - fl23[1];
+    s.h[i >> 2] = h01 | (h23 << 16);
+    s.l[i >> 2] = l01 | (l23 << 16);
+    sl = __builtin_fmaf(fl01[0], fl01[0], sl);
+    sl = __builtin_fmaf(fl01[1], fl01[1], sl);
+    sl = __builtin_fmaf(fl23[0], fl23[0], sl);
+    sl = __builtin_fmaf(fl23[1], fl23[1], sl);
+    se = __builtin_fmaf(e0, e0, se);
+    se = __builtin_fmaf(e1, e1, se);
+    se = __builtin_fmaf(e2, e2, se);
+    se = __builtin_fmaf(e3, e3, se);
+  }
+  s.nl = sqrtf(sl) * 1.0001f;
+  s.ne = sqrtf(se) * 1.0001f;
+  return s;
+}
+
+// four fp8 pieces of v against the multipliers 2^k0, 2^(k0-4), 2^(k0-8),
+// 2^(k0-12): packed bytes and the remaining residual |v - sum|
+__device__ __forceinline__ uint32_t pieces8(float v, float inv0, float& resid) {
+  float r = v, m = inv0, mul = 1.0f / inv0;
+  uint32_t out = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t b = pk8(r * m, 0.0f) & 0xFFu;
+    const float pf = unpk8(b)[0];
+    r = r - pf * mul;   // exact while the pieces track the residual
+    out |= b << (8 * i);
+    m *= 16.0f;
+    mul *= 0.0625f;
+  }
+  resid = fabsf(r);
+  return out;
+}
+
+template <int NT>
+struct SubOps8 {
+  i32x8 A[NT];
+  float muv[16];
+  float inv_sigma, sigma2, Lc, Ec, Cc, Rc, ncmax;
+  uint32_t mult_c;   // fp8 16, 1, 1/16, 1/256: row-side multipliers of the centroid norm pieces
+};
+
+template <int NB, int NT>
+__device__ __forceinline__ void load_sub_ops8(SubOps8<NT>& o, const i32x8* __restrict__ aop,
+                                              const float* __restrict__ stats, int sub, int lane) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) o.A[t] = aop[(size_t)(sub * NT + t) * 64 + lane];
+  const float* st = stats + (size_t)sub * kFp8Stats;
+  auto uni = [](float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); };
+#pragma unroll
+  for (int e = 0; e < NB * 8; ++e) o.muv[e] = uni(st[e]);
+  o.inv_sigma = uni(st[16]);
+  o.sigma2 = uni(st[17]);
+  o.Lc = uni(st[18]);
+  o.Ec = uni(st[19]);
+  o.Cc = uni(st[20]);
+  o.Rc = uni(st[21]);
+  o.ncmax = uni(st[22]);
+  o.mult_c = (uint32_t)__builtin_amdgcn_readfirstlane((int)(pk8(16.0f, 1.0f) | (pk8(0.0625f, 0.00390625f) << 16)));
+}
+
+// FP8 decision for the row held by lanes l and l^32; estimates and the bound
+// are in units of sigma^2.
+template <int NB, int NT>
+__device__ __forceinline__ int decide_tile_fp8(const float (&xraw)[NB * 8], const SubOps8<NT>& o, int half, int ks,
+                                               float g_exact, bool& amb) {
+  constexpr int DW = NB * 8;
+  float xv[DW];   // x~ = (x - mu) / sigma, clamped to the fp8 range
+  float nx = 0.0f;
+#pragma unroll
+  for (int e = 0; e < DW; ++e) {
+    const float v = (xraw[e] - o.muv[e]) * o.inv_sigma;
+    nx = __builtin_fmaf(v, v, nx);
+    xv[e] = v;
+  }
+  const Split8 sx = split8<DW>(xv);
+  float rx;
+  const uint32_t q = pieces8(nx, 1.0f / 256.0f, rx);
+  const uint32_t mult_c = o.mult_c;
+  i32x8 B;
+  if (DW == 8) {
+    if (half == 0) {
+      B = i32x8{(int)sx.h[0], (int)sx.h[1], (int)sx.h[0], (int)sx.h[1], (int)sx.l[0], (int)sx.l[1], (int)mult_c,
+                (int)q};
+    } else {
+      B = i32x8{0, 0, 0, 0, 0, 0, 0, 0};
+    }
+  } else {
+    if (half == 0) {
+      B = i32x8{(int)sx.h[0], (int)sx.h[1], (int)sx.h[2], (int)sx.h[3],
+                (int)sx.h[0], (int)sx.h[1], (int)sx.h[2], (int)sx.h[3]};
+    } else {
+      B = i32x8{(int)sx.l[0], (int)sx.l[1], (int)sx.l[2], (int)sx.l[3], (int)mult_c, (int)q, 0, 0};
+    }
+  }
+  auto tile = [&](int t) {
+    f32x16 acc = {};
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(o.A[t], B, acc, 0, 0, 0, 0, 0, 0);
+  };
+  float f1, f2;
+  const int code = reduce_scores<NT>(tile, f1, f2);
+  // bound on |estimate - ||x~ - c~||^2| (see the section comment)
+  const float xnorm = sqrtf(nx) * 1.0001f;
+  const float xh_norm = xnorm + sx.ne;
+  const float beta = (sx.nl * o.Lc + xh_norm * o.Ec + sx.ne * o.Cc + o.Rc + rx +
+                      7.7e-6f * (nx + o.ncmax + 3.0f * xh_norm * o.Cc) + 1.9e-6f * (nx + o.ncmax)) * 1.001f;
+  amb = not_separated(f1, f2, beta, g_exact, nx) || code >= ks;
+  return code;
+}
+
+// FP8 operands of one subspace (block = subspace, thread = centroid; ks <= 256).
+template <int NB>
+__global__ __launch_bounds__(256) void k_pack_fp8(const float* __restrict__ c32, int ks, int ds, int nt,
+                                                  i32x8* __restrict__ aop, float* __restrict__ stats) {
+  constexpr int DW = NB * 8;
+  __shared__ float red[4][2 * DW];
+  __shared__ float mu_s[DW];
+  __shared__ float mx[4][6];
+  __shared__ float sig_s;
+  const int sub = blockIdx.x;
+  const int k = threadIdx.x;
+  const int lane = k & 63, w = k >> 6;
+  const bool real = k < ks;
+  const float* c = c32 + ((size_t)sub * ks + (real ? k : 0)) * ds;
+  float cv[DW];
+#pragma unroll
+  for (int e = 0; e < DW; ++e) cv[e] = e < ds ? c[e < ds ? e : 0] : 0.0f;
+  // centre: midpoint of the coordinate range of the centroids
+#pragma unroll
+  for (int e = 0; e < DW; ++e) {
+    float lo = real ? cv[e] : INFINITY, hi = real ? cv[e] : -INFINITY;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      lo = fminf(lo, __shfl_xor(lo, off, 64));
+      hi = fmaxf(hi, __shfl_xor(hi, off, 64));
+    }
+    if (lane == 0) {
+      red[w][e] = lo;
+      red[w][DW + e] = hi;
+    }
+  }
+  __syncthreads();
+  if (k < DW) {
+    float lo = red[0][k], hi = red[0][DW + k];
+    for (int i = 1; i < 4; ++i) {
+      lo = fminf(lo, red[i][k]);
+      hi = fmaxf(hi, red[i][DW + k]);
+    }
+    mu_s[k] = (k < ds && lo <= hi) ? 0.5f * lo + 0.5f * hi : 0.0f;
+  }
+  __syncthreads();
+  // sigma: power of two with max |c - mu| / sigma <= 16
+  float a = 0.0f;
+#pragma unroll
+  for (int e = 0; e < DW; ++e) a = fmaxf(a, real ? fabsf(cv[e] - mu_s[e]) : 0.0f);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) a = fmaxf(a, __shfl_xor(a, off, 64));
+  if (lane == 0) mx[w][0] = a;
+  __syncthreads();
+  if (k == 0) {
+    const float am = fmaxf(fmaxf(mx[0][0], mx[1][0]), fmaxf(mx[2][0], mx[3][0]));
+    int ex = 0;
+    (void)frexpf(am * 0.0625f, &ex);
+    sig_s = am > 0.0f && am < INFINITY ? ldexpf(1.0f, ex) : 1.0f;
+  }
+  __syncthreads();
+  const float sigma = sig_s;
+  const float inv = 1.0f / sigma;   // exact: a power of two
+  float ch[DW];
+  float nc = 0.0f, cn2 = 0.0f;
+#pragma unroll
+  for (int e = 0; e < DW; ++e) {
+    const float ct = (cv[e] - mu_s[e]) * inv;
+    nc = __builtin_fmaf(ct, ct, nc);
+    ch[e] = -2.0f * ct;
+    cn2 = __builtin_fmaf(ch[e], ch[e], cn2);
+  }
+  Split8 sc = split8<DW>(ch);
+  float rc;
+  uint32_t pc = pieces8(nc, 0.0625f, rc);
+  // bounds over the real centroids
+  float v[5] = {real ? sc.nl : 0.0f, real ? sc.ne : 0.0f, real ? sqrtf(cn2) * 1.0001f : 0.0f, real ? rc : 0.0f,
+                real ? nc : 0.0f};
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[i] = fmaxf(v[i], __shfl_xor(v[i], off, 64));
+    if (lane == 0) mx[w][i] = v[i];
+  }
+  __syncthreads();
+  float* st = stats + (size_t)sub * kFp8Stats;
+  if (k < 5) {
+    const float r = fmaxf(fmaxf(mx[0][k], mx[1][k]), fmaxf(mx[2][k], mx[3][k]));
+    st[18 + k] = r;
+  }
+  if (k < 16) st[k] = k < DW ? mu_s[k] : 0.0f;
+  if (k == 0) {
+    st[16] = inv;
+    st[17] = sigma * sigma;
+    st[23] = 0.0f;
+  }
+  if (k < nt * 32) {
+    if (!real) {   // padded candidate: zero parts, large norm
+      for (int i = 0; i < 4; ++i) sc.h[i] = sc.l[i] = 0u;
+      pc = pk8(kFp8Max, kFp8Max) | (pk8(kFp8Max, kFp8Max) << 16);
+    }
+    const uint32_t mult_x = pk8(256.0f, 16.0f) | (pk8(1.0f, 0.0625f) << 16);
+    i32x8 a0, a1;
+    if (DW == 8) {
+      a0 = i32x8{(int)sc.h[0], (int)sc.h[1], (int)sc.l[0], (int)sc.l[1], (int)sc.h[0], (int)sc.h[1], (int)pc,
+                 (int)mult_x};
+      a1 = i32x8{0, 0, 0, 0, 0, 0, 0, 0};
+    } else {
+      a0 = i32x8{(int)sc.h[0], (int)sc.h[1], (int)sc.h[2], (int)sc.h[3],
+                 (int)sc.l[0], (int)sc.l[1], (int)sc.l[2], (int)sc.l[3]};
+      a1 = i32x8{(int)sc.h[0], (int)sc.h[1], (int)sc.h[2], (int)sc.h[3], (int)pc, (int)mult_x, 0, 0};
+    }
+    const int t = k >> 5, i = k & 31;
+    aop[((size_t)sub * nt + t) * 64 + i] = a0;
+    aop[((size_t)sub * nt + t) * 64 + 32 + i] = a1;
+  }
+}
+
+// One problem, FP8 operands; same geometry and exact re-decision as the BF16 kernel.
+template <int NB, int NT, bool FULL>
+__global__ __launch_bounds__(kThreads) void k_assign_fp8(
+    const float* __restrict__ x, int64_t n, int d, int m, int ks, int ds, const i32x8* __restrict__ aop,
+    const float* __restrict__ stats, const float* __restrict__ c32, uint8_t* __restrict__ codes,
+    unsigned long long* __restrict__ rescored, int groups, int rpb, float g_exact) {
+  const XcdMap bm = xcd_map(blockIdx.x, groups);
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int sub = bm.group * 4 + w;
+  const int64_t rbeg = (int64_t)bm.rowblk * rpb;
+  if (sub >= m || rbeg >= n) return;
+  const int64_t rend = min(n, rbeg + rpb);
+  SubOps8<NT> o;
+  load_sub_ops8<NB, NT>(o, aop, stats, sub, lane);
+  extern __shared__ uint32_t pend_all[];
+  auto decide = [&](const float (&xv)[NB * 8], int half, bool& amb) {
+    return decide_tile_fp8<NB, NT>(xv, o, half, ks, g_exact, amb);
+  };
+  const uint32_t nres = assign_rows<NB * 8, FULL, false>(x, d, ds, m, ks, sub, rbeg, rend, decide,
+                                                         c32 + (int64_t)sub * ks * ds, codes, pend_all + w * rpb,
+                                                         0, lane);
   if (rescored && lane == 0 && nres) atomicAdd(rescored, (unsigned long long)nres);
 }
 
@@ -580,6 +889,63 @@ int launch_assign_bf16_batched(const BatchProb* probs, int nprob, int64_t units,
                   (void*)&aop, (void*)&aop_stride, (void*)&cmax, (void*)&mu, (void*)&resc,
                   (void*)&bd.e_cross, (void*)&bd.e_norm, (void*)&bd.g_exact};
   MIPQ_HIP(hipLaunchKernel(pick_batched(ds, ks, full), dim3(grid), dim3(kThreads), args, 0, s));
+  return MIPQ_OK;
+}
+
+size_t fp8_operand_count(int m, int ks) { return (size_t)m * tiles_for(ks) * 64; }
+size_t fp8_stats_count(int m) { return (size_t)m * kFp8Stats; }
+
+int launch_pack_fp8(const float* c32, int m, int ks, int ds, void* aop, float* stats, hipStream_t s) {
+  const int nt = tiles_for(ks);
+  ProfScope ps(MIPQ_K_PACK_FP8, s);
+  if (ds <= 8)
+    k_pack_fp8<1><<<m, 256, 0, s>>>(c32, ks, ds, nt, (i32x8*)aop, stats);
+  else
+    k_pack_fp8<2><<<m, 256, 0, s>>>(c32, ks, ds, nt, (i32x8*)aop, stats);
+  MIPQ_LAUNCHED("k_pack_fp8");
+  return MIPQ_OK;
+}
+
+int launch_assign_fp8(const float* x, int64_t n, int d, int m, int ks, const void* aop, const float* stats,
+                      const float* c32, uint8_t* codes, int64_t* rescored, hipStream_t s) {
+  const int ds = d / m;
+  const int nb = (ds + 7) / 8;
+  const int nt = tiles_for(ks);
+  const Bf16Geom g = bf16_geometry(n, m);
+  if (g.blocks == 0) return MIPQ_OK;
+  const float g_exact = band_for(ds).g_exact;
+  ProfScope ps(MIPQ_K_ASSIGN_FP8, s);
+  const bool full = (ds == nb * 8) && (d % 4 == 0) && ((reinterpret_cast<uintptr_t>(x) & 15) == 0);
+  unsigned long long* resc = reinterpret_cast<unsigned long long*>(rescored);
+  const size_t pend_bytes = (size_t)(kThreads / 64) * g.rpb * sizeof(uint32_t);
+#define LAUNCH(NB, NT)                                                                                         \
+  do {                                                                                                         \
+    if (full)                                                                                                  \
+      k_assign_fp8<NB, NT, true><<<g.blocks, kThreads, pend_bytes, s>>>(x, n, d, m, ks, ds, (const i32x8*)aop, \
+                                                                        stats, c32, codes, resc, g.groups,     \
+                                                                        g.rpb, g_exact);                       \
+    else                                                                                                       \
+      k_assign_fp8<NB, NT, false><<<g.blocks, kThreads, pend_bytes, s>>>(x, n, d, m, ks, ds,                   \
+                                                                         (const i32x8*)aop, stats, c32, codes, \
+                                                                         resc, g.groups, g.rpb, g_exact);      \
+  } while (0)
+  if (nb == 1) {
+    switch (nt) {
+      case 1: LAUNCH(1, 1); break;
+      case 2: LAUNCH(1, 2); break;
+      case 4: LAUNCH(1, 4); break;
+      default: LAUNCH(1, 8); break;
+    }
+  } else {
+    switch (nt) {
+      case 1: LAUNCH(2, 1); break;
+      case 2: LAUNCH(2, 2); break;
+      case 4: LAUNCH(2, 4); break;
+      default: LAUNCH(2, 8); break;
+    }
+  }
+#undef LAUNCH
+  MIPQ_LAUNCHED("k_assign_fp8");
   return MIPQ_OK;
 }
 

@@ -50,7 +50,7 @@ ENCODE_CASES = [
 ]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
 @pytest.mark.parametrize("case", ENCODE_CASES, ids=lambda c: "n%(n)d_d%(d)d_m%(m)d_ks%(ks)d" % c)
 def test_encode_matches_oracle(prec, case):
     print("encode", prec, case, flush=True)
@@ -85,7 +85,7 @@ def test_bf16_and_fp32_agree_on_duplicate_rows_and_ties():
     assert int(resc.item()) > 0
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
 def test_fit_end_to_end_and_lockstep(prec):
     w = wl.plain_pq(seed=1, n=4000, m=8, ks=64, iters=6)
     print("fit", prec, flush=True)
@@ -105,6 +105,21 @@ def test_fit_end_to_end_and_lockstep(prec):
         upd, _, _ = pq.update(w.x, codes, cb.astype(np.float64))
         np.testing.assert_allclose(step["codebook64"].cpu().numpy(), upd, rtol=1e-12, atol=1e-12)
         cb = step["codebook"].cpu().numpy()
+
+
+def test_fp8_outlier_rows_and_rescoring_counts():
+    # rows far outside the centroid range saturate the fp8 operands; their
+    # residuals widen the bound and the exact rule decides them
+    x = _data("float", 4000, 128, seed=21)
+    cb = _codebook(x, 16, 256, seed=22)
+    x[::97] *= 1e4
+    x[5::131] = -3e6
+    codes, resc = mipq.pq_encode(_t(x), _t(cb), "fp8", rescored=True)
+    ref32, _, _ = pq.assign(x, cb.astype(np.float64), "fp32")
+    np.testing.assert_array_equal(codes.cpu().numpy().astype(np.int64), ref32)
+    _, resc16 = mipq.pq_encode(_t(x), _t(cb), "bf16", rescored=True)
+    print("rescored pairs fp8", int(resc.item()), "bf16", int(resc16.item()), "of", x.shape[0] * 16, flush=True)
+    assert int(resc.item()) >= int(resc16.item())
 
 
 def test_fit_on_a_row_sample_with_empty_clusters():
