@@ -339,3 +339,23 @@ def pq_fit_batched(xs, init_rows, m: int, ks: int, iters: int, precision="bf16",
     torch.cuda.current_stream(b.device).synchronize()
     b.close()
     return b.results
+
+
+def two_level_fit(xs, chunk_inits, global_init, m: int, ks: int, iters: int, precision="bf16"):
+    """The paper's two-level chunked fit (Section 3), composed from the
+    boundary calls: every chunk is fitted on its own rows (one batched fit of
+    all chunks), each chunk's codebook is decoded into its Ks centroid rows
+    (the decode of the code rows (k, k, ..., k)), the rows of all chunks are
+    pooled, and one global codebook is fitted on the pool from
+    ``global_init`` (int64 [m, ks], rows of the pool).
+
+    Returns dict(pool float32 [chunks*ks, d], codebook float32 [m, ks, d/m],
+    chunk_codebooks list).
+    """
+    b = BatchedFit(xs, chunk_inits, m, ks, iters, precision="bf16", plan=False, objective=False, sse=False)
+    b.run()
+    dev = b.device
+    kk = torch.arange(ks, device=dev, dtype=torch.int32).to(torch.uint8).unsqueeze(1).repeat(1, m).contiguous()
+    pool = torch.cat([pq_decode_rmse(kk, r["codebook"], x_hat=True)[0] for r in b.results])
+    g = pq_fit(pool, m, ks, iters, init_rows=global_init, precision=precision, labels=False, objective=False)
+    return {"pool": pool, "codebook": g["codebook"], "chunk_codebooks": [r["codebook"] for r in b.results]}
