@@ -177,7 +177,8 @@ int mipq_pq_fit(const float* x, int64_t n, const int64_t* train_rows, int64_t n_
     if ((rc = assign_any(train, nt, d, m, ks, c32, precision, codes, f.enc, nullptr, s))) return rc;
     // the update also packs the next round's operands (BF16)
     if ((rc = launch_update(train, nt, d, m, ks, codes, c32, c64, f.nch, f.part_s, f.part_cnt, f.part_j,
-                            f.j_sub + (size_t)it * m, bf ? f.enc.aop : nullptr, f.enc.cmax, f.enc.mu, s)))
+                            f.j_sub + (size_t)it * m, bf ? f.enc.aop : nullptr, f.enc.cmax, f.enc.mu,
+                            objective != nullptr, s)))
       return rc;
     if (precision == MIPQ_FP8 && it + 1 < iters && (rc = launch_pack_fp8(c32, m, ks, ds, f.enc.aop, f.enc.mu, s)))
       return rc;

@@ -568,25 +568,43 @@ __global__ void k_gather_coarse(const float* __restrict__ x, int64_t n, int d, c
 }
 
 // r = x - c_label, float32
+// r = x - c_label, float32.  Block-stride over rows, the block's threads over
+// the row's elements (16-byte accesses when d % 4 == 0).
 __global__ void k_residuals(const float* __restrict__ x, int64_t n, int d, const int32_t* __restrict__ labels,
-                            const float* __restrict__ cc, int kc, float* __restrict__ r) {
-  const int64_t total = n * d;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = i / d;
-    const int t = int(i - row * d);
+                            const float* __restrict__ cc, int kc, float* __restrict__ r, int vec4) {
+  const int per = vec4 ? d / 4 : d;
+  const int rpb = blockDim.x / per > 0 ? blockDim.x / per : 1;   // rows per block step
+  const int lr = threadIdx.x / per;
+  for (int64_t row0 = (int64_t)blockIdx.x * rpb; row0 < n; row0 += (int64_t)gridDim.x * rpb) {
+    const int64_t row = row0 + lr;
+    if (lr >= rpb || row >= n) continue;
     const int l = labels[row];
-    r[i] = (l >= 0 && l < kc) ? x[i] - cc[(int64_t)l * d + t] : NAN;
+    const bool ok = l >= 0 && l < kc;
+    const float* c = cc + (int64_t)(ok ? l : 0) * d;
+    for (int e = threadIdx.x - lr * per; e < per; e += (per > (int)blockDim.x ? blockDim.x : per)) {
+      if (vec4) {
+        const float4 a = reinterpret_cast<const float4*>(x + row * d)[e];
+        const float4 b = reinterpret_cast<const float4*>(c)[e];
+        reinterpret_cast<float4*>(r + row * d)[e] =
+            ok ? make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w) : make_float4(NAN, NAN, NAN, NAN);
+      } else {
+        r[row * d + e] = ok ? x[row * d + e] - c[e] : NAN;
+      }
+    }
   }
 }
 
-// codes_sorted[i] = codes[ids[i]] (m bytes per row)
+// codes_sorted[i] = codes[ids[i]] (m bytes per row); one thread per row
 __global__ void k_gather_codes(const uint8_t* __restrict__ codes, int64_t n, int m, const int32_t* __restrict__ ids,
-                               uint8_t* __restrict__ out) {
-  const int64_t total = n * m;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t p = i / m;
-    const int j = int(i - p * m);
-    out[i] = codes[(int64_t)ids[p] * m + j];
+                               uint8_t* __restrict__ out, int vec16) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint8_t* src = codes + (int64_t)ids[i] * m;
+    uint8_t* dst = out + i * m;
+    if (vec16) {
+      for (int j = 0; j < m; j += 16) *reinterpret_cast<uint4*>(dst + j) = *reinterpret_cast<const uint4*>(src + j);
+    } else {
+      for (int j = 0; j < m; ++j) dst[j] = src[j];
+    }
   }
 }
 
@@ -712,14 +730,17 @@ int launch_gather_coarse(const float* x, int64_t n, int d, const int64_t* rows, 
 int launch_residuals(const float* x, int64_t n, int d, const int32_t* labels, const float* cc, int kc, float* r,
                      hipStream_t s) {
   if (n == 0) return MIPQ_OK;
-  k_residuals<<<grid_cap(n * d, 8192), kT, 0, s>>>(x, n, d, labels, cc, kc, r);
+  const int vec4 = (d % 4 == 0) && (((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(cc) |
+                                       reinterpret_cast<uintptr_t>(r)) & 15) == 0);
+  k_residuals<<<grid_cap(n, 8192), kT, 0, s>>>(x, n, d, labels, cc, kc, r, vec4);
   MIPQ_LAUNCHED("k_residuals");
   return MIPQ_OK;
 }
 
 int launch_gather_codes(const uint8_t* codes, int64_t n, int m, const int32_t* ids, uint8_t* out, hipStream_t s) {
   if (n == 0) return MIPQ_OK;
-  k_gather_codes<<<grid_cap(n * m, 8192), kT, 0, s>>>(codes, n, m, ids, out);
+  const int vec16 = (m % 16 == 0) && (((reinterpret_cast<uintptr_t>(codes) | reinterpret_cast<uintptr_t>(out)) & 15) == 0);
+  k_gather_codes<<<grid_cap(n, 8192), kT, 0, s>>>(codes, n, m, ids, out, vec16);
   MIPQ_LAUNCHED("k_gather_codes");
   return MIPQ_OK;
 }

@@ -98,9 +98,10 @@ int launch_assign_fp32(const float* x, int64_t n, int d, int m, int ks, const fl
                        uint8_t* codes, hipStream_t s);
 // Lloyd update of one round; aop == NULL: plain path (no operand packing)
 int update_chunks(int64_t n, int m);
+// objective: also the float64 objective terms of the round (else part_j holds zeros)
 int launch_update(const float* x, int64_t n, int d, int m, int ks, const uint8_t* codes, float* c32,
                   double* c64, int nch, double* part_s, uint32_t* part_cnt, double* part_j,
-                  double* j_sub, void* aop, float* cmax, float* mu, hipStream_t s);
+                  double* j_sub, void* aop, float* cmax, float* mu, bool objective, hipStream_t s);
 int launch_objective(const double* j_sub, int iters, int m, double* objective, hipStream_t s);
 int launch_copy_f64(const double* src, double* dst, size_t count, hipStream_t s);
 int launch_decode_sse(const uint8_t* codes, int64_t n, int d, int m, int ks, const float* c32,

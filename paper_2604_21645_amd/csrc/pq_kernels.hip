@@ -34,20 +34,27 @@ __global__ void k_zero_u32(uint32_t* p, size_t count) {
   if (i < count) p[i] = 0u;
 }
 
+// out[r] = x[rows[r]]; block-stride over output rows, threads over the row
+// (16-byte accesses when d % 4 == 0).  Out-of-range indices give NaN rows.
 __global__ void k_gather_rows(const float* __restrict__ x, int64_t n, int d,
                               const int64_t* __restrict__ rows, int64_t n_rows,
-                              float* __restrict__ out, uint32_t* bad) {
-  const int64_t total = n_rows * d;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = i / d;
-    const int t = int(i - r * d);
+                              float* __restrict__ out, uint32_t* bad, int vec4) {
+  const int per = vec4 ? d / 4 : d;
+  const int rpb = blockDim.x / per > 0 ? blockDim.x / per : 1;
+  const int lr = threadIdx.x / per;
+  for (int64_t r0 = (int64_t)blockIdx.x * rpb; r0 < n_rows; r0 += (int64_t)gridDim.x * rpb) {
+    const int64_t r = r0 + lr;
+    if (lr >= rpb || r >= n_rows) continue;
     const int64_t src = rows[r];
-    if (src < 0 || src >= n) {
-      out[i] = NAN;
-      if (t == 0) atomicOr(bad, 1u);
-    } else {
-      out[i] = x[src * d + t];
+    const bool ok = src >= 0 && src < n;
+    for (int e = threadIdx.x - lr * per; e < per; e += (per > (int)blockDim.x ? blockDim.x : per)) {
+      if (vec4) {
+        reinterpret_cast<float4*>(out + r * d)[e] =
+            ok ? reinterpret_cast<const float4*>(x + src * d)[e] : make_float4(NAN, NAN, NAN, NAN);
+      } else {
+        out[r * d + e] = ok ? x[src * d + e] : NAN;
+      }
+      if (!ok && e == 0) atomicOr(bad, 1u);
     }
   }
 }
@@ -155,14 +162,15 @@ __device__ __forceinline__ double decode_sse_part(const uint8_t* __restrict__ co
   double acc = 0.0;
   const int per_row = d / VEC;
   const int64_t items = n * per_row;
-  for (int64_t p = blk * blockDim.x + threadIdx.x; p < items; p += nblk * blockDim.x) {
-    const int64_t row = p / per_row;
-    const int col = int(p - row * per_row) * VEC;
+  const int64_t stride = nblk * blockDim.x;
+  // item p: VEC consecutive elements of one row, all in one subspace
+  // item (row, col4) advanced incrementally: no division in the loop
+  auto one = [&](int64_t row, int c4, float (&cv)[VEC], float (&xv)[VEC], int64_t& off) {
+    const int col = c4 * VEC;
     const int sub = col / ds;
     const int t = col - sub * ds;
     const int code = codes[row * m + sub];
-    const int64_t off = row * d + col;
-    float cv[VEC];
+    off = row * d + col;
     const bool ok = code < ks;
     const float* c = c32 + ((int64_t)sub * ks + (ok ? code : 0)) * ds + t;
     if (VEC == 4) {
@@ -174,25 +182,61 @@ __device__ __forceinline__ double decode_sse_part(const uint8_t* __restrict__ co
     if (!ok)
 #pragma unroll
       for (int i = 0; i < VEC; ++i) cv[i] = NAN;
-    if (x_hat) {
-      if (VEC == 4) *reinterpret_cast<float4*>(x_hat + off) = make_float4(cv[0], cv[VEC > 1 ? 1 : 0], cv[VEC > 2 ? 2 : 0], cv[VEC > 3 ? 3 : 0]);
-      else x_hat[off] = cv[0];
-    }
     if (x) {
-      float xv[VEC];
       if (VEC == 4) {
         const float4 q = *reinterpret_cast<const float4*>(x + off);
         xv[0] = q.x; xv[VEC > 1 ? 1 : 0] = q.y; xv[VEC > 2 ? 2 : 0] = q.z; xv[VEC > 3 ? 3 : 0] = q.w;
       } else {
         xv[0] = x[off];
       }
+    }
+  };
+  auto finish = [&](const float (&cv)[VEC], const float (&xv)[VEC], int64_t off) {
+    if (x_hat) {
+      if (VEC == 4) *reinterpret_cast<float4*>(x_hat + off) = make_float4(cv[0], cv[VEC > 1 ? 1 : 0], cv[VEC > 2 ? 2 : 0], cv[VEC > 3 ? 3 : 0]);
+      else x_hat[off] = cv[0];
+    }
+    if (x) {
 #pragma unroll
       for (int i = 0; i < VEC; ++i) {
         const double df = (double)xv[i] - (double)cv[i];
         acc += df * df;
       }
     }
+  };
+  const int64_t p0 = blk * blockDim.x + threadIdx.x;
+  int64_t row = p0 / per_row;
+  int c4 = int(p0 - row * per_row);
+  const int64_t srow = stride / per_row;
+  const int scol = int(stride - srow * per_row);
+  auto advance = [&](int64_t& r, int& c) {
+    r += srow;
+    c += scol;
+    if (c >= per_row) {
+      c -= per_row;
+      ++r;
+    }
+  };
+  // two items in flight per iteration; the sum order per thread is item order
+  while (row < n) {
+    int64_t row1 = row;
+    int c41 = c4;
+    advance(row1, c41);
+    float c0[VEC], x0[VEC], c1[VEC], x1[VEC];
+    int64_t o0, o1;
+    one(row, c4, c0, x0, o0);
+    if (row1 < n) {
+      one(row1, c41, c1, x1, o1);
+      finish(c0, x0, o0);
+      finish(c1, x1, o1);
+      advance(row1, c41);
+    } else {
+      finish(c0, x0, o0);
+    }
+    row = row1;
+    c4 = c41;
   }
+  (void)items;
   return acc;
 }
 
@@ -329,7 +373,10 @@ int launch_zero_u32(uint32_t* p, size_t count, hipStream_t s) {
 
 int launch_gather_rows(const float* x, int64_t n, int d, const int64_t* rows, int64_t n_rows,
                        float* out, uint32_t* bad, hipStream_t s) {
-  k_gather_rows<<<grid_for(n_rows * d, kThreads, 8192), kThreads, 0, s>>>(x, n, d, rows, n_rows, out, bad);
+  const int vec4 = (d % 4 == 0) && (((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(out)) & 15) == 0);
+  const int per = vec4 ? d / 4 : d;
+  const int rpb = kThreads / per > 0 ? kThreads / per : 1;   // rows per block step
+  k_gather_rows<<<grid_for(n_rows, rpb, 8192), kThreads, 0, s>>>(x, n, d, rows, n_rows, out, bad, vec4);
   MIPQ_LAUNCHED("k_gather_rows");
   return MIPQ_OK;
 }

@@ -23,7 +23,7 @@ constexpr int kPackRed = 544;   // floats of LDS scratch for pack_subspace
 // stores them as the chunk's partials.
 // With GX the block also writes dL/dx = 2 g (x - c) (float64 product rounded to
 // float32, g = *gscale) for the reconstruction loss L = sum (x - x_hat)^2.
-template <bool GX>
+template <bool GX, bool OBJ, bool CHECK>
 __device__ __forceinline__ void accumulate_chunk(
     const float* __restrict__ x, int64_t n, int d, int m, int ks, int ds,
     const uint8_t* __restrict__ codes, const float* __restrict__ c32, int64_t rpc, int c, int sub,
@@ -36,7 +36,8 @@ __device__ __forceinline__ void accumulate_chunk(
   const int per = ks * ds;
   for (int i = threadIdx.x; i < ks * stride; i += blockDim.x) S[i] = 0.0;
   for (int i = threadIdx.x; i < ks; i += blockDim.x) cnt[i] = 0u;
-  for (int i = threadIdx.x; i < per; i += blockDim.x) cbs[i] = c32[(int64_t)sub * per + i];
+  if (OBJ)
+    for (int i = threadIdx.x; i < per; i += blockDim.x) cbs[i] = c32[(int64_t)sub * per + i];
   __syncthreads();
 
   const int lane = threadIdx.x & 63;
@@ -45,39 +46,51 @@ __device__ __forceinline__ void accumulate_chunk(
   const int g = lane / ds, t = lane - g * ds;
   const int64_t r0 = (int64_t)c * rpc;
   const int64_t r1 = min(n, r0 + rpc);
-  const int64_t step = (int64_t)(blockDim.x >> 6) * rpw;
+  const int64_t step = (int64_t)(blockDim.x >> 6) * rpw;   // rows between a lane's consecutive rows
+  const int64_t first = r0 + (int64_t)wave * rpw + g;
+  // this lane's rows: first, first + step, ... below r1
+  const int64_t nrows = (g < rpw && first < r1) ? (r1 - first + step - 1) / step : 0;
+  const float* xp = x + first * d + (int64_t)sub * ds + t;
+  const uint8_t* cp = codes + first * m + sub;
+  float* gp = GX ? grad_x + first * d + (int64_t)sub * ds + t : nullptr;
+  const int64_t xs = step * d, cs = step * m;
   double jl = 0.0;
   const double g2 = GX ? 2.0 * (gscale ? *gscale : 1.0) : 0.0;
-  constexpr int U = 8;   // rows in flight per lane
-  if (g < rpw && r0 < r1) {
-    for (int64_t row0 = r0 + (int64_t)wave * rpw + g; row0 < r1; row0 += step * U) {
-      int code[U];
-      float xv[U];
-      // clamped, unconditional loads: all U rows are in flight together
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t row = row0 + u * step;
-        const int64_t rc = row < r1 ? row : row0;
-        const int cd = (int)codes[rc * m + sub];
-        code[u] = row < r1 ? cd : -1;
-        xv[u] = x[rc * d + (int64_t)sub * ds + t];
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (code[u] < 0) continue;
-        const int64_t gi = (row0 + u * step) * d + (int64_t)sub * ds + t;
-        if (code[u] >= ks) {   // corrupt code: poison the objective, touch no sum
-          jl += NAN;
-          if (GX) grad_x[gi] = NAN;
-          continue;
-        }
-        const double df = (double)xv[u] - (double)cbs[code[u] * ds + t];
-        jl += df * df;
-        if (GX) grad_x[gi] = (float)(g2 * df);
-        atomicAdd(&S[code[u] * stride + t], (double)xv[u]);
-        if (t == 0) atomicAdd(&cnt[code[u]], 1u);
-      }
+  auto add_row = [&](int code, float xv, int64_t off) {
+    if (CHECK && code >= ks) {   // corrupt code: poison the objective, touch no sum
+      jl += NAN;
+      if (GX) gp[off] = NAN;
+      return;
     }
+    if (OBJ) {
+      const double df = (double)xv - (double)cbs[code * ds + t];
+      jl += df * df;
+      if (GX) gp[off] = (float)(g2 * df);
+    }
+    atomicAdd(&S[code * stride + t], (double)xv);
+    if (t == 0) atomicAdd(&cnt[code], 1u);
+  };
+  constexpr int U = 8;   // rows in flight per lane
+  int64_t i = 0;
+  for (; i + U <= nrows; i += U) {
+    int code[U];
+    float xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      code[u] = (int)cp[u * cs];
+      xv[u] = xp[u * xs];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) add_row(code[u], xv[u], u * xs);
+    xp += U * xs;
+    cp += U * cs;
+    if (GX) gp += U * xs;
+  }
+  for (; i < nrows; ++i) {
+    add_row((int)cp[0], xp[0], 0);
+    xp += xs;
+    cp += cs;
+    if (GX) gp += xs;
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) jl += __shfl_xor(jl, off, 64);
@@ -97,7 +110,7 @@ __device__ __forceinline__ void accumulate_chunk(
 }
 
 // One problem: block (c, j) = chunk c, subspace j.
-template <bool GX>
+template <bool GX, bool OBJ, bool CHECK>
 __global__ __launch_bounds__(kUpdThreads) void k_accumulate(
     const float* __restrict__ x, int64_t n, int d, int m, int ks, int ds,
     const uint8_t* __restrict__ codes, const float* __restrict__ c32, int64_t rpc,
@@ -105,8 +118,8 @@ __global__ __launch_bounds__(kUpdThreads) void k_accumulate(
     const double* __restrict__ gscale, float* __restrict__ grad_x) {
   extern __shared__ double smem[];
   __shared__ double redj[kUpdThreads / 64];
-  accumulate_chunk<GX>(x, n, d, m, ks, ds, codes, c32, rpc, blockIdx.x, blockIdx.y, part_s, part_cnt, part_j,
-                       gscale, grad_x, smem, redj);
+  accumulate_chunk<GX, OBJ, CHECK>(x, n, d, m, ks, ds, codes, c32, rpc, blockIdx.x, blockIdx.y, part_s, part_cnt,
+                                   part_j, gscale, grad_x, smem, redj);
 }
 
 // the last problem p with key(p) <= i (problems in ascending key order)
@@ -137,8 +150,9 @@ __global__ __launch_bounds__(kUpdThreads) void k_accumulate_batched(const BatchP
   const int local = (int)(i - item0);
   const int c = local / m, sub = local - (local / m) * m;
   const size_t per = (size_t)ks * ds;
-  accumulate_chunk<false>(probs[p].x, probs[p].n, d, m, ks, ds, probs[p].codes, probs[p].c32, probs[p].rpc, c, sub,
-                          part_s + item0 * per, part_cnt + item0 * ks, part_j + item0, nullptr, nullptr, smem, redj);
+  accumulate_chunk<false, true, false>(probs[p].x, probs[p].n, d, m, ks, ds, probs[p].codes, probs[p].c32,
+                                       probs[p].rpc, c, sub, part_s + item0 * per, part_cnt + item0 * ks,
+                                       part_j + item0, nullptr, nullptr, smem, redj);
 }
 
 // Subspace sub: sums the chunk partials in chunk order, centroid = sum /
@@ -330,7 +344,7 @@ int update_chunks(int64_t n, int m) {
 
 int launch_update(const float* x, int64_t n, int d, int m, int ks, const uint8_t* codes, float* c32,
                   double* c64, int nch, double* part_s, uint32_t* part_cnt, double* part_j,
-                  double* j_sub, void* aop, float* cmax, float* mu, hipStream_t s) {
+                  double* j_sub, void* aop, float* cmax, float* mu, bool objective, hipStream_t s) {
   const int ds = d / m;
   const int64_t rpc = (n + nch - 1) / nch;
   {
@@ -338,8 +352,12 @@ int launch_update(const float* x, int64_t n, int d, int m, int ks, const uint8_t
                        (size_t)ks * ds * sizeof(float);
     dim3 grid(nch, m);
     ProfScope ps(MIPQ_K_UPDATE, s);
-    k_accumulate<false><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, part_s, part_cnt,
-                                                       part_j, nullptr, nullptr);
+    if (objective)
+      k_accumulate<false, true, false><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, part_s,
+                                                                      part_cnt, part_j, nullptr, nullptr);
+    else
+      k_accumulate<false, false, false><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, part_s,
+                                                                       part_cnt, part_j, nullptr, nullptr);
     MIPQ_LAUNCHED("k_accumulate");
   }
   const int nt = tiles_for(ks);
@@ -375,11 +393,11 @@ int launch_backward(const float* x, int64_t n, int d, int m, int ks, const uint8
     dim3 grid(nch, m);
     ProfScope ps(MIPQ_K_BACKWARD, s);
     if (grad_x)
-      k_accumulate<true><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, part_s, part_cnt,
-                                                        part_j, gscale, grad_x);
+      k_accumulate<true, true, true><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, part_s,
+                                                                    part_cnt, part_j, gscale, grad_x);
     else
-      k_accumulate<false><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, part_s, part_cnt,
-                                                         part_j, nullptr, nullptr);
+      k_accumulate<false, true, true><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, part_s,
+                                                                     part_cnt, part_j, nullptr, nullptr);
     MIPQ_LAUNCHED("k_accumulate");
   }
   k_grad_codebook<<<m, kUpdThreads, 0, s>>>(m, ks, ds, nch, part_s, part_cnt, part_j, c32, gscale, grad_c,
