@@ -109,16 +109,33 @@ __device__ __forceinline__ void accumulate_chunk(
   }
 }
 
-// One problem: block (c, j) = chunk c, subspace j.
+// Block -> (chunk, subspace) so that the m blocks of one chunk run on one XCD
+// (hardware block id mod 8) next to each other: they read the same rows, which
+// then come from that XCD's L2.  Chunks go round-robin over the XCDs.
+struct ChunkMap {
+  int64_t chunk;
+  int sub;
+};
+__device__ __forceinline__ ChunkMap chunk_map(int64_t b, int m) {
+  const int64_t xcd = b & 7, slot = b >> 3;
+  ChunkMap r;
+  r.chunk = (slot / m) * 8 + xcd;
+  r.sub = (int)(slot - (slot / m) * m);
+  return r;
+}
+
+// One problem: chunk c, subspace j (see chunk_map).
 template <bool GX, bool OBJ, bool CHECK>
 __global__ __launch_bounds__(kUpdThreads) void k_accumulate(
     const float* __restrict__ x, int64_t n, int d, int m, int ks, int ds,
-    const uint8_t* __restrict__ codes, const float* __restrict__ c32, int64_t rpc,
+    const uint8_t* __restrict__ codes, const float* __restrict__ c32, int64_t rpc, int nch,
     double* __restrict__ part_s, uint32_t* __restrict__ part_cnt, double* __restrict__ part_j,
     const double* __restrict__ gscale, float* __restrict__ grad_x) {
   extern __shared__ double smem[];
   __shared__ double redj[kUpdThreads / 64];
-  accumulate_chunk<GX, OBJ, CHECK>(x, n, d, m, ks, ds, codes, c32, rpc, blockIdx.x, blockIdx.y, part_s, part_cnt,
+  const ChunkMap cm = chunk_map(blockIdx.x, m);
+  if (cm.chunk >= nch) return;   // padding of the grid (every chunk's partials are written)
+  accumulate_chunk<GX, OBJ, CHECK>(x, n, d, m, ks, ds, codes, c32, rpc, (int)cm.chunk, cm.sub, part_s, part_cnt,
                                    part_j, gscale, grad_x, smem, redj);
 }
 
@@ -138,13 +155,15 @@ __device__ __forceinline__ int find_problem(const BatchProb* __restrict__ probs,
 // subspace j) with items problem-major, then chunk, then subspace; problem p's
 // partials use the single-problem layout at offset item0.
 __global__ __launch_bounds__(kUpdThreads) void k_accumulate_batched(const BatchProb* __restrict__ probs, int nprob,
-                                                                    int d, int m, int ks, int ds,
+                                                                    int64_t items, int d, int m, int ks, int ds,
                                                                     double* __restrict__ part_s,
                                                                     uint32_t* __restrict__ part_cnt,
                                                                     double* __restrict__ part_j) {
   extern __shared__ double smem[];
   __shared__ double redj[kUpdThreads / 64];
-  const int64_t i = blockIdx.x;
+  const ChunkMap cmap = chunk_map(blockIdx.x, m);
+  const int64_t i = cmap.chunk * m + cmap.sub;   // item: chunks of all problems in order, then subspace
+  if (i >= items) return;
   const int p = find_problem(probs, nprob, i, [](const BatchProb& b) { return b.item0; });
   const int64_t item0 = probs[p].item0;
   const int local = (int)(i - item0);
@@ -350,13 +369,13 @@ int launch_update(const float* x, int64_t n, int d, int m, int ks, const uint8_t
   {
     const size_t shm = (size_t)ks * (ds + 1) * sizeof(double) + ((ks + 1) / 2) * sizeof(double) +
                        (size_t)ks * ds * sizeof(float);
-    dim3 grid(nch, m);
+    const unsigned grid = (unsigned)(((nch + 7) / 8) * 8 * m);
     ProfScope ps(MIPQ_K_UPDATE, s);
     if (objective)
-      k_accumulate<false, true, false><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, part_s,
+      k_accumulate<false, true, false><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, nch, part_s,
                                                                       part_cnt, part_j, nullptr, nullptr);
     else
-      k_accumulate<false, false, false><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, part_s,
+      k_accumulate<false, false, false><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, nch, part_s,
                                                                        part_cnt, part_j, nullptr, nullptr);
     MIPQ_LAUNCHED("k_accumulate");
   }
@@ -390,13 +409,13 @@ int launch_backward(const float* x, int64_t n, int d, int m, int ks, const uint8
   {
     const size_t shm = (size_t)ks * (ds + 1) * sizeof(double) + ((ks + 1) / 2) * sizeof(double) +
                        (size_t)ks * ds * sizeof(float);
-    dim3 grid(nch, m);
+    const unsigned grid = (unsigned)(((nch + 7) / 8) * 8 * m);
     ProfScope ps(MIPQ_K_BACKWARD, s);
     if (grad_x)
-      k_accumulate<true, true, true><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, part_s,
+      k_accumulate<true, true, true><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, nch, part_s,
                                                                     part_cnt, part_j, gscale, grad_x);
     else
-      k_accumulate<false, true, true><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, part_s,
+      k_accumulate<false, true, true><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, nch, part_s,
                                                                      part_cnt, part_j, nullptr, nullptr);
     MIPQ_LAUNCHED("k_accumulate");
   }
@@ -441,8 +460,9 @@ int launch_update_batched(const BatchProb* probs, int nprob, int64_t items, int 
     const size_t shm = (size_t)ks * (ds + 1) * sizeof(double) + ((ks + 1) / 2) * sizeof(double) +
                        (size_t)ks * ds * sizeof(float);
     ProfScope ps(MIPQ_K_UPDATE, s);
-    k_accumulate_batched<<<(unsigned)items, kUpdThreads, shm, s>>>(probs, nprob, d, m, ks, ds, part_s, part_cnt,
-                                                                   part_j);
+    const int64_t chunks = items / m;
+    const unsigned grid = (unsigned)(((chunks + 7) / 8) * 8 * m);
+    k_accumulate_batched<<<grid, kUpdThreads, shm, s>>>(probs, nprob, items, d, m, ks, ds, part_s, part_cnt, part_j);
     MIPQ_LAUNCHED("k_accumulate_batched");
   }
   const int nt = tiles_for(ks);
