@@ -194,6 +194,17 @@ int mipq_plan_info(const mipq_plan* plan, int64_t* info, int count);
 int mipq_plan_destroy(mipq_plan* plan);
 
 /* -------------------------------------------------------------------------
+ * Decoded centroids (paper Section 3: every chunk returns its centroids as
+ * rows, which are pooled into a centroid dataset for the global fit).
+ *
+ *   codebooks  float32 [nbooks][m][ks][ds]
+ *   out        OUT float32 [nbooks*ks][d]: row b*ks + k is the decode of the
+ *              code row (k, k, ..., k) with codebook b
+ * ------------------------------------------------------------------------- */
+int mipq_pq_decode_centroids(const float* codebooks, int64_t nbooks, int d, int m, int ks, float* out,
+                              void* stream);
+
+/* -------------------------------------------------------------------------
  * Inverted file (paper Section 2.2: the ids of rows are stored per bucket and
  * a query returns its first to k-th nearest neighbours).  Buckets are coarse
  * k-means lists; each row stores the PQ codes of its residual x - c_list.

@@ -261,7 +261,8 @@ class BatchedFit:
     """
 
     def __init__(self, xs, init_rows, m: int, ks: int, iters: int, precision="bf16", plan: bool = True,
-                 autotune: bool = True, graph: bool = True, objective: bool = True, sse: bool = True):
+                 autotune: bool = True, graph: bool = True, objective: bool = True, sse: bool = True,
+                 codebooks: torch.Tensor | None = None):
         L = lib()
         if len(xs) != len(init_rows) or not xs:
             raise ValueError("need one init_rows tensor per problem (and at least one problem)")
@@ -278,8 +279,14 @@ class BatchedFit:
         ds = d // m if m else 0
         self.results = []
         table = (MipqProblem * len(self.xs))()
+        if codebooks is not None:   # caller's contiguous [nprob, m, ks, ds] storage
+            if codebooks.shape != (len(self.xs), m, ks, ds) or not codebooks.is_contiguous():
+                raise ValueError("codebooks must be a contiguous [nprob, m, ks, d/m] tensor")
+            codebooks = _dev(codebooks, torch.float32, "codebooks")
+        self.codebooks = codebooks
         for i, (x, r) in enumerate(zip(self.xs, self.init_rows)):
-            res = {"codebook": torch.empty((m, ks, ds), dtype=torch.float32, device=dev),
+            res = {"codebook": codebooks[i] if codebooks is not None else
+                   torch.empty((m, ks, ds), dtype=torch.float32, device=dev),
                    "codes": torch.empty((x.shape[0], m), dtype=torch.uint8, device=dev)}
             if sse:
                 res["sse_rmse"] = torch.empty(2, dtype=torch.float64, device=dev)
@@ -352,10 +359,22 @@ def two_level_fit(xs, chunk_inits, global_init, m: int, ks: int, iters: int, pre
     Returns dict(pool float32 [chunks*ks, d], codebook float32 [m, ks, d/m],
     chunk_codebooks list).
     """
-    b = BatchedFit(xs, chunk_inits, m, ks, iters, precision="bf16", plan=False, objective=False, sse=False)
+    dev = xs[0].device
+    d = xs[0].shape[1]
+    books = torch.empty((len(xs), m, ks, d // m), dtype=torch.float32, device=dev)
+    b = BatchedFit(xs, chunk_inits, m, ks, iters, precision="bf16", plan=False, objective=False, sse=False,
+                   codebooks=books)
     b.run()
-    dev = b.device
-    kk = torch.arange(ks, device=dev, dtype=torch.int32).to(torch.uint8).unsqueeze(1).repeat(1, m).contiguous()
-    pool = torch.cat([pq_decode_rmse(kk, r["codebook"], x_hat=True)[0] for r in b.results])
+    pool = decode_centroids(books)
     g = pq_fit(pool, m, ks, iters, init_rows=global_init, precision=precision, labels=False, objective=False)
     return {"pool": pool, "codebook": g["codebook"], "chunk_codebooks": [r["codebook"] for r in b.results]}
+
+
+def decode_centroids(codebooks: torch.Tensor) -> torch.Tensor:
+    """[nbooks, m, ks, ds] codebooks -> float32 [nbooks*ks, m*ds]: row b*ks + k
+    is the decode of the code row (k, ..., k) with codebook b."""
+    cb = _dev(codebooks, torch.float32, "codebooks")
+    nb, m, ks, ds = cb.shape
+    out = torch.empty((nb * ks, m * ds), dtype=torch.float32, device=cb.device)
+    check(lib().mipq_pq_decode_centroids(_ptr(cb), nb, m * ds, m, ks, _ptr(out), _stream(cb.device)))
+    return out

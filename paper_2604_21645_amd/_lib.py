@@ -31,6 +31,7 @@ SIGNATURES = {
     "mipq_pq_encode": (_I, [_P, _L, _I, _I, _I, _P, _I, _P, _P, _P, _S, _P]),
     "mipq_pq_decode_rmse_workspace_size": (_S, [_L, _I, _I, _I]),
     "mipq_pq_decode_rmse": (_I, [_P, _L, _I, _I, _I, _P, _P, _P, _P, _P, _S, _P]),
+    "mipq_pq_decode_centroids": (_I, [_P, _L, _I, _I, _I, _P, _P]),
     "mipq_recon_backward_workspace_size": (_S, [_L, _I, _I, _I]),
     "mipq_recon_backward": (_I, [_P, _P, _P, _L, _I, _I, _I, _P, _P, _P, _P, _P, _S, _P]),
     "mipq_coarse_assign_workspace_size": (_S, [_I, _I, _I]),

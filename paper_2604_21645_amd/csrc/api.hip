@@ -234,6 +234,15 @@ int mipq_pq_decode_rmse(const uint8_t* codes, int64_t n, int d, int m, int ks, c
   return MIPQ_OK;
 }
 
+int mipq_pq_decode_centroids(const float* codebooks, int64_t nbooks, int d, int m, int ks, float* out,
+                              void* stream) {
+  int rc;
+  if (nbooks < 0) return fail(MIPQ_EINVAL, "nbooks must be >= 0");
+  if ((rc = check_shape(0, d, m, ks, MIPQ_FP32, false))) return rc;
+  if (nbooks > 0 && (!codebooks || !out)) return fail(MIPQ_EINVAL, "codebooks and out are required");
+  return launch_decode_centroids(codebooks, nbooks, m, ks, d / m, out, static_cast<hipStream_t>(stream));
+}
+
 size_t mipq_recon_backward_workspace_size(int64_t n, int d, int m, int ks) {
   if (check_shape(n, d, m, ks, MIPQ_FP32, true) != MIPQ_OK) return 0;
   const int nch = backward_chunks(n, m);

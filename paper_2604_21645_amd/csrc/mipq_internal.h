@@ -107,6 +107,7 @@ int launch_copy_f64(const double* src, double* dst, size_t count, hipStream_t s)
 int launch_decode_sse(const uint8_t* codes, int64_t n, int d, int m, int ks, const float* c32,
                       const float* x, float* x_hat, double* partials, int nblk, hipStream_t s);
 int decode_blocks(int64_t n, int m);
+int launch_decode_centroids(const float* cb, int64_t nbooks, int m, int ks, int ds, float* out, hipStream_t s);
 int launch_sse_final(const double* partials, int nblk, int64_t n, int d, double* out, hipStream_t s);
 
 // BF16 matrix-core path

@@ -355,6 +355,23 @@ __global__ void k_objective_batched(const BatchProb* __restrict__ probs, int npr
   out[r] = s;
 }
 
+// Decoded centroids of many codebooks: out[(b*ks + k)*d + j*ds + t] =
+// cb[((b*m + j)*ks + k)*ds + t], i.e. row k of book b is the decode of the code
+// row (k, k, ..., k).
+__global__ void k_decode_centroids(const float* __restrict__ cb, int64_t nbooks, int m, int ks, int ds,
+                                   float* __restrict__ out) {
+  const int d = m * ds;
+  const int64_t total = nbooks * ks * d;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t bk = i / d;   // b * ks + k
+    const int col = int(i - bk * d);
+    const int j = col / ds, t = col - j * ds;
+    const int64_t b = bk / ks;
+    const int k = int(bk - b * ks);
+    out[i] = cb[((b * m + j) * ks + k) * ds + t];
+  }
+}
+
 int grid_for(int64_t work, int per_block, int cap) {
   int64_t g = (work + per_block - 1) / per_block;
   if (g < 1) g = 1;
@@ -485,6 +502,14 @@ int launch_objective_batched(const BatchProb* probs, int nprob, int iters, int m
   if (iters <= 0) return MIPQ_OK;
   k_objective_batched<<<ceil_div((int64_t)nprob * iters, 64), 64, 0, s>>>(probs, nprob, iters, m, j_all);
   MIPQ_LAUNCHED("k_objective_batched");
+  return MIPQ_OK;
+}
+
+int launch_decode_centroids(const float* cb, int64_t nbooks, int m, int ks, int ds, float* out, hipStream_t s) {
+  const int64_t total = nbooks * ks * (int64_t)m * ds;
+  if (total == 0) return MIPQ_OK;
+  k_decode_centroids<<<grid_for(total, kThreads, 8192), kThreads, 0, s>>>(cb, nbooks, m, ks, ds, out);
+  MIPQ_LAUNCHED("k_decode_centroids");
   return MIPQ_OK;
 }
 

@@ -352,9 +352,11 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_bf16_batched(const BatchP
 
 }  // namespace
 
-// about one 1024-thread block per CU over all (chunk, subspace) pairs
+// at least 4096 rows per chunk (the block's fixed cost of clearing and
+// storing its sums stays small), at most about one 1024-thread block per CU
+// over all (chunk, subspace) pairs
 int update_chunks(int64_t n, int m) {
-  int nch = ceil_div(n, 1024);
+  int nch = ceil_div(n, 4096);
   int cap = 256 / m;
   if (cap < 1) cap = 1;
   if (nch > cap) nch = cap;

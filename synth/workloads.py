@@ -161,6 +161,38 @@ def batched_uneven(seed: int = 3, n_prob: int = 64, n_lo: int = 20_000, n_hi: in
 
 
 @dataclass
+class ChunkedWorkload:
+    """Rows split into equal chunks (the paper's chunked layout), for the
+    two-level fit: per-chunk init rows and init rows of the pooled centroids."""
+    x: np.ndarray
+    chunk_rows: int
+    chunk_inits: list
+    global_init: np.ndarray
+    m: int
+    ks: int
+    iters: int
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def chunks(self):
+        return [self.x[i:i + self.chunk_rows] for i in range(0, self.x.shape[0], self.chunk_rows)]
+
+
+def soil_chunks(seed: int = 6, n_chunks: int = 400, chunk_rows: int = 16_750, d: int = 48, n_comp: int = 500,
+                m: int = 8, ks: int = 256, iters: int = 20, sigma: float = 0.08) -> ChunkedWorkload:
+    """Stand-in with the shape of the paper's data: 6.7M x 48 rows in 400
+    chunks of 16,750 rows (Section 3's SoilGrids sample, which is not
+    available).  A Gaussian mixture of ``n_comp`` components, means
+    U[0,1)^48; M=8 gives 6-dimensional subspaces."""
+    x = gaussian_mixture(seed, n_chunks * chunk_rows, d, n_comp, sigma=sigma)
+    inits = [init_rows_per_subspace(seed, chunk_rows, m, ks, key=i) for i in range(n_chunks)]
+    ginit = init_rows_per_subspace(seed, n_chunks * ks, m, ks, key=n_chunks + 1)
+    return ChunkedWorkload(x, chunk_rows, inits, ginit, m, ks, iters,
+                           meta=dict(seed=seed, n_chunks=n_chunks, chunk_rows=chunk_rows, d=d, n_comp=n_comp,
+                                     sigma=sigma))
+
+
+@dataclass
 class IvfWorkload:
     """Inverted index with residual PQ, plus queries from the same mixture."""
     x: np.ndarray

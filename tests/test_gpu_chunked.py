@@ -62,3 +62,38 @@ def test_two_level_rmse_beside_a_single_global_fit():
     r2, r1 = sr2[1].item(), sr1[1].item()
     print("RMSE two-level %.4f single %.4f relative gap %.4f" % (r2, r1, (r2 - r1) / r1), flush=True)
     assert np.isfinite(r2) and r2 > 0 and abs(r2 - r1) / r1 < 0.25
+
+
+def test_decode_centroids_is_the_transposed_codebooks():
+    rng = np.random.default_rng(3)
+    books = rng.standard_normal((5, 6, 37, 8)).astype(np.float32)
+    out = mipq.decode_centroids(_t(books)).cpu().numpy()
+    ref = np.concatenate([chunked.decoded_centroids(b) for b in books])
+    np.testing.assert_array_equal(out, ref)
+
+
+def test_soil_shaped_two_level_pipeline_sampled():
+    """400 chunks x 16,750 rows x 48 (ds = 6): two-level fit, encode all rows,
+    RMSE; sampled codes and the pool against the oracle."""
+    w = wl.soil_chunks()
+    xt = _t(w.x)
+    xs = list(torch.split(xt, w.chunk_rows))
+    out = mipq.two_level_fit(xs, [_t(i) for i in w.chunk_inits], _t(w.global_init), w.m, w.ks, w.iters)
+    pool = out["pool"].cpu().numpy()
+    books = [b.cpu().numpy() for b in out["chunk_codebooks"]]
+    for c in (0, 199, 399):
+        np.testing.assert_array_equal(pool[c * w.ks:(c + 1) * w.ks], chunked.decoded_centroids(books[c]))
+        rows = np.random.default_rng(c).choice(w.chunk_rows, 200, replace=False)
+        # encoding a chunk with its own codebook follows the exact rule
+        xc = w.chunks[c]
+        codes = mipq.pq_encode(_t(xc), out["chunk_codebooks"][c], "bf16").cpu().numpy().astype(np.int64)
+        ref, _ = pq.encode(xc[rows], books[c].astype(np.float64), decide="fp32")
+        np.testing.assert_array_equal(codes[rows], ref)
+    cb = out["codebook"]
+    codes = mipq.pq_encode(xt, cb, "bf16")
+    _, sr = mipq.pq_decode_rmse(codes, cb, xt)
+    rows = np.random.default_rng(9).choice(w.x.shape[0], 3000, replace=False)
+    ref, _ = pq.encode(w.x[rows], cb.cpu().numpy().astype(np.float64), decide="fp32")
+    np.testing.assert_array_equal(codes.cpu().numpy()[rows].astype(np.int64), ref)
+    print("soil-shaped two-level RMSE %.5f" % sr[1].item(), flush=True)
+    assert np.isfinite(sr[1].item())
