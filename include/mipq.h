@@ -251,6 +251,45 @@ int mipq_ii_build(const float* x, int64_t n, int d, int kc, int coarse_iters, co
                   double* coarse_objective, void* ws, size_t ws_bytes, void* stream);
 
 /* -------------------------------------------------------------------------
+ * Index built piecewise (paper Section 3.1.2, the index library: codes are
+ * added to an index and indexes are merged, which is how the index is built
+ * in parallel over the data chunks of Section 3).
+ *
+ * mipq_ii_add: the posting lists of rows x [n][d] under fixed quantisers
+ *   (coarse float32 [kc][d], pq_codebook float32 [m][ks][d/m], e.g. those of
+ *   an mipq_ii_build): coarse labels, residual codes and stable bucketing,
+ *   exactly as the last two steps of mipq_ii_build.  Outputs as there:
+ *   offsets int64 [kc+1], ids int32 [n] (row ids 0..n-1 of this x, ascending
+ *   inside a list), codes_sorted uint8 [n][m], optional labels int32 [n].
+ *   n == 0 is valid (all offsets 0).  precision: MIPQ_FP32 or MIPQ_BF16 as
+ *   in mipq_ii_build; the code rule and the coarse rule make every row's
+ *   label and code independent of the other rows, so adding the rows of
+ *   consecutive chunks and merging gives the lists of one call on all rows.
+ *
+ * mipq_ii_merge: concatenates nparts indexes over consecutive row ranges
+ *   (part p covers rows base_p .. base_p + part_n[p] - 1, base_p = sum of
+ *   part_n of the parts before it).  List l of the result is list l of part
+ *   0, then of part 1, ..., with every id shifted by its part's base.
+ *   part_offsets[p] (int64 [kc+1]), part_ids[p] (int32 [part_n[p]]) and
+ *   part_codes[p] (uint8 [part_n[p]][m]) are DEVICE pointers held in HOST
+ *   arrays of length nparts; the parts must be valid indexes of this kc and
+ *   m (offsets non-decreasing from 0 to part_n[p], ids in [0, part_n[p])),
+ *   which the call does not check on the device.  Outputs: offsets int64
+ *   [kc+1], ids int32 [sum part_n], codes_sorted uint8 [sum part_n][m].
+ *   The call copies the part table into the workspace and waits for that
+ *   copy on the stream before it returns (the kernels stay queued).
+ *   Requirements: 1 <= nparts, kc <= 65536, m <= 256, sum part_n < 2^31.
+ * ------------------------------------------------------------------------- */
+size_t mipq_ii_add_workspace_size(int64_t n, int d, int kc, int m, int ks, int precision);
+int mipq_ii_add(const float* x, int64_t n, int d, const float* coarse, int kc, const float* pq_codebook, int m,
+                int ks, int precision, int64_t* offsets, int32_t* ids, uint8_t* codes_sorted, int32_t* labels,
+                void* ws, size_t ws_bytes, void* stream);
+size_t mipq_ii_merge_workspace_size(int nparts, int kc);
+int mipq_ii_merge(const int64_t* const* part_offsets, const int32_t* const* part_ids,
+                  const uint8_t* const* part_codes, const int64_t* part_n, int nparts, int kc, int m,
+                  int64_t* offsets, int32_t* ids, uint8_t* codes_sorted, void* ws, size_t ws_bytes, void* stream);
+
+/* -------------------------------------------------------------------------
  * ADC search over an index built by mipq_ii_build (paper Section 2.2: the
  * first to k-th nearest neighbours of a query).
  *

@@ -117,6 +117,37 @@ def build(x: np.ndarray, train_rows: np.ndarray, coarse_init: np.ndarray, coarse
                 code_ties=ctie, offsets=offsets, ids=ids)
 
 
+def add(x: np.ndarray, cc: np.ndarray, pq_cb: np.ndarray, decide: str = "kernel"):
+    """Index of the rows ``x`` under fixed quantisers (the library's "add codes"
+    step of Section 3.1.2): labels, residual codes and posting lists, with the
+    row ids 0..n-1 of this ``x``."""
+    cc32 = np.asarray(cc, np.float32)
+    labels, _ = coarse_assign(x, cc32 if decide != "fp64" else cc, decide)
+    codes, _ = pq.encode(residuals(x, labels, cc32), pq_cb, decide="fp32" if decide != "fp64" else "fp64")
+    offsets, ids = posting_lists(labels, cc32.shape[0])
+    return dict(labels=labels, codes=codes, offsets=offsets, ids=ids)
+
+
+def merge(parts):
+    """One index from indexes over consecutive row ranges (the library's
+    "merge" step of Section 3.1.2).  ``parts``: dicts with offsets, ids and
+    codes (codes by the part's own row id).  List l of the result is list l
+    of part 0, then of part 1, ..., every id shifted by the number of rows in
+    the parts before its own."""
+    kc = len(parts[0]["offsets"]) - 1
+    base, lists, codes = 0, [[] for _ in range(kc)], []
+    for p in parts:
+        off, ids = p["offsets"], p["ids"]
+        for l in range(kc):
+            lists[l].append(np.asarray(ids[off[l]:off[l + 1]], np.int64) + base)
+        codes.append(p["codes"])
+        base += len(p["ids"])
+    flat = [np.concatenate(ls) for ls in lists]
+    offsets = np.zeros(kc + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum([len(f) for f in flat])
+    return dict(offsets=offsets, ids=np.concatenate(flat), codes=np.concatenate(codes))
+
+
 def adc_lut(q: np.ndarray, c_list: np.ndarray, pq_cb: np.ndarray) -> np.ndarray:
     """LUT[j][k] for one (query, list): subspace distance of (q - c_list) to C_j[k]."""
     m, ks, ds = pq_cb.shape

@@ -225,6 +225,73 @@ def ii_build(x: torch.Tensor, kc: int, coarse_iters: int, train_rows: torch.Tens
     return out
 
 
+def ii_add(x: torch.Tensor, coarse: torch.Tensor, pq_codebook: torch.Tensor, precision="bf16",
+           labels: bool = False):
+    """Posting lists of the rows ``x`` under fixed quantisers (``mipq_ii_add``):
+    dict with coarse, pq_codebook (the given ones), offsets, ids (0..n-1 of
+    this ``x``), codes_sorted and, on request, labels."""
+    L = lib()
+    x = _dev(x, torch.float32, "x")
+    cc = _dev(coarse, torch.float32, "coarse")
+    pqc = _dev(pq_codebook, torch.float32, "pq_codebook")
+    dev = x.device
+    n, d = x.shape
+    kc = cc.shape[0]
+    m, ks, _ = pqc.shape
+    p = _prec(precision)
+    out = {
+        "coarse": cc,
+        "pq_codebook": pqc,
+        "offsets": torch.empty(kc + 1, dtype=torch.int64, device=dev),
+        "ids": torch.empty(n, dtype=torch.int32, device=dev),
+        "codes_sorted": torch.empty((n, m), dtype=torch.uint8, device=dev),
+    }
+    if labels:
+        out["labels"] = torch.empty(n, dtype=torch.int32, device=dev)
+    ws = _ws(L.mipq_ii_add_workspace_size(n, d, kc, m, ks, p), dev)
+    check(L.mipq_ii_add(_ptr(x), n, d, _ptr(cc), kc, _ptr(pqc), m, ks, p, _ptr(out["offsets"]), _ptr(out["ids"]),
+                        _ptr(out["codes_sorted"]), _ptr(out.get("labels")), _ptr(ws), ws.numel(), _stream(dev)))
+    return out
+
+
+def ii_merge(parts):
+    """One index from indexes over consecutive row ranges (``mipq_ii_merge``):
+    list l is list l of every part in order, ids shifted by the rows of the
+    parts before.  ``parts``: dicts from ``ii_add`` / ``ii_build`` sharing
+    the quantisers of the first."""
+    L = lib()
+    if not parts:
+        raise ValueError("need at least one part")
+    first = parts[0]
+    cc, pqc = first["coarse"], first["pq_codebook"]
+    dev = cc.device
+    kc = cc.shape[0]
+    m = pqc.shape[0]
+    offs = [_dev(p["offsets"], torch.int64, "offsets") for p in parts]
+    ids = [_dev(p["ids"], torch.int32, "ids") for p in parts]
+    codes = [_dev(p["codes_sorted"], torch.uint8, "codes_sorted") for p in parts]
+    if any(o.numel() != kc + 1 for o in offs) or any(c.dim() != 2 or c.shape[1] != m for c in codes):
+        raise ValueError("every part needs kc + 1 offsets and m codes per row")
+    ns = [int(i.numel()) for i in ids]
+    total = sum(ns)
+    k = len(parts)
+    out = {
+        "coarse": cc,
+        "pq_codebook": pqc,
+        "offsets": torch.empty(kc + 1, dtype=torch.int64, device=dev),
+        "ids": torch.empty(total, dtype=torch.int32, device=dev),
+        "codes_sorted": torch.empty((total, m), dtype=torch.uint8, device=dev),
+    }
+    po = (ctypes.c_void_p * k)(*[_ptr(o) for o in offs])
+    pi = (ctypes.c_void_p * k)(*[_ptr(i) for i in ids])
+    pc = (ctypes.c_void_p * k)(*[_ptr(c) for c in codes])
+    pn = (ctypes.c_int64 * k)(*ns)
+    ws = _ws(L.mipq_ii_merge_workspace_size(k, kc), dev)
+    check(L.mipq_ii_merge(po, pi, pc, pn, k, kc, m, _ptr(out["offsets"]), _ptr(out["ids"]),
+                          _ptr(out["codes_sorted"]), _ptr(ws), ws.numel(), _stream(dev)))
+    return out
+
+
 def adc_search(q: torch.Tensor, index: dict, nprobe: int, topk: int, wide: bool = False):
     """Top-k (ids int32 [nq, topk], distances float32 [nq, topk]) per query
     over an index from ``ii_build``; optionally the int64 number of queries

@@ -39,6 +39,10 @@ SIGNATURES = {
     "mipq_ii_build_workspace_size": (_S, [_L, _I, _I, _L, _I, _I, _I, _I, _I]),
     "mipq_ii_build": (_I, [_P, _L, _I, _I, _I, _P, _L, _P, _I, _I, _I, _P, _I, _P, _P, _P, _P, _P, _P, _P,
                            _P, _S, _P]),
+    "mipq_ii_add_workspace_size": (_S, [_L, _I, _I, _I, _I, _I]),
+    "mipq_ii_add": (_I, [_P, _L, _I, _P, _I, _P, _I, _I, _I, _P, _P, _P, _P, _P, _S, _P]),
+    "mipq_ii_merge_workspace_size": (_S, [_I, _I]),
+    "mipq_ii_merge": (_I, [_P, _P, _P, _P, _I, _I, _I, _P, _P, _P, _P, _S, _P]),
     "mipq_adc_search_workspace_size": (_S, [_I, _I, _I, _I, _I]),
     "mipq_adc_search": (_I, [_P, _I, _I, _P, _I, _P, _I, _I, _P, _P, _P, _I, _I, _P, _P, _P, _P, _S, _P]),
     "mipq_pq_fit_batched_workspace_size": (_S, [_P, _I, _I, _I, _I, _I, _I]),

@@ -3,6 +3,8 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <vector>
+
 #include "mipq_internal.h"
 
 namespace mipq {
@@ -449,6 +451,129 @@ int mipq_ii_build(const float* x, int64_t n, int d, int kc, int coarse_iters, co
                                  offsets, s)))
     return rc;
   return launch_gather_codes(b.codes, n, m, ids, codes_sorted, s);
+}
+
+namespace {
+struct AddWs {
+  CoarseWs cw;
+  uint32_t *keys_a, *keys_b, *keys_sorted, *hist;
+  int32_t *vals_a, *vals_b, *lab;
+  uint8_t* codes;
+  float* rbuf;
+  int64_t chunk;
+  void* sub;
+  size_t sub_bytes;
+  size_t bytes;
+};
+
+AddWs carve_add(void* ws, int64_t n, int d, int kc, int m, int ks, int precision, bool need_labels) {
+  Carver c(ws);
+  AddWs a;
+  const int64_t nn = n > 0 ? n : 1;
+  a.cw = carve_coarse(c, d, kc, precision);
+  a.keys_a = c.take<uint32_t>(nn);
+  a.keys_b = c.take<uint32_t>(nn);
+  a.keys_sorted = c.take<uint32_t>(nn);
+  a.hist = c.take<uint32_t>((size_t)64 * sort_blocks(nn));
+  a.vals_a = c.take<int32_t>(nn);
+  a.vals_b = c.take<int32_t>(nn);
+  a.lab = need_labels ? c.take<int32_t>(nn) : nullptr;
+  a.codes = c.take<uint8_t>((size_t)nn * m);
+  a.chunk = nn < (int64_t(1) << 20) ? nn : (int64_t(1) << 20);
+  a.rbuf = c.take<float>((size_t)a.chunk * d);
+  a.sub_bytes = mipq_pq_encode_workspace_size(a.chunk, d, m, ks, precision);
+  a.sub = a.sub_bytes ? c.take<char>(a.sub_bytes) : nullptr;
+  a.bytes = c.bytes();
+  return a;
+}
+}  // namespace
+
+size_t mipq_ii_add_workspace_size(int64_t n, int d, int kc, int m, int ks, int precision) {
+  if (check_coarse(n, d, kc, precision) != MIPQ_OK || check_shape(n, d, m, ks, precision, false) != MIPQ_OK)
+    return 0;
+  return carve_add(nullptr, n, d, kc, m, ks, precision, true).bytes;
+}
+
+int mipq_ii_add(const float* x, int64_t n, int d, const float* coarse, int kc, const float* pq_codebook, int m,
+                int ks, int precision, int64_t* offsets, int32_t* ids, uint8_t* codes_sorted, int32_t* labels,
+                void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_coarse(n, d, kc, precision))) return rc;
+  if ((rc = check_shape(n, d, m, ks, precision, false))) return rc;
+  if (!coarse || !pq_codebook || !offsets || (n > 0 && (!x || !ids || !codes_sorted)))
+    return fail(MIPQ_EINVAL, "a required pointer is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  AddWs a = carve_add(ws, n, d, kc, m, ks, precision, labels == nullptr);
+  if ((rc = check_ws(ws, ws_bytes, a.bytes))) return rc;
+  int32_t* lab = labels ? labels : a.lab;
+  if (n == 0) return launch_zero_u32(reinterpret_cast<uint32_t*>(offsets), 2 * (kc + 1), s);
+  // labels and residual codes of the rows, then stable bucketing by label
+  if ((rc = coarse_assign_any(x, n, d, coarse, kc, precision, a.cw, lab, nullptr, s))) return rc;
+  for (int64_t r = 0; r < n; r += a.chunk) {
+    const int64_t cnt = (n - r) < a.chunk ? (n - r) : a.chunk;
+    if ((rc = launch_residuals(x + r * d, cnt, d, lab + r, coarse, kc, a.rbuf, s))) return rc;
+    if ((rc = mipq_pq_encode(a.rbuf, cnt, d, m, ks, pq_codebook, precision, a.codes + r * m, nullptr, a.sub,
+                             a.sub_bytes, stream)))
+      return rc;
+  }
+  if ((rc = launch_sort_by_label(lab, n, kc, a.keys_a, a.keys_b, a.vals_a, a.vals_b, a.hist, ids, a.keys_sorted,
+                                 offsets, s)))
+    return rc;
+  return launch_gather_codes(a.codes, n, m, ids, codes_sorted, s);
+}
+
+size_t mipq_ii_merge_workspace_size(int nparts, int kc) {
+  if (nparts < 1 || kc < 1 || kc > 65536) return 0;
+  Carver c(nullptr);
+  c.take<char>(merge_part_bytes() * (size_t)nparts);
+  c.take<int64_t>((size_t)nparts * kc);
+  c.take<int64_t>(kc);
+  return c.bytes();
+}
+
+int mipq_ii_merge(const int64_t* const* part_offsets, const int32_t* const* part_ids,
+                  const uint8_t* const* part_codes, const int64_t* part_n, int nparts, int kc, int m,
+                  int64_t* offsets, int32_t* ids, uint8_t* codes_sorted, void* ws, size_t ws_bytes, void* stream) {
+  if (nparts < 1) return fail(MIPQ_EINVAL, "nparts must be positive");
+  if (kc < 1 || kc > 65536) return fail(MIPQ_EINVAL, "kc must be in [1, 65536] (got %d)", kc);
+  if (m < 1 || m > 256) return fail(MIPQ_EINVAL, "m must be in [1, 256] (got %d)", m);
+  if (!part_offsets || !part_ids || !part_codes || !part_n || !offsets)
+    return fail(MIPQ_EINVAL, "a required pointer is NULL");
+  struct Part {
+    const int64_t* off;
+    const int32_t* ids;
+    const uint8_t* codes;
+    int64_t n;
+    int64_t base;
+  };
+  static_assert(sizeof(Part) == 40, "part record");
+  if (merge_part_bytes() != sizeof(Part)) return fail(MIPQ_EINVAL, "part record size mismatch");
+  std::vector<Part> table((size_t)nparts);
+  int64_t total = 0;
+  bool vec16 = (m % 16) == 0 && (reinterpret_cast<uintptr_t>(codes_sorted) % 16) == 0;
+  for (int p = 0; p < nparts; ++p) {
+    const int64_t np = part_n[p];
+    if (np < 0) return fail(MIPQ_EINVAL, "part %d has a negative row count", p);
+    if (!part_offsets[p] || (np > 0 && (!part_ids[p] || !part_codes[p])))
+      return fail(MIPQ_EINVAL, "part %d: a required pointer is NULL", p);
+    vec16 = vec16 && (reinterpret_cast<uintptr_t>(part_codes[p]) % 16) == 0;
+    table[p] = Part{part_offsets[p], part_ids[p], part_codes[p], np, total};
+    total += np;
+    if (total >= (int64_t(1) << 31)) return fail(MIPQ_EINVAL, "merged index exceeds 2^31 - 1 rows");
+  }
+  if (total > 0 && (!ids || !codes_sorted)) return fail(MIPQ_EINVAL, "ids and codes_sorted are required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Carver c(ws);
+  void* dtab = c.take<char>(sizeof(Part) * (size_t)nparts);
+  int64_t* pre = c.take<int64_t>((size_t)nparts * kc);
+  int64_t* tot = c.take<int64_t>(kc);
+  int rc;
+  if ((rc = check_ws(ws, ws_bytes, c.bytes()))) return rc;
+  // the table lives in this call's host memory: copy it and wait
+  hipError_t e = hipMemcpyAsync(dtab, table.data(), sizeof(Part) * (size_t)nparts, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(part table)");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return launch_merge_lists(dtab, nparts, total, kc, m, pre, tot, offsets, ids, codes_sorted, vec16, s);
 }
 
 namespace {

@@ -608,6 +608,90 @@ __global__ void k_gather_codes(const uint8_t* __restrict__ codes, int64_t n, int
   }
 }
 
+// ---------------------------------------------------------------- list merge
+// Merge of inverted lists built over consecutive row ranges ("parts"): list l
+// of the result is the concatenation, in part order, of list l of every
+// part, ids shifted by the part's first row.  Ids ascend inside every part's
+// list and the parts cover increasing row ranges, so merged lists ascend.
+struct MergePart {
+  const int64_t* off;
+  const int32_t* ids;
+  const uint8_t* codes;
+  int64_t n;
+  int64_t base;   // first row of the part
+};
+
+// thread per list: rows of list l in the parts before p (pre[p*kc + l]) and in all
+__global__ void k_merge_prefix(const MergePart* __restrict__ parts, int nparts, int kc, int64_t* __restrict__ pre,
+                               int64_t* __restrict__ total) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= kc) return;
+  int64_t acc = 0;
+  for (int p = 0; p < nparts; ++p) {
+    pre[(size_t)p * kc + l] = acc;
+    acc += parts[p].off[l + 1] - parts[p].off[l];
+  }
+  total[l] = acc;
+}
+
+// exclusive scan of total[0..kc) into offsets[0..kc], one block
+__global__ __launch_bounds__(kT) void k_merge_scan(const int64_t* __restrict__ total, int kc,
+                                                   int64_t* __restrict__ offsets) {
+  __shared__ int64_t part[kT];
+  const int per = (kc + kT - 1) / kT;
+  const int s0 = threadIdx.x * per;
+  int64_t run = 0;
+  for (int i = 0; i < per; ++i)
+    if (s0 + i < kc) run += total[s0 + i];
+  part[threadIdx.x] = run;
+  __syncthreads();
+  for (int off = 1; off < kT; off <<= 1) {
+    const int64_t v = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int64_t acc = part[threadIdx.x] - run;
+  for (int i = 0; i < per; ++i)
+    if (s0 + i < kc) {
+      offsets[s0 + i] = acc;
+      acc += total[s0 + i];
+    }
+  if (threadIdx.x == kT - 1) offsets[kc] = part[kT - 1];
+}
+
+// thread per row of all parts: its list by binary search in the part's offsets
+__global__ void k_merge_copy(const MergePart* __restrict__ parts, int nparts, int64_t total_rows, int kc, int m,
+                             const int64_t* __restrict__ pre, const int64_t* __restrict__ offsets,
+                             int32_t* __restrict__ ids, uint8_t* __restrict__ codes, int vec16) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total_rows;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = nparts - 1;
+    while (lo < hi) {   // last part with base <= g
+      const int mid = (lo + hi + 1) >> 1;
+      if (parts[mid].base <= g) lo = mid;
+      else hi = mid - 1;
+    }
+    const MergePart& P = parts[lo];
+    const int64_t i = g - P.base;
+    int a = 0, b = kc - 1;
+    while (a < b) {   // last list l with off[l] <= i
+      const int mid = (a + b + 1) >> 1;
+      if (P.off[mid] <= i) a = mid;
+      else b = mid - 1;
+    }
+    const int64_t dst = offsets[a] + pre[(size_t)lo * kc + a] + (i - P.off[a]);
+    ids[dst] = (int32_t)(P.ids[i] + P.base);
+    const uint8_t* src = P.codes + i * m;
+    uint8_t* out = codes + dst * m;
+    if (vec16) {
+      for (int j = 0; j < m; j += 16) *reinterpret_cast<uint4*>(out + j) = *reinterpret_cast<const uint4*>(src + j);
+    } else {
+      for (int j = 0; j < m; ++j) out[j] = src[j];
+    }
+  }
+}
+
 int grid_cap(int64_t work, int cap) {
   int64_t g = (work + kT - 1) / kT;
   if (g < 1) g = 1;
@@ -742,6 +826,23 @@ int launch_gather_codes(const uint8_t* codes, int64_t n, int m, const int32_t* i
   const int vec16 = (m % 16 == 0) && (((reinterpret_cast<uintptr_t>(codes) | reinterpret_cast<uintptr_t>(out)) & 15) == 0);
   k_gather_codes<<<grid_cap(n, 8192), kT, 0, s>>>(codes, n, m, ids, out, vec16);
   MIPQ_LAUNCHED("k_gather_codes");
+  return MIPQ_OK;
+}
+
+size_t merge_part_bytes() { return sizeof(MergePart); }
+
+int launch_merge_lists(const void* parts, int nparts, int64_t total_rows, int kc, int m, int64_t* pre,
+                       int64_t* total, int64_t* offsets, int32_t* ids, uint8_t* codes, bool vec16, hipStream_t s) {
+  const MergePart* P = static_cast<const MergePart*>(parts);
+  k_merge_prefix<<<ceil_div(kc, kT), kT, 0, s>>>(P, nparts, kc, pre, total);
+  MIPQ_LAUNCHED("k_merge_prefix");
+  k_merge_scan<<<1, kT, 0, s>>>(total, kc, offsets);
+  MIPQ_LAUNCHED("k_merge_scan");
+  if (total_rows > 0) {
+    k_merge_copy<<<grid_cap(total_rows, 8192), kT, 0, s>>>(P, nparts, total_rows, kc, m, pre, offsets, ids, codes,
+                                                          vec16 ? 1 : 0);
+    MIPQ_LAUNCHED("k_merge_copy");
+  }
   return MIPQ_OK;
 }
 

@@ -144,6 +144,11 @@ int launch_gather_coarse(const float* x, int64_t n, int d, const int64_t* rows, 
 int launch_residuals(const float* x, int64_t n, int d, const int32_t* labels, const float* cc, int kc, float* r,
                      hipStream_t s);
 int launch_gather_codes(const uint8_t* codes, int64_t n, int m, const int32_t* ids, uint8_t* out, hipStream_t s);
+// merge of inverted lists of consecutive row ranges; parts: device array of
+// {const int64_t* off; const int32_t* ids; const uint8_t* codes; int64_t n; int64_t base}
+size_t merge_part_bytes();
+int launch_merge_lists(const void* parts, int nparts, int64_t total_rows, int kc, int m, int64_t* pre,
+                       int64_t* total, int64_t* offsets, int32_t* ids, uint8_t* codes, bool vec16, hipStream_t s);
 
 // ADC search (adc.hip)
 int launch_adc(const float* q, int nq, int d, const float* cc, int kc, const void* aop, const float* mu,

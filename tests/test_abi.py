@@ -128,3 +128,38 @@ def test_plan_rejects_bad_arguments(L):
     assert L.mipq_plan_destroy(None) == 0
     info = (ctypes.c_int64 * 4)()
     assert L.mipq_plan_info(None, info, 4) == EINVAL
+
+
+def test_ii_add_rejects_bad_arguments(L):
+    add = L.mipq_ii_add
+    args = [4096, 100, 32, 4096, 64, 4096, 4, 16, 1, 4096, 4096, 4096, None, 4096, 1 << 30, None]
+    a = list(args)
+    a[8] = 2                                          # FP8: the coarse rule runs in FP32 or BF16
+    assert add(*a) == EUNSUPPORTED
+    a = list(args)
+    a[6] = 5                                          # d % m != 0
+    assert add(*a) == EINVAL
+    a = list(args)
+    a[5] = None                                       # no codebook
+    assert add(*a) == EINVAL
+    a = list(args)
+    a[14] = 64                                        # workspace too small
+    assert add(*a) == ENOMEM
+    assert L.mipq_ii_add_workspace_size(100, 32, 64, 4, 16, 1) > 0
+    assert L.mipq_ii_add_workspace_size(100, 32, 64, 4, 16, 2) == 0
+
+
+def test_ii_merge_rejects_bad_arguments(L):
+    P = ctypes.c_void_p * 2
+    offs, ids, codes = P(4096, 8192), P(4096, 8192), P(4096, 8192)
+    ns = (ctypes.c_int64 * 2)(10, 20)
+    merge = L.mipq_ii_merge
+    assert merge(offs, ids, codes, ns, 0, 8, 4, 4096, 4096, 4096, 4096, 1 << 20, None) == EINVAL
+    assert merge(offs, ids, codes, ns, 2, 0, 4, 4096, 4096, 4096, 4096, 1 << 20, None) == EINVAL
+    assert merge(offs, ids, codes, ns, 2, 8, 0, 4096, 4096, 4096, 4096, 1 << 20, None) == EINVAL
+    bad = (ctypes.c_int64 * 2)(10, -1)
+    assert merge(offs, ids, codes, bad, 2, 8, 4, 4096, 4096, 4096, 4096, 1 << 20, None) == EINVAL
+    assert merge(offs, P(4096, None), codes, ns, 2, 8, 4, 4096, 4096, 4096, 4096, 1 << 20, None) == EINVAL
+    assert merge(offs, ids, codes, ns, 2, 8, 4, 4096, 4096, 4096, 4096, 64, None) == ENOMEM
+    assert merge(offs, ids, codes, ns, 2, 8, 4, 4096, 4096, 4096, 4096 + 8, 1 << 20, None) == EINVAL
+    assert L.mipq_ii_merge_workspace_size(2, 8) > 0 and L.mipq_ii_merge_workspace_size(0, 8) == 0

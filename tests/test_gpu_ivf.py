@@ -140,3 +140,54 @@ def test_full_size_index_and_search_sampled():
     ri, rd = ivf.adc_search(w.queries[qs], cc, pqc, off, ids, codes_by_id, w.nprobe, w.topk, decide="kernel")
     np.testing.assert_array_equal(gi.cpu().numpy()[qs].astype(np.int64), ri)
     np.testing.assert_array_equal(gd.cpu().numpy()[qs], rd.astype(np.float32))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_chunk_adds_merged_equal_the_global_build(prec):
+    """Index built chunk by chunk with the global quantisers, then merged:
+    offsets, ids and codes equal one build over all rows bit for bit, and the
+    oracle's add + merge on the same quantisers."""
+    w = _small()
+    print("add/merge", prec, flush=True)
+    xt = _t(w.x)
+    idx = mipq.ii_build(xt, w.kc, w.coarse_iters, _t(w.coarse_train), _t(w.coarse_init), w.m, w.ks,
+                        w.pq_iters, _t(w.pq_init), precision=prec)
+    whole = mipq.ii_add(xt, idx["coarse"], idx["pq_codebook"], prec, labels=True)
+    for k in ("offsets", "ids", "codes_sorted", "labels"):
+        assert torch.equal(whole[k], idx[k]), k
+    cuts = [0, 1, 5000, 5000, 12345, 19999, 20000]
+    parts = [mipq.ii_add(xt[a:b], idx["coarse"], idx["pq_codebook"], prec) for a, b in zip(cuts[:-1], cuts[1:])]
+    merged = mipq.ii_merge(parts)
+    for k in ("offsets", "ids", "codes_sorted"):
+        assert torch.equal(merged[k], idx[k]), k
+    cc = idx["coarse"].cpu().numpy()
+    pcb = idx["pq_codebook"].cpu().numpy().astype(np.float64)
+    ref = ivf.merge([ivf.add(w.x[a:b], cc, pcb) for a, b in zip(cuts[:-1], cuts[1:])])
+    np.testing.assert_array_equal(merged["offsets"].cpu().numpy(), ref["offsets"])
+    ids = merged["ids"].cpu().numpy().astype(np.int64)
+    np.testing.assert_array_equal(ids, ref["ids"])
+    np.testing.assert_array_equal(merged["codes_sorted"].cpu().numpy().astype(np.int64), ref["codes"][ids])
+
+
+@pytest.mark.parametrize("kc,m,nparts", [(1, 16, 3), (300, 5, 37), (5000, 32, 9), (64, 16, 1)])
+def test_merge_of_synthetic_parts_matches_oracle(kc, m, nparts):
+    """Merge alone on part indexes with random labels (empty parts, empty and
+    crowded lists, 16-byte and byte-wise code rows) against the oracle."""
+    rng = np.random.default_rng(kc + m + nparts)
+    parts_np, parts = [], []
+    for p in range(nparts):
+        n = 0 if p % 4 == 1 else int(rng.integers(1, 3000))
+        lab = np.minimum(rng.geometric(0.02, size=n) - 1, kc - 1) if n else np.zeros(0, np.int64)
+        off, ids = ivf.posting_lists(lab, kc)
+        codes = rng.integers(0, 256, size=(n, m))
+        parts_np.append(dict(offsets=off, ids=ids, codes=codes))
+        parts.append(dict(coarse=torch.zeros((kc, 4), device=DEV), pq_codebook=torch.zeros((m, 1, 1), device=DEV),
+                          offsets=_t(off), ids=_t(ids.astype(np.int32)),
+                          codes_sorted=_t(codes[ids].astype(np.uint8).reshape(n, m))))
+    print("merge", kc, m, nparts, flush=True)
+    got = mipq.ii_merge(parts)
+    ref = ivf.merge(parts_np)
+    np.testing.assert_array_equal(got["offsets"].cpu().numpy(), ref["offsets"])
+    ids = got["ids"].cpu().numpy().astype(np.int64)
+    np.testing.assert_array_equal(ids, ref["ids"])
+    np.testing.assert_array_equal(got["codes_sorted"].cpu().numpy().astype(np.int64), ref["codes"][ids])

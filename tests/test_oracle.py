@@ -355,6 +355,40 @@ def test_adc_pads_when_lists_are_short():
         assert np.all(ids[qi, n_real:] == -1) and np.all(np.isinf(dist[qi, n_real:]))
 
 
+def test_merge_hand_worked_two_parts():
+    # part 0: rows 0..2 with labels (1, 0, 1); part 1: rows 0..1 with labels (0, 0)
+    p0 = dict(offsets=np.array([0, 1, 3]), ids=np.array([1, 0, 2]), codes=np.array([[5], [6], [7]]))
+    p1 = dict(offsets=np.array([0, 2, 2]), ids=np.array([0, 1]), codes=np.array([[8], [9]]))
+    r = ivf.merge([p0, p1])
+    assert r["offsets"].tolist() == [0, 3, 5]
+    assert r["ids"].tolist() == [1, 3, 4, 0, 2]
+    assert r["codes"][:, 0].tolist() == [5, 6, 7, 8, 9]
+    # an empty part changes nothing
+    pe = dict(offsets=np.zeros(3, np.int64), ids=np.zeros(0, np.int64), codes=np.zeros((0, 1), np.int64))
+    r2 = ivf.merge([pe, p0, pe, p1, pe])
+    assert r2["offsets"].tolist() == r["offsets"].tolist() and r2["ids"].tolist() == r["ids"].tolist()
+
+
+def test_merge_of_chunk_adds_equals_the_index_of_all_rows():
+    w, idx = _small_index()
+    cc32 = idx["coarse"].astype(np.float32)
+    pcb = idx["pq"].astype(np.float32).astype(np.float64)
+    whole = ivf.add(w.x, cc32, pcb)
+    np.testing.assert_array_equal(whole["labels"], idx["labels"])
+    np.testing.assert_array_equal(whole["offsets"], idx["offsets"])
+    np.testing.assert_array_equal(whole["ids"], idx["ids"])
+    cuts = [0, 1, 700, 700, 1999, 3000]
+    parts = [ivf.add(w.x[a:b], cc32, pcb) for a, b in zip(cuts[:-1], cuts[1:])]
+    r = ivf.merge(parts)
+    np.testing.assert_array_equal(r["offsets"], whole["offsets"])
+    np.testing.assert_array_equal(r["ids"], whole["ids"])
+    np.testing.assert_array_equal(r["codes"], whole["codes"])
+    # the merged lists are the definition: list l = ascending ids with label l
+    for l in range(len(r["offsets"]) - 1):
+        got = r["ids"][r["offsets"][l]:r["offsets"][l + 1]]
+        np.testing.assert_array_equal(got, np.flatnonzero(idx["labels"] == l))
+
+
 # ---------------------------------------------------------------- the paper's chunked fit
 
 def test_single_chunk_two_level_fit_reproduces_direct_fit():
