@@ -49,12 +49,13 @@ def _ws(nbytes: int, device) -> torch.Tensor:
 
 def pq_fit(x: torch.Tensor, m: int, ks: int, iters: int, init_rows: torch.Tensor | None = None,
            init_codebook: torch.Tensor | None = None, train_rows: torch.Tensor | None = None,
-           precision="bf16", labels: bool = True, codebook64: bool = False, objective: bool = True):
+           precision="bf16", labels: bool = True, codebook64: bool = False, objective: bool = True,
+           out: torch.Tensor | None = None):
     """Fit per-subspace k-means codebooks (Lloyd, ``iters`` rounds).
 
-    Returns a dict with ``codebook`` float32 [m, ks, d/m] and, on request,
-    ``labels`` uint8 [n_train, m] (last assignment), ``codebook64`` and
-    ``objective`` float64 [iters].
+    Returns a dict with ``codebook`` float32 [m, ks, d/m] (written into
+    ``out`` when given) and, on request, ``labels`` uint8 [n_train, m] (last
+    assignment), ``codebook64`` and ``objective`` float64 [iters].
     """
     L = lib()
     x = _dev(x, torch.float32, "x")
@@ -66,19 +67,25 @@ def pq_fit(x: torch.Tensor, m: int, ks: int, iters: int, init_rows: torch.Tensor
     ir = _dev(init_rows, torch.int64, "init_rows") if init_rows is not None else None
     ic = _dev(init_codebook, torch.float32, "init_codebook") if init_codebook is not None else None
     p = _prec(precision)
-    out = {"codebook": torch.empty((m, ks, ds), dtype=torch.float32, device=dev)}
+    if out is not None:
+        if (out.dtype != torch.float32 or out.device != dev or tuple(out.shape) != (m, ks, ds)
+                or not out.is_contiguous()):
+            raise ValueError("out must be a contiguous float32 [m, ks, d/m] tensor on the device of x")
+        res = {"codebook": out}
+    else:
+        res = {"codebook": torch.empty((m, ks, ds), dtype=torch.float32, device=dev)}
     if labels:
-        out["labels"] = torch.empty((n_train, m), dtype=torch.uint8, device=dev)
+        res["labels"] = torch.empty((n_train, m), dtype=torch.uint8, device=dev)
     if codebook64:
-        out["codebook64"] = torch.empty((m, ks, ds), dtype=torch.float64, device=dev)
+        res["codebook64"] = torch.empty((m, ks, ds), dtype=torch.float64, device=dev)
     if objective:
-        out["objective"] = torch.empty(max(iters, 0), dtype=torch.float64, device=dev)
+        res["objective"] = torch.empty(max(iters, 0), dtype=torch.float64, device=dev)
     nbytes = L.mipq_pq_fit_workspace_size(n_train, d, m, ks, iters, p)
     ws = _ws(nbytes, dev)
     check(L.mipq_pq_fit(_ptr(x), n, _ptr(tr), n_train, d, m, ks, iters, _ptr(ir), _ptr(ic), p,
-                        _ptr(out["codebook"]), _ptr(out.get("codebook64")), _ptr(out.get("labels")),
-                        _ptr(out.get("objective")), _ptr(ws), ws.numel(), _stream(dev)))
-    return out
+                        _ptr(res["codebook"]), _ptr(res.get("codebook64")), _ptr(res.get("labels")),
+                        _ptr(res.get("objective")), _ptr(ws), ws.numel(), _stream(dev)))
+    return res
 
 
 def pq_encode(x: torch.Tensor, codebook: torch.Tensor, precision="bf16", rescored: bool = False):
@@ -417,24 +424,35 @@ def pq_fit_batched(xs, init_rows, m: int, ks: int, iters: int, precision="bf16",
 
 def two_level_fit(xs, chunk_inits, global_init, m: int, ks: int, iters: int, precision="bf16"):
     """The paper's two-level chunked fit (Section 3), composed from the
-    boundary calls: every chunk is fitted on its own rows (one batched fit of
-    all chunks), each chunk's codebook is decoded into its Ks centroid rows
-    (the decode of the code rows (k, k, ..., k)), the rows of all chunks are
-    pooled, and one global codebook is fitted on the pool from
-    ``global_init`` (int64 [m, ks], rows of the pool).
+    boundary calls: every chunk is fitted on its own rows, each chunk's
+    codebook is decoded into its Ks centroid rows (the decode of the code rows
+    (k, k, ..., k)), the rows of all chunks are pooled, and one global
+    codebook is fitted on the pool from ``global_init`` (int64 [m, ks], rows
+    of the pool).  The chunk fits are one batched fit of all chunks in BF16
+    when d/m <= 16 and ``precision`` is not FP32; otherwise one ``pq_fit`` per
+    chunk in ``precision`` (FP32 for wider subspaces).
 
     Returns dict(pool float32 [chunks*ks, d], codebook float32 [m, ks, d/m],
     chunk_codebooks list).
     """
     dev = xs[0].device
     d = xs[0].shape[1]
-    books = torch.empty((len(xs), m, ks, d // m), dtype=torch.float32, device=dev)
-    b = BatchedFit(xs, chunk_inits, m, ks, iters, precision="bf16", plan=False, objective=False, sse=False,
-                   codebooks=books)
-    b.run()
+    ds = d // m
+    books = torch.empty((len(xs), m, ks, ds), dtype=torch.float32, device=dev)
+    if ds > 16 or _prec(precision) == FP32:
+        cp = FP32 if ds > 16 else _prec(precision)
+        for i, (x, ini) in enumerate(zip(xs, chunk_inits)):
+            pq_fit(x, m, ks, iters, init_rows=ini, precision=cp, labels=False, objective=False, out=books[i])
+        chunk_books = list(books.unbind(0))
+    else:
+        b = BatchedFit(xs, chunk_inits, m, ks, iters, precision="bf16", plan=False, objective=False, sse=False,
+                       codebooks=books)
+        b.run()
+        chunk_books = [r["codebook"] for r in b.results]
     pool = decode_centroids(books)
-    g = pq_fit(pool, m, ks, iters, init_rows=global_init, precision=precision, labels=False, objective=False)
-    return {"pool": pool, "codebook": g["codebook"], "chunk_codebooks": [r["codebook"] for r in b.results]}
+    gp = FP32 if ds > 16 else precision
+    g = pq_fit(pool, m, ks, iters, init_rows=global_init, precision=gp, labels=False, objective=False)
+    return {"pool": pool, "codebook": g["codebook"], "chunk_codebooks": chunk_books}
 
 
 def decode_centroids(codebooks: torch.Tensor) -> torch.Tensor:

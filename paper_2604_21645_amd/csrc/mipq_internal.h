@@ -59,7 +59,11 @@ struct Carver {
 constexpr int kMaxKs = 256;        // codes are uint8
 constexpr int kMaxDsBf16 = 16;     // two 8-dimension blocks per subspace
 constexpr int kMaxDsFp32 = 64;
-constexpr int kMaxDsFit = 32;      // float64 centroid sums held in LDS
+constexpr int kMaxDsFit = 48;      // float64 centroid sums held in LDS
+// LDS of one update block at ks = 256, d/m = 48: sums 256 x 49 float64, counts,
+// the float32 codebook of the subspace; within the 160 KiB of a CU
+static_assert(256 * (kMaxDsFit + 1) * 8 + 128 * 8 + 256 * kMaxDsFit * 4 + 16 * 8 <= 160 * 1024,
+              "update block LDS");
 
 // One problem of a batched fit (device copy, built by the host from the
 // caller's problem table).  Work-list offsets: unit0 = first (32-row tile x

@@ -163,3 +163,11 @@ def test_ii_merge_rejects_bad_arguments(L):
     assert merge(offs, ids, codes, ns, 2, 8, 4, 4096, 4096, 4096, 4096, 64, None) == ENOMEM
     assert merge(offs, ids, codes, ns, 2, 8, 4, 4096, 4096, 4096, 4096 + 8, 1 << 20, None) == EINVAL
     assert L.mipq_ii_merge_workspace_size(2, 8) > 0 and L.mipq_ii_merge_workspace_size(0, 8) == 0
+
+
+def test_fit_width_limits(L):
+    # FP32 fits take subspaces up to 48 wide (float64 sums of 256 centroids in LDS)
+    assert L.mipq_pq_fit_workspace_size(1000, 48, 1, 256, 5, 0) > 0
+    assert L.mipq_pq_fit_workspace_size(1000, 64, 1, 256, 5, 0) == 0
+    assert L.mipq_pq_fit_workspace_size(1000, 48, 2, 256, 5, 1) == 0    # matrix-core paths: d/m <= 16
+    assert L.mipq_recon_backward_workspace_size(1000, 48, 1, 256) > 0
