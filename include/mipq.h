@@ -335,6 +335,35 @@ int mipq_recon_backward(const float* x, const uint8_t* codes, const float* codeb
                         double* loss, void* ws, size_t ws_bytes, void* stream);
 
 /* -------------------------------------------------------------------------
+ * Optimized PQ (paper Section 3.1.1: the PQ library implements PQ and
+ * optimized PQ).  Rows are quantised after an orthogonal rotation y = x R;
+ * R is fitted by alternating Lloyd rounds on the rotated rows with the
+ * orthogonal Procrustes step below (the composition is in the Python layer).
+ *
+ * mipq_rotate: y [n][d] = x [n][d] R, R float64 [d][d] row-major (y_j =
+ *   sum over t of x_t R[t][j]).  Each output is the float64 sum over t
+ *   ascending of the float64 products x_t * R[t][j] (product and sum rounded
+ *   separately), rounded once to float32.  y must not overlap x.  n == 0 is
+ *   valid.  d in [1, 4096].
+ *
+ * mipq_opq_procrustes: the orthogonal R minimising ||X R - Y_hat||_F for
+ *   x, y_hat float32 [n][d]: R = U V^T for U S V^T = M = X^T Y_hat.
+ *   M is summed in float64 (float32 products are exact; the order of the
+ *   sums is fixed by n and d, so results repeat bit for bit).  The singular
+ *   value decomposition is one-sided Jacobi in float64 on one work-group;
+ *   columns of U whose singular value is at most d * 2^-52 * the largest are
+ *   completed to an orthonormal basis (R is then one of the minimisers).
+ *   rotation: OUT float64 [d][d] row-major; cross: OUT optional float64
+ *   [d][d] (M); sweeps: OUT optional device int (Jacobi sweeps run, 65 if
+ *   64 sweeps did not converge).  d in [1, 256]; n >= 0 (n == 0 gives M = 0
+ *   and R = I).
+ * ------------------------------------------------------------------------- */
+int mipq_rotate(const float* x, int64_t n, int d, const double* rotation, float* y, void* stream);
+size_t mipq_opq_procrustes_workspace_size(int64_t n, int d);
+int mipq_opq_procrustes(const float* x, const float* y_hat, int64_t n, int d, double* rotation,
+                        double* cross, int* sweeps, void* ws, size_t ws_bytes, void* stream);
+
+/* -------------------------------------------------------------------------
  * Per-kernel timing (tracing aid, off by default).
  *
  * mipq_profile_enable(1) makes every subsequent launch of the kernels below
@@ -358,7 +387,10 @@ enum mipq_kernel {
   MIPQ_K_ASSIGN_BF16_BATCHED = 12, /* persistent matrix-core assignment, many problems */
   MIPQ_K_ASSIGN_FP8 = 13,   /* FP8 matrix-core assignment (with exact re-decision) */
   MIPQ_K_PACK_FP8 = 14,     /* FP8 centroid operand packing */
-  MIPQ_KERNEL_COUNT = 15
+  MIPQ_K_ROTATE = 15,       /* optimized PQ: rotation y = x R */
+  MIPQ_K_CROSS = 16,        /* optimized PQ: cross matrix X^T Y_hat */
+  MIPQ_K_POLAR = 17,        /* optimized PQ: orthogonal factor by Jacobi */
+  MIPQ_KERNEL_COUNT = 18
 };
 int mipq_profile_enable(int on);
 int mipq_profile_collect(int kernel, int64_t* launches, double* total_ms);

@@ -21,6 +21,7 @@ Modules
   ivf    -- coarse quantiser, residual PQ, posting lists, ADC top-k search (Section 2.2)
   grad   -- reconstruction loss and its gradient with codes held fixed
   chunked -- the paper's chunk-then-pool two-level fit (Section 3)
+  opq    -- optimized PQ: an orthogonal rotation learnt before PQ (Section 3.1.1)
 """
 
-from . import pq, ivf, grad, chunked  # noqa: F401
+from . import pq, ivf, grad, chunked, opq  # noqa: F401

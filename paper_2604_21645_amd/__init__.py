@@ -323,6 +323,88 @@ def adc_search(q: torch.Tensor, index: dict, nprobe: int, topk: int, wide: bool 
     return (out_ids, out_d, w) if wide else (out_ids, out_d)
 
 
+def rotate(x: torch.Tensor, rotation: torch.Tensor) -> torch.Tensor:
+    """y = x R (``mipq_rotate``): x float32 [n, d], R float64 [d, d]."""
+    x = _dev(x, torch.float32, "x")
+    r = _dev(rotation, torch.float64, "rotation")
+    n, d = x.shape
+    if tuple(r.shape) != (d, d):
+        raise ValueError("rotation must be [d, d]")
+    y = torch.empty((n, d), dtype=torch.float32, device=x.device)
+    check(lib().mipq_rotate(_ptr(x), n, d, _ptr(r), _ptr(y), _stream(x.device)))
+    return y
+
+
+def procrustes(x: torch.Tensor, y_hat: torch.Tensor):
+    """Orthogonal R minimising ||x R - y_hat|| (``mipq_opq_procrustes``):
+    returns (R float64 [d, d], M = x^T y_hat float64 [d, d], Jacobi sweeps
+    int32 [1])."""
+    L = lib()
+    x = _dev(x, torch.float32, "x")
+    yh = _dev(y_hat, torch.float32, "y_hat")
+    if x.shape != yh.shape:
+        raise ValueError("x and y_hat must have the same shape")
+    n, d = x.shape
+    dev = x.device
+    r = torch.empty((d, d), dtype=torch.float64, device=dev)
+    m = torch.empty((d, d), dtype=torch.float64, device=dev)
+    sw = torch.empty(1, dtype=torch.int32, device=dev)
+    ws = _ws(L.mipq_opq_procrustes_workspace_size(n, d), dev)
+    check(L.mipq_opq_procrustes(_ptr(x), _ptr(yh), n, d, _ptr(r), _ptr(m), _ptr(sw), _ptr(ws), ws.numel(),
+                                _stream(dev)))
+    return r, m, sw
+
+
+def opq_fit(x: torch.Tensor, m: int, ks: int, outer_iters: int, pq_iters: int, init_rows: torch.Tensor,
+            precision="bf16", history: bool = False):
+    """Optimized PQ (non-parametric): R = I and a codebook seeded from the
+    rows ``init_rows`` of x, then ``outer_iters`` times: y = x R; ``pq_iters``
+    Lloyd rounds on y from the current codebook; codes of y; R = the
+    Procrustes rotation of x onto the decoded codes.  Composed from the
+    boundary calls.
+
+    Returns dict(R float64 [d, d], codebook float32 [m, ks, d/m], objective
+    float64 [outer_iters] = SSE of x R (rounded to float32) against the
+    decoded codes after each rotation update, and with ``history`` the lists
+    ``rotations`` and ``codebooks`` of every outer iteration).
+    """
+    x = _dev(x, torch.float32, "x")
+    dev = x.device
+    n, d = x.shape
+    r = torch.eye(d, dtype=torch.float64, device=dev)
+    cb = None
+    obj = torch.empty(max(outer_iters, 0), dtype=torch.float64, device=dev)
+    rots, books = [], []
+    for it in range(outer_iters):
+        y = rotate(x, r)
+        if cb is None:
+            cb = pq_fit(y, m, ks, pq_iters, init_rows=init_rows, precision=precision, labels=False,
+                        objective=False)["codebook"]
+        else:
+            cb = pq_fit(y, m, ks, pq_iters, init_codebook=cb, precision=precision, labels=False,
+                        objective=False)["codebook"]
+        codes = pq_encode(y, cb, precision)
+        yh, _ = pq_decode_rmse(codes, cb, x_hat=True)
+        r, _, _ = procrustes(x, yh)
+        _, sr = pq_decode_rmse(codes, cb, rotate(x, r))
+        obj[it:it + 1].copy_(sr[0:1])
+        if history:
+            rots.append(r)
+            books.append(cb)
+    if cb is None:
+        raise ValueError("outer_iters must be >= 1")
+    out = {"R": r, "codebook": cb, "objective": obj}
+    if history:
+        out["rotations"] = rots
+        out["codebooks"] = books
+    return out
+
+
+def opq_encode(x: torch.Tensor, rotation: torch.Tensor, codebook: torch.Tensor, precision="bf16"):
+    """Codes of the rotated rows x R."""
+    return pq_encode(rotate(x, rotation), codebook, precision)
+
+
 class BatchedFit:
     """Fit + encode of many independent problems sharing d, m and ks, every
     phase one launch over all problems (``mipq_pq_fit_batched``).

@@ -50,6 +50,9 @@ SIGNATURES = {
     "mipq_plan_create": (_I, [_P, _P, _I, _I, _I, _I, _I, _I, _I, _P, _S, _P]),
     "mipq_plan_info": (_I, [_P, _P, _I]),
     "mipq_plan_destroy": (_I, [_P]),
+    "mipq_rotate": (_I, [_P, _L, _I, _P, _P, _P]),
+    "mipq_opq_procrustes_workspace_size": (_S, [_L, _I]),
+    "mipq_opq_procrustes": (_I, [_P, _P, _L, _I, _P, _P, _P, _P, _S, _P]),
     "mipq_profile_enable": (_I, [_I]),
     "mipq_profile_collect": (_I, [_I, ctypes.POINTER(_L), ctypes.POINTER(ctypes.c_double)]),
 }
@@ -57,7 +60,8 @@ SIGNATURES = {
 # kernel ids of mipq_profile_collect (enum mipq_kernel)
 KERNELS = {"assign_fp32": 0, "assign_bf16": 1, "update": 2, "finalize": 3, "pack_bf16": 4, "decode": 5,
            "backward": 6, "coarse_pack": 7, "coarse_assign": 8, "sort": 9, "coarse_update": 10, "adc": 11,
-           "assign_bf16_batched": 12, "assign_fp8": 13, "pack_fp8": 14}
+           "assign_bf16_batched": 12, "assign_fp8": 13, "pack_fp8": 14, "rotate": 15, "cross": 16,
+           "polar": 17}
 
 
 class MipqProblem(ctypes.Structure):

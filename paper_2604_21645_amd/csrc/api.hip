@@ -630,3 +630,66 @@ int mipq_adc_search(const float* q, int nq, int d, const float* coarse, int kc, 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- optimized PQ
+namespace {
+constexpr int kPolarSweeps = 64;
+
+struct ProcWs {
+  double *part, *m, *a, *v;
+  int* sweeps;
+  int nch;
+  size_t bytes;
+};
+
+ProcWs carve_proc(void* ws, int64_t n, int d, bool need_m, bool need_sweeps) {
+  Carver c(ws);
+  ProcWs w;
+  const size_t dd = (size_t)d * d;
+  w.nch = n > 0 ? cross_chunks(n, d) : 0;
+  w.part = w.nch ? c.take<double>((size_t)w.nch * dd) : nullptr;
+  w.m = need_m ? c.take<double>(dd) : nullptr;
+  w.a = c.take<double>(dd);
+  w.v = c.take<double>(dd);
+  w.sweeps = need_sweeps ? c.take<int>(1) : nullptr;
+  w.bytes = c.bytes();
+  return w;
+}
+}  // namespace
+
+int mipq_rotate(const float* x, int64_t n, int d, const double* rotation, float* y, void* stream) {
+  if (n < 0) return fail(MIPQ_EINVAL, "n must be >= 0");
+  if (d < 1 || d > 4096) return fail(MIPQ_EINVAL, "d must be in [1, 4096] (got %d)", d);
+  if (!rotation || (n > 0 && (!x || !y))) return fail(MIPQ_EINVAL, "x, rotation and y are required");
+  if (n > 0) {
+    const char* xb = reinterpret_cast<const char*>(x);
+    const char* yb = reinterpret_cast<const char*>(y);
+    const size_t bytes = (size_t)n * d * sizeof(float);
+    if (xb < yb + bytes && yb < xb + bytes) return fail(MIPQ_EINVAL, "y must not overlap x");
+  }
+  return launch_rotate(x, n, d, rotation, y, static_cast<hipStream_t>(stream));
+}
+
+size_t mipq_opq_procrustes_workspace_size(int64_t n, int d) {
+  if (n < 0 || d < 1 || d > 256) return 0;
+  return carve_proc(nullptr, n, d, true, true).bytes;
+}
+
+int mipq_opq_procrustes(const float* x, const float* y_hat, int64_t n, int d, double* rotation, double* cross,
+                        int* sweeps, void* ws, size_t ws_bytes, void* stream) {
+  if (n < 0) return fail(MIPQ_EINVAL, "n must be >= 0");
+  if (d < 1 || d > 256) return fail(MIPQ_EUNSUPPORTED, "the rotation fit supports 1 <= d <= 256 (got %d)", d);
+  if (!rotation || (n > 0 && (!x || !y_hat))) return fail(MIPQ_EINVAL, "x, y_hat and rotation are required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ProcWs w = carve_proc(ws, n, d, cross == nullptr, sweeps == nullptr);
+  int rc;
+  if ((rc = check_ws(ws, ws_bytes, w.bytes))) return rc;
+  double* m = cross ? cross : w.m;
+  int* sw = sweeps ? sweeps : w.sweeps;
+  if (n == 0) {
+    if ((rc = launch_zero_u32(reinterpret_cast<uint32_t*>(m), (size_t)d * d * 2, s))) return rc;
+  } else if ((rc = launch_cross(x, y_hat, n, d, w.nch, w.part, m, s))) {
+    return rc;
+  }
+  return launch_polar(m, d, kPolarSweeps, w.a, w.v, rotation, sw, s);
+}

@@ -148,6 +148,14 @@ int launch_gather_coarse(const float* x, int64_t n, int d, const int64_t* rows, 
 int launch_residuals(const float* x, int64_t n, int d, const int32_t* labels, const float* cc, int kc, float* r,
                      hipStream_t s);
 int launch_gather_codes(const uint8_t* codes, int64_t n, int m, const int32_t* ids, uint8_t* out, hipStream_t s);
+// optimized PQ: rotation y = x R, cross matrix X^T Y_hat (chunk partials in
+// part, nch from cross_chunks), orthogonal polar factor of M (one work-group)
+int launch_rotate(const float* x, int64_t n, int d, const double* r, float* y, hipStream_t s);
+int cross_chunks(int64_t n, int d);
+int launch_cross(const float* x, const float* yh, int64_t n, int d, int nch, double* part, double* m,
+                 hipStream_t s);
+int launch_polar(const double* m, int d, int max_sweeps, double* a, double* v, double* r, int* sweeps,
+                 hipStream_t s);
 // merge of inverted lists of consecutive row ranges; parts: device array of
 // {const int64_t* off; const int32_t* ids; const uint8_t* codes; int64_t n; int64_t base}
 size_t merge_part_bytes();

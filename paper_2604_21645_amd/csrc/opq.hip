@@ -1,0 +1,416 @@
+// Optimized PQ (paper Section 3.1.1 names it beside PQ): rows are quantised
+// after an orthogonal rotation y = x R, and R is re-fitted by the orthogonal
+// Procrustes problem min ||X R - Y_hat||_F over orthogonal R, solved by
+// R = U V^T from the singular value decomposition U S V^T = X^T Y_hat.
+//
+// Kernels:
+//   k_rotate        y = x R, float64 products and sums in ascending t, unfused
+//                   (the product of a float32 and a float64 is not exact), one
+//                   rounding to float32 per output;
+//   k_cross_partial X^T Y_hat over a chunk of rows per block, float64 (float32
+//                   products are exact in float64), partials summed in chunk
+//                   order by k_cross_reduce;
+//   k_polar         one work-group: one-sided (Hestenes) Jacobi on the columns
+//                   of M = X^T Y_hat, A = M V with orthogonal columns, U = A's
+//                   normalised columns (rank-deficient columns completed to an
+//                   orthonormal basis), R = U V^T.
+#include <math.h>
+
+#include "mipq_internal.h"
+
+namespace mipq {
+
+namespace {
+
+constexpr int kTile = 64;      // output tile edge (rows x columns)
+constexpr int kTk = 32;        // reduction depth staged per step
+constexpr int kThreads = 256;  // 16 x 16 threads, 4 x 4 outputs each
+
+// Block (row tile, column tile) of y = x R.  XCD-aware: consecutive column
+// tiles of one row tile go to one XCD (blocks b, b + 8, ...) so that the row
+// tile is read from HBM once and then from that XCD's L2.
+__global__ __launch_bounds__(kThreads) void k_rotate(const float* __restrict__ x, int64_t n, int d,
+                                                     const double* __restrict__ r, float* __restrict__ y,
+                                                     int ctiles, int64_t nblocks) {
+  __shared__ __align__(16) float xs[kTk][kTile + 4];   // x tile, transposed: xs[t][row]
+  __shared__ __align__(16) double rs[kTk][kTile + 2];  // R tile: rs[t][col]
+  // logical block -> (row tile, column tile)
+  const int64_t b = blockIdx.x;
+  const int64_t xcd = b & 7, slot = b >> 3;
+  const int64_t per_xcd = (nblocks + 7) >> 3;
+  const int64_t lb = xcd * per_xcd + slot;     // logical block, contiguous per XCD
+  if (lb >= nblocks) return;
+  const int64_t rt = lb / ctiles;
+  const int ct = (int)(lb - rt * ctiles);
+  const int64_t row0 = rt * kTile;
+  const int col0 = ct * kTile;
+  const int tid = threadIdx.x;
+  const int tc = tid & 15, tr = tid >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+
+  for (int t0 = 0; t0 < d; t0 += kTk) {
+    // stage x[row0 .. +64][t0 .. +32] transposed (8 floats per thread)
+    for (int e = tid; e < kTile * kTk; e += kThreads) {
+      const int rr = e / kTk, tt = e - rr * kTk;
+      const int64_t row = row0 + rr;
+      const int t = t0 + tt;
+      xs[tt][rr] = (row < n && t < d) ? x[row * d + t] : 0.0f;
+    }
+    // stage R[t0 .. +32][col0 .. +64]
+    for (int e = tid; e < kTk * kTile; e += kThreads) {
+      const int tt = e / kTile, cc = e - tt * kTile;
+      const int t = t0 + tt, col = col0 + cc;
+      rs[tt][cc] = (t < d && col < d) ? r[(int64_t)t * d + col] : 0.0;
+    }
+    __syncthreads();
+    const int tend = min(kTk, d - t0);
+    for (int tt = 0; tt < tend; ++tt) {
+      const float4 xv = *reinterpret_cast<const float4*>(&xs[tt][tr * 4]);
+      const double xa[4] = {(double)xv.x, (double)xv.y, (double)xv.z, (double)xv.w};
+      double ra[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) ra[j] = rs[tt][tc * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = acc[i][j] + xa[i] * ra[j];   // unfused: rounded product, rounded sum
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t row = row0 + tr * 4 + i;
+    if (row >= n) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = col0 + tc * 4 + j;
+      if (col < d) y[row * d + col] = (float)acc[i][j];
+    }
+  }
+}
+
+// Block (chunk c, tile (ti, tj)): part[c][t][j] = sum over the chunk's rows n
+// of x[n][t] * yh[n][j] for t in tile ti, j in tile tj.
+__global__ __launch_bounds__(kThreads) void k_cross_partial(const float* __restrict__ x,
+                                                            const float* __restrict__ yh, int64_t n, int d,
+                                                            int64_t rpc, int tiles, double* __restrict__ part) {
+  __shared__ __align__(16) float xs[kTk][kTile + 4];   // xs[row][t]
+  __shared__ __align__(16) float ys[kTk][kTile + 4];   // ys[row][j]
+  const int tile = blockIdx.x % (tiles * tiles);
+  const int64_t c = blockIdx.x / (tiles * tiles);
+  const int ti = tile / tiles, tj = tile - ti * tiles;
+  const int tbase = ti * kTile, jbase = tj * kTile;
+  const int64_t r0 = c * rpc;
+  const int64_t r1 = min(n, r0 + rpc);
+  const int tid = threadIdx.x;
+  const int tc = tid & 15, tr = tid >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int64_t s0 = r0; s0 < r1; s0 += kTk) {
+    for (int e = tid; e < kTk * kTile; e += kThreads) {
+      const int rr = e / kTile, cc = e - rr * kTile;
+      const int64_t row = s0 + rr;
+      const bool okr = row < r1;
+      xs[rr][cc] = (okr && tbase + cc < d) ? x[row * d + tbase + cc] : 0.0f;
+      ys[rr][cc] = (okr && jbase + cc < d) ? yh[row * d + jbase + cc] : 0.0f;
+    }
+    __syncthreads();
+    const int rend = (int)min((int64_t)kTk, r1 - s0);
+    for (int rr = 0; rr < rend; ++rr) {
+      const float4 xv = *reinterpret_cast<const float4*>(&xs[rr][tr * 4]);
+      const float4 yv = *reinterpret_cast<const float4*>(&ys[rr][tc * 4]);
+      const double xa[4] = {(double)xv.x, (double)xv.y, (double)xv.z, (double)xv.w};
+      const double ya[4] = {(double)yv.x, (double)yv.y, (double)yv.z, (double)yv.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(xa[i], ya[j], acc[i][j]);   // exact product
+    }
+    __syncthreads();
+  }
+  double* out = part + (size_t)c * d * d;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int t = tbase + tr * 4 + i;
+    if (t >= d) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int jj = jbase + tc * 4 + j;
+      if (jj < d) out[(size_t)t * d + jj] = acc[i][j];
+    }
+  }
+}
+
+// M[t][j] = sum over chunks in order of part[c][t][j]
+__global__ void k_cross_reduce(const double* __restrict__ part, int nch, int d, double* __restrict__ m) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t dd = (int64_t)d * d;
+  if (e >= dd) return;
+  double s = 0.0;
+  for (int c = 0; c < nch; ++c) s += part[c * dd + e];
+  m[e] = s;
+}
+
+constexpr int kPolarThreads = 1024;
+
+// dot products of columns p and q over the group's rows, reduced over the G
+// lanes of the group (G a power of two within one wave)
+template <int G>
+__device__ __forceinline__ void group_sum3(double& a, double& b, double& c) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    b += __shfl_xor(b, off, 64);
+    c += __shfl_xor(c, off, 64);
+  }
+}
+
+// Column pair of slot k in round r of the round-robin schedule over de
+// (even) columns: position 0 stays, the others turn by one each round.
+__device__ __forceinline__ void round_pair(int de, int r, int k, int& p, int& q) {
+  const int mm = de - 1;
+  auto at = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + r) % mm; };
+  p = at(k);
+  q = at(de - 1 - k);
+}
+
+template <int G>
+__device__ void jacobi_sweeps(double* __restrict__ a, double* __restrict__ v, int d, int de, int max_sweeps,
+                              int* __restrict__ flag, int* sweeps_done) {
+  const int npairs = de / 2;
+  const int grp = threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  const double tol = 2.220446049250313e-16 * (double)d;
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    if (threadIdx.x == 0) *flag = 0;
+    __syncthreads();
+    for (int rnd = 0; rnd < de - 1; ++rnd) {
+      if (grp < npairs) {
+        int p, q;
+        round_pair(de, rnd, grp, p, q);
+        if (p > q) {
+          const int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        if (q < d) {   // a pair with the padding column (odd d) is idle
+          double* ap = a + (size_t)p * d;
+          double* aq = a + (size_t)q * d;
+          double alpha = 0.0, beta = 0.0, gamma = 0.0;
+          for (int i = lane; i < d; i += G) {
+            const double u = ap[i], w = aq[i];
+            alpha += u * u;
+            beta += w * w;
+            gamma += u * w;
+          }
+          group_sum3<G>(alpha, beta, gamma);
+          if (fabs(gamma) > tol * sqrt(alpha * beta) && fabs(gamma) > 0.0) {
+            const double zeta = (beta - alpha) / (2.0 * gamma);
+            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double cs = 1.0 / sqrt(1.0 + t * t);
+            const double sn = cs * t;
+            double* vp = v + (size_t)p * d;
+            double* vq = v + (size_t)q * d;
+            for (int i = lane; i < d; i += G) {
+              const double u = ap[i], w = aq[i];
+              ap[i] = cs * u - sn * w;
+              aq[i] = sn * u + cs * w;
+              const double vu = vp[i], vw = vq[i];
+              vp[i] = cs * vu - sn * vw;
+              vq[i] = sn * vu + cs * vw;
+            }
+            if (lane == 0) *flag = 1;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    const int any = *flag;
+    __syncthreads();
+    if (!any) break;
+  }
+  if (threadIdx.x == 0) *sweeps_done = sweep;
+}
+
+constexpr int kPolarMaxD = 256;
+
+// One work-group.  a: M copied column-major (a[col * d + row]); v: identity,
+// column-major; r: out R = U V^T (row-major float64); sweeps: out int (Jacobi
+// sweeps run; max_sweeps + 1 when not converged).  Threads exchange data
+// through global memory only across __syncthreads.
+__global__ __launch_bounds__(kPolarThreads) void k_polar(const double* __restrict__ m, int d, int max_sweeps,
+                                                         double* __restrict__ a, double* __restrict__ v,
+                                                         double* __restrict__ r, int* __restrict__ sweeps) {
+  __shared__ int flag;
+  __shared__ int sweeps_done;
+  __shared__ int best_k;
+  __shared__ double sig[kPolarMaxD];    // singular values; -1 marks a column still to complete
+  __shared__ double work[kPolarMaxD];   // residual norms, then projections
+  __shared__ double red[kPolarThreads / 64];
+  const int dd = d * d;
+  for (int e = threadIdx.x; e < dd; e += blockDim.x) {
+    const int col = e / d, row = e - col * d;
+    a[e] = m[(size_t)row * d + col];
+    v[e] = (row == col) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int de = d + (d & 1);
+  const int npairs = de / 2;
+  // lanes per pair: a power of two in [1, 64] with npairs * G <= 1024
+  int g = 64;
+  while (g > 1 && npairs * g > kPolarThreads) g >>= 1;
+  switch (g) {
+    case 64: jacobi_sweeps<64>(a, v, d, de, max_sweeps, &flag, &sweeps_done); break;
+    case 32: jacobi_sweeps<32>(a, v, d, de, max_sweeps, &flag, &sweeps_done); break;
+    case 16: jacobi_sweeps<16>(a, v, d, de, max_sweeps, &flag, &sweeps_done); break;
+    case 8: jacobi_sweeps<8>(a, v, d, de, max_sweeps, &flag, &sweeps_done); break;
+    case 4: jacobi_sweeps<4>(a, v, d, de, max_sweeps, &flag, &sweeps_done); break;
+    case 2: jacobi_sweeps<2>(a, v, d, de, max_sweeps, &flag, &sweeps_done); break;
+    default: jacobi_sweeps<1>(a, v, d, de, max_sweeps, &flag, &sweeps_done); break;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  // column norms = singular values, one wave per column
+  for (int col = wave; col < d; col += nw) {
+    double s = 0.0;
+    for (int i = lane; i < d; i += 64) s += a[(size_t)col * d + i] * a[(size_t)col * d + i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) sig[col] = sqrt(s);
+  }
+  __syncthreads();
+  double smax = 0.0;
+  for (int i = threadIdx.x; i < d; i += blockDim.x) smax = fmax(smax, sig[i]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off, 64));
+  if (lane == 0) red[wave] = smax;
+  __syncthreads();
+  smax = 0.0;
+  for (int i = 0; i < nw; ++i) smax = fmax(smax, red[i]);
+  // numerical rank: columns at or below d * eps * sigma_max are completed below
+  const double thr = smax * (double)d * 2.220446049250313e-16;
+  for (int e = threadIdx.x; e < dd; e += blockDim.x) {
+    const double sc = sig[e / d];
+    if (sc > thr && sc > 0.0) a[e] = a[e] / sc;
+  }
+  __syncthreads();
+  for (int col = threadIdx.x; col < d; col += blockDim.x)
+    if (!(sig[col] > thr && sig[col] > 0.0)) sig[col] = -1.0;
+  __syncthreads();
+  // basis completion, one missing column at a time: start from the unit
+  // vector e_k with the largest residual against the accepted columns, then
+  // two passes of classical Gram-Schmidt and a normalisation
+  for (int col = 0; col < d; ++col) {
+    if (sig[col] >= 0.0) continue;   // uniform: sig is in LDS, read after a barrier
+    double* u = a + (size_t)col * d;
+    for (int k = threadIdx.x; k < d; k += blockDim.x) {
+      double s = 0.0;
+      for (int c = 0; c < d; ++c)
+        if (sig[c] >= 0.0) s += a[(size_t)c * d + k] * a[(size_t)c * d + k];
+      work[k] = 1.0 - s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int bk = 0;
+      for (int k = 1; k < d; ++k)
+        if (work[k] > work[bk]) bk = k;
+      best_k = bk;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < d; i += blockDim.x) u[i] = (i == best_k) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int c = threadIdx.x; c < d; c += blockDim.x) {
+        double s = 0.0;
+        if (sig[c] >= 0.0)
+          for (int i = 0; i < d; ++i) s += a[(size_t)c * d + i] * u[i];
+        work[c] = s;
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < d; i += blockDim.x) {
+        double s = u[i];
+        for (int c = 0; c < d; ++c)
+          if (sig[c] >= 0.0) s -= work[c] * a[(size_t)c * d + i];
+        u[i] = s;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int i = 0; i < d; ++i) s += u[i] * u[i];
+      work[0] = 1.0 / sqrt(s);
+    }
+    __syncthreads();
+    const double inv = work[0];
+    for (int i = threadIdx.x; i < d; i += blockDim.x) u[i] *= inv;
+    __syncthreads();
+    if (threadIdx.x == 0) sig[col] = 0.0;   // accepted from now on
+    __syncthreads();
+  }
+  // R[t][j] = sum over columns c of U[t][c] V[j][c]
+  for (int e = threadIdx.x; e < dd; e += blockDim.x) {
+    const int t = e / d, j = e - t * d;
+    double s = 0.0;
+    for (int c = 0; c < d; ++c) s += a[(size_t)c * d + t] * v[(size_t)c * d + j];
+    r[e] = s;
+  }
+  if (threadIdx.x == 0) *sweeps = sweeps_done < max_sweeps ? sweeps_done : max_sweeps + 1;
+}
+
+}  // namespace
+
+int launch_rotate(const float* x, int64_t n, int d, const double* r, float* y, hipStream_t s) {
+  if (n == 0) return MIPQ_OK;
+  const int ctiles = (d + kTile - 1) / kTile;
+  const int64_t rtiles = (n + kTile - 1) / kTile;
+  const int64_t nblocks = rtiles * ctiles;
+  const int64_t grid = ((nblocks + 7) / 8) * 8;
+  if (grid > 0x7fffffff) return fail(MIPQ_EUNSUPPORTED, "too many rows for one rotation launch");
+  ProfScope ps(MIPQ_K_ROTATE, s);
+  k_rotate<<<(unsigned)grid, kThreads, 0, s>>>(x, n, d, r, y, ctiles, nblocks);
+  MIPQ_LAUNCHED("k_rotate");
+  return MIPQ_OK;
+}
+
+int cross_chunks(int64_t n, int d) {
+  const int tiles = (d + kTile - 1) / kTile;
+  int64_t nch = (n + 1023) / 1024;
+  int64_t cap = 2048 / (tiles * tiles);
+  if (cap < 1) cap = 1;
+  if (nch > cap) nch = cap;
+  return nch < 1 ? 1 : (int)nch;
+}
+
+int launch_cross(const float* x, const float* yh, int64_t n, int d, int nch, double* part, double* m,
+                 hipStream_t s) {
+  const int tiles = (d + kTile - 1) / kTile;
+  const int64_t rpc = (n + nch - 1) / nch;
+  ProfScope ps(MIPQ_K_CROSS, s);
+  k_cross_partial<<<(unsigned)(nch * tiles * tiles), kThreads, 0, s>>>(x, yh, n, d, rpc > 0 ? rpc : 1, tiles,
+                                                                       part);
+  MIPQ_LAUNCHED("k_cross_partial");
+  const int64_t dd = (int64_t)d * d;
+  k_cross_reduce<<<(unsigned)((dd + 255) / 256), 256, 0, s>>>(part, nch, d, m);
+  MIPQ_LAUNCHED("k_cross_reduce");
+  return MIPQ_OK;
+}
+
+int launch_polar(const double* m, int d, int max_sweeps, double* a, double* v, double* r, int* sweeps,
+                 hipStream_t s) {
+  if (d < 1 || d > kPolarMaxD) return fail(MIPQ_EUNSUPPORTED, "the rotation fit supports 1 <= d <= %d", kPolarMaxD);
+  ProfScope ps(MIPQ_K_POLAR, s);
+  k_polar<<<1, kPolarThreads, 0, s>>>(m, d, max_sweeps, a, v, r, sweeps);
+  MIPQ_LAUNCHED("k_polar");
+  return MIPQ_OK;
+}
+
+}  // namespace mipq

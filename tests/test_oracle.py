@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 import scipy.cluster.vq as scv
 
-from oracle import chunked, grad, ivf, pq
+from oracle import chunked, grad, ivf, opq, pq
 from synth import workloads as wl
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -414,3 +414,61 @@ def test_paper_sizing_examples():
     cb = pq.init_codebook(x, init, vals["subspaces_example"])
     codes, _ = pq.encode(x, cb)
     assert codes.shape[1] == vals["codes_per_row_example"]
+
+
+# ---------------------------------------------------------------- optimized PQ
+
+def _orthogonal(seed, d):
+    q, r = np.linalg.qr(np.random.default_rng(seed).standard_normal((d, d)))
+    return q * np.sign(np.diag(r))[None, :]
+
+
+def test_rotation_by_a_permutation_and_identity_is_exact():
+    x = _rand(30, 200, 24)
+    perm = np.random.default_rng(31).permutation(24)
+    p = np.eye(24)[perm].T          # (x P)[:, j] = x[:, perm[j]]
+    np.testing.assert_array_equal(opq.rotate(x, p), x[:, perm])
+    np.testing.assert_array_equal(opq.rotate(x, np.eye(24)), x)
+
+
+def test_procrustes_recovers_a_known_rotation():
+    x = _rand(32, 500, 16).astype(np.float64)
+    q = _orthogonal(33, 16)
+    r, m = opq.procrustes(x, x @ q)
+    np.testing.assert_allclose(r, q, atol=1e-10)
+    np.testing.assert_allclose(m, x.T @ x @ q, rtol=1e-12, atol=1e-9)
+
+
+def test_procrustes_is_orthogonal_and_beats_other_rotations():
+    x = _rand(34, 300, 12).astype(np.float64)
+    y = _rand(35, 300, 12).astype(np.float64)
+    r, _ = opq.procrustes(x, y)
+    np.testing.assert_allclose(r.T @ r, np.eye(12), atol=1e-12)
+    best = np.linalg.norm(x @ r - y)
+    for s in range(100):
+        assert best <= np.linalg.norm(x @ _orthogonal(100 + s, 12) - y) + 1e-12
+    # and every small rotation away from R (Cayley transform of a small skew matrix)
+    rng = np.random.default_rng(36)
+    for _ in range(50):
+        a = 1e-3 * rng.standard_normal((12, 12))
+        k = a - a.T
+        c = np.linalg.solve(np.eye(12) + k, np.eye(12) - k)
+        assert best <= np.linalg.norm(x @ (r @ c) - y) + 1e-12
+
+
+def test_first_outer_iteration_is_plain_pq_and_objective_falls():
+    x = wl.gaussian_mixture(37, 2000, 16, 30, sigma=0.1)
+    x = (x.astype(np.float64) @ _orthogonal(38, 16)).astype(np.float32)   # correlated dimensions
+    init = wl.init_rows_per_subspace(37, 2000, 4, 16)
+    fit1 = opq.opq_fit(x, init, 4, 1, 3)
+    ref = pq.lloyd(x, init, 4, 3, decide="fp32")
+    np.testing.assert_array_equal(fit1["codebook"], ref["codebook"].astype(np.float32).astype(np.float64))
+    # the first Procrustes step cannot raise the distortion of plain PQ (R = I)
+    codes, _ = pq.encode(x, fit1["codebook"], decide="fp32")
+    e_pq = opq.distortion(x, np.eye(16), codes, fit1["codebook"])
+    assert fit1["objective"][0] <= e_pq * (1 + 1e-6)
+    fit = opq.opq_fit(x, init, 4, 6, 2)
+    obj = fit["objective"]
+    assert np.all(np.diff(obj) <= 1e-5 * obj[:-1])
+    assert obj[-1] < 0.97 * e_pq
+    np.testing.assert_allclose(fit["R"].T @ fit["R"], np.eye(16), atol=1e-12)
