@@ -637,6 +637,7 @@ constexpr int kPolarSweeps = 64;
 
 struct ProcWs {
   double *part, *m, *a, *v;
+  void* rlog;
   int* sweeps;
   int nch;
   size_t bytes;
@@ -651,6 +652,8 @@ ProcWs carve_proc(void* ws, int64_t n, int d, bool need_m, bool need_sweeps) {
   w.m = need_m ? c.take<double>(dd) : nullptr;
   w.a = c.take<double>(dd);
   w.v = c.take<double>(dd);
+  const size_t lb = polar_log_bytes(d, kPolarSweeps);
+  w.rlog = lb ? c.take<char>(lb) : nullptr;
   w.sweeps = need_sweeps ? c.take<int>(1) : nullptr;
   w.bytes = c.bytes();
   return w;
@@ -691,5 +694,5 @@ int mipq_opq_procrustes(const float* x, const float* y_hat, int64_t n, int d, do
   } else if ((rc = launch_cross(x, y_hat, n, d, w.nch, w.part, m, s))) {
     return rc;
   }
-  return launch_polar(m, d, kPolarSweeps, w.a, w.v, rotation, sw, s);
+  return launch_polar(m, d, kPolarSweeps, w.a, w.v, w.rlog, rotation, sw, s);
 }

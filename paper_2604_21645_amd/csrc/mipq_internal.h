@@ -154,7 +154,8 @@ int launch_rotate(const float* x, int64_t n, int d, const double* r, float* y, h
 int cross_chunks(int64_t n, int d);
 int launch_cross(const float* x, const float* yh, int64_t n, int d, int nch, double* part, double* m,
                  hipStream_t s);
-int launch_polar(const double* m, int d, int max_sweeps, double* a, double* v, double* r, int* sweeps,
+size_t polar_log_bytes(int d, int max_sweeps);   // rotation log of launch_polar (0: none needed)
+int launch_polar(const double* m, int d, int max_sweeps, double* a, double* v, void* rlog, double* r, int* sweeps,
                  hipStream_t s);
 // merge of inverted lists of consecutive row ranges; parts: device array of
 // {const int64_t* off; const int32_t* ids; const uint8_t* codes; int64_t n; int64_t base}

@@ -181,9 +181,14 @@ __device__ __forceinline__ void round_pair(int de, int r, int k, int& p, int& q)
   q = at(de - 1 - k);
 }
 
+// Sweeps of one-sided Jacobi over the columns of a (column c at a + c * lda)
+// until a sweep rotates no pair.  With v, the rotations are applied to v's
+// columns (stride d) as they happen; with rlog, each pair slot of each round
+// records its rotation (cos, sin) instead ((1, 0) for none), to be replayed
+// onto V afterwards.
 template <int G>
-__device__ void jacobi_sweeps(double* __restrict__ a, double* __restrict__ v, int d, int de, int max_sweeps,
-                              int* __restrict__ flag, int* sweeps_done) {
+__device__ void jacobi_sweeps(double* __restrict__ a, int lda, double* __restrict__ v, double2* __restrict__ rlog,
+                              int d, int de, int max_sweeps, int* __restrict__ flag, int* sweeps_done) {
   const int npairs = de / 2;
   const int grp = threadIdx.x / G;
   const int lane = threadIdx.x % G;
@@ -201,9 +206,10 @@ __device__ void jacobi_sweeps(double* __restrict__ a, double* __restrict__ v, in
           p = q;
           q = tmp;
         }
+        double cs = 1.0, sn = 0.0;
         if (q < d) {   // a pair with the padding column (odd d) is idle
-          double* ap = a + (size_t)p * d;
-          double* aq = a + (size_t)q * d;
+          double* ap = a + (size_t)p * lda;
+          double* aq = a + (size_t)q * lda;
           double alpha = 0.0, beta = 0.0, gamma = 0.0;
           for (int i = lane; i < d; i += G) {
             const double u = ap[i], w = aq[i];
@@ -215,21 +221,26 @@ __device__ void jacobi_sweeps(double* __restrict__ a, double* __restrict__ v, in
           if (fabs(gamma) > tol * sqrt(alpha * beta) && fabs(gamma) > 0.0) {
             const double zeta = (beta - alpha) / (2.0 * gamma);
             const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double cs = 1.0 / sqrt(1.0 + t * t);
-            const double sn = cs * t;
-            double* vp = v + (size_t)p * d;
-            double* vq = v + (size_t)q * d;
+            cs = 1.0 / sqrt(1.0 + t * t);
+            sn = cs * t;
             for (int i = lane; i < d; i += G) {
               const double u = ap[i], w = aq[i];
               ap[i] = cs * u - sn * w;
               aq[i] = sn * u + cs * w;
-              const double vu = vp[i], vw = vq[i];
-              vp[i] = cs * vu - sn * vw;
-              vq[i] = sn * vu + cs * vw;
+            }
+            if (v) {
+              double* vp = v + (size_t)p * d;
+              double* vq = v + (size_t)q * d;
+              for (int i = lane; i < d; i += G) {
+                const double vu = vp[i], vw = vq[i];
+                vp[i] = cs * vu - sn * vw;
+                vq[i] = sn * vu + cs * vw;
+              }
             }
             if (lane == 0) *flag = 1;
           }
         }
+        if (rlog && lane == 0) rlog[((size_t)sweep * (de - 1) + rnd) * npairs + grp] = make_double2(cs, sn);
       }
       __syncthreads();
     }
@@ -240,26 +251,73 @@ __device__ void jacobi_sweeps(double* __restrict__ a, double* __restrict__ v, in
   if (threadIdx.x == 0) *sweeps_done = sweep;
 }
 
-constexpr int kPolarMaxD = 256;
+// V = the product of the logged rotations of `sweeps` sweeps, applied to the
+// identity in the order they were taken (column c at v + c * ldv)
+template <int G>
+__device__ void replay_rotations(double* __restrict__ v, int ldv, const double2* __restrict__ rlog, int d, int de,
+                                 int sweeps) {
+  const int npairs = de / 2;
+  const int grp = threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+    const int col = e / d, row = e - col * d;
+    v[(size_t)col * ldv + row] = (row == col) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int sw = 0; sw < sweeps; ++sw)
+    for (int rnd = 0; rnd < de - 1; ++rnd) {
+      if (grp < npairs) {
+        const double2 r = rlog[((size_t)sw * (de - 1) + rnd) * npairs + grp];
+        int p, q;
+        round_pair(de, rnd, grp, p, q);
+        if (p > q) {
+          const int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        if (q < d && r.y != 0.0) {
+          double* vp = v + (size_t)p * ldv;
+          double* vq = v + (size_t)q * ldv;
+          for (int i = lane; i < d; i += G) {
+            const double vu = vp[i], vw = vq[i];
+            vp[i] = r.x * vu - r.y * vw;
+            vq[i] = r.y * vu + r.x * vw;
+          }
+        }
+      }
+      __syncthreads();
+    }
+}
 
-// One work-group.  a: M copied column-major (a[col * d + row]); v: identity,
-// column-major; r: out R = U V^T (row-major float64); sweeps: out int (Jacobi
-// sweeps run; max_sweeps + 1 when not converged).  Threads exchange data
-// through global memory only across __syncthreads.
+constexpr int kPolarMaxD = 256;
+constexpr int kPolarMaxDLds = 128;   // A (d x (d+1) float64) in LDS up to this d
+
+// One work-group.  a: out M V column-major (a[col * d + row]), then U; v: out
+// V column-major; r: out R = U V^T (row-major float64); sweeps: out int
+// (Jacobi sweeps run; max_sweeps + 1 when not converged).
+// LDSA: the Jacobi sweeps run on a copy of M in LDS (d <= 128) and log their
+// rotations in rlog; V is then rebuilt in LDS from the log.  Otherwise they
+// run on a and v in global memory.  Threads exchange data through global
+// memory only across __syncthreads.
+template <bool LDSA>
 __global__ __launch_bounds__(kPolarThreads) void k_polar(const double* __restrict__ m, int d, int max_sweeps,
                                                          double* __restrict__ a, double* __restrict__ v,
-                                                         double* __restrict__ r, int* __restrict__ sweeps) {
+                                                         double2* __restrict__ rlog, double* __restrict__ r,
+                                                         int* __restrict__ sweeps) {
   __shared__ int flag;
   __shared__ int sweeps_done;
   __shared__ int best_k;
   __shared__ double sig[kPolarMaxD];    // singular values; -1 marks a column still to complete
   __shared__ double work[kPolarMaxD];   // residual norms, then projections
   __shared__ double red[kPolarThreads / 64];
+  extern __shared__ double lds_mat[];   // LDSA: d x (d + 1)
   const int dd = d * d;
+  const int ld = LDSA ? d + 1 : d;
+  double* aw = LDSA ? lds_mat : a;
   for (int e = threadIdx.x; e < dd; e += blockDim.x) {
     const int col = e / d, row = e - col * d;
-    a[e] = m[(size_t)row * d + col];
-    v[e] = (row == col) ? 1.0 : 0.0;
+    aw[(size_t)col * ld + row] = m[(size_t)row * d + col];
+    if (!LDSA) v[e] = (row == col) ? 1.0 : 0.0;
   }
   __syncthreads();
   const int de = d + (d & 1);
@@ -267,14 +325,38 @@ __global__ __launch_bounds__(kPolarThreads) void k_polar(const double* __restric
   // lanes per pair: a power of two in [1, 64] with npairs * G <= 1024
   int g = 64;
   while (g > 1 && npairs * g > kPolarThreads) g >>= 1;
+  double* vv = LDSA ? nullptr : v;
+  double2* lg = LDSA ? rlog : nullptr;
   switch (g) {
-    case 64: jacobi_sweeps<64>(a, v, d, de, max_sweeps, &flag, &sweeps_done); break;
-    case 32: jacobi_sweeps<32>(a, v, d, de, max_sweeps, &flag, &sweeps_done); break;
-    case 16: jacobi_sweeps<16>(a, v, d, de, max_sweeps, &flag, &sweeps_done); break;
-    case 8: jacobi_sweeps<8>(a, v, d, de, max_sweeps, &flag, &sweeps_done); break;
-    case 4: jacobi_sweeps<4>(a, v, d, de, max_sweeps, &flag, &sweeps_done); break;
-    case 2: jacobi_sweeps<2>(a, v, d, de, max_sweeps, &flag, &sweeps_done); break;
-    default: jacobi_sweeps<1>(a, v, d, de, max_sweeps, &flag, &sweeps_done); break;
+    case 64: jacobi_sweeps<64>(aw, ld, vv, lg, d, de, max_sweeps, &flag, &sweeps_done); break;
+    case 32: jacobi_sweeps<32>(aw, ld, vv, lg, d, de, max_sweeps, &flag, &sweeps_done); break;
+    case 16: jacobi_sweeps<16>(aw, ld, vv, lg, d, de, max_sweeps, &flag, &sweeps_done); break;
+    case 8: jacobi_sweeps<8>(aw, ld, vv, lg, d, de, max_sweeps, &flag, &sweeps_done); break;
+    case 4: jacobi_sweeps<4>(aw, ld, vv, lg, d, de, max_sweeps, &flag, &sweeps_done); break;
+    case 2: jacobi_sweeps<2>(aw, ld, vv, lg, d, de, max_sweeps, &flag, &sweeps_done); break;
+    default: jacobi_sweeps<1>(aw, ld, vv, lg, d, de, max_sweeps, &flag, &sweeps_done); break;
+  }
+  if (LDSA) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < dd; e += blockDim.x) {
+      const int col = e / d, row = e - col * d;
+      a[e] = lds_mat[(size_t)col * ld + row];
+    }
+    __syncthreads();
+    const int nsw = sweeps_done;
+    switch (g) {
+      case 64: replay_rotations<64>(lds_mat, ld, rlog, d, de, nsw); break;
+      case 32: replay_rotations<32>(lds_mat, ld, rlog, d, de, nsw); break;
+      case 16: replay_rotations<16>(lds_mat, ld, rlog, d, de, nsw); break;
+      case 8: replay_rotations<8>(lds_mat, ld, rlog, d, de, nsw); break;
+      case 4: replay_rotations<4>(lds_mat, ld, rlog, d, de, nsw); break;
+      case 2: replay_rotations<2>(lds_mat, ld, rlog, d, de, nsw); break;
+      default: replay_rotations<1>(lds_mat, ld, rlog, d, de, nsw); break;
+    }
+    for (int e = threadIdx.x; e < dd; e += blockDim.x) {
+      const int col = e / d, row = e - col * d;
+      v[e] = lds_mat[(size_t)col * ld + row];
+    }
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -404,11 +486,23 @@ int launch_cross(const float* x, const float* yh, int64_t n, int d, int nch, dou
   return MIPQ_OK;
 }
 
-int launch_polar(const double* m, int d, int max_sweeps, double* a, double* v, double* r, int* sweeps,
+size_t polar_log_bytes(int d, int max_sweeps) {
+  if (d > kPolarMaxDLds) return 0;
+  const int de = d + (d & 1);
+  return (size_t)max_sweeps * (de - 1) * (de / 2) * sizeof(double2);
+}
+
+int launch_polar(const double* m, int d, int max_sweeps, double* a, double* v, void* rlog, double* r, int* sweeps,
                  hipStream_t s) {
   if (d < 1 || d > kPolarMaxD) return fail(MIPQ_EUNSUPPORTED, "the rotation fit supports 1 <= d <= %d", kPolarMaxD);
   ProfScope ps(MIPQ_K_POLAR, s);
-  k_polar<<<1, kPolarThreads, 0, s>>>(m, d, max_sweeps, a, v, r, sweeps);
+  if (d <= kPolarMaxDLds) {
+    if (!rlog) return fail(MIPQ_EINVAL, "rotation log missing");
+    const size_t shm = (size_t)d * (d + 1) * sizeof(double);
+    k_polar<true><<<1, kPolarThreads, shm, s>>>(m, d, max_sweeps, a, v, static_cast<double2*>(rlog), r, sweeps);
+  } else {
+    k_polar<false><<<1, kPolarThreads, 0, s>>>(m, d, max_sweeps, a, v, nullptr, r, sweeps);
+  }
   MIPQ_LAUNCHED("k_polar");
   return MIPQ_OK;
 }
