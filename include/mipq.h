@@ -353,15 +353,20 @@ int mipq_recon_backward(const float* x, const uint8_t* codes, const float* codeb
  *   value decomposition is one-sided Jacobi in float64 on one work-group;
  *   columns of U whose singular value is at most d * 2^-52 * the largest are
  *   completed to an orthonormal basis (R is then one of the minimisers).
- *   rotation: OUT float64 [d][d] row-major; cross: OUT optional float64
- *   [d][d] (M); sweeps: OUT optional device int (Jacobi sweeps run, 65 if
- *   64 sweeps did not converge).  d in [1, 256]; n >= 0 (n == 0 gives M = 0
- *   and R = I).
+ *   v_init: optional float64 [d][d] row-major orthogonal start V0 (the
+ *   v_out of a previous call on a similar M): the sweeps then run on M V0,
+ *   which converges in fewer sweeps; R is the same minimiser up to rounding.
+ *   rotation: OUT float64 [d][d] row-major; v_out: OUT optional float64
+ *   [d][d] row-major (V); cross: OUT optional float64 [d][d] (M); sweeps:
+ *   OUT optional device int (Jacobi sweeps run, 65 if 64 sweeps did not
+ *   converge).  d in [1, 256]; n >= 0 (n == 0 gives M = 0 and R = I when
+ *   v_init is not given).
  * ------------------------------------------------------------------------- */
 int mipq_rotate(const float* x, int64_t n, int d, const double* rotation, float* y, void* stream);
 size_t mipq_opq_procrustes_workspace_size(int64_t n, int d);
-int mipq_opq_procrustes(const float* x, const float* y_hat, int64_t n, int d, double* rotation,
-                        double* cross, int* sweeps, void* ws, size_t ws_bytes, void* stream);
+int mipq_opq_procrustes(const float* x, const float* y_hat, int64_t n, int d, const double* v_init,
+                        double* rotation, double* v_out, double* cross, int* sweeps, void* ws, size_t ws_bytes,
+                        void* stream);
 
 /* -------------------------------------------------------------------------
  * Per-kernel timing (tracing aid, off by default).

@@ -335,10 +335,12 @@ def rotate(x: torch.Tensor, rotation: torch.Tensor) -> torch.Tensor:
     return y
 
 
-def procrustes(x: torch.Tensor, y_hat: torch.Tensor):
+def procrustes(x: torch.Tensor, y_hat: torch.Tensor, v_init: torch.Tensor | None = None,
+               return_v: bool = False):
     """Orthogonal R minimising ||x R - y_hat|| (``mipq_opq_procrustes``):
     returns (R float64 [d, d], M = x^T y_hat float64 [d, d], Jacobi sweeps
-    int32 [1])."""
+    int32 [1]) and, with ``return_v``, V float64 [d, d] to warm-start the
+    next call through ``v_init``."""
     L = lib()
     x = _dev(x, torch.float32, "x")
     yh = _dev(y_hat, torch.float32, "y_hat")
@@ -346,13 +348,17 @@ def procrustes(x: torch.Tensor, y_hat: torch.Tensor):
         raise ValueError("x and y_hat must have the same shape")
     n, d = x.shape
     dev = x.device
+    v0 = _dev(v_init, torch.float64, "v_init") if v_init is not None else None
+    if v0 is not None and tuple(v0.shape) != (d, d):
+        raise ValueError("v_init must be [d, d]")
     r = torch.empty((d, d), dtype=torch.float64, device=dev)
     m = torch.empty((d, d), dtype=torch.float64, device=dev)
+    v = torch.empty((d, d), dtype=torch.float64, device=dev) if return_v else None
     sw = torch.empty(1, dtype=torch.int32, device=dev)
     ws = _ws(L.mipq_opq_procrustes_workspace_size(n, d), dev)
-    check(L.mipq_opq_procrustes(_ptr(x), _ptr(yh), n, d, _ptr(r), _ptr(m), _ptr(sw), _ptr(ws), ws.numel(),
-                                _stream(dev)))
-    return r, m, sw
+    check(L.mipq_opq_procrustes(_ptr(x), _ptr(yh), n, d, _ptr(v0), _ptr(r), _ptr(v), _ptr(m), _ptr(sw), _ptr(ws),
+                                ws.numel(), _stream(dev)))
+    return (r, m, sw, v) if return_v else (r, m, sw)
 
 
 def opq_fit(x: torch.Tensor, m: int, ks: int, outer_iters: int, pq_iters: int, init_rows: torch.Tensor,
@@ -365,13 +371,17 @@ def opq_fit(x: torch.Tensor, m: int, ks: int, outer_iters: int, pq_iters: int, i
 
     Returns dict(R float64 [d, d], codebook float32 [m, ks, d/m], objective
     float64 [outer_iters] = SSE of x R (rounded to float32) against the
-    decoded codes after each rotation update, and with ``history`` the lists
-    ``rotations`` and ``codebooks`` of every outer iteration).
+    decoded codes after each rotation update, sweeps (Jacobi sweeps of each
+    Procrustes step, each warm-started from the previous step's V), and with
+    ``history`` the lists ``rotations`` and ``codebooks`` of every outer
+    iteration).
     """
     x = _dev(x, torch.float32, "x")
     dev = x.device
     n, d = x.shape
     r = torch.eye(d, dtype=torch.float64, device=dev)
+    v = None      # V of the previous Procrustes step: warm start of the next
+    sweeps = []
     cb = None
     obj = torch.empty(max(outer_iters, 0), dtype=torch.float64, device=dev)
     rots, books = [], []
@@ -385,7 +395,8 @@ def opq_fit(x: torch.Tensor, m: int, ks: int, outer_iters: int, pq_iters: int, i
                         objective=False)["codebook"]
         codes = pq_encode(y, cb, precision)
         yh, _ = pq_decode_rmse(codes, cb, x_hat=True)
-        r, _, _ = procrustes(x, yh)
+        r, _, sw, v = procrustes(x, yh, v_init=v, return_v=True)
+        sweeps.append(sw)
         _, sr = pq_decode_rmse(codes, cb, rotate(x, r))
         obj[it:it + 1].copy_(sr[0:1])
         if history:
@@ -393,7 +404,7 @@ def opq_fit(x: torch.Tensor, m: int, ks: int, outer_iters: int, pq_iters: int, i
             books.append(cb)
     if cb is None:
         raise ValueError("outer_iters must be >= 1")
-    out = {"R": r, "codebook": cb, "objective": obj}
+    out = {"R": r, "codebook": cb, "objective": obj, "sweeps": sweeps}
     if history:
         out["rotations"] = rots
         out["codebooks"] = books

@@ -52,7 +52,7 @@ SIGNATURES = {
     "mipq_plan_destroy": (_I, [_P]),
     "mipq_rotate": (_I, [_P, _L, _I, _P, _P, _P]),
     "mipq_opq_procrustes_workspace_size": (_S, [_L, _I]),
-    "mipq_opq_procrustes": (_I, [_P, _P, _L, _I, _P, _P, _P, _P, _S, _P]),
+    "mipq_opq_procrustes": (_I, [_P, _P, _L, _I, _P, _P, _P, _P, _P, _P, _S, _P]),
     "mipq_profile_enable": (_I, [_I]),
     "mipq_profile_collect": (_I, [_I, ctypes.POINTER(_L), ctypes.POINTER(ctypes.c_double)]),
 }

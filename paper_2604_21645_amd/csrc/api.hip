@@ -636,7 +636,7 @@ namespace {
 constexpr int kPolarSweeps = 64;
 
 struct ProcWs {
-  double *part, *m, *a, *v;
+  double *part, *m, *a, *v, *m0, *rj, *vj;
   void* rlog;
   int* sweeps;
   int nch;
@@ -652,6 +652,9 @@ ProcWs carve_proc(void* ws, int64_t n, int d, bool need_m, bool need_sweeps) {
   w.m = need_m ? c.take<double>(dd) : nullptr;
   w.a = c.take<double>(dd);
   w.v = c.take<double>(dd);
+  w.m0 = c.take<double>(dd);
+  w.rj = c.take<double>(dd);
+  w.vj = c.take<double>(dd);
   const size_t lb = polar_log_bytes(d, kPolarSweeps);
   w.rlog = lb ? c.take<char>(lb) : nullptr;
   w.sweeps = need_sweeps ? c.take<int>(1) : nullptr;
@@ -678,8 +681,9 @@ size_t mipq_opq_procrustes_workspace_size(int64_t n, int d) {
   return carve_proc(nullptr, n, d, true, true).bytes;
 }
 
-int mipq_opq_procrustes(const float* x, const float* y_hat, int64_t n, int d, double* rotation, double* cross,
-                        int* sweeps, void* ws, size_t ws_bytes, void* stream) {
+int mipq_opq_procrustes(const float* x, const float* y_hat, int64_t n, int d, const double* v_init,
+                        double* rotation, double* v_out, double* cross, int* sweeps, void* ws, size_t ws_bytes,
+                        void* stream) {
   if (n < 0) return fail(MIPQ_EINVAL, "n must be >= 0");
   if (d < 1 || d > 256) return fail(MIPQ_EUNSUPPORTED, "the rotation fit supports 1 <= d <= 256 (got %d)", d);
   if (!rotation || (n > 0 && (!x || !y_hat))) return fail(MIPQ_EINVAL, "x, y_hat and rotation are required");
@@ -694,5 +698,5 @@ int mipq_opq_procrustes(const float* x, const float* y_hat, int64_t n, int d, do
   } else if ((rc = launch_cross(x, y_hat, n, d, w.nch, w.part, m, s))) {
     return rc;
   }
-  return launch_polar(m, d, kPolarSweeps, w.a, w.v, w.rlog, rotation, sw, s);
+  return launch_polar(m, d, kPolarSweeps, v_init, w.m0, w.a, w.v, w.rj, w.vj, w.rlog, rotation, v_out, sw, s);
 }

@@ -155,8 +155,8 @@ int cross_chunks(int64_t n, int d);
 int launch_cross(const float* x, const float* yh, int64_t n, int d, int nch, double* part, double* m,
                  hipStream_t s);
 size_t polar_log_bytes(int d, int max_sweeps);   // rotation log of launch_polar (0: none needed)
-int launch_polar(const double* m, int d, int max_sweeps, double* a, double* v, void* rlog, double* r, int* sweeps,
-                 hipStream_t s);
+int launch_polar(const double* m, int d, int max_sweeps, const double* v0, double* m0, double* a, double* v,
+                 double* rj, double* vj, void* rlog, double* r, double* v_out, int* sweeps, hipStream_t s);
 // merge of inverted lists of consecutive row ranges; parts: device array of
 // {const int64_t* off; const int32_t* ids; const uint8_t* codes; int64_t n; int64_t base}
 size_t merge_part_bytes();

@@ -174,19 +174,52 @@ __device__ __forceinline__ void group_sum3(double& a, double& b, double& c) {
 
 // Column pair of slot k in round r of the round-robin schedule over de
 // (even) columns: position 0 stays, the others turn by one each round.
+// Returned with p < q.
 __device__ __forceinline__ void round_pair(int de, int r, int k, int& p, int& q) {
   const int mm = de - 1;
-  auto at = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + r) % mm; };
-  p = at(k);
-  q = at(de - 1 - k);
+  auto at = [&](int pos) {
+    if (pos == 0) return 0;
+    int v = pos - 1 + r;   // < 2 * mm
+    if (v >= mm) v -= mm;
+    return 1 + v;
+  };
+  const int a = at(k), b = at(de - 1 - k);
+  p = a < b ? a : b;
+  q = a < b ? b : a;
+}
+
+// Work-group barrier.  LOCAL: orders LDS accesses only (outstanding global
+// stores, such as the rotation log, are not waited for at every barrier).
+template <bool LOCAL>
+__device__ __forceinline__ void block_sync() {
+  if (LOCAL) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  } else {
+    __syncthreads();
+  }
+}
+
+// Jacobi rotation (cos, sin) that makes columns with squared norms alpha,
+// beta and inner product gamma orthogonal: tan = sign(z) / (|z| + sqrt(1 + z^2))
+// with z = (beta - alpha) / (2 gamma), written with one division.
+__device__ __forceinline__ void jacobi_rotation(double alpha, double beta, double gamma, double& cs, double& sn) {
+  const double h = beta - alpha;
+  const double g2 = 2.0 * fabs(gamma);
+  double t = g2 / (fabs(h) + sqrt(h * h + g2 * g2));
+  if ((h < 0.0) != (gamma < 0.0)) t = -t;   // sign of z = h / (2 gamma)
+  cs = rsqrt(1.0 + t * t);
+  sn = cs * t;
 }
 
 // Sweeps of one-sided Jacobi over the columns of a (column c at a + c * lda)
-// until a sweep rotates no pair.  With v, the rotations are applied to v's
-// columns (stride d) as they happen; with rlog, each pair slot of each round
-// records its rotation (cos, sin) instead ((1, 0) for none), to be replayed
-// onto V afterwards.
-template <int G>
+// until a sweep rotates no pair.  The G lanes of a pair hold its two columns
+// in registers, RPL rows each (RPL * G >= d).  With v, the rotations are
+// applied to v's columns (stride d) as they happen; with rlog, each pair slot
+// of each round records its rotation (cos, sin) instead ((1, 0) for none), to
+// be replayed onto V afterwards.
+template <int G, int RPL, bool LOCAL>
 __device__ void jacobi_sweeps(double* __restrict__ a, int lda, double* __restrict__ v, double2* __restrict__ rlog,
                               int d, int de, int max_sweeps, int* __restrict__ flag, int* sweeps_done) {
   const int npairs = de / 2;
@@ -196,37 +229,54 @@ __device__ void jacobi_sweeps(double* __restrict__ a, int lda, double* __restric
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
     if (threadIdx.x == 0) *flag = 0;
-    __syncthreads();
+    block_sync<LOCAL>();
     for (int rnd = 0; rnd < de - 1; ++rnd) {
       if (grp < npairs) {
         int p, q;
         round_pair(de, rnd, grp, p, q);
-        if (p > q) {
-          const int tmp = p;
-          p = q;
-          q = tmp;
-        }
         double cs = 1.0, sn = 0.0;
         if (q < d) {   // a pair with the padding column (odd d) is idle
           double* ap = a + (size_t)p * lda;
           double* aq = a + (size_t)q * lda;
+          // up to 8 rows per lane stay in registers from the dot products to
+          // the rotation; longer columns are read again in chunks of 8
+          constexpr int CH = RPL < 8 ? RPL : 8;
+          double u[CH], w[CH];
           double alpha = 0.0, beta = 0.0, gamma = 0.0;
-          for (int i = lane; i < d; i += G) {
-            const double u = ap[i], w = aq[i];
-            alpha += u * u;
-            beta += w * w;
-            gamma += u * w;
+          for (int k0 = 0; k0 < RPL; k0 += CH) {
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+              const int i = lane + (k0 + k) * G;
+              u[k] = i < d ? ap[i] : 0.0;
+              w[k] = i < d ? aq[i] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+              alpha += u[k] * u[k];
+              beta += w[k] * w[k];
+              gamma += u[k] * w[k];
+            }
           }
           group_sum3<G>(alpha, beta, gamma);
           if (fabs(gamma) > tol * sqrt(alpha * beta) && fabs(gamma) > 0.0) {
-            const double zeta = (beta - alpha) / (2.0 * gamma);
-            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            cs = 1.0 / sqrt(1.0 + t * t);
-            sn = cs * t;
-            for (int i = lane; i < d; i += G) {
-              const double u = ap[i], w = aq[i];
-              ap[i] = cs * u - sn * w;
-              aq[i] = sn * u + cs * w;
+            jacobi_rotation(alpha, beta, gamma, cs, sn);
+            for (int k0 = 0; k0 < RPL; k0 += CH) {
+              if (RPL > CH) {
+#pragma unroll
+                for (int k = 0; k < CH; ++k) {
+                  const int i = lane + (k0 + k) * G;
+                  u[k] = i < d ? ap[i] : 0.0;
+                  w[k] = i < d ? aq[i] : 0.0;
+                }
+              }
+#pragma unroll
+              for (int k = 0; k < CH; ++k) {
+                const int i = lane + (k0 + k) * G;
+                if (i < d) {
+                  ap[i] = cs * u[k] - sn * w[k];
+                  aq[i] = sn * u[k] + cs * w[k];
+                }
+              }
             }
             if (v) {
               double* vp = v + (size_t)p * d;
@@ -242,10 +292,10 @@ __device__ void jacobi_sweeps(double* __restrict__ a, int lda, double* __restric
         }
         if (rlog && lane == 0) rlog[((size_t)sweep * (de - 1) + rnd) * npairs + grp] = make_double2(cs, sn);
       }
-      __syncthreads();
+      block_sync<LOCAL>();
     }
     const int any = *flag;
-    __syncthreads();
+    block_sync<LOCAL>();
     if (!any) break;
   }
   if (threadIdx.x == 0) *sweeps_done = sweep;
@@ -253,7 +303,7 @@ __device__ void jacobi_sweeps(double* __restrict__ a, int lda, double* __restric
 
 // V = the product of the logged rotations of `sweeps` sweeps, applied to the
 // identity in the order they were taken (column c at v + c * ldv)
-template <int G>
+template <int G, int RPL>
 __device__ void replay_rotations(double* __restrict__ v, int ldv, const double2* __restrict__ rlog, int d, int de,
                                  int sweeps) {
   const int npairs = de / 2;
@@ -263,29 +313,43 @@ __device__ void replay_rotations(double* __restrict__ v, int ldv, const double2*
     const int col = e / d, row = e - col * d;
     v[(size_t)col * ldv + row] = (row == col) ? 1.0 : 0.0;
   }
-  __syncthreads();
+  block_sync<true>();
+  // the log entry of the next round is loaded one round ahead
+  const size_t nrounds = (size_t)sweeps * (de - 1);
+  double2 nxt = make_double2(1.0, 0.0);
+  if (grp < npairs && nrounds > 0) nxt = rlog[grp];
   for (int sw = 0; sw < sweeps; ++sw)
     for (int rnd = 0; rnd < de - 1; ++rnd) {
       if (grp < npairs) {
-        const double2 r = rlog[((size_t)sw * (de - 1) + rnd) * npairs + grp];
+        const double2 r = nxt;
+        const size_t idx = (size_t)sw * (de - 1) + rnd + 1;
+        if (idx < nrounds) nxt = rlog[idx * npairs + grp];
         int p, q;
         round_pair(de, rnd, grp, p, q);
-        if (p > q) {
-          const int tmp = p;
-          p = q;
-          q = tmp;
-        }
         if (q < d && r.y != 0.0) {
           double* vp = v + (size_t)p * ldv;
           double* vq = v + (size_t)q * ldv;
-          for (int i = lane; i < d; i += G) {
-            const double vu = vp[i], vw = vq[i];
-            vp[i] = r.x * vu - r.y * vw;
-            vq[i] = r.y * vu + r.x * vw;
+          constexpr int CH = RPL < 8 ? RPL : 8;
+          for (int k0 = 0; k0 < RPL; k0 += CH) {
+            double u[CH], w[CH];
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+              const int i = lane + (k0 + k) * G;
+              u[k] = i < d ? vp[i] : 0.0;
+              w[k] = i < d ? vq[i] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+              const int i = lane + (k0 + k) * G;
+              if (i < d) {
+                vp[i] = r.x * u[k] - r.y * w[k];
+                vq[i] = r.y * u[k] + r.x * w[k];
+              }
+            }
           }
         }
       }
-      __syncthreads();
+      block_sync<true>();
     }
 }
 
@@ -294,7 +358,8 @@ constexpr int kPolarMaxDLds = 128;   // A (d x (d+1) float64) in LDS up to this 
 
 // One work-group.  a: out M V column-major (a[col * d + row]), then U; v: out
 // V column-major; r: out R = U V^T (row-major float64); sweeps: out int
-// (Jacobi sweeps run; max_sweeps + 1 when not converged).
+// (Jacobi sweeps run; max_sweeps + 1 when not converged); v_out: optional
+// row-major copy of V.
 // LDSA: the Jacobi sweeps run on a copy of M in LDS (d <= 128) and log their
 // rotations in rlog; V is then rebuilt in LDS from the log.  Otherwise they
 // run on a and v in global memory.  Threads exchange data through global
@@ -303,7 +368,7 @@ template <bool LDSA>
 __global__ __launch_bounds__(kPolarThreads) void k_polar(const double* __restrict__ m, int d, int max_sweeps,
                                                          double* __restrict__ a, double* __restrict__ v,
                                                          double2* __restrict__ rlog, double* __restrict__ r,
-                                                         int* __restrict__ sweeps) {
+                                                         double* __restrict__ v_out, int* __restrict__ sweeps) {
   __shared__ int flag;
   __shared__ int sweeps_done;
   __shared__ int best_k;
@@ -323,19 +388,19 @@ __global__ __launch_bounds__(kPolarThreads) void k_polar(const double* __restric
   const int de = d + (d & 1);
   const int npairs = de / 2;
   // lanes per pair: a power of two in [1, 64] with npairs * G <= 1024
+  // lanes per pair: the largest power of two <= 64 with npairs * G <= 1024
+  // (a round's latency falls with more lanes per pair)
   int g = 64;
-  while (g > 1 && npairs * g > kPolarThreads) g >>= 1;
+  while (g > 8 && npairs * g > kPolarThreads) g >>= 1;
   double* vv = LDSA ? nullptr : v;
   double2* lg = LDSA ? rlog : nullptr;
-  switch (g) {
-    case 64: jacobi_sweeps<64>(aw, ld, vv, lg, d, de, max_sweeps, &flag, &sweeps_done); break;
-    case 32: jacobi_sweeps<32>(aw, ld, vv, lg, d, de, max_sweeps, &flag, &sweeps_done); break;
-    case 16: jacobi_sweeps<16>(aw, ld, vv, lg, d, de, max_sweeps, &flag, &sweeps_done); break;
-    case 8: jacobi_sweeps<8>(aw, ld, vv, lg, d, de, max_sweeps, &flag, &sweeps_done); break;
-    case 4: jacobi_sweeps<4>(aw, ld, vv, lg, d, de, max_sweeps, &flag, &sweeps_done); break;
-    case 2: jacobi_sweeps<2>(aw, ld, vv, lg, d, de, max_sweeps, &flag, &sweeps_done); break;
-    default: jacobi_sweeps<1>(aw, ld, vv, lg, d, de, max_sweeps, &flag, &sweeps_done); break;
-  }
+  // G = 64, 32, 16, 8 for d <= 32, 64, 128, 256: RPL * G >= d rows per column
+  // rows per lane RPL * G >= d: d <= 32, 64, 128, 256 -> G = 64, 32, 16, 8
+  // (LDSA: d <= 128)
+  if (g == 64) jacobi_sweeps<64, 1, LDSA>(aw, ld, vv, lg, d, de, max_sweeps, &flag, &sweeps_done);
+  else if (g == 32) jacobi_sweeps<32, 2, LDSA>(aw, ld, vv, lg, d, de, max_sweeps, &flag, &sweeps_done);
+  else if (LDSA || g == 16) jacobi_sweeps<16, 8, LDSA>(aw, ld, vv, lg, d, de, max_sweeps, &flag, &sweeps_done);
+  else jacobi_sweeps<8, 32, LDSA>(aw, ld, vv, lg, d, de, max_sweeps, &flag, &sweeps_done);
   if (LDSA) {
     __syncthreads();
     for (int e = threadIdx.x; e < dd; e += blockDim.x) {
@@ -345,13 +410,9 @@ __global__ __launch_bounds__(kPolarThreads) void k_polar(const double* __restric
     __syncthreads();
     const int nsw = sweeps_done;
     switch (g) {
-      case 64: replay_rotations<64>(lds_mat, ld, rlog, d, de, nsw); break;
-      case 32: replay_rotations<32>(lds_mat, ld, rlog, d, de, nsw); break;
-      case 16: replay_rotations<16>(lds_mat, ld, rlog, d, de, nsw); break;
-      case 8: replay_rotations<8>(lds_mat, ld, rlog, d, de, nsw); break;
-      case 4: replay_rotations<4>(lds_mat, ld, rlog, d, de, nsw); break;
-      case 2: replay_rotations<2>(lds_mat, ld, rlog, d, de, nsw); break;
-      default: replay_rotations<1>(lds_mat, ld, rlog, d, de, nsw); break;
+      case 64: replay_rotations<64, 1>(lds_mat, ld, rlog, d, de, nsw); break;
+      case 32: replay_rotations<32, 2>(lds_mat, ld, rlog, d, de, nsw); break;
+      default: replay_rotations<16, 8>(lds_mat, ld, rlog, d, de, nsw); break;
     }
     for (int e = threadIdx.x; e < dd; e += blockDim.x) {
       const int col = e / d, row = e - col * d;
@@ -444,6 +505,7 @@ __global__ __launch_bounds__(kPolarThreads) void k_polar(const double* __restric
     double s = 0.0;
     for (int c = 0; c < d; ++c) s += a[(size_t)c * d + t] * v[(size_t)c * d + j];
     r[e] = s;
+    if (v_out) v_out[e] = v[(size_t)j * d + t];   // V[t][j]
   }
   if (threadIdx.x == 0) *sweeps = sweeps_done < max_sweeps ? sweeps_done : max_sweeps + 1;
 }
@@ -492,18 +554,62 @@ size_t polar_log_bytes(int d, int max_sweeps) {
   return (size_t)max_sweeps * (de - 1) * (de / 2) * sizeof(double2);
 }
 
-int launch_polar(const double* m, int d, int max_sweeps, double* a, double* v, void* rlog, double* r, int* sweeps,
-                 hipStream_t s) {
-  if (d < 1 || d > kPolarMaxD) return fail(MIPQ_EUNSUPPORTED, "the rotation fit supports 1 <= d <= %d", kPolarMaxD);
-  ProfScope ps(MIPQ_K_POLAR, s);
-  if (d <= kPolarMaxDLds) {
-    if (!rlog) return fail(MIPQ_EINVAL, "rotation log missing");
-    const size_t shm = (size_t)d * (d + 1) * sizeof(double);
-    k_polar<true><<<1, kPolarThreads, shm, s>>>(m, d, max_sweeps, a, v, static_cast<double2*>(rlog), r, sweeps);
-  } else {
-    k_polar<false><<<1, kPolarThreads, 0, s>>>(m, d, max_sweeps, a, v, nullptr, r, sweeps);
+// c = op(a) op(b) for d x d row-major float64 matrices (op: optional
+// transpose), one thread per output, k ascending; j is the fastest index so
+// that b's rows (or a^T's) are read coalesced.
+__global__ void k_gemm64(const double* __restrict__ a, const double* __restrict__ b, int d, int ta, int tb,
+                         double* __restrict__ c) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)d * d) return;
+  const int i = (int)(e / d), j = (int)(e - (int64_t)i * d);
+  double acc = 0.0;
+  for (int k = 0; k < d; ++k) {
+    const double av = ta ? a[(size_t)k * d + i] : a[(size_t)i * d + k];
+    const double bv = tb ? b[(size_t)j * d + k] : b[(size_t)k * d + j];
+    acc += av * bv;
   }
-  MIPQ_LAUNCHED("k_polar");
+  c[e] = acc;
+}
+
+int launch_gemm64(const double* a, const double* b, int d, bool ta, bool tb, double* c, hipStream_t s) {
+  const int64_t dd = (int64_t)d * d;
+  k_gemm64<<<(unsigned)((dd + 255) / 256), 256, 0, s>>>(a, b, d, ta ? 1 : 0, tb ? 1 : 0, c);
+  MIPQ_LAUNCHED("k_gemm64");
+  return MIPQ_OK;
+}
+
+// R for M: without v0, one polar launch.  With v0 (orthogonal, row-major):
+// the sweeps run on M0 = M V0 (written to m0), giving U and V_J with
+// R_J = U V_J^T; then R = R_J V0^T and V = V0 V_J (to v_out).
+int launch_polar(const double* m, int d, int max_sweeps, const double* v0, double* m0, double* a, double* v,
+                 double* rj, double* vj, void* rlog, double* r, double* v_out, int* sweeps, hipStream_t s) {
+  if (d < 1 || d > kPolarMaxD) return fail(MIPQ_EUNSUPPORTED, "the rotation fit supports 1 <= d <= %d", kPolarMaxD);
+  int rc;
+  const double* mm = m;
+  double* r_out = r;
+  double* vj_out = v_out;
+  if (v0) {
+    if ((rc = launch_gemm64(m, v0, d, false, false, m0, s))) return rc;
+    mm = m0;
+    r_out = rj;
+    vj_out = vj;
+  }
+  {
+    ProfScope ps(MIPQ_K_POLAR, s);
+    if (d <= kPolarMaxDLds) {
+      if (!rlog) return fail(MIPQ_EINVAL, "rotation log missing");
+      const size_t shm = (size_t)d * (d + 1) * sizeof(double);
+      k_polar<true><<<1, kPolarThreads, shm, s>>>(mm, d, max_sweeps, a, v, static_cast<double2*>(rlog), r_out,
+                                                  vj_out, sweeps);
+    } else {
+      k_polar<false><<<1, kPolarThreads, 0, s>>>(mm, d, max_sweeps, a, v, nullptr, r_out, vj_out, sweeps);
+    }
+    MIPQ_LAUNCHED("k_polar");
+  }
+  if (v0) {
+    if ((rc = launch_gemm64(rj, v0, d, false, true, r, s))) return rc;
+    if (v_out && (rc = launch_gemm64(v0, vj, d, false, false, v_out, s))) return rc;
+  }
   return MIPQ_OK;
 }
 

@@ -54,8 +54,17 @@ def test_procrustes_matches_oracle(n, d):
     np.testing.assert_allclose(r, rr, atol=1e-9)
     assert 0 < int(sw.item()) <= 64
     # results repeat bit for bit
-    r2, m2, _ = mipq.procrustes(_t(x), _t(yh))
+    r2, m2, _, v = mipq.procrustes(_t(x), _t(yh), return_v=True)
     assert np.array_equal(r2.cpu().numpy(), r) and np.array_equal(m2.cpu().numpy(), m)
+    # V is orthogonal and R = U V^T with U = M V S^-1 (full-rank M)
+    vv = v.cpu().numpy()
+    np.testing.assert_allclose(vv.T @ vv, np.eye(d), atol=1e-12)
+    # a warm start (V of this M, or any orthogonal matrix) gives the same R
+    r3, _, sw3 = mipq.procrustes(_t(x), _t(yh), v_init=v)
+    np.testing.assert_allclose(r3.cpu().numpy(), rr, atol=1e-9)
+    assert int(sw3.item()) <= 2 < int(sw.item()) or d <= 2
+    r4, _, _ = mipq.procrustes(_t(x), _t(yh), v_init=_t(_orthogonal(d + 7, d)))
+    np.testing.assert_allclose(r4.cpu().numpy(), rr, atol=1e-9)
 
 
 def test_procrustes_recovers_a_known_rotation():
