@@ -452,11 +452,25 @@ def bench_ivf(args) -> dict:
                            "finalize", "pack_bf16"])
     mipq.adc_search(q, idx, w.nprobe, w.topk)
     torch.cuda.synchronize()
-    ka = kernel_totals(L, ["adc"])
+    ka = kernel_totals(L, ["adc", "adc_scan"])
     L.mipq_profile_enable(0)
     flops = 2.0 * n * d * w.kc
     avg = ca[1] / max(ca[0], 1)
     achieved = flops / (avg * 1e-3) / 1e12
+    # candidates scanned: the probed lists of every query, ranked on the CPU in
+    # float64 (differs from the GPU's exact-rule probes only at near-ties)
+    cc64 = idx["coarse"].cpu().numpy().astype(np.float64)
+    sizes = np.diff(idx["offsets"].cpu().numpy())
+    cand = 0
+    for q0 in range(0, nq, 2000):
+        qq = w.queries[q0:q0 + 2000].astype(np.float64)
+        dq = (qq * qq).sum(1)[:, None] - 2.0 * qq @ cc64.T + (cc64 * cc64).sum(1)[None, :]
+        pr = np.argpartition(dq, w.nprobe - 1, axis=1)[:, :w.nprobe]
+        cand += int(sizes[pr].sum())
+    scan_bytes = cand * (w.m + 4)
+    ns, ts = ka["adc_scan"]
+    scan_ms = ts / max(ns, 1)
+    scan_gbs = scan_bytes / (scan_ms * 1e-3) / 1e9
 
     base, parity = None, None
     if not args.no_cpu_baseline:
@@ -492,10 +506,16 @@ def bench_ivf(args) -> dict:
         "build_ms": build_ms,
         "build_vectors_per_s": n / (build_ms * 1e-3),
         "oracle_parity": parity,
-        "roofline": {"bound": "mfma", "kernel": "k_coarse_assign_mfma", "achieved": achieved, "peak": 2500.0,
-                     "unit": "TFLOP/s", "frac": achieved / 2500.0, "traffic": None,
-                     "alg_flops_per_launch": flops, "avg_launch_ms": avg, "launches": ca[0],
-                     "note": "coarse assignment of all 10M rows against Kc=4096 (2*N*D*Kc flops per launch)"},
+        "roofline": {"bound": "hbm", "kernel": "k_adc_scan", "achieved": scan_gbs, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": scan_gbs / PEAK_HBM_GBS, "traffic": None,
+                     "alg_bytes_per_launch": scan_bytes, "avg_launch_ms": scan_ms, "launches": ns,
+                     "candidates_per_launch": cand,
+                     "note": "each (query, probed list) block reads the list's codes and ids: M + 4 bytes per "
+                             "candidate"},
+        "build_roofline": {"bound": "mfma", "kernel": "k_coarse_assign_mfma", "achieved": achieved, "peak": 2500.0,
+                           "unit": "TFLOP/s", "frac": achieved / 2500.0, "traffic": None,
+                           "alg_flops_per_launch": flops, "avg_launch_ms": avg, "launches": ca[0],
+                           "note": "coarse assignment of all 10M rows against Kc=4096 (2*N*D*Kc flops per launch)"},
         "coarse_rows_rescored": int(ca_resc.item()),
         "build_kernels_ms": {k2: v[1] for k2, v in kb.items() if v[0]},
         "search_kernels_ms": {k2: v[1] for k2, v in ka.items()},

@@ -94,8 +94,8 @@ const char* mipq_last_error(void);
  *   objective    OUT optional float64 [iters]: objective[t] = sum over rows,
  *                subspaces and dimensions of (x - c)^2 in float64, c the
  *                float32 centroid chosen in round t
- * Requirements: d % m == 0, d/m <= 16 (BF16) or <= 32 (FP32), 1 <= ks <= 256,
- * n_train >= 1, iters >= 0, init rows in range.
+ * Requirements: d % m == 0, d/m <= 16 (BF16, FP8) or <= 48 (FP32),
+ * 1 <= ks <= 256, n_train >= 1, iters >= 0, init rows in range.
  * ------------------------------------------------------------------------- */
 size_t mipq_pq_fit_workspace_size(int64_t n_train, int d, int m, int ks, int iters, int precision);
 int mipq_pq_fit(const float* x, int64_t n, const int64_t* train_rows, int64_t n_train,
@@ -395,7 +395,8 @@ enum mipq_kernel {
   MIPQ_K_ROTATE = 15,       /* optimized PQ: rotation y = x R */
   MIPQ_K_CROSS = 16,        /* optimized PQ: cross matrix X^T Y_hat */
   MIPQ_K_POLAR = 17,        /* optimized PQ: orthogonal factor by Jacobi */
-  MIPQ_KERNEL_COUNT = 18
+  MIPQ_K_ADC_SCAN = 18,     /* ADC search: the list scans alone (also inside MIPQ_K_ADC) */
+  MIPQ_KERNEL_COUNT = 19
 };
 int mipq_profile_enable(int on);
 int mipq_profile_collect(int kernel, int64_t* launches, double* total_ms);

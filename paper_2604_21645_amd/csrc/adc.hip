@@ -260,7 +260,9 @@ __global__ __launch_bounds__(kT) void k_adc_probe(const float* __restrict__ q, i
   for (int i = threadIdx.x; i < nprobe; i += blockDim.x) probes[(int64_t)qi * nprobe + i] = i < nb ? band[i].l : -1;
 }
 
-constexpr int kBatch = kT;   // keys inserted per block step (one per thread)
+constexpr int kBatch = kT;   // keys inserted per merge step (one per thread)
+constexpr int kScanRows = 4;  // rows per thread per scan step
+constexpr int kScanBatch = kScanRows * kT;
 
 __device__ void sort_keys(uint64_t* buf, int n2) {
   for (int kk = 2; kk <= n2; kk <<= 1)
@@ -286,12 +288,12 @@ __device__ __forceinline__ uint64_t load_relaxed(const unsigned long long* p) {
 
 // Block-wide top-k collection of unique uint64 keys: a key is kept while it is
 // <= *thr; once the LDS buffer (cap, a power of two) could not take another
-// batch, it is sorted, cut to the best topk and *thr lowered to the topk-th
-// key (and to *ext, a bound shared with other blocks, when given).  Call
-// after a barrier that follows the batch's insertions.
+// batch of `batch` keys, it is sorted, cut to the best topk and *thr lowered
+// to the topk-th key (and to *ext, a bound shared with other blocks, when
+// given).  Call after a barrier that follows the batch's insertions.
 __device__ __forceinline__ void topk_compact(uint64_t* buf, int cap, int topk, int* cnt, uint64_t* thr,
-                                             const unsigned long long* ext) {
-  if (*cnt <= cap - kBatch) return;   // block-uniform
+                                             const unsigned long long* ext, int batch) {
+  if (*cnt <= cap - batch) return;   // block-uniform
   const int c = *cnt < cap ? *cnt : cap;
   for (int i = c + threadIdx.x; i < cap; i += blockDim.x) buf[i] = ~0ull;
   __syncthreads();
@@ -366,37 +368,71 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
   }
   __syncthreads();
   const int64_t a = offsets[l], b = offsets[l + 1];
-  for (int64_t p0 = a; p0 < b; p0 += kBatch) {
-    const int64_t p = p0 + threadIdx.x;
+  // each step takes kScanRows rows per thread (rows p0 + r * kT + thread), so
+  // that their loads are in flight together; room for a whole step of keys is
+  // kept free in the buffer
+  auto insert = [&](float s, int32_t id, uint64_t tl) {
+    const uint64_t key = ((uint64_t)__float_as_uint(s) << 32) | (uint32_t)id;
+    if (key <= tl) {
+      const int slot = atomicAdd(&cnt, 1);
+      buf[slot] = key;
+    }
+  };
+  for (int64_t p0 = a; p0 < b; p0 += kScanBatch) {
     const uint64_t tl = thr;
-    if (p < b) {
-      float s;
-      if (V16) {   // m % 16 == 0 and aligned rows: 16 codes per load
-        const uint4* cr = reinterpret_cast<const uint4*>(codes + p * m);
-        s = 0.0f;
-        for (int j0 = 0; j0 < m; j0 += 16) {
-          const uint4 v = cr[j0 >> 4];
-          const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+    if (V16 && m == 16) {   // one 16-byte code row per row
+      uint4 cv[kScanRows];
+      int32_t iv[kScanRows];
+#pragma unroll
+      for (int r = 0; r < kScanRows; ++r) {
+        const int64_t p = p0 + r * kT + threadIdx.x;
+        if (p < b) {
+          cv[r] = reinterpret_cast<const uint4*>(codes)[p];
+          iv[r] = ids[p];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kScanRows; ++r) {
+        const int64_t p = p0 + r * kT + threadIdx.x;
+        if (p < b) {
+          const uint32_t w4[4] = {cv[r].x, cv[r].y, cv[r].z, cv[r].w};
+          float s = 0.0f;
 #pragma unroll
           for (int u = 0; u < 16; ++u) {
-            const int j = j0 + u;
-            const float e = lut[j * ks + ((w4[u >> 2] >> (8 * (u & 3))) & 0xFFu)];
-            s = (j == 0) ? e : s + e;
+            const float e = lut[u * ks + ((w4[u >> 2] >> (8 * (u & 3))) & 0xFFu)];
+            s = (u == 0) ? e : s + e;
           }
+          insert(s, iv[r], tl);
         }
-      } else {
-        const uint8_t* cr = codes + p * m;
-        s = lut[cr[0]];
-        for (int j = 1; j < m; ++j) s = s + lut[j * ks + cr[j]];
       }
-      const uint64_t key = ((uint64_t)__float_as_uint(s) << 32) | (uint32_t)ids[p];
-      if (key <= tl) {
-        const int slot = atomicAdd(&cnt, 1);
-        buf[slot] = key;   // slot < cap: room for a whole batch is kept free
+    } else {
+      for (int r = 0; r < kScanRows; ++r) {
+        const int64_t p = p0 + r * kT + threadIdx.x;
+        if (p >= b) break;
+        float s;
+        if (V16) {   // m % 16 == 0 and aligned rows: 16 codes per load
+          const uint4* cr = reinterpret_cast<const uint4*>(codes + p * m);
+          s = 0.0f;
+          for (int j0 = 0; j0 < m; j0 += 16) {
+            const uint4 v = cr[j0 >> 4];
+            const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+              const int j = j0 + u;
+              const float e = lut[j * ks + ((w4[u >> 2] >> (8 * (u & 3))) & 0xFFu)];
+              s = (j == 0) ? e : s + e;
+            }
+          }
+        } else {
+          const uint8_t* cr = codes + p * m;
+          s = lut[cr[0]];
+          for (int j = 1; j < m; ++j) s = s + lut[j * ks + cr[j]];
+        }
+        insert(s, ids[p], tl);
       }
     }
     __syncthreads();
-    topk_compact(buf, cap, topk, &cnt, &thr, qthr + qi);
+    topk_compact(buf, cap, topk, &cnt, &thr, qthr + qi, kScanBatch);
   }
   const int c = cnt;
   topk_finish(buf, c);
@@ -430,7 +466,7 @@ __global__ __launch_bounds__(kT) void k_adc_merge(const uint64_t* __restrict__ p
       mbuf[slot] = key;
     }
     __syncthreads();
-    topk_compact(mbuf, cap, topk, &cnt, &thr, nullptr);
+    topk_compact(mbuf, cap, topk, &cnt, &thr, nullptr, kBatch);
   }
   const int c = cnt;
   topk_finish(mbuf, c);
@@ -445,15 +481,15 @@ __global__ __launch_bounds__(kT) void k_adc_merge(const uint64_t* __restrict__ p
 
 // key buffer of a scan block / the merge block: a power of two with room for
 // topk kept keys plus one full batch
-int adc_key_cap(int topk) {
+int adc_key_cap(int topk, int batch) {
   int c = 512;
-  while (c < topk + kBatch) c <<= 1;
+  while (c < topk + batch) c <<= 1;
   return c;
 }
 
 int adc_scan_smem(int d, int m, int ks, int topk) {
   return (int)((size_t)m * ks * sizeof(float) + (size_t)((d + 1) & ~1) * sizeof(float) +
-               (size_t)adc_key_cap(topk) * sizeof(uint64_t));
+               (size_t)adc_key_cap(topk, kScanBatch) * sizeof(uint64_t));
 }
 
 int launch_adc(const float* q, int nq, int d, const float* cc, int kc, const void* aop, const float* mu,
@@ -490,7 +526,8 @@ int launch_adc(const float* q, int nq, int d, const float* cc, int kc, const voi
   k_fill_u64<<<ceil_div(nq, kT), kT, 0, s>>>(qthr, nq, ~0ull);
   MIPQ_LAUNCHED("k_fill_u64");
   const int ds = d / m;
-  const int cap = adc_key_cap(topk);
+  const int cap = adc_key_cap(topk, kScanBatch);
+  const int mcap = adc_key_cap(topk, kBatch);
   const size_t shm = adc_scan_smem(d, m, ks, topk);
   const bool v16 = (m % 16 == 0) && ((reinterpret_cast<uintptr_t>(codes) & 15) == 0);
   const unsigned sblocks = (unsigned)((int64_t)nq * nprobe);
@@ -503,17 +540,21 @@ int launch_adc(const float* q, int nq, int d, const float* cc, int kc, const voi
       k_adc_scan<DSV, false><<<sblocks, kT, shm, s>>>(q, d, cc, pq, m, ks, offsets, ids, codes, probes, nq,  \
                                                       nprobe, topk, cap, qthr, pair_out);                    \
   } while (0)
-  switch (ds) {
-    case 1: SC(1); break;
-    case 2: SC(2); break;
-    case 4: SC(4); break;
-    case 8: SC(8); break;
-    case 16: SC(16); break;
-    default: return fail(MIPQ_EUNSUPPORTED, "ADC supports d/m in {1, 2, 4, 8, 16} (got %d)", ds);
+  {
+    ProfScope pscan(MIPQ_K_ADC_SCAN, s);
+    switch (ds) {
+      case 1: SC(1); break;
+      case 2: SC(2); break;
+      case 4: SC(4); break;
+      case 8: SC(8); break;
+      case 16: SC(16); break;
+      default: return fail(MIPQ_EUNSUPPORTED, "ADC supports d/m in {1, 2, 4, 8, 16} (got %d)", ds);
+    }
   }
 #undef SC
   MIPQ_LAUNCHED("k_adc_scan");
-  k_adc_merge<<<nq, kT, (size_t)cap * sizeof(uint64_t), s>>>(pair_out, nprobe, topk, cap, qthr, out_ids, out_dist);
+  k_adc_merge<<<nq, kT, (size_t)mcap * sizeof(uint64_t), s>>>(pair_out, nprobe, topk, mcap, qthr, out_ids,
+                                                               out_dist);
   MIPQ_LAUNCHED("k_adc_merge");
   return MIPQ_OK;
 }
