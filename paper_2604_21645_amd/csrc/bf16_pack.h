@@ -45,6 +45,53 @@ __device__ __forceinline__ void store_pack(uint4* dst, const Pack8& p) {
   *dst = q;
 }
 
+// Operand slot f of lane half `half` for centroid ck (its ds float32 values;
+// nullptr for a padded centroid) centred by mu; cn: its float64 centred norm.
+template <int NB>
+__device__ __forceinline__ Pack8 slot_value(const float* ck, const float* mu, int ds, int f, int half, double& cn) {
+  constexpr int NMF = bf16_nmfma(NB);
+  constexpr int DW = NB * 8;
+  const bool real = ck != nullptr;
+  float hv[DW], lv[DW];
+  cn = 0.0;
+#pragma unroll
+  for (int e = 0; e < DW; ++e) {
+    const float c = (real && e < ds) ? ck[e] - mu[e] : 0.0f;
+    cn += (double)c * (double)c;
+    const float v = -2.0f * c;
+    hv[e] = bf16_bits_to_f32(bf16_bits_rne(v));
+    lv[e] = bf16_bits_to_f32(bf16_bits_rne(v - hv[e]));
+  }
+  Pack8 norm = {};
+  if (real) {
+    const uint16_t h = bf16_bits_rne((float)cn);
+    const double r1 = cn - (double)bf16_bits_to_f32(h);
+    const uint16_t md = bf16_bits_rne((float)r1);
+    const double r2 = r1 - (double)bf16_bits_to_f32(md);
+    norm.v[0] = h;
+    norm.v[1] = md;
+    norm.v[2] = bf16_bits_rne((float)r2);
+  } else {
+    norm.v[0] = 0x7F80u;   // +inf: padded centroids never win
+  }
+  norm.v[3] = norm.v[4] = norm.v[5] = kBf16One;
+  Pack8 out = {};
+  auto block_of = [&](const float* src, int b) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out.v[e] = bf16_bits_rne(src[b * 8 + e]);
+  };
+  if (f < NB) {
+    block_of(half ? lv : hv, f);
+  } else if (f < NB + (NB + 1) / 2) {
+    const int b = 2 * (f - NB) + half;
+    if (b < NB) block_of(hv, b);
+    else out = norm;
+  } else {
+    if (!half) out = norm;
+  }
+  return out;
+}
+
 // Block-wide packing of one subspace's tiles [t_begin, t_end).  cb points to
 // the subspace's float32 centroids ([ks][ds], global or LDS).  All threads of
 // the block must call it (it synchronises).  red must hold 2*16*16 + 16 + 16
@@ -128,46 +175,9 @@ __device__ void pack_subspace(const float* cb, int ks, int ds, int nt, int sub, 
     const int l = s & 63;
     const int f = (s >> 6) % NMF;
     const int t = t_begin + s / (NMF * 64);
-    const int i = l & 31, half = l >> 5;
-    const int k = t * 32 + i;
-    const bool real = k < ks;
-    float hv[DW], lv[DW];
-    double cn = 0.0;
-#pragma unroll
-    for (int e = 0; e < DW; ++e) {
-      const float c = (real && e < ds) ? cb[k * ds + e] - mu_s[e] : 0.0f;
-      cn += (double)c * (double)c;
-      const float v = -2.0f * c;
-      hv[e] = bf16_bits_to_f32(bf16_bits_rne(v));
-      lv[e] = bf16_bits_to_f32(bf16_bits_rne(v - hv[e]));
-    }
-    Pack8 norm = {};
-    if (real) {
-      const uint16_t h = bf16_bits_rne((float)cn);
-      const double r1 = cn - (double)bf16_bits_to_f32(h);
-      const uint16_t md = bf16_bits_rne((float)r1);
-      const double r2 = r1 - (double)bf16_bits_to_f32(md);
-      norm.v[0] = h;
-      norm.v[1] = md;
-      norm.v[2] = bf16_bits_rne((float)r2);
-    } else {
-      norm.v[0] = 0x7F80u;   // +inf: padded centroids never win
-    }
-    norm.v[3] = norm.v[4] = norm.v[5] = kBf16One;
-    Pack8 out = {};
-    auto block_of = [&](const float* src, int b) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) out.v[e] = bf16_bits_rne(src[b * 8 + e]);
-    };
-    if (f < NB) {
-      block_of(half ? lv : hv, f);
-    } else if (f < NB + (NB + 1) / 2) {
-      const int b = 2 * (f - NB) + half;
-      if (b < NB) block_of(hv, b);
-      else out = norm;
-    } else {
-      if (!half) out = norm;
-    }
+    const int k = t * 32 + (l & 31);
+    double cn;
+    const Pack8 out = slot_value<NB>(k < ks ? cb + k * ds : nullptr, mu_s, ds, f, l >> 5, cn);
     store_pack(aop + ((size_t)(sub * nt + t) * NMF + f) * 64 + l, out);
   }
 }

@@ -130,9 +130,13 @@ __global__ __launch_bounds__(kUpdThreads) void k_accumulate(
     const float* __restrict__ x, int64_t n, int d, int m, int ks, int ds,
     const uint8_t* __restrict__ codes, const float* __restrict__ c32, int64_t rpc, int nch,
     double* __restrict__ part_s, uint32_t* __restrict__ part_cnt, double* __restrict__ part_j,
-    const double* __restrict__ gscale, float* __restrict__ grad_x) {
+    const double* __restrict__ gscale, float* __restrict__ grad_x, float* __restrict__ cmax_zero) {
   extern __shared__ double smem[];
   __shared__ double redj[kUpdThreads / 64];
+  // the next finalize raises cmax[j] tile by tile from zero (the round's
+  // assignment, which read it, has finished)
+  if (cmax_zero && blockIdx.x == 0)
+    for (int j = threadIdx.x; j < m; j += blockDim.x) cmax_zero[j] = 0.0f;
   const ChunkMap cm = chunk_map(blockIdx.x, m);
   if (cm.chunk >= nch) return;   // padding of the grid (every chunk's partials are written)
   accumulate_chunk<GX, OBJ, CHECK>(x, n, d, m, ks, ds, codes, c32, rpc, (int)cm.chunk, cm.sub, part_s, part_cnt,
@@ -241,6 +245,93 @@ __global__ __launch_bounds__(kUpdThreads) void k_finalize(int m, int ks, int ds,
   __shared__ float packred[kPackRed];
   finalize_sub<NB, PACK>(blockIdx.x, m, ks, ds, nch, part_s, part_cnt, part_j, c32, c64, j_sub + blockIdx.x, aop,
                          cmax, mu, nt, newc, packred);
+}
+
+// One problem, block (tile t, subspace j): the means of the tile's 32
+// centroids (chunk partials summed in chunk order, float64; empty keeps its
+// value), then the tile's operand slots for the next round, centred by the
+// subspace centre mu fixed at the start of the fit, and the tile's largest
+// centred norm raised into cmax[j] (zeroed by the accumulation).  Block t = 0
+// also sums the round's objective.  All tiles of all subspaces run at once.
+constexpr int kFinTileThreads = 256;
+
+template <int NB>
+__global__ __launch_bounds__(kFinTileThreads) void k_finalize_tiles(int m, int ks, int ds, int nch,
+                                                                    const double* __restrict__ part_s,
+                                                                    const uint32_t* __restrict__ part_cnt,
+                                                                    const double* __restrict__ part_j,
+                                                                    float* __restrict__ c32, double* __restrict__ c64,
+                                                                    double* __restrict__ j_sub,
+                                                                    uint4* __restrict__ aop,
+                                                                    float* __restrict__ cmax,
+                                                                    const float* __restrict__ mu, int nt) {
+  constexpr int NMF = bf16_nmfma(NB);
+  __shared__ float newc[32 * NB * 8];
+  __shared__ float mus[NB * 8];
+  __shared__ float wmax[kFinTileThreads / 64];
+  const int t = blockIdx.x, sub = blockIdx.y;
+  const int per = ks * ds;
+  const int k0 = t * 32;
+  const int kn = min(32, ks - k0);
+  for (int le = threadIdx.x; le < kn * ds; le += blockDim.x) {
+    const int e = k0 * ds + le;
+    const int k = e / ds;
+    double sacc = 0.0;
+    uint64_t cacc = 0;
+    constexpr int V = 8;   // partials in flight, added in chunk order
+    for (int c0 = 0; c0 < nch; c0 += V) {
+      double sv[V];
+      uint32_t cv[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const int cc = c0 + v < nch ? c0 + v : nch - 1;
+        const size_t b2 = (size_t)cc * m + sub;
+        sv[v] = part_s[b2 * per + e];
+        cv[v] = part_cnt[b2 * ks + k];
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        if (c0 + v < nch) {
+          sacc += sv[v];
+          cacc += cv[v];
+        }
+    }
+    const size_t o = (size_t)sub * per + e;
+    const double v = cacc ? sacc / (double)cacc : c64[o];
+    c64[o] = v;
+    const float f = (float)v;
+    c32[o] = f;
+    newc[le] = f;
+  }
+  if (threadIdx.x < NB * 8) mus[threadIdx.x] = mu[sub * kMaxDsBf16 + threadIdx.x];
+  if (t == 0 && threadIdx.x < 64) {   // objective: lane-strided chunk sums, then a fixed xor tree
+    double js = 0.0;
+    for (int cc = threadIdx.x; cc < nch; cc += 64) js += part_j[(size_t)cc * m + sub];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) js += __shfl_xor(js, off, 64);
+    if (threadIdx.x == 0 && j_sub) j_sub[sub] = js;
+  }
+  __syncthreads();
+  float mx = 0.0f;
+  for (int s = threadIdx.x; s < NMF * 64; s += blockDim.x) {
+    const int l = s & 63;
+    const int f = s >> 6;
+    const int i = l & 31;
+    double cn;
+    const Pack8 out = slot_value<NB>(i < kn ? newc + i * ds : nullptr, mus, ds, f, l >> 5, cn);
+    store_pack(aop + ((size_t)(sub * nt + t) * NMF + f) * 64 + l, out);
+    if (i < kn) mx = fmaxf(mx, (float)(sqrt(cn) * (1.0 + 1e-6)));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float a = wmax[0];
+    for (int i = 1; i < kFinTileThreads / 64; ++i) a = fmaxf(a, wmax[i]);
+    // non-negative floats order as their bit patterns
+    atomicMax(reinterpret_cast<unsigned int*>(cmax + sub), __float_as_uint(a));
+  }
 }
 
 // Many problems: block b = (problem b / m, subspace b % m).  The round index
@@ -373,24 +464,30 @@ int launch_update(const float* x, int64_t n, int d, int m, int ks, const uint8_t
                        (size_t)ks * ds * sizeof(float);
     const unsigned grid = (unsigned)(((nch + 7) / 8) * 8 * m);
     ProfScope ps(MIPQ_K_UPDATE, s);
+    float* cz = aop ? cmax : nullptr;
     if (objective)
       k_accumulate<false, true, false><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, nch, part_s,
-                                                                      part_cnt, part_j, nullptr, nullptr);
+                                                                      part_cnt, part_j, nullptr, nullptr, cz);
     else
       k_accumulate<false, false, false><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, nch, part_s,
-                                                                       part_cnt, part_j, nullptr, nullptr);
+                                                                       part_cnt, part_j, nullptr, nullptr, cz);
     MIPQ_LAUNCHED("k_accumulate");
   }
   const int nt = tiles_for(ks);
-  const size_t shm = (size_t)ks * ds * sizeof(float);
   ProfScope ps(MIPQ_K_FINALIZE, s);
-#define FIN(NB, PK)                                                                                  \
-  k_finalize<NB, PK><<<m, kUpdThreads, shm, s>>>(m, ks, ds, nch, part_s, part_cnt, part_j, c32, c64, \
-                                                 j_sub, (uint4*)aop, cmax, mu, nt)
-  if (!aop) FIN(1, false);
-  else if (ds <= 8) FIN(1, true);
-  else FIN(2, true);
-#undef FIN
+  if (!aop) {
+    const size_t shm = (size_t)ks * ds * sizeof(float);
+    k_finalize<1, false><<<m, kUpdThreads, shm, s>>>(m, ks, ds, nch, part_s, part_cnt, part_j, c32, c64, j_sub,
+                                                     nullptr, cmax, mu, nt);
+  } else {   // matrix-core operands: every (tile, subspace) block at once
+    dim3 grid(nt, m);
+    if (ds <= 8)
+      k_finalize_tiles<1><<<grid, kFinTileThreads, 0, s>>>(m, ks, ds, nch, part_s, part_cnt, part_j, c32, c64, j_sub,
+                                                            (uint4*)aop, cmax, mu, nt);
+    else
+      k_finalize_tiles<2><<<grid, kFinTileThreads, 0, s>>>(m, ks, ds, nch, part_s, part_cnt, part_j, c32, c64, j_sub,
+                                                            (uint4*)aop, cmax, mu, nt);
+  }
   MIPQ_LAUNCHED("k_finalize");
   return MIPQ_OK;
 }
@@ -415,10 +512,10 @@ int launch_backward(const float* x, int64_t n, int d, int m, int ks, const uint8
     ProfScope ps(MIPQ_K_BACKWARD, s);
     if (grad_x)
       k_accumulate<true, true, true><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, nch, part_s,
-                                                                    part_cnt, part_j, gscale, grad_x);
+                                                                    part_cnt, part_j, gscale, grad_x, nullptr);
     else
       k_accumulate<false, true, true><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, nch, part_s,
-                                                                     part_cnt, part_j, nullptr, nullptr);
+                                                                     part_cnt, part_j, nullptr, nullptr, nullptr);
     MIPQ_LAUNCHED("k_accumulate");
   }
   k_grad_codebook<<<m, kUpdThreads, 0, s>>>(m, ks, ds, nch, part_s, part_cnt, part_j, c32, gscale, grad_c,
