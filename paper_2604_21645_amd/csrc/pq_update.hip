@@ -162,9 +162,13 @@ __global__ __launch_bounds__(kUpdThreads) void k_accumulate_batched(const BatchP
                                                                     int64_t items, int d, int m, int ks, int ds,
                                                                     double* __restrict__ part_s,
                                                                     uint32_t* __restrict__ part_cnt,
-                                                                    double* __restrict__ part_j) {
+                                                                    double* __restrict__ part_j,
+                                                                    float* __restrict__ cmax_zero, int nzero) {
   extern __shared__ double smem[];
   __shared__ double redj[kUpdThreads / 64];
+  // the next finalize raises every cmax from zero (see k_accumulate)
+  if (blockIdx.x == 0)
+    for (int j = threadIdx.x; j < nzero; j += blockDim.x) cmax_zero[j] = 0.0f;
   const ChunkMap cmap = chunk_map(blockIdx.x, m);
   const int64_t i = cmap.chunk * m + cmap.sub;   // item: chunks of all problems in order, then subspace
   if (i >= items) return;
@@ -178,18 +182,14 @@ __global__ __launch_bounds__(kUpdThreads) void k_accumulate_batched(const BatchP
                                        part_j + item0, nullptr, nullptr, smem, redj);
 }
 
-// Subspace sub: sums the chunk partials in chunk order, centroid = sum /
-// count (an empty centroid keeps its value), float32 copy by
-// round-to-nearest, the subspace objective (*j_out), and with PACK the next
-// round's operands.  newc: ks*ds floats of LDS.
-template <int NB, bool PACK>
+// Subspace sub (paths without matrix-core operands): sums the chunk partials
+// in chunk order, centroid = sum / count (an empty centroid keeps its value),
+// float32 copy by round-to-nearest, and the subspace objective (*j_out).
 __device__ __forceinline__ void finalize_sub(int sub, int m, int ks, int ds, int nch,
                                              const double* __restrict__ part_s,
                                              const uint32_t* __restrict__ part_cnt,
                                              const double* __restrict__ part_j, float* __restrict__ c32,
-                                             double* __restrict__ c64, double* __restrict__ j_out,
-                                             uint4* __restrict__ aop, float* __restrict__ cmax,
-                                             float* __restrict__ mu, int nt, float* newc, float* packred) {
+                                             double* __restrict__ c64, double* __restrict__ j_out) {
   const int per = ks * ds;
   for (int e = threadIdx.x; e < per; e += blockDim.x) {
     const int k = e / ds;
@@ -218,7 +218,6 @@ __device__ __forceinline__ void finalize_sub(int sub, int m, int ks, int ds, int
     c64[o] = v;
     const float f = (float)v;
     c32[o] = f;
-    newc[e] = f;
   }
   if (threadIdx.x < 64) {   // objective: lane-strided chunk sums, then a fixed xor tree
     double js = 0.0;
@@ -227,24 +226,16 @@ __device__ __forceinline__ void finalize_sub(int sub, int m, int ks, int ds, int
     for (int off = 32; off > 0; off >>= 1) js += __shfl_xor(js, off, 64);
     if (threadIdx.x == 0 && j_out) *j_out = js;
   }
-  __syncthreads();
-  if (PACK) pack_subspace<NB>(newc, ks, ds, nt, sub, 0, nt, aop, cmax + sub, mu + sub * kMaxDsBf16, true, packred);
 }
 
 // One block per subspace.
-template <int NB, bool PACK>
 __global__ __launch_bounds__(kUpdThreads) void k_finalize(int m, int ks, int ds, int nch,
                                                           const double* __restrict__ part_s,
                                                           const uint32_t* __restrict__ part_cnt,
                                                           const double* __restrict__ part_j,
                                                           float* __restrict__ c32, double* __restrict__ c64,
-                                                          double* __restrict__ j_sub, uint4* __restrict__ aop,
-                                                          float* __restrict__ cmax, float* __restrict__ mu,
-                                                          int nt) {
-  extern __shared__ float newc[];   // new float32 centroids of this subspace
-  __shared__ float packred[kPackRed];
-  finalize_sub<NB, PACK>(blockIdx.x, m, ks, ds, nch, part_s, part_cnt, part_j, c32, c64, j_sub + blockIdx.x, aop,
-                         cmax, mu, nt, newc, packred);
+                                                          double* __restrict__ j_sub) {
+  finalize_sub(blockIdx.x, m, ks, ds, nch, part_s, part_cnt, part_j, c32, c64, j_sub + blockIdx.x);
 }
 
 // One problem, block (tile t, subspace j): the means of the tile's 32
@@ -256,20 +247,15 @@ __global__ __launch_bounds__(kUpdThreads) void k_finalize(int m, int ks, int ds,
 constexpr int kFinTileThreads = 256;
 
 template <int NB>
-__global__ __launch_bounds__(kFinTileThreads) void k_finalize_tiles(int m, int ks, int ds, int nch,
-                                                                    const double* __restrict__ part_s,
-                                                                    const uint32_t* __restrict__ part_cnt,
-                                                                    const double* __restrict__ part_j,
-                                                                    float* __restrict__ c32, double* __restrict__ c64,
-                                                                    double* __restrict__ j_sub,
-                                                                    uint4* __restrict__ aop,
-                                                                    float* __restrict__ cmax,
-                                                                    const float* __restrict__ mu, int nt) {
+__device__ __forceinline__ void finalize_tile(int t, int sub, int m, int ks, int ds, int nch,
+                                              const double* __restrict__ part_s,
+                                              const uint32_t* __restrict__ part_cnt,
+                                              const double* __restrict__ part_j, float* __restrict__ c32,
+                                              double* __restrict__ c64, double* __restrict__ j_out,
+                                              uint4* __restrict__ aop, float* __restrict__ cmax,
+                                              const float* __restrict__ mu, int nt, float* newc, float* mus,
+                                              float* wmax) {
   constexpr int NMF = bf16_nmfma(NB);
-  __shared__ float newc[32 * NB * 8];
-  __shared__ float mus[NB * 8];
-  __shared__ float wmax[kFinTileThreads / 64];
-  const int t = blockIdx.x, sub = blockIdx.y;
   const int per = ks * ds;
   const int k0 = t * 32;
   const int kn = min(32, ks - k0);
@@ -304,12 +290,12 @@ __global__ __launch_bounds__(kFinTileThreads) void k_finalize_tiles(int m, int k
     newc[le] = f;
   }
   if (threadIdx.x < NB * 8) mus[threadIdx.x] = mu[sub * kMaxDsBf16 + threadIdx.x];
-  if (t == 0 && threadIdx.x < 64) {   // objective: lane-strided chunk sums, then a fixed xor tree
+  if (t == 0 && j_out && threadIdx.x < 64) {   // objective: lane-strided chunk sums, then a fixed xor tree
     double js = 0.0;
     for (int cc = threadIdx.x; cc < nch; cc += 64) js += part_j[(size_t)cc * m + sub];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) js += __shfl_xor(js, off, 64);
-    if (threadIdx.x == 0 && j_sub) j_sub[sub] = js;
+    if (threadIdx.x == 0) *j_out = js;
   }
   __syncthreads();
   float mx = 0.0f;
@@ -334,34 +320,43 @@ __global__ __launch_bounds__(kFinTileThreads) void k_finalize_tiles(int m, int k
   }
 }
 
-// Many problems: block b = (problem b / m, subspace b % m).  The round index
-// is read from *round (advanced by k_next_round at the end of each round), so
-// that one recorded sequence of launches serves every round: the objective of
-// round r goes to j_all[(r * nprob + p) * m + j].
 template <int NB>
-__global__ __launch_bounds__(kUpdThreads) void k_finalize_batched(const BatchProb* __restrict__ probs, int nprob,
-                                                                  int m, int ks, int ds,
-                                                                  const double* __restrict__ part_s,
-                                                                  const uint32_t* __restrict__ part_cnt,
-                                                                  const double* __restrict__ part_j,
-                                                                  double* __restrict__ c64_all,
-                                                                  double* __restrict__ j_all,
-                                                                  const uint32_t* __restrict__ round, int iters,
-                                                                  uint4* __restrict__ aop_all, size_t aop_stride,
-                                                                  float* __restrict__ cmax_all,
-                                                                  float* __restrict__ mu_all, int nt) {
-  extern __shared__ float newc[];
-  __shared__ float packred[kPackRed];
-  const int p = blockIdx.x / m;
-  const int sub = blockIdx.x - p * m;
+__global__ __launch_bounds__(kFinTileThreads) void k_finalize_tiles(int m, int ks, int ds, int nch,
+                                                                    const double* __restrict__ part_s,
+                                                                    const uint32_t* __restrict__ part_cnt,
+                                                                    const double* __restrict__ part_j,
+                                                                    float* __restrict__ c32, double* __restrict__ c64,
+                                                                    double* __restrict__ j_sub,
+                                                                    uint4* __restrict__ aop,
+                                                                    float* __restrict__ cmax,
+                                                                    const float* __restrict__ mu, int nt) {
+  __shared__ float newc[32 * NB * 8];
+  __shared__ float mus[NB * 8];
+  __shared__ float wmax[kFinTileThreads / 64];
+  finalize_tile<NB>(blockIdx.x, blockIdx.y, m, ks, ds, nch, part_s, part_cnt, part_j, c32, c64,
+                    j_sub ? j_sub + blockIdx.y : nullptr, aop, cmax, mu, nt, newc, mus, wmax);
+}
+
+// Many problems: block (tile t, subspace j, problem p), as k_finalize_tiles
+// on problem p's partials; the round index comes from *round (see
+// k_finalize_batched).
+template <int NB>
+__global__ __launch_bounds__(kFinTileThreads) void k_finalize_tiles_batched(
+    const BatchProb* __restrict__ probs, int nprob, int m, int ks, int ds, const double* __restrict__ part_s,
+    const uint32_t* __restrict__ part_cnt, const double* __restrict__ part_j, double* __restrict__ c64_all,
+    double* __restrict__ j_all, const uint32_t* __restrict__ round, int iters, uint4* __restrict__ aop_all,
+    size_t aop_stride, float* __restrict__ cmax_all, const float* __restrict__ mu_all, int nt) {
+  __shared__ float newc[32 * NB * 8];
+  __shared__ float mus[NB * 8];
+  __shared__ float wmax[kFinTileThreads / 64];
+  const int t = blockIdx.x, sub = blockIdx.y, p = blockIdx.z;
   const int64_t item0 = probs[p].item0;
   const size_t per = (size_t)ks * ds;
   const uint32_t r = *round;
   double* j_out = r < (uint32_t)iters ? j_all + ((size_t)r * nprob + p) * m + sub : nullptr;
-  finalize_sub<NB, true>(sub, m, ks, ds, probs[p].nch, part_s + item0 * per, part_cnt + item0 * ks,
-                         part_j + item0, probs[p].c32, c64_all + (size_t)p * m * per, j_out,
-                         aop_all + (size_t)p * aop_stride, cmax_all + (size_t)p * m,
-                         mu_all + (size_t)p * m * kMaxDsBf16, nt, newc, packred);
+  finalize_tile<NB>(t, sub, m, ks, ds, probs[p].nch, part_s + item0 * per, part_cnt + item0 * ks, part_j + item0,
+                    probs[p].c32, c64_all + (size_t)p * m * per, j_out, aop_all + (size_t)p * aop_stride,
+                    cmax_all + (size_t)p * m, mu_all + (size_t)p * m * kMaxDsBf16, nt, newc, mus, wmax);
 }
 
 __global__ void k_next_round(uint32_t* round) {
@@ -476,9 +471,7 @@ int launch_update(const float* x, int64_t n, int d, int m, int ks, const uint8_t
   const int nt = tiles_for(ks);
   ProfScope ps(MIPQ_K_FINALIZE, s);
   if (!aop) {
-    const size_t shm = (size_t)ks * ds * sizeof(float);
-    k_finalize<1, false><<<m, kUpdThreads, shm, s>>>(m, ks, ds, nch, part_s, part_cnt, part_j, c32, c64, j_sub,
-                                                     nullptr, cmax, mu, nt);
+    k_finalize<<<m, kUpdThreads, 0, s>>>(m, ks, ds, nch, part_s, part_cnt, part_j, c32, c64, j_sub);
   } else {   // matrix-core operands: every (tile, subspace) block at once
     dim3 grid(nt, m);
     if (ds <= 8)
@@ -561,21 +554,22 @@ int launch_update_batched(const BatchProb* probs, int nprob, int64_t items, int 
     ProfScope ps(MIPQ_K_UPDATE, s);
     const int64_t chunks = items / m;
     const unsigned grid = (unsigned)(((chunks + 7) / 8) * 8 * m);
-    k_accumulate_batched<<<grid, kUpdThreads, shm, s>>>(probs, nprob, items, d, m, ks, ds, part_s, part_cnt, part_j);
+    k_accumulate_batched<<<grid, kUpdThreads, shm, s>>>(probs, nprob, items, d, m, ks, ds, part_s, part_cnt, part_j,
+                                                        cmax, nprob * m);
     MIPQ_LAUNCHED("k_accumulate_batched");
   }
   const int nt = tiles_for(ks);
-  const size_t shm = (size_t)ks * ds * sizeof(float);
   ProfScope ps(MIPQ_K_FINALIZE, s);
+  dim3 grid(nt, m, nprob);
   if (ds <= 8)
-    k_finalize_batched<1><<<nprob * m, kUpdThreads, shm, s>>>(probs, nprob, m, ks, ds, part_s, part_cnt, part_j, c64,
-                                                              j_all, round, iters, (uint4*)aop, aop_stride, cmax,
-                                                              mu, nt);
+    k_finalize_tiles_batched<1><<<grid, kFinTileThreads, 0, s>>>(probs, nprob, m, ks, ds, part_s, part_cnt, part_j,
+                                                                 c64, j_all, round, iters, (uint4*)aop, aop_stride,
+                                                                 cmax, mu, nt);
   else
-    k_finalize_batched<2><<<nprob * m, kUpdThreads, shm, s>>>(probs, nprob, m, ks, ds, part_s, part_cnt, part_j, c64,
-                                                              j_all, round, iters, (uint4*)aop, aop_stride, cmax,
-                                                              mu, nt);
-  MIPQ_LAUNCHED("k_finalize_batched");
+    k_finalize_tiles_batched<2><<<grid, kFinTileThreads, 0, s>>>(probs, nprob, m, ks, ds, part_s, part_cnt, part_j,
+                                                                 c64, j_all, round, iters, (uint4*)aop, aop_stride,
+                                                                 cmax, mu, nt);
+  MIPQ_LAUNCHED("k_finalize_tiles_batched");
   k_next_round<<<1, 64, 0, s>>>(const_cast<uint32_t*>(round));
   MIPQ_LAUNCHED("k_next_round");
   return MIPQ_OK;
