@@ -12,7 +12,7 @@ namespace mipq {
 
 namespace {
 
-constexpr int kUpdThreads = 1024;
+constexpr int kUpdThreads = 512;   // accumulation blocks: several per CU overlap their set-up and stores
 constexpr int kPackThreads = 256;
 constexpr int kPackRed = 544;   // floats of LDS scratch for pack_subspace
 
@@ -124,15 +124,19 @@ __device__ __forceinline__ ChunkMap chunk_map(int64_t b, int m) {
   return r;
 }
 
-// One problem: chunk c, subspace j (see chunk_map).
-template <bool GX, bool OBJ, bool CHECK>
-__global__ __launch_bounds__(kUpdThreads) void k_accumulate(
+// One problem: chunk c, subspace j (see chunk_map).  NT threads per block:
+// kUpdThreads for the fit; the backward, which also writes dL/dx, runs
+// kBwdThreads.
+constexpr int kBwdThreads = 1024;
+
+template <bool GX, bool OBJ, bool CHECK, int NT>
+__global__ __launch_bounds__(NT) void k_accumulate(
     const float* __restrict__ x, int64_t n, int d, int m, int ks, int ds,
     const uint8_t* __restrict__ codes, const float* __restrict__ c32, int64_t rpc, int nch,
     double* __restrict__ part_s, uint32_t* __restrict__ part_cnt, double* __restrict__ part_j,
     const double* __restrict__ gscale, float* __restrict__ grad_x, float* __restrict__ cmax_zero) {
   extern __shared__ double smem[];
-  __shared__ double redj[kUpdThreads / 64];
+  __shared__ double redj[NT / 64];
   // the next finalize raises cmax[j] tile by tile from zero (the round's
   // assignment, which read it, has finished)
   if (cmax_zero && blockIdx.x == 0)
@@ -439,8 +443,7 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_bf16_batched(const BatchP
 }  // namespace
 
 // at least 4096 rows per chunk (the block's fixed cost of clearing and
-// storing its sums stays small), at most about one 1024-thread block per CU
-// over all (chunk, subspace) pairs
+// storing its sums stays small), at most 256 (chunk, subspace) blocks
 int update_chunks(int64_t n, int m) {
   int nch = ceil_div(n, 4096);
   int cap = 256 / m;
@@ -461,11 +464,11 @@ int launch_update(const float* x, int64_t n, int d, int m, int ks, const uint8_t
     ProfScope ps(MIPQ_K_UPDATE, s);
     float* cz = aop ? cmax : nullptr;
     if (objective)
-      k_accumulate<false, true, false><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, nch, part_s,
-                                                                      part_cnt, part_j, nullptr, nullptr, cz);
+      k_accumulate<false, true, false, kUpdThreads><<<grid, kUpdThreads, shm, s>>>(
+          x, n, d, m, ks, ds, codes, c32, rpc, nch, part_s, part_cnt, part_j, nullptr, nullptr, cz);
     else
-      k_accumulate<false, false, false><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, nch, part_s,
-                                                                       part_cnt, part_j, nullptr, nullptr, cz);
+      k_accumulate<false, false, false, kUpdThreads><<<grid, kUpdThreads, shm, s>>>(
+          x, n, d, m, ks, ds, codes, c32, rpc, nch, part_s, part_cnt, part_j, nullptr, nullptr, cz);
     MIPQ_LAUNCHED("k_accumulate");
   }
   const int nt = tiles_for(ks);
@@ -504,11 +507,11 @@ int launch_backward(const float* x, int64_t n, int d, int m, int ks, const uint8
     const unsigned grid = (unsigned)(((nch + 7) / 8) * 8 * m);
     ProfScope ps(MIPQ_K_BACKWARD, s);
     if (grad_x)
-      k_accumulate<true, true, true><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, nch, part_s,
-                                                                    part_cnt, part_j, gscale, grad_x, nullptr);
+      k_accumulate<true, true, true, kBwdThreads><<<grid, kBwdThreads, shm, s>>>(
+          x, n, d, m, ks, ds, codes, c32, rpc, nch, part_s, part_cnt, part_j, gscale, grad_x, nullptr);
     else
-      k_accumulate<false, true, true><<<grid, kUpdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, nch, part_s,
-                                                                     part_cnt, part_j, nullptr, nullptr, nullptr);
+      k_accumulate<false, true, true, kBwdThreads><<<grid, kBwdThreads, shm, s>>>(
+          x, n, d, m, ks, ds, codes, c32, rpc, nch, part_s, part_cnt, part_j, nullptr, nullptr, nullptr);
     MIPQ_LAUNCHED("k_accumulate");
   }
   k_grad_codebook<<<m, kUpdThreads, 0, s>>>(m, ks, ds, nch, part_s, part_cnt, part_j, c32, gscale, grad_c,
