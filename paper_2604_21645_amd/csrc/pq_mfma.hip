@@ -329,15 +329,82 @@ __device__ __forceinline__ int decide_tile(const float (&xraw)[NB * 8], const Su
 }
 
 // The exact rule for the np pending rows (absolute row indices) of subspace
-// sub, one row at a time by the whole wave; overwrites their codes.
-template <int DW>
+// sub by the whole wave, one row after another; overwrites their codes.  Lane
+// i holds centroids i, i+64, i+128, i+192 (ks <= 256) in registers for all the
+// rows, and the next row's slice is loaded while the current one is decided:
+// per row the wave computes the ks distances (float32, dimensions ascending,
+// unfused; padding dimensions add exact zeros) and takes the lexicographic
+// (distance, index) minimum over the lanes.
+// REG false (kernels with no registers to spare): the rows one at a time with
+// the centroids read for each row (exact_code_wave), the same arithmetic.
+template <int DW, bool REG>
 __device__ __forceinline__ void redecide(const uint32_t* pend, int np, const float* __restrict__ x, int d, int m,
                                          int ks, int ds, int sub, const float* __restrict__ cbsub,
                                          uint8_t* __restrict__ codes, int lane) {
+  if (np == 0) return;   // wave-uniform
+  if (!REG) {
+    for (int i = 0; i < np; ++i) {
+      const int64_t prow = pend[i];
+      const int ec = exact_code_wave<DW>(x + prow * d + (int64_t)sub * ds, cbsub, ds, ks, lane);
+      if (lane == 0) codes[prow * m + sub] = (uint8_t)ec;
+    }
+    return;
+  }
+  constexpr int KPL = kMaxKs / 64;
+  float cv[KPL][DW];
+#pragma unroll
+  for (int j = 0; j < KPL; ++j) {
+    const int k = lane + 64 * j;
+    const float* c = cbsub + (int64_t)(k < ks ? k : 0) * ds;
+#pragma unroll
+    for (int t = 0; t < DW; ++t) {
+      const float v = c[t < ds ? t : ds - 1];
+      cv[j][t] = (k < ks && t < ds) ? v : 0.0f;
+    }
+  }
+  auto load_x = [&](int64_t row, float (&xo)[DW]) {
+    const float* xr = x + row * d + (int64_t)sub * ds;
+#pragma unroll
+    for (int t = 0; t < DW; ++t) {
+      const float v = xr[t < ds ? t : ds - 1];
+      xo[t] = t < ds ? v : 0.0f;
+    }
+  };
+  float xn[DW];
+  load_x(pend[0], xn);
   for (int i = 0; i < np; ++i) {
     const int64_t prow = pend[i];
-    const int ec = exact_code_wave<DW>(x + prow * d + (int64_t)sub * ds, cbsub, ds, ks, lane);
-    if (lane == 0) codes[prow * m + sub] = (uint8_t)ec;
+    float xo[DW];
+#pragma unroll
+    for (int t = 0; t < DW; ++t) xo[t] = xn[t];
+    if (i + 1 < np) load_x(pend[i + 1], xn);   // next row in flight
+    float best = INFINITY;
+    int bk = 0x7FFFFFFF;
+#pragma unroll
+    for (int j = 0; j < KPL; ++j) {
+      const int k = lane + 64 * j;
+      float acc = 0.0f;
+#pragma unroll
+      for (int t = 0; t < DW; ++t) {
+        const float df = xo[t] - cv[j][t];
+        const float sq = df * df;
+        acc = acc + sq;
+      }
+      if (k < ks && acc < best) {
+        best = acc;
+        bk = k;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const float ob = __shfl_xor(best, off, 64);
+      const int ok = __shfl_xor(bk, off, 64);
+      if (ob < best || (ob == best && ok < bk)) {
+        best = ob;
+        bk = ok;
+      }
+    }
+    if (lane == 0) codes[prow * m + sub] = (uint8_t)(bk < ks ? bk : 0);
   }
 }
 
@@ -346,7 +413,7 @@ __device__ __forceinline__ void redecide(const uint32_t* pend, int np, const flo
 // are queued in the wave's LDS list and re-decided with the exact rule after
 // the loop (and, with MIDFLUSH, whenever more than flush_at are queued).
 // Returns the number of re-decided rows.
-template <int DW, bool FULL, bool MIDFLUSH, class Decide>
+template <int DW, bool FULL, bool MIDFLUSH, bool REG, class Decide>
 __device__ __forceinline__ uint32_t assign_rows(const float* __restrict__ x, int d, int ds, int m, int ks, int sub,
                                                 int64_t rb, int64_t re, Decide decide,
                                                 const float* __restrict__ cbsub, uint8_t* __restrict__ codes,
@@ -358,7 +425,7 @@ __device__ __forceinline__ uint32_t assign_rows(const float* __restrict__ x, int
   load_rows<DW, FULL>(xnext, x, rb, re, d, sub, ds, lane);
   for (int64_t r0 = rb; r0 < re; r0 += 32) {
     if (MIDFLUSH && np > flush_at) {
-      redecide<DW>(pend, np, x, d, m, ks, ds, sub, cbsub, codes, lane);
+      redecide<DW, REG>(pend, np, x, d, m, ks, ds, sub, cbsub, codes, lane);
       nres += (uint32_t)np;
       np = 0;
     }
@@ -380,7 +447,7 @@ __device__ __forceinline__ uint32_t assign_rows(const float* __restrict__ x, int
       np += __popcll(mask);
     }
   }
-  redecide<DW>(pend, np, x, d, m, ks, ds, sub, cbsub, codes, lane);
+  redecide<DW, REG>(pend, np, x, d, m, ks, ds, sub, cbsub, codes, lane);
   return nres + (uint32_t)np;
 }
 
@@ -407,7 +474,7 @@ __global__ __launch_bounds__(kThreads) void k_assign_bf16(
   auto decide = [&](const float (&xv)[NB * 8], int half, bool& amb) {
     return decide_tile<NB, NT>(xv, o, half, ks, bd, amb);
   };
-  const uint32_t nres = assign_rows<NB * 8, FULL, false>(x, d, ds, m, ks, sub, rbeg, rend, decide,
+  const uint32_t nres = assign_rows<NB * 8, FULL, false, true>(x, d, ds, m, ks, sub, rbeg, rend, decide,
                                                          c32 + (int64_t)sub * ks * ds, codes, pend_all + w * rpb,
                                                          0, lane);
   if (rescored && lane == 0 && nres) atomicAdd(rescored, (unsigned long long)nres);
@@ -469,7 +536,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NB == 
       return decide_tile<NB, NT>(xv, o, half, ks, bd, amb);
     };
     for (int64_t pb = rb; pb < re; pb += PC)
-      nres += assign_rows<NB * 8, FULL, false>(px, d, ds, m, ks, sub, pb, min(re, pb + PC), decide,
+      nres += assign_rows<NB * 8, FULL, false, false>(px, d, ds, m, ks, sub, pb, min(re, pb + PC), decide,
                                                probs[p].c32 + (int64_t)sub * ks * ds, probs[p].codes,
                                                pend_all + w * PC, 0, lane);
   }
@@ -759,7 +826,7 @@ __global__ __launch_bounds__(kThreads) void k_assign_fp8(
   auto decide = [&](const float (&xv)[NB * 8], int half, bool& amb) {
     return decide_tile_fp8<NB, NT>(xv, o, half, ks, g_exact, amb);
   };
-  const uint32_t nres = assign_rows<NB * 8, FULL, false>(x, d, ds, m, ks, sub, rbeg, rend, decide,
+  const uint32_t nres = assign_rows<NB * 8, FULL, false, true>(x, d, ds, m, ks, sub, rbeg, rend, decide,
                                                          c32 + (int64_t)sub * ks * ds, codes, pend_all + w * rpb,
                                                          0, lane);
   if (rescored && lane == 0 && nres) atomicAdd(rescored, (unsigned long long)nres);
