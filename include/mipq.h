@@ -239,6 +239,23 @@ int mipq_pq_decode_centroids(const float* codebooks, int64_t nbooks, int d, int 
  * Requirements: kc <= 65536, n < 2^31, d % m == 0, d % 16 == 0 and d <= 256
  * for MIPQ_BF16 coarse ranking.
  * ------------------------------------------------------------------------- */
+/* mipq_kmeans_fit: the coarse quantiser on its own (k-means over whole rows,
+ *   k <= 65536 centroids): Lloyd, `iters` rounds, assignments by the coarse
+ *   rule above, centroid = float64 mean of its rows summed in id order (an
+ *   empty centroid keeps its value).  Steps 1-2 of mipq_ii_build.
+ *   x, train_rows, n_train  as in mipq_pq_fit (train_rows optional)
+ *   init_rows     int64 [k]: centroid l starts as training row init_rows[l]
+ *   centroids     OUT float32 [k][d]
+ *   labels        OUT optional int32 [n_train]: the last assignment (against
+ *                 the centroids before the last update); unwritten if iters == 0
+ *   objective     OUT optional float64 [iters]: sum over rows of the squared
+ *                 distance (float64) to the float32 centroid chosen in round t
+ *   precision     MIPQ_FP32 or MIPQ_BF16 (ranking on matrix cores, exact decisions)
+ */
+size_t mipq_kmeans_fit_workspace_size(int64_t n_train, int d, int k, int iters, int precision);
+int mipq_kmeans_fit(const float* x, int64_t n, const int64_t* train_rows, int64_t n_train, int d, int k,
+                    int iters, const int64_t* init_rows, int precision, float* centroids, int32_t* labels,
+                    double* objective, void* ws, size_t ws_bytes, void* stream);
 size_t mipq_coarse_assign_workspace_size(int d, int kc, int precision);
 int mipq_coarse_assign(const float* x, int64_t n, int d, const float* coarse, int kc, int precision,
                        int32_t* labels, int64_t* rescored, void* ws, size_t ws_bytes, void* stream);

@@ -199,6 +199,35 @@ def coarse_assign(x: torch.Tensor, coarse: torch.Tensor, precision="bf16", resco
     return (labels, resc) if rescored else labels
 
 
+def kmeans_fit(x: torch.Tensor, k: int, iters: int, init_rows: torch.Tensor, train_rows: torch.Tensor | None = None,
+               precision="bf16", labels: bool = True, objective: bool = True):
+    """k-means over whole rows (``mipq_kmeans_fit``, the coarse quantiser):
+    dict(centroids float32 [k, d], labels int32 [n_train] (last assignment),
+    objective float64 [iters])."""
+    L = lib()
+    x = _dev(x, torch.float32, "x")
+    dev = x.device
+    n, d = x.shape
+    tr = _dev(train_rows, torch.int64, "train_rows") if train_rows is not None else None
+    n_train = tr.numel() if tr is not None else n
+    ir = _dev(init_rows, torch.int64, "init_rows")
+    if ir.numel() != k:
+        raise ValueError("init_rows must hold k row indices")
+    p = _prec(precision)
+    out = {"centroids": torch.empty((k, d), dtype=torch.float32, device=dev)}
+    if labels:
+        out["labels"] = torch.empty(n_train, dtype=torch.int32, device=dev)
+    if objective:
+        out["objective"] = torch.empty(max(iters, 1), dtype=torch.float64, device=dev)
+    ws = _ws(L.mipq_kmeans_fit_workspace_size(n_train, d, k, iters, p), dev)
+    check(L.mipq_kmeans_fit(_ptr(x), n, _ptr(tr), n_train, d, k, iters, _ptr(ir), p, _ptr(out["centroids"]),
+                            _ptr(out.get("labels")), _ptr(out.get("objective")), _ptr(ws), ws.numel(),
+                            _stream(dev)))
+    if objective:
+        out["objective"] = out["objective"][:iters]
+    return out
+
+
 def ii_build(x: torch.Tensor, kc: int, coarse_iters: int, train_rows: torch.Tensor, coarse_init: torch.Tensor,
              m: int, ks: int, pq_iters: int, pq_init: torch.Tensor, precision="bf16", labels: bool = True,
              coarse_objective: bool = False):

@@ -34,6 +34,8 @@ SIGNATURES = {
     "mipq_pq_decode_centroids": (_I, [_P, _L, _I, _I, _I, _P, _P]),
     "mipq_recon_backward_workspace_size": (_S, [_L, _I, _I, _I]),
     "mipq_recon_backward": (_I, [_P, _P, _P, _L, _I, _I, _I, _P, _P, _P, _P, _P, _S, _P]),
+    "mipq_kmeans_fit_workspace_size": (_S, [_L, _I, _I, _I, _I]),
+    "mipq_kmeans_fit": (_I, [_P, _L, _P, _L, _I, _I, _I, _P, _I, _P, _P, _P, _P, _S, _P]),
     "mipq_coarse_assign_workspace_size": (_S, [_I, _I, _I]),
     "mipq_coarse_assign": (_I, [_P, _L, _I, _P, _I, _I, _P, _P, _P, _S, _P]),
     "mipq_ii_build_workspace_size": (_S, [_L, _I, _I, _L, _I, _I, _I, _I, _I]),

@@ -393,6 +393,77 @@ int mipq_coarse_assign(const float* x, int64_t n, int d, const float* coarse, in
   return coarse_assign_any(x, n, d, coarse, kc, precision, w, labels, rescored, s);
 }
 
+namespace {
+struct KmWs {
+  float* xs;
+  double* cc64;
+  int32_t* lab;
+  uint32_t *keys_a, *keys_b, *keys_sorted, *hist;
+  int32_t *vals_a, *vals_b, *tids;
+  int64_t* toffsets;
+  double* obj_list;
+  CoarseWs cw;
+  size_t bytes;
+};
+
+KmWs carve_kmeans(void* ws, int64_t n_train, bool gather, int d, int k, int precision, bool need_labels) {
+  Carver c(ws);
+  KmWs w;
+  w.xs = gather ? c.take<float>((size_t)n_train * d) : nullptr;
+  w.cc64 = c.take<double>((size_t)k * d);
+  w.lab = need_labels ? c.take<int32_t>(n_train) : nullptr;
+  w.keys_a = c.take<uint32_t>(n_train);
+  w.keys_b = c.take<uint32_t>(n_train);
+  w.keys_sorted = c.take<uint32_t>(n_train);
+  w.hist = c.take<uint32_t>((size_t)64 * sort_blocks(n_train));
+  w.vals_a = c.take<int32_t>(n_train);
+  w.vals_b = c.take<int32_t>(n_train);
+  w.tids = c.take<int32_t>(n_train);
+  w.toffsets = c.take<int64_t>(k + 1);
+  w.obj_list = c.take<double>(k);
+  w.cw = carve_coarse(c, d, k, precision);
+  w.bytes = c.bytes();
+  return w;
+}
+}  // namespace
+
+size_t mipq_kmeans_fit_workspace_size(int64_t n_train, int d, int k, int iters, int precision) {
+  if (n_train < 1 || iters < 0 || check_coarse(n_train, d, k, precision) != MIPQ_OK) return 0;
+  return carve_kmeans(nullptr, n_train, true, d, k, precision, true).bytes;
+}
+
+int mipq_kmeans_fit(const float* x, int64_t n, const int64_t* train_rows, int64_t n_train, int d, int k, int iters,
+                    const int64_t* init_rows, int precision, float* centroids, int32_t* labels, double* objective,
+                    void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  const int64_t nt = train_rows ? n_train : n;
+  if ((rc = check_coarse(nt, d, k, precision))) return rc;
+  if (nt < 1 || (train_rows && n < 1)) return fail(MIPQ_EINVAL, "fit needs at least one training row");
+  if (iters < 0 || iters > (1 << 16)) return fail(MIPQ_EINVAL, "iters out of range (%d)", iters);
+  if (!x || !init_rows || !centroids) return fail(MIPQ_EINVAL, "x, init_rows and centroids are required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  KmWs w = carve_kmeans(ws, nt, train_rows != nullptr, d, k, precision, labels == nullptr);
+  if ((rc = check_ws(ws, ws_bytes, w.bytes))) return rc;
+  const float* train = x;
+  if (train_rows) {
+    uint32_t* bad = w.hist;   // scratch flag before the first sort
+    if ((rc = launch_gather_rows(x, n, d, train_rows, nt, w.xs, bad, s))) return rc;
+    train = w.xs;
+  }
+  int32_t* lab = labels ? labels : w.lab;
+  if ((rc = launch_gather_coarse(train, nt, d, init_rows, k, centroids, w.cc64, s))) return rc;
+  for (int it = 0; it < iters; ++it) {
+    if ((rc = coarse_assign_any(train, nt, d, centroids, k, precision, w.cw, lab, nullptr, s))) return rc;
+    if ((rc = launch_sort_by_label(lab, nt, k, w.keys_a, w.keys_b, w.vals_a, w.vals_b, w.hist, w.tids,
+                                   w.keys_sorted, w.toffsets, s)))
+      return rc;
+    if ((rc = launch_coarse_update(train, d, w.tids, w.toffsets, k, centroids, w.cc64, w.obj_list,
+                                   objective ? objective + it : nullptr, s)))
+      return rc;
+  }
+  return MIPQ_OK;
+}
+
 size_t mipq_ii_build_workspace_size(int64_t n, int d, int kc, int64_t n_train, int m, int ks, int pq_iters,
                                     int coarse_iters, int precision) {
   if (check_coarse(n, d, kc, precision) != MIPQ_OK || check_shape(n_train, d, m, ks, precision, true) != MIPQ_OK)

@@ -171,3 +171,14 @@ def test_fit_width_limits(L):
     assert L.mipq_pq_fit_workspace_size(1000, 64, 1, 256, 5, 0) == 0
     assert L.mipq_pq_fit_workspace_size(1000, 48, 2, 256, 5, 1) == 0    # matrix-core paths: d/m <= 16
     assert L.mipq_recon_backward_workspace_size(1000, 48, 1, 256) > 0
+
+
+def test_kmeans_fit_rejects_bad_arguments(L):
+    km = L.mipq_kmeans_fit
+    assert L.mipq_kmeans_fit_workspace_size(1000, 128, 64, 5, 1) > 0
+    assert L.mipq_kmeans_fit_workspace_size(1000, 128, 64, 5, 2) == 0       # FP8: not offered
+    assert km(4096, 100, None, 0, 128, 64, 5, None, 1, 4096, None, None, 4096, 1 << 30, None) == EINVAL   # no init
+    assert km(4096, 100, None, 0, 128, 64, -1, 4096, 1, 4096, None, None, 4096, 1 << 30, None) == EINVAL
+    assert km(4096, 100, None, 0, 128, 0, 5, 4096, 1, 4096, None, None, 4096, 1 << 30, None) == EINVAL
+    assert km(4096, 100, None, 0, 100, 64, 5, 4096, 1, 4096, None, None, 4096, 1 << 30, None) == EUNSUPPORTED
+    assert km(4096, 100, None, 0, 128, 64, 5, 4096, 1, 4096, None, None, 4096, 64, None) == ENOMEM

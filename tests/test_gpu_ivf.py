@@ -191,3 +191,24 @@ def test_merge_of_synthetic_parts_matches_oracle(kc, m, nparts):
     ids = got["ids"].cpu().numpy().astype(np.int64)
     np.testing.assert_array_equal(ids, ref["ids"])
     np.testing.assert_array_equal(got["codes_sorted"].cpu().numpy().astype(np.int64), ref["codes"][ids])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_kmeans_fit_matches_oracle(prec):
+    """The coarse quantiser on its own: centroids (float64 means in id order,
+    rounded) and last labels bit for bit, objective to float64 rounding."""
+    w = _small()
+    xt = _t(w.x)
+    print("kmeans", prec, flush=True)
+    got = mipq.kmeans_fit(xt, w.kc, w.coarse_iters, _t(w.coarse_init), train_rows=_t(w.coarse_train), precision=prec)
+    ref = ivf.coarse_fit(w.x[w.coarse_train], w.coarse_init, w.coarse_iters)
+    np.testing.assert_array_equal(got["centroids"].cpu().numpy(), ref["codebook"].astype(np.float32))
+    np.testing.assert_array_equal(got["labels"].cpu().numpy().astype(np.int64), ref["labels"])
+    np.testing.assert_allclose(got["objective"].cpu().numpy(), ref["objective"], rtol=1e-12)
+    # all rows as the training set, and zero rounds
+    init = np.arange(0, 20000, 20000 // w.kc)[:w.kc]
+    g2 = mipq.kmeans_fit(xt, w.kc, 3, _t(init), precision=prec)
+    r2 = ivf.coarse_fit(w.x, init, 3)
+    np.testing.assert_array_equal(g2["centroids"].cpu().numpy(), r2["codebook"].astype(np.float32))
+    g0 = mipq.kmeans_fit(xt, w.kc, 0, _t(init), precision=prec, labels=False, objective=False)
+    np.testing.assert_array_equal(g0["centroids"].cpu().numpy(), w.x[init])
