@@ -32,16 +32,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+CSRC = os.path.join(ROOT, "paper_2604_21645_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_assign_bf16_integer_pq_1M_traffic.json")
-MFMA_SOURCE = os.path.join(ROOT, "paper_2604_21645_amd", "csrc", "pq_mfma.hip")
+MFMA_SOURCE = os.path.join(CSRC, "pq_mfma.hip")
+ADC_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_adc_scan_ivf_adc_10M_traffic.json")
+ADC_SOURCE = os.path.join(CSRC, "adc.hip")
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    with open(MFMA_SOURCE, "rb") as f:
+def kernel_source_hash(path: str = MFMA_SOURCE) -> str:
+    with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
@@ -85,15 +88,16 @@ def base_record(metric, value, unit, steps, warmup, ms, dtype, config):
             "dtype": dtype, "data": "synthetic", "config": config}
 
 
-def measured_traffic(per_launch_alg_bytes: float):
-    """HBM bytes per launch of the assignment kernel from committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE counters, or None if absent or stale."""
+def measured_traffic(traffic_file: str = TRAFFIC_FILE, source: str = MFMA_SOURCE):
+    """HBM bytes per launch of a kernel from committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE counters (copy-calibrated), or None if absent or stale (the
+    kernel's source changed since the counters were taken)."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+    if t.get("kernel_source_sha256_16") != kernel_source_hash(source):
         return None
     return t.get("bytes_per_launch")
 
@@ -265,12 +269,6 @@ def bench_integer_pq(args) -> dict:
             "rmse": float(sr8[1].item()),
         }
 
-    if args.copy_calibration:
-        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-
     base, parity = None, {}
     if not args.no_cpu_baseline:
         log("oracle leg: parity on %d sampled rows" % args.oracle_sample)
@@ -278,7 +276,7 @@ def bench_integer_pq(args) -> dict:
         log("oracle leg: cpu baseline on a %.0f%% sample" % (100 * args.cpu_frac))
         base = cpu_baseline(w, args.cpu_frac)
 
-    traffic = measured_traffic(alg_bytes_per_launch)
+    traffic = measured_traffic()
     res = {
         "metric": "PQ fit+encode vectors/s, BF16-MFMA vs FP32 plain, % codes equal to oracle",
         "value": n / (ms * 1e-3),
@@ -507,7 +505,8 @@ def bench_ivf(args) -> dict:
         "build_vectors_per_s": n / (build_ms * 1e-3),
         "oracle_parity": parity,
         "roofline": {"bound": "hbm", "kernel": "k_adc_scan", "achieved": scan_gbs, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": scan_gbs / PEAK_HBM_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": scan_gbs / PEAK_HBM_GBS,
+                     "traffic": measured_traffic(ADC_TRAFFIC_FILE, ADC_SOURCE),
                      "alg_bytes_per_launch": scan_bytes, "avg_launch_ms": scan_ms, "launches": ns,
                      "candidates_per_launch": cand,
                      "note": "each (query, probed list) block reads the list's codes and ids: M + 4 bytes per "
@@ -837,6 +836,11 @@ def main() -> int:
     import torch
     torch.cuda.set_device(0)
     rec = WORKLOADS[args.workload](args)
+    if args.copy_calibration:   # a 1 GiB device copy: reference dispatch for the HBM counters
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
     print(json.dumps(rec), flush=True)
     return 0
 
