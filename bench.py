@@ -509,8 +509,10 @@ def bench_ivf(args) -> dict:
                      "traffic": measured_traffic(ADC_TRAFFIC_FILE, ADC_SOURCE),
                      "alg_bytes_per_launch": scan_bytes, "avg_launch_ms": scan_ms, "launches": ns,
                      "candidates_per_launch": cand,
+                     "table_lookups_per_cu_clock": cand * w.m / (scan_ms * 1e-3) / (256 * 2.4e9),
                      "note": "each (query, probed list) block reads the list's codes and ids: M + 4 bytes per "
-                             "candidate"},
+                             "candidate; blocks of one list run together, so most reads hit L2 (traffic) and the "
+                             "scan is held by its M table reads per candidate from LDS, at random banks"},
         "build_roofline": {"bound": "mfma", "kernel": "k_coarse_assign_mfma", "achieved": achieved, "peak": 2500.0,
                            "unit": "TFLOP/s", "frac": achieved / 2500.0, "traffic": None,
                            "alg_flops_per_launch": flops, "avg_launch_ms": avg, "launches": ca[0],

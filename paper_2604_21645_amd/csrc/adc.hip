@@ -321,6 +321,27 @@ __device__ __forceinline__ void topk_finish(uint64_t* buf, int c) {
   sort_keys(buf, p2);
 }
 
+// Scan order of the (query, probe slot) pairs.  Probe slots are taken in
+// bands of kOrderBand ranks, nearest lists first, so the per-query bounds
+// tighten early; within a band the pairs are bucketed by list, so the blocks
+// that read one list run close together.  Key of pair p = pi * nq + qi:
+// band * (kc + 1) + list (kc: no list).  Bands wider than one rank scan more
+// candidates before the bounds tighten, which costs more than the list reuse
+// gains (10M rows, Kc = 4096, nprobe 32: one rank per band is fastest).
+constexpr int kOrderBand = 1;
+constexpr int kXcdRun = 16;   // consecutive logical blocks given to one XCD
+inline int order_labels(int nprobe, int kc) { return ((nprobe + kOrderBand - 1) / kOrderBand) * (kc + 1); }
+
+__global__ void k_pair_lists(const int32_t* __restrict__ probes, int nq, int nprobe, int kc,
+                             int32_t* __restrict__ plab) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (int64_t)nq * nprobe) return;
+  const int pi = (int)(p / nq);
+  const int qi = (int)(p - (int64_t)pi * nq);
+  const int l = probes[(int64_t)qi * nprobe + pi];
+  plab[p] = (pi / kOrderBand) * (kc + 1) + (l < 0 ? kc : l);
+}
+
 __global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -340,15 +361,23 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
                                                  const uint8_t* __restrict__ codes, const int32_t* __restrict__ probes,
                                                  int nq, int nprobe, int topk, int cap,
                                                  unsigned long long* __restrict__ qthr,
-                                                 uint64_t* __restrict__ pair_out) {
+                                                 uint64_t* __restrict__ pair_out,
+                                                 const int32_t* __restrict__ order, int npairs) {
   extern __shared__ float sm[];
   float* lut = sm;                                   // m*ks
   float* rq = lut + m * ks;                          // d
   uint64_t* buf = reinterpret_cast<uint64_t*>(rq + ((d + 1) & ~1));   // cap
   __shared__ int cnt;
   __shared__ uint64_t thr;
-  const int pi = blockIdx.x / nq;
-  const int qi = blockIdx.x - pi * nq;
+  // logical block: runs of kXcdRun consecutive ones on one XCD (hardware
+  // block id mod 8), so the pairs of one list, adjacent in `order`, read it
+  // through that XCD's L2; the runs advance through `order` together
+  const int xcd = (int)(blockIdx.x & 7), t = (int)(blockIdx.x >> 3);
+  const int lbk = (t / kXcdRun) * (8 * kXcdRun) + xcd * kXcdRun + t % kXcdRun;
+  if (lbk >= npairs) return;   // block-uniform
+  const int pair = order[lbk];
+  const int pi = pair / nq;
+  const int qi = pair - pi * nq;
   uint64_t* outp = pair_out + ((size_t)qi * nprobe + pi) * topk;
   const int l = probes[(int64_t)qi * nprobe + pi];
   if (l < 0) {   // block-uniform
@@ -492,11 +521,39 @@ int adc_scan_smem(int d, int m, int ks, int topk) {
                (size_t)adc_key_cap(topk, kScanBatch) * sizeof(uint64_t));
 }
 
+namespace {
+struct OrderWs {
+  int32_t *plab, *vals_a, *vals_b, *order;
+  uint32_t *keys_a, *keys_b, *keys_sorted, *hist;
+  int64_t* poff;
+  size_t bytes;
+};
+OrderWs carve_order(void* ws, int64_t pairs, int nlabels) {
+  Carver c(ws);
+  OrderWs o;
+  o.plab = c.take<int32_t>(pairs);
+  o.keys_a = c.take<uint32_t>(pairs);
+  o.keys_b = c.take<uint32_t>(pairs);
+  o.keys_sorted = c.take<uint32_t>(pairs);
+  o.hist = c.take<uint32_t>((size_t)64 * sort_blocks(pairs));
+  o.vals_a = c.take<int32_t>(pairs);
+  o.vals_b = c.take<int32_t>(pairs);
+  o.order = c.take<int32_t>(pairs);
+  o.poff = c.take<int64_t>((size_t)nlabels + 1);
+  o.bytes = c.bytes();
+  return o;
+}
+}  // namespace
+
+size_t adc_order_bytes(int64_t pairs, int nprobe, int kc) {
+  return carve_order(nullptr, pairs > 0 ? pairs : 1, order_labels(nprobe, kc)).bytes;
+}
+
 int launch_adc(const float* q, int nq, int d, const float* cc, int kc, const void* aop, const float* mu,
                const unsigned int* cmax_bits, const float* pq, int m, int ks, const int64_t* offsets,
                const int32_t* ids, const uint8_t* codes, int nprobe, int topk, float* est, int32_t* probes,
-               unsigned long long* qthr, uint64_t* pair_out, int64_t* wide, int32_t* out_ids, float* out_dist,
-               hipStream_t s) {
+               unsigned long long* qthr, uint64_t* pair_out, void* order_ws, int64_t* wide, int32_t* out_ids,
+               float* out_dist, hipStream_t s) {
   if (nq == 0) return MIPQ_OK;
   ProfScope ps(MIPQ_K_ADC, s);
   const int S = coarse_ksteps(d);
@@ -525,20 +582,32 @@ int launch_adc(const float* q, int nq, int d, const float* cc, int kc, const voi
   MIPQ_LAUNCHED("k_adc_probe");
   k_fill_u64<<<ceil_div(nq, kT), kT, 0, s>>>(qthr, nq, ~0ull);
   MIPQ_LAUNCHED("k_fill_u64");
+  // scan blocks in list order: a stable bucketing of the (query, probe) pairs
+  // by probed list, pairs without a list last
+  const int64_t npairs = (int64_t)nq * nprobe;
+  const int nlabels = order_labels(nprobe, kc);
+  const OrderWs ow = carve_order(order_ws, npairs, nlabels);
+  k_pair_lists<<<(unsigned)((npairs + kT - 1) / kT), kT, 0, s>>>(probes, nq, nprobe, kc, ow.plab);
+  MIPQ_LAUNCHED("k_pair_lists");
+  {
+    const int rc = launch_sort_by_label(ow.plab, npairs, nlabels, ow.keys_a, ow.keys_b, ow.vals_a, ow.vals_b,
+                                        ow.hist, ow.order, ow.keys_sorted, ow.poff, s);
+    if (rc) return rc;
+  }
   const int ds = d / m;
   const int cap = adc_key_cap(topk, kScanBatch);
   const int mcap = adc_key_cap(topk, kBatch);
   const size_t shm = adc_scan_smem(d, m, ks, topk);
   const bool v16 = (m % 16 == 0) && ((reinterpret_cast<uintptr_t>(codes) & 15) == 0);
-  const unsigned sblocks = (unsigned)((int64_t)nq * nprobe);
+  const unsigned sblocks = (unsigned)(((npairs + 8 * kXcdRun - 1) / (8 * kXcdRun)) * (8 * kXcdRun));
 #define SC(DSV)                                                                                              \
   do {                                                                                                       \
     if (v16)                                                                                                 \
       k_adc_scan<DSV, true><<<sblocks, kT, shm, s>>>(q, d, cc, pq, m, ks, offsets, ids, codes, probes, nq,   \
-                                                     nprobe, topk, cap, qthr, pair_out);                     \
+                                                     nprobe, topk, cap, qthr, pair_out, ow.order, (int)npairs); \
     else                                                                                                     \
       k_adc_scan<DSV, false><<<sblocks, kT, shm, s>>>(q, d, cc, pq, m, ks, offsets, ids, codes, probes, nq,  \
-                                                      nprobe, topk, cap, qthr, pair_out);                    \
+                                                      nprobe, topk, cap, qthr, pair_out, ow.order, (int)npairs); \
   } while (0)
   {
     ProfScope pscan(MIPQ_K_ADC_SCAN, s);

@@ -654,6 +654,7 @@ struct AdcWs {
   int32_t* probes;
   unsigned long long* qthr;
   uint64_t* pair_out;
+  void* order_ws;
   size_t bytes;
 };
 AdcWs carve_adc(void* ws, int nq, int d, int kc, int nprobe, int topk) {
@@ -664,6 +665,7 @@ AdcWs carve_adc(void* ws, int nq, int d, int kc, int nprobe, int topk) {
   a.probes = c.take<int32_t>((size_t)nq * nprobe);
   a.qthr = c.take<unsigned long long>((size_t)nq);
   a.pair_out = c.take<uint64_t>((size_t)nq * nprobe * topk);
+  a.order_ws = c.take<char>(adc_order_bytes((int64_t)nq * nprobe, nprobe, kc));
   a.bytes = c.bytes();
   return a;
 }
@@ -697,7 +699,8 @@ int mipq_adc_search(const float* q, int nq, int d, const float* coarse, int kc, 
   if (nq == 0) return MIPQ_OK;
   if ((rc = launch_coarse_prepare(coarse, kc, d, a.cw.mu, a.cw.cmax, a.cw.aop, s))) return rc;
   return launch_adc(q, nq, d, coarse, kc, a.cw.aop, a.cw.mu, a.cw.cmax, pq_codebook, m, ks, offsets, ids,
-                    codes_sorted, nprobe, topk, a.est, a.probes, a.qthr, a.pair_out, wide, out_ids, out_dist, s);
+                    codes_sorted, nprobe, topk, a.est, a.probes, a.qthr, a.pair_out, a.order_ws, wide, out_ids,
+                    out_dist, s);
 }
 
 }  // extern "C"

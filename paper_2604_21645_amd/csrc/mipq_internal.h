@@ -164,11 +164,13 @@ int launch_merge_lists(const void* parts, int nparts, int64_t total_rows, int kc
                        int64_t* total, int64_t* offsets, int32_t* ids, uint8_t* codes, bool vec16, hipStream_t s);
 
 // ADC search (adc.hip)
+// order_ws: adc_order_bytes(nq * nprobe, nprobe, kc) bytes (the scan blocks' order)
+size_t adc_order_bytes(int64_t pairs, int nprobe, int kc);
 int launch_adc(const float* q, int nq, int d, const float* cc, int kc, const void* aop, const float* mu,
                const unsigned int* cmax_bits, const float* pq, int m, int ks, const int64_t* offsets,
                const int32_t* ids, const uint8_t* codes, int nprobe, int topk, float* est, int32_t* probes,
-               unsigned long long* qthr, uint64_t* pair_out, int64_t* wide, int32_t* out_ids, float* out_dist,
-               hipStream_t s);
+               unsigned long long* qthr, uint64_t* pair_out, void* order_ws, int64_t* wide, int32_t* out_ids,
+               float* out_dist, hipStream_t s);
 
 // operands of the centred codebook; mu: m * kMaxDsBf16 floats (subspace centres)
 int launch_pack_bf16(const float* c32, int m, int ks, int ds, void* aop, float* cmax, float* mu,
