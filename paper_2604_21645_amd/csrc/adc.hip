@@ -18,6 +18,8 @@
 // 4. k_adc_merge: per query, the topk smallest of its lists' candidates.
 #include <math.h>
 
+#include <type_traits>
+
 #include "bf16_pack.h"
 #include "dist32.h"
 #include "mipq_internal.h"
@@ -175,14 +177,30 @@ __global__ __launch_bounds__(kT) void k_adc_probe(const float* __restrict__ q, i
       if ((k & pmask) == sel_prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t need = sel_need, b = 0;
-      while (b < 255 && hist[b] < need) {
-        need -= hist[b];
-        ++b;
+    // the digit: the first bin whose running count reaches sel_need (the
+    // last bin at most); lane i of wave 0 holds bins 4i .. 4i + 3
+    if (threadIdx.x < 64) {
+      const int ln = threadIdx.x;
+      uint32_t hh[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) hh[k] = hist[4 * ln + k];
+      const uint32_t tot = hh[0] + hh[1] + hh[2] + hh[3];
+      uint32_t inc = tot;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(inc, o, 64);
+        if (ln >= o) inc += v;
       }
-      sel_prefix |= b << shift;
-      sel_need = need;
+      const uint32_t exc = inc - tot, need = sel_need;
+      if ((exc < need && need <= inc) || (ln == 63 && inc < need)) {
+        uint32_t nd = need - exc, b = 4 * ln;
+        for (int k = 0; k < 3 && hh[k] < nd; ++k) {
+          nd -= hh[k];
+          ++b;
+        }
+        sel_prefix |= b << shift;
+        sel_need = nd;
+      }
     }
     __syncthreads();
   }
@@ -263,6 +281,11 @@ __global__ __launch_bounds__(kT) void k_adc_probe(const float* __restrict__ q, i
 constexpr int kBatch = kT;   // keys inserted per merge step (one per thread)
 constexpr int kScanRows = 4;  // rows per thread per scan step
 constexpr int kScanBatch = kScanRows * kT;
+// M = 16 rows are first summed over their first kScanPre subspaces; table
+// entries are non-negative and the float32 sum runs in a fixed order, so it
+// never decreases, and a row whose partial sum is already above the bound
+// cannot be inserted.  The other rows are finished from a per-wave queue.
+constexpr int kScanPre = 3;
 
 __device__ void sort_keys(uint64_t* buf, int n2) {
   for (int kk = 2; kk <= n2; kk <<= 1)
@@ -369,6 +392,8 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
   uint64_t* buf = reinterpret_cast<uint64_t*>(rq + ((d + 1) & ~1));   // cap
   __shared__ int cnt;
   __shared__ uint64_t thr;
+  __shared__ uint16_t wq[kScanBatch];   // per wave: its rows left after the partial sums
+  __shared__ int need;                  // 1 + the last step at which a row needed the full table
   // logical block: runs of kXcdRun consecutive ones on one XCD (hardware
   // block id mod 8), so the pairs of one list, adjacent in `order`, read it
   // through that XCD's L2; the runs advance through `order` together
@@ -385,18 +410,35 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
     return;
   }
   const float* qr = q + (int64_t)qi * d;
+  const int64_t a = offsets[l], b = offsets[l + 1];
+  const bool m16 = V16 && m == 16;
+  const uint4* c4 = reinterpret_cast<const uint4*>(codes);
+  // M = 16: the first step's code rows, in flight while the table is built
+  uint4 cv[kScanRows];
+  if (m16) {
+#pragma unroll
+    for (int r = 0; r < kScanRows; ++r) {
+      const int64_t p = a + r * kT + threadIdx.x;
+      if (p < b) cv[r] = c4[p];
+    }
+  }
   if (threadIdx.x == 0) {
     cnt = 0;
+    need = 0;
     thr = load_relaxed(qthr + qi);
   }
   for (int t = threadIdx.x; t < d; t += blockDim.x) rq[t] = qr[t] - cc[(int64_t)l * d + t];
   __syncthreads();
-  for (int e = threadIdx.x; e < m * ks; e += blockDim.x) {
-    const int j = e / ks, k = e - j * ks;
-    lut[e] = sqdist_fixed<DS>(rq + j * DS, pq + ((int64_t)j * ks + k) * DS);
-  }
+  auto build_lut = [&](int e0, int e1) {
+    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+      const int j = e / ks, k = e - j * ks;
+      lut[e] = sqdist_fixed<DS>(rq + j * DS, pq + ((int64_t)j * ks + k) * DS);
+    }
+  };
+  // M = 16 rows: the table of the first kScanPre subspaces now, the rest once
+  // a row needs it (the rows of distant lists mostly never do)
+  build_lut(0, (m16 ? kScanPre : m) * ks);
   __syncthreads();
-  const int64_t a = offsets[l], b = offsets[l + 1];
   // each step takes kScanRows rows per thread (rows p0 + r * kT + thread), so
   // that their loads are in flight together; room for a whole step of keys is
   // kept free in the buffer
@@ -407,34 +449,94 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
       buf[slot] = key;
     }
   };
-  for (int64_t p0 = a; p0 < b; p0 += kScanBatch) {
-    const uint64_t tl = thr;
-    if (V16 && m == 16) {   // one 16-byte code row per row
-      uint4 cv[kScanRows];
-      int32_t iv[kScanRows];
+  // sum of the first U table entries of a 16-code row, subspaces ascending
+  auto sum16 = [&](const uint4 v, auto U) {
+    const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+    float s = 0.0f;
 #pragma unroll
-      for (int r = 0; r < kScanRows; ++r) {
-        const int64_t p = p0 + r * kT + threadIdx.x;
-        if (p < b) {
-          cv[r] = reinterpret_cast<const uint4*>(codes)[p];
-          iv[r] = ids[p];
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < kScanRows; ++r) {
-        const int64_t p = p0 + r * kT + threadIdx.x;
-        if (p < b) {
-          const uint32_t w4[4] = {cv[r].x, cv[r].y, cv[r].z, cv[r].w};
-          float s = 0.0f;
-#pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            const float e = lut[u * ks + ((w4[u >> 2] >> (8 * (u & 3))) & 0xFFu)];
-            s = (u == 0) ? e : s + e;
-          }
-          insert(s, iv[r], tl);
-        }
-      }
+    for (int u = 0; u < decltype(U)::value; ++u) {
+      const float e = lut[u * ks + ((w4[u >> 2] >> (8 * (u & 3))) & 0xFFu)];
+      s = (u == 0) ? e : s + e;
+    }
+    return s;
+  };
+  // end of a step: compaction when the buffer may not hold another step,
+  // else the query's bound as other lists of the query may have lowered it
+  // (ext: its value loaded by thread 0 at the start of the step)
+  auto step_end = [&](uint64_t ext) {
+    __syncthreads();
+    if (cnt > cap - kScanBatch) {   // block-uniform
+      topk_compact(buf, cap, topk, &cnt, &thr, qthr + qi, kScanBatch);
     } else {
+      if (threadIdx.x == 0 && ext < thr) thr = ext;
+      __syncthreads();
+    }
+  };
+  auto ext_load = [&]() { return threadIdx.x == 0 ? load_relaxed(qthr + qi) : ~0ull; };
+  if (m16) {   // one 16-byte code row per row
+    const int lane = threadIdx.x & 63;
+    uint16_t* wql = wq + (threadIdx.x >> 6) * (64 * kScanRows);
+    bool full = false;   // table of all subspaces built (block-uniform)
+    int step = 0;
+    for (int64_t p0 = a; p0 < b; p0 += kScanBatch, ++step) {
+      const uint64_t tl = thr;
+      const uint32_t tb = (uint32_t)(tl >> 32);   // score bits of the bound
+      const uint64_t ext = ext_load();
+      // the next step's code rows, in flight while this step is scored
+      uint4 nx[kScanRows];
+#pragma unroll
+      for (int r = 0; r < kScanRows; ++r) {
+        const int64_t p = p0 + kScanBatch + r * kT + threadIdx.x;
+        if (p < b) nx[r] = c4[p];
+      }
+      if (tb != 0xFFFFFFFFu) {
+        // partial sums over the first kScanPre subspaces; the rows that may
+        // still be inserted, compacted per wave, are finished by all lanes
+        int nq_w = 0;
+#pragma unroll
+        for (int r = 0; r < kScanRows; ++r) {
+          const int64_t p = p0 + r * kT + threadIdx.x;
+          bool keep = false;
+          if (p < b) keep = __float_as_uint(sum16(cv[r], std::integral_constant<int, kScanPre>{})) <= tb;
+          const unsigned long long bal = __ballot(keep);
+          if (keep) wql[nq_w + __popcll(bal & __lanemask_lt())] = (uint16_t)(r * kT + threadIdx.x);
+          nq_w += __popcll(bal);
+        }
+        if (!full) {
+          if (lane == 0 && nq_w > 0) need = step + 1;
+          __syncthreads();
+          if (need == step + 1) {
+            build_lut(kScanPre * ks, m * ks);
+            __syncthreads();
+            full = true;
+          }
+        } else {
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
+        for (int i = lane; i < nq_w; i += 64) {
+          const int64_t p = p0 + wql[i];
+          insert(sum16(c4[p], std::integral_constant<int, 16>{}), ids[p], tl);
+        }
+      } else {   // no bound yet: every row is summed in full
+        if (!full) {
+          build_lut(kScanPre * ks, m * ks);
+          __syncthreads();
+          full = true;
+        }
+#pragma unroll
+        for (int r = 0; r < kScanRows; ++r) {
+          const int64_t p = p0 + r * kT + threadIdx.x;
+          if (p < b) insert(sum16(cv[r], std::integral_constant<int, 16>{}), ids[p], tl);
+        }
+      }
+      step_end(ext);
+#pragma unroll
+      for (int r = 0; r < kScanRows; ++r) cv[r] = nx[r];
+    }
+  } else {
+    for (int64_t p0 = a; p0 < b; p0 += kScanBatch) {
+      const uint64_t tl = thr;
+      const uint64_t ext = ext_load();
       for (int r = 0; r < kScanRows; ++r) {
         const int64_t p = p0 + r * kT + threadIdx.x;
         if (p >= b) break;
@@ -459,9 +561,8 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
         }
         insert(s, ids[p], tl);
       }
+      step_end(ext);
     }
-    __syncthreads();
-    topk_compact(buf, cap, topk, &cnt, &thr, qthr + qi, kScanBatch);
   }
   const int c = cnt;
   topk_finish(buf, c);

@@ -2,6 +2,8 @@
 full index build and ADC top-k search, against the oracle in its
 kernel-decision mode (bit for bit) and the float64 oracle outside near-ties."""
 
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -102,6 +104,39 @@ def test_adc_search_matches_oracle(nprobe, topk):
     ri, rd = ivf.adc_search(w.queries, cc, pqc, off, ids, codes_by_id, nprobe, topk, decide="kernel")
     np.testing.assert_array_equal(gi.cpu().numpy().astype(np.int64), ri)
     np.testing.assert_array_equal(gd.cpu().numpy(), rd.astype(np.float32))
+
+
+@pytest.mark.parametrize("case", ["mixture", "integer_ties"])
+@pytest.mark.parametrize("nprobe,topk", [(4, 10), (3, 100)])
+def test_adc_search_m16_long_lists_matches_oracle(case, nprobe, topk):
+    """M = 16 rows (the partial-sum pruned scan) over lists of several scan
+    steps, so the bounds tighten inside a list and across lists; the
+    integer-valued case puts many candidates at exactly the bound's score."""
+    if case == "mixture":
+        w = wl.ivf_adc(seed=31, n=60000, d=64, n_comp=40, kc=16, n_query=30, m=16, ks=64, coarse_iters=4,
+                       pq_iters=4, n_train=6000, nprobe=nprobe, topk=topk)
+    else:
+        w = wl.ivf_adc(seed=32, n=40000, d=32, n_comp=8, kc=8, n_query=30, m=16, ks=16, coarse_iters=3,
+                       pq_iters=3, n_train=4000, nprobe=nprobe, topk=topk)
+        # rows repeat 200 prototypes, so equal codes in one list give equal scores
+        rng = np.random.default_rng(33)
+        protos = rng.integers(0, 3, size=(200, w.x.shape[1])).astype(np.float32)
+        w = dataclasses.replace(w, x=protos[rng.integers(0, 200, w.x.shape[0])],
+                                queries=rng.integers(0, 3, size=w.queries.shape).astype(np.float32))
+    print("adc m16", case, nprobe, topk, flush=True)
+    idx = mipq.ii_build(_t(w.x), w.kc, w.coarse_iters, _t(w.coarse_train), _t(w.coarse_init), w.m, w.ks,
+                        w.pq_iters, _t(w.pq_init))
+    cc, pqc, off, ids = _gpu_index_np(idx)
+    assert np.diff(off).max() > 3 * 1024
+    codes_sorted = idx["codes_sorted"].cpu().numpy().astype(np.int64)
+    codes_by_id = np.empty_like(codes_sorted)
+    codes_by_id[ids] = codes_sorted
+    gi, gd = mipq.adc_search(_t(w.queries), idx, w.nprobe, w.topk)
+    ri, rd = ivf.adc_search(w.queries, cc, pqc, off, ids, codes_by_id, w.nprobe, w.topk, decide="kernel")
+    np.testing.assert_array_equal(gi.cpu().numpy().astype(np.int64), ri)
+    np.testing.assert_array_equal(gd.cpu().numpy(), rd.astype(np.float32))
+    if case == "integer_ties":   # the top-k ends inside a run of equal distances
+        assert np.mean(rd[:, -1] == rd[:, -2]) > 0.5
 
 
 def test_full_size_index_and_search_sampled():
