@@ -112,10 +112,38 @@ __global__ __launch_bounds__(kT) void k_adc_dist(const float* __restrict__ q, in
   }
 }
 
-__device__ __forceinline__ double coarse_exact(const float* __restrict__ qr, const float* __restrict__ c, int d) {
+// qs: the query row in LDS.  vec (c 16-byte aligned, d % 16 == 0): the row
+// of c is read 16 floats at a time, the next 16 in flight while the current
+// ones are summed; the sum itself runs over t ascending either way.
+__device__ __forceinline__ double coarse_exact(const float* qs, const float* __restrict__ c, int d, bool vec) {
   double acc = 0.0;
+  if (vec) {
+    const float4* c4 = reinterpret_cast<const float4*>(c);
+    const int nch = d >> 4;
+    float4 cur[4], nxt[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cur[k] = c4[k];
+    for (int ch = 0; ch < nch; ++ch) {
+      if (ch + 1 < nch) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) nxt[k] = c4[(ch + 1) * 4 + k];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float cv[4] = {cur[k].x, cur[k].y, cur[k].z, cur[k].w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const double df = (double)(qs[ch * 16 + k * 4 + i] - cv[i]);
+          acc = acc + df * df;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) cur[k] = nxt[k];
+    }
+    return acc;
+  }
   for (int t = 0; t < d; ++t) {
-    const double df = (double)(qr[t] - c[t]);
+    const double df = (double)(qs[t] - c[t]);
     acc = acc + df * df;
   }
   return acc;
@@ -134,6 +162,7 @@ struct DK {   // (distance, list) ordered lexicographically
 __device__ __forceinline__ bool dk_less(const DK& a, const DK& b) { return a.d < b.d || (a.d == b.d && a.l < b.l); }
 
 constexpr int kBandMax = 512;
+constexpr int kMaxCoarseD = 256;   // the search's coarse matrix-core path takes d <= 256
 
 // One block per query: select the nprobe lists (exact rule, ties to the lower
 // list) from the estimates; see the file comment for the band argument.
@@ -147,9 +176,12 @@ __global__ __launch_bounds__(kT) void k_adc_probe(const float* __restrict__ q, i
   __shared__ DK band[kBandMax];
   __shared__ int nband;
   __shared__ float red[kT / 64];
+  __shared__ float qs[kMaxCoarseD];
   const int qi = blockIdx.x;
   const float* qr = q + (int64_t)qi * d;
   const float* er = est + (int64_t)qi * kc;
+  const bool vec = ((reinterpret_cast<uintptr_t>(cc) & 15) == 0) && (d % 16 == 0);
+  for (int t = threadIdx.x; t < d; t += blockDim.x) qs[t] = qr[t];
   // ||q - mu|| for the error bound
   float xn = 0.0f;
   for (int t = threadIdx.x; t < d; t += blockDim.x) {
@@ -214,7 +246,7 @@ __global__ __launch_bounds__(kT) void k_adc_probe(const float* __restrict__ q, i
   for (int l = threadIdx.x; l < kc; l += blockDim.x) {
     if (!(er[l] <= lim)) continue;
     const int p = atomicAdd(&nband, 1);
-    if (p < kBandMax) band[p] = DK{coarse_exact(qr, cc + (int64_t)l * d, d), l};
+    if (p < kBandMax) band[p] = DK{coarse_exact(qs, cc + (int64_t)l * d, d, vec), l};
   }
   __syncthreads();
   int nb = nband;
@@ -232,7 +264,7 @@ __global__ __launch_bounds__(kT) void k_adc_probe(const float* __restrict__ q, i
       const int keep = next == 0 ? 0 : nprobe;
       for (int i = threadIdx.x; i < kBandMax - keep; i += blockDim.x) {
         const int l = next + i;
-        band[keep + i] = l < kc ? DK{coarse_exact(qr, cc + (int64_t)l * d, d), l} : DK{INFINITY, 0x7FFFFFFF};
+        band[keep + i] = l < kc ? DK{coarse_exact(qs, cc + (int64_t)l * d, d, vec), l} : DK{INFINITY, 0x7FFFFFFF};
       }
       next += kBandMax - keep;
       __syncthreads();
@@ -344,16 +376,62 @@ __device__ __forceinline__ void topk_finish(uint64_t* buf, int c) {
   sort_keys(buf, p2);
 }
 
-// Scan order of the (query, probe slot) pairs.  Probe slots are taken in
-// bands of kOrderBand ranks, nearest lists first, so the per-query bounds
-// tighten early; within a band the pairs are bucketed by list, so the blocks
-// that read one list run close together.  Key of pair p = pi * nq + qi:
-// band * (kc + 1) + list (kc: no list).  Bands wider than one rank scan more
-// candidates before the bounds tighten, which costs more than the list reuse
-// gains (10M rows, Kc = 4096, nprobe 32: one rank per band is fastest).
-constexpr int kOrderBand = 1;
-constexpr int kXcdRun = 16;   // consecutive logical blocks given to one XCD
-inline int order_labels(int nprobe, int kc) { return ((nprobe + kOrderBand - 1) / kOrderBand) * (kc + 1); }
+// Scan order of the (query, probe slot) pairs: probe rank major, so every
+// query's nearest lists are scanned first and its bound tightens early; within
+// a rank the pairs are bucketed by list, so the blocks that read one list run
+// close together.  (Bucketing several ranks together shares a list among more
+// queries but scans more candidates before the bounds tighten: on 10M rows,
+// Kc = 4096, nprobe 32, one rank per bucketing is fastest.)  The order within
+// a list does not change the search results.
+constexpr int kXcdRun = 16;        // consecutive logical blocks given to one XCD
+constexpr int kOrderT = 1024;
+constexpr int kOrderMaxBins = 8192;   // LDS counters of k_pair_order
+
+// one block per probe rank pi: pair ids pi * nq + qi bucketed by probed list
+// (kc: no list), written to order[pi * nq, (pi + 1) * nq)
+__global__ __launch_bounds__(kOrderT) void k_pair_order(const int32_t* __restrict__ probes, int nq, int nprobe,
+                                                        int kc, int32_t* __restrict__ order) {
+  extern __shared__ uint32_t cnt[];   // kc + 1
+  __shared__ uint32_t part[kOrderT / 64];
+  const int pi = blockIdx.x, nb = kc + 1;
+  auto bin = [&](int qi) {
+    const int l = probes[(int64_t)qi * nprobe + pi];
+    return (l < 0 || l >= kc) ? kc : l;
+  };
+  for (int i = threadIdx.x; i < nb; i += kOrderT) cnt[i] = 0u;
+  __syncthreads();
+  for (int qi = threadIdx.x; qi < nq; qi += kOrderT) atomicAdd(&cnt[bin(qi)], 1u);
+  __syncthreads();
+  // exclusive prefix of the counts: thread t owns bins [t * per, (t + 1) * per)
+  const int per = (nb + kOrderT - 1) / kOrderT;
+  const int b0 = threadIdx.x * per;
+  uint32_t tot = 0u;
+  for (int i = 0; i < per; ++i)
+    if (b0 + i < nb) tot += cnt[b0 + i];
+  uint32_t inc = tot;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t v = __shfl_up(inc, o, 64);
+    if ((threadIdx.x & 63) >= o) inc += v;
+  }
+  if ((threadIdx.x & 63) == 63) part[threadIdx.x >> 6] = inc;
+  __syncthreads();
+  uint32_t run = inc - tot;
+  for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) run += part[w];
+  for (int i = 0; i < per; ++i)
+    if (b0 + i < nb) {
+      const uint32_t c = cnt[b0 + i];
+      cnt[b0 + i] = run;
+      run += c;
+    }
+  __syncthreads();
+  int32_t* out = order + (int64_t)pi * nq;
+  for (int qi = threadIdx.x; qi < nq; qi += kOrderT) out[atomicAdd(&cnt[bin(qi)], 1u)] = pi * nq + qi;
+}
+
+// larger kc: the same order by the stable radix sort of the index build on
+// the key pi * (kc + 1) + list
+inline int order_labels(int nprobe, int kc) { return nprobe * (kc + 1); }
 
 __global__ void k_pair_lists(const int32_t* __restrict__ probes, int nq, int nprobe, int kc,
                              int32_t* __restrict__ plab) {
@@ -362,7 +440,7 @@ __global__ void k_pair_lists(const int32_t* __restrict__ probes, int nq, int npr
   const int pi = (int)(p / nq);
   const int qi = (int)(p - (int64_t)pi * nq);
   const int l = probes[(int64_t)qi * nprobe + pi];
-  plab[p] = (pi / kOrderBand) * (kc + 1) + (l < 0 ? kc : l);
+  plab[p] = pi * (kc + 1) + ((l < 0 || l >= kc) ? kc : l);
 }
 
 __global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
@@ -683,14 +761,16 @@ int launch_adc(const float* q, int nq, int d, const float* cc, int kc, const voi
   MIPQ_LAUNCHED("k_adc_probe");
   k_fill_u64<<<ceil_div(nq, kT), kT, 0, s>>>(qthr, nq, ~0ull);
   MIPQ_LAUNCHED("k_fill_u64");
-  // scan blocks in list order: a stable bucketing of the (query, probe) pairs
-  // by probed list, pairs without a list last
+  // the scan blocks' order (see k_pair_order)
   const int64_t npairs = (int64_t)nq * nprobe;
   const int nlabels = order_labels(nprobe, kc);
   const OrderWs ow = carve_order(order_ws, npairs, nlabels);
-  k_pair_lists<<<(unsigned)((npairs + kT - 1) / kT), kT, 0, s>>>(probes, nq, nprobe, kc, ow.plab);
-  MIPQ_LAUNCHED("k_pair_lists");
-  {
+  if (kc + 1 <= kOrderMaxBins) {
+    k_pair_order<<<nprobe, kOrderT, (size_t)(kc + 1) * sizeof(uint32_t), s>>>(probes, nq, nprobe, kc, ow.order);
+    MIPQ_LAUNCHED("k_pair_order");
+  } else {
+    k_pair_lists<<<(unsigned)((npairs + kT - 1) / kT), kT, 0, s>>>(probes, nq, nprobe, kc, ow.plab);
+    MIPQ_LAUNCHED("k_pair_lists");
     const int rc = launch_sort_by_label(ow.plab, npairs, nlabels, ow.keys_a, ow.keys_b, ow.vals_a, ow.vals_b,
                                         ow.hist, ow.order, ow.keys_sorted, ow.poff, s);
     if (rc) return rc;

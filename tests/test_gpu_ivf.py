@@ -139,6 +139,24 @@ def test_adc_search_m16_long_lists_matches_oracle(case, nprobe, topk):
         assert np.mean(rd[:, -1] == rd[:, -2]) > 0.5
 
 
+def test_adc_search_many_lists_matches_oracle():
+    """Kc above the LDS counters of the per-rank pair ordering: the scan
+    order comes from the radix-sort path instead; results are the same."""
+    w = wl.ivf_adc(seed=34, n=40000, d=32, n_comp=200, kc=9000, n_query=20, m=8, ks=16, coarse_iters=2,
+                   pq_iters=2, n_train=20000, nprobe=40, topk=20)
+    print("adc kc", w.kc, flush=True)
+    idx = mipq.ii_build(_t(w.x), w.kc, w.coarse_iters, _t(w.coarse_train), _t(w.coarse_init), w.m, w.ks,
+                        w.pq_iters, _t(w.pq_init))
+    cc, pqc, off, ids = _gpu_index_np(idx)
+    codes_sorted = idx["codes_sorted"].cpu().numpy().astype(np.int64)
+    codes_by_id = np.empty_like(codes_sorted)
+    codes_by_id[ids] = codes_sorted
+    gi, gd = mipq.adc_search(_t(w.queries), idx, w.nprobe, w.topk)
+    ri, rd = ivf.adc_search(w.queries, cc, pqc, off, ids, codes_by_id, w.nprobe, w.topk, decide="kernel")
+    np.testing.assert_array_equal(gi.cpu().numpy().astype(np.int64), ri)
+    np.testing.assert_array_equal(gd.cpu().numpy(), rd.astype(np.float32))
+
+
 def test_full_size_index_and_search_sampled():
     """10M x 128 rows, Kc = 4096, residual PQ M=16 Ks=256, 10k queries,
     nprobe 32, top-100: bucket invariants on every row, sampled labels and
