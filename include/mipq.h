@@ -322,7 +322,9 @@ int mipq_ii_merge(const int64_t* const* part_offsets, const int32_t* const* part
  *   wide      OUT optional int64 [1]: queries whose probe selection needed the
  *             exact rule on every list
  * Requirements: 1 <= nprobe <= min(kc, 256), 1 <= topk <= 1024, d/m in
- * {1, 2, 4, 8, 16}, d <= 16 or d in {32, 64, 96, 128, 192, 256}.
+ * {1, 2, 4, 8, 16}, d <= 16 or d in {32, 64, 96, 128, 192, 256}, and the
+ * table with its key buffer within 64 KiB of LDS (m * ks <= 11264 always
+ * fits; larger tables return MIPQ_EUNSUPPORTED).
  * ------------------------------------------------------------------------- */
 size_t mipq_adc_search_workspace_size(int nq, int d, int kc, int nprobe, int topk);
 int mipq_adc_search(const float* q, int nq, int d, const float* coarse, int kc, const float* pq_codebook,

@@ -311,7 +311,7 @@ __global__ __launch_bounds__(kT) void k_adc_probe(const float* __restrict__ q, i
 }
 
 constexpr int kBatch = kT;   // keys inserted per merge step (one per thread)
-constexpr int kScanRows = 4;  // rows per thread per scan step
+constexpr int kScanRows = 2;  // rows per thread per scan step
 constexpr int kScanBatch = kScanRows * kT;
 // M = 16 rows are first summed over their first kScanPre subspaces; table
 // entries are non-negative and the float32 sum runs in a fixed order, so it
@@ -491,13 +491,15 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
   const int64_t a = offsets[l], b = offsets[l + 1];
   const bool m16 = V16 && m == 16;
   const uint4* c4 = reinterpret_cast<const uint4*>(codes);
-  // M = 16: the first step's code rows, in flight while the table is built
-  uint4 cv[kScanRows];
+  // M = 16: the code rows of the first two steps, in flight while the table
+  // is built; each step then loads the rows two steps ahead
+  uint4 cv[kScanRows], n1[kScanRows];
   if (m16) {
 #pragma unroll
     for (int r = 0; r < kScanRows; ++r) {
       const int64_t p = a + r * kT + threadIdx.x;
       if (p < b) cv[r] = c4[p];
+      if (p + kScanBatch < b) n1[r] = c4[p + kScanBatch];
     }
   }
   if (threadIdx.x == 0) {
@@ -560,11 +562,11 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
       const uint64_t tl = thr;
       const uint32_t tb = (uint32_t)(tl >> 32);   // score bits of the bound
       const uint64_t ext = ext_load();
-      // the next step's code rows, in flight while this step is scored
+      // the code rows two steps ahead, in flight while this step is scored
       uint4 nx[kScanRows];
 #pragma unroll
       for (int r = 0; r < kScanRows; ++r) {
-        const int64_t p = p0 + kScanBatch + r * kT + threadIdx.x;
+        const int64_t p = p0 + 2 * kScanBatch + r * kT + threadIdx.x;
         if (p < b) nx[r] = c4[p];
       }
       if (tb != 0xFFFFFFFFu) {
@@ -609,7 +611,10 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
       }
       step_end(ext);
 #pragma unroll
-      for (int r = 0; r < kScanRows; ++r) cv[r] = nx[r];
+      for (int r = 0; r < kScanRows; ++r) {
+        cv[r] = n1[r];
+        n1[r] = nx[r];
+      }
     }
   } else {
     for (int64_t p0 = a; p0 < b; p0 += kScanBatch) {
@@ -698,6 +703,11 @@ int adc_key_cap(int topk, int batch) {
 int adc_scan_smem(int d, int m, int ks, int topk) {
   return (int)((size_t)m * ks * sizeof(float) + (size_t)((d + 1) & ~1) * sizeof(float) +
                (size_t)adc_key_cap(topk, kScanBatch) * sizeof(uint64_t));
+}
+
+bool adc_fits_lds(int d, int m, int ks, int topk) {
+  // dynamic part + the survivor queues and counters of the scan block
+  return (size_t)adc_scan_smem(d, m, ks, topk) + kScanBatch * sizeof(uint16_t) + 64 <= kAdcMaxLds;
 }
 
 namespace {

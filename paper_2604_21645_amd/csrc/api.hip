@@ -687,6 +687,8 @@ int mipq_adc_search(const float* q, int nq, int d, const float* coarse, int kc, 
   const int ds = d / m;
   if (!(ds == 1 || ds == 2 || ds == 4 || ds == 8 || ds == 16))
     return fail(MIPQ_EUNSUPPORTED, "ADC supports d/m in {1, 2, 4, 8, 16} (got %d)", ds);
+  if (topk >= 1 && topk <= 1024 && !adc_fits_lds(d, m, ks, topk))
+    return fail(MIPQ_EUNSUPPORTED, "ADC table of m x ks = %d x %d floats does not fit one block's LDS", m, ks);
   if (nprobe < 1 || nprobe > kc || nprobe > 256) return fail(MIPQ_EINVAL, "nprobe must be in [1, min(kc, 256)]");
   if (topk < 1 || topk > 1024) return fail(MIPQ_EINVAL, "topk must be in [1, 1024]");
   if (nq > 0 && (!q || !coarse || !pq_codebook || !offsets || !ids || !codes_sorted || !out_ids || !out_dist))

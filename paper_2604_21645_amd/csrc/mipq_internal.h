@@ -164,6 +164,9 @@ int launch_merge_lists(const void* parts, int nparts, int64_t total_rows, int kc
                        int64_t* total, int64_t* offsets, int32_t* ids, uint8_t* codes, bool vec16, hipStream_t s);
 
 // ADC search (adc.hip)
+// LDS of one scan block (the table m x ks floats, the query, the key buffer)
+constexpr size_t kAdcMaxLds = 64 * 1024;
+bool adc_fits_lds(int d, int m, int ks, int topk);
 // order_ws: adc_order_bytes(nq * nprobe, nprobe, kc) bytes (the scan blocks' order)
 size_t adc_order_bytes(int64_t pairs, int nprobe, int kc);
 int launch_adc(const float* q, int nq, int d, const float* cc, int kc, const void* aop, const float* mu,

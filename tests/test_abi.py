@@ -182,3 +182,12 @@ def test_kmeans_fit_rejects_bad_arguments(L):
     assert km(4096, 100, None, 0, 128, 0, 5, 4096, 1, 4096, None, None, 4096, 1 << 30, None) == EINVAL
     assert km(4096, 100, None, 0, 100, 64, 5, 4096, 1, 4096, None, None, 4096, 1 << 30, None) == EUNSUPPORTED
     assert km(4096, 100, None, 0, 128, 64, 5, 4096, 1, 4096, None, None, 4096, 64, None) == ENOMEM
+
+
+def test_adc_search_rejects_tables_beyond_lds(L):
+    # d = 256, m = 256 (d/m = 1), ks = 256: a 256 KiB table per (query, list)
+    adc = L.mipq_adc_search
+    F = 4096
+    assert adc(F, 10, 256, F, 64, F, 256, 256, F, F, F, 8, 10, F, F, None, F, 1 << 30, None) == EUNSUPPORTED
+    # m * ks = 192 * 58 <= 11264 fits with topk = 1024: refused only for the too-small workspace
+    assert adc(F, 10, 192, F, 64, F, 192, 58, F, F, F, 8, 1024, F, F, None, F, 64, None) == ENOMEM
