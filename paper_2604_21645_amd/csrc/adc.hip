@@ -319,22 +319,36 @@ constexpr int kScanBatch = kScanRows * kT;
 // cannot be inserted.  The other rows are finished from a per-wave queue.
 constexpr int kScanPre = 3;
 
-__device__ void sort_keys(uint64_t* buf, int n2) {
-  for (int kk = 2; kk <= n2; kk <<= 1)
-    for (int j = kk >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-        const int ij = i ^ j;
-        if (ij > i) {
-          const bool up = (i & kk) == 0;
-          const uint64_t a = buf[i], b = buf[ij];
-          if (up ? (b < a) : (a < b)) {
-            buf[i] = b;
-            buf[ij] = a;
-          }
-        }
+// Ascending sort of buf[0, n), any n: a bitonic network in the form where
+// every comparator is ascending (each merge first compares mirrored
+// positions), so positions n and beyond act as +infinity and are never read.
+__device__ void sort_keys(uint64_t* buf, int n) {
+  int n2 = 1;
+  while (n2 < n) n2 <<= 1;
+  auto cswap = [&](int lo, int hi) {
+    if (hi < n) {
+      const uint64_t a = buf[lo], b = buf[hi];
+      if (b < a) {
+        buf[lo] = b;
+        buf[hi] = a;
+      }
+    }
+  };
+  for (int kk = 2; kk <= n2; kk <<= 1) {
+    const int h = kk >> 1;
+    for (int i = threadIdx.x; i < (n2 >> 1); i += blockDim.x) {
+      const int base = (i / h) * kk, off = i % h;
+      cswap(base + off, base + kk - 1 - off);
+    }
+    __syncthreads();
+    for (int j = kk >> 2; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < (n2 >> 1); i += blockDim.x) {
+        const int lo = (i / j) * 2 * j + i % j;
+        cswap(lo, lo + j);
       }
       __syncthreads();
     }
+  }
 }
 
 __device__ __forceinline__ uint64_t load_relaxed(const unsigned long long* p) {
@@ -350,9 +364,8 @@ __device__ __forceinline__ void topk_compact(uint64_t* buf, int cap, int topk, i
                                              const unsigned long long* ext, int batch) {
   if (*cnt <= cap - batch) return;   // block-uniform
   const int c = *cnt < cap ? *cnt : cap;
-  for (int i = c + threadIdx.x; i < cap; i += blockDim.x) buf[i] = ~0ull;
   __syncthreads();
-  sort_keys(buf, cap);
+  sort_keys(buf, c);
   if (threadIdx.x == 0) {
     const int keep = c < topk ? c : topk;
     *cnt = keep;
@@ -367,13 +380,10 @@ __device__ __forceinline__ void topk_compact(uint64_t* buf, int cap, int topk, i
   __syncthreads();
 }
 
-// final sort of the first c keys of buf (padded to a power of two)
+// final sort of the first c keys of buf
 __device__ __forceinline__ void topk_finish(uint64_t* buf, int c) {
-  int p2 = 1;
-  while (p2 < c) p2 <<= 1;
-  for (int i = c + threadIdx.x; i < p2; i += blockDim.x) buf[i] = ~0ull;
   __syncthreads();
-  sort_keys(buf, p2);
+  sort_keys(buf, c);
 }
 
 // Scan order of the (query, probe slot) pairs: probe rank major, so every
@@ -692,13 +702,9 @@ __global__ __launch_bounds__(kT) void k_adc_merge(const uint64_t* __restrict__ p
 
 }  // namespace
 
-// key buffer of a scan block / the merge block: a power of two with room for
-// topk kept keys plus one full batch
-int adc_key_cap(int topk, int batch) {
-  int c = 512;
-  while (c < topk + batch) c <<= 1;
-  return c;
-}
+// key buffer of a scan block / the merge block: room for topk kept keys plus
+// one full batch, rounded up to 64 keys
+int adc_key_cap(int topk, int batch) { return ((topk + batch + 63) / 64) * 64; }
 
 int adc_scan_smem(int d, int m, int ks, int topk) {
   return (int)((size_t)m * ks * sizeof(float) + (size_t)((d + 1) & ~1) * sizeof(float) +
