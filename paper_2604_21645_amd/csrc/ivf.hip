@@ -130,8 +130,46 @@ __global__ __launch_bounds__(kT) void k_coarse_pack(const float* __restrict__ cc
 
 // ---------------------------------------------------------------- exact rule
 // float32 differences, float64 squares and sums in ascending dimension order
+// (rows of 16-float multiples at 16-byte alignment are read 16 floats at a
+// time, the next 16 in flight; the order of the sum is the same)
 __device__ __forceinline__ double coarse_exact_dist(const float* __restrict__ xr, const float* __restrict__ c, int d) {
   double acc = 0.0;
+  if ((d & 15) == 0 && ((reinterpret_cast<uintptr_t>(xr) | reinterpret_cast<uintptr_t>(c)) & 15) == 0) {
+    const float4* x4 = reinterpret_cast<const float4*>(xr);
+    const float4* c4 = reinterpret_cast<const float4*>(c);
+    const int nch = d >> 4;
+    float4 xc[4], cc4[4], xn[4], cn[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      xc[k] = x4[k];
+      cc4[k] = c4[k];
+    }
+    for (int ch = 0; ch < nch; ++ch) {
+      if (ch + 1 < nch) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          xn[k] = x4[(ch + 1) * 4 + k];
+          cn[k] = c4[(ch + 1) * 4 + k];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float xv[4] = {xc[k].x, xc[k].y, xc[k].z, xc[k].w};
+        const float cv[4] = {cc4[k].x, cc4[k].y, cc4[k].z, cc4[k].w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const double df = (double)(xv[i] - cv[i]);
+          acc = acc + df * df;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        xc[k] = xn[k];
+        cc4[k] = cn[k];
+      }
+    }
+    return acc;
+  }
   for (int t = 0; t < d; ++t) {
     const double df = (double)(xr[t] - c[t]);
     acc = acc + df * df;
@@ -199,8 +237,10 @@ __global__ __launch_bounds__(kT) void k_coarse_assign_exact(const float* __restr
 // rule over all centroids.
 constexpr int kCandCap = 256;   // candidate pairs per wave
 
+// (registers capped for three waves per SIMD: at d = 128 the two waves the
+// uncapped kernel allowed took 35 ms on 10M rows x Kc = 4096, three 30 ms)
 template <int S, int RG>
-__global__ __launch_bounds__(kT) void k_coarse_assign_mfma(
+__global__ __launch_bounds__(kT, 3) void k_coarse_assign_mfma(
     const float* __restrict__ x, int64_t n, int d, int kc, const bf16x8* __restrict__ aop,
     const float* __restrict__ mu, const unsigned int* __restrict__ cmax_bits, const float* __restrict__ cc,
     int32_t* __restrict__ labels, unsigned long long* __restrict__ rescored, float e_cross, float e_norm,
@@ -208,14 +248,19 @@ __global__ __launch_bounds__(kT) void k_coarse_assign_mfma(
   constexpr int NK = S + 1;
   __shared__ uint32_t cand_rk_all[kT / 64][kCandCap];   // (row in wave) << 16 | centroid
   __shared__ double cand_d_all[kT / 64][kCandCap];
+  __shared__ bf16x8 a_lds[2][NK * 64];
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
   const int w = threadIdx.x >> 6;
   const int64_t r0 = ((int64_t)blockIdx.x * (kT / 64) + w) * (32 * RG);
-  if (r0 >= n) return;
+  // waves past the last row still stage operands and meet the block's
+  // barriers; their rows read row n - 1 and write nothing
   uint32_t* cand_rk = cand_rk_all[w];
   double* cand_d = cand_d_all[w];
   const float cm = __uint_as_float(*cmax_bits);
+  // every row slice is whole and 16-byte aligned (mu is a workspace buffer)
+  const bool vec = d == 16 * S && (reinterpret_cast<uintptr_t>(x) & 15) == 0 &&
+                   (reinterpret_cast<uintptr_t>(mu) & 15) == 0;
 
   // row operands (centred), ||x - mu||^2
   bf16x8 B[RG][NK];
@@ -223,17 +268,31 @@ __global__ __launch_bounds__(kT) void k_coarse_assign_mfma(
 #pragma unroll
   for (int g = 0; g < RG; ++g) {
     const int64_t row = r0 + 32 * g + (lane & 31);
-    const float* xr = x + (row < n ? row : r0) * d;
+    const float* xr = x + (row < n ? row : n - 1) * d;
     float xn_part = 0.0f;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       float v[8];
+      if (vec) {   // the 8 dimensions 16 s + 8 h .. + 7 as two float4
+        const float4 xa = *reinterpret_cast<const float4*>(xr + 16 * s + 8 * h);
+        const float4 xb = *reinterpret_cast<const float4*>(xr + 16 * s + 8 * h + 4);
+        const float4 ma = *reinterpret_cast<const float4*>(mu + 16 * s + 8 * h);
+        const float4 mb = *reinterpret_cast<const float4*>(mu + 16 * s + 8 * h + 4);
+        const float xs[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
+        const float ms[8] = {ma.x, ma.y, ma.z, ma.w, mb.x, mb.y, mb.z, mb.w};
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int dim = 16 * s + 8 * h + e;
-        const float xv = xr[dim < d ? dim : d - 1];
-        v[e] = dim < d ? xv - mu[dim] : 0.0f;
-        xn_part = xn_part + v[e] * v[e];
+        for (int e = 0; e < 8; ++e) {
+          v[e] = xs[e] - ms[e];
+          xn_part = xn_part + v[e] * v[e];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int dim = 16 * s + 8 * h + e;
+          const float xv = xr[dim < d ? dim : d - 1];
+          v[e] = dim < d ? xv - mu[dim] : 0.0f;
+          xn_part = xn_part + v[e] * v[e];
+        }
       }
       B[g][s] = to_bf16x8(v);
     }
@@ -261,25 +320,50 @@ __global__ __launch_bounds__(kT) void k_coarse_assign_mfma(
     i1[g] = 0;
   }
   const int nt = (kc + 31) / 32;
-  for (int t = 0; t < nt; ++t) {
-    bf16x8 A[NK];
+  // centroid operands of a tile: staged in LDS once for the block's four
+  // waves (two buffers); the next tile's chunks are loaded into registers
+  // while the current tile is scored, and stored after it
+  constexpr int CH = NK * 64;               // 16-byte operand chunks per tile
+  constexpr int PT = (CH + kT - 1) / kT;    // chunks per thread
+  bf16x8 pre[PT];
+  auto fetch = [&](int t) {
 #pragma unroll
-    for (int s = 0; s < NK; ++s) A[s] = aop[((size_t)t * NK + s) * 64 + lane];
+    for (int i = 0; i < PT; ++i) {
+      const int c = threadIdx.x + i * kT;
+      if (c < CH) pre[i] = aop[(size_t)t * CH + c];
+    }
+  };
+  auto put = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+      const int c = threadIdx.x + i * kT;
+      if (c < CH) a_lds[buf][c] = pre[i];
+    }
+  };
+  fetch(0);
+  put(0);
+  __syncthreads();
+  for (int t = 0; t < nt; ++t) {
+    const int cur = t & 1;
+    if (t + 1 < nt) fetch(t + 1);
 #pragma unroll
     for (int g = 0; g < RG; ++g) {
       f32x16 acc = {};
 #pragma unroll
-      for (int s = 0; s < NK; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s], B[g][s], acc, 0, 0, 0);
+      for (int s = 0; s < NK; ++s)
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_lds[cur][s * 64 + lane], B[g][s], acc, 0, 0, 0);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const float v = acc[r];
         const int k = t * 32 + (r >> 2) * 8 + h * 4 + (r & 3);
-        v2[g] = fminf(v2[g], fmaxf(v1[g], v));   // runner-up of {v1, v2, v}, v1 <= v2
+        v2[g] = __builtin_amdgcn_fmed3f(v1[g], v2[g], v);   // runner-up of {v1, v2, v}, v1 <= v2
         const bool lt = v < v1[g];
         i1[g] = lt ? k : i1[g];
         v1[g] = lt ? v : v1[g];
       }
     }
+    if (t + 1 < nt) put(cur ^ 1);
+    __syncthreads();
   }
 
   // merge the two lanes of each row; separation test
