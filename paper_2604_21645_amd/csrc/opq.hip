@@ -25,6 +25,7 @@ namespace {
 constexpr int kTile = 64;      // output tile edge (rows x columns)
 constexpr int kTk = 32;        // reduction depth staged per step
 constexpr int kThreads = 256;  // 16 x 16 threads, 4 x 4 outputs each
+typedef double XsT;            // x staged in LDS as float64: converted once per block, not per use
 
 // Block (row tile, column tile) of y = x R.  XCD-aware: consecutive column
 // tiles of one row tile go to one XCD (blocks b, b + 8, ...) so that the row
@@ -32,7 +33,7 @@ constexpr int kThreads = 256;  // 16 x 16 threads, 4 x 4 outputs each
 __global__ __launch_bounds__(kThreads) void k_rotate(const float* __restrict__ x, int64_t n, int d,
                                                      const double* __restrict__ r, float* __restrict__ y,
                                                      int ctiles, int64_t nblocks) {
-  __shared__ __align__(16) float xs[kTk][kTile + 4];   // x tile, transposed: xs[t][row]
+  __shared__ __align__(16) XsT xs[kTk][kTile + 4];      // x tile, transposed: xs[t][row]
   __shared__ __align__(16) double rs[kTk][kTile + 2];  // R tile: rs[t][col]
   // logical block -> (row tile, column tile)
   const int64_t b = blockIdx.x;
@@ -52,26 +53,44 @@ __global__ __launch_bounds__(kThreads) void k_rotate(const float* __restrict__ x
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
 
-  for (int t0 = 0; t0 < d; t0 += kTk) {
-    // stage x[row0 .. +64][t0 .. +32] transposed (8 floats per thread)
-    for (int e = tid; e < kTile * kTk; e += kThreads) {
+  // staging of x[row0 .. +64][t0 .. +32] (transposed) and R[t0 .. +32][col0 ..
+  // +64]: the next step's elements are loaded into registers while the current
+  // step is computed
+  constexpr int PE = kTile * kTk / kThreads;   // elements of each tile per thread
+  float px[PE];
+  double pr[PE];
+  auto fetch = [&](int t0) {
+#pragma unroll
+    for (int k = 0; k < PE; ++k) {
+      const int e = tid + k * kThreads;
       const int rr = e / kTk, tt = e - rr * kTk;
       const int64_t row = row0 + rr;
       const int t = t0 + tt;
-      xs[tt][rr] = (row < n && t < d) ? x[row * d + t] : 0.0f;
+      px[k] = (row < n && t < d) ? x[row * d + t] : 0.0f;
+      const int t2 = t0 + e / kTile, col = col0 + (e - (e / kTile) * kTile);
+      pr[k] = (t2 < d && col < d) ? r[(int64_t)t2 * d + col] : 0.0;
     }
-    // stage R[t0 .. +32][col0 .. +64]
-    for (int e = tid; e < kTk * kTile; e += kThreads) {
-      const int tt = e / kTile, cc = e - tt * kTile;
-      const int t = t0 + tt, col = col0 + cc;
-      rs[tt][cc] = (t < d && col < d) ? r[(int64_t)t * d + col] : 0.0;
+  };
+  auto put = [&]() {
+#pragma unroll
+    for (int k = 0; k < PE; ++k) {
+      const int e = tid + k * kThreads;
+      const int rr = e / kTk;
+      xs[e - rr * kTk][rr] = (XsT)px[k];
+      rs[e / kTile][e - (e / kTile) * kTile] = pr[k];
     }
-    __syncthreads();
+  };
+  fetch(0);
+  put();
+  __syncthreads();
+  for (int t0 = 0; t0 < d; t0 += kTk) {
+    const bool more = t0 + kTk < d;
+    if (more) fetch(t0 + kTk);
     const int tend = min(kTk, d - t0);
     for (int tt = 0; tt < tend; ++tt) {
-      const float4 xv = *reinterpret_cast<const float4*>(&xs[tt][tr * 4]);
-      const double xa[4] = {(double)xv.x, (double)xv.y, (double)xv.z, (double)xv.w};
-      double ra[4];
+      double xa[4], ra[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) xa[i] = (double)xs[tt][tr * 4 + i];
 #pragma unroll
       for (int j = 0; j < 4; ++j) ra[j] = rs[tt][tc * 4 + j];
 #pragma unroll
@@ -80,6 +99,10 @@ __global__ __launch_bounds__(kThreads) void k_rotate(const float* __restrict__ x
         for (int j = 0; j < 4; ++j) acc[i][j] = acc[i][j] + xa[i] * ra[j];   // unfused: rounded product, rounded sum
     }
     __syncthreads();
+    if (more) {
+      put();
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
