@@ -26,6 +26,8 @@ constexpr int kTile = 64;      // output tile edge (rows x columns)
 constexpr int kTk = 32;        // reduction depth staged per step
 constexpr int kThreads = 256;  // 16 x 16 threads, 4 x 4 outputs each
 typedef double XsT;            // x staged in LDS as float64: converted once per block, not per use
+constexpr int kRotR = 4;       // rows per thread of the rotation (16 x kRotR rows per block; 8 measured slower)
+constexpr int kRotRows = 16 * kRotR;
 
 // Block (row tile, column tile) of y = x R.  XCD-aware: consecutive column
 // tiles of one row tile go to one XCD (blocks b, b + 8, ...) so that the row
@@ -33,7 +35,7 @@ typedef double XsT;            // x staged in LDS as float64: converted once per
 __global__ __launch_bounds__(kThreads) void k_rotate(const float* __restrict__ x, int64_t n, int d,
                                                      const double* __restrict__ r, float* __restrict__ y,
                                                      int ctiles, int64_t nblocks) {
-  __shared__ __align__(16) XsT xs[kTk][kTile + 4];      // x tile, transposed: xs[t][row]
+  __shared__ __align__(16) XsT xs[kTk][kRotRows + 4];   // x tile, transposed: xs[t][row]
   __shared__ __align__(16) double rs[kTk][kTile + 2];  // R tile: rs[t][col]
   // logical block -> (row tile, column tile)
   const int64_t b = blockIdx.x;
@@ -43,40 +45,49 @@ __global__ __launch_bounds__(kThreads) void k_rotate(const float* __restrict__ x
   if (lb >= nblocks) return;
   const int64_t rt = lb / ctiles;
   const int ct = (int)(lb - rt * ctiles);
-  const int64_t row0 = rt * kTile;
+  const int64_t row0 = rt * kRotRows;
   const int col0 = ct * kTile;
   const int tid = threadIdx.x;
   const int tc = tid & 15, tr = tid >> 4;
-  double acc[4][4];
+  double acc[kRotR][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < kRotR; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
 
-  // staging of x[row0 .. +64][t0 .. +32] (transposed) and R[t0 .. +32][col0 ..
-  // +64]: the next step's elements are loaded into registers while the current
-  // step is computed
-  constexpr int PE = kTile * kTk / kThreads;   // elements of each tile per thread
-  float px[PE];
-  double pr[PE];
+  // staging of x[row0 .. +kRotRows][t0 .. +32] (transposed) and R[t0 .. +32]
+  // [col0 .. +64]: the next step's elements are loaded into registers while
+  // the current step is computed
+  constexpr int PX = kRotRows * kTk / kThreads;   // x elements per thread
+  constexpr int PR = kTile * kTk / kThreads;      // R elements per thread
+  float px[PX];
+  double pr[PR];
   auto fetch = [&](int t0) {
 #pragma unroll
-    for (int k = 0; k < PE; ++k) {
+    for (int k = 0; k < PX; ++k) {
       const int e = tid + k * kThreads;
       const int rr = e / kTk, tt = e - rr * kTk;
       const int64_t row = row0 + rr;
       const int t = t0 + tt;
       px[k] = (row < n && t < d) ? x[row * d + t] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < PR; ++k) {
+      const int e = tid + k * kThreads;
       const int t2 = t0 + e / kTile, col = col0 + (e - (e / kTile) * kTile);
       pr[k] = (t2 < d && col < d) ? r[(int64_t)t2 * d + col] : 0.0;
     }
   };
   auto put = [&]() {
 #pragma unroll
-    for (int k = 0; k < PE; ++k) {
+    for (int k = 0; k < PX; ++k) {
       const int e = tid + k * kThreads;
       const int rr = e / kTk;
       xs[e - rr * kTk][rr] = (XsT)px[k];
+    }
+#pragma unroll
+    for (int k = 0; k < PR; ++k) {
+      const int e = tid + k * kThreads;
       rs[e / kTile][e - (e / kTile) * kTile] = pr[k];
     }
   };
@@ -88,13 +99,13 @@ __global__ __launch_bounds__(kThreads) void k_rotate(const float* __restrict__ x
     if (more) fetch(t0 + kTk);
     const int tend = min(kTk, d - t0);
     for (int tt = 0; tt < tend; ++tt) {
-      double xa[4], ra[4];
+      double xa[kRotR], ra[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) xa[i] = (double)xs[tt][tr * 4 + i];
+      for (int i = 0; i < kRotR; ++i) xa[i] = (double)xs[tt][tr * kRotR + i];
 #pragma unroll
       for (int j = 0; j < 4; ++j) ra[j] = rs[tt][tc * 4 + j];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < kRotR; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = acc[i][j] + xa[i] * ra[j];   // unfused: rounded product, rounded sum
     }
@@ -105,8 +116,8 @@ __global__ __launch_bounds__(kThreads) void k_rotate(const float* __restrict__ x
     }
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t row = row0 + tr * 4 + i;
+  for (int i = 0; i < kRotR; ++i) {
+    const int64_t row = row0 + tr * kRotR + i;
     if (row >= n) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -538,7 +549,7 @@ __global__ __launch_bounds__(kPolarThreads) void k_polar(const double* __restric
 int launch_rotate(const float* x, int64_t n, int d, const double* r, float* y, hipStream_t s) {
   if (n == 0) return MIPQ_OK;
   const int ctiles = (d + kTile - 1) / kTile;
-  const int64_t rtiles = (n + kTile - 1) / kTile;
+  const int64_t rtiles = (n + kRotRows - 1) / kRotRows;
   const int64_t nblocks = rtiles * ctiles;
   const int64_t grid = ((nblocks + 7) / 8) * 8;
   if (grid > 0x7fffffff) return fail(MIPQ_EUNSUPPORTED, "too many rows for one rotation launch");
