@@ -529,6 +529,33 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
   // a row needs it (the rows of distant lists mostly never do)
   build_lut(0, (m16 ? kScanPre : m) * ks);
   __syncthreads();
+  // M = 16: a lower bound of every row's partial sum, from the smallest entry
+  // of each of the first kScanPre table rows summed in the same order (float
+  // addition is monotone); once the bound's score is below it, no row of the
+  // list can be inserted and the list is left
+  __shared__ float lb_w[kScanPre][kT / 64];
+  __shared__ uint32_t lb_bits;
+  if (m16) {
+#pragma unroll
+    for (int u = 0; u < kScanPre; ++u) {
+      float v = (int)threadIdx.x < ks ? lut[u * ks + threadIdx.x] : INFINITY;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+      if ((threadIdx.x & 63) == 0) lb_w[u][threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float lb = 0.0f;
+#pragma unroll
+      for (int u = 0; u < kScanPre; ++u) {
+        float mu = lb_w[u][0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) mu = fminf(mu, lb_w[u][w]);
+        lb = (u == 0) ? mu : lb + mu;
+      }
+      lb_bits = __float_as_uint(lb);
+    }
+    __syncthreads();
+  }
   // each step takes kScanRows rows per thread (rows p0 + r * kT + thread), so
   // that their loads are in flight together; room for a whole step of keys is
   // kept free in the buffer
@@ -571,6 +598,7 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
     for (int64_t p0 = a; p0 < b; p0 += kScanBatch, ++step) {
       const uint64_t tl = thr;
       const uint32_t tb = (uint32_t)(tl >> 32);   // score bits of the bound
+      if (tb != 0xFFFFFFFFu && lb_bits > tb) break;   // block-uniform: no row can be inserted
       const uint64_t ext = ext_load();
       // the code rows two steps ahead, in flight while this step is scored
       uint4 nx[kScanRows];
