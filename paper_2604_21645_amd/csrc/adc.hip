@@ -317,7 +317,10 @@ constexpr int kScanBatch = kScanRows * kT;
 // entries are non-negative and the float32 sum runs in a fixed order, so it
 // never decreases, and a row whose partial sum is already above the bound
 // cannot be inserted.  The other rows are finished from a per-wave queue.
-constexpr int kScanPre = 3;
+constexpr int kScanPre = 4;
+// table rows built before the scan (M = 16): they also give the list's lower bound
+constexpr int kLutPre = 8;
+static_assert(kScanPre <= kLutPre && kLutPre <= 16, "partial sums use built table rows");
 
 // Ascending sort of buf[0, n), any n: a bitonic network in the form where
 // every comparator is ascending (each merge first compares mirrored
@@ -525,19 +528,19 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
       lut[e] = sqdist_fixed<DS>(rq + j * DS, pq + ((int64_t)j * ks + k) * DS);
     }
   };
-  // M = 16 rows: the table of the first kScanPre subspaces now, the rest once
+  // M = 16 rows: the table of the first kLutPre subspaces now, the rest once
   // a row needs it (the rows of distant lists mostly never do)
-  build_lut(0, (m16 ? kScanPre : m) * ks);
+  build_lut(0, (m16 ? kLutPre : m) * ks);
   __syncthreads();
   // M = 16: a lower bound of every row's partial sum, from the smallest entry
-  // of each of the first kScanPre table rows summed in the same order (float
+  // of each of the first kLutPre table rows summed in the same order (float
   // addition is monotone); once the bound's score is below it, no row of the
   // list can be inserted and the list is left
-  __shared__ float lb_w[kScanPre][kT / 64];
+  __shared__ float lb_w[kLutPre][kT / 64];
   __shared__ uint32_t lb_bits;
   if (m16) {
 #pragma unroll
-    for (int u = 0; u < kScanPre; ++u) {
+    for (int u = 0; u < kLutPre; ++u) {
       float v = (int)threadIdx.x < ks ? lut[u * ks + threadIdx.x] : INFINITY;
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
@@ -547,7 +550,7 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
     if (threadIdx.x == 0) {
       float lb = 0.0f;
 #pragma unroll
-      for (int u = 0; u < kScanPre; ++u) {
+      for (int u = 0; u < kLutPre; ++u) {
         float mu = lb_w[u][0];
         for (int w = 1; w < (int)(blockDim.x >> 6); ++w) mu = fminf(mu, lb_w[u][w]);
         lb = (u == 0) ? mu : lb + mu;
@@ -624,7 +627,7 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
           if (lane == 0 && nq_w > 0) need = step + 1;
           __syncthreads();
           if (need == step + 1) {
-            build_lut(kScanPre * ks, m * ks);
+            build_lut(kLutPre * ks, m * ks);
             __syncthreads();
             full = true;
           }
@@ -637,7 +640,7 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
         }
       } else {   // no bound yet: every row is summed in full
         if (!full) {
-          build_lut(kScanPre * ks, m * ks);
+          build_lut(kLutPre * ks, m * ks);
           __syncthreads();
           full = true;
         }
