@@ -200,13 +200,31 @@ __global__ __launch_bounds__(kT) void k_adc_probe(const float* __restrict__ q, i
   __syncthreads();
   float xs = 0.0f;
   for (int i = 0; i < (int)(blockDim.x >> 6); ++i) xs += red[i];
+  // the thread's estimates l = tid + i * kT, held in registers when Kc fits
+  constexpr int kEstRegs = 16;
+  const bool in_regs = kc <= kEstRegs * kT;   // block-uniform
+  uint32_t ek[kEstRegs];
+  if (in_regs) {
+#pragma unroll
+    for (int i = 0; i < kEstRegs; ++i) {
+      const int l = threadIdx.x + i * kT;
+      ek[i] = l < kc ? fkey(er[l]) : 0xFFFFFFFFu;
+    }
+  }
   for (int shift = 24; shift >= 0; shift -= 8) {
     hist[threadIdx.x] = 0u;
     __syncthreads();
     const uint32_t pmask = shift == 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
-    for (int l = threadIdx.x; l < kc; l += blockDim.x) {
-      const uint32_t k = fkey(er[l]);
-      if ((k & pmask) == sel_prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+    const uint32_t pre = sel_prefix;
+    if (in_regs) {
+#pragma unroll
+      for (int i = 0; i < kEstRegs; ++i)
+        if (threadIdx.x + i * kT < kc && (ek[i] & pmask) == pre) atomicAdd(&hist[(ek[i] >> shift) & 255u], 1u);
+    } else {
+      for (int l = threadIdx.x; l < kc; l += blockDim.x) {
+        const uint32_t k = fkey(er[l]);
+        if ((k & pmask) == pre) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+      }
     }
     __syncthreads();
     // the digit: the first bin whose running count reaches sel_need (the
@@ -241,12 +259,27 @@ __global__ __launch_bounds__(kT) void k_adc_probe(const float* __restrict__ q, i
   const float cm = __uint_as_float(*cmax_bits);
   const float beta = e_cross * sqrtf(xs) * 1.0001f * cm + e_norm * (cm * cm + xs);
   const float lim = T + 2.0f * beta + g_exact * (2.0f * fabsf(T) + 4.0f * beta + 2.0f * xs * g_exact);
-  // band members, re-scored with the exact rule
+  // band members: listed first, then re-scored with the exact rule one per
+  // thread, so that the lanes of a wave run their exact sums together
   bool overflow = false;
-  for (int l = threadIdx.x; l < kc; l += blockDim.x) {
-    if (!(er[l] <= lim)) continue;
+  auto add_member = [&](int l) {
     const int p = atomicAdd(&nband, 1);
-    if (p < kBandMax) band[p] = DK{coarse_exact(qs, cc + (int64_t)l * d, d, vec), l};
+    if (p < kBandMax) band[p].l = l;
+  };
+  if (in_regs) {
+#pragma unroll
+    for (int i = 0; i < kEstRegs; ++i) {
+      const int l = threadIdx.x + i * kT;
+      if (l < kc && er[l] <= lim) add_member(l);
+    }
+  } else {
+    for (int l = threadIdx.x; l < kc; l += blockDim.x)
+      if (er[l] <= lim) add_member(l);
+  }
+  __syncthreads();
+  {
+    const int nm = nband < kBandMax ? nband : kBandMax;
+    for (int i = threadIdx.x; i < nm; i += blockDim.x) band[i].d = coarse_exact(qs, cc + (int64_t)band[i].l * d, d, vec);
   }
   __syncthreads();
   int nb = nband;
