@@ -555,25 +555,24 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
   }
   for (int t = threadIdx.x; t < d; t += blockDim.x) rq[t] = qr[t] - cc[(int64_t)l * d + t];
   __syncthreads();
-  auto build_lut = [&](int e0, int e1) {
-    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-      const int j = e / ks, k = e - j * ks;
-      lut[e] = sqdist_fixed<DS>(rq + j * DS, pq + ((int64_t)j * ks + k) * DS);
-    }
+  // table rows of subspaces [j0, j1)
+  auto build_lut = [&](int j0, int j1) {
+    for (int j = j0; j < j1; ++j)
+      for (int k = threadIdx.x; k < ks; k += blockDim.x)
+        lut[j * ks + k] = sqdist_fixed<DS>(rq + j * DS, pq + ((int64_t)j * ks + k) * DS);
   };
   // M = 16 rows: the table of the first kLutPre subspaces now, the rest once
-  // a row needs it (the rows of distant lists mostly never do)
-  build_lut(0, (m16 ? kLutPre : m) * ks);
-  __syncthreads();
-  // M = 16: a lower bound of every row's partial sum, from the smallest entry
-  // of each of the first kLutPre table rows summed in the same order (float
-  // addition is monotone); once the bound's score is below it, no row of the
-  // list can be inserted and the list is left
+  // a row needs it (the rows of distant lists mostly never do).
+  // A lower bound of every row's running sum over those subspaces: the
+  // smallest entry of each table row, summed in the same order (float
+  // addition is monotone).  Once the score of the query's bound is below it,
+  // no row of the list can be inserted and the list is left.  The bound over
+  // the first half of the rows is checked before the second half is built.
   __shared__ float lb_w[kLutPre][kT / 64];
+  __shared__ float lb_run;
   __shared__ uint32_t lb_bits;
-  if (m16) {
-#pragma unroll
-    for (int u = 0; u < kLutPre; ++u) {
+  auto bound_rows = [&](int j0, int j1) {   // lb_run += the minima of rows [j0, j1), in order
+    for (int u = j0; u < j1; ++u) {
       float v = (int)threadIdx.x < ks ? lut[u * ks + threadIdx.x] : INFINITY;
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
@@ -581,15 +580,32 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      float lb = 0.0f;
-#pragma unroll
-      for (int u = 0; u < kLutPre; ++u) {
+      float lb = lb_run;
+      for (int u = j0; u < j1; ++u) {
         float mu = lb_w[u][0];
         for (int w = 1; w < (int)(blockDim.x >> 6); ++w) mu = fminf(mu, lb_w[u][w]);
         lb = (u == 0) ? mu : lb + mu;
       }
+      lb_run = lb;
       lb_bits = __float_as_uint(lb);
     }
+    __syncthreads();
+  };
+  if (m16) {
+    constexpr int kHalf = kLutPre / 2;
+    build_lut(0, kHalf);
+    __syncthreads();
+    bound_rows(0, kHalf);
+    const uint32_t tb0 = (uint32_t)(thr >> 32);
+    if (tb0 != 0xFFFFFFFFu && lb_bits > tb0) {   // block-uniform: the list is left
+      for (int i = threadIdx.x; i < topk; i += blockDim.x) outp[i] = ~0ull;
+      return;
+    }
+    build_lut(kHalf, kLutPre);
+    __syncthreads();
+    bound_rows(kHalf, kLutPre);
+  } else {
+    build_lut(0, m);
     __syncthreads();
   }
   // each step takes kScanRows rows per thread (rows p0 + r * kT + thread), so
@@ -660,7 +676,7 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
           if (lane == 0 && nq_w > 0) need = step + 1;
           __syncthreads();
           if (need == step + 1) {
-            build_lut(kLutPre * ks, m * ks);
+            build_lut(kLutPre, m);
             __syncthreads();
             full = true;
           }
@@ -673,7 +689,7 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
         }
       } else {   // no bound yet: every row is summed in full
         if (!full) {
-          build_lut(kLutPre * ks, m * ks);
+          build_lut(kLutPre, m);
           __syncthreads();
           full = true;
         }
