@@ -49,7 +49,6 @@ __device__ __forceinline__ void store_pack(uint4* dst, const Pack8& p) {
 // nullptr for a padded centroid) centred by mu; cn: its float64 centred norm.
 template <int NB>
 __device__ __forceinline__ Pack8 slot_value(const float* ck, const float* mu, int ds, int f, int half, double& cn) {
-  constexpr int NMF = bf16_nmfma(NB);
   constexpr int DW = NB * 8;
   const bool real = ck != nullptr;
   float hv[DW], lv[DW];
