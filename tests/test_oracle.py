@@ -75,6 +75,31 @@ def test_assign_ties_go_to_lowest_index():
         assert tie[:, 0].tolist() == [True, True]
 
 
+
+def test_near_tie_threshold_is_relative_to_the_best_distance():
+    # tie iff d2 - d1 <= 1e-5 * d1 for the two smallest distances d1 <= d2,
+    # wherever they sit in the row
+    d1 = 1024.0
+    rows = [
+        ([5.0e3, d1 * (1 + 0.9e-5), 9.0e3, d1], True),    # inside the band
+        ([d1, 7.0e3, d1 * (1 + 1.1e-5)], False),           # outside the band
+        ([d1 * (1 - 0.9e-5), d1], True),                   # runner-up first, best second
+        ([d1, d1 * (1 - 1.1e-5)], False),
+        # relative to d1, not d2: a gap of 1.000005e-5 d1 is within 1e-5 d2
+        ([d1, d1 * (1 + 1.000005e-5)], False),
+        # relative, not absolute: a gap of 5e-6 relative is 0.005 absolute
+        ([1000.0, 1000.005], True),
+        ([1e-3, 1e-3 + 2e-8], False),
+        ([0.0, 0.0, 4.0], True),                            # duplicate zero distances
+        ([3.0, 0.0, 1e-300], False),                        # d1 = 0 < d2
+        ([2.0, 2.0], True),                                 # exact tie
+    ]
+    for vals, want in rows:
+        got = pq.near_tie_mask(np.array([vals], np.float64))[0]
+        assert bool(got) == want, (vals, want)
+    # one candidate has no runner-up
+    assert not pq.near_tie_mask(np.array([[1.0]]))[0]
+
 def test_assign_matches_scipy_vq():
     x = _rand(2, 300, 16)
     cb = _rand(3, 4 * 20, 4).reshape(4, 20, 4).astype(np.float64)
@@ -330,6 +355,80 @@ def test_adc_exhaustive_probe_equals_brute_force_topk():
         assert np.all(np.diff(dist[qi]) >= 0)
 
 
+
+def _line_index():
+    """Six lists with centroids at x = 0, 10, ..., 50 on the first axis; list l
+    holds rows 2l (residual code 0 = (0, 0)) and 2l + 1 (code 1 = (0, 1))."""
+    cc = np.array([[10.0 * l, 0.0] for l in range(6)], np.float32)
+    pcb = np.array([[[0.0, 0.0], [0.0, 1.0]]], np.float32)     # m = 1, ks = 2, ds = 2
+    offsets = np.arange(0, 13, 2, dtype=np.int64)
+    ids = np.arange(12, dtype=np.int64)
+    codes = (ids % 2).reshape(12, 1)
+    return cc, pcb, offsets, ids, codes
+
+
+@pytest.mark.parametrize("decide", ["kernel", "fp64"])
+def test_adc_probes_the_nearest_lists_with_ties_to_the_lower_list(decide):
+    cc, pcb, off, ids, codes = _line_index()
+    q = np.array([[30.0, 0.0], [25.0, 0.0]], np.float32)
+    # query 0: list distances 900, 400, 100, 0, 100, 400 -> lists 3 then 2
+    # (2 and 4 tie at the boundary; the lower list wins)
+    # query 1: 625, 225, 25, 25, 225, 625 -> list 2 alone at nprobe = 1
+    got_ids, got_d = ivf.adc_search(q, cc, pcb, off, ids, codes, nprobe=2, topk=6, decide=decide)
+    np.testing.assert_array_equal(got_ids[0], [6, 7, 4, 5, -1, -1])
+    np.testing.assert_array_equal(got_d[0], [0.0, 1.0, 100.0, 101.0, np.inf, np.inf])
+    np.testing.assert_array_equal(got_ids[1], [4, 6, 5, 7, -1, -1])
+    np.testing.assert_array_equal(got_d[1], [25.0, 25.0, 26.0, 26.0, np.inf, np.inf])
+    got_ids, got_d = ivf.adc_search(q, cc, pcb, off, ids, codes, nprobe=1, topk=3, decide=decide)
+    np.testing.assert_array_equal(got_ids, [[6, 7, -1], [4, 5, -1]])
+    # query 0 at nprobe = 3 takes lists 3, 2 and 4: equal scores order by id
+    got_ids, got_d = ivf.adc_search(q[:1], cc, pcb, off, ids, codes, nprobe=3, topk=6, decide=decide)
+    np.testing.assert_array_equal(got_ids[0], [6, 7, 4, 8, 5, 9])
+    np.testing.assert_array_equal(got_d[0], [0.0, 1.0, 100.0, 100.0, 101.0, 101.0])
+    # query 1 at nprobe = 3: lists 2 and 3 (tied), then 1 (1 and 4 tie)
+    got_ids, _ = ivf.adc_search(q[1:], cc, pcb, off, ids, codes, nprobe=3, topk=12, decide=decide)
+    assert set(got_ids[0][got_ids[0] >= 0]) == {2, 3, 4, 5, 6, 7}
+
+
+def test_adc_probe_selection_matches_brute_force_below_full_probing():
+    # nprobe < Kc on a real index: the probed lists are the nprobe smallest
+    # (distance, list) pairs of a plain Python sort, and the results are the
+    # brute-force top-k over the decoded rows of exactly those lists
+    w, idx = _small_index()
+    cc32 = idx["coarse"].astype(np.float32)
+    pcb = idx["pq"].astype(np.float32)
+    kc, nprobe, topk = cc32.shape[0], 5, 20
+    got_ids, got_d = ivf.adc_search(w.queries, cc32, pcb, idx["offsets"], idx["ids"], idx["codes"],
+                                    nprobe=nprobe, topk=topk, decide="fp64")
+    xhat = cc32.astype(np.float64)[idx["labels"]] + pq.decode(idx["codes"], pcb)
+    checked = 0
+    for qi in range(w.queries.shape[0]):
+        qv = [float(v) for v in w.queries[qi]]
+        dl = []
+        for l in range(kc):
+            acc = 0.0
+            for t in range(len(qv)):
+                diff = qv[t] - float(cc32[l, t])
+                acc += diff * diff
+            dl.append((acc, l))
+        dl.sort()
+        if dl[nprobe][0] - dl[nprobe - 1][0] <= 1e-9 * dl[nprobe][0]:
+            continue   # a near-tie at the probe boundary
+        probed = {l for _, l in dl[:nprobe]}
+        rows = [i for i in range(len(idx["labels"])) if idx["labels"][i] in probed]
+        assert set(got_ids[qi][got_ids[qi] >= 0]) <= set(rows)
+        score = {i: float(((w.queries[qi].astype(np.float64) - xhat[i]) ** 2).sum()) for i in rows}
+        want = sorted((score[i], i) for i in rows)[:topk]
+        gi = got_ids[qi][:len(want)]
+        np.testing.assert_allclose(got_d[qi][:len(want)], [v for v, _ in want], rtol=1e-9)
+        # every returned id carries its own brute-force score ...
+        np.testing.assert_allclose([score[int(i)] for i in gi], got_d[qi][:len(want)], rtol=1e-9)
+        # ... and the ids clearly inside the top-k are exactly the brute-force ones
+        edge = want[-1][0] * (1 - 1e-9)
+        assert {i for v, i in want if v < edge} == {int(i) for i in gi if score[int(i)] < edge}
+        checked += 1
+    assert checked >= 8
+
 def test_adc_kernel_mode_sorted_and_close_to_fp64():
     w, idx = _small_index()
     cc32 = idx["coarse"].astype(np.float32)
@@ -430,6 +529,27 @@ def test_rotation_by_a_permutation_and_identity_is_exact():
     np.testing.assert_array_equal(opq.rotate(x, p), x[:, perm])
     np.testing.assert_array_equal(opq.rotate(x, np.eye(24)), x)
 
+
+
+def test_rotation_sums_products_in_ascending_order_without_fusion():
+    # Hand-worked values where the summation order and fusion change the
+    # result.  Order: 1 + 2^-60 rounds to 1, so ascending t gives
+    # ((1 + 2^-60) - 1) + 2^-60 = 2^-60, while descending t or pairwise
+    # sums give 0.
+    x = np.array([[1.0, 2.0 ** -60, -1.0, 2.0 ** -60]], np.float32)
+    assert opq.rotate(x, np.ones((4, 1)))[0, 0] == np.float32(2.0 ** -60)
+    # Fusion: with a = 1 + 2^-23 and r = 1 + 2^-52, fl64(a r) = 1 + 2^-23 + 2^-52
+    # (the 2^-75 term is lost), so the separately rounded a r - a r is exactly
+    # 0; a fused multiply-add of the second term would leave -2^-75.
+    a = np.float32(1.0 + 2.0 ** -23)
+    r = 1.0 + 2.0 ** -52
+    y = opq.rotate(np.array([[a, -a]], np.float32), np.array([[r, 1.0], [r, 1.0]]))
+    assert y[0, 0] == 0.0 and not np.signbit(y[0, 0])
+    assert y[0, 1] == 0.0
+    # One rounding to float32 at the end: 1 + 3 * 2^-25 (exact in float64)
+    # rounds to 1 + 2^-23, whereas float32 partial sums would stay at 1.
+    z = opq.rotate(np.array([[1.0, 2.0 ** -25, 2.0 ** -25, 2.0 ** -25]], np.float32), np.ones((4, 1)))
+    assert z[0, 0] == np.float32(1.0 + 2.0 ** -23)
 
 def test_procrustes_recovers_a_known_rotation():
     x = _rand(32, 500, 16).astype(np.float64)
