@@ -103,6 +103,22 @@ def measured_traffic(traffic_file: str = TRAFFIC_FILE, source: str = MFMA_SOURCE
     return t.get("bytes_per_launch")
 
 
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_assign_bf16_integer_pq_1M_counters.json")
+
+
+def measured_counters(counters_file: str = COUNTERS_FILE, source: str = MFMA_SOURCE):
+    """VALU and MFMA busy fractions of a kernel from a committed rocprofv3
+    counter record (the step's launch mix), or None if absent or stale."""
+    try:
+        with open(counters_file) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash(source):
+        return None
+    return t.get("step_mix")
+
+
 def cpu_baseline(w, frac: float):
     """The oracle, as it stands, on a bounded sample of the same workload:
     fit on frac * n_train training rows (same rounds), encode frac * N rows."""
@@ -278,6 +294,7 @@ def bench_integer_pq(args) -> dict:
         base = cpu_baseline(w, args.cpu_frac)
 
     traffic = measured_traffic()
+    counters = measured_counters()
     res = {
         "metric": "PQ fit+encode vectors/s, BF16-MFMA vs FP32 plain, % codes equal to oracle",
         "value": n / (ms * 1e-3),
@@ -312,6 +329,8 @@ def bench_integer_pq(args) -> dict:
             "alg_bytes_per_launch": alg_bytes_per_launch,
             "avg_launch_ms": avg_launch_ms,
             "launches": nl.value,
+            "valu_frac": (counters or {}).get("valu_busy"),
+            "mfma_util": (counters or {}).get("mfma_busy"),
         },
         "kernels_ms_per_step": {k: v[1] / prof_steps for k, v in kernel_stats.items()},
         "cpu_baseline": base,
@@ -815,8 +834,55 @@ def bench_opq(args) -> dict:
     return rec
 
 
+PUBLISHED = {   # per-launch rates the roofline fractions are quoted against
+    "add_f32": ("T lane-ops/s", 256 * 4 * 16 * 2.4e9 / 1e12),
+    "fma_f32": ("T lane-ops/s", 256 * 4 * 16 * 2.4e9 / 1e12),
+    "min3_f32": ("T lane-ops/s", 256 * 4 * 16 * 2.4e9 / 1e12),
+    "fma_f64": ("T lane-ops/s", 256 * 4 * 16 * 2.4e9 / 1e12),
+    "mfma_bf16": ("TFLOP/s", 2500.0),
+    "mfma_f8": ("TFLOP/s", 5000.0),
+    "copy": ("GB/s", PEAK_HBM_GBS),
+}
+
+
+def bench_peaks(args) -> dict:
+    """What one launch of each instruction kind sustains on this device
+    (mipq_peak_probe), beside the unit-count or published figure it checks."""
+    import torch
+
+    import paper_2604_21645_amd as mipq
+
+    dev = torch.device("cuda:0")
+    blocks = 256 * 8   # 8 blocks of 4 waves per CU: 8 waves per SIMD
+    buf = torch.empty(blocks * 256 * 8, dtype=torch.uint8, device=dev)
+    big = torch.empty(2 << 30, dtype=torch.uint8, device=dev)   # 1 GiB copied within 2 GiB
+    rates = {}
+    for kind, (unit, pub) in PUBLISHED.items():
+        b, t = (big, 256 * 64) if kind == "copy" else (buf, blocks)
+        work = mipq.peak_probe(kind, t, b)   # warm-up
+        best = float("inf")
+        for _ in range(max(args.steps, 3)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            mipq.peak_probe(kind, t, b)
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        scale = 1e9 if unit == "GB/s" else 1e12
+        got = work / (best * 1e-3) / scale
+        rates[kind] = {"measured": got, "unit": unit, "derived_or_published": pub, "frac": got / pub,
+                       "ms": best}
+        log("%-10s %10.2f %s (%.3f of %.1f)" % (kind, got, unit, got / pub, pub))
+    rec = base_record("sustained issue rate of unpacked float32 adds (probe)", rates["add_f32"]["measured"],
+                      "T lane-ops/s", max(args.steps, 3), 1, rates["add_f32"]["ms"], "f32",
+                      {"workload": "peak probes: 2048 blocks x 256 threads, 8 chains x 2048 instructions "
+                                   "per lane; MFMA 4 accumulators x 512 per wave; copy 1 GiB"})
+    rec["probes"] = rates
+    return rec
+
+
 WORKLOADS = {"integer_pq": bench_integer_pq, "batched_uneven": bench_batched, "ivf_adc": bench_ivf,
-             "diff_codebooks": bench_diff, "soil_chunks": bench_soil, "opq": bench_opq}
+             "diff_codebooks": bench_diff, "soil_chunks": bench_soil, "opq": bench_opq, "peaks": bench_peaks}
 
 
 def main() -> int:

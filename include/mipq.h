@@ -420,6 +420,36 @@ enum mipq_kernel {
 int mipq_profile_enable(int on);
 int mipq_profile_collect(int kernel, int64_t* launches, double* total_ms);
 
+/* -------------------------------------------------------------------------
+ * Peak probes (measurement aid for the roofline fractions, not part of the
+ * method).
+ *
+ * mipq_peak_probe enqueues one launch of `blocks` work-groups of 256 threads
+ * that does nothing but one kind of work, so that its sustained rate can be
+ * timed by the caller (events on `stream`):
+ *   MIPQ_PROBE_ADD_F32 / FMA_F32 / MIN3_F32 / FMA_F64: 8 independent chains
+ *     of 2048 instructions per lane (v_add_f32, v_fma_f32, v_min3_f32,
+ *     v_fma_f64); work = lane instructions of the launch;
+ *   MIPQ_PROBE_MFMA_BF16 / MFMA_F8: four independent accumulators of 512
+ *     32x32x16 BF16 (32x32x64 E4M3) MFMAs per wave; work = flops;
+ *   MIPQ_PROBE_COPY: copies the first half of `out` onto its second half in
+ *     16-byte words; work = bytes read + written.
+ *   out        device buffer: >= blocks*256*8 bytes (its contents become
+ *              meaningless), or for MIPQ_PROBE_COPY the buffer to copy
+ *              within (16-byte aligned)
+ *   work       OUT optional host double: the work of one launch (above)
+ * ------------------------------------------------------------------------- */
+enum mipq_probe {
+  MIPQ_PROBE_ADD_F32 = 0,
+  MIPQ_PROBE_FMA_F32 = 1,
+  MIPQ_PROBE_MIN3_F32 = 2,
+  MIPQ_PROBE_FMA_F64 = 3,
+  MIPQ_PROBE_MFMA_BF16 = 4,
+  MIPQ_PROBE_MFMA_F8 = 5,
+  MIPQ_PROBE_COPY = 6
+};
+int mipq_peak_probe(int kind, int blocks, void* out, size_t out_bytes, double* work, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

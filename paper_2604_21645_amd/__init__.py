@@ -585,3 +585,18 @@ def decode_centroids(codebooks: torch.Tensor) -> torch.Tensor:
     out = torch.empty((nb * ks, m * ds), dtype=torch.float32, device=cb.device)
     check(lib().mipq_pq_decode_centroids(_ptr(cb), nb, m * ds, m, ks, _ptr(out), _stream(cb.device)))
     return out
+
+
+def peak_probe(kind: str, blocks: int, buf: torch.Tensor) -> float:
+    """Enqueue one probe launch (mipq_peak_probe) on the current stream of
+    buf's device; returns the work of the launch (lane instructions, flops or
+    bytes moved)."""
+    from ._lib import PROBES
+    if kind not in PROBES:
+        raise ValueError("unknown probe %r" % kind)
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("probe buffer must be a contiguous device tensor")
+    w = ctypes.c_double(0)
+    check(lib().mipq_peak_probe(PROBES[kind], int(blocks), _ptr(buf), buf.numel() * buf.element_size(),
+                                ctypes.byref(w), _stream(buf.device)))
+    return w.value

@@ -57,6 +57,7 @@ SIGNATURES = {
     "mipq_opq_procrustes": (_I, [_P, _P, _L, _I, _P, _P, _P, _P, _P, _P, _S, _P]),
     "mipq_profile_enable": (_I, [_I]),
     "mipq_profile_collect": (_I, [_I, ctypes.POINTER(_L), ctypes.POINTER(ctypes.c_double)]),
+    "mipq_peak_probe": (_I, [_I, _I, _P, _S, ctypes.POINTER(ctypes.c_double), _P]),
 }
 
 # kernel ids of mipq_profile_collect (enum mipq_kernel)
@@ -73,6 +74,9 @@ class MipqProblem(ctypes.Structure):
 
 
 PLAN_AUTOTUNE, PLAN_GRAPH = 1, 2
+
+# kinds of mipq_peak_probe (enum mipq_probe)
+PROBES = {"add_f32": 0, "fma_f32": 1, "min3_f32": 2, "fma_f64": 3, "mfma_bf16": 4, "mfma_f8": 5, "copy": 6}
 
 _lib = None
 

@@ -39,6 +39,8 @@ EXTRA = {
     # matrix-core results straight to VGPRs
     "ivf.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
     "adc.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    # the minimum chains of the issue-rate probe become v_min3_f32
+    "peaks.hip": ["-fno-honor-nans", "-mno-amdgpu-ieee", "-mllvm", "-amdgpu-mfma-vgpr-form"],
 }
 
 
