@@ -51,15 +51,34 @@
 extern "C" {
 #endif
 
-#define MIPQ_ABI_VERSION 1
+#define MIPQ_ABI_VERSION 2
 
 enum mipq_status {
   MIPQ_OK = 0,
   MIPQ_EINVAL = -1,       /* bad shape, null required pointer, bad enum */
   MIPQ_ENOMEM = -2,       /* workspace smaller than the *_workspace_size() query */
   MIPQ_EHIP = -3,         /* a HIP runtime call failed (text in mipq_last_error) */
-  MIPQ_EUNSUPPORTED = -4  /* valid request this build does not implement */
+  MIPQ_EUNSUPPORTED = -4, /* valid request this build does not implement */
+  MIPQ_ENONFINITE = -5    /* MIPQ_CHECK_FINITE found a NaN or infinite input value */
 };
+
+/* Call flags (bit set) of mipq_pq_fit and mipq_pq_encode.
+ *   MIPQ_CHECK_FINITE   before any other work, check that every input value
+ *       the call reads (the training or encoded rows, an initial codebook, the
+ *       codebook to encode with) is finite; if one is not, return
+ *       MIPQ_ENONFINITE with nothing written.  The check waits for `stream`
+ *       (the call is then synchronous up to the check).  Without the flag,
+ *       non-finite inputs give unspecified codes: the matrix-core paths
+ *       order NaN estimates differently from the float32 rule, in which a NaN
+ *       distance never wins, so a row with a NaN in a subspace gets code 0
+ *       there on the FP32 path and an arbitrary code on the others.
+ *   MIPQ_DETERMINISTIC  (mipq_pq_fit) the float64 centroid sums of a round
+ *       are formed in a fixed order (rows of each chunk by centroid, in row
+ *       order, chunks in order) instead of by atomic additions, so two runs
+ *       on the same inputs give bit-identical codebooks, labels and
+ *       objectives.  Slower; the sums may differ from the default mode's in
+ *       the last bits. */
+enum mipq_flags { MIPQ_CHECK_FINITE = 1, MIPQ_DETERMINISTIC = 2 };
 
 enum mipq_precision { MIPQ_FP32 = 0, MIPQ_BF16 = 1, MIPQ_FP8 = 2 };
 
@@ -94,28 +113,42 @@ const char* mipq_last_error(void);
  *   objective    OUT optional float64 [iters]: objective[t] = sum over rows,
  *                subspaces and dimensions of (x - c)^2 in float64, c the
  *                float32 centroid chosen in round t
+ *   rescored     OUT optional int64 [iters]: (row, subspace) pairs of round
+ *                t's assignment whose matrix-core ranking was not separated
+ *                by its error bound and were re-decided with the float32 rule
+ *                (0 for MIPQ_FP32)
+ *   flags        MIPQ_CHECK_FINITE, MIPQ_DETERMINISTIC (see mipq_flags)
  * Requirements: d % m == 0, d/m <= 16 (BF16, FP8) or <= 48 (FP32),
  * 1 <= ks <= 256, n_train >= 1, iters >= 0, init rows in range.
  * ------------------------------------------------------------------------- */
 size_t mipq_pq_fit_workspace_size(int64_t n_train, int d, int m, int ks, int iters, int precision);
 int mipq_pq_fit(const float* x, int64_t n, const int64_t* train_rows, int64_t n_train,
                 int d, int m, int ks, int iters,
-                const int64_t* init_rows, const float* init_codebook, int precision,
+                const int64_t* init_rows, const float* init_codebook, int precision, int flags,
                 float* codebook, double* codebook64, uint8_t* labels, double* objective,
-                void* ws, size_t ws_bytes, void* stream);
+                int64_t* rescored, void* ws, size_t ws_bytes, void* stream);
 
 /* -------------------------------------------------------------------------
  * Encode (paper Section 2.1: each row of each subspace is represented by
- * its nearest subspace centroid, so a row becomes m codes).
+ * its nearest subspace centroid, so a row becomes m codes; the paper's
+ * library also gives the distance of each item to its centroid).
  *
  *   codes     OUT uint8 [n][m]
+ *   min_dist  OUT optional float32 [n][m]: the float32-rule distance of the
+ *             subspace block of each row to its chosen centroid (the value
+ *             the code minimises)
+ *   sse_rmse  OUT optional float64 [2]: SSE and RMSE of the codes, exactly as
+ *             mipq_pq_decode_rmse defines them (float64 squares of the
+ *             float64 differences); the sum order differs, so the two agree
+ *             to float64 rounding, not bit for bit
  *   rescored  OUT optional int64 [1]: number of (row, subspace) pairs the
  *             BF16 path re-decided in FP32 arithmetic (0 for MIPQ_FP32)
+ *   flags     MIPQ_CHECK_FINITE (see mipq_flags)
  * ------------------------------------------------------------------------- */
 size_t mipq_pq_encode_workspace_size(int64_t n, int d, int m, int ks, int precision);
 int mipq_pq_encode(const float* x, int64_t n, int d, int m, int ks, const float* codebook,
-                   int precision, uint8_t* codes, int64_t* rescored,
-                   void* ws, size_t ws_bytes, void* stream);
+                   int precision, int flags, uint8_t* codes, float* min_dist, double* sse_rmse,
+                   int64_t* rescored, void* ws, size_t ws_bytes, void* stream);
 
 /* -------------------------------------------------------------------------
  * Decode and reconstruction error (paper Section 3: rows are encoded and
@@ -174,7 +207,10 @@ typedef struct mipq_problem {
  * mipq_plan_create waits for `stream`.  Graphs are replayed on whatever
  * stream mipq_pq_fit_batched is given. */
 typedef struct mipq_plan mipq_plan;
-enum mipq_plan_flags { MIPQ_PLAN_AUTOTUNE = 1, MIPQ_PLAN_GRAPH = 2 };
+/* MIPQ_PLAN_DETERMINISTIC: the float64 centroid sums in a fixed order, as
+ * MIPQ_DETERMINISTIC does for mipq_pq_fit (runs of the plan are then
+ * bit-identical). */
+enum mipq_plan_flags { MIPQ_PLAN_AUTOTUNE = 1, MIPQ_PLAN_GRAPH = 2, MIPQ_PLAN_DETERMINISTIC = 4 };
 
 /* n: host int64 [nprob], the rows of every problem. */
 size_t mipq_pq_fit_batched_workspace_size(const int64_t* n, int nprob, int d, int m, int ks, int iters,

@@ -12,7 +12,8 @@ import torch
 
 import ctypes
 
-from ._lib import PLAN_AUTOTUNE, PLAN_GRAPH, MipqError, MipqProblem, check, lib  # noqa: F401
+from ._lib import (CHECK_FINITE, DETERMINISTIC, ENONFINITE, PLAN_AUTOTUNE, PLAN_DETERMINISTIC,  # noqa: F401
+                   PLAN_GRAPH, MipqError, MipqProblem, check, lib)
 
 FP32, BF16, FP8 = 0, 1, 2
 _PREC = {"fp32": FP32, "bf16": BF16, "fp8": FP8, FP32: FP32, BF16: BF16, FP8: FP8}
@@ -50,12 +51,17 @@ def _ws(nbytes: int, device) -> torch.Tensor:
 def pq_fit(x: torch.Tensor, m: int, ks: int, iters: int, init_rows: torch.Tensor | None = None,
            init_codebook: torch.Tensor | None = None, train_rows: torch.Tensor | None = None,
            precision="bf16", labels: bool = True, codebook64: bool = False, objective: bool = True,
-           out: torch.Tensor | None = None):
+           out: torch.Tensor | None = None, rescored: bool = False, deterministic: bool = False,
+           check_finite: bool = False):
     """Fit per-subspace k-means codebooks (Lloyd, ``iters`` rounds).
 
     Returns a dict with ``codebook`` float32 [m, ks, d/m] (written into
     ``out`` when given) and, on request, ``labels`` uint8 [n_train, m] (last
-    assignment), ``codebook64`` and ``objective`` float64 [iters].
+    assignment), ``codebook64``, ``objective`` float64 [iters] and
+    ``rescored`` int64 [iters] (pairs re-decided by the float32 rule in each
+    round).  ``deterministic``: float64 sums in a fixed order (bit-identical
+    runs); ``check_finite``: raise MipqError (code ENONFINITE) on NaN or
+    infinite inputs.
     """
     L = lib()
     x = _dev(x, torch.float32, "x")
@@ -80,17 +86,24 @@ def pq_fit(x: torch.Tensor, m: int, ks: int, iters: int, init_rows: torch.Tensor
         res["codebook64"] = torch.empty((m, ks, ds), dtype=torch.float64, device=dev)
     if objective:
         res["objective"] = torch.empty(max(iters, 0), dtype=torch.float64, device=dev)
+    if rescored:
+        res["rescored"] = torch.empty(max(iters, 0), dtype=torch.int64, device=dev)
+    flags = (DETERMINISTIC if deterministic else 0) | (CHECK_FINITE if check_finite else 0)
     nbytes = L.mipq_pq_fit_workspace_size(n_train, d, m, ks, iters, p)
     ws = _ws(nbytes, dev)
-    check(L.mipq_pq_fit(_ptr(x), n, _ptr(tr), n_train, d, m, ks, iters, _ptr(ir), _ptr(ic), p,
+    check(L.mipq_pq_fit(_ptr(x), n, _ptr(tr), n_train, d, m, ks, iters, _ptr(ir), _ptr(ic), p, flags,
                         _ptr(res["codebook"]), _ptr(res.get("codebook64")), _ptr(res.get("labels")),
-                        _ptr(res.get("objective")), _ptr(ws), ws.numel(), _stream(dev)))
+                        _ptr(res.get("objective")), _ptr(res.get("rescored")), _ptr(ws), ws.numel(),
+                        _stream(dev)))
     return res
 
 
-def pq_encode(x: torch.Tensor, codebook: torch.Tensor, precision="bf16", rescored: bool = False):
-    """Codes uint8 [n, m]; with ``rescored=True`` also the int64 count of
-    (row, subspace) pairs the BF16 path re-decided in float32."""
+def pq_encode_ex(x: torch.Tensor, codebook: torch.Tensor, precision="bf16", min_dist: bool = False,
+                 sse_rmse: bool = False, rescored: bool = False, check_finite: bool = False) -> dict:
+    """Encode (mipq_pq_encode) with every optional output: a dict with
+    ``codes`` uint8 [n, m] and, on request, ``min_dist`` float32 [n, m] (the
+    float32-rule distance to the chosen centroid), ``sse_rmse`` float64 [2]
+    and ``rescored`` int64 [1]."""
     L = lib()
     x = _dev(x, torch.float32, "x")
     cb = _dev(codebook, torch.float32, "codebook")
@@ -100,12 +113,25 @@ def pq_encode(x: torch.Tensor, codebook: torch.Tensor, precision="bf16", rescore
     if m * ds != d:
         raise ValueError("codebook shape %s does not match d=%d" % (tuple(cb.shape), d))
     p = _prec(precision)
-    codes = torch.empty((n, m), dtype=torch.uint8, device=dev)
-    resc = torch.zeros(1, dtype=torch.int64, device=dev) if rescored else None
+    res = {"codes": torch.empty((n, m), dtype=torch.uint8, device=dev)}
+    if min_dist:
+        res["min_dist"] = torch.empty((n, m), dtype=torch.float32, device=dev)
+    if sse_rmse:
+        res["sse_rmse"] = torch.empty(2, dtype=torch.float64, device=dev)
+    if rescored:
+        res["rescored"] = torch.zeros(1, dtype=torch.int64, device=dev)
     ws = _ws(L.mipq_pq_encode_workspace_size(n, d, m, ks, p), dev)
-    check(L.mipq_pq_encode(_ptr(x), n, d, m, ks, _ptr(cb), p, _ptr(codes), _ptr(resc), _ptr(ws),
-                           ws.numel(), _stream(dev)))
-    return (codes, resc) if rescored else codes
+    check(L.mipq_pq_encode(_ptr(x), n, d, m, ks, _ptr(cb), p, CHECK_FINITE if check_finite else 0,
+                           _ptr(res["codes"]), _ptr(res.get("min_dist")), _ptr(res.get("sse_rmse")),
+                           _ptr(res.get("rescored")), _ptr(ws), ws.numel(), _stream(dev)))
+    return res
+
+
+def pq_encode(x: torch.Tensor, codebook: torch.Tensor, precision="bf16", rescored: bool = False):
+    """Codes uint8 [n, m]; with ``rescored=True`` also the int64 count of
+    (row, subspace) pairs the BF16 path re-decided in float32."""
+    r = pq_encode_ex(x, codebook, precision, rescored=rescored)
+    return (r["codes"], r["rescored"]) if rescored else r["codes"]
 
 
 def pq_decode_rmse(codes: torch.Tensor, codebook: torch.Tensor, x: torch.Tensor | None = None,
@@ -452,13 +478,15 @@ class BatchedFit:
     ``xs``: list of float32 [n_i, d] device tensors; ``init_rows``: list of
     int64 [m, ks] device tensors (rows of the matching x).  With ``plan`` the
     grid is fixed once (``autotune``: timed on the problems) and, with
-    ``graph``, the launches are replayed from HIP graphs.  ``run()`` fills
-    ``results[i]`` = dict(codebook, codes, sse_rmse, objective).
+    ``graph``, the launches are replayed from HIP graphs; ``deterministic``
+    forms the float64 centroid sums in a fixed order (needs a plan).
+    ``run()`` fills ``results[i]`` = dict(codebook, codes, sse_rmse,
+    objective).
     """
 
     def __init__(self, xs, init_rows, m: int, ks: int, iters: int, precision="bf16", plan: bool = True,
                  autotune: bool = True, graph: bool = True, objective: bool = True, sse: bool = True,
-                 codebooks: torch.Tensor | None = None):
+                 codebooks: torch.Tensor | None = None, deterministic: bool = False):
         L = lib()
         if len(xs) != len(init_rows) or not xs:
             raise ValueError("need one init_rows tensor per problem (and at least one problem)")
@@ -499,8 +527,11 @@ class BatchedFit:
                                         _stream(dev)))
         self.ws = _ws(nbytes, dev)
         self._plan = ctypes.c_void_p()
+        if deterministic and not plan:
+            raise ValueError("deterministic batched fits need a plan (plan=True)")
         if plan:
-            flags = (PLAN_AUTOTUNE if autotune else 0) | (PLAN_GRAPH if graph else 0)
+            flags = ((PLAN_AUTOTUNE if autotune else 0) | (PLAN_GRAPH if graph else 0) |
+                     (PLAN_DETERMINISTIC if deterministic else 0))
             check(L.mipq_plan_create(ctypes.byref(self._plan), table, len(self.xs), d, m, ks, iters, self.precision,
                                      flags, _ptr(self.ws), self.ws.numel(), _stream(dev)))
 

@@ -26,9 +26,9 @@ SIGNATURES = {
     "mipq_abi_version": (_I, []),
     "mipq_last_error": (ctypes.c_char_p, []),
     "mipq_pq_fit_workspace_size": (_S, [_L, _I, _I, _I, _I, _I]),
-    "mipq_pq_fit": (_I, [_P, _L, _P, _L, _I, _I, _I, _I, _P, _P, _I, _P, _P, _P, _P, _P, _S, _P]),
+    "mipq_pq_fit": (_I, [_P, _L, _P, _L, _I, _I, _I, _I, _P, _P, _I, _I, _P, _P, _P, _P, _P, _P, _S, _P]),
     "mipq_pq_encode_workspace_size": (_S, [_L, _I, _I, _I, _I]),
-    "mipq_pq_encode": (_I, [_P, _L, _I, _I, _I, _P, _I, _P, _P, _P, _S, _P]),
+    "mipq_pq_encode": (_I, [_P, _L, _I, _I, _I, _P, _I, _I, _P, _P, _P, _P, _P, _S, _P]),
     "mipq_pq_decode_rmse_workspace_size": (_S, [_L, _I, _I, _I]),
     "mipq_pq_decode_rmse": (_I, [_P, _L, _I, _I, _I, _P, _P, _P, _P, _P, _S, _P]),
     "mipq_pq_decode_centroids": (_I, [_P, _L, _I, _I, _I, _P, _P]),
@@ -73,7 +73,9 @@ class MipqProblem(ctypes.Structure):
                 ("sse_rmse", _P), ("objective", _P)]
 
 
-PLAN_AUTOTUNE, PLAN_GRAPH = 1, 2
+PLAN_AUTOTUNE, PLAN_GRAPH, PLAN_DETERMINISTIC = 1, 2, 4
+CHECK_FINITE, DETERMINISTIC = 1, 2   # call flags of pq_fit / pq_encode
+ENONFINITE = -5
 
 # kinds of mipq_peak_probe (enum mipq_probe)
 PROBES = {"add_f32": 0, "fma_f32": 1, "min3_f32": 2, "fma_f64": 3, "mfma_bf16": 4, "mfma_f8": 5, "copy": 6}

@@ -3,6 +3,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <initializer_list>
 #include <vector>
 
 #include "mipq_internal.h"
@@ -55,6 +56,24 @@ struct EncodeWs {
   size_t bytes = 0;
 };
 
+// flag word of the finite check and the squared-error partials of an encode
+struct EncodeExtraWs {
+  uint32_t* flag = nullptr;
+  double* partials = nullptr;
+  int nblk = 0;
+  size_t bytes = 0;
+};
+
+EncodeExtraWs carve_encode_extra(void* ws, int64_t n, int m) {
+  Carver c(ws);
+  EncodeExtraWs e;
+  e.flag = c.take<uint32_t>(4);
+  e.nblk = decode_blocks(n, m);
+  e.partials = c.take<double>(e.nblk);
+  e.bytes = c.bytes();
+  return e;
+}
+
 EncodeWs carve_encode(void* ws, int m, int ks, int ds, int precision) {
   Carver c(ws);
   EncodeWs e;
@@ -79,6 +98,7 @@ struct FitWs {
   double* part_j = nullptr;
   double* j_sub = nullptr;
   uint32_t* bad = nullptr;
+  uint32_t* flag = nullptr;
   int nch = 1;
   EncodeWs enc;
   size_t bytes = 0;
@@ -98,11 +118,35 @@ FitWs carve_fit(void* ws, int64_t n_train, bool gather, int d, int m, int ks, in
   f.part_j = c.take<double>((size_t)f.nch * m);
   f.j_sub = c.take<double>((size_t)(iters > 0 ? iters : 1) * m);
   f.bad = c.take<uint32_t>(4);
+  f.flag = c.take<uint32_t>(4);
   const size_t off = c.bytes();
   EncodeWs e = carve_encode(ws ? static_cast<char*>(ws) + off : nullptr, m, ks, ds, precision);
   f.enc = e;
   f.bytes = off + e.bytes;
   return f;
+}
+
+// MIPQ_CHECK_FINITE: flag |= 1 for any non-finite value of the arrays, then
+// wait for the stream and report
+struct FloatSpan {
+  const float* p;
+  size_t count;
+};
+int check_finite(std::initializer_list<FloatSpan> arrays, uint32_t* flag, hipStream_t s) {
+  int rc;
+  if ((rc = launch_zero_u32(flag, 1, s))) return rc;
+  for (const FloatSpan& a : arrays)
+    if (a.p && (rc = launch_nonfinite(a.p, a.count, flag, s))) return rc;
+  uint32_t h = 0;
+  MIPQ_HIP(hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, s));
+  MIPQ_HIP(hipStreamSynchronize(s));
+  if (h) return fail(MIPQ_ENONFINITE, "an input value is NaN or infinite");
+  return MIPQ_OK;
+}
+
+int check_flags(int flags, int allowed) {
+  if (flags & ~allowed) return fail(MIPQ_EINVAL, "unknown flags 0x%x", flags & ~allowed);
+  return MIPQ_OK;
 }
 
 int check_ws(void* ws, size_t have, size_t need) {
@@ -147,11 +191,12 @@ size_t mipq_pq_fit_workspace_size(int64_t n_train, int d, int m, int ks, int ite
 
 int mipq_pq_fit(const float* x, int64_t n, const int64_t* train_rows, int64_t n_train, int d, int m,
                 int ks, int iters, const int64_t* init_rows, const float* init_codebook,
-                int precision, float* codebook, double* codebook64, uint8_t* labels,
-                double* objective, void* ws, size_t ws_bytes, void* stream) {
+                int precision, int flags, float* codebook, double* codebook64, uint8_t* labels,
+                double* objective, int64_t* rescored, void* ws, size_t ws_bytes, void* stream) {
   int rc;
   const int64_t nt = train_rows ? n_train : n;
   if ((rc = check_shape(nt, d, m, ks, precision, true))) return rc;
+  if ((rc = check_flags(flags, MIPQ_CHECK_FINITE | MIPQ_DETERMINISTIC))) return rc;
   if (train_rows && (n < 1 || n_train < 1)) return fail(MIPQ_EINVAL, "empty row set");
   if (nt < 1) return fail(MIPQ_EINVAL, "fit needs at least one training row");
   if (iters < 0 || iters > (1 << 16)) return fail(MIPQ_EINVAL, "iters out of range (%d)", iters);
@@ -167,20 +212,28 @@ int mipq_pq_fit(const float* x, int64_t n, const int64_t* train_rows, int64_t n_
     if ((rc = launch_gather_rows(x, n, d, train_rows, n_train, f.xs, f.bad, s))) return rc;
     train = f.xs;
   }
+  if ((flags & MIPQ_CHECK_FINITE) &&
+      (rc = check_finite({{train, (size_t)nt * d}, {init_codebook, init_codebook ? (size_t)m * ks * ds : 0}},
+                         f.flag, s)))
+    return rc;
   uint8_t* codes = labels ? labels : f.codes;
   double* c64 = codebook64 ? codebook64 : f.c64;
   float* c32 = codebook;   // working float32 codebook, final value on return
+  if (rescored && (rc = launch_zero_u32(reinterpret_cast<uint32_t*>(rescored), 2 * (size_t)iters, s))) return rc;
   if ((rc = launch_init_codebook(train, nt, d, m, ks, init_codebook ? nullptr : init_rows, init_codebook,
                                  c64, c32, f.bad, nullptr, s)))
     return rc;
   const bool bf = precision == MIPQ_BF16;
+  const bool det = (flags & MIPQ_DETERMINISTIC) != 0;
   if (iters > 0 && (rc = pack_any(c32, m, ks, ds, precision, f.enc, s))) return rc;
   for (int it = 0; it < iters; ++it) {
-    if ((rc = assign_any(train, nt, d, m, ks, c32, precision, codes, f.enc, nullptr, s))) return rc;
+    if ((rc = assign_any(train, nt, d, m, ks, c32, precision, codes, f.enc, rescored ? rescored + it : nullptr,
+                         s)))
+      return rc;
     // the update also packs the next round's operands (BF16)
     if ((rc = launch_update(train, nt, d, m, ks, codes, c32, c64, f.nch, f.part_s, f.part_cnt, f.part_j,
                             f.j_sub + (size_t)it * m, bf ? f.enc.aop : nullptr, f.enc.cmax, f.enc.mu,
-                            objective != nullptr, s)))
+                            objective != nullptr, det, s)))
       return rc;
     if (precision == MIPQ_FP8 && it + 1 < iters && (rc = launch_pack_fp8(c32, m, ks, ds, f.enc.aop, f.enc.mu, s)))
       return rc;
@@ -191,22 +244,34 @@ int mipq_pq_fit(const float* x, int64_t n, const int64_t* train_rows, int64_t n_
 
 size_t mipq_pq_encode_workspace_size(int64_t n, int d, int m, int ks, int precision) {
   if (check_shape(n, d, m, ks, precision, false) != MIPQ_OK) return 0;
-  return carve_encode(nullptr, m, ks, d / m, precision).bytes;
+  const size_t main = carve_encode(nullptr, m, ks, d / m, precision).bytes;
+  return main + carve_encode_extra(nullptr, n, m).bytes;
 }
 
 int mipq_pq_encode(const float* x, int64_t n, int d, int m, int ks, const float* codebook,
-                   int precision, uint8_t* codes, int64_t* rescored, void* ws, size_t ws_bytes,
-                   void* stream) {
+                   int precision, int flags, uint8_t* codes, float* min_dist, double* sse_rmse,
+                   int64_t* rescored, void* ws, size_t ws_bytes, void* stream) {
   int rc;
   if ((rc = check_shape(n, d, m, ks, precision, false))) return rc;
+  if ((rc = check_flags(flags, MIPQ_CHECK_FINITE))) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (n > 0 && (!x || !codebook || !codes)) return fail(MIPQ_EINVAL, "x, codebook and codes are required");
   EncodeWs e = carve_encode(ws, m, ks, d / m, precision);
-  if (n > 0 && (rc = check_ws(ws, ws_bytes, e.bytes))) return rc;
+  EncodeExtraWs ex = carve_encode_extra(ws ? static_cast<char*>(ws) + e.bytes : nullptr, n, m);
+  if ((n > 0 || (flags & MIPQ_CHECK_FINITE)) && (rc = check_ws(ws, ws_bytes, e.bytes + ex.bytes))) return rc;
+  if ((flags & MIPQ_CHECK_FINITE) &&
+      (rc = check_finite({{x, (size_t)n * d}, {codebook, (size_t)m * ks * (d / m)}}, ex.flag, s)))
+    return rc;
   if (rescored && (rc = launch_zero_u32(reinterpret_cast<uint32_t*>(rescored), 2, s))) return rc;
-  if (n == 0) return MIPQ_OK;
-  if ((rc = pack_any(codebook, m, ks, d / m, precision, e, s))) return rc;
-  return assign_any(x, n, d, m, ks, codebook, precision, codes, e, rescored, s);
+  if (n > 0) {
+    if ((rc = pack_any(codebook, m, ks, d / m, precision, e, s))) return rc;
+    if ((rc = assign_any(x, n, d, m, ks, codebook, precision, codes, e, rescored, s))) return rc;
+    if ((min_dist || sse_rmse) &&
+        (rc = launch_code_dist(x, n, d, m, ks, codebook, codes, min_dist, ex.partials, ex.nblk, s)))
+      return rc;
+  }
+  if (sse_rmse && (rc = launch_sse_final(ex.partials, n > 0 ? ex.nblk : 0, n, d, sse_rmse, s))) return rc;
+  return MIPQ_OK;
 }
 
 size_t mipq_pq_decode_rmse_workspace_size(int64_t n, int d, int m, int ks) {
@@ -505,16 +570,16 @@ int mipq_ii_build(const float* x, int64_t n, int d, int kc, int coarse_iters, co
   // 3. final sample labels, residuals, residual PQ fit
   if ((rc = coarse_assign_any(b.xs, n_train, d, coarse, kc, precision, b.cw, b.tlabels, nullptr, s))) return rc;
   if ((rc = launch_residuals(b.xs, n_train, d, b.tlabels, coarse, kc, b.rtrain, s))) return rc;
-  if ((rc = mipq_pq_fit(b.rtrain, n_train, nullptr, 0, d, m, ks, pq_iters, pq_init, nullptr, precision,
-                        pq_codebook, nullptr, nullptr, nullptr, b.sub, b.sub_bytes, stream)))
+  if ((rc = mipq_pq_fit(b.rtrain, n_train, nullptr, 0, d, m, ks, pq_iters, pq_init, nullptr, precision, 0,
+                        pq_codebook, nullptr, nullptr, nullptr, nullptr, b.sub, b.sub_bytes, stream)))
     return rc;
   // 4. labels and residual codes of all rows (residuals formed chunk by chunk)
   if ((rc = coarse_assign_any(x, n, d, coarse, kc, precision, b.cw, lab, nullptr, s))) return rc;
   for (int64_t a = 0; a < n; a += b.chunk) {
     const int64_t cnt = (n - a) < b.chunk ? (n - a) : b.chunk;
     if ((rc = launch_residuals(x + a * d, cnt, d, lab + a, coarse, kc, b.rbuf, s))) return rc;
-    if ((rc = mipq_pq_encode(b.rbuf, cnt, d, m, ks, pq_codebook, precision, b.codes + a * m, nullptr, b.sub,
-                             b.sub_bytes, stream)))
+    if ((rc = mipq_pq_encode(b.rbuf, cnt, d, m, ks, pq_codebook, precision, 0, b.codes + a * m, nullptr, nullptr,
+                             nullptr, b.sub, b.sub_bytes, stream)))
       return rc;
   }
   // 5. stable bucketing by label, codes in list order
@@ -583,8 +648,8 @@ int mipq_ii_add(const float* x, int64_t n, int d, const float* coarse, int kc, c
   for (int64_t r = 0; r < n; r += a.chunk) {
     const int64_t cnt = (n - r) < a.chunk ? (n - r) : a.chunk;
     if ((rc = launch_residuals(x + r * d, cnt, d, lab + r, coarse, kc, a.rbuf, s))) return rc;
-    if ((rc = mipq_pq_encode(a.rbuf, cnt, d, m, ks, pq_codebook, precision, a.codes + r * m, nullptr, a.sub,
-                             a.sub_bytes, stream)))
+    if ((rc = mipq_pq_encode(a.rbuf, cnt, d, m, ks, pq_codebook, precision, 0, a.codes + r * m, nullptr, nullptr,
+                             nullptr, a.sub, a.sub_bytes, stream)))
       return rc;
   }
   if ((rc = launch_sort_by_label(lab, n, kc, a.keys_a, a.keys_b, a.vals_a, a.vals_b, a.hist, ids, a.keys_sorted,

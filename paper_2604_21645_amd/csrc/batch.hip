@@ -142,13 +142,14 @@ struct BatchRun {
   int nprob, d, m, ks, iters;
   bool full, vec;
   int grid;
+  bool det = false;   // MIPQ_PLAN_DETERMINISTIC
 };
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 BatchRun make_run(const BatchLayout& L, const mipq_problem* probs, int nprob, int d, int m, int ks, int iters,
                   int grid) {
-  BatchRun r{L, nprob, d, m, ks, iters, true, true, grid};
+  BatchRun r{L, nprob, d, m, ks, iters, true, true, grid, false};
   const int ds = d / m;
   const int nb = (ds + 7) / 8;
   r.full = (ds == nb * 8) && (d % 4 == 0);
@@ -177,7 +178,7 @@ int run_round(const BatchRun& r, hipStream_t s) {
                                        r.full, r.grid, nullptr, s)))
     return rc;
   return launch_update_batched(L.probs, r.nprob, L.items, r.d, r.m, r.ks, L.c64, L.part_s, L.part_cnt, L.part_j,
-                               L.j_all, L.round, r.iters, L.aop, L.aop_stride, L.cmax, L.mu, s);
+                               L.j_all, L.round, r.iters, L.aop, L.aop_stride, L.cmax, L.mu, r.det, s);
 }
 
 // encode with the final codebooks, reconstruction errors, objectives
@@ -249,7 +250,8 @@ int mipq_plan_create(mipq_plan** out, const mipq_problem* probs, int nprob, int 
   *out = nullptr;
   if ((rc = check_batch_shape(nprob, d, m, ks, iters, precision))) return rc;
   if ((rc = check_problems(probs, nprob, m))) return rc;
-  if (flags & ~(MIPQ_PLAN_AUTOTUNE | MIPQ_PLAN_GRAPH)) return fail(MIPQ_EINVAL, "unknown plan flags 0x%x", flags);
+  if (flags & ~(MIPQ_PLAN_AUTOTUNE | MIPQ_PLAN_GRAPH | MIPQ_PLAN_DETERMINISTIC))
+    return fail(MIPQ_EINVAL, "unknown plan flags 0x%x", flags);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const std::vector<int64_t> n = sizes_of(probs, nprob);
   std::vector<BatchProb> table;
@@ -269,6 +271,7 @@ int mipq_plan_create(mipq_plan** out, const mipq_problem* probs, int nprob, int 
   plan->ws = ws;
   plan->ws_bytes = ws_bytes;
   BatchRun r = make_run(L, probs, nprob, d, m, ks, iters, 8);
+  r.det = (flags & MIPQ_PLAN_DETERMINISTIC) != 0;
   auto bail = [&](int code) {
     destroy_graphs(plan);
     delete plan;
@@ -386,7 +389,8 @@ int mipq_pq_fit_batched(const mipq_problem* probs, int nprob, int d, int m, int 
         return rc;
       grid = 2 * (((resident > 8 ? resident : 8) + 7) / 8 * 8);
     }
-    const BatchRun r = make_run(L, probs, nprob, d, m, ks, iters, grid);
+    BatchRun r = make_run(L, probs, nprob, d, m, ks, iters, grid);
+    r.det = plan && (plan->flags & MIPQ_PLAN_DETERMINISTIC);
     if ((rc = run_setup(r, s))) return rc;
     for (int it = 0; it < iters; ++it)
       if ((rc = run_round(r, s))) return rc;

@@ -103,9 +103,10 @@ int launch_assign_fp32(const float* x, int64_t n, int d, int m, int ks, const fl
 // Lloyd update of one round; aop == NULL: plain path (no operand packing)
 int update_chunks(int64_t n, int m);
 // objective: also the float64 objective terms of the round (else part_j holds zeros)
+// det: float64 sums in a fixed order (no atomic additions; MIPQ_DETERMINISTIC)
 int launch_update(const float* x, int64_t n, int d, int m, int ks, const uint8_t* codes, float* c32,
                   double* c64, int nch, double* part_s, uint32_t* part_cnt, double* part_j,
-                  double* j_sub, void* aop, float* cmax, float* mu, bool objective, hipStream_t s);
+                  double* j_sub, void* aop, float* cmax, float* mu, bool objective, bool det, hipStream_t s);
 int launch_objective(const double* j_sub, int iters, int m, double* objective, hipStream_t s);
 int launch_copy_f64(const double* src, double* dst, size_t count, hipStream_t s);
 int launch_decode_sse(const uint8_t* codes, int64_t n, int d, int m, int ks, const float* c32,
@@ -113,6 +114,12 @@ int launch_decode_sse(const uint8_t* codes, int64_t n, int d, int m, int ks, con
 int decode_blocks(int64_t n, int m);
 int launch_decode_centroids(const float* cb, int64_t nbooks, int m, int ks, int ds, float* out, hipStream_t s);
 int launch_sse_final(const double* partials, int nblk, int64_t n, int d, double* out, hipStream_t s);
+// float32-rule distance of each (row, subspace) to its coded centroid
+// (min_dist optional) and per-block float64 squared-error partials
+int launch_code_dist(const float* x, int64_t n, int d, int m, int ks, const float* c32, const uint8_t* codes,
+                     float* min_dist, double* partials, int nblk, hipStream_t s);
+// flag[0] |= 1 if any of the count floats is NaN or infinite
+int launch_nonfinite(const float* p, size_t count, uint32_t* flag, hipStream_t s);
 
 // BF16 matrix-core path
 struct Bf16Geom {
@@ -191,7 +198,7 @@ int launch_assign_bf16_batched(const BatchProb* probs, int nprob, int64_t units,
 int launch_update_batched(const BatchProb* probs, int nprob, int64_t items, int d, int m, int ks, double* c64,
                           double* part_s, uint32_t* part_cnt, double* part_j, double* j_all,
                           const uint32_t* round, int iters, void* aop, size_t aop_stride, float* cmax, float* mu,
-                          hipStream_t s);
+                          bool det, hipStream_t s);
 int launch_decode_sse_batched(const BatchProb* probs, int nprob, int64_t blocks, int d, int m, int ks, bool vec,
                               double* partials, hipStream_t s);
 int launch_objective_batched(const BatchProb* probs, int nprob, int iters, int m, const double* j_all,

@@ -253,6 +253,69 @@ __global__ __launch_bounds__(kThreads) void k_decode_sse(const uint8_t* __restri
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+
+// Distance of every (row, subspace) to its coded centroid: the float32 rule
+// (min_dist, optional) and the float64 squared error of the decode (sum of
+// ((double)x - (double)c)^2 over the subspace's dimensions, ascending), one
+// thread per (row, subspace) pair in pair order; per-block partial sums are
+// reduced in a fixed order by k_sse_final.  Codes >= ks give NaN.
+template <int DS>
+__global__ __launch_bounds__(kThreads) void k_code_dist(const float* __restrict__ x, int64_t n, int d, int m,
+                                                        int ks, int ds_rt, const float* __restrict__ c32,
+                                                        const uint8_t* __restrict__ codes,
+                                                        float* __restrict__ min_dist,
+                                                        double* __restrict__ partials) {
+  __shared__ double red[kThreads / 64];
+  const int ds = DS ? DS : ds_rt;
+  const int64_t items = n * m;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t row = i / m;
+  int sub = int(i - row * m);
+  const int64_t srow = stride / m;
+  const int ssub = int(stride - srow * m);
+  double acc = 0.0;
+  for (; i < items; i += stride) {
+    const int code = codes[i];
+    const bool ok = code < ks;
+    const float* c = c32 + ((int64_t)sub * ks + (ok ? code : 0)) * ds;
+    const float* xr = x + row * d + (int64_t)sub * ds;
+    float dist = 0.0f;
+    double sq = 0.0;
+    for (int t = 0; t < ds; ++t) {
+      const float xv = xr[t], cv = c[t];
+      const float df = xv - cv;
+      const float s2 = df * df;
+      dist = dist + s2;
+      const double dd = (double)xv - (double)cv;
+      sq = sq + dd * dd;
+    }
+    if (!ok) {
+      dist = NAN;
+      sq = NAN;
+    }
+    if (min_dist) min_dist[i] = dist;
+    acc += sq;
+    row += srow;
+    sub += ssub;
+    if (sub >= m) {
+      sub -= m;
+      ++row;
+    }
+  }
+  const double s = block_sum_f64(acc, red);
+  if (threadIdx.x == 0 && partials) partials[blockIdx.x] = s;
+}
+
+// flag[0] = 1 when any of the count floats at p is NaN or infinite
+__global__ __launch_bounds__(kThreads) void k_nonfinite(const float* __restrict__ p, size_t count,
+                                                        uint32_t* __restrict__ flag) {
+  bool bad = false;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(p[i]);
+  if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
+}
+
 // the last problem p with key(p) <= i (problems in ascending key order)
 template <class Key>
 __device__ __forceinline__ int find_problem(const BatchProb* __restrict__ probs, int nprob, int64_t i, Key key) {
@@ -434,6 +497,25 @@ int launch_assign_fp32(const float* x, int64_t n, int d, int m, int ks, const fl
   MIPQ_DS_SWITCH(ds, CALL)
 #undef CALL
   MIPQ_LAUNCHED("k_assign_fp32");
+  return MIPQ_OK;
+}
+
+int launch_code_dist(const float* x, int64_t n, int d, int m, int ks, const float* c32, const uint8_t* codes,
+                     float* min_dist, double* partials, int nblk, hipStream_t s) {
+  if (n == 0) return MIPQ_OK;
+  const int ds = d / m;
+#define CALL(DSV) \
+  k_code_dist<DSV><<<nblk, kThreads, 0, s>>>(x, n, d, m, ks, ds, c32, codes, min_dist, partials)
+  MIPQ_DS_SWITCH(ds, CALL)
+#undef CALL
+  MIPQ_LAUNCHED("k_code_dist");
+  return MIPQ_OK;
+}
+
+int launch_nonfinite(const float* p, size_t count, uint32_t* flag, hipStream_t s) {
+  if (!count) return MIPQ_OK;
+  k_nonfinite<<<grid_for((int64_t)count, kThreads, 4096), kThreads, 0, s>>>(p, count, flag);
+  MIPQ_LAUNCHED("k_nonfinite");
   return MIPQ_OK;
 }
 

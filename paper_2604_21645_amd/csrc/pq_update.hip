@@ -109,6 +109,183 @@ __device__ __forceinline__ void accumulate_chunk(
   }
 }
 
+// Deterministic variant (MIPQ_DETERMINISTIC): no floating-point atomics.  The
+// chunk's rows are taken in pieces of kDetPiece rows; each piece's positions
+// are sorted by code with a stable two-pass counting sort on 4-bit digits
+// (low, then high; ranks inside 64 consecutive elements from wave ballots),
+// then thread q owns the sums of pair q = (centroid k, dimension t) and adds
+// x[row][t] of the piece's rows coded k in row order, pieces in order.  The
+// objective terms are added by the same threads in the same order.  Every sum
+// therefore depends only on the inputs.
+constexpr int kDetPiece = 1024;
+constexpr int kDetBatches = kDetPiece / 64;
+
+__host__ __device__ constexpr size_t det_lds_bytes(int ks, int ds, bool obj) {
+  return (size_t)ks * ds * sizeof(double) + (obj ? (size_t)ks * ds * sizeof(float) : 0) +
+         ((size_t)3 * ks + 1 + 16 * kDetBatches + 32) * sizeof(uint32_t) + 2 * kDetPiece * sizeof(uint16_t) +
+         kDetPiece;
+}
+
+template <bool OBJ>
+__device__ __forceinline__ void accumulate_chunk_det(
+    const float* __restrict__ x, int64_t n, int d, int m, int ks, int ds, const uint8_t* __restrict__ codes,
+    const float* __restrict__ c32, int64_t rpc, int c, int sub, double* __restrict__ part_s,
+    uint32_t* __restrict__ part_cnt, double* __restrict__ part_j, char* smem, double* redj) {
+  const int per = ks * ds;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  double* S = reinterpret_cast<double*>(smem);                     // [per]
+  float* cbs = reinterpret_cast<float*>(S + per);                  // [per] (OBJ)
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(cbs + (OBJ ? per : 0));   // [ks]
+  uint32_t* cntp = cnt + ks;                                       // [ks] histogram of the piece
+  uint32_t* off = cntp + ks;                                       // [ks + 1]
+  uint32_t* bcount = off + ks + 1;                                 // [kDetBatches][16]
+  uint32_t* dtot = bcount + 16 * kDetBatches;                      // [16] digit totals
+  uint32_t* dbase = dtot + 16;                                     // [16]
+  uint16_t* permA = reinterpret_cast<uint16_t*>(dbase + 16);       // [kDetPiece]
+  uint16_t* permB = permA + kDetPiece;                             // [kDetPiece]
+  uint8_t* pc = reinterpret_cast<uint8_t*>(permB + kDetPiece);     // [kDetPiece]
+  for (int i = tid; i < per; i += nthr) {
+    S[i] = 0.0;
+    if (OBJ) cbs[i] = c32[(int64_t)sub * per + i];
+  }
+  for (int i = tid; i < ks; i += nthr) cnt[i] = 0u;
+  const int64_t r0 = (int64_t)c * rpc;
+  const int64_t r1 = min(n, r0 + rpc);
+  const float* xs = x + (int64_t)sub * ds;
+  double jl = 0.0;
+  for (int64_t p0 = r0; p0 < r1; p0 += kDetPiece) {
+    const int L = (int)min((int64_t)kDetPiece, r1 - p0);
+    for (int i = tid; i < ks; i += nthr) cntp[i] = 0u;
+    __syncthreads();
+    for (int i = tid; i < L; i += nthr) {
+      const int cd = codes[(p0 + i) * m + sub];
+      pc[i] = (uint8_t)cd;
+      if (cd < ks) atomicAdd(&cntp[cd], 1u);   // integer counts: order-independent
+    }
+    __syncthreads();
+    // exclusive scan of the piece histogram (one wave, 4 bins per lane)
+    if (wave == 0) {
+      uint32_t v[4], run = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = lane * 4 + q;
+        v[q] = k < ks ? cntp[k] : 0u;
+        run += v[q];
+      }
+      uint32_t inc = run;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+      }
+      uint32_t e = inc - run;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = lane * 4 + q;
+        if (k < ks) off[k] = e;
+        e += v[q];
+      }
+      if (lane == 63) off[ks] = inc;
+    }
+    // stable sort of the piece's positions by code
+    for (int pass = 0; pass < 2; ++pass) {
+      const int shift = 4 * pass;
+      uint16_t* dst = pass ? permB : permA;
+      for (int i = tid; i < 16 * kDetBatches; i += nthr) bcount[i] = 0u;
+      __syncthreads();
+      constexpr int kPer = 4;   // elements per thread (kDetPiece / 256 threads at most)
+      int rank[kPer], dig[kPer], pos[kPer];
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        const int e = j * nthr + tid;   // batch e / 64: lanes hold consecutive elements
+        const bool live = e < L;
+        pos[j] = live ? (pass ? (int)permA[e] : e) : 0;
+        dig[j] = live ? ((pc[pos[j]] >> shift) & 15) : 0;
+        uint64_t eq = __ballot(live);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const uint64_t bm = __ballot(live && ((dig[j] >> b) & 1));
+          eq &= ((dig[j] >> b) & 1) ? bm : ~bm;
+        }
+        rank[j] = __popcll(eq & ((1ull << lane) - 1ull));
+        if (live && rank[j] == 0) bcount[(e >> 6) * 16 + dig[j]] = (uint32_t)__popcll(eq);
+        if (!live) rank[j] = -1;
+      }
+      __syncthreads();
+      if (tid < 16) {   // per digit: batches in order
+        uint32_t run = 0;
+        for (int b = 0; b < kDetBatches; ++b) {
+          const uint32_t v = bcount[b * 16 + tid];
+          bcount[b * 16 + tid] = run;
+          run += v;
+        }
+        dtot[tid] = run;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        uint32_t run = 0;
+        for (int g = 0; g < 16; ++g) {
+          dbase[g] = run;
+          run += dtot[g];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        const int e = j * nthr + tid;
+        if (rank[j] >= 0) dst[dbase[dig[j]] + bcount[(e >> 6) * 16 + dig[j]] + rank[j]] = (uint16_t)pos[j];
+      }
+      __syncthreads();
+    }
+    // sums of the piece: pair q = (k, t), rows of code k in row order
+    for (int q = tid; q < per; q += nthr) {
+      const int k = q / ds, t = q - k * ds;
+      const uint32_t b = off[k], e = off[k + 1];
+      double acc = S[q];
+      const double cv = OBJ ? (double)cbs[q] : 0.0;
+      const float* xc = xs + p0 * d + t;
+      uint32_t i = b;
+      for (; i + 4 <= e; i += 4) {
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = xc[(int64_t)permB[i + u] * d];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          acc += (double)v[u];
+          if (OBJ) {
+            const double df = (double)v[u] - cv;
+            jl += df * df;
+          }
+        }
+      }
+      for (; i < e; ++i) {
+        const float v = xc[(int64_t)permB[i] * d];
+        acc += (double)v;
+        if (OBJ) {
+          const double df = (double)v - cv;
+          jl += df * df;
+        }
+      }
+      S[q] = acc;
+    }
+    for (int k = tid; k < ks; k += nthr) cnt[k] += cntp[k];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) jl += __shfl_xor(jl, o, 64);
+  if (lane == 0) redj[wave] = jl;
+  __syncthreads();
+  const size_t base = (size_t)c * m + sub;
+  for (int i = tid; i < per; i += nthr) part_s[base * per + i] = S[i];
+  for (int i = tid; i < ks; i += nthr) part_cnt[base * ks + i] = cnt[i];
+  if (tid == 0) {
+    double js = 0.0;
+    for (int i = 0; i < (nthr >> 6); ++i) js += redj[i];
+    part_j[base] = js;
+  }
+}
+
 // Block -> (chunk, subspace) so that the m blocks of one chunk run on one XCD
 // (hardware block id mod 8) next to each other: they read the same rows, which
 // then come from that XCD's L2.  Chunks go round-robin over the XCDs.
@@ -128,6 +305,7 @@ __device__ __forceinline__ ChunkMap chunk_map(int64_t b, int m) {
 // kUpdThreads for the fit; the backward, which also writes dL/dx, runs
 // kBwdThreads.
 constexpr int kBwdThreads = 1024;
+constexpr int kDetThreads = 256;   // four elements per thread in the piece sort
 
 template <bool GX, bool OBJ, bool CHECK, int NT>
 __global__ __launch_bounds__(NT) void k_accumulate(
@@ -147,6 +325,22 @@ __global__ __launch_bounds__(NT) void k_accumulate(
                                    part_j, gscale, grad_x, smem, redj);
 }
 
+// Deterministic accumulation (see accumulate_chunk_det), one problem.
+template <bool OBJ>
+__global__ __launch_bounds__(kDetThreads) void k_accumulate_det(
+    const float* __restrict__ x, int64_t n, int d, int m, int ks, int ds, const uint8_t* __restrict__ codes,
+    const float* __restrict__ c32, int64_t rpc, int nch, double* __restrict__ part_s,
+    uint32_t* __restrict__ part_cnt, double* __restrict__ part_j, float* __restrict__ cmax_zero) {
+  extern __shared__ double smem[];
+  __shared__ double redj[kDetThreads / 64];
+  if (cmax_zero && blockIdx.x == 0)
+    for (int j = threadIdx.x; j < m; j += blockDim.x) cmax_zero[j] = 0.0f;
+  const ChunkMap cm = chunk_map(blockIdx.x, m);
+  if (cm.chunk >= nch) return;
+  accumulate_chunk_det<OBJ>(x, n, d, m, ks, ds, codes, c32, rpc, (int)cm.chunk, cm.sub, part_s, part_cnt, part_j,
+                            reinterpret_cast<char*>(smem), redj);
+}
+
 // the last problem p with key(p) <= i (problems in ascending key order)
 template <class Key>
 __device__ __forceinline__ int find_problem(const BatchProb* __restrict__ probs, int nprob, int64_t i, Key key) {
@@ -162,14 +356,15 @@ __device__ __forceinline__ int find_problem(const BatchProb* __restrict__ probs,
 // Many problems: block i is accumulation item i = (problem p, chunk c,
 // subspace j) with items problem-major, then chunk, then subspace; problem p's
 // partials use the single-problem layout at offset item0.
-__global__ __launch_bounds__(kUpdThreads) void k_accumulate_batched(const BatchProb* __restrict__ probs, int nprob,
-                                                                    int64_t items, int d, int m, int ks, int ds,
-                                                                    double* __restrict__ part_s,
-                                                                    uint32_t* __restrict__ part_cnt,
-                                                                    double* __restrict__ part_j,
-                                                                    float* __restrict__ cmax_zero, int nzero) {
+template <bool DET, int NT>
+__global__ __launch_bounds__(NT) void k_accumulate_batched(const BatchProb* __restrict__ probs, int nprob,
+                                                           int64_t items, int d, int m, int ks, int ds,
+                                                           double* __restrict__ part_s,
+                                                           uint32_t* __restrict__ part_cnt,
+                                                           double* __restrict__ part_j,
+                                                           float* __restrict__ cmax_zero, int nzero) {
   extern __shared__ double smem[];
-  __shared__ double redj[kUpdThreads / 64];
+  __shared__ double redj[NT / 64];
   // the next finalize raises every cmax from zero (see k_accumulate)
   if (blockIdx.x == 0)
     for (int j = threadIdx.x; j < nzero; j += blockDim.x) cmax_zero[j] = 0.0f;
@@ -181,9 +376,16 @@ __global__ __launch_bounds__(kUpdThreads) void k_accumulate_batched(const BatchP
   const int local = (int)(i - item0);
   const int c = local / m, sub = local - (local / m) * m;
   const size_t per = (size_t)ks * ds;
-  accumulate_chunk<false, true, false>(probs[p].x, probs[p].n, d, m, ks, ds, probs[p].codes, probs[p].c32,
-                                       probs[p].rpc, c, sub, part_s + item0 * per, part_cnt + item0 * ks,
-                                       part_j + item0, nullptr, nullptr, smem, redj);
+  // the deterministic sums run with the single-problem block size, so that
+  // every result (the objective too) equals the single call's
+  if (DET)
+    accumulate_chunk_det<true>(probs[p].x, probs[p].n, d, m, ks, ds, probs[p].codes, probs[p].c32, probs[p].rpc, c,
+                               sub, part_s + item0 * per, part_cnt + item0 * ks, part_j + item0,
+                               reinterpret_cast<char*>(smem), redj);
+  else
+    accumulate_chunk<false, true, false>(probs[p].x, probs[p].n, d, m, ks, ds, probs[p].codes, probs[p].c32,
+                                         probs[p].rpc, c, sub, part_s + item0 * per, part_cnt + item0 * ks,
+                                         part_j + item0, nullptr, nullptr, smem, redj);
 }
 
 // Subspace sub (paths without matrix-core operands): sums the chunk partials
@@ -454,10 +656,21 @@ int update_chunks(int64_t n, int m) {
 
 int launch_update(const float* x, int64_t n, int d, int m, int ks, const uint8_t* codes, float* c32,
                   double* c64, int nch, double* part_s, uint32_t* part_cnt, double* part_j,
-                  double* j_sub, void* aop, float* cmax, float* mu, bool objective, hipStream_t s) {
+                  double* j_sub, void* aop, float* cmax, float* mu, bool objective, bool det, hipStream_t s) {
   const int ds = d / m;
   const int64_t rpc = (n + nch - 1) / nch;
-  {
+  if (det) {
+    const unsigned grid = (unsigned)(((nch + 7) / 8) * 8 * m);
+    ProfScope ps(MIPQ_K_UPDATE, s);
+    float* cz = aop ? cmax : nullptr;
+    if (objective)
+      k_accumulate_det<true><<<grid, kDetThreads, det_lds_bytes(ks, ds, true), s>>>(
+          x, n, d, m, ks, ds, codes, c32, rpc, nch, part_s, part_cnt, part_j, cz);
+    else
+      k_accumulate_det<false><<<grid, kDetThreads, det_lds_bytes(ks, ds, false), s>>>(
+          x, n, d, m, ks, ds, codes, c32, rpc, nch, part_s, part_cnt, part_j, cz);
+    MIPQ_LAUNCHED("k_accumulate_det");
+  } else {
     const size_t shm = (size_t)ks * (ds + 1) * sizeof(double) + ((ks + 1) / 2) * sizeof(double) +
                        (size_t)ks * ds * sizeof(float);
     const unsigned grid = (unsigned)(((nch + 7) / 8) * 8 * m);
@@ -549,7 +762,7 @@ int launch_pack_bf16_batched(const BatchProb* probs, int nprob, int m, int ks, i
 int launch_update_batched(const BatchProb* probs, int nprob, int64_t items, int d, int m, int ks, double* c64,
                           double* part_s, uint32_t* part_cnt, double* part_j, double* j_all,
                           const uint32_t* round, int iters, void* aop, size_t aop_stride, float* cmax, float* mu,
-                          hipStream_t s) {
+                          bool det, hipStream_t s) {
   const int ds = d / m;
   {
     const size_t shm = (size_t)ks * (ds + 1) * sizeof(double) + ((ks + 1) / 2) * sizeof(double) +
@@ -557,8 +770,13 @@ int launch_update_batched(const BatchProb* probs, int nprob, int64_t items, int 
     ProfScope ps(MIPQ_K_UPDATE, s);
     const int64_t chunks = items / m;
     const unsigned grid = (unsigned)(((chunks + 7) / 8) * 8 * m);
-    k_accumulate_batched<<<grid, kUpdThreads, shm, s>>>(probs, nprob, items, d, m, ks, ds, part_s, part_cnt, part_j,
-                                                        cmax, nprob * m);
+    if (det)
+      k_accumulate_batched<true, kDetThreads><<<grid, kDetThreads, det_lds_bytes(ks, ds, true), s>>>(
+          probs, nprob, items, d, m, ks, ds, part_s, part_cnt, part_j, cmax, nprob * m);
+    else
+      k_accumulate_batched<false, kUpdThreads><<<grid, kUpdThreads, shm, s>>>(probs, nprob, items, d, m, ks, ds,
+                                                                              part_s, part_cnt, part_j, cmax,
+                                                                              nprob * m);
     MIPQ_LAUNCHED("k_accumulate_batched");
   }
   const int nt = tiles_for(ks);

@@ -25,7 +25,7 @@ def test_every_header_function_is_exported(L):
 
 def test_single_hip_runtime_and_version(L):
     assert len(_lib.hip_runtimes_mapped()) == 1
-    assert L.mipq_abi_version() == 1
+    assert L.mipq_abi_version() == 2
 
 
 def test_workspace_queries(L):
@@ -33,14 +33,15 @@ def test_workspace_queries(L):
     big = L.mipq_pq_encode_workspace_size(100000, 128, 16, 256, 1)
     assert 0 < small <= big
     assert L.mipq_pq_fit_workspace_size(1000, 128, 16, 256, 25, 1) < L.mipq_pq_fit_workspace_size(100000, 128, 16, 256, 25, 1)
-    assert L.mipq_pq_encode_workspace_size(1000, 128, 16, 256, 0) == 0   # FP32 needs none
+    # FP32 needs only the error partials and the check flag
+    assert 0 < L.mipq_pq_encode_workspace_size(1000, 128, 16, 256, 0) < small
     assert L.mipq_pq_encode_workspace_size(1000, 130, 16, 256, 1) == 0   # invalid shape
     assert L.mipq_pq_fit_workspace_size(1000, 128, 16, 256, 25, 1) > 0
     assert L.mipq_pq_decode_rmse_workspace_size(1000, 128, 16, 256) > 0
 
 
-def _encode(L, n=10, d=128, m=16, ks=256, prec=1, ws=None, ws_bytes=0, x=1, cb=1, codes=1):
-    return L.mipq_pq_encode(x, n, d, m, ks, cb, prec, codes, None, ws, ws_bytes, None)
+def _encode(L, n=10, d=128, m=16, ks=256, prec=1, ws=None, ws_bytes=0, x=1, cb=1, codes=1, flags=0):
+    return L.mipq_pq_encode(x, n, d, m, ks, cb, prec, flags, codes, None, None, None, ws, ws_bytes, None)
 
 
 @pytest.mark.parametrize("kw,code", [
@@ -54,6 +55,9 @@ def _encode(L, n=10, d=128, m=16, ks=256, prec=1, ws=None, ws_bytes=0, x=1, cb=1
     (dict(x=None), EINVAL),
     (dict(ws=None), EINVAL),
     (dict(ws=256, ws_bytes=16), ENOMEM),
+    (dict(flags=2), EINVAL),     # MIPQ_DETERMINISTIC is a fit flag
+    (dict(flags=8), EINVAL),
+    (dict(n=0, flags=1), EINVAL),   # the finite check needs the workspace even for no rows
 ])
 def test_encode_rejects_bad_arguments(L, kw, code):
     assert _encode(L, **kw) == code
@@ -61,16 +65,21 @@ def test_encode_rejects_bad_arguments(L, kw, code):
 
 
 def test_fit_rejects_bad_arguments(L):
-    fit = L.mipq_pq_fit
+    def fit(init_rows=1, iters=5, ws=256, ws_bytes=1 << 30, flags=0):
+        return L.mipq_pq_fit(1, 100, None, 0, 128, 16, 256, iters, init_rows, None, 1, flags, 1, None, None, None,
+                             None, ws, ws_bytes, None)
     # no initial codebook or rows
-    assert fit(1, 100, None, 0, 128, 16, 256, 5, None, None, 1, 1, None, None, None, 256, 1 << 30, None) == EINVAL
+    assert fit(init_rows=None) == EINVAL
     # negative iterations
-    assert fit(1, 100, None, 0, 128, 16, 256, -1, 1, None, 1, 1, None, None, None, 256, 1 << 30, None) == EINVAL
+    assert fit(iters=-1) == EINVAL
     # workspace too small
-    assert fit(1, 100, None, 0, 128, 16, 256, 5, 1, None, 1, 1, None, None, None, 256, 64, None) == ENOMEM
+    assert fit(ws_bytes=64) == ENOMEM
     assert b"workspace" in L.mipq_last_error()
     # misaligned workspace
-    assert fit(1, 100, None, 0, 128, 16, 256, 5, 1, None, 1, 1, None, None, None, 257, 1 << 30, None) == EINVAL
+    assert fit(ws=257) == EINVAL
+    # unknown flag
+    assert fit(flags=4) == EINVAL
+    assert b"flags" in L.mipq_last_error()
 
 
 def test_decode_needs_x_for_the_error(L):

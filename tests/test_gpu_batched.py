@@ -174,3 +174,22 @@ def test_full_size_uneven_batch_sampled():
                              r["codebook"].cpu().numpy().astype(np.float64))
         assert r["sse_rmse"][0].item() == pytest.approx(sse, rel=1e-12)
     b.close()
+
+
+def test_deterministic_plan_repeats_and_equals_single_deterministic_fits():
+    m, ks, iters, d = 12, 64, 4, 96
+    xs, inits = _problems([3000, 9001, 5000, 700], d, m, ks, "float", seed=41)
+    xt = [_t(x) for x in xs]
+    it = [_t(i) for i in inits]
+    b = mipq.BatchedFit(xt, it, m, ks, iters, plan=True, autotune=False, graph=True, deterministic=True)
+    b.run()
+    first = [{k: v.clone() for k, v in r.items()} for r in b.results]
+    b.run()
+    torch.cuda.synchronize()
+    for i, (x, init) in enumerate(zip(xs, inits)):
+        r = b.results[i]
+        for k in ("codebook", "codes", "sse_rmse", "objective"):
+            assert torch.equal(r[k], first[i][k]), (i, k)
+        fit = mipq.pq_fit(xt[i], m, ks, iters, init_rows=it[i], precision="bf16", labels=False, deterministic=True)
+        assert torch.equal(r["codebook"], fit["codebook"]), i
+        assert torch.equal(r["objective"], fit["objective"]), i

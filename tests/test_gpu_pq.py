@@ -167,3 +167,116 @@ def test_full_size_integer_workload_sampled_parity():
     rows = np.random.default_rng(0).choice(w.x.shape[0], 4000, replace=False)
     ref32, _, _ = pq.assign(w.x[rows], cb.cpu().numpy().astype(np.float64), "fp32")
     np.testing.assert_array_equal(cb16.cpu().numpy()[rows].astype(np.int64), ref32)
+
+
+ENCODE_OUT_CASES = [
+    dict(n=3001, d=128, m=16, ks=256, kind="integer"),   # ds=8, ragged tail
+    dict(n=1500, d=96, m=8, ks=200, kind="float"),       # ds=12
+    dict(n=257, d=48, m=16, ks=32, kind="float"),        # ds=3
+]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("case", ENCODE_OUT_CASES, ids=lambda c: "n%(n)d_d%(d)d_m%(m)d_ks%(ks)d" % c)
+def test_encode_min_dist_and_error(prec, case):
+    """The distance of every (row, subspace) to its chosen centroid (the value
+    the code minimises under the float32 rule) and the float64 squared error
+    of the codes, from the encode call itself."""
+    print("encode outputs", prec, case, flush=True)
+    x = _data(case["kind"], case["n"], case["d"], seed=case["n"] + 5)
+    cb = _codebook(x, case["m"], case["ks"], seed=case["d"] + 5)
+    m, ds = case["m"], case["d"] // case["m"]
+    r = mipq.pq_encode_ex(_t(x), _t(cb), prec, min_dist=True, sse_rmse=True, rescored=True)
+    codes = r["codes"].cpu().numpy().astype(np.int64)
+    ref32, _, _ = pq.assign(x, cb.astype(np.float64), "fp32")
+    np.testing.assert_array_equal(codes, ref32)
+    want = np.stack([pq.dist32(pq.block(x, j, ds), cb[j]).min(axis=1) for j in range(m)], axis=1)
+    np.testing.assert_array_equal(r["min_dist"].cpu().numpy(), want)
+    sse, rmse = pq.sse_rmse(x, codes, cb.astype(np.float64))
+    got = r["sse_rmse"].cpu().numpy()
+    assert got[0] == pytest.approx(sse, rel=1e-12)
+    assert got[1] == pytest.approx(rmse, rel=1e-12)
+    _, sr = mipq.pq_decode_rmse(r["codes"], _t(cb), _t(x))
+    assert sr.cpu().numpy()[0] == pytest.approx(got[0], rel=1e-13)
+
+
+def test_encode_outputs_on_empty_input():
+    x = torch.empty((0, 128), dtype=torch.float32, device=DEV)
+    cb = torch.zeros((16, 256, 8), dtype=torch.float32, device=DEV)
+    for prec in ("fp32", "bf16"):
+        r = mipq.pq_encode_ex(x, cb, prec, min_dist=True, sse_rmse=True)
+        assert r["min_dist"].shape == (0, 16)
+        assert r["sse_rmse"].cpu().numpy().tolist() == [0.0, 0.0]
+
+
+def test_fit_reports_rescored_pairs_per_round():
+    w = wl.plain_pq(seed=4, n=3000, m=8, ks=64, iters=4)
+    out32 = mipq.pq_fit(_t(w.x), w.m, w.ks, w.iters, init_rows=_t(w.init_rows), precision="fp32", rescored=True)
+    assert out32["rescored"].cpu().numpy().tolist() == [0] * w.iters
+    out = mipq.pq_fit(_t(w.x), w.m, w.ks, w.iters, init_rows=_t(w.init_rows), precision="bf16", rescored=True)
+    r = out["rescored"].cpu().numpy()
+    assert r.shape == (w.iters,) and np.all(r >= 0)
+    # round 0 assigns against the initial codebook: the same pairs as an encode with it
+    cb0 = pq.init_codebook(w.x, w.init_rows, w.m).astype(np.float32)
+    _, resc0 = mipq.pq_encode(_t(w.x), _t(cb0), "bf16", rescored=True)
+    assert int(r[0]) == int(resc0.item())
+    print("rescored per round", r.tolist(), flush=True)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_check_finite_rejects_nan_and_inf(prec):
+    x = _data("float", 700, 64, seed=5)
+    cb = _codebook(x, 8, 32, seed=6)
+    init = wl.init_rows_per_subspace(5, x.shape[0], 8, 32)
+    clean = mipq.pq_encode_ex(_t(x), _t(cb), prec, check_finite=True)["codes"]
+    assert torch.equal(clean, mipq.pq_encode(_t(x), _t(cb), prec))
+    mipq.pq_fit(_t(x), 8, 32, 2, init_rows=_t(init), precision=prec, check_finite=True)
+    for bad in (np.nan, np.inf, -np.inf):
+        xb = x.copy()
+        xb[123, 7] = bad
+        cbb = cb.copy()
+        cbb[3, 5, 1] = bad
+        for call in (lambda: mipq.pq_encode_ex(_t(xb), _t(cb), prec, check_finite=True),
+                     lambda: mipq.pq_encode_ex(_t(x), _t(cbb), prec, check_finite=True),
+                     lambda: mipq.pq_fit(_t(xb), 8, 32, 2, init_rows=_t(init), precision=prec,
+                                         check_finite=True)):
+            with pytest.raises(mipq.MipqError) as e:
+                call()
+            assert e.value.code == mipq.ENONFINITE
+    # with a training sample, only the sampled rows are checked
+    xb = x.copy()
+    xb[1] = np.nan
+    sample = np.arange(2, x.shape[0], dtype=np.int64)
+    init_s = wl.init_rows_per_subspace(6, len(sample), 8, 32)
+    mipq.pq_fit(_t(xb), 8, 32, 2, init_rows=_t(init_s), train_rows=_t(sample), precision=prec, check_finite=True)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_deterministic_fit_repeats_bit_for_bit(prec):
+    """Real-valued rows in 5 row chunks: the fixed-order float64 sums give the
+    same codebook, labels and objective on every run, equal to the default
+    mode's to float64 rounding and to the oracle's."""
+    w = wl.plain_pq(seed=7, n=20000, m=8, ks=256, iters=4)
+    print("deterministic fit", prec, flush=True)
+    runs = [mipq.pq_fit(_t(w.x), w.m, w.ks, w.iters, init_rows=_t(w.init_rows), precision=prec, codebook64=True,
+                        deterministic=True) for _ in range(3)]
+    for r in runs[1:]:
+        assert torch.equal(r["codebook64"], runs[0]["codebook64"])
+        assert torch.equal(r["labels"], runs[0]["labels"])
+        assert torch.equal(r["objective"], runs[0]["objective"])
+    default = mipq.pq_fit(_t(w.x), w.m, w.ks, w.iters, init_rows=_t(w.init_rows), precision=prec, codebook64=True)
+    np.testing.assert_allclose(runs[0]["codebook64"].cpu().numpy(), default["codebook64"].cpu().numpy(),
+                               rtol=1e-12, atol=1e-12)
+    ref = pq.lloyd(w.x, w.init_rows, w.m, w.iters, decide="fp32")
+    np.testing.assert_allclose(runs[0]["codebook64"].cpu().numpy(), ref["codebook"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(runs[0]["objective"].cpu().numpy(), ref["objective"], rtol=1e-12)
+
+
+def test_deterministic_fit_on_integer_rows_equals_the_oracle():
+    # integer rows: every float64 sum is exact, so both modes equal the oracle bit for bit
+    w = wl.integer_pq(seed=3, n=30000, n_comp=30, m=16, ks=256, iters=3, n_train=9000)
+    out = mipq.pq_fit(_t(w.x), w.m, w.ks, w.iters, init_rows=_t(w.init_rows), train_rows=_t(w.train_rows),
+                      precision="bf16", codebook64=True, deterministic=True)
+    ref = pq.lloyd(w.train, w.init_rows, w.m, w.iters, decide="fp32")
+    np.testing.assert_array_equal(out["labels"].cpu().numpy().astype(np.int64), ref["codes"])
+    np.testing.assert_array_equal(out["codebook64"].cpu().numpy(), ref["codebook"])
