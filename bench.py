@@ -119,32 +119,76 @@ def measured_counters(counters_file: str = COUNTERS_FILE, source: str = MFMA_SOU
     return t.get("step_mix")
 
 
-def cpu_baseline(w, frac: float):
-    """The oracle, as it stands, on a bounded sample of the same workload:
-    fit on frac * n_train training rows (same rounds), encode frac * N rows."""
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+CPU_SHARE = 16   # host threads per GPU on the measurement boxes
+
+
+def oracle_threads(m: int) -> int:
+    return max(1, min(m, CPU_SHARE, os.cpu_count() or 1))
+
+
+def oracle_fit_encode(train, init, x_enc, m: int, iters: int, threads: int):
+    """The oracle's Lloyd fit and float32-rule encode, one subspace per
+    thread: the subspaces of a product quantiser are independent problems, so
+    running the oracle's functions on each subspace's columns gives its
+    results exactly (NumPy releases the GIL inside the array operations).
+    Returns (codebook, fit seconds, encode seconds)."""
     import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
 
     from oracle import pq
+
+    ds = train.shape[1] // m
+
+    def fit_one(j):
+        return pq.lloyd(np.ascontiguousarray(train[:, j * ds:(j + 1) * ds]), init[j:j + 1], 1, iters,
+                        decide="fp32")["codebook"]
+
+    def enc_one(j):
+        return pq.encode(np.ascontiguousarray(x_enc[:, j * ds:(j + 1) * ds]), cbs[j], decide="fp32")[0]
+
+    with ThreadPoolExecutor(threads) as ex:
+        t0 = time.perf_counter()
+        cbs = list(ex.map(fit_one, range(m)))
+        t1 = time.perf_counter()
+        list(ex.map(enc_one, range(m)))
+        t2 = time.perf_counter()
+    return np.concatenate(cbs, 0), t1 - t0, t2 - t1
+
+
+def cpu_baseline(w, frac: float):
+    """The oracle, as it stands, on a bounded sample of the same workload:
+    fit on frac * n_train training rows (same rounds), encode frac * N rows,
+    one subspace per host thread."""
     from synth import workloads as wl
 
     n_tr = max(w.ks, int(round(frac * len(w.train_rows))))
     n_en = int(round(frac * w.x.shape[0]))
     train = w.x[w.train_rows[:n_tr]]
     init = wl.init_rows_per_subspace(w.meta["seed"], n_tr, w.m, w.ks, key=7)
-    t0 = time.perf_counter()
-    fit = pq.lloyd(train, init, w.m, w.iters, decide="fp32")
-    t1 = time.perf_counter()
-    pq.encode(w.x[:n_en], fit["codebook"], decide="fp32")
-    t2 = time.perf_counter()
+    threads = oracle_threads(w.m)
+    _, tf, te = oracle_fit_encode(train, init, w.x[:n_en], w.m, w.iters, threads)
     return {
-        "value": n_en / (t2 - t0),
+        "value": n_en / (tf + te),
         "unit": "vectors/s",
-        "cores": 1,
+        "cores": threads,
         "host_cpus": os.cpu_count(),
+        "cpu_model": cpu_model(),
         "kind": "oracle",
         "sample": "fit on %d training rows x %d rounds, encode %d rows (%.0f%% of the workload); "
-                  "float32 decisions, numpy single thread; fit %.1fs, encode %.1fs"
-                  % (n_tr, w.iters, n_en, 100 * frac, t1 - t0, t2 - t1),
+                  "float32 decisions, one subspace per thread (%d threads); fit %.1fs, encode %.1fs"
+                  % (n_tr, w.iters, n_en, 100 * frac, threads, tf, te),
     }
 
 
@@ -336,6 +380,89 @@ def bench_integer_pq(args) -> dict:
         "cpu_baseline": base,
     }
     return res
+
+
+def bench_plain(args) -> dict:
+    """plain_pq: 10,000 x 128 rows (64-component mixture), M=8, Ks=256, 20
+    Lloyd rounds from seeded rows, encode all rows with the fused error.  The
+    step is a few dozen small launches, so it is captured once in a HIP graph
+    and replayed; the eager time is reported beside it."""
+    import numpy as np
+    import torch
+
+    import paper_2604_21645_amd as mipq
+    from paper_2604_21645_amd import _lib
+    from synth import workloads as wl
+
+    dev = torch.device("cuda:0")
+    w = wl.plain_pq()
+    n, d = w.x.shape
+    x = torch.from_numpy(w.x).to(dev)
+    init = torch.from_numpy(w.init_rows).to(dev)
+    prec = "bf16"
+
+    def step():
+        fit = mipq.pq_fit(x, w.m, w.ks, w.iters, init_rows=init, precision=prec, labels=False, objective=False)
+        enc = mipq.pq_encode_ex(x, fit["codebook"], prec, sse_rmse=True)
+        return fit["codebook"], enc["codes"], enc["sse_rmse"]
+
+    log("plain_pq eager: %d warmup + %d timed steps" % (args.warmup, args.steps))
+    ms_eager, (cb_e, codes_e, sr_e) = timed_steps(step, args.steps, args.warmup)
+    # per-kernel durations of one eager step
+    L = _lib.lib()
+    L.mipq_profile_enable(1)
+    drop_profile(L)
+    step()
+    torch.cuda.synchronize()
+    L.mipq_profile_enable(0)
+    kt = kernel_totals(L, ["assign_bf16", "update", "finalize", "pack_bf16"])
+    log("plain_pq: capturing one step in a graph")
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cs):
+        step()   # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(cs)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=cs):
+        cb_g, codes_g, sr_g = step()
+    torch.cuda.synchronize()
+    ms, _ = timed_steps(g.replay, args.steps, args.warmup)
+    same = bool(torch.equal(cb_g, cb_e) and torch.equal(codes_g, codes_e) and torch.equal(sr_g, sr_e))
+    sse, rmse = sr_g.cpu().numpy().tolist()
+    na, ta = kt["assign_bf16"]
+    fit_launches = w.iters
+    rows_per_step = w.iters * n + n
+    alg_per_launch = rows_per_step * (4 * d + w.m) / max(na, 1)
+    avg_ms = ta / max(na, 1)
+    achieved = alg_per_launch / (avg_ms * 1e-3) / 1e9 if na else 0.0
+    base = None
+    if not args.no_cpu_baseline:
+        log("oracle leg: plain_pq fit + encode on the CPU")
+        threads = oracle_threads(w.m)
+        _, tf, te = oracle_fit_encode(w.x, w.init_rows, w.x, w.m, w.iters, threads)
+        base = {"value": n / (tf + te), "unit": "vectors/s", "cores": threads, "kind": "oracle",
+                "host_cpus": os.cpu_count(), "cpu_model": cpu_model(),
+                "sample": "the whole step: 20 Lloyd rounds on all 10,000 rows and their encode, float32 "
+                          "decisions, one subspace per thread; fit %.1fs, encode %.1fs" % (tf, te)}
+    rec = base_record("PQ fit+encode vectors/s, BF16-MFMA vs FP32 plain, % codes equal to oracle", n / (ms * 1e-3),
+                      "vectors/s", args.steps, args.warmup, ms, "bf16",
+                      {"workload": "plain_pq: 10,000 x 128 rows, 64-component mixture (sigma 0.05), M=8, Ks=256, "
+                                   "20 Lloyd rounds from 256 seeded rows per subspace, encode all, RMSE",
+                       "n": n, "d": d, "m": w.m, "ks": w.ks, "iters": w.iters, "precision": prec,
+                       "parallelism": "single GPU", "launch": "one HIP graph per step"})
+    rec.update({
+        "ms_per_step_eager": ms_eager,
+        "graph_replay_identical_to_eager": same,
+        "rmse": rmse,
+        "roofline": {"bound": "hbm", "kernel": "k_assign_bf16", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "alg_bytes_per_launch": alg_per_launch, "avg_launch_ms": avg_ms, "launches": na,
+                     "note": "5 MB per launch: bound by launch and wave start-up latency, not by a roofline"},
+        "kernels_ms_per_step_eager": {k: v[1] for k, v in kt.items()},
+        "cpu_baseline": base,
+    })
+    return rec
 
 
 def bench_batched(args) -> dict:
@@ -881,8 +1008,9 @@ def bench_peaks(args) -> dict:
     return rec
 
 
-WORKLOADS = {"integer_pq": bench_integer_pq, "batched_uneven": bench_batched, "ivf_adc": bench_ivf,
-             "diff_codebooks": bench_diff, "soil_chunks": bench_soil, "opq": bench_opq, "peaks": bench_peaks}
+WORKLOADS = {"integer_pq": bench_integer_pq, "plain_pq": bench_plain, "batched_uneven": bench_batched,
+             "ivf_adc": bench_ivf, "diff_codebooks": bench_diff, "soil_chunks": bench_soil, "opq": bench_opq,
+             "peaks": bench_peaks}
 
 
 def main() -> int:
@@ -895,7 +1023,7 @@ def main() -> int:
     ap.add_argument("--fp8-steps", type=int, default=3)
     ap.add_argument("--build-steps", type=int, default=2, help="ivf_adc: timed index builds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-frac", type=float, default=0.02)
+    ap.add_argument("--cpu-frac", type=float, default=0.08)
     ap.add_argument("--batched-cpu-rows", type=int, default=8000)
     ap.add_argument("--ivf-cpu-queries", type=int, default=100)
     ap.add_argument("--diff-cpu-rows", type=int, default=20000)

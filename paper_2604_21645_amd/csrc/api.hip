@@ -64,11 +64,13 @@ struct EncodeExtraWs {
   size_t bytes = 0;
 };
 
-EncodeExtraWs carve_encode_extra(void* ws, int64_t n, int m) {
+// partials: decode_blocks of the separate distance pass, or the per-wave
+// partials of the BF16 assignment, which forms them itself
+EncodeExtraWs carve_encode_extra(void* ws, int64_t n, int m, int precision) {
   Carver c(ws);
   EncodeExtraWs e;
   e.flag = c.take<uint32_t>(4);
-  e.nblk = decode_blocks(n, m);
+  e.nblk = precision == MIPQ_BF16 ? assign_bf16_sse_parts(n, m) : decode_blocks(n, m);
   e.partials = c.take<double>(e.nblk);
   e.bytes = c.bytes();
   return e;
@@ -162,7 +164,7 @@ int assign_any(const float* x, int64_t n, int d, int m, int ks, const float* c32
                uint8_t* codes, const EncodeWs& e, int64_t* rescored, hipStream_t s) {
   if (precision == MIPQ_FP32) return launch_assign_fp32(x, n, d, m, ks, c32, codes, s);
   if (precision == MIPQ_FP8) return launch_assign_fp8(x, n, d, m, ks, e.aop, e.mu, c32, codes, rescored, s);
-  return launch_assign_bf16(x, n, d, m, ks, e.aop, e.cmax, e.mu, c32, codes, rescored, s);
+  return launch_assign_bf16(x, n, d, m, ks, e.aop, e.cmax, e.mu, c32, codes, rescored, nullptr, nullptr, s);
 }
 
 // operands of the matrix-core paths for the codebook c32
@@ -245,7 +247,7 @@ int mipq_pq_fit(const float* x, int64_t n, const int64_t* train_rows, int64_t n_
 size_t mipq_pq_encode_workspace_size(int64_t n, int d, int m, int ks, int precision) {
   if (check_shape(n, d, m, ks, precision, false) != MIPQ_OK) return 0;
   const size_t main = carve_encode(nullptr, m, ks, d / m, precision).bytes;
-  return main + carve_encode_extra(nullptr, n, m).bytes;
+  return main + carve_encode_extra(nullptr, n, m, precision).bytes;
 }
 
 int mipq_pq_encode(const float* x, int64_t n, int d, int m, int ks, const float* codebook,
@@ -257,7 +259,7 @@ int mipq_pq_encode(const float* x, int64_t n, int d, int m, int ks, const float*
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (n > 0 && (!x || !codebook || !codes)) return fail(MIPQ_EINVAL, "x, codebook and codes are required");
   EncodeWs e = carve_encode(ws, m, ks, d / m, precision);
-  EncodeExtraWs ex = carve_encode_extra(ws ? static_cast<char*>(ws) + e.bytes : nullptr, n, m);
+  EncodeExtraWs ex = carve_encode_extra(ws ? static_cast<char*>(ws) + e.bytes : nullptr, n, m, precision);
   if ((n > 0 || (flags & MIPQ_CHECK_FINITE)) && (rc = check_ws(ws, ws_bytes, e.bytes + ex.bytes))) return rc;
   if ((flags & MIPQ_CHECK_FINITE) &&
       (rc = check_finite({{x, (size_t)n * d}, {codebook, (size_t)m * ks * (d / m)}}, ex.flag, s)))
@@ -265,10 +267,16 @@ int mipq_pq_encode(const float* x, int64_t n, int d, int m, int ks, const float*
   if (rescored && (rc = launch_zero_u32(reinterpret_cast<uint32_t*>(rescored), 2, s))) return rc;
   if (n > 0) {
     if ((rc = pack_any(codebook, m, ks, d / m, precision, e, s))) return rc;
-    if ((rc = assign_any(x, n, d, m, ks, codebook, precision, codes, e, rescored, s))) return rc;
-    if ((min_dist || sse_rmse) &&
-        (rc = launch_code_dist(x, n, d, m, ks, codebook, codes, min_dist, ex.partials, ex.nblk, s)))
-      return rc;
+    if (precision == MIPQ_BF16) {   // distances and squared errors formed by the assignment itself
+      if ((rc = launch_assign_bf16(x, n, d, m, ks, e.aop, e.cmax, e.mu, codebook, codes, rescored, min_dist,
+                                   sse_rmse ? ex.partials : nullptr, s)))
+        return rc;
+    } else {
+      if ((rc = assign_any(x, n, d, m, ks, codebook, precision, codes, e, rescored, s))) return rc;
+      if ((min_dist || sse_rmse) &&
+          (rc = launch_code_dist(x, n, d, m, ks, codebook, codes, min_dist, ex.partials, ex.nblk, s)))
+        return rc;
+    }
   }
   if (sse_rmse && (rc = launch_sse_final(ex.partials, n > 0 ? ex.nblk : 0, n, d, sse_rmse, s))) return rc;
   return MIPQ_OK;

@@ -212,8 +212,12 @@ int launch_assign_fp8(const float* x, int64_t n, int d, int m, int ks, const voi
                       const float* c32, uint8_t* codes, int64_t* rescored, hipStream_t s);
 
 // rescored: optional int64 counter, incremented by the pairs re-decided exactly
+// min_dist / sse_part (either optional; both NULL: codes only): the chosen
+// centroid's float32-rule distance and per-wave float64 squared-error partials
+// (assign_bf16_sse_parts(n, m) of them, reduced by launch_sse_final)
 int launch_assign_bf16(const float* x, int64_t n, int d, int m, int ks, const void* aop,
                        const float* cmax, const float* mu, const float* c32, uint8_t* codes,
-                       int64_t* rescored, hipStream_t s);
+                       int64_t* rescored, float* min_dist, double* sse_part, hipStream_t s);
+int assign_bf16_sse_parts(int64_t n, int m);
 
 }  // namespace mipq

@@ -203,7 +203,7 @@ __device__ __forceinline__ void load_rows(float (&xv)[DW], const float* __restri
 // and register (hence its index), and the runner-up (two candidates of one
 // lane differ in tile or in register); then the lane pair merges.
 template <int NT, class TileFn>
-__device__ __forceinline__ int reduce_scores(TileFn tile, float& f1, float& f2) {
+__device__ __forceinline__ void lane_keys(TileFn tile, int& a1o, int& s2o, int& rlo) {
   float amin[NT];
   float bmin[16];
 #pragma unroll
@@ -239,21 +239,33 @@ __device__ __forceinline__ int reduce_scores(TileFn tile, float& f1, float& f2) 
     b2 = min(b2, med3i(ka, kb, b1));   // runner-up of {b1, b2, ka, kb}, b1 <= b2
     b1 = min(b1, min(ka, kb));
   }
-  const int rl = b1 & 15;
-  const int s2 = min(a2, b2);
+  a1o = a1;
+  s2o = min(a2, b2);
+  rlo = b1 & 15;
+}
 
-  // merge the two lanes holding the candidates of a row
-  const int2 A1 = halves(a1);
-  const int2 S2 = halves(s2);
-  const int2 RL = halves(rl);
-  const bool hiw = A1.y < A1.x;
-  const int w1 = min(A1.x, A1.y);
-  const int sec = min(max(A1.x, A1.y), min(S2.x, S2.y));
-  const int tw = (hiw ? A1.y : A1.x) & 7;
-  const int rw = hiw ? RL.y : RL.x;
+// Merge of the keys of the two lanes holding one row's candidates (x: the
+// lane of half 0, y: half 1): best estimate f1, runner-up f2, winning index.
+__device__ __forceinline__ int merge_keys(int a1x, int a1y, int s2x, int s2y, int rlx, int rly, float& f1,
+                                          float& f2) {
+  const bool hiw = a1y < a1x;
+  const int w1 = min(a1x, a1y);
+  const int sec = min(max(a1x, a1y), min(s2x, s2y));
+  const int tw = (hiw ? a1y : a1x) & 7;
+  const int rw = hiw ? rly : rlx;
   f1 = __int_as_float(w1);
   f2 = __int_as_float(sec);
   return tw * 32 + (rw >> 2) * 8 + (hiw ? 4 : 0) + (rw & 3);
+}
+
+template <int NT, class TileFn>
+__device__ __forceinline__ int reduce_scores(TileFn tile, float& f1, float& f2) {
+  int a1, s2, rl;
+  lane_keys<NT>(tile, a1, s2, rl);
+  const int2 A1 = halves(a1);
+  const int2 S2 = halves(s2);
+  const int2 RL = halves(rl);
+  return merge_keys(A1.x, A1.y, S2.x, S2.y, RL.x, RL.y, f1, f2);
 }
 
 // Separation test: true when the two best estimates f1 <= f2 (error at most
@@ -337,10 +349,14 @@ __device__ __forceinline__ int decide_tile(const float (&xraw)[NB * 8], const Su
 // (distance, index) minimum over the lanes.
 // REG false (kernels with no registers to spare): the rows one at a time with
 // the centroids read for each row (exact_code_wave), the same arithmetic.
-template <int DW, bool REG>
+// OUT (REG only): also the exact distance of the winner (min_dist, optional)
+// and the float64 squared error of the row's subspace block, added to *sse
+// by lane 0.
+template <int DW, bool REG, bool OUT = false>
 __device__ __forceinline__ void redecide(const uint32_t* pend, int np, const float* __restrict__ x, int d, int m,
                                          int ks, int ds, int sub, const float* __restrict__ cbsub,
-                                         uint8_t* __restrict__ codes, int lane) {
+                                         uint8_t* __restrict__ codes, int lane, float* __restrict__ min_dist = nullptr,
+                                         double* sse = nullptr) {
   if (np == 0) return;   // wave-uniform
   if (!REG) {
     for (int i = 0; i < np; ++i) {
@@ -404,7 +420,22 @@ __device__ __forceinline__ void redecide(const uint32_t* pend, int np, const flo
         bk = ok;
       }
     }
-    if (lane == 0) codes[prow * m + sub] = (uint8_t)(bk < ks ? bk : 0);
+    const int code = bk < ks ? bk : 0;
+    if (lane == 0) {
+      codes[prow * m + sub] = (uint8_t)code;
+      if (OUT) {
+        if (min_dist) min_dist[prow * m + sub] = best;
+        const float* c = cbsub + (int64_t)code * ds;
+        double sq = 0.0;
+#pragma unroll
+        for (int t = 0; t < DW; ++t)
+          if (t < ds) {
+            const double dd = (double)xo[t] - (double)c[t];
+            sq = sq + dd * dd;
+          }
+        *sse += sq;
+      }
+    }
   }
 }
 
@@ -451,33 +482,239 @@ __device__ __forceinline__ uint32_t assign_rows(const float* __restrict__ x, int
   return nres + (uint32_t)np;
 }
 
-// One problem: block = (row block, group of 4 subspaces), one subspace per wave.
-template <int NB, int NT, bool FULL>
-__global__ __launch_bounds__(kThreads) void k_assign_bf16(
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+// Row-side operand parts of one row: its centred subspace slice's squared
+// norm xn, the bfloat16 high and low parts and the three pieces of xn (the
+// arithmetic of decide_tile).
+template <int NB>
+struct RowParts {
+  bf16x8 XH[NB], XL[NB], normB;
+  float xn;
+};
+
+template <int NB>
+__device__ __forceinline__ void row_parts(const float (&xraw)[NB * 8], const float (&muv)[NB * 8],
+                                          RowParts<NB>& r) {
+  constexpr int DW = NB * 8;
+  float xv[DW];
+#pragma unroll
+  for (int e = 0; e < DW; ++e) xv[e] = xraw[e] - muv[e];
+  float xn = 0.0f;
+#pragma unroll
+  for (int e = 0; e < DW; ++e) xn = xn + xv[e] * xv[e];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    r.XH[b] = to_bf16x8(xv + b * 8);
+    float rem[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) rem[e] = xv[b * 8 + e] - (float)r.XH[b][e];
+    r.XL[b] = to_bf16x8(rem);
+  }
+  const __bf16 h = (__bf16)xn;
+  const float r1 = xn - (float)h;
+  const __bf16 md = (__bf16)r1;
+  r.normB = bf16x8{};
+  r.normB[0] = r.normB[1] = r.normB[2] = (__bf16)1.0f;
+  r.normB[3] = h;
+  r.normB[4] = md;
+  r.normB[5] = (__bf16)(r1 - (float)md);
+  r.xn = xn;
+}
+
+// [p.lo | q.lo] and [p.hi | q.hi] (lo: lanes 0-31, hi: lanes 32-63), one
+// v_permlane32_swap per dword
+__device__ __forceinline__ void swap_halves(const bf16x8& p, const bf16x8& q, bf16x8& lo, bf16x8& hi) {
+  const i32x4 pi = __builtin_bit_cast(i32x4, p), qi = __builtin_bit_cast(i32x4, q);
+  i32x4 a, b;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const auto r = __builtin_amdgcn_permlane32_swap(pi[w], qi[w], false, false);
+    a[w] = (int)r[0];
+    b[w] = (int)r[1];
+  }
+  lo = __builtin_bit_cast(bf16x8, a);
+  hi = __builtin_bit_cast(bf16x8, b);
+}
+__device__ __forceinline__ void swap_halves(int p, int q, int& lo, int& hi) {
+  const auto r = __builtin_amdgcn_permlane32_swap(p, q, false, false);
+  lo = (int)r[0];
+  hi = (int)r[1];
+}
+
+// Row operands of both 32-row groups of a 64-row step from the lanes' own
+// rows (lanes 0-31: group A, 32-63: group B).  MFMA f takes P_f of the row
+// on lanes 0-31 and Q_f on lanes 32-63 (the layout of decide_tile's B); a
+// swap of P_f with Q_f leaves [P_f(A) | Q_f(A)] and [P_f(B) | Q_f(B)].
+template <int NB>
+__device__ __forceinline__ void row_operands(const RowParts<NB>& r, bf16x8 (&BA)[bf16_nmfma(NB)],
+                                             bf16x8 (&BB)[bf16_nmfma(NB)]) {
+  constexpr int NMF = bf16_nmfma(NB);
+  const bf16x8 zero8 = {};
+#pragma unroll
+  for (int f = 0; f < NMF; ++f) {
+    bf16x8 P, Q;
+    if (f < NB) {
+      P = r.XH[f];
+      Q = r.XH[f];
+    } else if (f < NB + (NB + 1) / 2) {
+      const int b0 = 2 * (f - NB);
+      P = r.XL[b0];
+      Q = (b0 + 1 < NB) ? r.XL[b0 + 1 < NB ? b0 + 1 : 0] : r.normB;
+    } else {
+      P = r.normB;
+      Q = zero8;
+    }
+    swap_halves(P, Q, BA[f], BB[f]);
+  }
+}
+
+// Raw subspace slice of row r0 + lane (clamped to r0 past rend).
+template <int DW, bool FULL>
+__device__ __forceinline__ void load_own_row(float (&xv)[DW], const float* __restrict__ x, int64_t r0, int64_t rend,
+                                             int d, int sub, int ds, int lane) {
+  const int64_t row = r0 + lane;
+  const float* xr = x + (row < rend ? row : r0) * d + (int64_t)sub * ds;
+  if (FULL) {
+#pragma unroll
+    for (int e = 0; e < DW; e += 4) {
+      const float4 v = *reinterpret_cast<const float4*>(xr + e);
+      xv[e] = v.x;
+      xv[e + 1] = v.y;
+      xv[e + 2] = v.z;
+      xv[e + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < DW; ++e) {
+      const float v = xr[e < ds ? e : ds - 1];
+      xv[e] = (e < ds) ? v : 0.0f;
+    }
+  }
+}
+
+// One problem: block = (row block, group of 4 subspaces), one subspace per
+// wave, 64 rows per step; lane l owns row r0 + l (lanes 0-31 form the step's
+// first 32-row group A, lanes 32-63 the second, B).  Every lane prepares
+// the operand parts of its own row; row_operands hands each lane its half's
+// operands in both groups; both groups' tiles run on the matrix cores and
+// each lane reduces its half of the candidates of group A's and group B's row
+// (lane_keys); one swap per key brings the two halves of a row to the row's
+// own lane, so the merge, the separation test, the code store and (OUT) the
+// distance of the chosen centroid and its float64 squared error run once per
+// row.  Ambiguous rows are re-decided by the whole wave after the loop.
+// OUT: min_dist (optional) and per-wave squared-error partials
+// sse_part[block * 4 + wave] (every wave writes its slot).
+template <int NB, int NT, bool FULL, bool OUT>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NB == 1 ? 3 : 1, 8))) void k_assign_bf16(
     const float* __restrict__ x, int64_t n, int d, int m, int ks, int ds,
     const bf16x8* __restrict__ aop, const float* __restrict__ cmax, const float* __restrict__ mu,
     const float* __restrict__ c32, uint8_t* __restrict__ codes,
     unsigned long long* __restrict__ rescored, int groups, int rpb, float e_cross, float e_norm,
-    float g_exact) {
+    float g_exact, float* __restrict__ min_dist, double* __restrict__ sse_part) {
+  constexpr int DW = NB * 8;
+  constexpr int NMF = bf16_nmfma(NB);
   const XcdMap bm = xcd_map(blockIdx.x, groups);
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int sub = bm.group * 4 + w;
   const int64_t rbeg = (int64_t)bm.rowblk * rpb;
-  if (sub >= m || rbeg >= n) return;
-  const int64_t rend = min(n, rbeg + rpb);
-  SubOps<NB, NT> o;
-  load_sub_ops<NB, NT>(o, aop, cmax, mu, sub, lane);
-  // LDS: rpb list entries per wave, so the list cannot overflow
-  extern __shared__ uint32_t pend_all[];
-  const Band bd{e_cross, e_norm, g_exact};
-  auto decide = [&](const float (&xv)[NB * 8], int half, bool& amb) {
-    return decide_tile<NB, NT>(xv, o, half, ks, bd, amb);
-  };
-  const uint32_t nres = assign_rows<NB * 8, FULL, false, true>(x, d, ds, m, ks, sub, rbeg, rend, decide,
-                                                         c32 + (int64_t)sub * ks * ds, codes, pend_all + w * rpb,
-                                                         0, lane);
-  if (rescored && lane == 0 && nres) atomicAdd(rescored, (unsigned long long)nres);
+  double sse = 0.0;
+  if (sub < m && rbeg < n) {
+    const int64_t rend = min(n, rbeg + rpb);
+    SubOps<NB, NT> o;
+    load_sub_ops<NB, NT>(o, aop, cmax, mu, sub, lane);
+    // LDS: rpb list entries per wave, so the list cannot overflow
+    extern __shared__ uint32_t pend_all[];
+    uint32_t* pend = pend_all + w * rpb;
+    const Band bd{e_cross, e_norm, g_exact};
+    const float* cbsub = c32 + (int64_t)sub * ks * ds;
+    int np = 0;
+    float xnext[DW];
+    load_own_row<DW, FULL>(xnext, x, rbeg, rend, d, sub, ds, lane);
+    for (int64_t r0 = rbeg; r0 < rend; r0 += 64) {
+      float xv[DW];
+#pragma unroll
+      for (int e = 0; e < DW; ++e) xv[e] = xnext[e];
+      if (r0 + 64 < rend) load_own_row<DW, FULL>(xnext, x, r0 + 64, rend, d, sub, ds, lane);   // next step in flight
+      const int64_t row = r0 + lane;
+      const bool valid = row < rend;
+      RowParts<NB> rp;
+      row_parts<NB>(xv, o.muv, rp);
+      bf16x8 BA[NMF], BB[NMF];
+      row_operands<NB>(rp, BA, BB);
+      int a1A, s2A, rlA, a1B, s2B, rlB;
+      lane_keys<NT>([&](int t) {
+        f32x16 acc = {};
+#pragma unroll
+        for (int f = 0; f < NMF; ++f) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.A[t][f], BA[f], acc, 0, 0, 0);
+        return acc;
+      }, a1A, s2A, rlA);
+      lane_keys<NT>([&](int t) {
+        f32x16 acc = {};
+#pragma unroll
+        for (int f = 0; f < NMF; ++f) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.A[t][f], BB[f], acc, 0, 0, 0);
+        return acc;
+      }, a1B, s2B, rlB);
+      // lanes 0-31: both halves of group A's row; lanes 32-63: group B's
+      int a1x, a1y, s2x, s2y, rlx, rly;
+      swap_halves(a1A, a1B, a1x, a1y);
+      swap_halves(s2A, s2B, s2x, s2y);
+      swap_halves(rlA, rlB, rlx, rly);
+      float f1, f2;
+      const int code = merge_keys(a1x, a1y, s2x, s2y, rlx, rly, f1, f2);
+      const float xnorm = sqrtf(rp.xn) * 1.0001f;
+      const float beta = bd.e_cross * xnorm * o.cm + bd.e_norm * (o.cm * o.cm + rp.xn);
+      const bool amb = not_separated(f1, f2, beta, bd.g_exact, rp.xn) || code >= ks;
+      if (valid) codes[row * m + sub] = (uint8_t)code;
+      const bool push = valid && amb;
+      const uint64_t mask = __ballot(push);
+      if (mask) {
+        if (push) pend[np + __popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)row;
+        np += __popcll(mask);
+      }
+      if (OUT && valid && !amb) {   // the chosen centroid's distance and squared error
+        // the row again (from cache): keeping it live through the matrix-core
+        // phase would cost registers and occupancy
+        load_own_row<DW, FULL>(xv, x, r0, rend, d, sub, ds, lane);
+        const float* c = cbsub + (int64_t)code * ds;
+        float cv[DW];
+        if (FULL) {
+#pragma unroll
+          for (int e = 0; e < DW; e += 4) {
+            const float4 v = *reinterpret_cast<const float4*>(c + e);
+            cv[e] = v.x;
+            cv[e + 1] = v.y;
+            cv[e + 2] = v.z;
+            cv[e + 3] = v.w;
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < DW; ++e) cv[e] = c[e < ds ? e : ds - 1];
+        }
+        float dist = 0.0f;
+        double sq = 0.0;
+#pragma unroll
+        for (int t = 0; t < DW; ++t)
+          if (t < ds) {
+            const float df = xv[t] - cv[t];
+            const float s2 = df * df;
+            dist = dist + s2;
+            const double dd = (double)xv[t] - (double)cv[t];
+            sq = sq + dd * dd;
+          }
+        if (min_dist) min_dist[row * m + sub] = dist;
+        sse += sq;
+      }
+    }
+    redecide<DW, true, OUT>(pend, np, x, d, m, ks, ds, sub, cbsub, codes, lane, min_dist, &sse);
+    if (rescored && lane == 0 && np) atomicAdd(rescored, (unsigned long long)np);
+  }
+  if (OUT && sse_part) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sse += __shfl_xor(sse, off, 64);
+    if (lane == 0) sse_part[blockIdx.x * 4 + w] = sse;
+  }
 }
 
 // Many problems in one persistent launch.  The work is the list of units
@@ -844,7 +1081,8 @@ Bf16Geom bf16_geometry(int64_t n, int m) {
   g.groups = ceil_div(m, 4);
   // one round of resident blocks (three per CU: the assignment kernels' register
   // use allows three waves per SIMD), so no partly filled last round; at most
-  // 64 row tiles per block.  (On 100k-row fit launches: 61 us against 65 us
+  // 64 row tiles per block, an even number (the single-problem kernel steps
+  // 64 rows at a time).  (On 100k-row fit launches: 61 us against 65 us
   // with ~8 blocks per CU.)
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
@@ -855,6 +1093,7 @@ Bf16Geom bf16_geometry(int64_t n, int m) {
   int64_t tpb = (row_tiles * g.groups + resident - 1) / resident;
   if (tpb < 1) tpb = 1;
   if (tpb > 64) tpb = 64;
+  tpb = (tpb + 1) & ~int64_t(1);   // whole 64-row steps
   g.rpb = int(tpb * 32);
   g.rowblks = n > 0 ? ceil_div(n, g.rpb) : 0;
   g.blocks = ceil_div(g.rowblks, 8) * 8 * g.groups;
@@ -879,7 +1118,7 @@ Band band_for(int ds) {
 
 int launch_assign_bf16(const float* x, int64_t n, int d, int m, int ks, const void* aop,
                        const float* cmax, const float* mu, const float* c32, uint8_t* codes,
-                       int64_t* rescored, hipStream_t s) {
+                       int64_t* rescored, float* min_dist, double* sse_part, hipStream_t s) {
   const int ds = d / m;
   const int nb = (ds + 7) / 8;
   const int nt = tiles_for(ks);
@@ -887,19 +1126,24 @@ int launch_assign_bf16(const float* x, int64_t n, int d, int m, int ks, const vo
   if (g.blocks == 0) return MIPQ_OK;
   const Band bd = band_for(ds);
   ProfScope ps(MIPQ_K_ASSIGN_BF16, s);
-  const bool full = (ds == nb * 8) && (d % 4 == 0) && ((reinterpret_cast<uintptr_t>(x) & 15) == 0);
+  const bool full = (ds == nb * 8) && (d % 4 == 0) &&
+                    (((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(c32)) & 15) == 0);
+  const bool out = min_dist || sse_part;
   unsigned long long* resc = reinterpret_cast<unsigned long long*>(rescored);
   const size_t pend_bytes = (size_t)(kThreads / 64) * g.rpb * sizeof(uint32_t);
-#define LAUNCH(NB, NT)                                                                              \
-  do {                                                                                              \
-    if (full)                                                                                       \
-      k_assign_bf16<NB, NT, true><<<g.blocks, kThreads, pend_bytes, s>>>(                           \
-          x, n, d, m, ks, ds, (const bf16x8*)aop, cmax, mu, c32, codes, resc, g.groups, g.rpb,      \
-          bd.e_cross, bd.e_norm, bd.g_exact);                                                       \
-    else                                                                                            \
-      k_assign_bf16<NB, NT, false><<<g.blocks, kThreads, pend_bytes, s>>>(                          \
-          x, n, d, m, ks, ds, (const bf16x8*)aop, cmax, mu, c32, codes, resc, g.groups, g.rpb,      \
-          bd.e_cross, bd.e_norm, bd.g_exact);                                                       \
+#define LAUNCH1(NB, NT, FULL, OUT)                                                                  \
+  k_assign_bf16<NB, NT, FULL, OUT><<<g.blocks, kThreads, pend_bytes, s>>>(                          \
+      x, n, d, m, ks, ds, (const bf16x8*)aop, cmax, mu, c32, codes, resc, g.groups, g.rpb, bd.e_cross, \
+      bd.e_norm, bd.g_exact, min_dist, sse_part)
+#define LAUNCH(NB, NT)                                 \
+  do {                                                 \
+    if (full) {                                        \
+      if (out) LAUNCH1(NB, NT, true, true);            \
+      else LAUNCH1(NB, NT, true, false);               \
+    } else {                                           \
+      if (out) LAUNCH1(NB, NT, false, true);           \
+      else LAUNCH1(NB, NT, false, false);              \
+    }                                                  \
   } while (0)
   if (nb == 1) {
     switch (nt) {
@@ -917,9 +1161,12 @@ int launch_assign_bf16(const float* x, int64_t n, int d, int m, int ks, const vo
     }
   }
 #undef LAUNCH
+#undef LAUNCH1
   MIPQ_LAUNCHED("k_assign_bf16");
   return MIPQ_OK;
 }
+
+int assign_bf16_sse_parts(int64_t n, int m) { return 4 * bf16_geometry(n, m).blocks; }
 
 namespace {
 template <int NB, int NT, bool FULL>

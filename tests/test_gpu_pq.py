@@ -6,6 +6,8 @@ and the float64 oracle's codes outside its near-ties; centroids, objective and
 RMSE are compared with tolerances derived from float64 summation order.
 """
 
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -280,3 +282,74 @@ def test_deterministic_fit_on_integer_rows_equals_the_oracle():
     ref = pq.lloyd(w.train, w.init_rows, w.m, w.iters, decide="fp32")
     np.testing.assert_array_equal(out["labels"].cpu().numpy().astype(np.int64), ref["codes"])
     np.testing.assert_array_equal(out["codebook64"].cpu().numpy(), ref["codebook"])
+
+
+@pytest.fixture(scope="module")
+def plain_golden():
+    return np.load(os.path.join(os.path.dirname(__file__), "golden", "plain_pq_fit.npz"), allow_pickle=False)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_plain_pq_full_shape(prec, plain_golden):
+    """The plain PQ configuration at its stated shape: 10,000 x 128 rows from a
+    64-component mixture (sigma 0.05), M=8 subspaces of 16 dimensions, Ks=256,
+    20 Lloyd rounds from 256 seeded rows per subspace, all rows encoded, RMSE.
+    Against the oracle's stored run (tests/golden/make_plain_pq_fit.py)."""
+    g = plain_golden
+    w = wl.plain_pq()
+    assert (w.x.shape, w.m, w.ks, w.iters) == ((10000, 128), 8, 256, 20)
+    xt = _t(w.x)
+    print("plain_pq full shape", prec, flush=True)
+    fit = mipq.pq_fit(xt, w.m, w.ks, w.iters, init_rows=_t(w.init_rows), precision=prec, codebook64=True,
+                      rescored=True)
+    np.testing.assert_array_equal(fit["labels"].cpu().numpy(), g["labels"])
+    np.testing.assert_allclose(fit["codebook64"].cpu().numpy(), g["codebook"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_array_equal(fit["codebook"].cpu().numpy(), g["codebook"].astype(np.float32))
+    np.testing.assert_allclose(fit["objective"].cpu().numpy(), g["objective"], rtol=1e-12)
+    enc = mipq.pq_encode_ex(xt, fit["codebook"], prec, sse_rmse=True, rescored=True)
+    codes = enc["codes"].cpu().numpy()
+    np.testing.assert_array_equal(codes, g["codes"])
+    tie = np.unpackbits(g["codes_near_tie"])[:codes.size].reshape(codes.shape).astype(bool)
+    assert np.all(codes[~tie] == g["codes_fp64_decision"][~tie])
+    sr = enc["sse_rmse"].cpu().numpy()
+    assert sr[0] == pytest.approx(g["sse_rmse"][0], rel=1e-12)
+    assert sr[1] == pytest.approx(g["sse_rmse"][1], rel=1e-12)
+    # against a fit that decides in float64 throughout: RMSE within 1e-4 relative
+    assert sr[1] == pytest.approx(g["rmse_fp64_fit"][0], rel=1e-4)
+    print("near-ties per round", g["near_ties"].tolist(), "final", int(tie.sum()),
+          "re-decided per round", fit["rescored"].cpu().numpy().tolist(), flush=True)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_fit_encode_step_replays_from_a_graph(prec):
+    """A fit + encode-with-error step captured once in a HIP graph: every
+    replay, with other eager work and synchronisations between the replays and
+    the outputs cleared before each, equals the eager step bit for bit."""
+    w = wl.plain_pq(seed=9, n=3000, m=8, ks=256, iters=5)
+    x, init = _t(w.x), _t(w.init_rows)
+
+    def step():
+        fit = mipq.pq_fit(x, w.m, w.ks, w.iters, init_rows=init, precision=prec, labels=False, objective=False)
+        enc = mipq.pq_encode_ex(x, fit["codebook"], prec, sse_rmse=True, min_dist=True)
+        return fit["codebook"], enc["codes"], enc["sse_rmse"], enc["min_dist"]
+
+    ref = [t.clone() for t in step()]
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cs):
+        step()
+    torch.cuda.current_stream().wait_stream(cs)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=cs):
+        out = step()
+    other = _t(np.ascontiguousarray(w.x[::-1]))
+    for rep in range(3):
+        mipq.pq_encode_ex(other, ref[0], prec, sse_rmse=True)   # eager work between replays
+        for t in out:
+            t.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(out, ref):
+            assert torch.equal(a, b), rep

@@ -592,3 +592,25 @@ def test_first_outer_iteration_is_plain_pq_and_objective_falls():
     assert np.all(np.diff(obj) <= 1e-5 * obj[:-1])
     assert obj[-1] < 0.97 * e_pq
     np.testing.assert_allclose(fit["R"].T @ fit["R"], np.eye(16), atol=1e-12)
+
+
+def test_plain_pq_golden_file_is_the_oracles():
+    """The stored results of the 10,000-row plain PQ workload (written by
+    tests/golden/make_plain_pq_fit.py from the oracle) agree with a fresh oracle
+    run on its first two rounds and on a sample of the final codes."""
+    g = np.load(os.path.join(GOLDEN, "plain_pq_fit.npz"), allow_pickle=False)
+    w = wl.plain_pq()
+    two = pq.lloyd(w.x, w.init_rows, w.m, 2, decide="fp32")
+    np.testing.assert_array_equal(two["objective"], g["objective"][:2])
+    np.testing.assert_array_equal(two["near_ties"], g["near_ties"][:2])
+    obj = g["objective"]
+    assert np.all(np.diff(obj) <= 1e-12 * obj[:-1])
+    rows = np.arange(0, w.x.shape[0], 97)
+    c32, _, tie = pq.assign(w.x[rows], g["codebook"], "fp32")
+    c64, _, _ = pq.assign(w.x[rows], g["codebook"], "fp64")
+    np.testing.assert_array_equal(c32, g["codes"][rows])
+    np.testing.assert_array_equal(c64, g["codes_fp64_decision"][rows])
+    full_tie = np.unpackbits(g["codes_near_tie"])[:w.x.shape[0] * w.m].reshape(w.x.shape[0], w.m).astype(bool)
+    np.testing.assert_array_equal(tie, full_tie[rows])
+    sse, rmse = pq.sse_rmse(w.x, g["codes"].astype(np.int64), g["codebook"])
+    assert (sse, rmse) == tuple(g["sse_rmse"])
