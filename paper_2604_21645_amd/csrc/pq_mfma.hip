@@ -277,69 +277,6 @@ __device__ __forceinline__ bool not_separated(float f1, float f2, float beta, fl
   return !(f2 - f1 > thr);
 }
 
-// BF16 matrix-core decision for the row held by lanes l and l^32 (raw slice
-// xraw): returns the winning candidate and sets amb when the two best are not
-// separated by the error bound (then the exact rule must decide).
-template <int NB, int NT>
-__device__ __forceinline__ int decide_tile(const float (&xraw)[NB * 8], const SubOps<NB, NT>& o, int half, int ks,
-                                           const Band& bd, bool& amb) {
-  constexpr int NMF = SubOps<NB, NT>::NMF;
-  constexpr int DW = NB * 8;
-  float xv[DW];   // centred row slice
-#pragma unroll
-  for (int e = 0; e < DW; ++e) xv[e] = xraw[e] - o.muv[e];
-
-  // row operands
-  float xn = 0.0f;
-#pragma unroll
-  for (int e = 0; e < DW; ++e) xn = xn + xv[e] * xv[e];
-  bf16x8 XH[NB], XL[NB];
-#pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    XH[b] = to_bf16x8(xv + b * 8);
-    float rem[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) rem[e] = xv[b * 8 + e] - (float)XH[b][e];
-    XL[b] = to_bf16x8(rem);
-  }
-  const bf16x8 zero8 = {};
-  bf16x8 normB = {};
-  {
-    const __bf16 h = (__bf16)xn;
-    const float r1 = xn - (float)h;
-    const __bf16 md = (__bf16)r1;
-    normB[0] = normB[1] = normB[2] = (__bf16)1.0f;
-    normB[3] = h;
-    normB[4] = md;
-    normB[5] = (__bf16)(r1 - (float)md);
-  }
-  bf16x8 B[NMF];
-#pragma unroll
-  for (int f = 0; f < NMF; ++f) {
-    if (f < NB) {
-      B[f] = XH[f];
-    } else if (f < NB + (NB + 1) / 2) {
-      const int b0 = 2 * (f - NB);
-      if (b0 + 1 < NB) B[f] = half ? XL[b0 + 1] : XL[b0];
-      else B[f] = half ? normB : XL[b0];
-    } else {
-      B[f] = half ? zero8 : normB;
-    }
-  }
-  auto tile = [&](int t) {
-    f32x16 acc = {};
-#pragma unroll
-    for (int f = 0; f < NMF; ++f) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.A[t][f], B[f], acc, 0, 0, 0);
-    return acc;
-  };
-  float f1, f2;
-  const int code = reduce_scores<NT>(tile, f1, f2);
-  const float xnorm = sqrtf(xn) * 1.0001f;
-  const float beta = bd.e_cross * xnorm * o.cm + bd.e_norm * (o.cm * o.cm + xn);
-  amb = not_separated(f1, f2, beta, bd.g_exact, xn) || code >= ks;
-  return code;
-}
-
 // The exact rule for the np pending rows (absolute row indices) of subspace
 // sub by the whole wave, one row after another; overwrites their codes.  Lane
 // i holds centroids i, i+64, i+128, i+192 (ks <= 256) in registers for all the
@@ -357,6 +294,7 @@ __device__ __forceinline__ void redecide(const uint32_t* pend, int np, const flo
                                          int ks, int ds, int sub, const float* __restrict__ cbsub,
                                          uint8_t* __restrict__ codes, int lane, float* __restrict__ min_dist = nullptr,
                                          double* sse = nullptr) {
+  static_assert(REG || !OUT, "the fused outputs need the register form");
   if (np == 0) return;   // wave-uniform
   if (!REG) {
     for (int i = 0; i < np; ++i) {
@@ -484,9 +422,11 @@ __device__ __forceinline__ uint32_t assign_rows(const float* __restrict__ x, int
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
-// Row-side operand parts of one row: its centred subspace slice's squared
-// norm xn, the bfloat16 high and low parts and the three pieces of xn (the
-// arithmetic of decide_tile).
+// Row-side operand parts of one row: its slice centred by mu, the squared
+// norm xn of the centred slice (float32, dimensions ascending), the
+// bfloat16 high parts XH and low parts XL (of the remainders), and normB =
+// [1, 1, 1, xn_hi, xn_mid, xn_lo, 0, 0], the pieces of xn against the ones of
+// the centroid norm slots (see bf16_pack.h for the operand layout).
 template <int NB>
 struct RowParts {
   bf16x8 XH[NB], XL[NB], normB;
@@ -544,7 +484,8 @@ __device__ __forceinline__ void swap_halves(int p, int q, int& lo, int& hi) {
 
 // Row operands of both 32-row groups of a 64-row step from the lanes' own
 // rows (lanes 0-31: group A, 32-63: group B).  MFMA f takes P_f of the row
-// on lanes 0-31 and Q_f on lanes 32-63 (the layout of decide_tile's B); a
+// on lanes 0-31 and Q_f on lanes 32-63 (bf16_pack.h: [xh | xh] for the
+// first NB, [xl_b | xl_b+1 or normB] for the pairs, [normB | 0] last); a
 // swap of P_f with Q_f leaves [P_f(A) | Q_f(A)] and [P_f(B) | Q_f(B)].
 template <int NB>
 __device__ __forceinline__ void row_operands(const RowParts<NB>& r, bf16x8 (&BA)[bf16_nmfma(NB)],
@@ -593,18 +534,112 @@ __device__ __forceinline__ void load_own_row(float (&xv)[DW], const float* __res
   }
 }
 
+// Rows [rb, re) of subspace sub by one wave, 64 rows per step; lane l owns
+// row r0 + l (lanes 0-31 form the step's first 32-row group A, lanes 32-63
+// the second, B).  Every lane prepares the operand parts of its own row;
+// row_operands hands each lane its half's operands in both groups; both
+// groups' tiles run on the matrix cores and each lane reduces its half of the
+// candidates of group A's and group B's row (lane_keys); one swap per key
+// brings the two halves of a row to the row's own lane, so the merge, the
+// separation test, the code store and (OUT) the distance of the chosen
+// centroid and its float64 squared error run once per row.  Ambiguous rows
+// are queued in the wave's LDS list `pend` (room for re - rb entries) and
+// re-decided by the whole wave after the loop.  Returns the number of
+// re-decided rows; OUT adds the squared errors to *sse (lane-local sums).
+template <int NB, int NT, bool FULL, bool OUT, bool REG>
+__device__ __forceinline__ int assign_rows64(const SubOps<NB, NT>& o, const Band& bd, const float* __restrict__ x,
+                                             int d, int ds, int m, int ks, int sub, int64_t rb, int64_t re,
+                                             const float* __restrict__ cbsub, uint8_t* __restrict__ codes,
+                                             uint32_t* pend, int lane, float* __restrict__ min_dist,
+                                             double* sse) {
+  constexpr int DW = NB * 8;
+  constexpr int NMF = bf16_nmfma(NB);
+  int np = 0;
+  float xnext[DW];
+  load_own_row<DW, FULL>(xnext, x, rb, re, d, sub, ds, lane);
+  for (int64_t r0 = rb; r0 < re; r0 += 64) {
+    float xv[DW];
+#pragma unroll
+    for (int e = 0; e < DW; ++e) xv[e] = xnext[e];
+    if (r0 + 64 < re) load_own_row<DW, FULL>(xnext, x, r0 + 64, re, d, sub, ds, lane);   // next step in flight
+    const int64_t row = r0 + lane;
+    const bool valid = row < re;
+    RowParts<NB> rp;
+    row_parts<NB>(xv, o.muv, rp);
+    bf16x8 BA[NMF], BB[NMF];
+    row_operands<NB>(rp, BA, BB);
+    int a1A, s2A, rlA, a1B, s2B, rlB;
+    lane_keys<NT>([&](int t) {
+      f32x16 acc = {};
+#pragma unroll
+      for (int f = 0; f < NMF; ++f) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.A[t][f], BA[f], acc, 0, 0, 0);
+      return acc;
+    }, a1A, s2A, rlA);
+    lane_keys<NT>([&](int t) {
+      f32x16 acc = {};
+#pragma unroll
+      for (int f = 0; f < NMF; ++f) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.A[t][f], BB[f], acc, 0, 0, 0);
+      return acc;
+    }, a1B, s2B, rlB);
+    // lanes 0-31: both halves of group A's row; lanes 32-63: group B's
+    int a1x, a1y, s2x, s2y, rlx, rly;
+    swap_halves(a1A, a1B, a1x, a1y);
+    swap_halves(s2A, s2B, s2x, s2y);
+    swap_halves(rlA, rlB, rlx, rly);
+    float f1, f2;
+    const int code = merge_keys(a1x, a1y, s2x, s2y, rlx, rly, f1, f2);
+    const float xnorm = sqrtf(rp.xn) * 1.0001f;
+    const float beta = bd.e_cross * xnorm * o.cm + bd.e_norm * (o.cm * o.cm + rp.xn);
+    const bool amb = not_separated(f1, f2, beta, bd.g_exact, rp.xn) || code >= ks;
+    if (valid) codes[row * m + sub] = (uint8_t)code;
+    const bool push = valid && amb;
+    const uint64_t mask = __ballot(push);
+    if (mask) {
+      if (push) pend[np + __popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)row;
+      np += __popcll(mask);
+    }
+    if (OUT && valid && !amb) {   // the chosen centroid's distance and squared error
+      // the row again (from cache): keeping it live through the matrix-core
+      // phase would cost registers and occupancy
+      load_own_row<DW, FULL>(xv, x, r0, re, d, sub, ds, lane);
+      const float* c = cbsub + (int64_t)code * ds;
+      float cv[DW];
+      if (FULL) {
+#pragma unroll
+        for (int e = 0; e < DW; e += 4) {
+          const float4 v = *reinterpret_cast<const float4*>(c + e);
+          cv[e] = v.x;
+          cv[e + 1] = v.y;
+          cv[e + 2] = v.z;
+          cv[e + 3] = v.w;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < DW; ++e) cv[e] = c[e < ds ? e : ds - 1];
+      }
+      float dist = 0.0f;
+      double sq = 0.0;
+#pragma unroll
+      for (int t = 0; t < DW; ++t)
+        if (t < ds) {
+          const float df = xv[t] - cv[t];
+          const float s2 = df * df;
+          dist = dist + s2;
+          const double dd = (double)xv[t] - (double)cv[t];
+          sq = sq + dd * dd;
+        }
+      if (min_dist) min_dist[row * m + sub] = dist;
+      *sse += sq;
+    }
+  }
+  redecide<DW, REG, OUT>(pend, np, x, d, m, ks, ds, sub, cbsub, codes, lane, min_dist, sse);
+  return np;
+}
+
 // One problem: block = (row block, group of 4 subspaces), one subspace per
-// wave, 64 rows per step; lane l owns row r0 + l (lanes 0-31 form the step's
-// first 32-row group A, lanes 32-63 the second, B).  Every lane prepares
-// the operand parts of its own row; row_operands hands each lane its half's
-// operands in both groups; both groups' tiles run on the matrix cores and
-// each lane reduces its half of the candidates of group A's and group B's row
-// (lane_keys); one swap per key brings the two halves of a row to the row's
-// own lane, so the merge, the separation test, the code store and (OUT) the
-// distance of the chosen centroid and its float64 squared error run once per
-// row.  Ambiguous rows are re-decided by the whole wave after the loop.
-// OUT: min_dist (optional) and per-wave squared-error partials
-// sse_part[block * 4 + wave] (every wave writes its slot).
+// wave (assign_rows64 over the block's rows).  OUT: min_dist (optional) and
+// per-wave squared-error partials sse_part[block * 4 + wave] (every wave
+// writes its slot).
 template <int NB, int NT, bool FULL, bool OUT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NB == 1 ? 3 : 1, 8))) void k_assign_bf16(
     const float* __restrict__ x, int64_t n, int d, int m, int ks, int ds,
@@ -612,8 +647,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NB == 
     const float* __restrict__ c32, uint8_t* __restrict__ codes,
     unsigned long long* __restrict__ rescored, int groups, int rpb, float e_cross, float e_norm,
     float g_exact, float* __restrict__ min_dist, double* __restrict__ sse_part) {
-  constexpr int DW = NB * 8;
-  constexpr int NMF = bf16_nmfma(NB);
   const XcdMap bm = xcd_map(blockIdx.x, groups);
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -626,88 +659,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NB == 
     load_sub_ops<NB, NT>(o, aop, cmax, mu, sub, lane);
     // LDS: rpb list entries per wave, so the list cannot overflow
     extern __shared__ uint32_t pend_all[];
-    uint32_t* pend = pend_all + w * rpb;
     const Band bd{e_cross, e_norm, g_exact};
-    const float* cbsub = c32 + (int64_t)sub * ks * ds;
-    int np = 0;
-    float xnext[DW];
-    load_own_row<DW, FULL>(xnext, x, rbeg, rend, d, sub, ds, lane);
-    for (int64_t r0 = rbeg; r0 < rend; r0 += 64) {
-      float xv[DW];
-#pragma unroll
-      for (int e = 0; e < DW; ++e) xv[e] = xnext[e];
-      if (r0 + 64 < rend) load_own_row<DW, FULL>(xnext, x, r0 + 64, rend, d, sub, ds, lane);   // next step in flight
-      const int64_t row = r0 + lane;
-      const bool valid = row < rend;
-      RowParts<NB> rp;
-      row_parts<NB>(xv, o.muv, rp);
-      bf16x8 BA[NMF], BB[NMF];
-      row_operands<NB>(rp, BA, BB);
-      int a1A, s2A, rlA, a1B, s2B, rlB;
-      lane_keys<NT>([&](int t) {
-        f32x16 acc = {};
-#pragma unroll
-        for (int f = 0; f < NMF; ++f) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.A[t][f], BA[f], acc, 0, 0, 0);
-        return acc;
-      }, a1A, s2A, rlA);
-      lane_keys<NT>([&](int t) {
-        f32x16 acc = {};
-#pragma unroll
-        for (int f = 0; f < NMF; ++f) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.A[t][f], BB[f], acc, 0, 0, 0);
-        return acc;
-      }, a1B, s2B, rlB);
-      // lanes 0-31: both halves of group A's row; lanes 32-63: group B's
-      int a1x, a1y, s2x, s2y, rlx, rly;
-      swap_halves(a1A, a1B, a1x, a1y);
-      swap_halves(s2A, s2B, s2x, s2y);
-      swap_halves(rlA, rlB, rlx, rly);
-      float f1, f2;
-      const int code = merge_keys(a1x, a1y, s2x, s2y, rlx, rly, f1, f2);
-      const float xnorm = sqrtf(rp.xn) * 1.0001f;
-      const float beta = bd.e_cross * xnorm * o.cm + bd.e_norm * (o.cm * o.cm + rp.xn);
-      const bool amb = not_separated(f1, f2, beta, bd.g_exact, rp.xn) || code >= ks;
-      if (valid) codes[row * m + sub] = (uint8_t)code;
-      const bool push = valid && amb;
-      const uint64_t mask = __ballot(push);
-      if (mask) {
-        if (push) pend[np + __popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)row;
-        np += __popcll(mask);
-      }
-      if (OUT && valid && !amb) {   // the chosen centroid's distance and squared error
-        // the row again (from cache): keeping it live through the matrix-core
-        // phase would cost registers and occupancy
-        load_own_row<DW, FULL>(xv, x, r0, rend, d, sub, ds, lane);
-        const float* c = cbsub + (int64_t)code * ds;
-        float cv[DW];
-        if (FULL) {
-#pragma unroll
-          for (int e = 0; e < DW; e += 4) {
-            const float4 v = *reinterpret_cast<const float4*>(c + e);
-            cv[e] = v.x;
-            cv[e + 1] = v.y;
-            cv[e + 2] = v.z;
-            cv[e + 3] = v.w;
-          }
-        } else {
-#pragma unroll
-          for (int e = 0; e < DW; ++e) cv[e] = c[e < ds ? e : ds - 1];
-        }
-        float dist = 0.0f;
-        double sq = 0.0;
-#pragma unroll
-        for (int t = 0; t < DW; ++t)
-          if (t < ds) {
-            const float df = xv[t] - cv[t];
-            const float s2 = df * df;
-            dist = dist + s2;
-            const double dd = (double)xv[t] - (double)cv[t];
-            sq = sq + dd * dd;
-          }
-        if (min_dist) min_dist[row * m + sub] = dist;
-        sse += sq;
-      }
-    }
-    redecide<DW, true, OUT>(pend, np, x, d, m, ks, ds, sub, cbsub, codes, lane, min_dist, &sse);
+    const int np = assign_rows64<NB, NT, FULL, OUT, true>(o, bd, x, d, ds, m, ks, sub, rbeg, rend,
+                                                          c32 + (int64_t)sub * ks * ds, codes, pend_all + w * rpb,
+                                                          lane, min_dist, &sse);
     if (rescored && lane == 0 && np) atomicAdd(rescored, (unsigned long long)np);
   }
   if (OUT && sse_part) {
@@ -769,13 +724,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NB == 
                          sub, lane);
     // rows in pieces of PC, so that a piece's pending list fits the wave's LDS
     const int64_t rb = t0 * 32, re = min(n, t1 * 32);
-    auto decide = [&](const float (&xv)[NB * 8], int half, bool& amb) {
-      return decide_tile<NB, NT>(xv, o, half, ks, bd, amb);
-    };
     for (int64_t pb = rb; pb < re; pb += PC)
-      nres += assign_rows<NB * 8, FULL, false, false>(px, d, ds, m, ks, sub, pb, min(re, pb + PC), decide,
-                                               probs[p].c32 + (int64_t)sub * ks * ds, probs[p].codes,
-                                               pend_all + w * PC, 0, lane);
+      nres += (uint32_t)assign_rows64<NB, NT, FULL, false, false>(o, bd, px, d, ds, m, ks, sub, pb,
+                                                                  min(re, pb + PC),
+                                                                  probs[p].c32 + (int64_t)sub * ks * ds,
+                                                                  probs[p].codes, pend_all + w * PC, lane,
+                                                                  nullptr, nullptr);
   }
   if (rescored && lane == 0 && nres) atomicAdd(rescored, (unsigned long long)nres);
 }

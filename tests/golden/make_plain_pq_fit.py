@@ -25,10 +25,11 @@ def main():
     f32 = pq.lloyd(w.x, w.init_rows, w.m, w.iters, decide="fp32")
     codes, _, tie = pq.assign(w.x, f32["codebook"], "fp32")
     codes_f64, _, _ = pq.assign(w.x, f32["codebook"], "fp64")
-    sse, rmse = pq.sse_rmse(w.x, codes, f32["codebook"])
+    # the error of the codes against the float32 codebook the library works with
+    sse, rmse = pq.sse_rmse(w.x, codes, f32["codebook"].astype(np.float32).astype(np.float64))
     f64 = pq.lloyd(w.x, w.init_rows, w.m, w.iters, decide="fp64")
     codes64, _, _ = pq.assign(w.x, f64["codebook"], "fp64")
-    _, rmse64 = pq.sse_rmse(w.x, codes64, f64["codebook"])
+    _, rmse64 = pq.sse_rmse(w.x, codes64, f64["codebook"].astype(np.float32).astype(np.float64))
     np.savez_compressed(OUT, codebook=f32["codebook"], labels=f32["codes"].astype(np.uint8),
                         objective=f32["objective"], near_ties=f32["near_ties"], codes=codes.astype(np.uint8),
                         codes_fp64_decision=codes_f64.astype(np.uint8),

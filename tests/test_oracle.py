@@ -612,5 +612,6 @@ def test_plain_pq_golden_file_is_the_oracles():
     np.testing.assert_array_equal(c64, g["codes_fp64_decision"][rows])
     full_tie = np.unpackbits(g["codes_near_tie"])[:w.x.shape[0] * w.m].reshape(w.x.shape[0], w.m).astype(bool)
     np.testing.assert_array_equal(tie, full_tie[rows])
-    sse, rmse = pq.sse_rmse(w.x, g["codes"].astype(np.int64), g["codebook"])
+    cb32 = g["codebook"].astype(np.float32).astype(np.float64)
+    sse, rmse = pq.sse_rmse(w.x, g["codes"].astype(np.int64), cb32)
     assert (sse, rmse) == tuple(g["sse_rmse"])
