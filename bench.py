@@ -966,6 +966,9 @@ PUBLISHED = {   # per-launch rates the roofline fractions are quoted against
     "fma_f32": ("T lane-ops/s", 256 * 4 * 16 * 2.4e9 / 1e12),
     "min3_f32": ("T lane-ops/s", 256 * 4 * 16 * 2.4e9 / 1e12),
     "fma_f64": ("T lane-ops/s", 256 * 4 * 16 * 2.4e9 / 1e12),
+    "add_vv": ("T lane-ops/s", 256 * 4 * 16 * 2.4e9 / 1e12),
+    "min_vv": ("T lane-ops/s", 256 * 4 * 16 * 2.4e9 / 1e12),
+    "min3_add": ("T lane-ops/s", 256 * 4 * 16 * 2.4e9 / 1e12),
     "mfma_bf16": ("TFLOP/s", 2500.0),
     "mfma_f8": ("TFLOP/s", 5000.0),
     "copy": ("GB/s", PEAK_HBM_GBS),

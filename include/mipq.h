@@ -464,8 +464,12 @@ int mipq_profile_collect(int kernel, int64_t* launches, double* total_ms);
  * that does nothing but one kind of work, so that its sustained rate can be
  * timed by the caller (events on `stream`):
  *   MIPQ_PROBE_ADD_F32 / FMA_F32 / MIN3_F32 / FMA_F64: 8 independent chains
- *     of 2048 instructions per lane (v_add_f32, v_fma_f32, v_min3_f32,
- *     v_fma_f64); work = lane instructions of the launch;
+ *     of 2048 instructions per lane (v_add_f32 with a scalar operand,
+ *     v_fma_f32, v_min3_f32, v_fma_f64); work = lane instructions of the
+ *     launch;
+ *   MIPQ_PROBE_ADD_VV / MIN_VV / MIN3_ADD: the same with vector-register
+ *     operands only (v_add_f32, v_min_f32; 3-input minima and adds in
+ *     alternate chains): which kinds issue two per quad-cycle;
  *   MIPQ_PROBE_MFMA_BF16 / MFMA_F8: four independent accumulators of 512
  *     32x32x16 BF16 (32x32x64 E4M3) MFMAs per wave; work = flops;
  *   MIPQ_PROBE_COPY: copies the first half of `out` onto its second half in
@@ -482,7 +486,10 @@ enum mipq_probe {
   MIPQ_PROBE_FMA_F64 = 3,
   MIPQ_PROBE_MFMA_BF16 = 4,
   MIPQ_PROBE_MFMA_F8 = 5,
-  MIPQ_PROBE_COPY = 6
+  MIPQ_PROBE_COPY = 6,
+  MIPQ_PROBE_ADD_VV = 7,
+  MIPQ_PROBE_MIN_VV = 8,
+  MIPQ_PROBE_MIN3_ADD = 9
 };
 int mipq_peak_probe(int kind, int blocks, void* out, size_t out_bytes, double* work, void* stream);
 

@@ -78,7 +78,8 @@ CHECK_FINITE, DETERMINISTIC = 1, 2   # call flags of pq_fit / pq_encode
 ENONFINITE = -5
 
 # kinds of mipq_peak_probe (enum mipq_probe)
-PROBES = {"add_f32": 0, "fma_f32": 1, "min3_f32": 2, "fma_f64": 3, "mfma_bf16": 4, "mfma_f8": 5, "copy": 6}
+PROBES = {"add_f32": 0, "fma_f32": 1, "min3_f32": 2, "fma_f64": 3, "mfma_bf16": 4, "mfma_f8": 5, "copy": 6,
+          "add_vv": 7, "min_vv": 8, "min3_add": 9}
 
 _lib = None
 
