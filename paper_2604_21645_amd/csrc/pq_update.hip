@@ -109,6 +109,111 @@ __device__ __forceinline__ void accumulate_chunk(
   }
 }
 
+// Vector form of accumulate_chunk for d/m and d multiples of 4 and 16-byte
+// aligned rows: lane l takes the 4 dimensions 4q..4q+3 (q = l % (ds/4)) of
+// row l / (ds/4) with one 16-byte load, and keeps U such rows in flight, so a
+// wave has 16 times the bytes of the scalar form outstanding.  The sums, the
+// counts and the order of the objective terms within a lane are those of the
+// scalar form applied to the lane's elements; the atomic additions make the
+// sums' last bits depend on their order, as there.
+template <bool GX, bool OBJ, bool CHECK>
+__device__ __forceinline__ void accumulate_chunk4(
+    const float* __restrict__ x, int64_t n, int d, int m, int ks, int ds,
+    const uint8_t* __restrict__ codes, const float* __restrict__ c32, int64_t rpc, int c, int sub,
+    double* __restrict__ part_s, uint32_t* __restrict__ part_cnt, double* __restrict__ part_j,
+    const double* __restrict__ gscale, float* __restrict__ grad_x, double* smem, double* redj) {
+  const int stride = ds + 1;
+  double* S = smem;
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(S + (size_t)ks * stride);
+  float* cbs = reinterpret_cast<float*>(S + (size_t)ks * stride + (ks + 1) / 2);
+  const int per = ks * ds;
+  for (int i = threadIdx.x; i < ks * stride; i += blockDim.x) S[i] = 0.0;
+  for (int i = threadIdx.x; i < ks; i += blockDim.x) cnt[i] = 0u;
+  if (OBJ)
+    for (int i = threadIdx.x; i < per; i += blockDim.x) cbs[i] = c32[(int64_t)sub * per + i];
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int lpr = ds >> 2;                 // lanes per row
+  const int rpw = 64 / lpr;                // rows per wave step
+  const int g = lane / lpr, t = (lane - g * lpr) * 4;
+  const int64_t r0 = (int64_t)c * rpc;
+  const int64_t r1 = min(n, r0 + rpc);
+  const int64_t step = (int64_t)(blockDim.x >> 6) * rpw;
+  const int64_t first = r0 + (int64_t)wave * rpw + g;
+  const int64_t nrows = (g < rpw && first < r1) ? (r1 - first + step - 1) / step : 0;
+  const float* xp = x + first * d + (int64_t)sub * ds + t;
+  const uint8_t* cp = codes + first * m + sub;
+  float* gp = GX ? grad_x + first * d + (int64_t)sub * ds + t : nullptr;
+  const int64_t xs = step * d, cs = step * m;
+  double jl = 0.0;
+  const double g2 = GX ? 2.0 * (gscale ? *gscale : 1.0) : 0.0;
+  auto add_row = [&](int code, const float4& v, int64_t off) {
+    const float xv[4] = {v.x, v.y, v.z, v.w};
+    if (CHECK && code >= ks) {
+      jl += NAN;
+      if (GX) *reinterpret_cast<float4*>(gp + off) = make_float4(NAN, NAN, NAN, NAN);
+      return;
+    }
+    if (OBJ) {
+      float gv[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double df = (double)xv[e] - (double)cbs[code * ds + t + e];
+        jl += df * df;
+        gv[e] = (float)(g2 * df);
+      }
+      if (GX) *reinterpret_cast<float4*>(gp + off) = make_float4(gv[0], gv[1], gv[2], gv[3]);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) atomicAdd(&S[code * stride + t + e], (double)xv[e]);
+    if (t == 0) atomicAdd(&cnt[code], 1u);
+  };
+  constexpr int U = 8;   // rows in flight per lane
+  int64_t i = 0;
+  for (; i + U <= nrows; i += U) {
+    int code[U];
+    float4 xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      code[u] = (int)cp[u * cs];
+      xv[u] = *reinterpret_cast<const float4*>(xp + u * xs);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) add_row(code[u], xv[u], u * xs);
+    xp += U * xs;
+    cp += U * cs;
+    if (GX) gp += U * xs;
+  }
+  for (; i < nrows; ++i) {
+    add_row((int)cp[0], *reinterpret_cast<const float4*>(xp), 0);
+    xp += xs;
+    cp += cs;
+    if (GX) gp += xs;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) jl += __shfl_xor(jl, off, 64);
+  if (lane == 0) redj[wave] = jl;
+  __syncthreads();
+  const size_t base = (size_t)c * m + sub;
+  for (int i = threadIdx.x; i < per; i += blockDim.x) {
+    const int k = i / ds;
+    part_s[base * per + i] = S[k * stride + (i - k * ds)];
+  }
+  for (int i = threadIdx.x; i < ks; i += blockDim.x) part_cnt[base * ks + i] = cnt[i];
+  if (threadIdx.x == 0) {
+    double js = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) js += redj[i];
+    part_j[base] = js;
+  }
+}
+
+// rows of x can be read 16 bytes at a time in every subspace
+__host__ __device__ __forceinline__ bool rows_vec4(const float* x, int d, int ds) {
+  return ds % 4 == 0 && d % 4 == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+}
+
 // Deterministic variant (MIPQ_DETERMINISTIC): no floating-point atomics.  The
 // chunk's rows are taken in pieces of kDetPiece rows; each piece's positions
 // are sorted by code with a stable two-pass counting sort on 4-bit digits
@@ -321,8 +426,12 @@ __global__ __launch_bounds__(NT) void k_accumulate(
     for (int j = threadIdx.x; j < m; j += blockDim.x) cmax_zero[j] = 0.0f;
   const ChunkMap cm = chunk_map(blockIdx.x, m);
   if (cm.chunk >= nch) return;   // padding of the grid (every chunk's partials are written)
-  accumulate_chunk<GX, OBJ, CHECK>(x, n, d, m, ks, ds, codes, c32, rpc, (int)cm.chunk, cm.sub, part_s, part_cnt,
-                                   part_j, gscale, grad_x, smem, redj);
+  if (rows_vec4(x, d, ds) && (!GX || rows_vec4(grad_x, d, ds)))
+    accumulate_chunk4<GX, OBJ, CHECK>(x, n, d, m, ks, ds, codes, c32, rpc, (int)cm.chunk, cm.sub, part_s, part_cnt,
+                                      part_j, gscale, grad_x, smem, redj);
+  else
+    accumulate_chunk<GX, OBJ, CHECK>(x, n, d, m, ks, ds, codes, c32, rpc, (int)cm.chunk, cm.sub, part_s, part_cnt,
+                                     part_j, gscale, grad_x, smem, redj);
 }
 
 // Deterministic accumulation (see accumulate_chunk_det), one problem.
@@ -382,6 +491,10 @@ __global__ __launch_bounds__(NT) void k_accumulate_batched(const BatchProb* __re
     accumulate_chunk_det<true>(probs[p].x, probs[p].n, d, m, ks, ds, probs[p].codes, probs[p].c32, probs[p].rpc, c,
                                sub, part_s + item0 * per, part_cnt + item0 * ks, part_j + item0,
                                reinterpret_cast<char*>(smem), redj);
+  else if (rows_vec4(probs[p].x, d, ds))
+    accumulate_chunk4<false, true, false>(probs[p].x, probs[p].n, d, m, ks, ds, probs[p].codes, probs[p].c32,
+                                          probs[p].rpc, c, sub, part_s + item0 * per, part_cnt + item0 * ks,
+                                          part_j + item0, nullptr, nullptr, smem, redj);
   else
     accumulate_chunk<false, true, false>(probs[p].x, probs[p].n, d, m, ks, ds, probs[p].codes, probs[p].c32,
                                          probs[p].rpc, c, sub, part_s + item0 * per, part_cnt + item0 * ks,
