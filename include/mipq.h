@@ -151,6 +151,28 @@ int mipq_pq_encode(const float* x, int64_t n, int d, int m, int ks, const float*
                    int64_t* rescored, void* ws, size_t ws_bytes, void* stream);
 
 /* -------------------------------------------------------------------------
+ * Encode that allocates nothing, for callers that cannot allocate device
+ * memory or pass a workspace: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation.
+ *
+ * Same arguments, rule and outputs as mipq_pq_encode, without the workspace.
+ * Its scratch memory (packed centroid operands, squared-error partials) is a
+ * fixed array of MIPQ_NOALLOC_SCRATCH_BYTES in device memory, one per GPU the
+ * library runs on, held until the process ends; the call takes no allocation
+ * of any kind.  Every call on a GPU uses that GPU's array: calls that overlap
+ * on one GPU race (order them on one stream).
+ * Limits: n <= MIPQ_NOALLOC_MAX_N and the scratch mipq_pq_encode_workspace_size
+ * reports within MIPQ_NOALLOC_SCRATCH_BYTES (MIPQ_ENOMEM otherwise; m <= 64
+ * with d/m <= 16 always fits); MIPQ_CHECK_FINITE is not accepted (it copies a
+ * flag to the host), MIPQ_EINVAL.
+ * ------------------------------------------------------------------------- */
+#define MIPQ_NOALLOC_SCRATCH_BYTES ((size_t)8 << 20)
+#define MIPQ_NOALLOC_MAX_N ((int64_t)1 << 24)
+int mipq_pq_encode_noalloc(const float* x, int64_t n, int d, int m, int ks, const float* codebook,
+                           int precision, int flags, uint8_t* codes, float* min_dist, double* sse_rmse,
+                           int64_t* rescored, void* stream);
+
+/* -------------------------------------------------------------------------
  * Decode and reconstruction error (paper Section 3: rows are encoded and
  * decoded to measure the reconstruction RMSE).
  *

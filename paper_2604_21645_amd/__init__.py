@@ -127,6 +127,31 @@ def pq_encode_ex(x: torch.Tensor, codebook: torch.Tensor, precision="bf16", min_
     return res
 
 
+def pq_encode_noalloc(x: torch.Tensor, codebook: torch.Tensor, precision="bf16", codes: torch.Tensor | None = None,
+                      min_dist: torch.Tensor | None = None, sse_rmse: torch.Tensor | None = None,
+                      rescored: torch.Tensor | None = None) -> torch.Tensor:
+    """mipq_pq_encode_noalloc: encode with the library's fixed scratch array
+    (no workspace).  Outputs may be passed in (then nothing is allocated
+    here either); ``codes`` is returned."""
+    L = lib()
+    x = _dev(x, torch.float32, "x")
+    cb = _dev(codebook, torch.float32, "codebook")
+    dev = x.device
+    n, d = x.shape
+    m, ks, ds = cb.shape
+    if m * ds != d:
+        raise ValueError("codebook shape %s does not match d=%d" % (tuple(cb.shape), d))
+    if codes is None:
+        codes = torch.empty((n, m), dtype=torch.uint8, device=dev)
+    for t, shape, dt, name in ((codes, (n, m), torch.uint8, "codes"), (min_dist, (n, m), torch.float32, "min_dist"),
+                               (sse_rmse, (2,), torch.float64, "sse_rmse"), (rescored, (1,), torch.int64, "rescored")):
+        if t is not None and (t.dtype != dt or tuple(t.shape) != shape or not t.is_contiguous() or t.device != dev):
+            raise ValueError("%s must be a contiguous %s tensor of shape %s on %s" % (name, dt, shape, dev))
+    check(L.mipq_pq_encode_noalloc(_ptr(x), n, d, m, ks, _ptr(cb), _prec(precision), 0, _ptr(codes), _ptr(min_dist),
+                                   _ptr(sse_rmse), _ptr(rescored), _stream(dev)))
+    return codes
+
+
 def pq_encode(x: torch.Tensor, codebook: torch.Tensor, precision="bf16", rescored: bool = False):
     """Codes uint8 [n, m]; with ``rescored=True`` also the int64 count of
     (row, subspace) pairs the BF16 path re-decided in float32."""

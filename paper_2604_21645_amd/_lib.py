@@ -29,6 +29,7 @@ SIGNATURES = {
     "mipq_pq_fit": (_I, [_P, _L, _P, _L, _I, _I, _I, _I, _P, _P, _I, _I, _P, _P, _P, _P, _P, _P, _S, _P]),
     "mipq_pq_encode_workspace_size": (_S, [_L, _I, _I, _I, _I]),
     "mipq_pq_encode": (_I, [_P, _L, _I, _I, _I, _P, _I, _I, _P, _P, _P, _P, _P, _S, _P]),
+    "mipq_pq_encode_noalloc": (_I, [_P, _L, _I, _I, _I, _P, _I, _I, _P, _P, _P, _P, _P]),
     "mipq_pq_decode_rmse_workspace_size": (_S, [_L, _I, _I, _I]),
     "mipq_pq_decode_rmse": (_I, [_P, _L, _I, _I, _I, _P, _P, _P, _P, _P, _S, _P]),
     "mipq_pq_decode_centroids": (_I, [_P, _L, _I, _I, _I, _P, _P]),

@@ -200,3 +200,14 @@ def test_adc_search_rejects_tables_beyond_lds(L):
     assert adc(F, 10, 256, F, 64, F, 256, 256, F, F, F, 8, 10, F, F, None, F, 1 << 30, None) == EUNSUPPORTED
     # m * ks = 192 * 58 <= 11264 fits with topk = 1024: refused only for the too-small workspace
     assert adc(F, 10, 192, F, 64, F, 192, 58, F, F, F, 8, 1024, F, F, None, F, 64, None) == ENOMEM
+
+
+def test_noalloc_encode_rejects_before_touching_the_device(L):
+    enc = L.mipq_pq_encode_noalloc
+    assert enc(1, (1 << 24) + 1, 128, 16, 256, 1, 1, 0, 1, None, None, None, None) == EINVAL
+    assert b"noalloc" in L.mipq_last_error()
+    assert enc(1, 100, 128, 16, 256, 1, 1, 1, 1, None, None, None, None) == EINVAL   # MIPQ_CHECK_FINITE
+    assert enc(1, 100, 130, 16, 256, 1, 1, 0, 1, None, None, None, None) == EINVAL   # shape
+    # more scratch than the fixed array: 2^23 rows of 256 one-dimensional subspaces
+    assert enc(1, 1 << 23, 256, 256, 256, 1, 1, 0, 1, None, None, None, None) == ENOMEM
+    assert b"scratch" in L.mipq_last_error()
