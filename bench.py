@@ -4,10 +4,11 @@
 Workload (integer_pq): N = 1,000,000 rows, D = 128, non-negative integer
 values in [0, 255] (clipped Gaussian mixture of 1,000 components, sigma 20),
 codebooks fitted on a seeded 100,000-row sample with M = 16 subspaces,
-Ks = 256 centroids, 25 Lloyd rounds, then all 1M rows encoded, decoded and
-the reconstruction RMSE computed.  One step = fit + encode + decode/RMSE,
-inputs resident in HBM.  The headline precision is BF16 on matrix cores; the
-plain FP32 path runs the same step for comparison (identical codes).
+Ks = 256 centroids, 25 Lloyd rounds, then all 1M rows encoded with the
+reconstruction RMSE of their codes (formed by the encode pass itself).  One
+step = fit + encode + RMSE, inputs resident in HBM.  The headline precision
+is BF16 on matrix cores; the plain FP32 path runs the same step for
+comparison (identical codes).
 
 Other workloads (one JSON line each, same contract, selected with
 --workload): batched_uneven (64 uneven problems fitted and encoded together),
@@ -240,14 +241,14 @@ def bench_integer_pq(args) -> dict:
 
     def step(prec, ev=None):
         fit = mipq.pq_fit(x, w.m, w.ks, w.iters, init_rows=init_rows, train_rows=train_rows,
-                          precision=prec, labels=False, objective=False)
+                          precision=prec, labels=False, objective=False, deterministic=args.deterministic)
         if ev:
             ev[1].record()
-        codes = mipq.pq_encode(x, fit["codebook"], prec)
+        # the reconstruction error of the codes comes out of the encode itself
+        enc = mipq.pq_encode_ex(x, fit["codebook"], prec, sse_rmse=True)
         if ev:
             ev[2].record()
-        _, sr = mipq.pq_decode_rmse(codes, fit["codebook"], x)
-        return fit["codebook"], codes, sr
+        return fit["codebook"], enc["codes"], enc["sse_rmse"]
 
     def timed(prec, steps, warmup, profile):
         for i in range(warmup):
@@ -258,20 +259,18 @@ def bench_integer_pq(args) -> dict:
             L.mipq_profile_enable(1)
             for k in _lib.KERNELS.values():   # drop anything recorded before
                 L.mipq_profile_collect(k, None, None)
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         out = None
         for i in range(steps):
             evs[i][0].record()
             out = step(prec, evs[i])
-            evs[i][3].record()
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / steps * 1e3
         if profile:
             L.mipq_profile_enable(0)
-        ph = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])]
-                       for e in evs]).mean(0)
+        ph = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])] for e in evs]).mean(0)
         return wall, ph, out
 
     log("bf16: %d warmup + %d timed steps" % (args.warmup, args.steps))
@@ -353,10 +352,10 @@ def bench_integer_pq(args) -> dict:
         "dtype": "bf16",
         "data": "synthetic",
         "config": {"workload": "integer_pq: 1M x 128 rows in [0,255], fit on 100k-row sample, "
-                               "M=16, Ks=256, 25 Lloyd rounds, encode 1M, decode+RMSE",
+                               "M=16, Ks=256, 25 Lloyd rounds, encode 1M with the reconstruction RMSE",
                    "n": n, "d": d, "m": w.m, "ks": w.ks, "iters": w.iters, "n_train": n_train,
-                   "precision": "bf16", "parallelism": "single GPU"},
-        "phases_ms": {"fit": ph[0], "encode": ph[1], "decode_rmse": ph[2]},
+                   "precision": "bf16", "parallelism": "single GPU", "deterministic_sums": args.deterministic},
+        "phases_ms": {"fit": ph[0], "encode_rmse": ph[1]},
         "fit_encode_vectors_per_s": n / ((ph[0] + ph[1]) * 1e-3),
         "fp32_plain": fp32,
         "fp8": fp8,
@@ -1032,6 +1031,7 @@ def main() -> int:
     ap.add_argument("--diff-cpu-rows", type=int, default=20000)
     ap.add_argument("--soil-cpu-rows", type=int, default=8000)
     ap.add_argument("--oracle-sample", type=int, default=20000)
+    ap.add_argument("--deterministic", action="store_true", help="fixed-order centroid sums in the fit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
