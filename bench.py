@@ -598,6 +598,9 @@ def bench_ivf(args) -> dict:
     torch.cuda.synchronize()
     ka = kernel_totals(L, ["adc", "adc_scan"])
     L.mipq_profile_enable(0)
+    # the work the scans executed (device counters; the exact skips avoid the rest)
+    _, _, wk = mipq.adc_search(q, idx, w.nprobe, w.topk, work=True)
+    lut_entries, part_rows, full_rows, lists_scanned = [int(v) for v in wk.cpu().numpy()]
     flops = 2.0 * n * d * w.kc
     avg = ca[1] / max(ca[0], 1)
     achieved = flops / (avg * 1e-3) / 1e12
@@ -612,11 +615,19 @@ def bench_ivf(args) -> dict:
         pr = np.argpartition(dq, w.nprobe - 1, axis=1)[:, :w.nprobe]
         cand += int(sizes[pr].sum())
     scan_bytes = cand * (w.m + 4)
-    scan_adds = cand * w.m           # the score: a float32 sum of M table entries per candidate
+    scan_adds = cand * w.m           # the method's score work: M table entries summed per candidate
     ns, ts = ka["adc_scan"]
     scan_ms = ts / max(ns, 1)
     scan_gbs = scan_bytes / (scan_ms * 1e-3) / 1e9
-    scan_tadd = scan_adds / (scan_ms * 1e-3) / 1e12
+    # executed: a table entry is ds float32 differences, squares and sums; a
+    # partial row sums 4 entries, a full row M; every summed entry is one LDS read
+    ds = d // w.m
+    pre = 4
+    exec_ops = lut_entries * 3 * ds + part_rows * pre + full_rows * w.m
+    lds_reads = part_rows * pre + full_rows * w.m
+    exec_t = exec_ops / (scan_ms * 1e-3) / 1e12
+    lds_peak_t = 256 * 32 * 2.4e9 / 1e12   # 4-byte LDS reads per second: 128 bytes per clock per CU
+    lds_t = lds_reads / (scan_ms * 1e-3) / 1e12
 
     base, parity = None, None
     if not args.no_cpu_baseline:
@@ -652,19 +663,21 @@ def bench_ivf(args) -> dict:
         "build_ms": build_ms,
         "build_vectors_per_s": n / (build_ms * 1e-3),
         "oracle_parity": parity,
-        "roofline": {"bound": "alu", "kernel": "k_adc_scan", "achieved": scan_tadd, "peak": PEAK_F32_ADD_T,
-                     "unit": "TFLOP/s", "frac": scan_tadd / PEAK_F32_ADD_T,
+        "roofline": {"bound": "alu", "kernel": "k_adc_scan", "achieved": exec_t, "peak": PEAK_F32_ADD_T,
+                     "unit": "T lane-ops/s", "frac": exec_t / PEAK_F32_ADD_T,
                      "traffic": measured_traffic(ADC_TRAFFIC_FILE, ADC_SOURCE),
-                     "alg_flops_per_launch": scan_adds, "avg_launch_ms": scan_ms, "launches": ns,
-                     "candidates_per_launch": cand,
-                     "bytes_view": {"alg_bytes_per_launch": scan_bytes, "achieved_gbs": scan_gbs,
-                                    "hbm_peak_gbs": PEAK_HBM_GBS, "frac": scan_gbs / PEAK_HBM_GBS},
-                     "table_lookups_per_cu_clock": scan_adds / (scan_ms * 1e-3) / (256 * 2.4e9),
-                     "note": "algorithmic work: M float32 table entries summed per candidate, against unpacked "
-                             "float32 adds (256 CUs x 64 lanes x 2.4 GHz); the (query, list) blocks of one list run "
-                             "together, so the M + 4 bytes per candidate mostly come from L2 (bytes_view above "
-                             "HBM peak, traffic measured past L2), and rows whose partial sum already exceeds the "
-                             "bound skip the rest of their table reads"},
+                     "executed_ops_per_launch": exec_ops, "avg_launch_ms": scan_ms, "launches": ns,
+                     "work_counters": {"table_entries_built": lut_entries, "rows_partial_sum_only": part_rows,
+                                       "rows_full_sum": full_rows, "lists_scanned": lists_scanned,
+                                       "pairs": nq * w.nprobe},
+                     "lds_view": {"reads_per_launch": lds_reads, "achieved_t_reads_per_s": lds_t,
+                                  "peak_t_reads_per_s": lds_peak_t, "frac": lds_t / lds_peak_t},
+                     "method_view": {"candidates_per_launch": cand, "table_adds_per_launch": scan_adds,
+                                     "alg_bytes_per_launch": scan_bytes, "alg_gbs": scan_gbs},
+                     "note": "executed work from device counters in the scan: table entries (3 ds float32 ops "
+                             "each) and summed entries (one add and one LDS read each), against unpacked float32 "
+                             "issue (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz); the exact list bound and partial "
+                             "sums skip the rest of the method's table adds (method_view)"},
         "build_roofline": {"bound": "mfma", "kernel": "k_coarse_assign_mfma", "achieved": achieved, "peak": 2500.0,
                            "unit": "TFLOP/s", "frac": achieved / 2500.0, "traffic": None,
                            "alg_flops_per_launch": flops, "avg_launch_ms": avg, "launches": ca[0],

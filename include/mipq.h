@@ -379,6 +379,11 @@ int mipq_ii_merge(const int64_t* const* part_offsets, const int32_t* const* part
  *   out_dist  OUT float32 [nq][topk]
  *   wide      OUT optional int64 [1]: queries whose probe selection needed the
  *             exact rule on every list
+ *   work      OUT optional int64 [4]: work the list scans executed (the exact
+ *             skips below avoid the rest): [0] table entries built, [1] rows
+ *             summed over their first 4 subspaces only, [2] rows summed over
+ *             all subspaces, [3] (query, list) pairs whose list was scanned
+ *             (not left at once by the list bound)
  * Requirements: 1 <= nprobe <= min(kc, 256), 1 <= topk <= 1024, d/m in
  * {1, 2, 4, 8, 16}, d <= 16 or d in {32, 64, 96, 128, 192, 256}, and the
  * table with its key buffer within 64 KiB of LDS (m * ks <= 11264 always
@@ -387,8 +392,8 @@ int mipq_ii_merge(const int64_t* const* part_offsets, const int32_t* const* part
 size_t mipq_adc_search_workspace_size(int nq, int d, int kc, int nprobe, int topk);
 int mipq_adc_search(const float* q, int nq, int d, const float* coarse, int kc, const float* pq_codebook,
                     int m, int ks, const int64_t* offsets, const int32_t* ids, const uint8_t* codes_sorted,
-                    int nprobe, int topk, int32_t* out_ids, float* out_dist, int64_t* wide, void* ws,
-                    size_t ws_bytes, void* stream);
+                    int nprobe, int topk, int32_t* out_ids, float* out_dist, int64_t* wide, int64_t* work,
+                    void* ws, size_t ws_bytes, void* stream);
 
 /* -------------------------------------------------------------------------
  * Reconstruction-loss backward with the codes held fixed.

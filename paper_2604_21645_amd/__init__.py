@@ -379,10 +379,13 @@ def ii_merge(parts):
     return out
 
 
-def adc_search(q: torch.Tensor, index: dict, nprobe: int, topk: int, wide: bool = False):
+def adc_search(q: torch.Tensor, index: dict, nprobe: int, topk: int, wide: bool = False, work: bool = False):
     """Top-k (ids int32 [nq, topk], distances float32 [nq, topk]) per query
-    over an index from ``ii_build``; optionally the int64 number of queries
-    whose probe selection ranked every list exactly."""
+    over an index from ``ii_build``; optionally (appended in this order) the
+    int64 number of queries whose probe selection ranked every list exactly
+    and the int64 [4] work counters of the list scans (table entries built,
+    rows summed over their first 4 subspaces only, rows summed in full,
+    lists scanned)."""
     L = lib()
     q = _dev(q, torch.float32, "q")
     dev = q.device
@@ -397,10 +400,17 @@ def adc_search(q: torch.Tensor, index: dict, nprobe: int, topk: int, wide: bool 
     out_ids = torch.empty((nq, topk), dtype=torch.int32, device=dev)
     out_d = torch.empty((nq, topk), dtype=torch.float32, device=dev)
     w = torch.zeros(1, dtype=torch.int64, device=dev) if wide else None
+    wk = torch.zeros(4, dtype=torch.int64, device=dev) if work else None
     ws = _ws(L.mipq_adc_search_workspace_size(nq, d, kc, nprobe, topk), dev)
     check(L.mipq_adc_search(_ptr(q), nq, d, _ptr(cc), kc, _ptr(pqc), m, ks, _ptr(off), _ptr(ids), _ptr(codes),
-                            nprobe, topk, _ptr(out_ids), _ptr(out_d), _ptr(w), _ptr(ws), ws.numel(), _stream(dev)))
-    return (out_ids, out_d, w) if wide else (out_ids, out_d)
+                            nprobe, topk, _ptr(out_ids), _ptr(out_d), _ptr(w), _ptr(wk), _ptr(ws), ws.numel(),
+                            _stream(dev)))
+    out = (out_ids, out_d)
+    if wide:
+        out += (w,)
+    if work:
+        out += (wk,)
+    return out
 
 
 def rotate(x: torch.Tensor, rotation: torch.Tensor) -> torch.Tensor:

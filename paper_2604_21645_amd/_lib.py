@@ -47,7 +47,7 @@ SIGNATURES = {
     "mipq_ii_merge_workspace_size": (_S, [_I, _I]),
     "mipq_ii_merge": (_I, [_P, _P, _P, _P, _I, _I, _I, _P, _P, _P, _P, _S, _P]),
     "mipq_adc_search_workspace_size": (_S, [_I, _I, _I, _I, _I]),
-    "mipq_adc_search": (_I, [_P, _I, _I, _P, _I, _P, _I, _I, _P, _P, _P, _I, _I, _P, _P, _P, _P, _S, _P]),
+    "mipq_adc_search": (_I, [_P, _I, _I, _P, _I, _P, _I, _I, _P, _P, _P, _I, _I, _P, _P, _P, _P, _P, _S, _P]),
     "mipq_pq_fit_batched_workspace_size": (_S, [_P, _I, _I, _I, _I, _I, _I]),
     "mipq_pq_fit_batched": (_I, [_P, _I, _I, _I, _I, _I, _I, _P, _P, _P, _S, _P]),
     "mipq_plan_create": (_I, [_P, _P, _I, _I, _I, _I, _I, _I, _I, _P, _S, _P]),

@@ -509,7 +509,8 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
                                                  int nq, int nprobe, int topk, int cap,
                                                  unsigned long long* __restrict__ qthr,
                                                  uint64_t* __restrict__ pair_out,
-                                                 const int32_t* __restrict__ order, int npairs) {
+                                                 const int32_t* __restrict__ order, int npairs,
+                                                 unsigned long long* __restrict__ work) {
   extern __shared__ float sm[];
   float* lut = sm;                                   // m*ks
   float* rq = lut + m * ks;                          // d
@@ -535,6 +536,20 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
   }
   const float* qr = q + (int64_t)qi * d;
   const int64_t a = offsets[l], b = offsets[l + 1];
+  // executed work (when `work` is given): table entries built, rows summed
+  // over the first kScanPre subspaces only, rows summed over all subspaces
+  uint32_t w_lut = 0, w_part = 0, w_full = 0;
+  auto report = [&](bool entered) {
+    if (!work) return;
+    unsigned long long v[3] = {w_lut, w_part, w_full};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off, 64);
+      if ((threadIdx.x & 63) == 0 && v[i]) atomicAdd(work + i, v[i]);
+    }
+    if (threadIdx.x == 0 && entered) atomicAdd(work + 3, 1ull);
+  };
   const bool m16 = V16 && m == 16;
   const uint4* c4 = reinterpret_cast<const uint4*>(codes);
   // M = 16: the code rows of the first two steps, in flight while the table
@@ -558,8 +573,10 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
   // table rows of subspaces [j0, j1)
   auto build_lut = [&](int j0, int j1) {
     for (int j = j0; j < j1; ++j)
-      for (int k = threadIdx.x; k < ks; k += blockDim.x)
+      for (int k = threadIdx.x; k < ks; k += blockDim.x) {
         lut[j * ks + k] = sqdist_fixed<DS>(rq + j * DS, pq + ((int64_t)j * ks + k) * DS);
+        ++w_lut;
+      }
   };
   // M = 16 rows: the table of the first kLutPre subspaces now, the rest once
   // a row needs it (the rows of distant lists mostly never do).
@@ -599,6 +616,7 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
     const uint32_t tb0 = (uint32_t)(thr >> 32);
     if (tb0 != 0xFFFFFFFFu && lb_bits > tb0) {   // block-uniform: the list is left
       for (int i = threadIdx.x; i < topk; i += blockDim.x) outp[i] = ~0ull;
+      report(false);
       return;
     }
     build_lut(kHalf, kLutPre);
@@ -667,7 +685,10 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
         for (int r = 0; r < kScanRows; ++r) {
           const int64_t p = p0 + r * kT + threadIdx.x;
           bool keep = false;
-          if (p < b) keep = __float_as_uint(sum16(cv[r], std::integral_constant<int, kScanPre>{})) <= tb;
+          if (p < b) {
+            keep = __float_as_uint(sum16(cv[r], std::integral_constant<int, kScanPre>{})) <= tb;
+            ++w_part;
+          }
           const unsigned long long bal = __ballot(keep);
           if (keep) wql[nq_w + __popcll(bal & __lanemask_lt())] = (uint16_t)(r * kT + threadIdx.x);
           nq_w += __popcll(bal);
@@ -686,6 +707,7 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
         for (int i = lane; i < nq_w; i += 64) {
           const int64_t p = p0 + wql[i];
           insert(sum16(c4[p], std::integral_constant<int, 16>{}), ids[p], tl);
+          ++w_full;
         }
       } else {   // no bound yet: every row is summed in full
         if (!full) {
@@ -696,7 +718,10 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
 #pragma unroll
         for (int r = 0; r < kScanRows; ++r) {
           const int64_t p = p0 + r * kT + threadIdx.x;
-          if (p < b) insert(sum16(cv[r], std::integral_constant<int, 16>{}), ids[p], tl);
+          if (p < b) {
+            insert(sum16(cv[r], std::integral_constant<int, 16>{}), ids[p], tl);
+            ++w_full;
+          }
         }
       }
       step_end(ext);
@@ -733,10 +758,12 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
           for (int j = 1; j < m; ++j) s = s + lut[j * ks + cr[j]];
         }
         insert(s, ids[p], tl);
+        ++w_full;
       }
       step_end(ext);
     }
   }
+  report(true);
   const int c = cnt;
   topk_finish(buf, c);
   const int keep = c < topk ? c : topk;
@@ -828,8 +855,9 @@ int launch_adc(const float* q, int nq, int d, const float* cc, int kc, const voi
                const unsigned int* cmax_bits, const float* pq, int m, int ks, const int64_t* offsets,
                const int32_t* ids, const uint8_t* codes, int nprobe, int topk, float* est, int32_t* probes,
                unsigned long long* qthr, uint64_t* pair_out, void* order_ws, int64_t* wide, int32_t* out_ids,
-               float* out_dist, hipStream_t s) {
+               float* out_dist, int64_t* work_out, hipStream_t s) {
   if (nq == 0) return MIPQ_OK;
+  unsigned long long* work = reinterpret_cast<unsigned long long*>(work_out);
   ProfScope ps(MIPQ_K_ADC, s);
   const int S = coarse_ksteps(d);
   const int nt = (kc + 31) / 32;
@@ -881,10 +909,10 @@ int launch_adc(const float* q, int nq, int d, const float* cc, int kc, const voi
   do {                                                                                                       \
     if (v16)                                                                                                 \
       k_adc_scan<DSV, true><<<sblocks, kT, shm, s>>>(q, d, cc, pq, m, ks, offsets, ids, codes, probes, nq,   \
-                                                     nprobe, topk, cap, qthr, pair_out, ow.order, (int)npairs); \
+                                                     nprobe, topk, cap, qthr, pair_out, ow.order, (int)npairs, work); \
     else                                                                                                     \
       k_adc_scan<DSV, false><<<sblocks, kT, shm, s>>>(q, d, cc, pq, m, ks, offsets, ids, codes, probes, nq,  \
-                                                      nprobe, topk, cap, qthr, pair_out, ow.order, (int)npairs); \
+                                                      nprobe, topk, cap, qthr, pair_out, ow.order, (int)npairs, work); \
   } while (0)
   {
     ProfScope pscan(MIPQ_K_ADC_SCAN, s);

@@ -751,8 +751,8 @@ size_t mipq_adc_search_workspace_size(int nq, int d, int kc, int nprobe, int top
 
 int mipq_adc_search(const float* q, int nq, int d, const float* coarse, int kc, const float* pq_codebook,
                     int m, int ks, const int64_t* offsets, const int32_t* ids, const uint8_t* codes_sorted,
-                    int nprobe, int topk, int32_t* out_ids, float* out_dist, int64_t* wide, void* ws,
-                    size_t ws_bytes, void* stream) {
+                    int nprobe, int topk, int32_t* out_ids, float* out_dist, int64_t* wide, int64_t* work,
+                    void* ws, size_t ws_bytes, void* stream) {
   int rc;
   if (nq < 0) return fail(MIPQ_EINVAL, "nq must be >= 0");
   if ((rc = check_coarse(0, d, kc, MIPQ_BF16))) return rc;
@@ -771,11 +771,12 @@ int mipq_adc_search(const float* q, int nq, int d, const float* coarse, int kc, 
   AdcWs a = carve_adc(ws, nq, d, kc, nprobe, topk);
   if ((rc = check_ws(ws, ws_bytes, a.bytes))) return rc;
   if (wide && (rc = launch_zero_u32(reinterpret_cast<uint32_t*>(wide), 2, s))) return rc;
+  if (work && (rc = launch_zero_u32(reinterpret_cast<uint32_t*>(work), 8, s))) return rc;
   if (nq == 0) return MIPQ_OK;
   if ((rc = launch_coarse_prepare(coarse, kc, d, a.cw.mu, a.cw.cmax, a.cw.aop, s))) return rc;
   return launch_adc(q, nq, d, coarse, kc, a.cw.aop, a.cw.mu, a.cw.cmax, pq_codebook, m, ks, offsets, ids,
                     codes_sorted, nprobe, topk, a.est, a.probes, a.qthr, a.pair_out, a.order_ws, wide, out_ids,
-                    out_dist, s);
+                    out_dist, work, s);
 }
 
 }  // extern "C"

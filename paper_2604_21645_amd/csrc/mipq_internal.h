@@ -180,7 +180,7 @@ int launch_adc(const float* q, int nq, int d, const float* cc, int kc, const voi
                const unsigned int* cmax_bits, const float* pq, int m, int ks, const int64_t* offsets,
                const int32_t* ids, const uint8_t* codes, int nprobe, int topk, float* est, int32_t* probes,
                unsigned long long* qthr, uint64_t* pair_out, void* order_ws, int64_t* wide, int32_t* out_ids,
-               float* out_dist, hipStream_t s);
+               float* out_dist, int64_t* work, hipStream_t s);
 
 // operands of the centred codebook; mu: m * kMaxDsBf16 floats (subspace centres)
 int launch_pack_bf16(const float* c32, int m, int ks, int ds, void* aop, float* cmax, float* mu,

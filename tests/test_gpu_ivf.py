@@ -137,6 +137,17 @@ def test_adc_search_m16_long_lists_matches_oracle(case, nprobe, topk):
     np.testing.assert_array_equal(gd.cpu().numpy(), rd.astype(np.float32))
     if case == "integer_ties":   # the top-k ends inside a run of equal distances
         assert np.mean(rd[:, -1] == rd[:, -2]) > 0.5
+    # the work counters leave the results unchanged and count within the method's work
+    wi, wd, wk = mipq.adc_search(_t(w.queries), idx, w.nprobe, w.topk, work=True)
+    assert torch.equal(wi, gi) and torch.equal(wd, gd)
+    lut, part, full, lists = wk.cpu().numpy().tolist()
+    pairs = w.queries.shape[0] * w.nprobe
+    probed = off[1:] - off[:-1]
+    assert 0 < lists <= pairs
+    # a scanned list built at least its first 8 table rows; no pair builds more than M
+    assert lut % w.ks == 0 and w.ks * 8 * lists <= lut <= w.ks * w.m * pairs
+    assert 0 < full <= part + full <= int(probed.max()) * pairs
+    print("adc work", case, dict(lut=lut, part=part, full=full, lists=lists, pairs=pairs), flush=True)
 
 
 def test_adc_search_many_lists_matches_oracle():
