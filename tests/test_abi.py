@@ -197,9 +197,9 @@ def test_adc_search_rejects_tables_beyond_lds(L):
     # d = 256, m = 256 (d/m = 1), ks = 256: a 256 KiB table per (query, list)
     adc = L.mipq_adc_search
     F = 4096
-    assert adc(F, 10, 256, F, 64, F, 256, 256, F, F, F, 8, 10, F, F, None, F, 1 << 30, None) == EUNSUPPORTED
+    assert adc(F, 10, 256, F, 64, F, 256, 256, F, F, F, 8, 10, F, F, None, None, F, 1 << 30, None) == EUNSUPPORTED
     # m * ks = 192 * 58 <= 11264 fits with topk = 1024: refused only for the too-small workspace
-    assert adc(F, 10, 192, F, 64, F, 192, 58, F, F, F, 8, 1024, F, F, None, F, 64, None) == ENOMEM
+    assert adc(F, 10, 192, F, 64, F, 192, 58, F, F, F, 8, 1024, F, F, None, None, F, 64, None) == ENOMEM
 
 
 def test_noalloc_encode_rejects_before_touching_the_device(L):
