@@ -15,6 +15,9 @@ import torch  # noqa: F401  (must precede loading the library)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmipq.so")
+# the host-sanitized build (tests of the C ABI only; see build.py)
+if os.environ.get("MIPQ_SANITIZED_LIB"):
+    LIB_PATH = os.environ["MIPQ_SANITIZED_LIB"]
 HEADER = os.path.join(os.path.dirname(HERE), "include", "mipq.h")
 
 _P = ctypes.c_void_p

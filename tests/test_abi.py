@@ -23,6 +23,11 @@ def test_every_header_function_is_exported(L):
         assert name in _lib.SIGNATURES, name
 
 
+def test_the_configured_library_is_the_one_mapped(L):
+    with open("/proc/self/maps") as f:
+        assert _lib.LIB_PATH in f.read()
+
+
 def test_single_hip_runtime_and_version(L):
     assert len(_lib.hip_runtimes_mapped()) == 1
     assert L.mipq_abi_version() == 2

@@ -115,12 +115,16 @@ def test_codebook_gradient_vanishes_after_an_update():
     assert np.all(np.abs(gc.cpu().numpy()) <= bound)
 
 
-def test_full_size_differentiable_codebooks_sampled():
+def test_full_size_differentiable_codebooks():
     """2M x 256 rows, M=32, Ks=256: fit 20 rounds on a 200k sample (BF16),
-    encode all rows (BF16), loss and backward; sampled gradient entries and
-    the loss against the oracle."""
+    encode all rows (BF16), loss and backward.  The loss and 1,000 seeded
+    gradient entries (500 codebook, 500 input) against the oracle's analytic
+    gradient on all rows, and the same entries against central finite
+    differences (h = 1e-3, realised float32 step) of the GPU loss of all 2M
+    rows."""
     w = wl.diff_codebooks()
     xt = _t(w.x)
+    print("full-size differentiable codebooks: fit", flush=True)
     fit = mipq.pq_fit(xt, w.m, w.ks, w.iters, init_rows=_t(w.init_rows), train_rows=_t(w.train_rows),
                       precision="bf16", labels=False)
     cb = fit["codebook"]
@@ -128,23 +132,52 @@ def test_full_size_differentiable_codebooks_sampled():
     loss, gx, gc = mipq.recon_backward(xt, cb, codes)
     cbn = cb.cpu().numpy().astype(np.float64)
     cn = codes.cpu().numpy().astype(np.int64)
-    lref = ograd.loss(w.x, cn, cbn)
+    print("oracle gradient on all rows", flush=True)
+    lref, gxr, gcr = ograd.grads(w.x, cn, cbn)
     assert loss.item() == pytest.approx(lref, rel=1e-11)
-    cbe, xe = wl.fd_entries(5, w.x.shape[0], w.x.shape[1], w.m, w.ks, w.x.shape[1] // w.m, count=1000)
-    gxn = gx.cpu().numpy()
-    xhat = pq.decode(cn[xe[:, 0]], cbn)
-    ref_x = (2.0 * (w.x[xe[:, 0], xe[:, 1]].astype(np.float64) - xhat[np.arange(len(xe)), xe[:, 1]])).astype(np.float32)
-    np.testing.assert_array_equal(gxn[xe[:, 0], xe[:, 1]], ref_x)
-    gcn = gc.cpu().numpy().astype(np.float64)
     ds = w.x.shape[1] // w.m
+    cbe, xe = wl.fd_entries(5, w.x.shape[0], w.x.shape[1], w.m, w.ks, ds, count=1000)
+    gxn = gx.cpu().numpy()
+    np.testing.assert_array_equal(gxn[xe[:, 0], xe[:, 1]], gxr[xe[:, 0], xe[:, 1]].astype(np.float32))
+    gcn = gc.cpu().numpy().astype(np.float64)
     for j in np.unique(cbe[:, 0]):
         sel = cbe[cbe[:, 0] == j]
         lab = cn[:, j]
         cnt = np.bincount(lab, minlength=w.ks).astype(np.float64)
-        xs = w.x[:, j * ds:(j + 1) * ds].astype(np.float64)
-        s = np.stack([np.bincount(lab, weights=xs[:, t], minlength=w.ks) for t in range(ds)], 1)
-        ref = 2.0 * (cnt[:, None] * cbn[j] - s)
-        sabs = np.stack([np.bincount(lab, weights=np.abs(xs[:, t]), minlength=w.ks) for t in range(ds)], 1)
-        scale = 2.0 * (cnt[:, None] * np.abs(cbn[j]) + sabs)
+        absx = np.abs(w.x[:, j * ds:(j + 1) * ds]).astype(np.float64)
+        sabs = np.stack([np.bincount(lab, weights=absx[:, t], minlength=w.ks) for t in range(ds)], 1)
+        scale = 2.0 * (cnt[:, None] * np.abs(cbn[j]) + sabs)   # float64 sums in different orders
         for _, k, t in sel:
-            assert abs(gcn[j, k, t] - ref[k, t]) <= 1e-12 * scale[k, t] + 2.0 ** -23 * abs(ref[k, t]) + 1e-30
+            assert abs(gcn[j, k, t] - gcr[j, k, t]) <= 1e-12 * scale[k, t] + 2.0 ** -23 * abs(gcr[j, k, t]) + 1e-30
+    del gxr
+    print("finite differences on 1,000 entries of the 2M-row loss", flush=True)
+    h = 1e-3
+    ct = cb.clone()
+
+    def loss_at(xx, cc):
+        _, sr = mipq.pq_decode_rmse(codes, cc, xx)
+        return sr[0].item()
+
+    worst = 0.0
+    for j, k, t in cbe:
+        c0 = float(ct[j, k, t].item())
+        cp, cm = np.float32(c0 + h), np.float32(c0 - h)
+        ct[j, k, t] = float(cp)
+        lp = loss_at(xt, ct)
+        ct[j, k, t] = float(cm)
+        lm = loss_at(xt, ct)
+        ct[j, k, t] = c0
+        fd = (lp - lm) / (float(cp) - float(cm))
+        worst = max(worst, abs(fd - gcn[j, k, t]) / max(abs(gcn[j, k, t]), 1.0))
+    for r, c in xe:
+        v0 = float(w.x[r, c])
+        vp, vm = np.float32(v0 + h), np.float32(v0 - h)
+        xt[r, c] = float(vp)
+        lp = loss_at(xt, ct)
+        xt[r, c] = float(vm)
+        lm = loss_at(xt, ct)
+        xt[r, c] = v0
+        fd = (lp - lm) / (float(vp) - float(vm))
+        worst = max(worst, abs(fd - float(gxn[r, c])) / max(abs(float(gxn[r, c])), 1.0))
+    print("worst relative FD error on the 2M-row loss", worst, flush=True)
+    assert worst < 1e-4
