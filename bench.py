@@ -667,7 +667,7 @@ def bench_ivf(args) -> dict:
                      "unit": "T lane-ops/s", "frac": exec_t / PEAK_F32_ADD_T,
                      "traffic": measured_traffic(ADC_TRAFFIC_FILE, ADC_SOURCE),
                      "executed_ops_per_launch": exec_ops, "avg_launch_ms": scan_ms, "launches": ns,
-                     "work_counters": {"table_entries_built": lut_entries, "rows_partial_sum_only": part_rows,
+                     "work_counters": {"table_entries_built": lut_entries, "rows_partial_sum": part_rows,
                                        "rows_full_sum": full_rows, "lists_scanned": lists_scanned,
                                        "pairs": nq * w.nprobe},
                      "lds_view": {"reads_per_launch": lds_reads, "achieved_t_reads_per_s": lds_t,

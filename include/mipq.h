@@ -219,20 +219,38 @@ typedef struct mipq_problem {
   double* objective;         /* OUT optional float64 [iters] (as mipq_pq_fit) */
 } mipq_problem;
 
-/* Launch plan for one problem table: the grid of the persistent assignment
- * (MIPQ_PLAN_AUTOTUNE: the fastest of a few sizes, timed on the problems'
- * own round-0 assignment, which writes their codes and codebooks) and, with
- * MIPQ_PLAN_GRAPH, the launch sequence recorded as HIP graphs (set-up, one
- * Lloyd round replayed `iters` times, encode + error).  A plan is bound to the
- * problem table (pointers and sizes), the shapes and the workspace it was
- * made with; the plan object is host memory owned by the library.
- * mipq_plan_create waits for `stream`.  Graphs are replayed on whatever
- * stream mipq_pq_fit_batched is given. */
+/* Launch plan for one problem table: the grid and register/occupancy variant
+ * of the persistent assignment and, with MIPQ_PLAN_GRAPH, the launch sequence
+ * recorded as HIP graphs (set-up, one Lloyd round replayed `iters` times,
+ * encode + error).  Neither choice changes any output: every grid and variant
+ * computes the same codes and codebooks.
+ *
+ * MIPQ_PLAN_AUTOTUNE: the choice is looked up in a tuning cache, keyed by the
+ * device architecture, subspace width, ks, m and the power-of-two buckets of
+ * the total rows and the problem count.  On a miss (or with MIPQ_PLAN_RETUNE,
+ * which ignores the cache) every variant is timed at 1, 2, 4, 8 and 16 times its
+ * resident blocks on the problems' own round-0 assignment (which writes their
+ * codes; the fit overwrites them), and the fastest is stored.  The cache is
+ * a JSON object, one entry per line, at $MIPQ_TUNE_CACHE, else
+ * $HOME/.cache/mipq/autotune.json; it is rewritten through a temporary file
+ * and rename.  A cache that cannot be read or written is treated as empty and
+ * never fails the call.  Without MIPQ_PLAN_AUTOTUNE: variant 0 at twice its
+ * resident blocks.
+ *
+ * A plan is bound to the problem table (pointers and sizes), the shapes and
+ * the workspace it was made with; the plan object is host memory owned by the
+ * library.  mipq_plan_create waits for `stream`.  Graphs are replayed on
+ * whatever stream mipq_pq_fit_batched is given. */
 typedef struct mipq_plan mipq_plan;
 /* MIPQ_PLAN_DETERMINISTIC: the float64 centroid sums in a fixed order, as
  * MIPQ_DETERMINISTIC does for mipq_pq_fit (runs of the plan are then
  * bit-identical). */
-enum mipq_plan_flags { MIPQ_PLAN_AUTOTUNE = 1, MIPQ_PLAN_GRAPH = 2, MIPQ_PLAN_DETERMINISTIC = 4 };
+enum mipq_plan_flags {
+  MIPQ_PLAN_AUTOTUNE = 1,
+  MIPQ_PLAN_GRAPH = 2,
+  MIPQ_PLAN_DETERMINISTIC = 4,
+  MIPQ_PLAN_RETUNE = 8
+};
 
 /* n: host int64 [nprob], the rows of every problem. */
 size_t mipq_pq_fit_batched_workspace_size(const int64_t* n, int nprob, int d, int m, int ks, int iters,
@@ -245,9 +263,11 @@ int mipq_pq_fit_batched(const mipq_problem* probs, int nprob, int d, int m, int 
                         const mipq_plan* plan, int64_t* rescored, void* ws, size_t ws_bytes, void* stream);
 int mipq_plan_create(mipq_plan** plan, const mipq_problem* probs, int nprob, int d, int m, int ks, int iters,
                      int precision, int flags, void* ws, size_t ws_bytes, void* stream);
-/* info (host int64 [count], count >= 4): [0] assignment grid, [1] resident
- * blocks of the assignment kernel, [2] graphs recorded (0/1), [3] candidates
- * timed, then (grid, nanoseconds per launch) for each candidate. */
+/* info (host int64 [count], count >= 6): [0] assignment grid, [1] resident
+ * blocks of the chosen variant (rounded up to a multiple of 8), [2] graphs
+ * recorded (0/1), [3] variant, [4] choice taken from the tuning cache (0/1),
+ * [5] candidates timed by this call, then (grid, variant, nanoseconds per
+ * launch) for each candidate.  Entries beyond what exists are set to 0. */
 int mipq_plan_info(const mipq_plan* plan, int64_t* info, int count);
 int mipq_plan_destroy(mipq_plan* plan);
 
@@ -381,9 +401,10 @@ int mipq_ii_merge(const int64_t* const* part_offsets, const int32_t* const* part
  *             exact rule on every list
  *   work      OUT optional int64 [4]: work the list scans executed (the exact
  *             skips below avoid the rest): [0] table entries built, [1] rows
- *             summed over their first 4 subspaces only, [2] rows summed over
- *             all subspaces, [3] (query, list) pairs whose list was scanned
- *             (not left at once by the list bound)
+ *             given the partial sum over their first 4 subspaces, [2] rows
+ *             summed over all subspaces (from the first; a row that passed
+ *             the partial sum is counted in both), [3] (query, list) pairs
+ *             whose list was scanned (not left at once by the list bound)
  * Requirements: 1 <= nprobe <= min(kc, 256), 1 <= topk <= 1024, d/m in
  * {1, 2, 4, 8, 16}, d <= 16 or d in {32, 64, 96, 128, 192, 256}, and the
  * table with its key buffer within 64 KiB of LDS (m * ks <= 11264 always

@@ -13,7 +13,7 @@ import torch
 import ctypes
 
 from ._lib import (CHECK_FINITE, DETERMINISTIC, ENONFINITE, PLAN_AUTOTUNE, PLAN_DETERMINISTIC,  # noqa: F401
-                   PLAN_GRAPH, MipqError, MipqProblem, check, lib)
+                   PLAN_GRAPH, PLAN_RETUNE, MipqError, MipqProblem, check, lib)
 
 FP32, BF16, FP8 = 0, 1, 2
 _PREC = {"fp32": FP32, "bf16": BF16, "fp8": FP8, FP32: FP32, BF16: BF16, FP8: FP8}
@@ -384,8 +384,9 @@ def adc_search(q: torch.Tensor, index: dict, nprobe: int, topk: int, wide: bool 
     over an index from ``ii_build``; optionally (appended in this order) the
     int64 number of queries whose probe selection ranked every list exactly
     and the int64 [4] work counters of the list scans (table entries built,
-    rows summed over their first 4 subspaces only, rows summed in full,
-    lists scanned)."""
+    rows given the partial sum over their first 4 subspaces, rows summed in
+    full -- a row that passed the partial sum counts in both -- and lists
+    scanned)."""
     L = lib()
     q = _dev(q, torch.float32, "q")
     dev = q.device
@@ -512,16 +513,18 @@ class BatchedFit:
 
     ``xs``: list of float32 [n_i, d] device tensors; ``init_rows``: list of
     int64 [m, ks] device tensors (rows of the matching x).  With ``plan`` the
-    grid is fixed once (``autotune``: timed on the problems) and, with
-    ``graph``, the launches are replayed from HIP graphs; ``deterministic``
-    forms the float64 centroid sums in a fixed order (needs a plan).
+    grid and kernel variant are fixed once (``autotune``: looked up in the
+    tuning cache, else timed on the problems and stored; ``retune`` ignores
+    the cache) and, with ``graph``, the launches are replayed from HIP graphs;
+    ``deterministic`` forms the float64 centroid sums in a fixed order (needs
+    a plan).
     ``run()`` fills ``results[i]`` = dict(codebook, codes, sse_rmse,
     objective).
     """
 
     def __init__(self, xs, init_rows, m: int, ks: int, iters: int, precision="bf16", plan: bool = True,
                  autotune: bool = True, graph: bool = True, objective: bool = True, sse: bool = True,
-                 codebooks: torch.Tensor | None = None, deterministic: bool = False):
+                 codebooks: torch.Tensor | None = None, deterministic: bool = False, retune: bool = False):
         L = lib()
         if len(xs) != len(init_rows) or not xs:
             raise ValueError("need one init_rows tensor per problem (and at least one problem)")
@@ -566,7 +569,7 @@ class BatchedFit:
             raise ValueError("deterministic batched fits need a plan (plan=True)")
         if plan:
             flags = ((PLAN_AUTOTUNE if autotune else 0) | (PLAN_GRAPH if graph else 0) |
-                     (PLAN_DETERMINISTIC if deterministic else 0))
+                     (PLAN_DETERMINISTIC if deterministic else 0) | (PLAN_RETUNE if retune else 0))
             check(L.mipq_plan_create(ctypes.byref(self._plan), table, len(self.xs), d, m, ks, iters, self.precision,
                                      flags, _ptr(self.ws), self.ws.numel(), _stream(dev)))
 
@@ -579,14 +582,18 @@ class BatchedFit:
         return resc
 
     def info(self) -> dict:
-        """Plan choices: assignment grid, resident blocks, graphs, timed candidates."""
+        """Plan choices: assignment grid and variant, resident blocks, graphs,
+        whether the choice came from the tuning cache, and the candidates this
+        plan timed as (grid, variant, nanoseconds per launch)."""
         if not self._plan.value:
             return {}
-        buf = (ctypes.c_int64 * 32)()
-        check(lib().mipq_plan_info(self._plan, buf, 32))
-        k = int(buf[3])
-        return {"grid": int(buf[0]), "resident": int(buf[1]), "graph": bool(buf[2]),
-                "candidates": [(int(buf[4 + 2 * i]), int(buf[5 + 2 * i])) for i in range(min(k, 14))]}
+        n = 6 + 3 * 16
+        buf = (ctypes.c_int64 * n)()
+        check(lib().mipq_plan_info(self._plan, buf, n))
+        k = min(int(buf[5]), 16)
+        return {"grid": int(buf[0]), "resident": int(buf[1]), "graph": bool(buf[2]), "variant": int(buf[3]),
+                "cached": bool(buf[4]),
+                "candidates": [tuple(int(buf[6 + 3 * i + j]) for j in range(3)) for i in range(k)]}
 
     def close(self):
         if getattr(self, "_plan", None) is not None and self._plan.value:

@@ -77,7 +77,7 @@ class MipqProblem(ctypes.Structure):
                 ("sse_rmse", _P), ("objective", _P)]
 
 
-PLAN_AUTOTUNE, PLAN_GRAPH, PLAN_DETERMINISTIC = 1, 2, 4
+PLAN_AUTOTUNE, PLAN_GRAPH, PLAN_DETERMINISTIC, PLAN_RETUNE = 1, 2, 4, 8
 CHECK_FINITE, DETERMINISTIC = 1, 2   # call flags of pq_fit / pq_encode
 ENONFINITE = -5
 

@@ -536,8 +536,9 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
   }
   const float* qr = q + (int64_t)qi * d;
   const int64_t a = offsets[l], b = offsets[l + 1];
-  // executed work (when `work` is given): table entries built, rows summed
-  // over the first kScanPre subspaces only, rows summed over all subspaces
+  // executed work (when `work` is given): table entries built, rows given the
+  // partial sum over the first kScanPre subspaces, rows summed over all
+  // subspaces (a row that passes the partial sum is summed again in full)
   uint32_t w_lut = 0, w_part = 0, w_full = 0;
   auto report = [&](bool entered) {
     if (!work) return;

@@ -9,8 +9,16 @@
 // timing candidates on the problems themselves) and can record the launch
 // sequence as three HIP graphs: set-up, one Lloyd round (replayed `iters`
 // times; the round index lives in device memory) and encode + error.
+#include <errno.h>
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
+#include <sys/stat.h>
+#include <unistd.h>
 
+#include <map>
+#include <string>
 #include <vector>
 
 #include "mipq_internal.h"
@@ -20,9 +28,11 @@ struct mipq_plan {
   int d = 0, m = 0, ks = 0, iters = 0, precision = 0, flags = 0;
   void* ws = nullptr;
   size_t ws_bytes = 0;
-  int grid = 0;       // blocks of the persistent assignment
-  int resident = 0;   // its resident blocks on this device
-  std::vector<int64_t> tried;   // (grid, nanoseconds) per timed candidate
+  int grid = 0;        // blocks of the persistent assignment
+  int variant = 0;     // its register/occupancy variant
+  int resident = 0;    // resident blocks of that variant on this device
+  bool cached = false; // the choice came from the tuning cache
+  std::vector<int64_t> tried;   // (grid, variant, nanoseconds) per timed candidate
   hipGraphExec_t g_setup = nullptr, g_round = nullptr, g_final = nullptr;
 };
 
@@ -143,13 +153,14 @@ struct BatchRun {
   bool full, vec;
   int grid;
   bool det = false;   // MIPQ_PLAN_DETERMINISTIC
+  int variant = 0;    // register/occupancy variant of the assignment
 };
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 BatchRun make_run(const BatchLayout& L, const mipq_problem* probs, int nprob, int d, int m, int ks, int iters,
                   int grid) {
-  BatchRun r{L, nprob, d, m, ks, iters, true, true, grid, false};
+  BatchRun r{L, nprob, d, m, ks, iters, true, true, grid, false, 0};
   const int ds = d / m;
   const int nb = (ds + 7) / 8;
   r.full = (ds == nb * 8) && (d % 4 == 0);
@@ -175,7 +186,7 @@ int run_round(const BatchRun& r, hipStream_t s) {
   int rc;
   const BatchLayout& L = r.L;
   if ((rc = launch_assign_bf16_batched(L.probs, r.nprob, L.units, r.d, r.m, r.ks, L.aop, L.aop_stride, L.cmax, L.mu,
-                                       r.full, r.grid, nullptr, s)))
+                                       r.full, r.variant, r.grid, nullptr, s)))
     return rc;
   return launch_update_batched(L.probs, r.nprob, L.items, r.d, r.m, r.ks, L.c64, L.part_s, L.part_cnt, L.part_j,
                                L.j_all, L.round, r.iters, L.aop, L.aop_stride, L.cmax, L.mu, r.det, s);
@@ -187,7 +198,7 @@ int run_final(const BatchRun& r, hipStream_t s) {
   const BatchLayout& L = r.L;
   if ((rc = launch_zero_u32(reinterpret_cast<uint32_t*>(L.resc), 2, s))) return rc;
   if ((rc = launch_assign_bf16_batched(L.probs, r.nprob, L.units, r.d, r.m, r.ks, L.aop, L.aop_stride, L.cmax, L.mu,
-                                       r.full, r.grid, L.resc, s)))
+                                       r.full, r.variant, r.grid, L.resc, s)))
     return rc;
   if ((rc = launch_decode_sse_batched(L.probs, r.nprob, L.dblocks, r.d, r.m, r.ks, r.vec, L.dpart, s))) return rc;
   return launch_objective_batched(L.probs, r.nprob, r.iters, r.m, L.j_all, s);
@@ -223,6 +234,133 @@ void destroy_graphs(mipq_plan* p) {
     }
 }
 
+// ---- tuning cache ------------------------------------------------------------
+// The plan's choice (grid multiple of the resident blocks, variant) per
+// (device architecture, subspace width, ks, m, size bucket), kept in a JSON
+// object (written one entry per line; read in any layout):
+//   "gfx950:sramecc+:xnack-|ds=8|ks=256|m=12|rows=2^23|probs=2^6": {"grid_mult": 8, "variant": 0, "ns": 2781430},
+// at $MIPQ_TUNE_CACHE, else $HOME/.cache/mipq/autotune.json.  Reading or
+// writing it never fails a call: an unreadable cache is an empty one.
+struct TuneEntry {
+  int grid_mult = 0, variant = 0;
+  long long ns = 0;
+};
+
+std::string tune_cache_path() {
+  const char* e = getenv("MIPQ_TUNE_CACHE");
+  if (e && *e) return e;
+  const char* h = getenv("HOME");
+  return std::string(h && *h ? h : ".") + "/.cache/mipq/autotune.json";
+}
+
+int log2_bucket(int64_t v) {
+  int b = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++b;
+  }
+  return b;
+}
+
+std::string tune_key(int ds, int ks, int m, int64_t rows, int nprob) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+  char buf[256];
+  snprintf(buf, sizeof(buf), "%s|ds=%d|ks=%d|m=%d|rows=2^%d|probs=2^%d", arch.c_str(), ds, ks, m, log2_bucket(rows),
+           log2_bucket(nprob));
+  return buf;
+}
+
+// the integer after "name": inside [b, e), or false
+bool json_int(const char* b, const char* e, const char* name, long long* out) {
+  const std::string pat = std::string("\"") + name + "\"";
+  const std::string obj(b, e);
+  const size_t at = obj.find(pat);
+  if (at == std::string::npos) return false;
+  const char* p = obj.c_str() + at + pat.size();
+  while (*p == ' ' || *p == '\t' || *p == '\n' || *p == '\r') ++p;
+  if (*p++ != ':') return false;
+  char* end = nullptr;
+  errno = 0;
+  const long long v = strtoll(p, &end, 10);
+  if (end == p || errno) return false;
+  *out = v;
+  return true;
+}
+
+// entries "key": {"grid_mult": g, "variant": v, "ns": t} in any layout;
+// anything else (or a damaged entry) is skipped
+std::map<std::string, TuneEntry> tune_cache_read(const std::string& path) {
+  std::map<std::string, TuneEntry> out;
+  FILE* f = fopen(path.c_str(), "r");
+  if (!f) return out;
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = fread(buf, 1, sizeof(buf), f)) > 0 && text.size() < (1u << 24)) text.append(buf, got);
+  fclose(f);
+  size_t pos = 0;
+  while ((pos = text.find('"', pos)) != std::string::npos) {
+    const size_t kend = text.find('"', pos + 1);
+    if (kend == std::string::npos) break;
+    const std::string key = text.substr(pos + 1, kend - pos - 1);
+    size_t q = kend + 1;
+    while (q < text.size() && (text[q] == ' ' || text[q] == '\t' || text[q] == '\n' || text[q] == '\r')) ++q;
+    if (q >= text.size() || text[q] != ':') {
+      pos = kend + 1;
+      continue;
+    }
+    ++q;
+    while (q < text.size() && (text[q] == ' ' || text[q] == '\t' || text[q] == '\n' || text[q] == '\r')) ++q;
+    if (q >= text.size() || text[q] != '{') {   // a field of an entry, not a key
+      pos = q;
+      continue;
+    }
+    const size_t close = text.find('}', q);
+    if (close == std::string::npos) break;
+    long long g = 0, v = 0, t = 0;
+    const char* b = text.c_str() + q;
+    const char* e = text.c_str() + close;
+    if (json_int(b, e, "grid_mult", &g) && json_int(b, e, "variant", &v) && json_int(b, e, "ns", &t) && g >= 1 &&
+        g <= 64 && v >= 0 && v < kBatchedVariants && t >= 0) {
+      TuneEntry te;
+      te.grid_mult = (int)g;
+      te.variant = (int)v;
+      te.ns = t;
+      out[key] = te;
+    }
+    pos = close + 1;
+  }
+  return out;
+}
+
+void make_dirs(const std::string& path) {   // parents of path
+  for (size_t i = 1; i < path.size(); ++i)
+    if (path[i] == '/') {
+      const std::string dir = path.substr(0, i);
+      if (mkdir(dir.c_str(), 0755) != 0 && errno != EEXIST) return;
+    }
+}
+
+void tune_cache_store(const std::string& path, const std::string& key, const TuneEntry& t) {
+  std::map<std::string, TuneEntry> all = tune_cache_read(path);
+  all[key] = t;
+  make_dirs(path);
+  const std::string tmp = path + ".tmp" + std::to_string((long long)getpid());
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  fprintf(f, "{\n");
+  size_t i = 0;
+  for (const auto& kv : all)
+    fprintf(f, " \"%s\": {\"grid_mult\": %d, \"variant\": %d, \"ns\": %lld}%s\n", kv.first.c_str(),
+            kv.second.grid_mult, kv.second.variant, kv.second.ns, ++i < all.size() ? "," : "");
+  fprintf(f, "}\n");
+  const bool ok = fclose(f) == 0;
+  if (!ok || rename(tmp.c_str(), path.c_str()) != 0) remove(tmp.c_str());
+}
+
 bool same_problems(const mipq_problem* a, const std::vector<mipq_problem>& b, int nprob) {
   if ((int)b.size() != nprob) return false;
   return memcmp(a, b.data(), sizeof(mipq_problem) * nprob) == 0;
@@ -250,7 +388,7 @@ int mipq_plan_create(mipq_plan** out, const mipq_problem* probs, int nprob, int 
   *out = nullptr;
   if ((rc = check_batch_shape(nprob, d, m, ks, iters, precision))) return rc;
   if ((rc = check_problems(probs, nprob, m))) return rc;
-  if (flags & ~(MIPQ_PLAN_AUTOTUNE | MIPQ_PLAN_GRAPH | MIPQ_PLAN_DETERMINISTIC))
+  if (flags & ~(MIPQ_PLAN_AUTOTUNE | MIPQ_PLAN_GRAPH | MIPQ_PLAN_DETERMINISTIC | MIPQ_PLAN_RETUNE))
     return fail(MIPQ_EINVAL, "unknown plan flags 0x%x", flags);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const std::vector<int64_t> n = sizes_of(probs, nprob);
@@ -277,50 +415,81 @@ int mipq_plan_create(mipq_plan** out, const mipq_problem* probs, int nprob, int 
     delete plan;
     return code;
   };
-  if ((rc = assign_bf16_batched_resident(d / m, ks, r.full, &plan->resident))) return bail(rc);
-  const int res8 = ((plan->resident > 8 ? plan->resident : 8) + 7) / 8 * 8;
-  plan->grid = 2 * res8;
+  // resident blocks of each variant, rounded up to whole XCD rounds (8)
+  int res8[kBatchedVariants];
+  for (int v = 0; v < kBatchedVariants; ++v) {
+    int res = 0;
+    if ((rc = assign_bf16_batched_resident(d / m, ks, r.full, v, &res))) return bail(rc);
+    res8[v] = ((res > 8 ? res : 8) + 7) / 8 * 8;
+  }
+  plan->variant = 0;
+  plan->grid = 2 * res8[0];
   if ((rc = upload_table(L, table, s))) return bail(rc);
 
   if (flags & MIPQ_PLAN_AUTOTUNE) {
-    // time the assignment of round 0 (initial codebooks) at a few grid sizes;
-    // the codes it writes are overwritten by the fit
-    if ((rc = run_setup(r, s))) return bail(rc);
-    hipEvent_t a = nullptr, b = nullptr;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
-      if (a) (void)hipEventDestroy(a);
-      return bail(fail(MIPQ_EHIP, "hipEventCreate failed"));
-    }
-    float best = 0.0f;
-    for (int mult : {1, 2, 4, 8}) {
-      r.grid = res8 * mult;
-      float ms = 0.0f;
-      hipError_t e = hipSuccess;
-      rc = launch_assign_bf16_batched(L.probs, nprob, L.units, d, m, ks, L.aop, L.aop_stride, L.cmax, L.mu, r.full,
-                                      r.grid, nullptr, s);   // warm-up
-      if (!rc && (e = hipEventRecord(a, s)) == hipSuccess) {
-        for (int rep = 0; rep < 2 && !rc; ++rep)
+    int64_t rows = 0;
+    for (int64_t v : n) rows += v;
+    const std::string path = tune_cache_path();
+    const std::string key = tune_key(d / m, ks, m, rows, nprob);
+    const std::map<std::string, TuneEntry> cache = (flags & MIPQ_PLAN_RETUNE) ? std::map<std::string, TuneEntry>()
+                                                                              : tune_cache_read(path);
+    const auto hit = cache.find(key);
+    if (hit != cache.end()) {
+      plan->variant = hit->second.variant;
+      plan->grid = res8[plan->variant] * hit->second.grid_mult;
+      plan->cached = true;
+    } else {
+      // time the assignment of round 0 (initial codebooks) for every variant
+      // at a few grid sizes; the codes it writes are overwritten by the fit
+      if ((rc = run_setup(r, s))) return bail(rc);
+      hipEvent_t a = nullptr, b = nullptr;
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        if (a) (void)hipEventDestroy(a);
+        return bail(fail(MIPQ_EHIP, "hipEventCreate failed"));
+      }
+      float best = 0.0f;
+      int best_mult = 2;
+      for (int v = 0; v < kBatchedVariants; ++v)
+        for (int mult : {1, 2, 4, 8, 16}) {
+          const int grid = res8[v] * mult;
+          float ms = 0.0f;
+          hipError_t e = hipSuccess;
           rc = launch_assign_bf16_batched(L.probs, nprob, L.units, d, m, ks, L.aop, L.aop_stride, L.cmax, L.mu,
-                                          r.full, r.grid, nullptr, s);
-        if (!rc && (e = hipEventRecord(b, s)) == hipSuccess && (e = hipEventSynchronize(b)) == hipSuccess)
-          e = hipEventElapsedTime(&ms, a, b);
-      }
-      if (rc || e != hipSuccess) {
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
-        return bail(rc ? rc : hip_fail(e, "autotune timing"));
-      }
-      plan->tried.push_back(r.grid);
-      plan->tried.push_back((int64_t)(ms * 0.5e6));
-      if (best == 0.0f || ms < best) {
-        best = ms;
-        plan->grid = r.grid;
-      }
+                                          r.full, v, grid, nullptr, s);   // warm-up
+          if (!rc && (e = hipEventRecord(a, s)) == hipSuccess) {
+            for (int rep = 0; rep < 2 && !rc; ++rep)
+              rc = launch_assign_bf16_batched(L.probs, nprob, L.units, d, m, ks, L.aop, L.aop_stride, L.cmax,
+                                              L.mu, r.full, v, grid, nullptr, s);
+            if (!rc && (e = hipEventRecord(b, s)) == hipSuccess && (e = hipEventSynchronize(b)) == hipSuccess)
+              e = hipEventElapsedTime(&ms, a, b);
+          }
+          if (rc || e != hipSuccess) {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            return bail(rc ? rc : hip_fail(e, "autotune timing"));
+          }
+          plan->tried.push_back(grid);
+          plan->tried.push_back(v);
+          plan->tried.push_back((int64_t)(ms * 0.5e6));
+          if (best == 0.0f || ms < best) {
+            best = ms;
+            plan->grid = grid;
+            plan->variant = v;
+            best_mult = mult;
+          }
+        }
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+      TuneEntry t;
+      t.grid_mult = best_mult;
+      t.variant = plan->variant;
+      t.ns = (long long)(best * 0.5e6);
+      tune_cache_store(path, key, t);
     }
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
   }
+  plan->resident = res8[plan->variant];
   r.grid = plan->grid;
+  r.variant = plan->variant;
 
   if (flags & MIPQ_PLAN_GRAPH) {
     hipStream_t cs = nullptr;
@@ -339,12 +508,14 @@ int mipq_plan_create(mipq_plan** out, const mipq_problem* probs, int nprob, int 
 }
 
 int mipq_plan_info(const mipq_plan* plan, int64_t* info, int count) {
-  if (!plan || !info || count < 4) return fail(MIPQ_EINVAL, "plan and info[>= 4] are required");
+  if (!plan || !info || count < 6) return fail(MIPQ_EINVAL, "plan and info[>= 6] are required");
   info[0] = plan->grid;
   info[1] = plan->resident;
   info[2] = plan->g_round != nullptr;
-  info[3] = (int64_t)plan->tried.size() / 2;
-  for (int i = 4; i < count; ++i) info[i] = (size_t)(i - 4) < plan->tried.size() ? plan->tried[i - 4] : 0;
+  info[3] = plan->variant;
+  info[4] = plan->cached;
+  info[5] = (int64_t)plan->tried.size() / 3;
+  for (int i = 6; i < count; ++i) info[i] = (size_t)(i - 6) < plan->tried.size() ? plan->tried[i - 6] : 0;
   return MIPQ_OK;
 }
 
@@ -378,19 +549,22 @@ int mipq_pq_fit_batched(const mipq_problem* probs, int nprob, int d, int m, int 
     for (int it = 0; it < iters; ++it) MIPQ_HIP(hipGraphLaunch(plan->g_round, s));
     MIPQ_HIP(hipGraphLaunch(plan->g_final, s));
   } else {
-    int grid = 0;
+    int grid = 0, variant = 0;
     if (plan) {
       grid = plan->grid;
+      variant = plan->variant;
     } else {
       if ((rc = upload_table(L, table, s))) return rc;
       const int ds = d / m;
       int resident = 0;
-      if ((rc = assign_bf16_batched_resident(ds, ks, make_run(L, probs, nprob, d, m, ks, iters, 8).full, &resident)))
+      if ((rc = assign_bf16_batched_resident(ds, ks, make_run(L, probs, nprob, d, m, ks, iters, 8).full, 0,
+                                             &resident)))
         return rc;
       grid = 2 * (((resident > 8 ? resident : 8) + 7) / 8 * 8);
     }
     BatchRun r = make_run(L, probs, nprob, d, m, ks, iters, grid);
     r.det = plan && (plan->flags & MIPQ_PLAN_DETERMINISTIC);
+    r.variant = variant;
     if ((rc = run_setup(r, s))) return rc;
     for (int it = 0; it < iters; ++it)
       if ((rc = run_round(r, s))) return rc;

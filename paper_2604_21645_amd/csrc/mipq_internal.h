@@ -190,10 +190,13 @@ int launch_init_batched(const BatchProb* probs, int nprob, int d, int m, int ks,
                         hipStream_t s);
 int launch_pack_bf16_batched(const BatchProb* probs, int nprob, int m, int ks, int ds, void* aop,
                              size_t aop_stride, float* cmax, float* mu, hipStream_t s);
-int assign_bf16_batched_resident(int ds, int ks, bool full, int* resident);
+// the batched assignment in two variants: 0 re-decides pending rows one at a
+// time, 1 with the centroids held in registers (more registers per wave)
+constexpr int kBatchedVariants = 2;
+int assign_bf16_batched_resident(int ds, int ks, bool full, int variant, int* resident);
 int launch_assign_bf16_batched(const BatchProb* probs, int nprob, int64_t units, int d, int m, int ks,
                                const void* aop, size_t aop_stride, const float* cmax, const float* mu, bool full,
-                               int grid, int64_t* rescored, hipStream_t s);
+                               int variant, int grid, int64_t* rescored, hipStream_t s);
 // one Lloyd update of every problem, then advances *round
 int launch_update_batched(const BatchProb* probs, int nprob, int64_t items, int d, int m, int ks, double* c64,
                           double* part_s, uint32_t* part_cnt, double* part_j, double* j_all,

@@ -679,8 +679,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NB == 
 // segment's operands in registers while it lasts.  Logical blocks are
 // numbered so that each XCD (hardware block id mod 8) holds a contiguous
 // eighth of the list: neighbouring segments share that XCD's L2.
-template <int NB, int NT, bool FULL>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NB == 1 ? 3 : 1, 8))) void k_assign_bf16_batched(
+// REG: how a piece's pending rows are re-decided (the register form, with the
+// subspace's centroids held in registers across the piece's rows, or one row
+// at a time with the centroids re-read); the register form is faster per row
+// but raises the kernel's register count, so the plan chooses between them.
+template <int NB, int NT, bool FULL, bool REG>
+__global__ __launch_bounds__(kThreads) void k_assign_bf16_batched(
     const BatchProb* __restrict__ probs, int nprob, int64_t units, int d, int m, int ks, int ds,
     const bf16x8* __restrict__ aop, size_t aop_stride, const float* __restrict__ cmax,
     const float* __restrict__ mu, unsigned long long* __restrict__ rescored, float e_cross, float e_norm,
@@ -725,7 +729,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NB == 
     // rows in pieces of PC, so that a piece's pending list fits the wave's LDS
     const int64_t rb = t0 * 32, re = min(n, t1 * 32);
     for (int64_t pb = rb; pb < re; pb += PC)
-      nres += (uint32_t)assign_rows64<NB, NT, FULL, false, false>(o, bd, px, d, ds, m, ks, sub, pb,
+      nres += (uint32_t)assign_rows64<NB, NT, FULL, false, REG>(o, bd, px, d, ds, m, ks, sub, pb,
                                                                   min(re, pb + PC),
                                                                   probs[p].c32 + (int64_t)sub * ks * ds,
                                                                   probs[p].codes, pend_all + w * PC, lane,
@@ -1123,19 +1127,25 @@ int launch_assign_bf16(const float* x, int64_t n, int d, int m, int ks, const vo
 int assign_bf16_sse_parts(int64_t n, int m) { return 4 * bf16_geometry(n, m).blocks; }
 
 namespace {
-template <int NB, int NT, bool FULL>
+template <int NB, int NT, bool FULL, bool REG>
 const void* batched_fn() {
-  return reinterpret_cast<const void*>(&k_assign_bf16_batched<NB, NT, FULL>);
+  return reinterpret_cast<const void*>(&k_assign_bf16_batched<NB, NT, FULL, REG>);
 }
-const void* pick_batched(int ds, int ks, bool full) {
+// variant 0: pending rows re-decided one at a time; variant 1: register form
+template <int NB, int NT>
+const void* batched_pick(bool full, int variant) {
+  if (variant == 0) return full ? batched_fn<NB, NT, true, false>() : batched_fn<NB, NT, false, false>();
+  return full ? batched_fn<NB, NT, true, true>() : batched_fn<NB, NT, false, true>();
+}
+const void* pick_batched(int ds, int ks, bool full, int variant) {
   const int nb = (ds + 7) / 8;
   const int nt = tiles_for(ks);
-#define PICK(NB)                                                                  \
-  switch (nt) {                                                                   \
-    case 1: return full ? batched_fn<NB, 1, true>() : batched_fn<NB, 1, false>(); \
-    case 2: return full ? batched_fn<NB, 2, true>() : batched_fn<NB, 2, false>(); \
-    case 4: return full ? batched_fn<NB, 4, true>() : batched_fn<NB, 4, false>(); \
-    default: return full ? batched_fn<NB, 8, true>() : batched_fn<NB, 8, false>(); \
+#define PICK(NB)                                                  \
+  switch (nt) {                                                   \
+    case 1: return batched_pick<NB, 1>(full, variant);            \
+    case 2: return batched_pick<NB, 2>(full, variant);            \
+    case 4: return batched_pick<NB, 4>(full, variant);            \
+    default: return batched_pick<NB, 8>(full, variant);           \
   }
   if (nb == 1) PICK(1)
   PICK(2)
@@ -1143,9 +1153,9 @@ const void* pick_batched(int ds, int ks, bool full) {
 }
 }  // namespace
 
-int assign_bf16_batched_resident(int ds, int ks, bool full, int* resident) {
+int assign_bf16_batched_resident(int ds, int ks, bool full, int variant, int* resident) {
   int per_cu = 0, dev = 0, cus = 0;
-  MIPQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pick_batched(ds, ks, full), kThreads, 0));
+  MIPQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pick_batched(ds, ks, full, variant), kThreads, 0));
   MIPQ_HIP(hipGetDevice(&dev));
   MIPQ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   *resident = per_cu * cus;
@@ -1154,7 +1164,7 @@ int assign_bf16_batched_resident(int ds, int ks, bool full, int* resident) {
 
 int launch_assign_bf16_batched(const BatchProb* probs, int nprob, int64_t units, int d, int m, int ks,
                                const void* aop, size_t aop_stride, const float* cmax, const float* mu, bool full,
-                               int grid, int64_t* rescored, hipStream_t s) {
+                               int variant, int grid, int64_t* rescored, hipStream_t s) {
   if (units == 0) return MIPQ_OK;
   if (grid < 8 || grid % 8) return fail(MIPQ_EINVAL, "batched assignment grid must be a positive multiple of 8");
   const int ds = d / m;
@@ -1164,7 +1174,7 @@ int launch_assign_bf16_batched(const BatchProb* probs, int nprob, int64_t units,
   void* args[] = {(void*)&probs, (void*)&nprob, (void*)&units, (void*)&d, (void*)&m, (void*)&ks, (void*)&ds,
                   (void*)&aop, (void*)&aop_stride, (void*)&cmax, (void*)&mu, (void*)&resc,
                   (void*)&bd.e_cross, (void*)&bd.e_norm, (void*)&bd.g_exact};
-  MIPQ_HIP(hipLaunchKernel(pick_batched(ds, ks, full), dim3(grid), dim3(kThreads), args, 0, s));
+  MIPQ_HIP(hipLaunchKernel(pick_batched(ds, ks, full, variant), dim3(grid), dim3(kThreads), args, 0, s));
   return MIPQ_OK;
 }
 

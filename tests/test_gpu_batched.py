@@ -8,6 +8,9 @@ exact, so there the comparison is bit for bit end to end; on real-valued
 rows the codes and errors are compared in lockstep (same codebook).
 """
 
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -18,6 +21,18 @@ from synth import workloads as wl
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _private_tune_cache(tmp_path_factory):
+    """Plans of this module read and write a tuning cache of their own."""
+    old = os.environ.get("MIPQ_TUNE_CACHE")
+    os.environ["MIPQ_TUNE_CACHE"] = str(tmp_path_factory.mktemp("tune") / "autotune.json")
+    yield
+    if old is None:
+        del os.environ["MIPQ_TUNE_CACHE"]
+    else:
+        os.environ["MIPQ_TUNE_CACHE"] = old
 
 
 def _t(a):
@@ -80,7 +95,8 @@ def test_integer_rows_equal_single_calls_bit_for_bit(mode):
     if mode == "graph":
         info = b.info()
         print("plan", info, flush=True)
-        assert info["graph"] and info["grid"] % 8 == 0 and len(info["candidates"]) >= 2
+        assert info["graph"] and info["grid"] % 8 == 0 and info["variant"] in (0, 1)
+        assert info["cached"] or len(info["candidates"]) == 10
     b.close()
 
 
@@ -193,3 +209,68 @@ def test_deterministic_plan_repeats_and_equals_single_deterministic_fits():
         fit = mipq.pq_fit(xt[i], m, ks, iters, init_rows=it[i], precision="bf16", labels=False, deterministic=True)
         assert torch.equal(r["codebook"], fit["codebook"]), i
         assert torch.equal(r["objective"], fit["objective"]), i
+
+
+def _outputs(b):
+    return [{k: v.clone() for k, v in r.items()} for r in b.results]
+
+
+@pytest.mark.parametrize("kind", ["integer", "float"])
+def test_every_tuner_choice_gives_the_same_outputs(kind, tmp_path):
+    """The tuner times both kernel variants at 1, 2, 4, 8 and 16 times their
+    resident blocks and stores the fastest in the cache; a second plan takes
+    it from there.  Every (variant, grid) forced through the cache gives the
+    same codebooks, codes, errors and objectives bit for bit (integer rows:
+    exact float64 sums in any order; float rows: deterministic sums)."""
+    cache = tmp_path / "tune.json"
+    os.environ["MIPQ_TUNE_CACHE"] = str(cache)
+    m, ks, iters, d = 12, 256, 3, 96
+    det = kind == "float"
+    xs, inits = _problems([700, 20011, 4097, 256, 9000], d, m, ks, kind, seed=43)
+    xt = [_t(x) for x in xs]
+    it = [_t(i) for i in inits]
+
+    def plan(**kw):
+        b = mipq.BatchedFit(xt, it, m, ks, iters, plan=True, graph=True, deterministic=det, **kw)
+        b.run()
+        torch.cuda.synchronize()
+        return b
+
+    b = plan(autotune=True, retune=True)
+    info = b.info()
+    print("tuned", info, flush=True)
+    assert not info["cached"] and len(info["candidates"]) == 10
+    assert {(c[1]) for c in info["candidates"]} == {0, 1}
+    fastest = min(info["candidates"], key=lambda c: c[2])
+    assert (info["grid"], info["variant"]) == fastest[:2]
+    ref = _outputs(b)
+    b.close()
+    entries = json.loads(cache.read_text())
+    assert len(entries) == 1
+    key, val = next(iter(entries.items()))
+    assert key.startswith(torch.cuda.get_device_properties(0).gcnArchName)
+    assert "|ds=8|ks=256|m=12|" in key and val["variant"] == info["variant"]
+
+    b = plan(autotune=True)   # a cache hit: nothing timed
+    hit = b.info()
+    assert hit["cached"] and not hit["candidates"]
+    assert (hit["grid"], hit["variant"]) == (info["grid"], info["variant"])
+    b.close()
+
+    for variant in (0, 1):
+        for mult in (1, 2, 4, 8, 16):
+            cache.write_text(json.dumps({key: {"grid_mult": mult, "variant": variant, "ns": 1}}, indent=0))
+            b = plan(autotune=True)
+            got = b.info()
+            print("forced", variant, mult, got, flush=True)
+            assert got["cached"] and got["variant"] == variant and got["grid"] == mult * got["resident"]
+            for i, (r0, r1) in enumerate(zip(ref, b.results)):
+                for k in r0:
+                    assert torch.equal(r0[k], r1[k]), (variant, mult, i, k)
+            b.close()
+
+    cache.write_text("not json {")   # unreadable: ignored, retuned, rewritten
+    b = plan(autotune=True)
+    assert not b.info()["cached"]
+    b.close()
+    assert key in json.loads(cache.read_text())

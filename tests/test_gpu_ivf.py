@@ -146,7 +146,8 @@ def test_adc_search_m16_long_lists_matches_oracle(case, nprobe, topk):
     assert 0 < lists <= pairs
     # a scanned list built at least its first 8 table rows; no pair builds more than M
     assert lut % w.ks == 0 and w.ks * 8 * lists <= lut <= w.ks * w.m * pairs
-    assert 0 < full <= part + full <= int(probed.max()) * pairs
+    # every row of a scanned list is summed partially, in full, or both
+    assert 0 < full <= int(probed.max()) * pairs and part <= int(probed.max()) * pairs
     print("adc work", case, dict(lut=lut, part=part, full=full, lists=lists, pairs=pairs), flush=True)
 
 
