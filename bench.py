@@ -35,7 +35,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_F32_ADD_T = 256 * 64 * 2.4e9 / 1e12   # unpacked float32 adds per second (T), 39.3
 CSRC = os.path.join(ROOT, "paper_2604_21645_amd", "csrc")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_assign_bf16_integer_pq_1M_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fit_round_bf16_integer_pq_1M_traffic.json")
 MFMA_SOURCE = os.path.join(CSRC, "pq_mfma.hip")
 ADC_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_adc_scan_ivf_adc_10M_traffic.json")
 ADC_SOURCE = os.path.join(CSRC, "adc.hip")
@@ -104,7 +104,7 @@ def measured_traffic(traffic_file: str = TRAFFIC_FILE, source: str = MFMA_SOURCE
     return t.get("bytes_per_launch")
 
 
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_assign_bf16_integer_pq_1M_counters.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_fit_round_bf16_integer_pq_1M_counters.json")
 
 
 def measured_counters(counters_file: str = COUNTERS_FILE, source: str = MFMA_SOURCE):
@@ -283,22 +283,24 @@ def bench_integer_pq(args) -> dict:
     timed("bf16", prof_steps, 0, profile=True)
     L = _lib.lib()
     import ctypes
-    nl, tot = ctypes.c_int64(0), ctypes.c_double(0)
-    L.mipq_profile_collect(_lib.KERNELS["assign_bf16"], ctypes.byref(nl), ctypes.byref(tot))
     kernel_stats = {}
     for name, kid in _lib.KERNELS.items():
-        if name == "assign_bf16":
-            kernel_stats[name] = (nl.value, tot.value)
-            continue
         a, b = ctypes.c_int64(0), ctypes.c_double(0)
         L.mipq_profile_collect(kid, ctypes.byref(a), ctypes.byref(b))
         if a.value:
             kernel_stats[name] = (a.value, b.value)
-    launches_per_step = w.iters + 1
-    rows_per_step = w.iters * n_train + n
-    alg_bytes_per_launch = rows_per_step * (4 * d + w.m) / launches_per_step
-    avg_launch_ms = tot.value / max(nl.value, 1)
-    achieved = alg_bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    # the dominant kernel: the fit's fused rounds (assignment + float64 sums),
+    # one launch per round over the n_train sampled rows; the encode's
+    # assignment of all n rows is reported beside it.  Algorithmic bytes per
+    # row: its float32 slice of every subspace read once (4 d) and its codes
+    # written (m); the sums and partials are not counted.
+    nl, tot = kernel_stats.get("fit_round_bf16", (0, 0.0))
+    alg_bytes_per_launch = n_train * (4 * d + w.m)
+    avg_launch_ms = tot / max(nl, 1)
+    achieved = alg_bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if nl else 0.0
+    ne, te = kernel_stats.get("assign_bf16", (0, 0.0))
+    enc_alg = n * (4 * d + w.m)
+    enc_ms = te / max(ne, 1)
     sse, rmse = sr.cpu().numpy().tolist()
 
     fp32 = None
@@ -363,7 +365,7 @@ def bench_integer_pq(args) -> dict:
         "oracle_parity": parity or None,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_assign_bf16",
+            "kernel": "k_fit_round_bf16",
             "achieved": achieved,
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
@@ -371,9 +373,13 @@ def bench_integer_pq(args) -> dict:
             "traffic": traffic,
             "alg_bytes_per_launch": alg_bytes_per_launch,
             "avg_launch_ms": avg_launch_ms,
-            "launches": nl.value,
+            "launches": nl,
             "valu_frac": (counters or {}).get("valu_busy"),
             "mfma_util": (counters or {}).get("mfma_busy"),
+            "encode_kernel": {"kernel": "k_assign_bf16", "alg_bytes_per_launch": enc_alg, "avg_launch_ms": enc_ms,
+                              "launches": ne,
+                              "achieved": enc_alg / (enc_ms * 1e-3) / 1e9 if ne else 0.0,
+                              "frac": enc_alg / (enc_ms * 1e-3) / 1e9 / PEAK_HBM_GBS if ne else 0.0},
         },
         "kernels_ms_per_step": {k: v[1] / prof_steps for k, v in kernel_stats.items()},
         "cpu_baseline": base,
@@ -414,7 +420,7 @@ def bench_plain(args) -> dict:
     step()
     torch.cuda.synchronize()
     L.mipq_profile_enable(0)
-    kt = kernel_totals(L, ["assign_bf16", "update", "finalize", "pack_bf16"])
+    kt = kernel_totals(L, ["fit_round_bf16", "assign_bf16", "update", "finalize", "pack_bf16"])
     log("plain_pq: capturing one step in a graph")
     g = torch.cuda.CUDAGraph()
     cs = torch.cuda.Stream()
@@ -429,10 +435,12 @@ def bench_plain(args) -> dict:
     ms, _ = timed_steps(g.replay, args.steps, args.warmup)
     same = bool(torch.equal(cb_g, cb_e) and torch.equal(codes_g, codes_e) and torch.equal(sr_g, sr_e))
     sse, rmse = sr_g.cpu().numpy().tolist()
-    na, ta = kt["assign_bf16"]
-    fit_launches = w.iters
-    rows_per_step = w.iters * n + n
-    alg_per_launch = rows_per_step * (4 * d + w.m) / max(na, 1)
+    # the fit's fused rounds (one launch per round, all n rows) and the
+    # encode's assignment: the same n (4 d + m) algorithmic bytes per launch
+    nf, tf_ms = kt["fit_round_bf16"]
+    ne, te_ms = kt["assign_bf16"]
+    na, ta = nf + ne, tf_ms + te_ms
+    alg_per_launch = n * (4 * d + w.m)
     avg_ms = ta / max(na, 1)
     achieved = alg_per_launch / (avg_ms * 1e-3) / 1e9 if na else 0.0
     base = None
@@ -454,8 +462,8 @@ def bench_plain(args) -> dict:
         "ms_per_step_eager": ms_eager,
         "graph_replay_identical_to_eager": same,
         "rmse": rmse,
-        "roofline": {"bound": "hbm", "kernel": "k_assign_bf16", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+        "roofline": {"bound": "hbm", "kernel": "k_fit_round_bf16 + k_assign_bf16", "achieved": achieved,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
                      "alg_bytes_per_launch": alg_per_launch, "avg_launch_ms": avg_ms, "launches": na,
                      "note": "5 MB per launch: bound by launch and wave start-up latency, not by a roofline"},
         "kernels_ms_per_step_eager": {k: v[1] for k, v in kt.items()},
@@ -592,8 +600,8 @@ def bench_ivf(args) -> dict:
     ca = kernel_totals(L, ["coarse_assign"])["coarse_assign"]
     build()
     torch.cuda.synchronize()
-    kb = kernel_totals(L, ["coarse_pack", "coarse_assign", "sort", "coarse_update", "assign_bf16", "update",
-                           "finalize", "pack_bf16"])
+    kb = kernel_totals(L, ["coarse_pack", "coarse_assign", "sort", "coarse_update", "fit_round_bf16", "assign_bf16",
+                           "update", "finalize", "pack_bf16"])
     mipq.adc_search(q, idx, w.nprobe, w.topk)
     torch.cuda.synchronize()
     ka = kernel_totals(L, ["adc", "adc_scan"])

@@ -499,7 +499,8 @@ enum mipq_kernel {
   MIPQ_K_CROSS = 16,        /* optimized PQ: cross matrix X^T Y_hat */
   MIPQ_K_POLAR = 17,        /* optimized PQ: orthogonal factor by Jacobi */
   MIPQ_K_ADC_SCAN = 18,     /* ADC search: the list scans alone (also inside MIPQ_K_ADC) */
-  MIPQ_KERNEL_COUNT = 19
+  MIPQ_K_FIT_ROUND_BF16 = 19, /* fit round: matrix-core assignment fused with the float64 sums */
+  MIPQ_KERNEL_COUNT = 20
 };
 int mipq_profile_enable(int on);
 int mipq_profile_collect(int kernel, int64_t* launches, double* total_ms);

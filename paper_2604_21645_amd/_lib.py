@@ -68,7 +68,7 @@ SIGNATURES = {
 KERNELS = {"assign_fp32": 0, "assign_bf16": 1, "update": 2, "finalize": 3, "pack_bf16": 4, "decode": 5,
            "backward": 6, "coarse_pack": 7, "coarse_assign": 8, "sort": 9, "coarse_update": 10, "adc": 11,
            "assign_bf16_batched": 12, "assign_fp8": 13, "pack_fp8": 14, "rotate": 15, "cross": 16,
-           "polar": 17, "adc_scan": 18}
+           "polar": 17, "adc_scan": 18, "fit_round_bf16": 19}
 
 
 class MipqProblem(ctypes.Structure):

@@ -101,10 +101,17 @@ struct FitWs {
   double* j_sub = nullptr;
   uint32_t* bad = nullptr;
   uint32_t* flag = nullptr;
-  int nch = 1;
+  float* cmax2 = nullptr;   // the second norm-bound buffer of the fused rounds
+  int nch = 1;   // chunk partials the workspace holds (two-pass or fused rounds)
   EncodeWs enc;
   size_t bytes = 0;
 };
+
+// BF16 fits without the objective and without MIPQ_DETERMINISTIC run each
+// Lloyd round as one fused launch (assignment + sums) and the finalize
+bool fused_rounds(int64_t n_train, int m, int ks, int ds, int precision, bool objective, bool det) {
+  return precision == MIPQ_BF16 && !objective && !det && fit_round_geometry(n_train, m, ks, ds).rpw > 0;
+}
 
 FitWs carve_fit(void* ws, int64_t n_train, bool gather, int d, int m, int ks, int iters,
                 int precision, bool need_codes, bool need_c64) {
@@ -112,6 +119,10 @@ FitWs carve_fit(void* ws, int64_t n_train, bool gather, int d, int m, int ks, in
   FitWs f;
   const int ds = d / m;
   f.nch = update_chunks(n_train, m);
+  if (precision == MIPQ_BF16) {   // room for the fused rounds' partials too
+    const int fch = fit_round_geometry(n_train, m, ks, ds).nch;
+    if (fch > f.nch) f.nch = fch;
+  }
   if (gather) f.xs = c.take<float>((size_t)n_train * d);
   if (need_codes) f.codes = c.take<uint8_t>((size_t)n_train * m);
   if (need_c64) f.c64 = c.take<double>((size_t)m * ks * ds);
@@ -121,6 +132,7 @@ FitWs carve_fit(void* ws, int64_t n_train, bool gather, int d, int m, int ks, in
   f.j_sub = c.take<double>((size_t)(iters > 0 ? iters : 1) * m);
   f.bad = c.take<uint32_t>(4);
   f.flag = c.take<uint32_t>(4);
+  if (precision == MIPQ_BF16) f.cmax2 = c.take<float>((size_t)m);
   const size_t off = c.bytes();
   EncodeWs e = carve_encode(ws ? static_cast<char*>(ws) + off : nullptr, m, ks, ds, precision);
   f.enc = e;
@@ -228,12 +240,28 @@ int mipq_pq_fit(const float* x, int64_t n, const int64_t* train_rows, int64_t n_
   const bool bf = precision == MIPQ_BF16;
   const bool det = (flags & MIPQ_DETERMINISTIC) != 0;
   if (iters > 0 && (rc = pack_any(c32, m, ks, ds, precision, f.enc, s))) return rc;
+  if (fused_rounds(nt, m, ks, ds, precision, objective != nullptr, det)) {
+    const int nch = fit_round_geometry(nt, m, ks, ds).nch;
+    for (int it = 0; it < iters; ++it) {
+      // the round reads one norm-bound buffer and clears the other, which its
+      // finalize raises for the next round
+      float* cm_read = (it & 1) ? f.cmax2 : f.enc.cmax;
+      float* cm_next = (it & 1) ? f.enc.cmax : f.cmax2;
+      if ((rc = launch_fit_round_bf16(train, nt, d, m, ks, f.enc.aop, cm_read, f.enc.mu, c32, codes,
+                                      rescored ? rescored + it : nullptr, f.part_s, f.part_cnt, cm_next, s)))
+        return rc;
+      if ((rc = launch_finalize(m, ks, ds, nch, f.part_s, f.part_cnt, nullptr, c32, c64, nullptr, f.enc.aop, cm_next,
+                                f.enc.mu, s)))
+        return rc;
+    }
+    return MIPQ_OK;
+  }
   for (int it = 0; it < iters; ++it) {
     if ((rc = assign_any(train, nt, d, m, ks, c32, precision, codes, f.enc, rescored ? rescored + it : nullptr,
                          s)))
       return rc;
     // the update also packs the next round's operands (BF16)
-    if ((rc = launch_update(train, nt, d, m, ks, codes, c32, c64, f.nch, f.part_s, f.part_cnt, f.part_j,
+    if ((rc = launch_update(train, nt, d, m, ks, codes, c32, c64, update_chunks(nt, m), f.part_s, f.part_cnt, f.part_j,
                             f.j_sub + (size_t)it * m, bf ? f.enc.aop : nullptr, f.enc.cmax, f.enc.mu,
                             objective != nullptr, det, s)))
       return rc;

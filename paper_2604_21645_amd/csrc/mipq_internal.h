@@ -107,6 +107,11 @@ int update_chunks(int64_t n, int m);
 int launch_update(const float* x, int64_t n, int d, int m, int ks, const uint8_t* codes, float* c32,
                   double* c64, int nch, double* part_s, uint32_t* part_cnt, double* part_j,
                   double* j_sub, void* aop, float* cmax, float* mu, bool objective, bool det, hipStream_t s);
+// the finalize of launch_update alone (centroid means, objective when j_sub,
+// next operands when aop) over nch chunk partials
+int launch_finalize(int m, int ks, int ds, int nch, const double* part_s, const uint32_t* part_cnt,
+                    const double* part_j, float* c32, double* c64, double* j_sub, void* aop, float* cmax,
+                    const float* mu, hipStream_t s);
 int launch_objective(const double* j_sub, int iters, int m, double* objective, hipStream_t s);
 int launch_copy_f64(const double* src, double* dst, size_t count, hipStream_t s);
 int launch_decode_sse(const uint8_t* codes, int64_t n, int d, int m, int ks, const float* c32,
@@ -222,5 +227,19 @@ int launch_assign_bf16(const float* x, int64_t n, int d, int m, int ks, const vo
                        const float* cmax, const float* mu, const float* c32, uint8_t* codes,
                        int64_t* rescored, float* min_dist, double* sse_part, hipStream_t s);
 int assign_bf16_sse_parts(int64_t n, int m);
+
+// Fused Lloyd round (BF16 assignment + float64 sums by code, one launch):
+// nch row chunks of (12 or 4 waves) * rpw rows (rpw = 0: the shape does not
+// fit the LDS).
+// Writes the chunks' partials in launch_update's layout (finalize with
+// launch_finalize); cmax is read, cmax_zero (another m floats) zeroed for the
+// finalize to raise.
+struct FitGeom {
+  int nch = 0, rpw = 0;
+};
+FitGeom fit_round_geometry(int64_t n, int m, int ks, int ds);
+int launch_fit_round_bf16(const float* x, int64_t n, int d, int m, int ks, const void* aop, const float* cmax,
+                          const float* mu, const float* c32, uint8_t* codes, int64_t* rescored, double* part_s,
+                          uint32_t* part_cnt, float* cmax_zero, hipStream_t s);
 
 }  // namespace mipq

@@ -40,6 +40,15 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kThreads = 256;   // 4 waves, one subspace each
 
+// LDS of k_fit_round_bf16: sums [ks][ds + 1] float64 and counts [ks], then
+// (16-byte aligned) the waves' stashes and 16-bit pending lists
+__host__ __device__ constexpr size_t fit_lds_stash_offset(int ks, int ds) {
+  return ((size_t)ks * (ds + 1) * sizeof(double) + (size_t)ks * sizeof(uint32_t) + 15) & ~size_t(15);
+}
+// its waves per block: three per SIMD for one 8-dimension block (about 168
+// VGPRs), one per SIMD for two (up to 256 VGPRs)
+__host__ __device__ constexpr int fit_waves(int nb) { return nb == 1 ? 12 : 4; }
+
 // ---- row side --------------------------------------------------------------
 __device__ __forceinline__ bf16x8 to_bf16x8(const float* v) {
   bf16x8 r;
@@ -277,7 +286,28 @@ __device__ __forceinline__ bool not_separated(float f1, float f2, float beta, fl
   return !(f2 - f1 > thr);
 }
 
-// The exact rule for the np pending rows (absolute row indices) of subspace
+// Fused Lloyd accumulation (k_fit_round_bf16): the block's float64 sums of
+// its rows by code, S [ks][ds + 1] (one padding double per centroid spreads a
+// centroid's dimensions over the LDS banks) and counts cnt [ks], and the
+// wave's stash of its lanes' row slices, [DW / 4][64] float4 (lane-minor, so
+// that a wave's 16-byte stores and loads are contiguous).
+struct AccLds {
+  double* S = nullptr;
+  uint32_t* cnt = nullptr;
+  float4* stash = nullptr;
+};
+
+// one row's slice v (dimensions t < ds) added to centroid code's sums
+template <int DW>
+__device__ __forceinline__ void acc_row(const AccLds& a, int code, const float (&v)[DW], int ds) {
+  double* sc = a.S + code * (ds + 1);
+#pragma unroll
+  for (int t = 0; t < DW; ++t)
+    if (t < ds) atomicAdd(sc + t, (double)v[t]);
+  atomicAdd(a.cnt + code, 1u);
+}
+
+// The exact rule for the np pending rows (rows base + pend[i]) of subspace
 // sub by the whole wave, one row after another; overwrites their codes.  Lane
 // i holds centroids i, i+64, i+128, i+192 (ks <= 256) in registers for all the
 // rows, and the next row's slice is loaded while the current one is decided:
@@ -288,17 +318,17 @@ __device__ __forceinline__ bool not_separated(float f1, float f2, float beta, fl
 // the centroids read for each row (exact_code_wave), the same arithmetic.
 // OUT (REG only): also the exact distance of the winner (min_dist, optional)
 // and the float64 squared error of the row's subspace block, added to *sse
-// by lane 0.
-template <int DW, bool REG, bool OUT = false>
-__device__ __forceinline__ void redecide(const uint32_t* pend, int np, const float* __restrict__ x, int d, int m,
-                                         int ks, int ds, int sub, const float* __restrict__ cbsub,
+// by lane 0.  ACC (REG only): lane 0 adds the row to the block's sums.
+template <int DW, bool REG, bool OUT = false, bool ACC = false, class P = uint32_t>
+__device__ __forceinline__ void redecide(const P* pend, int64_t base, int np, const float* __restrict__ x, int d,
+                                         int m, int ks, int ds, int sub, const float* __restrict__ cbsub,
                                          uint8_t* __restrict__ codes, int lane, float* __restrict__ min_dist = nullptr,
-                                         double* sse = nullptr) {
-  static_assert(REG || !OUT, "the fused outputs need the register form");
+                                         double* sse = nullptr, const AccLds& acc = AccLds()) {
+  static_assert(REG || (!OUT && !ACC), "the fused outputs need the register form");
   if (np == 0) return;   // wave-uniform
   if (!REG) {
     for (int i = 0; i < np; ++i) {
-      const int64_t prow = pend[i];
+      const int64_t prow = base + pend[i];
       const int ec = exact_code_wave<DW>(x + prow * d + (int64_t)sub * ds, cbsub, ds, ks, lane);
       if (lane == 0) codes[prow * m + sub] = (uint8_t)ec;
     }
@@ -325,13 +355,13 @@ __device__ __forceinline__ void redecide(const uint32_t* pend, int np, const flo
     }
   };
   float xn[DW];
-  load_x(pend[0], xn);
+  load_x(base + pend[0], xn);
   for (int i = 0; i < np; ++i) {
-    const int64_t prow = pend[i];
+    const int64_t prow = base + pend[i];
     float xo[DW];
 #pragma unroll
     for (int t = 0; t < DW; ++t) xo[t] = xn[t];
-    if (i + 1 < np) load_x(pend[i + 1], xn);   // next row in flight
+    if (i + 1 < np) load_x(base + pend[i + 1], xn);   // next row in flight
     float best = INFINITY;
     int bk = 0x7FFFFFFF;
 #pragma unroll
@@ -361,6 +391,7 @@ __device__ __forceinline__ void redecide(const uint32_t* pend, int np, const flo
     const int code = bk < ks ? bk : 0;
     if (lane == 0) {
       codes[prow * m + sub] = (uint8_t)code;
+      if (ACC) acc_row<DW>(acc, code, xo, ds);
       if (OUT) {
         if (min_dist) min_dist[prow * m + sub] = best;
         const float* c = cbsub + (int64_t)code * ds;
@@ -394,7 +425,7 @@ __device__ __forceinline__ uint32_t assign_rows(const float* __restrict__ x, int
   load_rows<DW, FULL>(xnext, x, rb, re, d, sub, ds, lane);
   for (int64_t r0 = rb; r0 < re; r0 += 32) {
     if (MIDFLUSH && np > flush_at) {
-      redecide<DW, REG>(pend, np, x, d, m, ks, ds, sub, cbsub, codes, lane);
+      redecide<DW, REG>(pend, 0, np, x, d, m, ks, ds, sub, cbsub, codes, lane);
       nres += (uint32_t)np;
       np = 0;
     }
@@ -416,7 +447,7 @@ __device__ __forceinline__ uint32_t assign_rows(const float* __restrict__ x, int
       np += __popcll(mask);
     }
   }
-  redecide<DW, REG>(pend, np, x, d, m, ks, ds, sub, cbsub, codes, lane);
+  redecide<DW, REG>(pend, 0, np, x, d, m, ks, ds, sub, cbsub, codes, lane);
   return nres + (uint32_t)np;
 }
 
@@ -543,15 +574,17 @@ __device__ __forceinline__ void load_own_row(float (&xv)[DW], const float* __res
 // brings the two halves of a row to the row's own lane, so the merge, the
 // separation test, the code store and (OUT) the distance of the chosen
 // centroid and its float64 squared error run once per row.  Ambiguous rows
-// are queued in the wave's LDS list `pend` (room for re - rb entries) and
-// re-decided by the whole wave after the loop.  Returns the number of
-// re-decided rows; OUT adds the squared errors to *sse (lane-local sums).
-template <int NB, int NT, bool FULL, bool OUT, bool REG>
+// are queued in the wave's LDS list `pend` as offsets from rb (room for
+// re - rb <= 65536 entries) and re-decided by the whole wave after the loop.  Returns the number of
+// re-decided rows; OUT adds the squared errors to *sse (lane-local sums); ACC
+// adds every row, once its code is final, to the block's sums (AccLds).
+template <int NB, int NT, bool FULL, bool OUT, bool REG, bool ACC = false>
 __device__ __forceinline__ int assign_rows64(const SubOps<NB, NT>& o, const Band& bd, const float* __restrict__ x,
                                              int d, int ds, int m, int ks, int sub, int64_t rb, int64_t re,
                                              const float* __restrict__ cbsub, uint8_t* __restrict__ codes,
-                                             uint32_t* pend, int lane, float* __restrict__ min_dist,
-                                             double* sse) {
+                                             uint16_t* pend, int lane, float* __restrict__ min_dist,
+                                             double* sse, const AccLds& acc = AccLds()) {
+  static_assert(!(ACC && OUT), "one fused output at a time");
   constexpr int DW = NB * 8;
   constexpr int NMF = bf16_nmfma(NB);
   int np = 0;
@@ -564,6 +597,10 @@ __device__ __forceinline__ int assign_rows64(const SubOps<NB, NT>& o, const Band
     if (r0 + 64 < re) load_own_row<DW, FULL>(xnext, x, r0 + 64, re, d, sub, ds, lane);   // next step in flight
     const int64_t row = r0 + lane;
     const bool valid = row < re;
+    if (ACC) {   // the slice waits in LDS until the row's code is known
+#pragma unroll
+      for (int e = 0; e < DW; e += 4) acc.stash[(e >> 2) * 64 + lane] = make_float4(xv[e], xv[e + 1], xv[e + 2], xv[e + 3]);
+    }
     RowParts<NB> rp;
     row_parts<NB>(xv, o.muv, rp);
     bf16x8 BA[NMF], BB[NMF];
@@ -595,8 +632,20 @@ __device__ __forceinline__ int assign_rows64(const SubOps<NB, NT>& o, const Band
     const bool push = valid && amb;
     const uint64_t mask = __ballot(push);
     if (mask) {
-      if (push) pend[np + __popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)row;
+      if (push) pend[np + __popcll(mask & ((1ull << lane) - 1ull))] = (uint16_t)(row - rb);
       np += __popcll(mask);
+    }
+    if (ACC && valid && !amb) {
+      float v[DW];
+#pragma unroll
+      for (int e = 0; e < DW; e += 4) {
+        const float4 q = acc.stash[(e >> 2) * 64 + lane];
+        v[e] = q.x;
+        v[e + 1] = q.y;
+        v[e + 2] = q.z;
+        v[e + 3] = q.w;
+      }
+      acc_row<DW>(acc, code, v, ds);
     }
     if (OUT && valid && !amb) {   // the chosen centroid's distance and squared error
       // the row again (from cache): keeping it live through the matrix-core
@@ -632,7 +681,7 @@ __device__ __forceinline__ int assign_rows64(const SubOps<NB, NT>& o, const Band
       *sse += sq;
     }
   }
-  redecide<DW, REG, OUT>(pend, np, x, d, m, ks, ds, sub, cbsub, codes, lane, min_dist, sse);
+  redecide<DW, REG, OUT, ACC>(pend, rb, np, x, d, m, ks, ds, sub, cbsub, codes, lane, min_dist, sse, acc);
   return np;
 }
 
@@ -658,10 +707,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NB == 
     SubOps<NB, NT> o;
     load_sub_ops<NB, NT>(o, aop, cmax, mu, sub, lane);
     // LDS: rpb list entries per wave, so the list cannot overflow
-    extern __shared__ uint32_t pend_all[];
+    extern __shared__ uint16_t pend16[];
     const Band bd{e_cross, e_norm, g_exact};
     const int np = assign_rows64<NB, NT, FULL, OUT, true>(o, bd, x, d, ds, m, ks, sub, rbeg, rend,
-                                                          c32 + (int64_t)sub * ks * ds, codes, pend_all + w * rpb,
+                                                          c32 + (int64_t)sub * ks * ds, codes, pend16 + w * rpb,
                                                           lane, min_dist, &sse);
     if (rescored && lane == 0 && np) atomicAdd(rescored, (unsigned long long)np);
   }
@@ -670,6 +719,72 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NB == 
     for (int off = 32; off > 0; off >>= 1) sse += __shfl_xor(sse, off, 64);
     if (lane == 0) sse_part[blockIdx.x * 4 + w] = sse;
   }
+}
+
+// One Lloyd round of one problem in one launch: the assignment of
+// k_assign_bf16 and the float64 sums of the rows by code (the accumulation
+// of paper Section 2.1's centroid update), which k_accumulate would otherwise
+// take in a second pass over the rows.  Block = (row chunk c, subspace j),
+// W = fit_waves(NB) waves: all the waves one CU holds at the kernel's
+// register use, so one block per CU shares one set of sums and the chunks
+// (hence the finalize's partials) are few.  xcd_map with one subspace per
+// group puts the m blocks of a chunk on one XCD and its L2.  Wave w takes
+// rows [(c W + w) rpw, + rpw) of subspace j (its pending list has room for
+// all of them; a loop over pieces would keep the operands live across the
+// re-decisions and spill).
+// The block's sums and counts are formed in
+// LDS (lane atomics, as k_accumulate) and stored as chunk c's partials in
+// k_accumulate's layout, for the finalize.  Block 0 also zeroes cmax_zero,
+// the per-subspace norm bound that the finalize raises for the next round
+// (a buffer other than the cmax this launch reads).
+template <int NB, int NT, bool FULL>
+__global__ __launch_bounds__(fit_waves(NB) * 64) __attribute__((amdgpu_waves_per_eu(NB == 1 ? 3 : 1, 8))) void
+k_fit_round_bf16(const float* __restrict__ x, int64_t n, int d, int m, int ks, int ds, const bf16x8* __restrict__ aop,
+                 const float* __restrict__ cmax, const float* __restrict__ mu, const float* __restrict__ c32,
+                 uint8_t* __restrict__ codes, unsigned long long* __restrict__ rescored, int nch, int rpw,
+                 float e_cross, float e_norm, float g_exact, double* __restrict__ part_s,
+                 uint32_t* __restrict__ part_cnt, float* __restrict__ cmax_zero) {
+  constexpr int DW = NB * 8;
+  constexpr int W = fit_waves(NB);
+  extern __shared__ __align__(16) unsigned char fit_lds[];
+  if (cmax_zero && blockIdx.x == 0)
+    for (int j = threadIdx.x; j < m; j += blockDim.x) cmax_zero[j] = 0.0f;
+  const XcdMap bm = xcd_map(blockIdx.x, m);
+  const int chunk = bm.rowblk, sub = bm.group;
+  if (chunk >= nch) return;   // grid padding (block-uniform)
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // LDS: sums, counts, the waves' stashes and pending lists
+  const int stride = ds + 1;
+  AccLds acc;
+  acc.S = reinterpret_cast<double*>(fit_lds);
+  acc.cnt = reinterpret_cast<uint32_t*>(acc.S + (size_t)ks * stride);
+  float4* stash0 = reinterpret_cast<float4*>(fit_lds + fit_lds_stash_offset(ks, ds));
+  acc.stash = stash0 + w * (DW / 4) * 64;
+  uint16_t* pend = reinterpret_cast<uint16_t*>(stash0 + W * (DW / 4) * 64) + w * rpw;
+  for (int i = threadIdx.x; i < ks * stride; i += blockDim.x) acc.S[i] = 0.0;
+  for (int i = threadIdx.x; i < ks; i += blockDim.x) acc.cnt[i] = 0u;
+  __syncthreads();
+  const int64_t rb = ((int64_t)chunk * W + w) * rpw;
+  const int64_t re = min(n, rb + rpw);
+  uint32_t nres = 0;
+  if (rb < re) {
+    SubOps<NB, NT> o;
+    load_sub_ops<NB, NT>(o, aop, cmax, mu, sub, lane);
+    const Band bd{e_cross, e_norm, g_exact};
+    nres = (uint32_t)assign_rows64<NB, NT, FULL, false, true, true>(o, bd, x, d, ds, m, ks, sub, rb, re,
+                                                                    c32 + (int64_t)sub * ks * ds, codes, pend,
+                                                                    lane, nullptr, nullptr, acc);
+  }
+  if (rescored && lane == 0 && nres) atomicAdd(rescored, (unsigned long long)nres);
+  __syncthreads();
+  const int per = ks * ds;
+  const size_t base = (size_t)chunk * m + sub;
+  for (int i = threadIdx.x; i < per; i += blockDim.x) {
+    const int k = i / ds;
+    part_s[base * per + i] = acc.S[k * stride + (i - k * ds)];
+  }
+  for (int i = threadIdx.x; i < ks; i += blockDim.x) part_cnt[base * ks + i] = acc.cnt[i];
 }
 
 // Many problems in one persistent launch.  The work is the list of units
@@ -690,7 +805,7 @@ __global__ __launch_bounds__(kThreads) void k_assign_bf16_batched(
     const float* __restrict__ mu, unsigned long long* __restrict__ rescored, float e_cross, float e_norm,
     float g_exact) {
   constexpr int PC = kBatchPend;
-  __shared__ uint32_t pend_all[(kThreads / 64) * PC];
+  __shared__ uint16_t pend_all[(kThreads / 64) * PC];
   const int G = gridDim.x;   // a multiple of 8
   const int lb = (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3);
   // block-uniform work indices, kept in scalar registers (the divisions
@@ -1088,7 +1203,7 @@ int launch_assign_bf16(const float* x, int64_t n, int d, int m, int ks, const vo
                     (((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(c32)) & 15) == 0);
   const bool out = min_dist || sse_part;
   unsigned long long* resc = reinterpret_cast<unsigned long long*>(rescored);
-  const size_t pend_bytes = (size_t)(kThreads / 64) * g.rpb * sizeof(uint32_t);
+  const size_t pend_bytes = (size_t)(kThreads / 64) * g.rpb * sizeof(uint16_t);
 #define LAUNCH1(NB, NT, FULL, OUT)                                                                  \
   k_assign_bf16<NB, NT, FULL, OUT><<<g.blocks, kThreads, pend_bytes, s>>>(                          \
       x, n, d, m, ks, ds, (const bf16x8*)aop, cmax, mu, c32, codes, resc, g.groups, g.rpb, bd.e_cross, \
@@ -1125,6 +1240,84 @@ int launch_assign_bf16(const float* x, int64_t n, int d, int m, int ks, const vo
 }
 
 int assign_bf16_sse_parts(int64_t n, int m) { return 4 * bf16_geometry(n, m).blocks; }
+
+namespace {
+constexpr int kFitBlocks = 256;     // one block per CU on 256 CUs
+constexpr int kFitRowsMax = 2048;   // rows per wave at most (as k_assign_bf16's blocks)
+constexpr size_t kFitLdsMax = 65536;
+
+size_t fit_lds_bytes(int ks, int ds, int rpw) {
+  const int nb = ds <= 8 ? 1 : 2;
+  const int w = fit_waves(nb);
+  return fit_lds_stash_offset(ks, ds) + (size_t)w * 64 * nb * 8 * sizeof(float) + (size_t)w * rpw * sizeof(uint16_t);
+}
+}  // namespace
+
+// Chunks of the fused round: kFitBlocks / m of them (one round of blocks), or
+// more when the rows per wave would pass kFitRowsMax or the pending lists'
+// LDS.  rpw = 0: the sums and stashes leave no LDS for a list.  Depends on
+// the shape only, so that workspace sizes need no device.
+FitGeom fit_round_geometry(int64_t n, int m, int ks, int ds) {
+  FitGeom g;
+  if (n < 1 || m < 1) return g;
+  const int w = fit_waves(ds <= 8 ? 1 : 2);
+  int cap = kFitBlocks / m;
+  if (cap < 1) cap = 1;
+  int64_t rpw = ceil_div(n, (int64_t)w * cap);
+  const size_t fixed = fit_lds_bytes(ks, ds, 0);
+  int64_t room = fixed < kFitLdsMax ? (int64_t)((kFitLdsMax - fixed) / (w * sizeof(uint16_t))) : 0;
+  if (room > kFitRowsMax) room = kFitRowsMax;
+  if (room < 64) return g;
+  if (rpw > room) rpw = room;
+  g.rpw = (int)rpw;
+  g.nch = (int)ceil_div(n, (int64_t)w * rpw);
+  return g;
+}
+
+int launch_fit_round_bf16(const float* x, int64_t n, int d, int m, int ks, const void* aop, const float* cmax,
+                          const float* mu, const float* c32, uint8_t* codes, int64_t* rescored, double* part_s,
+                          uint32_t* part_cnt, float* cmax_zero, hipStream_t s) {
+  const int ds = d / m;
+  const int nb = (ds + 7) / 8;
+  const int nt = tiles_for(ks);
+  const FitGeom g = fit_round_geometry(n, m, ks, ds);
+  if (g.rpw == 0) return fail(MIPQ_EUNSUPPORTED, "fused round: sums of ks=%d, ds=%d leave no LDS", ks, ds);
+  const Band bd = band_for(ds);
+  const bool full = (ds == nb * 8) && (d % 4 == 0) &&
+                    (((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(c32)) & 15) == 0);
+  unsigned long long* resc = reinterpret_cast<unsigned long long*>(rescored);
+  const size_t lds = fit_lds_bytes(ks, ds, g.rpw);
+  const unsigned grid = (unsigned)(ceil_div(g.nch, 8) * 8 * m);
+  ProfScope ps(MIPQ_K_FIT_ROUND_BF16, s);
+#define LAUNCH1(NB, NT, FULL)                                                                             \
+  k_fit_round_bf16<NB, NT, FULL><<<grid, fit_waves(NB) * 64, lds, s>>>(                                    \
+      x, n, d, m, ks, ds, (const bf16x8*)aop, cmax, mu, c32, codes, resc, g.nch, g.rpw, bd.e_cross,          \
+      bd.e_norm, bd.g_exact, part_s, part_cnt, cmax_zero)
+#define LAUNCH(NB, NT)                 \
+  do {                                 \
+    if (full) LAUNCH1(NB, NT, true);   \
+    else LAUNCH1(NB, NT, false);       \
+  } while (0)
+  if (nb == 1) {
+    switch (nt) {
+      case 1: LAUNCH(1, 1); break;
+      case 2: LAUNCH(1, 2); break;
+      case 4: LAUNCH(1, 4); break;
+      default: LAUNCH(1, 8); break;
+    }
+  } else {
+    switch (nt) {
+      case 1: LAUNCH(2, 1); break;
+      case 2: LAUNCH(2, 2); break;
+      case 4: LAUNCH(2, 4); break;
+      default: LAUNCH(2, 8); break;
+    }
+  }
+#undef LAUNCH
+#undef LAUNCH1
+  MIPQ_LAUNCHED("k_fit_round_bf16");
+  return MIPQ_OK;
+}
 
 namespace {
 template <int NB, int NT, bool FULL, bool REG>

@@ -514,7 +514,7 @@ __device__ __forceinline__ void finalize_sub(int sub, int m, int ks, int ds, int
     const int k = e / ds;
     double sacc = 0.0;
     uint64_t cacc = 0;
-    constexpr int V = 8;   // partials in flight, added in chunk order
+    constexpr int V = 16;   // partials in flight, added in chunk order
     for (int c0 = 0; c0 < nch; c0 += V) {
       double sv[V];
       uint32_t cv[V];
@@ -583,7 +583,7 @@ __device__ __forceinline__ void finalize_tile(int t, int sub, int m, int ks, int
     const int k = e / ds;
     double sacc = 0.0;
     uint64_t cacc = 0;
-    constexpr int V = 8;   // partials in flight, added in chunk order
+    constexpr int V = 16;   // partials in flight, added in chunk order
     for (int c0 = 0; c0 < nch; c0 += V) {
       double sv[V];
       uint32_t cv[V];
@@ -797,6 +797,12 @@ int launch_update(const float* x, int64_t n, int d, int m, int ks, const uint8_t
           x, n, d, m, ks, ds, codes, c32, rpc, nch, part_s, part_cnt, part_j, nullptr, nullptr, cz);
     MIPQ_LAUNCHED("k_accumulate");
   }
+  return launch_finalize(m, ks, ds, nch, part_s, part_cnt, part_j, c32, c64, j_sub, aop, cmax, mu, s);
+}
+
+int launch_finalize(int m, int ks, int ds, int nch, const double* part_s, const uint32_t* part_cnt,
+                    const double* part_j, float* c32, double* c64, double* j_sub, void* aop, float* cmax,
+                    const float* mu, hipStream_t s) {
   const int nt = tiles_for(ks);
   ProfScope ps(MIPQ_K_FINALIZE, s);
   if (!aop) {

@@ -353,3 +353,57 @@ def test_fit_encode_step_replays_from_a_graph(prec):
         torch.cuda.synchronize()
         for a, b in zip(out, ref):
             assert torch.equal(a, b), rep
+
+
+FUSED_CASES = [
+    dict(kind="integer", n=20000, d=128, m=16, ks=256, iters=4),   # ds=8, 8 tiles
+    dict(kind="float", n=4000, d=128, m=8, ks=64, iters=6),        # ds=16: two 8-dim blocks
+    dict(kind="float", n=3001, d=48, m=16, ks=100, iters=5),       # ds=3, partial tile, padded rows
+    dict(kind="integer", n=130, d=64, m=8, ks=32, iters=3),        # fewer rows than one step per wave
+]
+
+
+@pytest.mark.parametrize("case", FUSED_CASES, ids=lambda c: "%(kind)s_n%(n)d_d%(d)d_m%(m)d_ks%(ks)d" % c)
+def test_fused_rounds_match_the_oracle(case):
+    """BF16 fits without the objective run each Lloyd round as one launch
+    (assignment fused with the float64 sums) plus the finalize.  Labels and
+    codebooks equal the oracle's float32-decision Lloyd; on integer rows the
+    codebooks equal the two-pass rounds' (objective on) bit for bit."""
+    x = _data(case["kind"], case["n"], case["d"], seed=case["n"] + 11)
+    m, ks, iters = case["m"], case["ks"], case["iters"]
+    rng = np.random.default_rng(case["n"])
+    init = np.stack([rng.choice(case["n"], size=ks, replace=False) for _ in range(m)])
+    print("fused rounds", case, flush=True)
+    fused = mipq.pq_fit(_t(x), m, ks, iters, init_rows=_t(init), precision="bf16", codebook64=True,
+                        objective=False, rescored=True)
+    ref = pq.lloyd(x, init, m, iters, decide="fp32")
+    np.testing.assert_array_equal(fused["labels"].cpu().numpy().astype(np.int64), ref["codes"])
+    np.testing.assert_allclose(fused["codebook64"].cpu().numpy(), ref["codebook"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_array_equal(fused["codebook"].cpu().numpy(), ref["codebook"].astype(np.float32))
+    two = mipq.pq_fit(_t(x), m, ks, iters, init_rows=_t(init), precision="bf16", codebook64=True,
+                      objective=True, rescored=True)
+    assert torch.equal(fused["rescored"], two["rescored"])
+    assert torch.equal(fused["labels"], two["labels"])
+    if case["kind"] == "integer":
+        assert torch.equal(fused["codebook64"], two["codebook64"])
+
+
+@pytest.mark.parametrize("n_train,iters", [(100_000, 25), (1_000_000, 2)])
+def test_fused_rounds_at_full_size_equal_the_two_pass_rounds(n_train, iters):
+    """The 1M x 128 integer workload (M=16, Ks=256): a 100k-row sample for 25
+    rounds (one block round) and all 1M rows for 2 rounds (rows per wave at
+    their cap, 123 chunks): fused and two-pass rounds give the same codebook
+    bit for bit (integer rows: exact float64 sums in any order), the same
+    labels and the same re-decided pairs per round."""
+    w = wl.integer_pq(n_train=n_train)
+    xt = _t(w.x)
+    init = wl.init_rows_per_subspace(w.meta["seed"], n_train, w.m, w.ks)
+    tr = _t(w.train_rows) if n_train < w.x.shape[0] else None
+    print("fused full size", n_train, iters, flush=True)
+    kw = dict(init_rows=_t(init), train_rows=tr, precision="bf16", codebook64=True, rescored=True)
+    fused = mipq.pq_fit(xt, w.m, w.ks, iters, objective=False, **kw)
+    two = mipq.pq_fit(xt, w.m, w.ks, iters, objective=True, **kw)
+    assert torch.equal(fused["codebook64"], two["codebook64"])
+    assert torch.equal(fused["labels"], two["labels"])
+    assert torch.equal(fused["rescored"], two["rescored"])
+    print("re-decided per round", fused["rescored"].cpu().numpy().tolist(), flush=True)
