@@ -133,7 +133,7 @@ struct Bf16Geom {
   int rowblks = 0;   // row blocks covering n
   int blocks = 0;    // launched blocks (XCD-padded)
 };
-Bf16Geom bf16_geometry(int64_t n, int m);
+Bf16Geom bf16_geometry(int64_t n, int m, int max_tiles);   // max_tiles: 32-row tiles per block at most
 size_t bf16_operand_count(int m, int ks, int ds);   // number of 16-byte operand slots
 // reconstruction-loss backward with fixed codes: grad_x (optional), grad_c
 // (optional), per-subspace loss; g = *gscale (NULL: 1)

@@ -39,6 +39,9 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kThreads = 256;   // 4 waves, one subspace each
+// row tiles per block of the assignment with fused outputs: its LDS (lists,
+// the block's centroids, stashes) then fits three blocks per CU
+constexpr int kOutTiles = 32;
 
 // LDS of k_fit_round_bf16: sums [ks][ds + 1] float64 and counts [ks], then
 // (16-byte aligned) the waves' stashes and 16-bit pending lists
@@ -71,6 +74,12 @@ __device__ __forceinline__ float min16(const f32x16& a) {
   const float m3 = min3f(a[9], a[10], a[11]);
   const float m4 = min3f(a[12], a[13], a[14]);
   return fminf(min3f(m0, m1, m2), min3f(m3, m4, a[15]));
+}
+
+// set bits of a wave-wide mask below the calling lane (v_mbcnt: no lane mask
+// kept in registers)
+__device__ __forceinline__ int lanes_below(uint64_t mask) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
 // signed-integer key: the float's bits with its low bits replaced by an index;
@@ -443,7 +452,7 @@ __device__ __forceinline__ uint32_t assign_rows(const float* __restrict__ x, int
     const bool push = (half == 0) && valid && amb;
     const uint64_t mask = __ballot(push);
     if (mask) {
-      if (push) pend[np + __popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)row;
+      if (push) pend[np + lanes_below(mask)] = (uint32_t)row;
       np += __popcll(mask);
     }
   }
@@ -597,7 +606,7 @@ __device__ __forceinline__ int assign_rows64(const SubOps<NB, NT>& o, const Band
     if (r0 + 64 < re) load_own_row<DW, FULL>(xnext, x, r0 + 64, re, d, sub, ds, lane);   // next step in flight
     const int64_t row = r0 + lane;
     const bool valid = row < re;
-    if (ACC) {   // the slice waits in LDS until the row's code is known
+    if (ACC || (OUT && NB == 1)) {   // the slice waits in LDS until the row's code is known
 #pragma unroll
       for (int e = 0; e < DW; e += 4) acc.stash[(e >> 2) * 64 + lane] = make_float4(xv[e], xv[e + 1], xv[e + 2], xv[e + 3]);
     }
@@ -632,7 +641,7 @@ __device__ __forceinline__ int assign_rows64(const SubOps<NB, NT>& o, const Band
     const bool push = valid && amb;
     const uint64_t mask = __ballot(push);
     if (mask) {
-      if (push) pend[np + __popcll(mask & ((1ull << lane) - 1ull))] = (uint16_t)(row - rb);
+      if (push) pend[np + lanes_below(mask)] = (uint16_t)(row - rb);
       np += __popcll(mask);
     }
     if (ACC && valid && !amb) {
@@ -648,9 +657,21 @@ __device__ __forceinline__ int assign_rows64(const SubOps<NB, NT>& o, const Band
       acc_row<DW>(acc, code, v, ds);
     }
     if (OUT && valid && !amb) {   // the chosen centroid's distance and squared error
-      // the row again (from cache): keeping it live through the matrix-core
-      // phase would cost registers and occupancy
-      load_own_row<DW, FULL>(xv, x, r0, re, d, sub, ds, lane);
+      // the row again, from the stash (one 8-dimension block) or from cache:
+      // keeping it live through the matrix-core phase would cost registers
+      // and occupancy
+      if (NB == 1) {
+#pragma unroll
+        for (int e = 0; e < DW; e += 4) {
+          const float4 q = acc.stash[(e >> 2) * 64 + lane];
+          xv[e] = q.x;
+          xv[e + 1] = q.y;
+          xv[e + 2] = q.z;
+          xv[e + 3] = q.w;
+        }
+      } else {
+        load_own_row<DW, FULL>(xv, x, r0, re, d, sub, ds, lane);
+      }
       const float* c = cbsub + (int64_t)code * ds;
       float cv[DW];
       if (FULL) {
@@ -702,16 +723,37 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NB == 
   const int sub = bm.group * 4 + w;
   const int64_t rbeg = (int64_t)bm.rowblk * rpb;
   double sse = 0.0;
+  // LDS: rpb list entries per wave, so the list cannot overflow; with OUT
+  // and one 8-dimension block (STAGE) also the float32 centroids of the
+  // block's four subspaces (the chosen centroid of every row is read from
+  // there) and the waves' stashes of their rows' slices (kept until the
+  // rows' codes are known)
+  constexpr bool STAGE = OUT && NB == 1;
+  extern __shared__ __align__(16) uint16_t pend16[];
+  float* cb_lds = reinterpret_cast<float*>(pend16 + (kThreads / 64) * rpb);
+  const int s0 = bm.group * 4;
+  if (STAGE) {
+    const int nsub = min(4, m - s0);
+    const int cnt = nsub * ks * ds;
+    const float* src = c32 + (int64_t)s0 * ks * ds;
+    if ((cnt & 3) == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+      for (int i = threadIdx.x; i < cnt / 4; i += blockDim.x)
+        reinterpret_cast<float4*>(cb_lds)[i] = reinterpret_cast<const float4*>(src)[i];
+    } else {
+      for (int i = threadIdx.x; i < cnt; i += blockDim.x) cb_lds[i] = src[i];
+    }
+    __syncthreads();
+  }
   if (sub < m && rbeg < n) {
     const int64_t rend = min(n, rbeg + rpb);
     SubOps<NB, NT> o;
     load_sub_ops<NB, NT>(o, aop, cmax, mu, sub, lane);
-    // LDS: rpb list entries per wave, so the list cannot overflow
-    extern __shared__ uint16_t pend16[];
     const Band bd{e_cross, e_norm, g_exact};
-    const int np = assign_rows64<NB, NT, FULL, OUT, true>(o, bd, x, d, ds, m, ks, sub, rbeg, rend,
-                                                          c32 + (int64_t)sub * ks * ds, codes, pend16 + w * rpb,
-                                                          lane, min_dist, &sse);
+    AccLds st;
+    if (STAGE) st.stash = reinterpret_cast<float4*>(cb_lds + 4 * ks * ds) + w * 2 * 64;
+    const float* cbsub = STAGE ? cb_lds + w * ks * ds : c32 + (int64_t)sub * ks * ds;
+    const int np = assign_rows64<NB, NT, FULL, OUT, true>(o, bd, x, d, ds, m, ks, sub, rbeg, rend, cbsub, codes,
+                                                          pend16 + w * rpb, lane, min_dist, &sse, st);
     if (rescored && lane == 0 && np) atomicAdd(rescored, (unsigned long long)np);
   }
   if (OUT && sse_part) {
@@ -1149,7 +1191,7 @@ size_t bf16_operand_count(int m, int ks, int ds) {
   return (size_t)m * tiles_for(ks) * bf16_nmfma(nb) * 64;
 }
 
-Bf16Geom bf16_geometry(int64_t n, int m) {
+Bf16Geom bf16_geometry(int64_t n, int m, int max_tiles) {
   Bf16Geom g;
   g.groups = ceil_div(m, 4);
   // one round of resident blocks (three per CU: the assignment kernels' register
@@ -1165,7 +1207,7 @@ Bf16Geom bf16_geometry(int64_t n, int m) {
   const int64_t row_tiles = (n + 31) / 32;
   int64_t tpb = (row_tiles * g.groups + resident - 1) / resident;
   if (tpb < 1) tpb = 1;
-  if (tpb > 64) tpb = 64;
+  if (tpb > max_tiles) tpb = max_tiles;
   tpb = (tpb + 1) & ~int64_t(1);   // whole 64-row steps
   g.rpb = int(tpb * 32);
   g.rowblks = n > 0 ? ceil_div(n, g.rpb) : 0;
@@ -1195,15 +1237,17 @@ int launch_assign_bf16(const float* x, int64_t n, int d, int m, int ks, const vo
   const int ds = d / m;
   const int nb = (ds + 7) / 8;
   const int nt = tiles_for(ks);
-  const Bf16Geom g = bf16_geometry(n, m);
+  const bool out = min_dist || sse_part;
+  const Bf16Geom g = bf16_geometry(n, m, out ? kOutTiles : 64);
   if (g.blocks == 0) return MIPQ_OK;
   const Band bd = band_for(ds);
   ProfScope ps(MIPQ_K_ASSIGN_BF16, s);
   const bool full = (ds == nb * 8) && (d % 4 == 0) &&
                     (((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(c32)) & 15) == 0);
-  const bool out = min_dist || sse_part;
   unsigned long long* resc = reinterpret_cast<unsigned long long*>(rescored);
-  const size_t pend_bytes = (size_t)(kThreads / 64) * g.rpb * sizeof(uint16_t);
+  const size_t pend_bytes = (size_t)(kThreads / 64) * g.rpb * sizeof(uint16_t) +
+                            (out && nb == 1 ? (size_t)4 * ks * ds * sizeof(float) + (size_t)(kThreads / 64) * 64 * 8 * sizeof(float)
+                                            : 0);
 #define LAUNCH1(NB, NT, FULL, OUT)                                                                  \
   k_assign_bf16<NB, NT, FULL, OUT><<<g.blocks, kThreads, pend_bytes, s>>>(                          \
       x, n, d, m, ks, ds, (const bf16x8*)aop, cmax, mu, c32, codes, resc, g.groups, g.rpb, bd.e_cross, \
@@ -1239,7 +1283,7 @@ int launch_assign_bf16(const float* x, int64_t n, int d, int m, int ks, const vo
   return MIPQ_OK;
 }
 
-int assign_bf16_sse_parts(int64_t n, int m) { return 4 * bf16_geometry(n, m).blocks; }
+int assign_bf16_sse_parts(int64_t n, int m) { return 4 * bf16_geometry(n, m, kOutTiles).blocks; }
 
 namespace {
 constexpr int kFitBlocks = 256;     // one block per CU on 256 CUs
@@ -1390,7 +1434,7 @@ int launch_assign_fp8(const float* x, int64_t n, int d, int m, int ks, const voi
   const int ds = d / m;
   const int nb = (ds + 7) / 8;
   const int nt = tiles_for(ks);
-  const Bf16Geom g = bf16_geometry(n, m);
+  const Bf16Geom g = bf16_geometry(n, m, 64);
   if (g.blocks == 0) return MIPQ_OK;
   const float g_exact = band_for(ds).g_exact;
   ProfScope ps(MIPQ_K_ASSIGN_FP8, s);
