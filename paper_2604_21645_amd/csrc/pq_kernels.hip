@@ -347,8 +347,20 @@ __global__ __launch_bounds__(kThreads) void k_decode_sse_batched(const BatchProb
 // then a fixed pairwise tree over the threads; out = {SSE, RMSE}.
 __device__ __forceinline__ void sse_final_body(const double* __restrict__ partials, int nblk, int64_t n, int d,
                                                double* out, double* red) {
+  // thread t adds partials t, t + blockDim, ... in that order, with eight
+  // loads in flight (one at a time would chain their latencies)
   double s = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += partials[i];
+  constexpr int V = 8;
+  const int step = blockDim.x;
+  int i = threadIdx.x;
+  for (; i + (V - 1) * step < nblk; i += V * step) {
+    double v[V];
+#pragma unroll
+    for (int u = 0; u < V; ++u) v[u] = partials[i + u * step];
+#pragma unroll
+    for (int u = 0; u < V; ++u) s += v[u];
+  }
+  for (; i < nblk; i += step) s += partials[i];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = blockDim.x / 2; w > 0; w >>= 1) {

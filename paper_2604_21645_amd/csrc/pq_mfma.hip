@@ -1298,9 +1298,10 @@ size_t fit_lds_bytes(int ks, int ds, int rpw) {
 }  // namespace
 
 // Chunks of the fused round: kFitBlocks / m of them (one round of blocks), or
-// more when the rows per wave would pass kFitRowsMax or the pending lists'
-// LDS.  rpw = 0: the sums and stashes leave no LDS for a list.  Depends on
-// the shape only, so that workspace sizes need no device.
+// a whole number of such rounds when the rows per wave would pass
+// kFitRowsMax or the pending lists' LDS.  rpw = 0: the sums and stashes leave
+// no LDS for a list.  Depends on the shape only, so that workspace sizes need
+// no device.
 FitGeom fit_round_geometry(int64_t n, int m, int ks, int ds) {
   FitGeom g;
   if (n < 1 || m < 1) return g;
@@ -1312,7 +1313,10 @@ FitGeom fit_round_geometry(int64_t n, int m, int ks, int ds) {
   int64_t room = fixed < kFitLdsMax ? (int64_t)((kFitLdsMax - fixed) / (w * sizeof(uint16_t))) : 0;
   if (room > kFitRowsMax) room = kFitRowsMax;
   if (room < 64) return g;
-  if (rpw > room) rpw = room;
+  if (rpw > room) {   // several rounds of blocks: as many equal full rounds as needed
+    const int64_t rounds = ceil_div(ceil_div(n, (int64_t)w * room), cap);
+    rpw = ceil_div(n, (int64_t)w * cap * rounds);
+  }
   g.rpw = (int)rpw;
   g.nch = (int)ceil_div(n, (int64_t)w * rpw);
   return g;
