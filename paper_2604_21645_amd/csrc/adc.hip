@@ -501,7 +501,7 @@ __global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
 // writes its list's best topk keys (~0 padded) and lowers the query's shared
 // bound qthr to its topk-th key: a row above the topk-th key of any single
 // list cannot be in the query's top topk.
-template <int DS, bool V16>
+template <int DS, bool V16, bool WORK>
 __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, int d, const float* __restrict__ cc,
                                                  const float* __restrict__ pq, int m, int ks,
                                                  const int64_t* __restrict__ offsets, const int32_t* __restrict__ ids,
@@ -536,12 +536,14 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
   }
   const float* qr = q + (int64_t)qi * d;
   const int64_t a = offsets[l], b = offsets[l + 1];
-  // executed work (when `work` is given): table entries built, rows given the
-  // partial sum over the first kScanPre subspaces, rows summed over all
-  // subspaces (a row that passes the partial sum is summed again in full)
+  // executed work (WORK, when `work` is given): table entries built, rows
+  // given the partial sum over the first kScanPre subspaces, rows summed over
+  // all subspaces (a row that passes the partial sum is summed again in
+  // full).  A separate instantiation: the counters cost registers and
+  // occupancy that the plain search keeps.
   uint32_t w_lut = 0, w_part = 0, w_full = 0;
   auto report = [&](bool entered) {
-    if (!work) return;
+    if (!WORK || !work) return;
     unsigned long long v[3] = {w_lut, w_part, w_full};
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -576,7 +578,7 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
     for (int j = j0; j < j1; ++j)
       for (int k = threadIdx.x; k < ks; k += blockDim.x) {
         lut[j * ks + k] = sqdist_fixed<DS>(rq + j * DS, pq + ((int64_t)j * ks + k) * DS);
-        ++w_lut;
+        if (WORK) ++w_lut;
       }
   };
   // M = 16 rows: the table of the first kLutPre subspaces now, the rest once
@@ -688,7 +690,7 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
           bool keep = false;
           if (p < b) {
             keep = __float_as_uint(sum16(cv[r], std::integral_constant<int, kScanPre>{})) <= tb;
-            ++w_part;
+            if (WORK) ++w_part;
           }
           const unsigned long long bal = __ballot(keep);
           if (keep) wql[nq_w + __popcll(bal & __lanemask_lt())] = (uint16_t)(r * kT + threadIdx.x);
@@ -708,7 +710,7 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
         for (int i = lane; i < nq_w; i += 64) {
           const int64_t p = p0 + wql[i];
           insert(sum16(c4[p], std::integral_constant<int, 16>{}), ids[p], tl);
-          ++w_full;
+          if (WORK) ++w_full;
         }
       } else {   // no bound yet: every row is summed in full
         if (!full) {
@@ -721,7 +723,7 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
           const int64_t p = p0 + r * kT + threadIdx.x;
           if (p < b) {
             insert(sum16(cv[r], std::integral_constant<int, 16>{}), ids[p], tl);
-            ++w_full;
+            if (WORK) ++w_full;
           }
         }
       }
@@ -759,7 +761,7 @@ __global__ __launch_bounds__(kT) void k_adc_scan(const float* __restrict__ q, in
           for (int j = 1; j < m; ++j) s = s + lut[j * ks + cr[j]];
         }
         insert(s, ids[p], tl);
-        ++w_full;
+        if (WORK) ++w_full;
       }
       step_end(ext);
     }
@@ -906,14 +908,18 @@ int launch_adc(const float* q, int nq, int d, const float* cc, int kc, const voi
   const size_t shm = adc_scan_smem(d, m, ks, topk);
   const bool v16 = (m % 16 == 0) && ((reinterpret_cast<uintptr_t>(codes) & 15) == 0);
   const unsigned sblocks = (unsigned)(((npairs + 8 * kXcdRun - 1) / (8 * kXcdRun)) * (8 * kXcdRun));
-#define SC(DSV)                                                                                              \
-  do {                                                                                                       \
-    if (v16)                                                                                                 \
-      k_adc_scan<DSV, true><<<sblocks, kT, shm, s>>>(q, d, cc, pq, m, ks, offsets, ids, codes, probes, nq,   \
-                                                     nprobe, topk, cap, qthr, pair_out, ow.order, (int)npairs, work); \
-    else                                                                                                     \
-      k_adc_scan<DSV, false><<<sblocks, kT, shm, s>>>(q, d, cc, pq, m, ks, offsets, ids, codes, probes, nq,  \
-                                                      nprobe, topk, cap, qthr, pair_out, ow.order, (int)npairs, work); \
+#define SC1(DSV, V, W)                                                                                  \
+  k_adc_scan<DSV, V, W><<<sblocks, kT, shm, s>>>(q, d, cc, pq, m, ks, offsets, ids, codes, probes, nq, nprobe, \
+                                                 topk, cap, qthr, pair_out, ow.order, (int)npairs, work)
+#define SC(DSV)                               \
+  do {                                        \
+    if (work) {                               \
+      if (v16) SC1(DSV, true, true);          \
+      else SC1(DSV, false, true);             \
+    } else {                                  \
+      if (v16) SC1(DSV, true, false);         \
+      else SC1(DSV, false, false);            \
+    }                                         \
   } while (0)
   {
     ProfScope pscan(MIPQ_K_ADC_SCAN, s);
@@ -927,6 +933,7 @@ int launch_adc(const float* q, int nq, int d, const float* cc, int kc, const voi
     }
   }
 #undef SC
+#undef SC1
   MIPQ_LAUNCHED("k_adc_scan");
   k_adc_merge<<<nq, kT, (size_t)mcap * sizeof(uint64_t), s>>>(pair_out, nprobe, topk, mcap, qthr, out_ids,
                                                                out_dist);
