@@ -76,6 +76,38 @@ __device__ __forceinline__ float min16(const f32x16& a) {
   return fminf(min3f(m0, m1, m2), min3f(m3, m4, a[15]));
 }
 
+// Lexicographic (value, index) minimum over the 64 lanes, returned on every
+// lane: the smallest value (float minimum), then the smallest index among the
+// lanes holding it.  Within 16-lane rows by DPP (quad swaps, half-row and row
+// mirrors), across rows by v_permlane16_swap and v_permlane32_swap: no LDS
+// round trips (ds_bpermute) on the re-decision's critical path.
+__device__ __forceinline__ float dpp_minf(float v) {
+  auto step = [](float a, int b) { return fminf(a, __int_as_float(b)); };
+  v = step(v, __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0xB1, 0xF, 0xF, false));  // quad [1,0,3,2]
+  v = step(v, __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x4E, 0xF, 0xF, false));  // quad [2,3,0,1]
+  v = step(v, __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x141, 0xF, 0xF, false)); // half-row mirror
+  v = step(v, __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x140, 0xF, 0xF, false)); // row mirror
+  const auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  v = fminf(__uint_as_float(r16[0]), __uint_as_float(r16[1]));
+  const auto r32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return fminf(__uint_as_float(r32[0]), __uint_as_float(r32[1]));
+}
+__device__ __forceinline__ int dpp_mini(int v) {
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));
+  const auto r16 = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+  v = min((int)r16[0], (int)r16[1]);
+  const auto r32 = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+  return min((int)r32[0], (int)r32[1]);
+}
+__device__ __forceinline__ void wave_argmin(float& best, int& bk) {
+  const float m = dpp_minf(best);
+  bk = dpp_mini(best == m ? bk : 0x7FFFFFFF);
+  best = m;
+}
+
 // set bits of a wave-wide mask below the calling lane (v_mbcnt: no lane mask
 // kept in registers)
 __device__ __forceinline__ int lanes_below(uint64_t mask) {
@@ -146,15 +178,7 @@ __device__ __forceinline__ int exact_code_wave(const float* __restrict__ xr, con
       bk = k;
     }
   }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const float ob = __shfl_xor(best, off, 64);
-    const int ok = __shfl_xor(bk, off, 64);
-    if (ob < best || (ob == best && ok < bk)) {
-      best = ob;
-      bk = ok;
-    }
-  }
+  wave_argmin(best, bk);
   return bk < ks ? bk : 0;
 }
 
@@ -345,14 +369,27 @@ __device__ __forceinline__ void redecide(const P* pend, int64_t base, int np, co
   }
   constexpr int KPL = kMaxKs / 64;
   float cv[KPL][DW];
+  // whole 16-byte centroid rows when ds fills the register block
+  const bool vec = ds == DW && (reinterpret_cast<uintptr_t>(cbsub) & 15) == 0;
 #pragma unroll
   for (int j = 0; j < KPL; ++j) {
     const int k = lane + 64 * j;
     const float* c = cbsub + (int64_t)(k < ks ? k : 0) * ds;
+    if (vec) {
 #pragma unroll
-    for (int t = 0; t < DW; ++t) {
-      const float v = c[t < ds ? t : ds - 1];
-      cv[j][t] = (k < ks && t < ds) ? v : 0.0f;
+      for (int t = 0; t < DW; t += 4) {
+        const float4 v = *reinterpret_cast<const float4*>(c + t);
+        cv[j][t] = k < ks ? v.x : 0.0f;
+        cv[j][t + 1] = k < ks ? v.y : 0.0f;
+        cv[j][t + 2] = k < ks ? v.z : 0.0f;
+        cv[j][t + 3] = k < ks ? v.w : 0.0f;
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < DW; ++t) {
+        const float v = c[t < ds ? t : ds - 1];
+        cv[j][t] = (k < ks && t < ds) ? v : 0.0f;
+      }
     }
   }
   auto load_x = [&](int64_t row, float (&xo)[DW]) {
@@ -388,15 +425,7 @@ __device__ __forceinline__ void redecide(const P* pend, int64_t base, int np, co
         bk = k;
       }
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const float ob = __shfl_xor(best, off, 64);
-      const int ok = __shfl_xor(bk, off, 64);
-      if (ob < best || (ob == best && ok < bk)) {
-        best = ob;
-        bk = ok;
-      }
-    }
+    wave_argmin(best, bk);
     const int code = bk < ks ? bk : 0;
     if (lane == 0) {
       codes[prow * m + sub] = (uint8_t)code;
