@@ -168,6 +168,19 @@ def oracle_fit_encode(train, init, x_enc, m: int, iters: int, threads: int):
     return np.concatenate(cbs, 0), t1 - t0, t2 - t1
 
 
+def oracle_row_chunks(k: int, threads: int, fn):
+    """Run fn(a, b) on `threads` contiguous row ranges of [0, k) at once (the
+    oracle's row-wise work is independent per row; NumPy releases the GIL
+    inside the array operations).  Returns (results in row order, seconds)."""
+    from concurrent.futures import ThreadPoolExecutor
+    bounds = [(k * i // threads, k * (i + 1) // threads) for i in range(threads)]
+    with ThreadPoolExecutor(threads) as ex:
+        t0 = time.perf_counter()
+        out = list(ex.map(lambda ab: fn(*ab), bounds))
+        t1 = time.perf_counter()
+    return out, t1 - t0
+
+
 def cpu_baseline(w, frac: float):
     """The oracle, as it stands, on a bounded sample of the same workload:
     fit on frac * n_train training rows (same rounds), encode frac * N rows,
@@ -525,19 +538,16 @@ def bench_batched(args) -> dict:
 
     base = None
     if not args.no_cpu_baseline:
-        from oracle import pq
         n_s = min(args.batched_cpu_rows, sizes[0])
         xs0 = w.problems[0].x[:n_s]
         init = wl.init_rows_per_subspace(w.meta["seed"], n_s, w.m, w.ks, key=99)
-        log("oracle leg: fit + encode of %d rows of problem 0" % n_s)
-        t1 = time.perf_counter()
-        fit = pq.lloyd(xs0, init, w.m, w.iters, decide="fp32")
-        pq.encode(xs0, fit["codebook"], decide="fp32")
-        t2 = time.perf_counter()
-        base = {"value": n_s / (t2 - t1), "unit": "vectors/s", "cores": 1, "host_cpus": os.cpu_count(),
-                "kind": "oracle",
-                "sample": "%d rows of problem 0 fitted %d rounds and encoded (float32 decisions, numpy single "
-                          "thread, %.1fs)" % (n_s, w.iters, t2 - t1)}
+        threads = oracle_threads(w.m)
+        log("oracle leg: fit + encode of %d rows of problem 0 (%d threads)" % (n_s, threads))
+        _, tf, te = oracle_fit_encode(xs0, init, xs0, w.m, w.iters, threads)
+        base = {"value": n_s / (tf + te), "unit": "vectors/s", "cores": threads, "host_cpus": os.cpu_count(),
+                "cpu_model": cpu_model(), "kind": "oracle",
+                "sample": "%d rows of problem 0 fitted %d rounds and encoded (float32 decisions, one subspace per "
+                          "thread; fit %.1fs, encode %.1fs)" % (n_s, w.iters, tf, te)}
     b.close()
     rec = base_record("PQ fit+encode vectors/s, 64 uneven problems batched (BF16-MFMA)", total / (ms * 1e-3),
                       "vectors/s", args.steps, args.warmup, ms, "bf16",
@@ -649,13 +659,15 @@ def bench_ivf(args) -> dict:
         cs = idx["codes_sorted"].cpu().numpy()
         cbi = np.empty_like(cs)
         cbi[idn] = cs
-        t1 = time.perf_counter()
-        ri, rd = ivf.adc_search(w.queries[:k], cc, pqc, off, idn, cbi, w.nprobe, w.topk, decide="kernel")
-        t2 = time.perf_counter()
-        base = {"value": k / (t2 - t1), "unit": "queries/s", "cores": 1, "host_cpus": os.cpu_count(),
-                "kind": "oracle",
+        threads = max(1, min(CPU_SHARE, os.cpu_count() or 1, k))
+        parts, tq = oracle_row_chunks(k, threads, lambda a, b: ivf.adc_search(
+            w.queries[a:b], cc, pqc, off, idn, cbi, w.nprobe, w.topk, decide="kernel"))
+        ri = np.concatenate([p_[0] for p_ in parts])
+        rd = np.concatenate([p_[1] for p_ in parts])
+        base = {"value": k / tq, "unit": "queries/s", "cores": threads, "host_cpus": os.cpu_count(),
+                "cpu_model": cpu_model(), "kind": "oracle",
                 "sample": "ADC top-%d of the first %d queries (nprobe %d) on the GPU-built index, float32 table "
-                          "arithmetic, numpy single thread, %.1fs" % (w.topk, k, w.nprobe, t2 - t1)}
+                          "arithmetic, queries split over %d threads, %.1fs" % (w.topk, k, w.nprobe, threads, tq)}
         gi = ids.cpu().numpy()[:k].astype(np.int64)
         parity = {"queries": k, "top100_identical_pct": 100.0 * float(np.all(gi == ri, axis=1).mean()),
                   "distances_identical": bool(np.array_equal(dist.cpu().numpy()[:k], rd.astype(np.float32)))}
@@ -748,14 +760,17 @@ def bench_diff(args) -> dict:
         k = min(args.diff_cpu_rows, n)
         log("oracle leg: encode + loss + gradients of %d rows" % k)
         cbn = cb.detach().cpu().numpy().astype(np.float64)
-        t1 = time.perf_counter()
-        codes_o, _ = pq.encode(w.x[:k], cbn, decide="fp32")
-        grad.grads(w.x[:k], codes_o, cbn)
-        t2 = time.perf_counter()
-        base = {"value": k / (t2 - t1), "unit": "vectors/s", "cores": 1, "host_cpus": os.cpu_count(),
-                "kind": "oracle",
-                "sample": "encode (float32 decisions) + float64 loss and gradients of the first %d rows, numpy "
-                          "single thread, %.1fs" % (k, t2 - t1)}
+        threads = max(1, min(CPU_SHARE, os.cpu_count() or 1))
+
+        def enc_grad(a, b):
+            codes_o, _ = pq.encode(w.x[a:b], cbn, decide="fp32")
+            return grad.grads(w.x[a:b], codes_o, cbn)
+
+        _, tg = oracle_row_chunks(k, threads, enc_grad)
+        base = {"value": k / tg, "unit": "vectors/s", "cores": threads, "host_cpus": os.cpu_count(),
+                "cpu_model": cpu_model(), "kind": "oracle",
+                "sample": "encode (float32 decisions) + float64 loss and gradients of the first %d rows, rows split "
+                          "over %d threads, %.1fs" % (k, threads, tg)}
     rec = base_record("Reconstruction-loss forward+backward vectors/s (BF16 encode, fixed codes)", n / (ms * 1e-3),
                       "vectors/s", args.steps, args.warmup, ms, "bf16",
                       {"workload": "diff_codebooks: 2M x 256 rows (8,192-component mixture), M=32, Ks=256 codebooks "
@@ -841,19 +856,16 @@ def bench_soil(args) -> dict:
 
     base = None
     if not args.no_cpu_baseline:
-        from oracle import pq
         k = min(args.soil_cpu_rows, w.chunk_rows)
         xs0 = w.x[:k]
         init = wl.init_rows_per_subspace(w.meta["seed"], k, w.m, w.ks, key=98)
-        log("oracle leg: fit + encode of %d rows of chunk 0" % k)
-        t1 = time.perf_counter()
-        fit = pq.lloyd(xs0, init, w.m, w.iters, decide="fp32")
-        pq.encode(xs0, fit["codebook"], decide="fp32")
-        t2 = time.perf_counter()
-        base = {"value": k / (t2 - t1), "unit": "vectors/s", "cores": 1, "host_cpus": os.cpu_count(),
-                "kind": "oracle",
-                "sample": "%d rows of chunk 0 fitted %d rounds and encoded (float32 decisions, numpy single "
-                          "thread, %.1fs)" % (k, w.iters, t2 - t1)}
+        threads = oracle_threads(w.m)
+        log("oracle leg: fit + encode of %d rows of chunk 0 (%d threads)" % (k, threads))
+        _, tf, te = oracle_fit_encode(xs0, init, xs0, w.m, w.iters, threads)
+        base = {"value": k / (tf + te), "unit": "vectors/s", "cores": threads, "host_cpus": os.cpu_count(),
+                "cpu_model": cpu_model(), "kind": "oracle",
+                "sample": "%d rows of chunk 0 fitted %d rounds and encoded (float32 decisions, one subspace per "
+                          "thread; fit %.1fs, encode %.1fs)" % (k, w.iters, tf, te)}
     info = b.info()
     b.close()
     rec = base_record("Two-level chunked PQ fit+encode vectors/s (the paper's pipeline, BF16-MFMA)",
@@ -946,17 +958,16 @@ def bench_opq(args) -> dict:
 
     base = None
     if not args.no_cpu_baseline:
-        k = 100000
+        k = min(n, 1000000)
         log("oracle leg: rotate + encode of %d rows" % k)
         cbn = cb.cpu().numpy().astype(np.float64)
-        t1 = time.perf_counter()
-        yk = opq_oracle.rotate(w.x[:k], rn)
-        pq.encode(yk, cbn, decide="fp32")
-        t2 = time.perf_counter()
-        base = {"value": k / (t2 - t1), "unit": "vectors/s", "cores": 1, "host_cpus": os.cpu_count(),
-                "kind": "oracle",
-                "sample": "rotation (float64, t ascending) + encode (float32 decisions) of the first %d rows, numpy "
-                          "single thread, %.1fs" % (k, t2 - t1)}
+        threads = max(1, min(CPU_SHARE, os.cpu_count() or 1))
+        _, tr_s = oracle_row_chunks(k, threads, lambda a, b: pq.encode(opq_oracle.rotate(w.x[a:b], rn), cbn,
+                                                                       decide="fp32"))
+        base = {"value": k / tr_s, "unit": "vectors/s", "cores": threads, "host_cpus": os.cpu_count(),
+                "cpu_model": cpu_model(), "kind": "oracle",
+                "sample": "rotation (float64, t ascending) + encode (float32 decisions) of the first %d rows, rows "
+                          "split over %d threads, %.1fs" % (k, threads, tr_s)}
     rec = base_record("Optimized-PQ encode vectors/s (float64 rotation + BF16-MFMA encode + RMSE)", n / (ms * 1e-3),
                       "vectors/s", args.steps, args.warmup, ms, "f64 rotation, bf16 encode",
                       {"workload": "opq: 1M x 128 integer-valued rows; R and codebooks (M=16, Ks=256) fitted once on "
@@ -1046,11 +1057,11 @@ def main() -> int:
     ap.add_argument("--fp8-steps", type=int, default=3)
     ap.add_argument("--build-steps", type=int, default=2, help="ivf_adc: timed index builds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-frac", type=float, default=0.08)
-    ap.add_argument("--batched-cpu-rows", type=int, default=8000)
-    ap.add_argument("--ivf-cpu-queries", type=int, default=100)
-    ap.add_argument("--diff-cpu-rows", type=int, default=20000)
-    ap.add_argument("--soil-cpu-rows", type=int, default=8000)
+    ap.add_argument("--cpu-frac", type=float, default=0.4)
+    ap.add_argument("--batched-cpu-rows", type=int, default=64000)
+    ap.add_argument("--ivf-cpu-queries", type=int, default=500)
+    ap.add_argument("--diff-cpu-rows", type=int, default=400000)
+    ap.add_argument("--soil-cpu-rows", type=int, default=16750)
     ap.add_argument("--oracle-sample", type=int, default=20000)
     ap.add_argument("--deterministic", action="store_true", help="fixed-order centroid sums in the fit")
     ap.add_argument("--copy-calibration", action="store_true",
