@@ -38,6 +38,9 @@ EXTRA = {
     "pq_mfma.hip": ["-fno-honor-nans", "-mno-amdgpu-ieee", "-mllvm", "-amdgpu-mfma-vgpr-form"],
     # matrix-core results straight to VGPRs
     "ivf.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    # minima of matrix-core estimates without NaN quieting; IEEE mode stays on
+    # (with it off the device library's work-item queries become calls)
+    "coarse.hip": ["-fno-honor-nans", "-mllvm", "-amdgpu-mfma-vgpr-form"],
     "adc.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
     # the minimum chains of the issue-rate probe become v_min3_f32
     "peaks.hip": ["-fno-honor-nans", "-mno-amdgpu-ieee", "-mllvm", "-amdgpu-mfma-vgpr-form"],

@@ -1,13 +1,7 @@
 // Inverted file (paper Section 2.2: row ids stored per bucket for fast lookup;
 // buckets here are coarse k-means lists, see the inverted-index reading).
 //
-//  * coarse assignment: label = argmin_l ||x - c_l||^2 over Kc full-dimension
-//    centroids.  Exact rule: float32 differences, squared and summed in
-//    float64 in ascending dimension order, lowest index on ties.  Ranked on
-//    matrix cores (32x32x16 bfloat16 MFMA, centred operands, squared norms
-//    folded into the contraction), each lane keeps its best two candidates;
-//    rows whose best two are not separated by the proven error bound are
-//    re-decided by the whole wave with the exact rule;
+//  * coarse assignment: coarse.hip;
 //  * stable counting sort of ids by label (least-significant-digit radix sort,
 //    6-bit digits, ranks from wave ballots), list offsets by binary search;
 //  * coarse Lloyd update from the sorted order: one block per list sums its
@@ -39,448 +33,6 @@ __device__ __forceinline__ bf16x8 to_bf16x8(const float* v) {
     r[e + 1] = q[1];
   }
   return r;
-}
-
-// ---------------------------------------------------------------- centre
-// mu[t] = bfloat16-rounded midpoint of min and max of centroid coordinate t;
-// one block per dimension.  Also clears the norm bound cell.
-__global__ __launch_bounds__(kT) void k_coarse_centre(const float* __restrict__ cc, int kc, int d,
-                                                      float* __restrict__ mu, unsigned int* __restrict__ cmax_bits) {
-  __shared__ float lo_s[kT / 64], hi_s[kT / 64];
-  const int t = blockIdx.x;
-  float lo = INFINITY, hi = -INFINITY;
-  for (int l = threadIdx.x; l < kc; l += blockDim.x) {
-    const float v = cc[(int64_t)l * d + t];
-    lo = fminf(lo, v);
-    hi = fmaxf(hi, v);
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    lo = fminf(lo, __shfl_xor(lo, off, 64));
-    hi = fmaxf(hi, __shfl_xor(hi, off, 64));
-  }
-  if ((threadIdx.x & 63) == 0) {
-    lo_s[threadIdx.x >> 6] = lo;
-    hi_s[threadIdx.x >> 6] = hi;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
-      lo = fminf(lo, lo_s[i]);
-      hi = fmaxf(hi, hi_s[i]);
-    }
-    lo = fminf(lo, lo_s[0]);
-    hi = fmaxf(hi, hi_s[0]);
-    mu[t] = bf16_bits_to_f32(bf16_bits_rne(0.5f * (lo + hi)));
-    if (t == 0) *cmax_bits = 0u;
-  }
-}
-
-// ---------------------------------------------------------------- packing
-// Operand slot ((t*NK + s)*64 + l) = lane l's 8 bfloat16 values of A for tile t
-// (32 centroids), K-step s: s < S: bf16(-2(c - mu)) of dimensions 16s + 8h ..
-// +7 (h = l/32, zero past d); s = S: [c2h, c2m, c2l, 1, 1, 1, 0, 0] for h = 0
-// (||c - mu||^2 in three pieces), zeros for h = 1.  Padded centroids get
-// c2h = +inf.  Also the largest centred norm (float bits, atomic max).
-__global__ __launch_bounds__(kT) void k_coarse_pack(const float* __restrict__ cc, int kc, int d, int S,
-                                                    const float* __restrict__ mu, uint4* __restrict__ aop,
-                                                    unsigned int* __restrict__ cmax_bits) {
-  const int NK = S + 1;
-  const int nt = (kc + 31) / 32;
-  const int total = nt * NK * 64;
-  for (int slot = blockIdx.x * blockDim.x + threadIdx.x; slot < total; slot += gridDim.x * blockDim.x) {
-    const int l = slot & 63;
-    const int s = (slot >> 6) % NK;
-    const int t = slot / (NK * 64);
-    const int i = l & 31, h = l >> 5;
-    const int k = t * 32 + i;
-    const bool real = k < kc;
-    Pack8 out = {};
-    if (s < S) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int dim = 16 * s + 8 * h + e;
-        const float c = (real && dim < d) ? cc[(int64_t)k * d + dim] - mu[dim] : 0.0f;
-        out.v[e] = bf16_bits_rne(-2.0f * c);
-      }
-    } else if (h == 0) {
-      if (real) {
-        double cn = 0.0;
-        for (int dim = 0; dim < d; ++dim) {
-          const double c = (double)(cc[(int64_t)k * d + dim] - mu[dim]);
-          cn += c * c;
-        }
-        const uint16_t hb = bf16_bits_rne((float)cn);
-        const double r1 = cn - (double)bf16_bits_to_f32(hb);
-        const uint16_t mb = bf16_bits_rne((float)r1);
-        const double r2 = r1 - (double)bf16_bits_to_f32(mb);
-        out.v[0] = hb;
-        out.v[1] = mb;
-        out.v[2] = bf16_bits_rne((float)r2);
-        const float nrm = (float)(sqrt(cn) * (1.0 + 1e-6));
-        atomicMax(cmax_bits, __float_as_uint(nrm));
-      } else {
-        out.v[0] = 0x7F80u;
-      }
-      out.v[3] = out.v[4] = out.v[5] = kBf16One;
-    }
-    store_pack(aop + slot, out);
-  }
-}
-
-// ---------------------------------------------------------------- exact rule
-// float32 differences, float64 squares and sums in ascending dimension order
-// (rows of 16-float multiples at 16-byte alignment are read 16 floats at a
-// time, the next 16 in flight; the order of the sum is the same)
-__device__ __forceinline__ double coarse_exact_dist(const float* __restrict__ xr, const float* __restrict__ c, int d) {
-  double acc = 0.0;
-  if ((d & 15) == 0 && ((reinterpret_cast<uintptr_t>(xr) | reinterpret_cast<uintptr_t>(c)) & 15) == 0) {
-    const float4* x4 = reinterpret_cast<const float4*>(xr);
-    const float4* c4 = reinterpret_cast<const float4*>(c);
-    const int nch = d >> 4;
-    float4 xc[4], cc4[4], xn[4], cn[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      xc[k] = x4[k];
-      cc4[k] = c4[k];
-    }
-    for (int ch = 0; ch < nch; ++ch) {
-      if (ch + 1 < nch) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          xn[k] = x4[(ch + 1) * 4 + k];
-          cn[k] = c4[(ch + 1) * 4 + k];
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const float xv[4] = {xc[k].x, xc[k].y, xc[k].z, xc[k].w};
-        const float cv[4] = {cc4[k].x, cc4[k].y, cc4[k].z, cc4[k].w};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const double df = (double)(xv[i] - cv[i]);
-          acc = acc + df * df;
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        xc[k] = xn[k];
-        cc4[k] = cn[k];
-      }
-    }
-    return acc;
-  }
-  for (int t = 0; t < d; ++t) {
-    const double df = (double)(xr[t] - c[t]);
-    acc = acc + df * df;
-  }
-  return acc;
-}
-
-// whole wave: lane i scans centroids i, i+64, ...; lexicographic minimum
-__device__ int coarse_exact_wave(const float* __restrict__ xr, const float* __restrict__ cc, int kc, int d,
-                                 int lane) {
-  double best = INFINITY;
-  int bk = 0x7FFFFFFF;
-  for (int k = lane; k < kc; k += 64) {
-    const double dk = coarse_exact_dist(xr, cc + (int64_t)k * d, d);
-    if (dk < best) {
-      best = dk;
-      bk = k;
-    }
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ob = __shfl_xor(best, off, 64);
-    const int ok = __shfl_xor(bk, off, 64);
-    if (ob < best || (ob == best && ok < bk)) {
-      best = ob;
-      bk = ok;
-    }
-  }
-  return bk < kc ? bk : 0;
-}
-
-// One lane per row, plain exact rule (small problems and reference).
-__global__ __launch_bounds__(kT) void k_coarse_assign_exact(const float* __restrict__ x, int64_t n, int d,
-                                                            const float* __restrict__ cc, int kc,
-                                                            int32_t* __restrict__ labels) {
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= n) return;
-  const float* xr = x + row * d;
-  double best = INFINITY;
-  int bk = 0;
-  for (int k = 0; k < kc; ++k) {
-    const double dk = coarse_exact_dist(xr, cc + (int64_t)k * d, d);
-    if (dk < best) {
-      best = dk;
-      bk = k;
-    }
-  }
-  labels[row] = bk;
-}
-
-// ---------------------------------------------------------------- MFMA assign
-// One wave = RG groups of 32 rows; lane l holds row l%32 of each group and the
-// dimensions 16s + 8h .. +7 (h = l/32) of every K-step s.  For each
-// 32-centroid tile the wave loads the tile's S+1 operands once and runs S+1
-// MFMAs per row group; lane l receives 16 distance estimates of its row
-// (centroids 8(r/4) + 4h + r%4 of the tile) and keeps its best two and the
-// best index.
-//
-// A row whose best two estimates are not separated by the proven bound is
-// ambiguous.  The wave then recomputes the estimates of its row groups that
-// hold ambiguous rows, collects every (row, centroid) whose estimate is within
-// the bound of the row's best (the exact winner is always among them) in an
-// LDS list, and decides each such row by the exact rule over its candidates
-// only.  Rows whose candidates do not fit the list are decided by the exact
-// rule over all centroids.
-constexpr int kCandCap = 256;   // candidate pairs per wave
-
-// (registers capped for three waves per SIMD: at d = 128 the two waves the
-// uncapped kernel allowed took 35 ms on 10M rows x Kc = 4096, three 30 ms)
-template <int S, int RG>
-__global__ __launch_bounds__(kT, 3) void k_coarse_assign_mfma(
-    const float* __restrict__ x, int64_t n, int d, int kc, const bf16x8* __restrict__ aop,
-    const float* __restrict__ mu, const unsigned int* __restrict__ cmax_bits, const float* __restrict__ cc,
-    int32_t* __restrict__ labels, unsigned long long* __restrict__ rescored, float e_cross, float e_norm,
-    float g_exact) {
-  constexpr int NK = S + 1;
-  __shared__ uint32_t cand_rk_all[kT / 64][kCandCap];   // (row in wave) << 16 | centroid
-  __shared__ double cand_d_all[kT / 64][kCandCap];
-  __shared__ bf16x8 a_lds[2][NK * 64];
-  const int lane = threadIdx.x & 63;
-  const int h = lane >> 5;
-  const int w = threadIdx.x >> 6;
-  const int64_t r0 = ((int64_t)blockIdx.x * (kT / 64) + w) * (32 * RG);
-  // waves past the last row still stage operands and meet the block's
-  // barriers; their rows read row n - 1 and write nothing
-  uint32_t* cand_rk = cand_rk_all[w];
-  double* cand_d = cand_d_all[w];
-  const float cm = __uint_as_float(*cmax_bits);
-  // every row slice is whole and 16-byte aligned (mu is a workspace buffer)
-  const bool vec = d == 16 * S && (reinterpret_cast<uintptr_t>(x) & 15) == 0 &&
-                   (reinterpret_cast<uintptr_t>(mu) & 15) == 0;
-
-  // row operands (centred), ||x - mu||^2
-  bf16x8 B[RG][NK];
-  float xn[RG];
-#pragma unroll
-  for (int g = 0; g < RG; ++g) {
-    const int64_t row = r0 + 32 * g + (lane & 31);
-    const float* xr = x + (row < n ? row : n - 1) * d;
-    float xn_part = 0.0f;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      float v[8];
-      if (vec) {   // the 8 dimensions 16 s + 8 h .. + 7 as two float4
-        const float4 xa = *reinterpret_cast<const float4*>(xr + 16 * s + 8 * h);
-        const float4 xb = *reinterpret_cast<const float4*>(xr + 16 * s + 8 * h + 4);
-        const float4 ma = *reinterpret_cast<const float4*>(mu + 16 * s + 8 * h);
-        const float4 mb = *reinterpret_cast<const float4*>(mu + 16 * s + 8 * h + 4);
-        const float xs[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
-        const float ms[8] = {ma.x, ma.y, ma.z, ma.w, mb.x, mb.y, mb.z, mb.w};
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          v[e] = xs[e] - ms[e];
-          xn_part = xn_part + v[e] * v[e];
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int dim = 16 * s + 8 * h + e;
-          const float xv = xr[dim < d ? dim : d - 1];
-          v[e] = dim < d ? xv - mu[dim] : 0.0f;
-          xn_part = xn_part + v[e] * v[e];
-        }
-      }
-      B[g][s] = to_bf16x8(v);
-    }
-    const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_int(xn_part), __float_as_int(xn_part), false, false);
-    xn[g] = __int_as_float((int)sw[0]) + __int_as_float((int)sw[1]);
-    bf16x8 nb = {};
-    if (h == 0) {
-      const __bf16 hb = (__bf16)xn[g];
-      const float r1 = xn[g] - (float)hb;
-      const __bf16 mb = (__bf16)r1;
-      nb[0] = nb[1] = nb[2] = (__bf16)1.0f;
-      nb[3] = hb;
-      nb[4] = mb;
-      nb[5] = (__bf16)(r1 - (float)mb);
-    }
-    B[g][S] = nb;
-  }
-
-  float v1[RG], v2[RG];
-  int i1[RG];
-#pragma unroll
-  for (int g = 0; g < RG; ++g) {
-    v1[g] = INFINITY;
-    v2[g] = INFINITY;
-    i1[g] = 0;
-  }
-  const int nt = (kc + 31) / 32;
-  // centroid operands of a tile: staged in LDS once for the block's four
-  // waves (two buffers); the next tile's chunks are loaded into registers
-  // while the current tile is scored, and stored after it
-  constexpr int CH = NK * 64;               // 16-byte operand chunks per tile
-  constexpr int PT = (CH + kT - 1) / kT;    // chunks per thread
-  bf16x8 pre[PT];
-  auto fetch = [&](int t) {
-#pragma unroll
-    for (int i = 0; i < PT; ++i) {
-      const int c = threadIdx.x + i * kT;
-      if (c < CH) pre[i] = aop[(size_t)t * CH + c];
-    }
-  };
-  auto put = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < PT; ++i) {
-      const int c = threadIdx.x + i * kT;
-      if (c < CH) a_lds[buf][c] = pre[i];
-    }
-  };
-  fetch(0);
-  put(0);
-  __syncthreads();
-  for (int t = 0; t < nt; ++t) {
-    const int cur = t & 1;
-    if (t + 1 < nt) fetch(t + 1);
-#pragma unroll
-    for (int g = 0; g < RG; ++g) {
-      f32x16 acc = {};
-#pragma unroll
-      for (int s = 0; s < NK; ++s)
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_lds[cur][s * 64 + lane], B[g][s], acc, 0, 0, 0);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float v = acc[r];
-        const int k = t * 32 + (r >> 2) * 8 + h * 4 + (r & 3);
-        v2[g] = __builtin_amdgcn_fmed3f(v1[g], v2[g], v);   // runner-up of {v1, v2, v}, v1 <= v2
-        const bool lt = v < v1[g];
-        i1[g] = lt ? k : i1[g];
-        v1[g] = lt ? v : v1[g];
-      }
-    }
-    if (t + 1 < nt) put(cur ^ 1);
-    __syncthreads();
-  }
-
-  // merge the two lanes of each row; separation test
-  float f1[RG], beta[RG];
-  bool amb[RG];
-  uint64_t any_amb = 0;
-#pragma unroll
-  for (int g = 0; g < RG; ++g) {
-    const auto a = __builtin_amdgcn_permlane32_swap(__float_as_int(v1[g]), __float_as_int(v1[g]), false, false);
-    const auto b = __builtin_amdgcn_permlane32_swap(__float_as_int(v2[g]), __float_as_int(v2[g]), false, false);
-    const auto c = __builtin_amdgcn_permlane32_swap(i1[g], i1[g], false, false);
-    const float v1l = __int_as_float((int)a[0]), v1h = __int_as_float((int)a[1]);
-    const float v2l = __int_as_float((int)b[0]), v2h = __int_as_float((int)b[1]);
-    const int i1l = (int)c[0], i1h = (int)c[1];
-    const bool hiw = (v1h < v1l) || (v1h == v1l && i1h < i1l);
-    f1[g] = fminf(v1l, v1h);
-    const float f2 = fminf(fmaxf(v1l, v1h), fminf(v2l, v2h));
-    const int code = hiw ? i1h : i1l;
-    beta[g] = e_cross * sqrtf(xn[g]) * 1.0001f * cm + e_norm * (cm * cm + xn[g]);
-    const float gap = f2 - f1[g];
-    const float thr = 2.0f * beta[g] + g_exact * (fabsf(f1[g]) + fabsf(f2) + 2.0f * beta[g] + 2.0f * xn[g] * g_exact);
-    const int64_t row = r0 + 32 * g + (lane & 31);
-    const bool valid = row < n;
-    amb[g] = valid && (!(gap > thr) || code >= kc);
-    if (h == 0 && valid) labels[row] = code;
-    any_amb |= __ballot(h == 0 && amb[g]);
-    if (rescored && lane == 0) {
-      const int c2 = __popcll(__ballot(h == 0 && amb[g]));
-      if (c2) atomicAdd(rescored, (unsigned long long)c2);
-    }
-  }
-  if (!any_amb) return;
-
-  // candidates of the ambiguous rows: est_k - f1 within the bound
-  int nc = 0;
-  bool ovf[RG];
-#pragma unroll
-  for (int g = 0; g < RG; ++g) ovf[g] = false;
-  uint64_t gmask = 0;
-#pragma unroll
-  for (int g = 0; g < RG; ++g)
-    if (__ballot(amb[g])) gmask |= 1ull << g;
-  for (int t = 0; t < nt; ++t) {
-    bf16x8 A[NK];
-#pragma unroll
-    for (int s = 0; s < NK; ++s) A[s] = aop[((size_t)t * NK + s) * 64 + lane];
-#pragma unroll
-    for (int g = 0; g < RG; ++g) {
-      if (!((gmask >> g) & 1)) continue;   // wave-uniform
-      f32x16 acc = {};
-#pragma unroll
-      for (int s = 0; s < NK; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[s], B[g][s], acc, 0, 0, 0);
-      uint32_t mine = 0;   // bit r: candidate in accumulator register r
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float v = acc[r];
-        const int k = t * 32 + (r >> 2) * 8 + h * 4 + (r & 3);
-        const float lim = 2.0f * beta[g] + g_exact * (fabsf(f1[g]) + fabsf(v) + 2.0f * beta[g] +
-                                                      2.0f * xn[g] * g_exact);
-        const bool cand = amb[g] && k < kc && !(v - f1[g] > lim);
-        mine |= cand ? (1u << r) : 0u;
-      }
-      if (!__ballot(mine != 0)) continue;
-      const uint32_t rl = (uint32_t)(32 * g + (lane & 31)) << 16;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const bool cand = (mine >> r) & 1u;
-        const uint64_t m = __ballot(cand);
-        if (!m) continue;
-        if (cand) {
-          const int pos = nc + __popcll(m & ((1ull << lane) - 1ull));
-          const int k = t * 32 + (r >> 2) * 8 + h * 4 + (r & 3);
-          if (pos < kCandCap) cand_rk[pos] = rl | (uint32_t)k;
-          else ovf[g] = true;
-        }
-        nc += __popcll(m);
-      }
-    }
-  }
-  const int ncl = nc < kCandCap ? nc : kCandCap;
-  __builtin_amdgcn_wave_barrier();
-  for (int i = lane; i < ncl; i += 64) {
-    const uint32_t rk = cand_rk[i];
-    const int64_t row = r0 + (rk >> 16);
-    cand_d[i] = coarse_exact_dist(x + row * d, cc + (int64_t)(rk & 0xFFFFu) * d, d);
-  }
-  __builtin_amdgcn_wave_barrier();
-#pragma unroll
-  for (int g = 0; g < RG; ++g) {
-    // a row overflowed when either of its two lanes dropped a candidate
-    const uint64_t ob = __ballot(ovf[g]);
-    const uint32_t rows_full = (uint32_t)(ob | (ob >> 32));
-    const int64_t row = r0 + 32 * g + (lane & 31);
-    if (h == 0 && amb[g] && !((rows_full >> (lane & 31)) & 1u)) {
-      const uint32_t rl = (uint32_t)(32 * g + (lane & 31));
-      double best = INFINITY;
-      int bk = 0x7FFFFFFF;
-      for (int i = 0; i < ncl; ++i) {
-        const uint32_t rk = cand_rk[i];
-        if ((rk >> 16) != rl) continue;
-        const double dv = cand_d[i];
-        const int k = (int)(rk & 0xFFFFu);
-        if (dv < best || (dv == best && k < bk)) {
-          best = dv;
-          bk = k;
-        }
-      }
-      labels[row] = bk;
-    }
-    uint32_t fm = rows_full & (uint32_t)__ballot(h == 0 && amb[g]);
-    while (fm) {   // wave-uniform
-      const int l = __ffs(fm) - 1;
-      fm &= fm - 1;
-      const int ec = coarse_exact_wave(x + (r0 + 32 * g + l) * d, cc, kc, d, lane);
-      if (lane == 0) labels[r0 + 32 * g + l] = ec;
-    }
-  }
 }
 
 // ---------------------------------------------------------------- radix sort
@@ -786,64 +338,6 @@ int grid_cap(int64_t work, int cap) {
 }  // namespace
 
 // ---------------------------------------------------------------- host side
-int coarse_ksteps(int d) { return (d + 15) / 16; }
-
-size_t coarse_operand_count(int kc, int d) { return (size_t)((kc + 31) / 32) * (coarse_ksteps(d) + 1) * 64; }
-
-int launch_coarse_prepare(const float* cc, int kc, int d, float* mu, unsigned int* cmax_bits, void* aop,
-                          hipStream_t s) {
-  ProfScope ps(MIPQ_K_COARSE_PACK, s);
-  k_coarse_centre<<<d, kT, 0, s>>>(cc, kc, d, mu, cmax_bits);
-  MIPQ_LAUNCHED("k_coarse_centre");
-  const int S = coarse_ksteps(d);
-  k_coarse_pack<<<grid_cap((int64_t)coarse_operand_count(kc, d), 4096), kT, 0, s>>>(cc, kc, d, S, mu,
-                                                                                    (uint4*)aop, cmax_bits);
-  MIPQ_LAUNCHED("k_coarse_pack");
-  return MIPQ_OK;
-}
-
-int launch_coarse_assign(const float* x, int64_t n, int d, const float* cc, int kc, const void* aop,
-                         const float* mu, const unsigned int* cmax_bits, int32_t* labels, int64_t* rescored,
-                         bool exact_only, hipStream_t s) {
-  if (n == 0) return MIPQ_OK;
-  ProfScope ps(MIPQ_K_COARSE_ASSIGN, s);
-  if (exact_only) {
-    k_coarse_assign_exact<<<ceil_div(n, kT), kT, 0, s>>>(x, n, d, cc, kc, labels);
-    MIPQ_LAUNCHED("k_coarse_assign_exact");
-    return MIPQ_OK;
-  }
-  const int S = coarse_ksteps(d);
-  // error bound: single bfloat16 products 2(2u + u^2) with u = 2^-8, twice for
-  // the -2 factor, float32 accumulation over 16(S+1) terms at 2^-23 each, the
-  // norm pieces and the centring; g_exact: float32 differences squared (2^-23)
-  const float e_cross = 0.0165f;
-  const float e_norm = 16.0f * (S + 1) * 1.2e-7f + 2.4e-7f;
-  const float g_exact = 1.3e-7f;
-  unsigned long long* resc = reinterpret_cast<unsigned long long*>(rescored);
-  // two row groups per wave (operands loaded once per tile for 64 rows) while
-  // the row operands fit the registers
-#define CA(SV)                                                                                                  \
-  do {                                                                                                          \
-    constexpr int RGV = SV <= 8 ? 2 : 1;                                                                        \
-    const int blocks = ceil_div((n + 32 * RGV - 1) / (32 * RGV), kT / 64);                                      \
-    k_coarse_assign_mfma<SV, RGV><<<blocks, kT, 0, s>>>(x, n, d, kc, (const bf16x8*)aop, mu, cmax_bits, cc,     \
-                                                        labels, resc, e_cross, e_norm, g_exact);                \
-  } while (0)
-  switch (S) {
-    case 1: CA(1); break;
-    case 2: CA(2); break;
-    case 4: CA(4); break;
-    case 6: CA(6); break;
-    case 8: CA(8); break;
-    case 12: CA(12); break;
-    case 16: CA(16); break;
-    default: return fail(MIPQ_EUNSUPPORTED, "coarse matrix-core path supports d in {<=16, 32, 64, 96, 128, 192, 256} (got %d)", d);
-  }
-#undef CA
-  MIPQ_LAUNCHED("k_coarse_assign_mfma");
-  return MIPQ_OK;
-}
-
 int sort_blocks(int64_t n) { return n > 0 ? ceil_div(n, kRsTile) : 1; }
 
 int launch_sort_by_label(const int32_t* labels, int64_t n, int kc, uint32_t* keys_a, uint32_t* keys_b,
