@@ -14,6 +14,8 @@
 // matrix-core estimates need no quieting of signalling NaNs.
 #include <math.h>
 
+#include <type_traits>
+
 #include "bf16_pack.h"
 #include "mipq_internal.h"
 
@@ -317,47 +319,105 @@ __device__ __forceinline__ void coarse_row_operands(const float* __restrict__ x,
   }
 }
 
+// s_waitcnt operand: at most n vector memory operations of the wave
+// outstanding, no LDS operation (expcnt left alone)
+constexpr int waitcnt_vm_lgkm0(int n) { return (n & 15) | (7 << 4) | ((n >> 4) << 14); }
+
+// The estimates of one tile for the wave's row groups, from its staged
+// operands.  They are read through a restrict pointer, so the LDS reads carry
+// an alias scope while the loads into the ring carry none (the operand
+// pointer of coarse_sweep and its callers are not restrict): the compiler's
+// wait insertion then leaves the loads in flight alone, and the waits of the
+// ring are the explicit ones at the end of each tile.
+template <int NK, int RG>
+__device__ __forceinline__ void coarse_tile_mfma(const bf16x8* __restrict__ a, int lane, const bf16x8 (&B)[RG][NK],
+                                                 f32x16 (&acc)[RG]) {
+#pragma unroll
+  for (int g = 0; g < RG; ++g) acc[g] = f32x16{};
+#pragma unroll
+  for (int s = 0; s < NK; ++s) {
+    const bf16x8 av = a[s * 64 + lane];
+#pragma unroll
+    for (int g = 0; g < RG; ++g) acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, B[g][s], acc[g], 0, 0, 0);
+  }
+}
+
 // The tile loop of both launches.  Tile t's operands are staged in LDS once for
-// the block's four waves (two buffers): the next tile's chunks go from memory
-// straight to the other buffer (global_load_lds, no registers held) while the
-// current tile is scored, and the barrier that ends a tile waits for them.
-// epi(t, g, acc) receives the 16 estimates of row group g.  Every wave of the
-// block runs every tile.
-template <int S, int RG, typename Epi>
-__device__ __forceinline__ void coarse_sweep(const bf16x8* __restrict__ aop, int nt, const bf16x8 (&B)[RG][S + 1],
+// the block's four waves, in a ring of P buffers: at the start of tile t the
+// chunks of tile t + P - 1 go from memory straight to the buffer tile t - 1
+// used (global_load_lds, no registers held), so each tile's operands are
+// requested P - 1 tiles before they are read.  The barrier that ends tile t
+// waits only for the wave's loads of tile t + 1 (its vector memory counter
+// may keep the younger tiles' loads outstanding: every wave issues at least
+// cnt_min chunks per tile) and for its LDS reads, so the buffer refilled next
+// is free.  (A release fence would also wait for the loads in flight, as they
+// write LDS.)  epi(t, g, acc)
+// receives the 16 estimates of row group g.  Every wave of the block runs
+// every tile.
+template <int S, int RG, int P, typename Epi>
+__device__ __forceinline__ void coarse_sweep(const bf16x8* aop, bf16x8* ring, int nt, const bf16x8 (&B)[RG][S + 1],
                                              Epi&& epi) {
+  static_assert(P >= 2, "at least two operand buffers");
   constexpr int NK = S + 1;
   constexpr int CH = NK * 64;               // 16-byte operand chunks per tile
   constexpr int PT = (CH + kT - 1) / kT;    // chunks per thread
-  __shared__ bf16x8 a_lds[2][CH];
+  // chunks per tile of the wave that issues the fewest (the last one)
+  constexpr int cnt_min = CH > kT - 64 ? (CH - (kT - 64) + kT - 1) / kT : 0;
+  constexpr int keep = (P - 2) * cnt_min;   // loads that may stay in flight at a tile's end
+  static_assert(keep < 64, "vector memory counter range");
   const int lane = threadIdx.x & 63;
   const int wbase = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * 64;
   auto fetch = [&](int t, int buf) {
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
-      const int c = threadIdx.x + i * kT;   // lane l of wave w lands in slot wbase + i kT + l
+      const int c = threadIdx.x + i * kT;   // lane l of wave w lands in slot wbase + i kT + l (wave-uniform test)
       if (c < CH)
         __builtin_amdgcn_global_load_lds(static_cast<const void*>(aop + (size_t)t * CH + c),
-                                         (__attribute__((address_space(3))) void*)(&a_lds[buf][wbase + i * kT]),
+                                         (__attribute__((address_space(3))) void*)(ring + buf * CH + wbase + i * kT),
                                          16, 0, 0);
     }
   };
-  fetch(0, 0);
-  __syncthreads();
-  for (int t = 0; t < nt; ++t) {
-    const int cur = t & 1;
-    if (t + 1 < nt) fetch(t + 1, cur ^ 1);
+  // the end of a tile: wait until at most n loads of the wave are in flight
+  // and its LDS reads are done, then the block's barrier
+  auto tile_end = [&](auto n) {
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(decltype(n)::value));
+    __builtin_amdgcn_s_barrier();
+  };
+  auto score = [&](int t, int cur) {
+    f32x16 acc[RG];
+    coarse_tile_mfma<NK, RG>(ring + cur * CH, lane, B, acc);
 #pragma unroll
-    for (int g = 0; g < RG; ++g) {
-      f32x16 acc = {};
+    for (int g = 0; g < RG; ++g) epi(t, g, acc[g]);
+  };
+  using keep_c = std::integral_constant<int, keep>;
+  using none_c = std::integral_constant<int, 0>;
 #pragma unroll
-      for (int s = 0; s < NK; ++s)
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_lds[cur][s * 64 + lane], B[g][s], acc, 0, 0, 0);
-      epi(t, g, acc);
-    }
-    __syncthreads();
+  for (int i = 0; i < P - 1; ++i)
+    if (i < nt) fetch(i, i);
+  if (P - 2 < nt) tile_end(keep_c{});   // tile 0 loaded, tiles 1 .. P - 2 may be in flight
+  else tile_end(none_c{});
+  int cur = 0;
+  int t = 0;
+  // tiles whose successor's loads are followed by P - 2 younger tiles' loads
+  for (; t + P - 1 < nt; ++t) {
+    fetch(t + P - 1, cur == 0 ? P - 1 : cur - 1);   // the buffer of tile t - 1
+    score(t, cur);
+    tile_end(keep_c{});
+    cur = cur == P - 1 ? 0 : cur + 1;
+  }
+  for (; t < nt; ++t) {   // the last P - 1 tiles: nothing left to fetch
+    score(t, cur);
+    tile_end(none_c{});
+    cur = cur == P - 1 ? 0 : cur + 1;
   }
 }
+
+// operand buffers of the first launch (three blocks per CU) and of the resolve
+// launch (two blocks per CU beside the candidate lists)
+constexpr int coarse_ring_assign(int S) { return S <= 12 ? 4 : 3; }
+constexpr int coarse_ring_resolve(int S) { return S <= 8 ? 4 : (S <= 12 ? 3 : 2); }
+// 16-byte operand chunks of one tile
+constexpr int coarse_tile_chunks(int S) { return (S + 1) * 64; }
 
 // minimum of the 16 estimates of a lane
 __device__ __forceinline__ float coarse_tile_min(const f32x16& acc) {
@@ -380,7 +440,7 @@ __device__ __forceinline__ float coarse_beta(float xn, float cm, float e_cross, 
 // of each group): labels of the separated rows, encoded f1 of the others.
 template <int S, int RG>
 __global__ __launch_bounds__(kT, 3) void k_coarse_assign_mfma(
-    const float* __restrict__ x, int64_t n, int d, int kc, const bf16x8* __restrict__ aop,
+    const float* __restrict__ x, int64_t n, int d, int kc, const bf16x8* aop,
     const float* __restrict__ mu, const unsigned int* __restrict__ cmax_bits, int32_t* __restrict__ labels,
     unsigned long long* __restrict__ rescored, float e_cross, float e_norm, float g_exact) {
   constexpr int NK = S + 1;
@@ -389,6 +449,7 @@ __global__ __launch_bounds__(kT, 3) void k_coarse_assign_mfma(
   const int w = threadIdx.x >> 6;
   const int64_t r0 = ((int64_t)blockIdx.x * (kT / 64) + w) * (32 * RG);
   auto row_at = [&](int i) -> int64_t { return r0 + i < n ? r0 + i : -1; };
+  __shared__ bf16x8 ring[coarse_ring_assign(S) * coarse_tile_chunks(S)];   // the kernel's only LDS object
   const float cm = __uint_as_float(*cmax_bits);
   bf16x8 B[RG][NK];
   float xn[RG];
@@ -413,7 +474,7 @@ __global__ __launch_bounds__(kT, 3) void k_coarse_assign_mfma(
 #pragma unroll
     for (int r = 0; r < 16; ++r) bmin[g][r] = INFINITY;
   }
-  coarse_sweep<S, RG>(aop, nt, B, [&](int t, int g, const f32x16& acc) {
+  coarse_sweep<S, RG, coarse_ring_assign(S)>(aop, ring, nt, B, [&](int t, int g, const f32x16& acc) {
     const float tmin = coarse_tile_min(acc);
 #pragma unroll
     for (int r = 0; r < 16; ++r) bmin[g][r] = fminf(bmin[g][r], acc[r]);
@@ -466,13 +527,12 @@ __global__ __launch_bounds__(kT, 3) void k_coarse_assign_mfma(
 // wave w: candidates within the bound of each row's f1 (from its label slot),
 // then the exact rule over them.  Every wave meets the block's barriers.
 template <int S, int RG>
-__device__ __forceinline__ void coarse_resolve_rows(
-    const float* __restrict__ x, int64_t n, int d, int kc, const bf16x8* __restrict__ aop,
-    const float* __restrict__ mu, const unsigned int* __restrict__ cmax_bits, const float* __restrict__ cc,
-    int32_t* __restrict__ labels, float e_cross, float e_norm, float g_exact, const int32_t* rlist, int take) {
+__device__ __forceinline__ void coarse_resolve_rows(const float* x, int64_t n, int d, int kc, const bf16x8* aop,
+                                                    const float* mu, const unsigned int* cmax_bits, const float* cc,
+                                                    int32_t* labels, float e_cross, float e_norm, float g_exact,
+                                                    const int32_t* rlist, int take, bf16x8* ring,
+                                                    uint32_t* cand_rk_all, double* cand_d_all) {
   constexpr int NK = S + 1;
-  __shared__ uint32_t cand_rk_all[kT / 64][kCandCap];   // (row in wave) << 16 | centroid
-  __shared__ double cand_d_all[kT / 64][kCandCap];
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
   const int w = threadIdx.x >> 6;
@@ -480,56 +540,53 @@ __device__ __forceinline__ void coarse_resolve_rows(
     const int slot = w * (32 * RG) + i;
     return slot < take ? (int64_t)rlist[slot] : -1;
   };
-  uint32_t* cand_rk = cand_rk_all[w];
-  double* cand_d = cand_d_all[w];
+  uint32_t* cand_rk = cand_rk_all + w * kCandCap;   // (row in wave) << 16 | centroid
+  double* cand_d = cand_d_all + w * kCandCap;
   const float cm = __uint_as_float(*cmax_bits);
   bf16x8 B[RG][NK];
   float xn[RG];
   coarse_row_operands<S, RG>(x, n, d, mu, row_at, B, xn);
   const int nt = (kc + 31) / 32;
   const float qk = coarse_key_quant(coarse_tile_bits(nt));
-  // candidate test est - f1 <= c0 + c1 |est|: the separation bound with the
-  // row's terms gathered in c0
+  // Candidate test: est - f1 <= c0 + c1 |est| (the separation bound, the
+  // row's terms gathered in c0).  Every estimate that passes it is at most
+  // T = f1 + c0 + 2 c1 (|f1| + c0) (c1 < 1/2), so the pass keeps the
+  // estimates up to T: a superset by at most c1 |est|, decided exactly all
+  // the same, for one compare per estimate.
   const float c1 = g_exact + qk;
-  float f1[RG], c0[RG];
+  float thr[RG];
   bool valid[RG];
 #pragma unroll
   for (int g = 0; g < RG; ++g) {
     const int64_t row = row_at(32 * g + (lane & 31));
     valid[g] = row >= 0;
-    f1[g] = valid[g] ? coarse_decode_f1(labels[row]) : 0.0f;
+    const float f1 = valid[g] ? coarse_decode_f1(labels[row]) : 0.0f;
     const float beta = coarse_beta(xn[g], cm, e_cross, e_norm);
-    c0[g] = 2.0f * beta + g_exact * (fabsf(f1[g]) + 2.0f * beta + 2.0f * xn[g] * g_exact) + qk * fabsf(f1[g]);
+    const float c0 = 2.0f * beta + g_exact * (fabsf(f1) + 2.0f * beta + 2.0f * xn[g] * g_exact) + qk * fabsf(f1);
+    const float tt = f1 + c0 + 2.0f * c1 * (fabsf(f1) + c0);
+    thr[g] = valid[g] ? tt + fabsf(tt) * 0x1p-20f : -INFINITY;   // and the rounding of T
   }
   int nc = 0;
   bool ovf[RG];
 #pragma unroll
   for (int g = 0; g < RG; ++g) ovf[g] = false;
-  coarse_sweep<S, RG>(aop, nt, B, [&](int t, int g, const f32x16& acc) {
-    // est - f1 - c1 |est| grows with est: no candidate of the lane in this
-    // tile when its smallest estimate fails the test
-    const float tmin = coarse_tile_min(acc);
-    if (!__ballot(valid[g] && !(tmin - f1[g] > fmaf(c1, fabsf(tmin), c0[g])))) return;   // wave-uniform
-    const int klim = kc - t * 32 - 4 * h;   // candidate 8(r/4) + r%4 exists while below klim
-    uint32_t mine = 0;                      // bit r: candidate in accumulator register r
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const float v = acc[r];
-      const bool cand = valid[g] && (r >> 2) * 8 + (r & 3) < klim && !(v - f1[g] > fmaf(c1, fabsf(v), c0[g]));
-      mine |= cand ? (1u << r) : 0u;
-    }
-    if (!__ballot(mine != 0)) return;
+  coarse_sweep<S, RG, coarse_ring_resolve(S)>(aop, ring, nt, B, [&](int t, int g, const f32x16& acc) {
+    // no candidate of the wave in this tile unless some lane's smallest
+    // estimate is within its threshold (padded centroids estimate +inf)
+    if (!__ballot(coarse_tile_min(acc) <= thr[g])) return;   // wave-uniform
     const uint32_t rl = (uint32_t)(32 * g + (lane & 31)) << 16;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const bool cand = (mine >> r) & 1u;
+      const bool cand = acc[r] <= thr[g];
       const uint64_t m = __ballot(cand);
-      if (!m) continue;
+      if (!m) continue;   // wave-uniform
       if (cand) {
-        const int pos = nc + __popcll(m & ((1ull << lane) - 1ull));
+        const int pos =
+            nc + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
         const int k = t * 32 + (r >> 2) * 8 + h * 4 + (r & 3);
-        if (pos < kCandCap) cand_rk[pos] = rl | (uint32_t)k;
-        else ovf[g] = true;
+        if (pos >= kCandCap) ovf[g] = true;
+        else if (k < kc) cand_rk[pos] = rl | (uint32_t)k;
+        else cand_rk[pos] = rl | (uint32_t)(kc - 1);   // never: a padded centroid estimates +inf
       }
       nc += __popcll(m);
     }
@@ -580,13 +637,22 @@ __device__ __forceinline__ void coarse_resolve_rows(
 // LDS and decides them kT / 64 * 32 RG at a time (full waves of such rows).
 template <int S, int RG>
 __global__ __launch_bounds__(kT, 2) void k_coarse_resolve_mfma(
-    const float* __restrict__ x, int64_t n, int d, int kc, const bf16x8* __restrict__ aop,
+    const float* __restrict__ x, int64_t n, int d, int kc, const bf16x8* aop,
     const float* __restrict__ mu, const unsigned int* __restrict__ cmax_bits, const float* __restrict__ cc,
     int32_t* __restrict__ labels, float e_cross, float e_norm, float g_exact, int64_t span) {
   constexpr int kRows = kT / 64 * 32 * RG;   // rows decided per pass of the block
   constexpr int kPer = 4;                     // labels scanned per thread and step
-  __shared__ int32_t rlist[kRows + kPer * kT];
-  __shared__ int rcnt;
+  // the kernel's only LDS object (separate objects would give the LDS reads
+  // of the ring alias scopes that make the compiler wait for its loads):
+  // operand ring, candidate lists, row list and its count
+  constexpr size_t kRing = (size_t)coarse_ring_resolve(S) * coarse_tile_chunks(S) * 16;
+  constexpr size_t kCand = (size_t)(kT / 64) * kCandCap;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[kRing + kCand * 12 + (kRows + kPer * kT + 1) * 4];
+  bf16x8* ring = reinterpret_cast<bf16x8*>(lds);
+  double* cand_d_all = reinterpret_cast<double*>(lds + kRing);
+  uint32_t* cand_rk_all = reinterpret_cast<uint32_t*>(lds + kRing + kCand * 8);
+  int32_t* rlist = reinterpret_cast<int32_t*>(lds + kRing + kCand * 12);
+  int& rcnt = rlist[kRows + kPer * kT];
   int64_t pos = (int64_t)blockIdx.x * span;
   const int64_t end = min(n, pos + span);
   if (threadIdx.x == 0) rcnt = 0;
@@ -606,7 +672,8 @@ __global__ __launch_bounds__(kT, 2) void k_coarse_resolve_mfma(
     const int c = rcnt;
     if (c == 0) break;   // block-uniform; pos == end
     const int take = c < kRows ? c : kRows;
-    coarse_resolve_rows<S, RG>(x, n, d, kc, aop, mu, cmax_bits, cc, labels, e_cross, e_norm, g_exact, rlist, take);
+    coarse_resolve_rows<S, RG>(x, n, d, kc, aop, mu, cmax_bits, cc, labels, e_cross, e_norm, g_exact, rlist, take,
+                               ring, cand_rk_all, cand_d_all);
     __syncthreads();
     // the rows not yet taken (fewer than kPer * kT) move to the front
     const int rest = c - take;
@@ -635,8 +702,8 @@ __global__ __launch_bounds__(kT, 2) void k_coarse_resolve_mfma(
 constexpr int64_t kResolveMinSpan = 1024;
 
 int resolve_blocks(int S, int RG) {
-  const size_t lds = 2 * (size_t)(S + 1) * 64 * 16 + (size_t)(kT / 64) * kCandCap * 12 +
-                     ((size_t)(kT / 64) * 32 * RG + 4 * kT) * 4 + 4;
+  const size_t lds = (size_t)coarse_ring_resolve(S) * coarse_tile_chunks(S) * 16 + (size_t)(kT / 64) * kCandCap * 12 +
+                     ((size_t)(kT / 64) * 32 * RG + 4 * kT + 1) * 4;
   size_t per_cu = (size_t)160 * 1024 / lds;
   if (per_cu > 2) per_cu = 2;
   if (per_cu < 1) per_cu = 1;
