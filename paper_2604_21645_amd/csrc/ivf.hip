@@ -140,7 +140,9 @@ __global__ __launch_bounds__(kT) void k_list_offsets(const uint32_t* __restrict_
 // ---------------------------------------------------------------- coarse update
 // One block per list: float64 sums of its rows in id order (thread t owns
 // dimensions t, t+blockDim, ...); centroid = sum / count (empty keeps its
-// value); also the list's objective sum of (x - c_old)^2 in float64.
+// value); also the list's objective sum of (x - c_old)^2 in float64.  The
+// rows are loaded kU at a time (their loads in flight together) and then
+// added in id order, so the sums are those of the plain loop.
 __global__ __launch_bounds__(kT) void k_coarse_update(const float* __restrict__ x, int d,
                                                       const int32_t* __restrict__ ids,
                                                       const int64_t* __restrict__ offsets,
@@ -150,14 +152,29 @@ __global__ __launch_bounds__(kT) void k_coarse_update(const float* __restrict__ 
   const int l = blockIdx.x;
   const int64_t a = offsets[l], b = offsets[l + 1];
   double jl = 0.0;
+  constexpr int kU = 32;
+  const int lane = threadIdx.x & 63;
   for (int t = threadIdx.x; t < d; t += blockDim.x) {
     const float cold = cc[(int64_t)l * d + t];
     double s = 0.0;
-    for (int64_t p = a; p < b; ++p) {
-      const float xv = x[(int64_t)ids[p] * d + t];
-      s += (double)xv;
-      const double df = (double)xv - (double)cold;
-      jl += df * df;
+    for (int64_t p0 = a; p0 < b; p0 += kU) {
+      const int cnt = b - p0 < kU ? (int)(b - p0) : kU;
+      // lane u holds the id of row p0 + u (one vector load), read back per row
+      const int myid = ids[p0 + (lane < cnt ? lane : cnt - 1)];
+      float xv[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int r = __builtin_amdgcn_readlane(myid, u < cnt ? u : cnt - 1);
+        xv[u] = x[(int64_t)r * d + t];   // all kU loads in flight
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        if (u < cnt) {
+          s += (double)xv[u];
+          const double df = (double)xv[u] - (double)cold;
+          jl += df * df;
+        }
+      }
     }
     if (b > a) {
       const double v = s / (double)(b - a);
