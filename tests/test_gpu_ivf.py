@@ -21,7 +21,8 @@ def _t(a):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-@pytest.mark.parametrize("n,d,kc", [(3001, 128, 100), (777, 64, 33), (1000, 32, 300), (64, 16, 7)])
+@pytest.mark.parametrize("n,d,kc", [(3001, 128, 100), (777, 64, 33), (1000, 32, 300), (64, 16, 7),
+                                    (1500, 96, 257), (1200, 192, 300), (900, 256, 161), (1000, 128, 2048)])
 def test_coarse_assign_matches_oracle(prec, n, d, kc):
     print("coarse", prec, n, d, kc, flush=True)
     x = wl.gaussian_mixture(n + d, n, d, 50, sigma=0.05)
