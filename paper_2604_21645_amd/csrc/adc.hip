@@ -840,7 +840,7 @@ OrderWs carve_order(void* ws, int64_t pairs, int nlabels) {
   o.keys_a = c.take<uint32_t>(pairs);
   o.keys_b = c.take<uint32_t>(pairs);
   o.keys_sorted = c.take<uint32_t>(pairs);
-  o.hist = c.take<uint32_t>((size_t)64 * sort_blocks(pairs));
+  o.hist = c.take<uint32_t>(sort_hist_entries(pairs));
   o.vals_a = c.take<int32_t>(pairs);
   o.vals_b = c.take<int32_t>(pairs);
   o.order = c.take<int32_t>(pairs);

@@ -451,7 +451,7 @@ BuildWs carve_build(void* ws, int64_t n, int d, int kc, int64_t n_train, int m, 
   b.keys_a = c.take<uint32_t>(nmax);
   b.keys_b = c.take<uint32_t>(nmax);
   b.keys_sorted = c.take<uint32_t>(nmax);
-  b.hist = c.take<uint32_t>((size_t)64 * sort_blocks(nmax));
+  b.hist = c.take<uint32_t>(sort_hist_entries(nmax));
   b.vals_a = c.take<int32_t>(nmax);
   b.vals_b = c.take<int32_t>(nmax);
   b.tids = c.take<int32_t>(n_train);
@@ -516,7 +516,7 @@ KmWs carve_kmeans(void* ws, int64_t n_train, bool gather, int d, int k, int prec
   w.keys_a = c.take<uint32_t>(n_train);
   w.keys_b = c.take<uint32_t>(n_train);
   w.keys_sorted = c.take<uint32_t>(n_train);
-  w.hist = c.take<uint32_t>((size_t)64 * sort_blocks(n_train));
+  w.hist = c.take<uint32_t>(sort_hist_entries(n_train));
   w.vals_a = c.take<int32_t>(n_train);
   w.vals_b = c.take<int32_t>(n_train);
   w.tids = c.take<int32_t>(n_train);
@@ -646,7 +646,7 @@ AddWs carve_add(void* ws, int64_t n, int d, int kc, int m, int ks, int precision
   a.keys_a = c.take<uint32_t>(nn);
   a.keys_b = c.take<uint32_t>(nn);
   a.keys_sorted = c.take<uint32_t>(nn);
-  a.hist = c.take<uint32_t>((size_t)64 * sort_blocks(nn));
+  a.hist = c.take<uint32_t>(sort_hist_entries(nn));
   a.vals_a = c.take<int32_t>(nn);
   a.vals_b = c.take<int32_t>(nn);
   a.lab = need_labels ? c.take<int32_t>(nn) : nullptr;

@@ -36,76 +36,95 @@ __device__ __forceinline__ bf16x8 to_bf16x8(const float* v) {
 }
 
 // ---------------------------------------------------------------- radix sort
-// Stable LSD radix sort of (key, value) by key, 6-bit digits.  Tile = kRsTile
-// consecutive elements per block; a round = 64 elements per wave, waves in
-// element order.
+// Stable LSD radix sort of (key, value) by key, 6-bit digits.  Tile = `tile`
+// consecutive elements per block (a multiple of kT, chosen so that the sort
+// runs on up to kRsMaxBlocks blocks); a round = 64 elements per wave, waves
+// in element order.
 constexpr int kRsBits = 6;
 constexpr int kRsBuckets = 1 << kRsBits;
-constexpr int kRsTile = 4096;
+constexpr int kRsMaxBlocks = 1024;
+static_assert(kRsBuckets == 64, "one bucket per lane of a wave");
 
 __global__ __launch_bounds__(kT) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
-                                                uint32_t* __restrict__ hist, int nblk) {
+                                                uint32_t* __restrict__ hist, int nblk, int64_t tile) {
   __shared__ uint32_t cnt[kRsBuckets];
   if (threadIdx.x < kRsBuckets) cnt[threadIdx.x] = 0u;
   __syncthreads();
-  const int64_t b0 = (int64_t)blockIdx.x * kRsTile;
-  const int64_t b1 = min(n, b0 + kRsTile);
+  const int64_t b0 = (int64_t)blockIdx.x * tile;
+  const int64_t b1 = min(n, b0 + tile);
   for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x)
     atomicAdd(&cnt[(keys[i] >> shift) & (kRsBuckets - 1)], 1u);
   __syncthreads();
   if (threadIdx.x < kRsBuckets) hist[(size_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// exclusive scan of hist (bucket-major) in place, one block of kT threads
-__global__ __launch_bounds__(kT) void k_rs_scan(uint32_t* __restrict__ hist, int total) {
-  __shared__ uint32_t part[kT];
-  const int per = (total + kT - 1) / kT;
-  const int s0 = threadIdx.x * per;
-  uint32_t run = 0;
-  for (int i = 0; i < per; ++i)
-    if (s0 + i < total) run += hist[s0 + i];
-  part[threadIdx.x] = run;
-  __syncthreads();
-  for (int off = 1; off < kT; off <<= 1) {
-    const uint32_t v = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
+// exclusive scan of each bucket's row of hist (bucket-major: row b holds the
+// nblk <= kRsMaxBlocks block counts of digit b) in place, one block per
+// bucket, one entry per thread; the row totals go to tot[b] (the scatter adds
+// their exclusive prefix)
+constexpr int kScanT = kRsMaxBlocks;
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
   }
-  uint32_t acc = part[threadIdx.x] - run;
-  for (int i = 0; i < per; ++i)
-    if (s0 + i < total) {
-      const uint32_t c = hist[s0 + i];
-      hist[s0 + i] = acc;
-      acc += c;
-    }
+  return v;
+}
+__global__ __launch_bounds__(kScanT) void k_rs_scan(uint32_t* __restrict__ hist, int nblk, uint32_t* __restrict__ tot) {
+  __shared__ uint32_t wsum[kScanT / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t* row = hist + (size_t)blockIdx.x * nblk;
+  const bool in = (int)threadIdx.x < nblk;
+  const uint32_t v = in ? row[threadIdx.x] : 0u;
+  const uint32_t incl = wave_incl_scan(v, lane);
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  if (w == 0) {
+    const uint32_t ws = lane < kScanT / 64 ? wsum[lane] : 0u;
+    const uint32_t wi = wave_incl_scan(ws, lane);
+    if (lane < kScanT / 64) wsum[lane] = wi - ws;   // exclusive prefix of the waves
+    if (lane == kScanT / 64 - 1) tot[blockIdx.x] = wi;
+  }
+  __syncthreads();
+  if (in) row[threadIdx.x] = wsum[w] + incl - v;
 }
 
-// scatter in element order; vals_in == NULL means value = element index
+// scatter in element order; vals_in == NULL means value = element index.  A
+// lane's rank among the wave's lanes with the same digit comes from one ballot
+// per digit bit (the lanes that agree with it on every bit).
 __global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t* __restrict__ keys_in,
                                                    const int32_t* __restrict__ vals_in, int64_t n, int shift,
-                                                   const uint32_t* __restrict__ offs, int nblk,
+                                                   const uint32_t* __restrict__ offs, int nblk, int64_t tile,
+                                                   const uint32_t* __restrict__ tot,
                                                    uint32_t* __restrict__ keys_out, int32_t* __restrict__ vals_out) {
   __shared__ uint32_t base[kRsBuckets];
   __shared__ uint32_t wcnt[kT / 64][kRsBuckets];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
-  if (threadIdx.x < kRsBuckets) base[threadIdx.x] = offs[(size_t)threadIdx.x * nblk + blockIdx.x];
-  const int64_t b0 = (int64_t)blockIdx.x * kRsTile;
-  const int64_t b1 = min(n, b0 + kRsTile);
+  if (threadIdx.x < kRsBuckets) {   // wave 0: the digit's start = earlier digits' totals + earlier blocks' counts
+    const uint32_t t = tot[threadIdx.x];
+    base[threadIdx.x] = wave_incl_scan(t, lane) - t + offs[(size_t)threadIdx.x * nblk + blockIdx.x];
+  }
+  const int64_t b0 = (int64_t)blockIdx.x * tile;
+  const int64_t b1 = min(n, b0 + tile);
   const uint64_t below = (1ull << lane) - 1ull;
   for (int64_t r0 = b0; r0 < b1; r0 += (int64_t)nw * 64) {
     const int64_t i = r0 + (int64_t)w * 64 + lane;
     const bool ok = i < b1;
     const uint32_t key = ok ? keys_in[i] : 0u;
     const int32_t val = ok ? (vals_in ? vals_in[i] : (int32_t)i) : 0;
-    const int dig = ok ? (int)((key >> shift) & (kRsBuckets - 1)) : -1;
-    int rank = 0;
-    for (int b = 0; b < kRsBuckets; ++b) {
-      const uint64_t m = __ballot(dig == b);
-      if (dig == b) rank = __popcll(m & below);
-      if (lane == b) wcnt[w][b] = (uint32_t)__popcll(m);
+    const int dig = ok ? (int)((key >> shift) & (kRsBuckets - 1)) : 0;
+    uint64_t peers = __ballot(ok);   // valid lanes with this lane's digit
+#pragma unroll
+    for (int b = 0; b < kRsBits; ++b) {
+      const bool bit = (dig >> b) & 1;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
     }
+    const int rank = __popcll(peers & below);
+    wcnt[w][lane] = 0u;   // lane b clears bucket b (kRsBuckets == 64), then the first lane of each digit counts it
+    if (ok && rank == 0) wcnt[w][dig] = (uint32_t)__popcll(peers);
     __syncthreads();
     if (ok) {
       uint32_t pos = base[dig] + (uint32_t)rank;
@@ -355,13 +374,26 @@ int grid_cap(int64_t work, int cap) {
 }  // namespace
 
 // ---------------------------------------------------------------- host side
-int sort_blocks(int64_t n) { return n > 0 ? ceil_div(n, kRsTile) : 1; }
+// elements per block of the sort: a multiple of kT, at most kRsMaxBlocks blocks
+int64_t sort_tile(int64_t n) {
+  int64_t t = (n + kRsMaxBlocks - 1) / kRsMaxBlocks;
+  t = (t + kT - 1) / kT * kT;
+  return t < kT ? kT : t;
+}
+int sort_blocks(int64_t n) { return n > 0 ? ceil_div(n, sort_tile(n)) : 1; }
+// (enough for every sort of up to n elements: sort_blocks(m) <= min(ceil(m / kT), kRsMaxBlocks), which
+// grows with m although sort_blocks itself does not)
+size_t sort_hist_entries(int64_t n) {
+  const int64_t b = (n + kT - 1) / kT;
+  return (size_t)kRsBuckets * (size_t)(b < 1 ? 1 : (b > kRsMaxBlocks ? kRsMaxBlocks : b)) + kRsBuckets;
+}
 
 int launch_sort_by_label(const int32_t* labels, int64_t n, int kc, uint32_t* keys_a, uint32_t* keys_b,
                          int32_t* vals_a, int32_t* vals_b, uint32_t* hist, int32_t* ids_out,
                          uint32_t* keys_out_sorted, int64_t* offsets, hipStream_t s) {
   ProfScope ps(MIPQ_K_SORT, s);
   const int nblk = sort_blocks(n);
+  const int64_t tile = sort_tile(n);
   int bits = 1;
   while ((1 << bits) < kc) ++bits;
   const int passes = (bits + kRsBits - 1) / kRsBits;
@@ -372,11 +404,12 @@ int launch_sort_by_label(const int32_t* labels, int64_t n, int kc, uint32_t* key
     uint32_t* kout = last ? keys_out_sorted : (p % 2 == 0 ? keys_a : keys_b);
     int32_t* vout = last ? ids_out : (p % 2 == 0 ? vals_a : vals_b);
     if (n > 0) {
-      k_rs_hist<<<nblk, kT, 0, s>>>(kin, n, p * kRsBits, hist, nblk);
+      k_rs_hist<<<nblk, kT, 0, s>>>(kin, n, p * kRsBits, hist, nblk, tile);
       MIPQ_LAUNCHED("k_rs_hist");
-      k_rs_scan<<<1, kT, 0, s>>>(hist, kRsBuckets * nblk);
+      k_rs_scan<<<kRsBuckets, kScanT, 0, s>>>(hist, nblk, hist + (size_t)kRsBuckets * nblk);
       MIPQ_LAUNCHED("k_rs_scan");
-      k_rs_scatter<<<nblk, kT, 0, s>>>(kin, vin, n, p * kRsBits, hist, nblk, kout, vout);
+      k_rs_scatter<<<nblk, kT, 0, s>>>(kin, vin, n, p * kRsBits, hist, nblk, tile, hist + (size_t)kRsBuckets * nblk,
+                                       kout, vout);
       MIPQ_LAUNCHED("k_rs_scatter");
     }
     kin = kout;

@@ -150,6 +150,8 @@ int launch_coarse_assign(const float* x, int64_t n, int d, const float* cc, int 
                          const float* mu, const unsigned int* cmax_bits, int32_t* labels, int64_t* rescored,
                          bool exact_only, hipStream_t s);
 int sort_blocks(int64_t n);
+// uint32 entries of the sort's histogram workspace (block counts and digit totals)
+size_t sort_hist_entries(int64_t n);
 int launch_sort_by_label(const int32_t* labels, int64_t n, int kc, uint32_t* keys_a, uint32_t* keys_b,
                          int32_t* vals_a, int32_t* vals_b, uint32_t* hist, int32_t* ids_out,
                          uint32_t* keys_out_sorted, int64_t* offsets, hipStream_t s);
