@@ -700,6 +700,12 @@ __global__ __launch_bounds__(kT, 2) void k_coarse_resolve_mfma(
 // candidate lists and the row list does not fit two), each scanning at least
 // kResolveMinSpan rows
 constexpr int64_t kResolveMinSpan = 1024;
+// up to this many rows the resolve launch is one pass per block, bound by the
+// latency of the tile loop rather than by throughput: one row group per wave
+// (9 instead of 18 MFMAs in a tile's chain) and spans of at least
+// kResolveMinSpanSmall rows (more, smaller blocks)
+constexpr int64_t kResolveSmallN = int64_t(1) << 20;
+constexpr int64_t kResolveMinSpanSmall = 256;
 
 int resolve_blocks(int S, int RG) {
   const size_t lds = (size_t)coarse_ring_resolve(S) * coarse_tile_chunks(S) * 16 + (size_t)(kT / 64) * kCandCap * 12 +
@@ -764,12 +770,21 @@ int launch_coarse_assign(const float* x, int64_t n, int d, const float* cc, int 
     k_coarse_assign_mfma<SV, RGV><<<blocks, kT, 0, s>>>(x, n, d, kc, (const bf16x8*)aop, mu, cmax_bits, labels, \
                                                         resc, e_cross, e_norm, g_exact);                        \
     MIPQ_LAUNCHED("k_coarse_assign_mfma");                                                                      \
-    const int64_t rb = resolve_blocks(SV, RGV);                                                                 \
-    int64_t span = (n + rb - 1) / rb;                                                                           \
-    if (span < kResolveMinSpan) span = kResolveMinSpan;                                                         \
-    k_coarse_resolve_mfma<SV, RGV><<<ceil_div(n, span), kT, 0, s>>>(x, n, d, kc, (const bf16x8*)aop, mu,        \
+    if (n <= kResolveSmallN) { /* one pass per block: one row group per wave halves the tile latency */        \
+      const int64_t rb = resolve_blocks(SV, 1);                                                                 \
+      int64_t span = (n + rb - 1) / rb;                                                                         \
+      if (span < kResolveMinSpanSmall) span = kResolveMinSpanSmall;                                             \
+      k_coarse_resolve_mfma<SV, 1><<<ceil_div(n, span), kT, 0, s>>>(x, n, d, kc, (const bf16x8*)aop, mu,        \
                                                                     cmax_bits, cc, labels, e_cross, e_norm,     \
                                                                     g_exact, span);                             \
+    } else {                                                                                                    \
+      const int64_t rb = resolve_blocks(SV, RGV);                                                               \
+      int64_t span = (n + rb - 1) / rb;                                                                         \
+      if (span < kResolveMinSpan) span = kResolveMinSpan;                                                       \
+      k_coarse_resolve_mfma<SV, RGV><<<ceil_div(n, span), kT, 0, s>>>(x, n, d, kc, (const bf16x8*)aop, mu,      \
+                                                                      cmax_bits, cc, labels, e_cross, e_norm,   \
+                                                                      g_exact, span);                           \
+    }                                                                                                           \
   } while (0)
   switch (S) {
     case 1: CA(1); break;
