@@ -44,7 +44,8 @@ constexpr int kThreads = 256;   // 4 waves, one subspace each
 constexpr int kOutTiles = 32;
 
 // LDS of k_fit_round_bf16: sums [ks][ds + 1] float64 and counts [ks], then
-// (16-byte aligned) the waves' stashes and 16-bit pending lists
+// (16-byte aligned) the waves' stashes, the block's 16-bit pending list and
+// two counters (the next 64-row step, the list's length)
 __host__ __device__ constexpr size_t fit_lds_stash_offset(int ks, int ds) {
   return ((size_t)ks * (ds + 1) * sizeof(double) + (size_t)ks * sizeof(uint32_t) + 15) & ~size_t(15);
 }
@@ -616,23 +617,46 @@ __device__ __forceinline__ void load_own_row(float (&xv)[DW], const float* __res
 // re - rb <= 65536 entries) and re-decided by the whole wave after the loop.  Returns the number of
 // re-decided rows; OUT adds the squared errors to *sse (lane-local sums); ACC
 // adds every row, once its code is final, to the block's sums (AccLds).
-template <int NB, int NT, bool FULL, bool OUT, bool REG, bool ACC = false>
+// DYN: [rb, re) is the block's range, shared by its waves: each wave claims
+// the next 64-row step from the counter dyn[0] (so the waves of a SIMD end
+// together however the SIMD shares its issue slots among them) and appends
+// its ambiguous rows to the block's list pend (count dyn[1]), which the waves
+// re-decide together once all are done (a barrier: every wave of the block
+// must call).  Returns the block's number of ambiguous rows.
+__device__ __forceinline__ int claim_step(int* ctr, int lane) {
+  int v = 0;
+  if (lane == 0) v = atomicAdd(ctr, 1);
+  return __builtin_amdgcn_readfirstlane(v);
+}
+template <int NB, int NT, bool FULL, bool OUT, bool REG, bool ACC = false, bool DYN = false>
 __device__ __forceinline__ int assign_rows64(const SubOps<NB, NT>& o, const Band& bd, const float* __restrict__ x,
                                              int d, int ds, int m, int ks, int sub, int64_t rb, int64_t re,
                                              const float* __restrict__ cbsub, uint8_t* __restrict__ codes,
                                              uint16_t* pend, int lane, float* __restrict__ min_dist,
-                                             double* sse, const AccLds& acc = AccLds()) {
+                                             double* sse, const AccLds& acc = AccLds(), int* dyn = nullptr) {
   static_assert(!(ACC && OUT), "one fused output at a time");
+  static_assert(!DYN || ACC, "the shared steps are the fused round's");
   constexpr int DW = NB * 8;
   constexpr int NMF = bf16_nmfma(NB);
   int np = 0;
+  const int nsteps = DYN ? (int)((re - rb + 63) / 64) : 0;
+  int step = DYN ? claim_step(dyn, lane) : 0;
   float xnext[DW];
-  load_own_row<DW, FULL>(xnext, x, rb, re, d, sub, ds, lane);
-  for (int64_t r0 = rb; r0 < re; r0 += 64) {
+  if (!DYN || step < nsteps) load_own_row<DW, FULL>(xnext, x, rb + (int64_t)step * 64, re, d, sub, ds, lane);
+  for (int64_t r0 = rb + (int64_t)step * 64; DYN ? step < nsteps : r0 < re;) {
     float xv[DW];
 #pragma unroll
     for (int e = 0; e < DW; ++e) xv[e] = xnext[e];
-    if (r0 + 64 < re) load_own_row<DW, FULL>(xnext, x, r0 + 64, re, d, sub, ds, lane);   // next step in flight
+    // the next step's row in flight
+    int64_t rnext;
+    if (DYN) {
+      step = claim_step(dyn, lane);
+      rnext = rb + (int64_t)step * 64;
+      if (step < nsteps) load_own_row<DW, FULL>(xnext, x, rnext, re, d, sub, ds, lane);
+    } else {
+      rnext = r0 + 64;
+      if (rnext < re) load_own_row<DW, FULL>(xnext, x, rnext, re, d, sub, ds, lane);
+    }
     const int64_t row = r0 + lane;
     const bool valid = row < re;
     if (ACC || (OUT && NB == 1)) {   // the slice waits in LDS until the row's code is known
@@ -670,7 +694,13 @@ __device__ __forceinline__ int assign_rows64(const SubOps<NB, NT>& o, const Band
     const bool push = valid && amb;
     const uint64_t mask = __ballot(push);
     if (mask) {
-      if (push) pend[np + lanes_below(mask)] = (uint16_t)(row - rb);
+      int at = np;
+      if (DYN) {   // the block's list
+        int b = 0;
+        if (lane == 0) b = atomicAdd(dyn + 1, __popcll(mask));
+        at = __builtin_amdgcn_readfirstlane(b);
+      }
+      if (push) pend[at + lanes_below(mask)] = (uint16_t)(row - rb);
       np += __popcll(mask);
     }
     if (ACC && valid && !amb) {
@@ -730,6 +760,15 @@ __device__ __forceinline__ int assign_rows64(const SubOps<NB, NT>& o, const Band
       if (min_dist) min_dist[row * m + sub] = dist;
       *sse += sq;
     }
+    r0 = rnext;
+  }
+  if (DYN) {   // the block's list once every wave is done, split evenly over the waves
+    __syncthreads();
+    const int nw = (int)(blockDim.x >> 6), w = (int)(threadIdx.x >> 6);
+    const int total = dyn[1];
+    const int s0 = (int)((int64_t)total * w / nw), s1 = (int)((int64_t)total * (w + 1) / nw);
+    redecide<DW, REG, OUT, ACC>(pend + s0, rb, s1 - s0, x, d, m, ks, ds, sub, cbsub, codes, lane, min_dist, sse, acc);
+    return total;
   }
   redecide<DW, REG, OUT, ACC>(pend, rb, np, x, d, m, ks, ds, sub, cbsub, codes, lane, min_dist, sse, acc);
   return np;
@@ -832,22 +871,25 @@ k_fit_round_bf16(const float* __restrict__ x, int64_t n, int d, int m, int ks, i
   acc.cnt = reinterpret_cast<uint32_t*>(acc.S + (size_t)ks * stride);
   float4* stash0 = reinterpret_cast<float4*>(fit_lds + fit_lds_stash_offset(ks, ds));
   acc.stash = stash0 + w * (DW / 4) * 64;
-  uint16_t* pend = reinterpret_cast<uint16_t*>(stash0 + W * (DW / 4) * 64) + w * rpw;
+  uint16_t* pend = reinterpret_cast<uint16_t*>(stash0 + W * (DW / 4) * 64);   // W rpw entries
+  int* dyn = reinterpret_cast<int*>(pend + W * rpw + (W * rpw & 1));
   for (int i = threadIdx.x; i < ks * stride; i += blockDim.x) acc.S[i] = 0.0;
   for (int i = threadIdx.x; i < ks; i += blockDim.x) acc.cnt[i] = 0u;
+  if (threadIdx.x < 2) dyn[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t rb = ((int64_t)chunk * W + w) * rpw;
-  const int64_t re = min(n, rb + rpw);
-  uint32_t nres = 0;
-  if (rb < re) {
+  // the block's rows, claimed 64 at a time by its waves
+  const int64_t rb = (int64_t)chunk * W * rpw;
+  const int64_t re = min(n, rb + (int64_t)W * rpw);
+  const float* cbsub = c32 + (int64_t)sub * ks * ds;
+  if (rb < re) {   // block-uniform
     SubOps<NB, NT> o;
     load_sub_ops<NB, NT>(o, aop, cmax, mu, sub, lane);
     const Band bd{e_cross, e_norm, g_exact};
-    nres = (uint32_t)assign_rows64<NB, NT, FULL, false, true, true>(o, bd, x, d, ds, m, ks, sub, rb, re,
-                                                                    c32 + (int64_t)sub * ks * ds, codes, pend,
-                                                                    lane, nullptr, nullptr, acc);
+    const int total = assign_rows64<NB, NT, FULL, false, true, true, true>(o, bd, x, d, ds, m, ks, sub, rb, re, cbsub,
+                                                                           codes, pend, lane, nullptr, nullptr, acc,
+                                                                           dyn);
+    if (rescored && threadIdx.x == 0 && total) atomicAdd(rescored, (unsigned long long)total);
   }
-  if (rescored && lane == 0 && nres) atomicAdd(rescored, (unsigned long long)nres);
   __syncthreads();
   const int per = ks * ds;
   const size_t base = (size_t)chunk * m + sub;
@@ -1322,7 +1364,8 @@ constexpr size_t kFitLdsMax = 65536;
 size_t fit_lds_bytes(int ks, int ds, int rpw) {
   const int nb = ds <= 8 ? 1 : 2;
   const int w = fit_waves(nb);
-  return fit_lds_stash_offset(ks, ds) + (size_t)w * 64 * nb * 8 * sizeof(float) + (size_t)w * rpw * sizeof(uint16_t);
+  return fit_lds_stash_offset(ks, ds) + (size_t)w * 64 * nb * 8 * sizeof(float) +
+         (((size_t)w * rpw * sizeof(uint16_t) + 3) & ~size_t(3)) + 2 * sizeof(int);
 }
 }  // namespace
 
