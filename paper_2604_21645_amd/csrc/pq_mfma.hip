@@ -1276,7 +1276,13 @@ Bf16Geom bf16_geometry(int64_t n, int m, int max_tiles) {
     cus = 256;
   const int64_t resident = 3 * (int64_t)cus;
   const int64_t row_tiles = (n + 31) / 32;
-  int64_t tpb = (row_tiles * g.groups + resident - 1) / resident;
+  // beyond max_tiles per block: as many rounds as needed, the tiles spread
+  // evenly over them (a last round nearly as full as the others, rather than
+  // a few max_tiles blocks running alone at the end)
+  const int64_t work = row_tiles * g.groups;
+  int64_t rounds = (work + resident * max_tiles - 1) / (resident * max_tiles);
+  if (rounds < 1) rounds = 1;
+  int64_t tpb = (work + resident * rounds - 1) / (resident * rounds);
   if (tpb < 1) tpb = 1;
   if (tpb > max_tiles) tpb = max_tiles;
   tpb = (tpb + 1) & ~int64_t(1);   // whole 64-row steps
