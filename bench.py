@@ -736,10 +736,11 @@ def bench_diff(args) -> dict:
     torch.cuda.synchronize()
 
     def step():
+        # the encode's fused error is the loss's forward (no second pass over the rows)
         xr.grad = None
         cb.grad = None
-        codes = mipq.pq_encode(xr.detach(), cb.detach(), "bf16")
-        loss = mipq.PQReconLoss.apply(xr, cb, codes)
+        enc = mipq.pq_encode_ex(xr.detach(), cb.detach(), "bf16", sse_rmse=True)
+        loss = mipq.PQReconLoss.apply(xr, cb, enc["codes"], enc["sse_rmse"])
         loss.backward()
         return loss
 
@@ -777,8 +778,8 @@ def bench_diff(args) -> dict:
     rec = base_record("Reconstruction-loss forward+backward vectors/s (BF16 encode, fixed codes)", n / (ms * 1e-3),
                       "vectors/s", args.steps, args.warmup, ms, "bf16",
                       {"workload": "diff_codebooks: 2M x 256 rows (8,192-component mixture), M=32, Ks=256 codebooks "
-                                   "fitted once (20 rounds on 200k rows); step = BF16 encode of all rows + float64 "
-                                   "loss + dL/dx and dL/dC",
+                                   "fitted once (20 rounds on 200k rows); step = BF16 encode of all rows with its fused "
+                                   "float64 error (the loss) + dL/dx and dL/dC",
                        "n": n, "d": d, "m": w.m, "ks": w.ks, "precision": "bf16 encode, float64 loss/sums",
                        "parallelism": "single GPU"})
     rec.update({

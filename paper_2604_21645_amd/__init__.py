@@ -214,22 +214,31 @@ class PQReconLoss(torch.autograd.Function):
     fixed; differentiable in x and codebook (float64 loss, float32 gradients).
 
         loss = PQReconLoss.apply(x, codebook, codes)
+        loss = PQReconLoss.apply(x, codebook, codes, sse)
+
+    sse (optional): a float64 device tensor whose first entry is already that
+    sum, as the encode of the same x against the same codebook writes it
+    (``pq_encode_ex(x, codebook, sse_rmse=True)["sse_rmse"]``, its fused
+    error); the forward then returns it instead of decoding the rows again.
     """
 
     @staticmethod
-    def forward(ctx, x, codebook, codes):
-        _, sr = pq_decode_rmse(codes, codebook, x)
+    def forward(ctx, x, codebook, codes, sse=None):
+        if sse is None:
+            _, sse = pq_decode_rmse(codes, codebook, x)
+        elif sse.dtype != torch.float64 or sse.device != x.device or sse.numel() < 1:
+            raise ValueError("sse must be a float64 tensor on the rows' device")
         ctx.save_for_backward(x, codebook, codes)
-        return sr[0].reshape(())
+        return sse[0].clone().reshape(())
 
     @staticmethod
     def backward(ctx, g):
         x, codebook, codes = ctx.saved_tensors
         need_x, need_c = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         if not (need_x or need_c):
-            return None, None, None
+            return None, None, None, None
         _, gx, gc = recon_backward(x, codebook, codes, grad_out=g, grad_x=need_x, grad_codebook=need_c)
-        return gx, gc, None
+        return gx, gc, None, None
 
 
 def coarse_assign(x: torch.Tensor, coarse: torch.Tensor, precision="bf16", rescored: bool = False):

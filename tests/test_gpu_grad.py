@@ -66,6 +66,26 @@ def test_autograd_function_and_upstream_scaling():
     assert loss.item() == pytest.approx(ref, rel=1e-12)
 
 
+def test_loss_from_the_encodes_fused_error():
+    # the encode's fused error as the forward: the same loss (float64 sums in
+    # another order) and the same gradients
+    x, cb, _ = _setup(n=20011, d=256, m=32, ks=256, seed=8)
+    r = mipq.pq_encode_ex(_t(x), _t(cb), "bf16", sse_rmse=True)
+    codes = r["codes"]
+    xt = _t(x).requires_grad_(True)
+    ct = _t(cb).requires_grad_(True)
+    loss = mipq.PQReconLoss.apply(xt, ct, codes, r["sse_rmse"])
+    loss.backward()
+    x2 = _t(x).requires_grad_(True)
+    c2 = _t(cb).requires_grad_(True)
+    ref = mipq.PQReconLoss.apply(x2, c2, codes)
+    ref.backward()
+    assert loss.item() == pytest.approx(ref.item(), rel=1e-12)
+    assert torch.equal(xt.grad, x2.grad) and torch.equal(ct.grad, c2.grad)
+    lref, _, _ = ograd.grads(x, codes.cpu().numpy().astype(np.int64), cb.astype(np.float64))
+    assert loss.item() == pytest.approx(lref, rel=1e-12)
+
+
 def test_central_finite_differences_on_1000_entries():
     x, cb, codes = _setup(n=20011, d=256, m=32, ks=256, seed=6)
     xt, ct = _t(x), _t(cb)
