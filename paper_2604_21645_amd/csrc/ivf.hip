@@ -173,8 +173,14 @@ __global__ __launch_bounds__(kT) void k_coarse_update(const float* __restrict__ 
   double jl = 0.0;
   constexpr int kU = 32;
   const int lane = threadIdx.x & 63;
-  for (int t = threadIdx.x; t < d; t += blockDim.x) {
-    const float cold = cc[(int64_t)l * d + t];
+  // every lane runs every pass (the ids are read back from lanes 0 .. kU - 1,
+  // which must all have loaded them); lanes past d load dimension d - 1 and
+  // keep nothing
+  for (int t0 = 0; t0 < d; t0 += blockDim.x) {
+    const int t = t0 + (int)threadIdx.x;
+    const bool act = t < d;
+    const int tc = act ? t : d - 1;
+    const float cold = cc[(int64_t)l * d + tc];
     double s = 0.0;
     for (int64_t p0 = a; p0 < b; p0 += kU) {
       const int cnt = b - p0 < kU ? (int)(b - p0) : kU;
@@ -184,18 +190,18 @@ __global__ __launch_bounds__(kT) void k_coarse_update(const float* __restrict__ 
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int r = __builtin_amdgcn_readlane(myid, u < cnt ? u : cnt - 1);
-        xv[u] = x[(int64_t)r * d + t];   // all kU loads in flight
+        xv[u] = x[(int64_t)r * d + tc];   // all kU loads in flight
       }
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
-        if (u < cnt) {
+        if (act && u < cnt) {
           s += (double)xv[u];
           const double df = (double)xv[u] - (double)cold;
           jl += df * df;
         }
       }
     }
-    if (b > a) {
+    if (act && b > a) {
       const double v = s / (double)(b - a);
       cc64[(int64_t)l * d + t] = v;
       cc[(int64_t)l * d + t] = (float)v;

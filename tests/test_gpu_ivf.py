@@ -87,6 +87,21 @@ def test_index_build_matches_oracle(prec):
     assert np.all(np.diff(obj) <= 1e-9 * obj[:-1])
 
 
+@pytest.mark.parametrize("n", [262144, 262145, 300001])
+def test_posting_lists_at_sort_tile_boundaries(n):
+    # the radix sort's tile grows past 256 elements above 262,144 keys (at most
+    # 1,024 blocks): the k-means sample and all rows sorted at such sizes
+    print("posting lists, n =", n, flush=True)
+    w = wl.ivf_adc(seed=23, n=n, d=16, n_comp=64, kc=64, n_query=1, m=4, ks=16, coarse_iters=3, pq_iters=2,
+                   n_train=n)
+    idx = mipq.ii_build(_t(w.x), w.kc, w.coarse_iters, _t(w.coarse_train), _t(w.coarse_init), w.m, w.ks,
+                        w.pq_iters, _t(w.pq_init))
+    ref = ivf.build(w.x, w.coarse_train, w.coarse_init, w.coarse_iters, w.m, w.pq_init, w.pq_iters)
+    np.testing.assert_array_equal(idx["coarse"].cpu().numpy(), ref["coarse"].astype(np.float32))
+    np.testing.assert_array_equal(idx["offsets"].cpu().numpy(), ref["offsets"])
+    np.testing.assert_array_equal(idx["ids"].cpu().numpy().astype(np.int64), ref["ids"])
+
+
 def _gpu_index_np(idx):
     return (idx["coarse"].cpu().numpy(), idx["pq_codebook"].cpu().numpy(), idx["offsets"].cpu().numpy(),
             idx["ids"].cpu().numpy().astype(np.int64))
