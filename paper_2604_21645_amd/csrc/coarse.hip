@@ -702,7 +702,7 @@ __global__ __launch_bounds__(kT, 2) void k_coarse_resolve_mfma(
 constexpr int64_t kResolveMinSpan = 1024;
 // up to this many rows the resolve launch is one pass per block, bound by the
 // latency of the tile loop rather than by throughput: one row group per wave
-// (9 instead of 18 MFMAs in a tile's chain) and spans of at least
+// (S + 1 instead of 2 (S + 1) MFMAs per tile and wave) and spans of at least
 // kResolveMinSpanSmall rows (more, smaller blocks)
 constexpr int64_t kResolveSmallN = int64_t(1) << 20;
 constexpr int64_t kResolveMinSpanSmall = 256;
