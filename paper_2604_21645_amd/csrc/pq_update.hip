@@ -578,6 +578,8 @@ __device__ __forceinline__ void finalize_tile(int t, int sub, int m, int ks, int
   const int per = ks * ds;
   const int k0 = t * 32;
   const int kn = min(32, ks - k0);
+  // the centre, loaded while the partials are summed
+  const float mu_t = threadIdx.x < NB * 8 ? mu[sub * kMaxDsBf16 + threadIdx.x] : 0.0f;
   for (int le = threadIdx.x; le < kn * ds; le += blockDim.x) {
     const int e = k0 * ds + le;
     const int k = e / ds;
@@ -608,7 +610,7 @@ __device__ __forceinline__ void finalize_tile(int t, int sub, int m, int ks, int
     c32[o] = f;
     newc[le] = f;
   }
-  if (threadIdx.x < NB * 8) mus[threadIdx.x] = mu[sub * kMaxDsBf16 + threadIdx.x];
+  if (threadIdx.x < NB * 8) mus[threadIdx.x] = mu_t;
   if (t == 0 && j_out && threadIdx.x < 64) {   // objective: lane-strided chunk sums, then a fixed xor tree
     double js = 0.0;
     for (int cc = threadIdx.x; cc < nch; cc += 64) js += part_j[(size_t)cc * m + sub];
