@@ -209,6 +209,125 @@ __device__ __forceinline__ void accumulate_chunk4(
   }
 }
 
+// As accumulate_chunk4, for G consecutive subspaces sub0 .. sub0 + G - 1 of
+// chunk c in one block, so that a row's G ds floats (G ds / 4 lanes, 16 bytes
+// each) are one contiguous read and one contiguous write: with one subspace
+// per block, the blocks of a chunk each read and write a 32-byte piece of a
+// row's cache lines at different times, and the lines went to and from HBM
+// about 1.5 times.  LDS: per subspace the sums S [ks][ds + 1], counts [ks]
+// and (OBJ) the float32 centroids.  The objective partial of each subspace is
+// reduced in a fixed order (lanes of one subspace by xor steps, then the
+// waves in order), as in accumulate_chunk4.
+template <bool GX, bool OBJ, bool CHECK, int G>
+__device__ __forceinline__ void accumulate_group4(
+    const float* __restrict__ x, int64_t n, int d, int m, int ks, int ds,
+    const uint8_t* __restrict__ codes, const float* __restrict__ c32, int64_t rpc, int c, int sub0,
+    double* __restrict__ part_s, uint32_t* __restrict__ part_cnt, double* __restrict__ part_j,
+    const double* __restrict__ gscale, float* __restrict__ grad_x, double* smem, double* redj) {
+  const int stride = ds + 1;
+  const int per = ks * ds;
+  double* S0 = smem;                                                          // [G][ks * stride]
+  uint32_t* cnt0 = reinterpret_cast<uint32_t*>(S0 + (size_t)G * ks * stride);   // [G][ks]
+  float* cbs0 = reinterpret_cast<float*>(cnt0 + (size_t)G * ks);               // [G][per]
+  for (int i = threadIdx.x; i < G * ks * stride; i += blockDim.x) S0[i] = 0.0;
+  for (int i = threadIdx.x; i < G * ks; i += blockDim.x) cnt0[i] = 0u;
+  if (OBJ)
+    for (int i = threadIdx.x; i < G * per; i += blockDim.x) cbs0[i] = c32[(int64_t)sub0 * per + i];
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int lps = ds >> 2;                 // lanes per subspace slice
+  const int lpr = G * lps;                 // lanes per row (a power of two <= 64)
+  const int rpw = 64 / lpr;                // rows per wave step
+  const int g = lane / lpr, li = lane - g * lpr;
+  const int j = li / lps, t = (li - j * lps) * 4;
+  double* S = S0 + (size_t)j * ks * stride;
+  uint32_t* cnt = cnt0 + (size_t)j * ks;
+  const float* cbs = cbs0 + (size_t)j * per;
+  const int64_t r0 = (int64_t)c * rpc;
+  const int64_t r1 = min(n, r0 + rpc);
+  const int64_t step = (int64_t)(blockDim.x >> 6) * rpw;
+  const int64_t first = r0 + (int64_t)wave * rpw + g;
+  const int64_t nrows = first < r1 ? (r1 - first + step - 1) / step : 0;
+  const float* xp = x + first * d + (int64_t)sub0 * ds + li * 4;
+  const uint8_t* cp = codes + first * m + sub0 + j;
+  float* gp = GX ? grad_x + first * d + (int64_t)sub0 * ds + li * 4 : nullptr;
+  const int64_t xs = step * d, cs = step * m;
+  double jl = 0.0;
+  const double g2 = GX ? 2.0 * (gscale ? *gscale : 1.0) : 0.0;
+  auto add_row = [&](int code, const float4& v, int64_t off) {
+    const float xv[4] = {v.x, v.y, v.z, v.w};
+    if (CHECK && code >= ks) {
+      jl += NAN;
+      if (GX) *reinterpret_cast<float4*>(gp + off) = make_float4(NAN, NAN, NAN, NAN);
+      return;
+    }
+    if (OBJ) {
+      float gv[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double df = (double)xv[e] - (double)cbs[code * ds + t + e];
+        jl += df * df;
+        gv[e] = (float)(g2 * df);
+      }
+      if (GX) *reinterpret_cast<float4*>(gp + off) = make_float4(gv[0], gv[1], gv[2], gv[3]);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) atomicAdd(&S[code * stride + t + e], (double)xv[e]);
+    if (t == 0) atomicAdd(&cnt[code], 1u);
+  };
+  constexpr int U = 6;   // rows in flight per lane (8 spills at 1024 threads)
+  int64_t i = 0;
+  for (; i + U <= nrows; i += U) {
+    int code[U];
+    float4 xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      code[u] = (int)cp[u * cs];
+      xv[u] = *reinterpret_cast<const float4*>(xp + u * xs);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) add_row(code[u], xv[u], u * xs);
+    xp += U * xs;
+    cp += U * cs;
+    if (GX) gp += U * xs;
+  }
+  for (; i < nrows; ++i) {
+    add_row((int)cp[0], *reinterpret_cast<const float4*>(xp), 0);
+    xp += xs;
+    cp += cs;
+    if (GX) gp += xs;
+  }
+  // the lanes of subspace j differ in their row (bits at and above lpr) and
+  // their slice (bits below lps): xor steps over those bits only
+  for (int off = 1; off < lps; off <<= 1) jl += __shfl_xor(jl, off, 64);
+  for (int off = lpr; off < 64; off <<= 1) jl += __shfl_xor(jl, off, 64);
+  if (g == 0 && t == 0) redj[wave * G + j] = jl;
+  __syncthreads();
+  const size_t base = (size_t)c * m + sub0;
+  for (int i2 = threadIdx.x; i2 < G * per; i2 += blockDim.x) {
+    const int jj = i2 / per, r = i2 - jj * per;
+    const int k = r / ds;
+    part_s[(base + jj) * per + r] = S0[(size_t)jj * ks * stride + k * stride + (r - k * ds)];
+  }
+  for (int i2 = threadIdx.x; i2 < G * ks; i2 += blockDim.x) {
+    const int jj = i2 / ks;
+    part_cnt[(base + jj) * ks + (i2 - jj * ks)] = cnt0[i2];
+  }
+  if (threadIdx.x < G) {
+    double js = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) js += redj[w * G + threadIdx.x];
+    part_j[base + threadIdx.x] = js;
+  }
+}
+
+// LDS of accumulate_group4 for G subspaces (OBJ: with the float32 centroids)
+__host__ __device__ constexpr size_t group4_lds_bytes(int ks, int ds, int G) {
+  return (size_t)G * ks * (ds + 1) * sizeof(double) + (size_t)G * ks * sizeof(uint32_t) +
+         (size_t)G * ks * ds * sizeof(float);
+}
+
 // rows of x can be read 16 bytes at a time in every subspace
 __host__ __device__ __forceinline__ bool rows_vec4(const float* x, int d, int ds) {
   return ds % 4 == 0 && d % 4 == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
@@ -465,6 +584,23 @@ __device__ __forceinline__ int find_problem(const BatchProb* __restrict__ probs,
 // Many problems: block i is accumulation item i = (problem p, chunk c,
 // subspace j) with items problem-major, then chunk, then subspace; problem p's
 // partials use the single-problem layout at offset item0.
+// The reconstruction-loss backward with G consecutive subspaces per block
+// (accumulate_group4): block -> (chunk, group of G) as chunk_map does for
+// single subspaces.
+template <bool GX, int G>
+__global__ __launch_bounds__(kBwdThreads) void k_backward_group(
+    const float* __restrict__ x, int64_t n, int d, int m, int ks, int ds, const uint8_t* __restrict__ codes,
+    const float* __restrict__ c32, int64_t rpc, int nch, double* __restrict__ part_s,
+    uint32_t* __restrict__ part_cnt, double* __restrict__ part_j, const double* __restrict__ gscale,
+    float* __restrict__ grad_x) {
+  extern __shared__ double smem[];
+  __shared__ double redj[kBwdThreads / 64 * G];
+  const ChunkMap cm = chunk_map(blockIdx.x, m / G);
+  if (cm.chunk >= nch) return;   // padding of the grid
+  accumulate_group4<GX, true, true, G>(x, n, d, m, ks, ds, codes, c32, rpc, (int)cm.chunk, cm.sub * G, part_s,
+                                       part_cnt, part_j, gscale, grad_x, smem, redj);
+}
+
 template <bool DET, int NT>
 __global__ __launch_bounds__(NT) void k_accumulate_batched(const BatchProb* __restrict__ probs, int nprob,
                                                            int64_t items, int d, int m, int ks, int ds,
@@ -835,7 +971,38 @@ int launch_backward(const float* x, int64_t n, int d, int m, int ks, const uint8
                     double* part_s, uint32_t* part_cnt, double* part_j, double* loss_sub, hipStream_t s) {
   const int ds = d / m;
   const int64_t rpc = (n + nch - 1) / nch;
-  {
+  // several subspaces per block when a row's slices of them are whole
+  // 16-byte pieces and their LDS fits a block
+  int G = 1;
+  if (ds % 4 == 0 && rows_vec4(x, d, ds) && (!grad_x || rows_vec4(grad_x, d, ds))) {
+    int dev = 0, lds_max = 65536;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      lds_max = 65536;
+    for (int g = 4; g >= 2; g >>= 1)
+      if (m % g == 0 && (g * ds / 4) <= 64 && group4_lds_bytes(ks, ds, g) <= (size_t)lds_max) {
+        G = g;
+        break;
+      }
+  }
+  if (G > 1) {
+    const unsigned grid = (unsigned)(((nch + 7) / 8) * 8 * (m / G));
+    const size_t shm = group4_lds_bytes(ks, ds, G);
+    ProfScope ps(MIPQ_K_BACKWARD, s);
+#define BG(GV)                                                                                                 \
+  do {                                                                                                         \
+    if (grad_x)                                                                                                \
+      k_backward_group<true, GV><<<grid, kBwdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, nch,        \
+                                                              part_s, part_cnt, part_j, gscale, grad_x);       \
+    else                                                                                                       \
+      k_backward_group<false, GV><<<grid, kBwdThreads, shm, s>>>(x, n, d, m, ks, ds, codes, c32, rpc, nch,       \
+                                                               part_s, part_cnt, part_j, nullptr, nullptr);    \
+  } while (0)
+    if (G == 4) BG(4);
+    else BG(2);
+#undef BG
+    MIPQ_LAUNCHED("k_backward_group");
+  } else {
     const size_t shm = (size_t)ks * (ds + 1) * sizeof(double) + ((ks + 1) / 2) * sizeof(double) +
                        (size_t)ks * ds * sizeof(float);
     const unsigned grid = (unsigned)(((nch + 7) / 8) * 8 * m);
