@@ -100,6 +100,55 @@ def test_integer_rows_equal_single_calls_bit_for_bit(mode):
     b.close()
 
 
+@pytest.mark.parametrize("mode", ["eager", "graph"])
+@pytest.mark.parametrize("d,m,ks", [(96, 12, 256), (48, 6, 100)])
+def test_plans_without_objective_equal_single_calls(mode, d, m, ks):
+    """Plans that return no objective (the benchmarked form): on integer
+    rows the codebooks, codes and errors equal the single calls, which fuse
+    the accumulation into the assignment, bit for bit (float64 sums of
+    integers are exact in any order)."""
+    iters = 4
+    xs, inits = _problems([ks, 4097, 20011, 333, 9000], d, m, ks, "integer", seed=35)
+    xt = [_t(x) for x in xs]
+    it = [_t(i) for i in inits]
+    print("no objective", mode, d, m, ks, flush=True)
+    b = mipq.BatchedFit(xt, it, m, ks, iters, plan=mode == "graph", autotune=False, graph=mode == "graph",
+                        objective=False)
+    b.run()
+    torch.cuda.synchronize()
+    for i, (x, init) in enumerate(zip(xs, inits)):
+        cb, codes, sr, _ = _single(x, init, m, ks, iters)
+        r = b.results[i]
+        assert "objective" not in r
+        assert torch.equal(r["codebook"], cb), i
+        assert torch.equal(r["codes"], codes), i
+        assert torch.equal(r["sse_rmse"], sr), i
+    b.close()
+
+
+def test_plans_without_objective_match_the_oracle_on_real_rows():
+    """Real-valued rows, plans without objectives: codes in lockstep with
+    the oracle's fp32-decision encode on the batched codebooks (sampled), and
+    codebooks equal to a plan with objectives up to float64 summation order."""
+    d, m, ks, iters = 96, 12, 256, 5
+    xs, inits = _problems([3001, 40000, 777], d, m, ks, "sphere", seed=36)
+    xt = [_t(x) for x in xs]
+    it = [_t(i) for i in inits]
+    a = mipq.BatchedFit(xt, it, m, ks, iters, plan=True, autotune=False, graph=True, objective=False)
+    a.run()
+    c = mipq.BatchedFit(xt, it, m, ks, iters, plan=True, autotune=False, graph=True, objective=True)
+    c.run()
+    torch.cuda.synchronize()
+    for i, x in enumerate(xs):
+        ra, rc = a.results[i], c.results[i]
+        np.testing.assert_allclose(ra["codebook"].cpu().numpy(), rc["codebook"].cpu().numpy(), rtol=1e-5, atol=1e-6)
+        rows = np.random.default_rng(i).choice(x.shape[0], min(500, x.shape[0]), replace=False)
+        ref, _ = pq.encode(x[rows], ra["codebook"].cpu().numpy().astype(np.float64), decide="fp32")
+        np.testing.assert_array_equal(ra["codes"].cpu().numpy()[rows].astype(np.int64), ref)
+    a.close()
+    c.close()
+
+
 def test_integer_rows_match_the_oracle():
     m, ks, iters, d = 12, 64, 4, 96
     xs, inits = _problems([64, 700, 2001], d, m, ks, "integer", seed=32)
