@@ -17,6 +17,7 @@
 #include <sys/stat.h>
 #include <unistd.h>
 
+#include <algorithm>
 #include <map>
 #include <string>
 #include <vector>
@@ -32,6 +33,7 @@ struct mipq_plan {
   int variant = 0;     // its register/occupancy variant
   int resident = 0;    // resident blocks of that variant on this device
   bool cached = false; // the choice came from the tuning cache
+  bool fused = false;  // rounds run as one fused launch (its chunk layout)
   std::vector<int64_t> tried;   // (grid, variant, nanoseconds) per timed candidate
   hipGraphExec_t g_setup = nullptr, g_round = nullptr, g_final = nullptr;
 };
@@ -58,6 +60,7 @@ struct BatchLayout {
   double* part_j = nullptr;
   double* j_all = nullptr;
   double* dpart = nullptr;
+  float* tmax = nullptr;        // per-tile norm bounds of the finalize
   int64_t units = 0, items = 0, dblocks = 0;
   size_t bytes = 0;
 };
@@ -65,14 +68,14 @@ struct BatchLayout {
 // Work-list offsets of every problem (table may be NULL) and the workspace
 // carving; the same code sizes and fills.
 BatchLayout carve_batch(void* ws, const int64_t* n, int nprob, int d, int m, int ks, int iters,
-                        std::vector<BatchProb>* table, const mipq_problem* probs) {
+                        std::vector<BatchProb>* table, const mipq_problem* probs, bool fused) {
   BatchLayout L;
   const int ds = d / m;
   const int groups = ceil_div(m, 4);
   if (table) table->resize(nprob);
   for (int p = 0; p < nprob; ++p) {
     const int64_t np = n[p];
-    const int nch = update_chunks(np, m);
+    const int nch = fused ? fused_chunks(np) : update_chunks(np, m);
     const int nblk = decode_blocks(np, m);
     if (table) {
       BatchProb& b = (*table)[p];
@@ -109,6 +112,7 @@ BatchLayout carve_batch(void* ws, const int64_t* n, int nprob, int d, int m, int
   L.part_j = c.take<double>((size_t)L.items);
   L.j_all = c.take<double>((size_t)(iters > 0 ? iters : 1) * nprob * m);
   L.dpart = c.take<double>((size_t)L.dblocks);
+  L.tmax = c.take<float>((size_t)nprob * m * kMaxTiles);
   L.bytes = c.bytes();
   return L;
 }
@@ -134,7 +138,7 @@ int check_problems(const mipq_problem* probs, int nprob, int m) {
     if (!q.x || !q.init_rows || !q.codebook || !q.codes)
       return fail(MIPQ_EINVAL, "problem %d: x, init_rows, codebook and codes are required", p);
     units += (q.n + 31) / 32;
-    blocks += update_chunks(q.n, m) * (int64_t)m;
+    blocks += std::max(update_chunks(q.n, m), fused_chunks(q.n)) * (int64_t)m;
   }
   if (units * ceil_div(m, 4) >= (1ll << 40) || blocks >= (1ll << 31))
     return fail(MIPQ_EUNSUPPORTED, "batched work list too long");
@@ -154,13 +158,15 @@ struct BatchRun {
   int grid;
   bool det = false;   // MIPQ_PLAN_DETERMINISTIC
   int variant = 0;    // register/occupancy variant of the assignment
+  bool obj = false;   // some problem returns its objective
+  int fused_rpw = 0;  // > 0: rounds fuse the accumulation into the assignment
 };
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 BatchRun make_run(const BatchLayout& L, const mipq_problem* probs, int nprob, int d, int m, int ks, int iters,
-                  int grid) {
-  BatchRun r{L, nprob, d, m, ks, iters, true, true, grid, false, 0};
+                  int grid, bool fused) {
+  BatchRun r{L, nprob, d, m, ks, iters, true, true, grid, false, 0, false, 0};
   const int ds = d / m;
   const int nb = (ds + 7) / 8;
   r.full = (ds == nb * 8) && (d % 4 == 0);
@@ -168,8 +174,20 @@ BatchRun make_run(const BatchLayout& L, const mipq_problem* probs, int nprob, in
   for (int p = 0; p < nprob; ++p) {
     r.full = r.full && aligned16(probs[p].x);
     r.vec = r.vec && aligned16(probs[p].x) && aligned16(probs[p].codebook);
+    r.obj = r.obj || probs[p].objective != nullptr;
   }
+  r.fused_rpw = fused ? fit_round_batched_rpw(ks, ds, kFusedChunkRows) : 0;
   return r;
+}
+
+// Rounds fuse the accumulation into the assignment (chunks of fused_chunks
+// rows) when no problem returns its objective, the sums need not be
+// deterministic and a chunk's pending list fits a block's LDS.
+bool batch_fused(const mipq_problem* probs, int nprob, int d, int m, int ks, bool det) {
+  if (det) return false;
+  for (int p = 0; p < nprob; ++p)
+    if (probs[p].objective) return false;
+  return fit_round_batched_rpw(ks, d / m, kFusedChunkRows) > 0;
 }
 
 // starting codebooks, round counter, operands of round 0
@@ -181,15 +199,22 @@ int run_setup(const BatchRun& r, hipStream_t s) {
   return launch_pack_bf16_batched(L.probs, r.nprob, r.m, r.ks, r.d / r.m, L.aop, L.aop_stride, L.cmax, L.mu, s);
 }
 
-// one Lloyd round of every problem: assign, accumulate, finalise (+ pack)
+// one Lloyd round of every problem: assign, accumulate (one fused launch
+// when the plan allows it), finalise (+ pack)
 int run_round(const BatchRun& r, hipStream_t s) {
   int rc;
   const BatchLayout& L = r.L;
-  if ((rc = launch_assign_bf16_batched(L.probs, r.nprob, L.units, r.d, r.m, r.ks, L.aop, L.aop_stride, L.cmax, L.mu,
-                                       r.full, r.variant, r.grid, nullptr, s)))
-    return rc;
+  const bool fused = r.fused_rpw > 0;
+  if (fused)
+    rc = launch_fit_round_bf16_batched(L.probs, r.nprob, L.items, r.d, r.m, r.ks, L.aop, L.aop_stride, L.cmax, L.mu,
+                                       r.full && r.vec, r.fused_rpw, L.part_s, L.part_cnt, L.part_j, s);
+  else
+    rc = launch_assign_bf16_batched(L.probs, r.nprob, L.units, r.d, r.m, r.ks, L.aop, L.aop_stride, L.cmax, L.mu,
+                                    r.full, r.variant, r.grid, nullptr, s);
+  if (rc) return rc;
   return launch_update_batched(L.probs, r.nprob, L.items, r.d, r.m, r.ks, L.c64, L.part_s, L.part_cnt, L.part_j,
-                               L.j_all, L.round, r.iters, L.aop, L.aop_stride, L.cmax, L.mu, r.det, s);
+                               L.j_all, L.round, r.iters, L.aop, L.aop_stride, L.cmax, L.mu, r.det, !fused, L.tmax,
+                               s);
 }
 
 // encode with the final codebooks, reconstruction errors, objectives
@@ -378,7 +403,9 @@ size_t mipq_pq_fit_batched_workspace_size(const int64_t* n, int nprob, int d, in
   if (!n || check_batch_shape(nprob, d, m, ks, iters, precision) != MIPQ_OK) return 0;
   for (int p = 0; p < nprob; ++p)
     if (n[p] < 1) return 0;
-  return carve_batch(nullptr, n, nprob, d, m, ks, iters, nullptr, nullptr).bytes;
+  // either chunk layout (fused rounds or not), whichever the plan takes
+  return std::max(carve_batch(nullptr, n, nprob, d, m, ks, iters, nullptr, nullptr, false).bytes,
+                  carve_batch(nullptr, n, nprob, d, m, ks, iters, nullptr, nullptr, true).bytes);
 }
 
 int mipq_plan_create(mipq_plan** out, const mipq_problem* probs, int nprob, int d, int m, int ks, int iters,
@@ -393,12 +420,14 @@ int mipq_plan_create(mipq_plan** out, const mipq_problem* probs, int nprob, int 
   hipStream_t s = static_cast<hipStream_t>(stream);
   const std::vector<int64_t> n = sizes_of(probs, nprob);
   std::vector<BatchProb> table;
-  const BatchLayout L = carve_batch(ws, n.data(), nprob, d, m, ks, iters, &table, probs);
+  const bool fused = batch_fused(probs, nprob, d, m, ks, (flags & MIPQ_PLAN_DETERMINISTIC) != 0);
+  const BatchLayout L = carve_batch(ws, n.data(), nprob, d, m, ks, iters, &table, probs, fused);
   if (!ws) return fail(MIPQ_EINVAL, "workspace pointer is NULL (%zu bytes needed)", L.bytes);
   if (ws_bytes < L.bytes) return fail(MIPQ_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, L.bytes);
   if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(MIPQ_EINVAL, "workspace must be 256-byte aligned");
 
   mipq_plan* plan = new mipq_plan;
+  plan->fused = fused;
   plan->probs.assign(probs, probs + nprob);
   plan->d = d;
   plan->m = m;
@@ -408,7 +437,7 @@ int mipq_plan_create(mipq_plan** out, const mipq_problem* probs, int nprob, int 
   plan->flags = flags;
   plan->ws = ws;
   plan->ws_bytes = ws_bytes;
-  BatchRun r = make_run(L, probs, nprob, d, m, ks, iters, 8);
+  BatchRun r = make_run(L, probs, nprob, d, m, ks, iters, 8, fused);
   r.det = (flags & MIPQ_PLAN_DETERMINISTIC) != 0;
   auto bail = [&](int code) {
     destroy_graphs(plan);
@@ -540,7 +569,8 @@ int mipq_pq_fit_batched(const mipq_problem* probs, int nprob, int d, int m, int 
     if (plan->ws != ws || plan->ws_bytes > ws_bytes) return fail(MIPQ_EINVAL, "the plan was made for another workspace");
   }
   std::vector<BatchProb> table;
-  const BatchLayout L = carve_batch(ws, n.data(), nprob, d, m, ks, iters, plan ? nullptr : &table, probs);
+  const bool fused = plan ? plan->fused : batch_fused(probs, nprob, d, m, ks, false);
+  const BatchLayout L = carve_batch(ws, n.data(), nprob, d, m, ks, iters, plan ? nullptr : &table, probs, fused);
   if (!ws) return fail(MIPQ_EINVAL, "workspace pointer is NULL (%zu bytes needed)", L.bytes);
   if (ws_bytes < L.bytes) return fail(MIPQ_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, L.bytes);
   if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(MIPQ_EINVAL, "workspace must be 256-byte aligned");
@@ -557,12 +587,12 @@ int mipq_pq_fit_batched(const mipq_problem* probs, int nprob, int d, int m, int 
       if ((rc = upload_table(L, table, s))) return rc;
       const int ds = d / m;
       int resident = 0;
-      if ((rc = assign_bf16_batched_resident(ds, ks, make_run(L, probs, nprob, d, m, ks, iters, 8).full, 0,
+      if ((rc = assign_bf16_batched_resident(ds, ks, make_run(L, probs, nprob, d, m, ks, iters, 8, fused).full, 0,
                                              &resident)))
         return rc;
       grid = 2 * (((resident > 8 ? resident : 8) + 7) / 8 * 8);
     }
-    BatchRun r = make_run(L, probs, nprob, d, m, ks, iters, grid);
+    BatchRun r = make_run(L, probs, nprob, d, m, ks, iters, grid, fused);
     r.det = plan && (plan->flags & MIPQ_PLAN_DETERMINISTIC);
     r.variant = variant;
     if ((rc = run_setup(r, s))) return rc;

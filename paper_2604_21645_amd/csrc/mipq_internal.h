@@ -90,6 +90,7 @@ constexpr int kBatchPend = 512;   // pending exact re-decisions per wave (LDS)
 __host__ __device__ constexpr int bf16_nmfma(int nb) { return nb + (nb + 1) / 2 + ((nb % 2 == 0) ? 1 : 0); }
 inline int ceil_div(int64_t a, int64_t b) { return int((a + b - 1) / b); }
 inline int tiles_for(int ks) { return ks <= 32 ? 1 : ks <= 64 ? 2 : ks <= 128 ? 4 : 8; }
+constexpr int kMaxTiles = 8;   // tiles_for(kMaxKs)
 
 // ---- launchers (each returns MIPQ_OK or an error code) ---------------------
 int launch_zero_u32(uint32_t* p, size_t count, hipStream_t s);
@@ -102,6 +103,10 @@ int launch_assign_fp32(const float* x, int64_t n, int d, int m, int ks, const fl
                        uint8_t* codes, hipStream_t s);
 // Lloyd update of one round; aop == NULL: plain path (no operand packing)
 int update_chunks(int64_t n, int m);
+// chunks of a problem in the fused batched round: at most kFusedChunkRows rows
+// each, so that a chunk's pending list fits its block's LDS
+constexpr int64_t kFusedChunkRows = 8192;
+inline int fused_chunks(int64_t n) { return n < 1 ? 1 : (int)((n + kFusedChunkRows - 1) / kFusedChunkRows); }
 // objective: also the float64 objective terms of the round (else part_j holds zeros)
 // det: float64 sums in a fixed order (no atomic additions; MIPQ_DETERMINISTIC)
 int launch_update(const float* x, int64_t n, int d, int m, int ks, const uint8_t* codes, float* c32,
@@ -204,11 +209,24 @@ int assign_bf16_batched_resident(int ds, int ks, bool full, int variant, int* re
 int launch_assign_bf16_batched(const BatchProb* probs, int nprob, int64_t units, int d, int m, int ks,
                                const void* aop, size_t aop_stride, const float* cmax, const float* mu, bool full,
                                int variant, int grid, int64_t* rescored, hipStream_t s);
-// one Lloyd update of every problem, then advances *round
+// one Lloyd update of every problem (accumulate: form the partials, which a
+// fused round has already formed otherwise), then the next round's norm
+// bounds cmax from the tiles' bounds tmax (nprob m kMaxTiles floats) and
+// *round advanced
 int launch_update_batched(const BatchProb* probs, int nprob, int64_t items, int d, int m, int ks, double* c64,
                           double* part_s, uint32_t* part_cnt, double* part_j, double* j_all,
                           const uint32_t* round, int iters, void* aop, size_t aop_stride, float* cmax, float* mu,
-                          bool det, hipStream_t s);
+                          bool det, bool accumulate, float* tmax, hipStream_t s);
+// rows per wave of the fused batched round's pending lists for chunks of at
+// most max_rpc rows, 0 when they do not fit a block's LDS (or 16-bit offsets)
+// or d/m is out of the matrix-core path's range
+int fit_round_batched_rpw(int ks, int ds, int64_t max_rpc);
+// one Lloyd round's assignment and partial sums of every problem (the items
+// and partial layout of launch_update_batched, chunks of fused_chunks rows),
+// for plans without objectives
+int launch_fit_round_bf16_batched(const BatchProb* probs, int nprob, int64_t items, int d, int m, int ks,
+                                  const void* aop, size_t aop_stride, const float* cmax, const float* mu, bool full,
+                                  int rpw, double* part_s, uint32_t* part_cnt, double* part_j, hipStream_t s);
 int launch_decode_sse_batched(const BatchProb* probs, int nprob, int64_t blocks, int d, int m, int ks, bool vec,
                               double* partials, hipStream_t s);
 int launch_objective_batched(const BatchProb* probs, int nprob, int iters, int m, const double* j_all,

@@ -900,6 +900,75 @@ k_fit_round_bf16(const float* __restrict__ x, int64_t n, int d, int m, int ks, i
   for (int i = threadIdx.x; i < ks; i += blockDim.x) part_cnt[base * ks + i] = acc.cnt[i];
 }
 
+// Many problems, one Lloyd round in one launch: k_fit_round_bf16 on the
+// accumulation items (problem p, chunk c, subspace j) of the batched update
+// (chunks of all problems in order, then subspace; problem p's chunk c is
+// rows [c rpc, (c + 1) rpc) of its own), so the partials keep that layout
+// and the batched finalize reads them unchanged.  The block's W waves claim
+// the chunk's 64-row steps; its pending list has room for W rpw >= rpc rows.
+// No objective terms are formed (part_j gets zeros).  cmax is only read: the
+// finalize writes per-tile maxima and the round's last kernel reduces them.
+template <int NB, int NT, bool FULL>
+__global__ __launch_bounds__(fit_waves(NB) * 64) __attribute__((amdgpu_waves_per_eu(NB == 1 ? 3 : 1, 8))) void
+k_fit_round_bf16_batched(const BatchProb* __restrict__ probs, int nprob, int64_t items, int d, int m, int ks,
+                         int ds, const bf16x8* __restrict__ aop, size_t aop_stride, const float* __restrict__ cmax,
+                         const float* __restrict__ mu, int rpw, float e_cross, float e_norm, float g_exact,
+                         double* __restrict__ part_s, uint32_t* __restrict__ part_cnt,
+                         double* __restrict__ part_j) {
+  constexpr int DW = NB * 8;
+  constexpr int W = fit_waves(NB);
+  extern __shared__ __align__(16) unsigned char fit_lds[];
+  const XcdMap bm = xcd_map(blockIdx.x, m);
+  const int64_t item = (int64_t)bm.rowblk * m + bm.group;
+  if (item >= items) return;   // grid padding (block-uniform)
+  // the problem holding the item: the last p with item0 <= item
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (probs[mid].item0 <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  const int p = lo;
+  const int local = (int)(item - probs[p].item0);
+  const int chunk = local / m, sub = local - chunk * m;
+  const float* px = probs[p].x;
+  const int64_t n = probs[p].n, rpc = probs[p].rpc;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int stride = ds + 1;
+  AccLds acc;
+  acc.S = reinterpret_cast<double*>(fit_lds);
+  acc.cnt = reinterpret_cast<uint32_t*>(acc.S + (size_t)ks * stride);
+  float4* stash0 = reinterpret_cast<float4*>(fit_lds + fit_lds_stash_offset(ks, ds));
+  acc.stash = stash0 + w * (DW / 4) * 64;
+  uint16_t* pend = reinterpret_cast<uint16_t*>(stash0 + W * (DW / 4) * 64);   // W rpw entries
+  int* dyn = reinterpret_cast<int*>(pend + W * rpw + (W * rpw & 1));
+  for (int i = threadIdx.x; i < ks * stride; i += blockDim.x) acc.S[i] = 0.0;
+  for (int i = threadIdx.x; i < ks; i += blockDim.x) acc.cnt[i] = 0u;
+  if (threadIdx.x < 2) dyn[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t rb = (int64_t)chunk * rpc;
+  const int64_t re = min(n, rb + rpc);
+  const float* cbsub = probs[p].c32 + (int64_t)sub * ks * ds;
+  if (rb < re) {   // block-uniform
+    SubOps<NB, NT> o;
+    load_sub_ops<NB, NT>(o, aop + (size_t)p * aop_stride, cmax + (size_t)p * m, mu + (size_t)p * m * kMaxDsBf16,
+                         sub, lane);
+    const Band bd{e_cross, e_norm, g_exact};
+    (void)assign_rows64<NB, NT, FULL, false, true, true, true>(o, bd, px, d, ds, m, ks, sub, rb, re, cbsub,
+                                                               probs[p].codes, pend, lane, nullptr, nullptr, acc,
+                                                               dyn);
+  }
+  __syncthreads();
+  const int per = ks * ds;
+  for (int i = threadIdx.x; i < per; i += blockDim.x) {
+    const int k = i / ds;
+    part_s[(size_t)item * per + i] = acc.S[k * stride + (i - k * ds)];
+  }
+  for (int i = threadIdx.x; i < ks; i += blockDim.x) part_cnt[(size_t)item * ks + i] = acc.cnt[i];
+  if (threadIdx.x == 0) part_j[item] = 0.0;
+}
+
 // Many problems in one persistent launch.  The work is the list of units
 // (problem, group of 4 subspaces, 32-row tile): problem-major, then group,
 // then tile.  Logical block b takes the contiguous range [U b / G, U (b+1) / G)
@@ -1398,6 +1467,59 @@ FitGeom fit_round_geometry(int64_t n, int m, int ks, int ds) {
   g.rpw = (int)rpw;
   g.nch = (int)ceil_div(n, (int64_t)w * rpw);
   return g;
+}
+
+int fit_round_batched_rpw(int ks, int ds, int64_t max_rpc) {
+  if (max_rpc < 1 || max_rpc > 65536 || ds > kMaxDsBf16) return 0;   // pending offsets are 16-bit
+  const int w = fit_waves(ds <= 8 ? 1 : 2);
+  const int rpw = (int)ceil_div(max_rpc, w);
+  int dev = 0, lds_max = 65536;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    lds_max = 65536;
+  return fit_lds_bytes(ks, ds, rpw) <= (size_t)lds_max ? rpw : 0;
+}
+
+int launch_fit_round_bf16_batched(const BatchProb* probs, int nprob, int64_t items, int d, int m, int ks,
+                                  const void* aop, size_t aop_stride, const float* cmax, const float* mu, bool full,
+                                  int rpw, double* part_s, uint32_t* part_cnt, double* part_j, hipStream_t s) {
+  const int ds = d / m;
+  const int nb = (ds + 7) / 8;
+  const int nt = tiles_for(ks);
+  if (rpw < 1) return fail(MIPQ_EINVAL, "fused batched round: no pending-list room");
+  const Band bd = band_for(ds);
+  const size_t lds = fit_lds_bytes(ks, ds, rpw);
+  const int64_t chunks = items / m;
+  const unsigned grid = (unsigned)(((chunks + 7) / 8) * 8 * m);
+  ProfScope ps(MIPQ_K_FIT_ROUND_BF16, s);
+#define LAUNCH1(NB, NT, FULL)                                                                                  \
+  k_fit_round_bf16_batched<NB, NT, FULL><<<grid, fit_waves(NB) * 64, lds, s>>>(                                \
+      probs, nprob, items, d, m, ks, ds, (const bf16x8*)aop, aop_stride, cmax, mu, rpw, bd.e_cross, bd.e_norm,   \
+      bd.g_exact, part_s, part_cnt, part_j)
+#define LAUNCH(NB, NT)                 \
+  do {                                 \
+    if (full) LAUNCH1(NB, NT, true);   \
+    else LAUNCH1(NB, NT, false);       \
+  } while (0)
+  if (nb == 1) {
+    switch (nt) {
+      case 1: LAUNCH(1, 1); break;
+      case 2: LAUNCH(1, 2); break;
+      case 4: LAUNCH(1, 4); break;
+      default: LAUNCH(1, 8); break;
+    }
+  } else {
+    switch (nt) {
+      case 1: LAUNCH(2, 1); break;
+      case 2: LAUNCH(2, 2); break;
+      case 4: LAUNCH(2, 4); break;
+      default: LAUNCH(2, 8); break;
+    }
+  }
+#undef LAUNCH
+#undef LAUNCH1
+  MIPQ_LAUNCHED("k_fit_round_bf16_batched");
+  return MIPQ_OK;
 }
 
 int launch_fit_round_bf16(const float* x, int64_t n, int d, int m, int ks, const void* aop, const float* cmax,

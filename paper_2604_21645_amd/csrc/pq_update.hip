@@ -606,13 +606,9 @@ __global__ __launch_bounds__(NT) void k_accumulate_batched(const BatchProb* __re
                                                            int64_t items, int d, int m, int ks, int ds,
                                                            double* __restrict__ part_s,
                                                            uint32_t* __restrict__ part_cnt,
-                                                           double* __restrict__ part_j,
-                                                           float* __restrict__ cmax_zero, int nzero) {
+                                                           double* __restrict__ part_j) {
   extern __shared__ double smem[];
   __shared__ double redj[NT / 64];
-  // the next finalize raises every cmax from zero (see k_accumulate)
-  if (blockIdx.x == 0)
-    for (int j = threadIdx.x; j < nzero; j += blockDim.x) cmax_zero[j] = 0.0f;
   const ChunkMap cmap = chunk_map(blockIdx.x, m);
   const int64_t i = cmap.chunk * m + cmap.sub;   // item: chunks of all problems in order, then subspace
   if (i >= items) return;
@@ -709,7 +705,7 @@ __device__ __forceinline__ void finalize_tile(int t, int sub, int m, int ks, int
                                               double* __restrict__ c64, double* __restrict__ j_out,
                                               uint4* __restrict__ aop, float* __restrict__ cmax,
                                               const float* __restrict__ mu, int nt, float* newc, float* mus,
-                                              float* wmax) {
+                                              float* wmax, float* __restrict__ tmax = nullptr) {
   constexpr int NMF = bf16_nmfma(NB);
   const int per = ks * ds;
   const int k0 = t * 32;
@@ -772,8 +768,10 @@ __device__ __forceinline__ void finalize_tile(int t, int sub, int m, int ks, int
   if (threadIdx.x == 0) {
     float a = wmax[0];
     for (int i = 1; i < kFinTileThreads / 64; ++i) a = fmaxf(a, wmax[i]);
-    // non-negative floats order as their bit patterns
-    atomicMax(reinterpret_cast<unsigned int*>(cmax + sub), __float_as_uint(a));
+    if (tmax)
+      tmax[t] = a;   // the tile's own slot, reduced by k_next_round_batched
+    else   // non-negative floats order as their bit patterns
+      atomicMax(reinterpret_cast<unsigned int*>(cmax + sub), __float_as_uint(a));
   }
 }
 
@@ -796,13 +794,16 @@ __global__ __launch_bounds__(kFinTileThreads) void k_finalize_tiles(int m, int k
 
 // Many problems: block (tile t, subspace j, problem p), as k_finalize_tiles
 // on problem p's partials; the round index comes from *round (see
-// k_finalize_batched).
+// k_finalize_batched).  The tile's norm bound goes to its own slot
+// tmax_all[(p m + j) kMaxTiles + t], so that no kernel of the round has to
+// clear cmax while another may read it; k_next_round_batched reduces them.
 template <int NB>
 __global__ __launch_bounds__(kFinTileThreads) void k_finalize_tiles_batched(
     const BatchProb* __restrict__ probs, int nprob, int m, int ks, int ds, const double* __restrict__ part_s,
     const uint32_t* __restrict__ part_cnt, const double* __restrict__ part_j, double* __restrict__ c64_all,
     double* __restrict__ j_all, const uint32_t* __restrict__ round, int iters, uint4* __restrict__ aop_all,
-    size_t aop_stride, float* __restrict__ cmax_all, const float* __restrict__ mu_all, int nt) {
+    size_t aop_stride, float* __restrict__ cmax_all, const float* __restrict__ mu_all, int nt,
+    float* __restrict__ tmax_all) {
   __shared__ float newc[32 * NB * 8];
   __shared__ float mus[NB * 8];
   __shared__ float wmax[kFinTileThreads / 64];
@@ -813,11 +814,26 @@ __global__ __launch_bounds__(kFinTileThreads) void k_finalize_tiles_batched(
   double* j_out = r < (uint32_t)iters ? j_all + ((size_t)r * nprob + p) * m + sub : nullptr;
   finalize_tile<NB>(t, sub, m, ks, ds, probs[p].nch, part_s + item0 * per, part_cnt + item0 * ks, part_j + item0,
                     probs[p].c32, c64_all + (size_t)p * m * per, j_out, aop_all + (size_t)p * aop_stride,
-                    cmax_all + (size_t)p * m, mu_all + (size_t)p * m * kMaxDsBf16, nt, newc, mus, wmax);
+                    cmax_all + (size_t)p * m, mu_all + (size_t)p * m * kMaxDsBf16, nt, newc, mus, wmax,
+                    tmax_all + ((size_t)p * m + sub) * kMaxTiles);
 }
 
 __global__ void k_next_round(uint32_t* round) {
   if (threadIdx.x == 0) round[0] = round[0] + 1u;
+}
+
+// Many problems: cmax[i] = the largest of subspace i's nt tile bounds (every
+// slot written by this round's finalize), then the round counter advances.
+__global__ __launch_bounds__(256) void k_next_round_batched(uint32_t* __restrict__ round,
+                                                            const float* __restrict__ tmax_all,
+                                                            float* __restrict__ cmax_all, int count, int nt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) {
+    float a = tmax_all[(size_t)i * kMaxTiles];
+    for (int t = 1; t < nt; ++t) a = fmaxf(a, tmax_all[(size_t)i * kMaxTiles + t]);
+    cmax_all[i] = a;
+  }
+  if (i == 0) round[0] = round[0] + 1u;
 }
 
 // dL/dC_j[k] = 2 g (cnt_jk C_j[k] - S_jk) with the chunk partials summed in
@@ -1050,9 +1066,9 @@ int launch_pack_bf16_batched(const BatchProb* probs, int nprob, int m, int ks, i
 int launch_update_batched(const BatchProb* probs, int nprob, int64_t items, int d, int m, int ks, double* c64,
                           double* part_s, uint32_t* part_cnt, double* part_j, double* j_all,
                           const uint32_t* round, int iters, void* aop, size_t aop_stride, float* cmax, float* mu,
-                          bool det, hipStream_t s) {
+                          bool det, bool accumulate, float* tmax, hipStream_t s) {
   const int ds = d / m;
-  {
+  if (accumulate) {
     const size_t shm = (size_t)ks * (ds + 1) * sizeof(double) + ((ks + 1) / 2) * sizeof(double) +
                        (size_t)ks * ds * sizeof(float);
     ProfScope ps(MIPQ_K_UPDATE, s);
@@ -1060,11 +1076,10 @@ int launch_update_batched(const BatchProb* probs, int nprob, int64_t items, int 
     const unsigned grid = (unsigned)(((chunks + 7) / 8) * 8 * m);
     if (det)
       k_accumulate_batched<true, kDetThreads><<<grid, kDetThreads, det_lds_bytes(ks, ds, true), s>>>(
-          probs, nprob, items, d, m, ks, ds, part_s, part_cnt, part_j, cmax, nprob * m);
+          probs, nprob, items, d, m, ks, ds, part_s, part_cnt, part_j);
     else
       k_accumulate_batched<false, kUpdThreads><<<grid, kUpdThreads, shm, s>>>(probs, nprob, items, d, m, ks, ds,
-                                                                              part_s, part_cnt, part_j, cmax,
-                                                                              nprob * m);
+                                                                              part_s, part_cnt, part_j);
     MIPQ_LAUNCHED("k_accumulate_batched");
   }
   const int nt = tiles_for(ks);
@@ -1073,14 +1088,15 @@ int launch_update_batched(const BatchProb* probs, int nprob, int64_t items, int 
   if (ds <= 8)
     k_finalize_tiles_batched<1><<<grid, kFinTileThreads, 0, s>>>(probs, nprob, m, ks, ds, part_s, part_cnt, part_j,
                                                                  c64, j_all, round, iters, (uint4*)aop, aop_stride,
-                                                                 cmax, mu, nt);
+                                                                 cmax, mu, nt, tmax);
   else
     k_finalize_tiles_batched<2><<<grid, kFinTileThreads, 0, s>>>(probs, nprob, m, ks, ds, part_s, part_cnt, part_j,
                                                                  c64, j_all, round, iters, (uint4*)aop, aop_stride,
-                                                                 cmax, mu, nt);
+                                                                 cmax, mu, nt, tmax);
   MIPQ_LAUNCHED("k_finalize_tiles_batched");
-  k_next_round<<<1, 64, 0, s>>>(const_cast<uint32_t*>(round));
-  MIPQ_LAUNCHED("k_next_round");
+  const int count = nprob * m;
+  k_next_round_batched<<<(count + 255) / 256, 256, 0, s>>>(const_cast<uint32_t*>(round), tmax, cmax, count, nt);
+  MIPQ_LAUNCHED("k_next_round_batched");
   return MIPQ_OK;
 }
 

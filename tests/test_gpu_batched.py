@@ -108,7 +108,8 @@ def test_plans_without_objective_equal_single_calls(mode, d, m, ks):
     the accumulation into the assignment, bit for bit (float64 sums of
     integers are exact in any order)."""
     iters = 4
-    xs, inits = _problems([ks, 4097, 20011, 333, 9000], d, m, ks, "integer", seed=35)
+    # 300,001 rows: more chunks than the 256-block cap allows (8,192 rows at most)
+    xs, inits = _problems([ks, 4097, 20011, 333, 9000, 300001], d, m, ks, "integer", seed=35)
     xt = [_t(x) for x in xs]
     it = [_t(i) for i in inits]
     print("no objective", mode, d, m, ks, flush=True)
@@ -239,6 +240,24 @@ def test_full_size_uneven_batch_sampled():
                              r["codebook"].cpu().numpy().astype(np.float64))
         assert r["sse_rmse"][0].item() == pytest.approx(sse, rel=1e-12)
     b.close()
+    # the benchmarked form: no objectives, one fused launch per round
+    f = mipq.BatchedFit([_t(x) for x in xs], [_t(i) for i in inits], w.m, w.ks, w.iters, plan=True, autotune=True,
+                        graph=True, objective=False)
+    f.run()
+    torch.cuda.synchronize()
+    print("fused plan", f.info(), flush=True)
+    for i, x in enumerate(xs):
+        r = f.results[i]
+        cb = r["codebook"].cpu().numpy().astype(np.float64)
+        rows = rng.choice(x.shape[0], 300, replace=False)
+        ref, _ = pq.encode(x[rows], cb, decide="fp32")
+        np.testing.assert_array_equal(r["codes"].cpu().numpy()[rows].astype(np.int64), ref)
+    for i in np.argsort([x.shape[0] for x in xs])[:4]:
+        r = f.results[i]
+        sse, _ = pq.sse_rmse(xs[i], r["codes"].cpu().numpy().astype(np.int64),
+                             r["codebook"].cpu().numpy().astype(np.float64))
+        assert r["sse_rmse"][0].item() == pytest.approx(sse, rel=1e-12)
+    f.close()
 
 
 def test_deterministic_plan_repeats_and_equals_single_deterministic_fits():
