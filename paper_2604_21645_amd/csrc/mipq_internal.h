@@ -105,7 +105,7 @@ int launch_assign_fp32(const float* x, int64_t n, int d, int m, int ks, const fl
 int update_chunks(int64_t n, int m);
 // chunks of a problem in the fused batched round: at most kFusedChunkRows rows
 // each, so that a chunk's pending list fits its block's LDS
-constexpr int64_t kFusedChunkRows = 8192;
+constexpr int64_t kFusedChunkRows = 32768;
 inline int fused_chunks(int64_t n) { return n < 1 ? 1 : (int)((n + kFusedChunkRows - 1) / kFusedChunkRows); }
 // objective: also the float64 objective terms of the round (else part_j holds zeros)
 // det: float64 sums in a fixed order (no atomic additions; MIPQ_DETERMINISTIC)
