@@ -797,7 +797,7 @@ def bench_diff(args) -> dict:
                        "parallelism": "single GPU"})
     rec.update({
         "loss": float(loss.item()),
-        "roofline": {"bound": "hbm", "kernel": "k_accumulate<grad_x> (backward)", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": "k_backward_group<grad_x> (backward)", "achieved": achieved,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
                      "alg_bytes_per_launch": alg, "avg_launch_ms": avg, "launches": nl},
         "kernels_ms_per_step": {k2: v[1] for k2, v in kt.items()},
