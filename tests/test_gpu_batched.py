@@ -101,12 +101,14 @@ def test_integer_rows_equal_single_calls_bit_for_bit(mode):
 
 
 @pytest.mark.parametrize("mode", ["eager", "graph"])
-@pytest.mark.parametrize("d,m,ks", [(96, 12, 256), (48, 6, 100)])
+@pytest.mark.parametrize("d,m,ks", [(96, 12, 256), (48, 6, 100), (48, 16, 16), (96, 8, 256), (64, 4, 100)])
 def test_plans_without_objective_equal_single_calls(mode, d, m, ks):
-    """Plans that return no objective (the benchmarked form): on integer
-    rows the codebooks, codes and errors equal the single calls, which fuse
-    the accumulation into the assignment, bit for bit (float64 sums of
-    integers are exact in any order)."""
+    """Plans that return no objective (the benchmarked form, one fused launch
+    per round; ds = 8, 8, 3, 12, 16 and Ks = 256, 100, 16, 256, 100 cover
+    whole and partial 8-dimension blocks, one and two of them, and 1 to 8
+    centroid tiles): on integer rows the codebooks, codes and errors equal
+    the single calls bit for bit (float64 sums of integers are exact in any
+    order)."""
     iters = 4
     # 300,001 rows: more chunks than the 256-block cap allows (8,192 rows at most)
     xs, inits = _problems([ks, 4097, 20011, 333, 9000, 300001], d, m, ks, "integer", seed=35)
