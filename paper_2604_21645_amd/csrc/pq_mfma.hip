@@ -580,7 +580,9 @@ __device__ __forceinline__ void row_operands(const RowParts<NB>& r, bf16x8 (&BA)
   }
 }
 
-// Raw subspace slice of row r0 + lane (clamped to r0 past rend).
+// Raw subspace slice of row r0 + lane (clamped to r0 past rend).  Without
+// whole 8-dimension blocks, an even ds on 8-byte aligned rows is read in pairs
+// of floats (the last pair repeated past ds), else one float at a time.
 template <int DW, bool FULL>
 __device__ __forceinline__ void load_own_row(float (&xv)[DW], const float* __restrict__ x, int64_t r0, int64_t rend,
                                              int d, int sub, int ds, int lane) {
@@ -594,6 +596,13 @@ __device__ __forceinline__ void load_own_row(float (&xv)[DW], const float* __res
       xv[e + 1] = v.y;
       xv[e + 2] = v.z;
       xv[e + 3] = v.w;
+    }
+  } else if ((ds & 1) == 0 && (reinterpret_cast<uintptr_t>(x) & 7) == 0) {
+#pragma unroll
+    for (int e = 0; e < DW; e += 2) {
+      const float2 v = *reinterpret_cast<const float2*>(xr + (e < ds ? e : ds - 2));
+      xv[e] = (e < ds) ? v.x : 0.0f;
+      xv[e + 1] = (e < ds) ? v.y : 0.0f;
     }
   } else {
 #pragma unroll
