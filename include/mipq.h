@@ -197,16 +197,22 @@ int mipq_pq_decode_rmse(const uint8_t* codes, int64_t n, int d, int m, int ks,
  * non-NULL, reports the reconstruction error of those codes.  All problems
  * share d, m, ks and precision (MIPQ_BF16 only).  Per problem the outputs are
  * those of mipq_pq_fit + mipq_pq_encode + mipq_pq_decode_rmse on that
- * problem: same code rule, same row chunks for the float64 centroid sums,
- * same reduction order for the objective and the error.  (Within a chunk the
- * float64 sums are formed by atomic additions, so their last bits, and hence
- * rarely a float32 centroid, can differ between any two runs; integer-valued
- * rows make every sum exact.)
+ * problem: same code rule, same reduction order for the error and, when any
+ * problem returns its objective (or the plan is deterministic), the same row
+ * chunks for the float64 centroid sums and the same reduction order for the
+ * objective.  (Within a chunk the float64 sums are formed by atomic
+ * additions, so their last bits, and hence rarely a float32 centroid, can
+ * differ between any two runs; integer-valued rows make every sum exact.)
  *
- * Each phase is one launch over all problems: a persistent matrix-core
- * assignment over the flat list of (problem, 4-subspace group, 32-row tile)
- * units, one accumulation launch over all (problem, row chunk, subspace)
- * items and one finalisation launch over all (problem, subspace) pairs.
+ * Each phase is one launch over all problems.  Without objectives (and not
+ * deterministic) a Lloyd round is one fused launch over all (problem, row
+ * chunk of at most 32,768 rows, subspace) items: the matrix-core assignment
+ * and the float64 sums of the chunk's rows.  Otherwise a round is a
+ * persistent matrix-core assignment over the flat list of (problem,
+ * 4-subspace group, 32-row tile) units and one accumulation launch over all
+ * (problem, row chunk, subspace) items.  Then one finalisation launch over
+ * all (problem, subspace, centroid tile) blocks.  The final encode is the
+ * persistent assignment.
  */
 typedef struct mipq_problem {
   const float* x;            /* rows [n][d] */
