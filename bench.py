@@ -67,13 +67,15 @@ def batched_roofline(kt, rows, d, m):
     """Roofline of a batched fit's dominant kernel: the fused round
     (assignment + float64 sums, one launch per Lloyd round) when the plan
     runs it, else the batched assignment; algorithmic bytes per launch are
-    every row read once (4 d bytes) and its m codes written."""
+    every row read once (4 d bytes), plus its m codes written by the
+    assignment (the fused rounds store no codes: the final encode does)."""
     nl, tot = kt["fit_round_bf16"]
     name = "k_fit_round_bf16_batched"
+    alg = rows * 4 * d
     if nl == 0:
         nl, tot = kt["assign_bf16_batched"]
         name = "k_assign_bf16_batched"
-    alg = rows * (4 * d + m)
+        alg = rows * (4 * d + m)
     avg = tot / max(nl, 1)
     achieved = alg / (avg * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",

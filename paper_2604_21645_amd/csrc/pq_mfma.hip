@@ -429,7 +429,7 @@ __device__ __forceinline__ void redecide(const P* pend, int64_t base, int np, co
     wave_argmin(best, bk);
     const int code = bk < ks ? bk : 0;
     if (lane == 0) {
-      codes[prow * m + sub] = (uint8_t)code;
+      if (codes) codes[prow * m + sub] = (uint8_t)code;
       if (ACC) acc_row<DW>(acc, code, xo, ds);
       if (OUT) {
         if (min_dist) min_dist[prow * m + sub] = best;
@@ -620,8 +620,9 @@ __device__ __forceinline__ void load_own_row(float (&xv)[DW], const float* __res
 // groups' tiles run on the matrix cores and each lane reduces its half of the
 // candidates of group A's and group B's row (lane_keys); one swap per key
 // brings the two halves of a row to the row's own lane, so the merge, the
-// separation test, the code store and (OUT) the distance of the chosen
-// centroid and its float64 squared error run once per row.  Ambiguous rows
+// separation test, the code store (none with codes NULL) and (OUT) the
+// distance of the chosen centroid and its float64 squared error run once per
+// row.  Ambiguous rows
 // are queued in the wave's LDS list `pend` as offsets from rb (room for
 // re - rb <= 65536 entries) and re-decided by the whole wave after the loop.  Returns the number of
 // re-decided rows; OUT adds the squared errors to *sse (lane-local sums); ACC
@@ -699,7 +700,7 @@ __device__ __forceinline__ int assign_rows64(const SubOps<NB, NT>& o, const Band
     const float xnorm = sqrtf(rp.xn) * 1.0001f;
     const float beta = bd.e_cross * xnorm * o.cm + bd.e_norm * (o.cm * o.cm + rp.xn);
     const bool amb = not_separated(f1, f2, beta, bd.g_exact, rp.xn) || code >= ks;
-    if (valid) codes[row * m + sub] = (uint8_t)code;
+    if (valid && codes) codes[row * m + sub] = (uint8_t)code;
     const bool push = valid && amb;
     const uint64_t mask = __ballot(push);
     if (mask) {
@@ -915,8 +916,11 @@ k_fit_round_bf16(const float* __restrict__ x, int64_t n, int d, int m, int ks, i
 // rows [c rpc, (c + 1) rpc) of its own), so the partials keep that layout
 // and the batched finalize reads them unchanged.  The block's W waves claim
 // the chunk's 64-row steps; its pending list has room for W rpw >= rpc rows.
-// No objective terms are formed (part_j gets zeros).  cmax is only read: the
-// finalize writes per-tile maxima and the round's last kernel reduces them.
+// No objective terms are formed (part_j gets zeros) and no codes are stored
+// (codes NULL to assign_rows64): the final encode writes every code, and a
+// byte column per block would make each code line travel to HBM many times.
+// cmax is only read: the finalize writes per-tile maxima and the round's last
+// kernel reduces them.
 template <int NB, int NT, bool FULL>
 __global__ __launch_bounds__(fit_waves(NB) * 64) __attribute__((amdgpu_waves_per_eu(NB == 1 ? 3 : 1, 8))) void
 k_fit_round_bf16_batched(const BatchProb* __restrict__ probs, int nprob, int64_t items, int d, int m, int ks,
@@ -965,8 +969,7 @@ k_fit_round_bf16_batched(const BatchProb* __restrict__ probs, int nprob, int64_t
                          sub, lane);
     const Band bd{e_cross, e_norm, g_exact};
     (void)assign_rows64<NB, NT, FULL, false, true, true, true>(o, bd, px, d, ds, m, ks, sub, rb, re, cbsub,
-                                                               probs[p].codes, pend, lane, nullptr, nullptr, acc,
-                                                               dyn);
+                                                               nullptr, pend, lane, nullptr, nullptr, acc, dyn);
   }
   __syncthreads();
   const int per = ks * ds;
