@@ -325,10 +325,11 @@ def bench_integer_pq(args) -> dict:
     # the dominant kernel: the fit's fused rounds (assignment + float64 sums),
     # one launch per round over the n_train sampled rows; the encode's
     # assignment of all n rows is reported beside it.  Algorithmic bytes per
-    # row: its float32 slice of every subspace read once (4 d) and its codes
-    # written (m); the sums and partials are not counted.
+    # row: its float32 slice of every subspace read once (4 d); the rounds
+    # store no codes (no labels are taken) and the sums and partials are not
+    # counted.  The encode also writes its m codes per row.
     nl, tot = kernel_stats.get("fit_round_bf16", (0, 0.0))
-    alg_bytes_per_launch = n_train * (4 * d + w.m)
+    alg_bytes_per_launch = n_train * 4 * d
     avg_launch_ms = tot / max(nl, 1)
     achieved = alg_bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if nl else 0.0
     ne, te = kernel_stats.get("assign_bf16", (0, 0.0))

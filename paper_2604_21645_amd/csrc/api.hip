@@ -247,7 +247,10 @@ int mipq_pq_fit(const float* x, int64_t n, const int64_t* train_rows, int64_t n_
       // finalize raises for the next round
       float* cm_read = (it & 1) ? f.cmax2 : f.enc.cmax;
       float* cm_next = (it & 1) ? f.enc.cmax : f.cmax2;
-      if ((rc = launch_fit_round_bf16(train, nt, d, m, ks, f.enc.aop, cm_read, f.enc.mu, c32, codes,
+      // the sums need no stored codes: only the last round stores them, and
+      // only for a caller that takes the labels
+      uint8_t* round_codes = (labels && it + 1 == iters) ? codes : nullptr;
+      if ((rc = launch_fit_round_bf16(train, nt, d, m, ks, f.enc.aop, cm_read, f.enc.mu, c32, round_codes,
                                       rescored ? rescored + it : nullptr, f.part_s, f.part_cnt, cm_next, s)))
         return rc;
       if ((rc = launch_finalize(m, ks, ds, nch, f.part_s, f.part_cnt, nullptr, c32, c64, nullptr, f.enc.aop, cm_next,
